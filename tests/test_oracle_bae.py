@@ -1,0 +1,238 @@
+"""Pins of the oracle's layer potentials, BAE operator, GMRES and Algorithm 1
+(Sec. 2-4 of the paper) to identities the paper proves, closed forms, library solvers
+and the error tables it prints."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import workloads as W
+from oracle import bae, geometry, gmres, lgf, operators, sparse
+
+HERE = os.path.dirname(__file__)
+
+
+def small(kind="sphere", n=13, sigma=0.0, params=None):
+    h = 1.0 / (n - 1)
+    params = params or {"sphere": (0.3,), "ellipsoid": (0.4, 0.3, 0.25), "torus": (0.26, 0.12),
+                        "star": (0.32, 0.15, 3.0, 2.0)}[kind]
+    g = geometry.build((n, n, n), h, (0, 0, 0), kind, (0.5, 0.5, 0.5), params)
+    G = lgf.LGFTable(g.max_offset() + 1, sigma * h * h)
+    return g, G, sigma * h * h
+
+
+def nplus(g):
+    return np.concatenate([g.mplus, g.gamma_minus])
+
+
+@pytest.mark.parametrize("kind,n", [("sphere", 13), ("ellipsoid", 17), ("torus", 25)])
+def test_gauss_law_sigma0(kind, n):
+    # Summation by parts of L G = delta over N+ (Sec. 3.2 double layer): (D 1)(m) = 1 on N+,
+    # 0 off N+ -- the discrete Gauss law; it fixes the sign convention and every G in D.
+    g, G, s = small(kind, n)
+    one = np.ones(len(g.gamma_minus))
+    v_in = operators.double_layer(g, G, one, nplus(g))
+    assert np.abs(v_in - 1.0).max() < 1e-13
+    v_out = operators.double_layer(g, G, one, g.ext)
+    assert np.abs(v_out).max() < 1e-13
+
+
+def test_gauss_law_sigma_positive():
+    # Same summation by parts with (6+s): (D 1)(m) = chi_{N+}(m) - s sum_{j in N+} G(m - j).
+    g, G, s = small("ellipsoid", 17, sigma=40.0)
+    one = np.ones(len(g.gamma_minus))
+    T = np.concatenate([nplus(g), g.ext])
+    v = operators.double_layer(g, G, one, T)
+    mass = G.pairs(T, nplus(g)).sum(axis=1)
+    chi = np.r_[np.ones(len(nplus(g))), np.zeros(len(g.ext))]
+    assert np.abs(v - (chi - s * mass)).max() < 1e-13
+
+
+def test_double_layer_diagonal():
+    # D(n, n) = |D_n| (G(0) - G(e1)) = |D_n| (1 - s G(0)) / 6.
+    g, G, s = small("sphere", 13, sigma=25.0)
+    D = operators.dense_double_layer(g, G, g.gamma_minus)
+    g0 = G(np.array([0, 0, 0]))
+    assert np.abs(np.diag(D) - g.d_count() * (1 - s * g0) / 6).max() < 1e-15
+
+
+@pytest.mark.parametrize("sigma", [0.0, 30.0])
+def test_layer_potentials_are_discrete_harmonic(sigma):
+    # Propositions of Sec. 3.2: single and double layer potentials satisfy L_h v = 0 on M+.
+    g, G, s = small("ellipsoid", 17, sigma=sigma)
+    rng = np.random.default_rng(1)
+    q = rng.standard_normal(len(g.gamma_minus))
+    mp = g.mplus
+    for layer in (operators.double_layer, operators.single_layer):
+        Lv = (6 + s) * layer(g, G, q, mp)
+        for d in geometry.DIRS:
+            Lv -= layer(g, G, q, mp + d)
+        assert np.abs(Lv).max() < 1e-12 * np.abs(q).max()
+
+
+def test_unit_data_gives_unit_density():
+    # sigma = 0, g = 1: D 1 = 1 on N+ and the closure rows sum to 1, so q_d = 1 solves A q = 1.
+    g, G, s = small("torus", 25)
+    b = np.ones(len(g.gamma_minus))
+    q, hist, conv = gmres.gmres(lambda x: operators.bae_apply(g, G, x), b, tol=1e-13)
+    dn = g.d_count() > 0
+    assert conv and np.abs(q[dn] - 1).max() < 1e-11
+
+
+def test_linear_data_reproduced_exactly():
+    # sigma = 0 and linear g: the discrete problem's solution is the linear function itself
+    # (the 7-point Laplacian of a linear function vanishes), so u_gamma is exact.
+    g, G, s = small("ellipsoid", 17)
+    lin = lambda X: 0.3 + 1.1 * X[:, 0] - 0.7 * X[:, 1] + 2.0 * X[:, 2]
+    b = lin(g.xstar)
+    q, hist, conv = gmres.gmres(lambda x: operators.bae_apply(g, G, x), b, tol=1e-14)
+    T = operators.gamma_targets(g)
+    ug = operators.double_layer(g, G, q, T)
+    assert np.abs(ug - lin(g.coords(T))).max() < 1e-12
+
+
+@pytest.mark.parametrize("kind,n,sigma,withf", [("sphere", 13, 0.0, False), ("star", 21, 0.0, True),
+                                               ("torus", 25, 10.0, True), ("ellipsoid", 17, 50.0, False)])
+def test_bae_equals_sparse_discrete_solve(kind, n, sigma, withf):
+    # Sec. 2.2 (finite/free-space equivalence) and eq. "equal": the BAE solution is the
+    # unique solution of the sparse discrete Dirichlet problem, whatever the representation.
+    g, G, s = small(kind, n, sigma)
+    X = g.coords(np.argwhere(np.ones(g.n, bool))).reshape(g.n + (3,))
+    u = lambda x, y, z: np.sin(2 * x + y) * np.cos(z) + x * y
+    f = None
+    if withf:
+        f = (-(-5 * np.sin(2 * X[..., 0] + X[..., 1]) * np.cos(X[..., 2])
+               - np.sin(2 * X[..., 0] + X[..., 1]) * np.cos(X[..., 2]))
+             + sigma * u(X[..., 0], X[..., 1], X[..., 2])).reshape(-1)
+    gx = u(*g.xstar.T)
+    b = operators.rhs(g, G, gx, f)
+    q, hist, conv = gmres.gmres(lambda x: operators.bae_apply(g, G, x), b, tol=1e-14)
+    T = operators.gamma_targets(g)
+    ug = operators.double_layer(g, G, q, T)
+    if f is not None:
+        ug += operators.volume_potential(g, G, f, T)
+    us = sparse.solve(g, s, gx, f)
+    assert np.abs(ug - us[tuple(T.T)]).max() < 1e-11
+
+
+def test_volume_potential_solves_the_source_problem():
+    # u_p = h^2 sum_{M+} G(m - n) f(n) satisfies L u_p = h^2 chi_{M+} f at every node.
+    g, G, s = small("sphere", 13, sigma=5.0)
+    rng = np.random.default_rng(3)
+    f = rng.standard_normal(int(np.prod(g.n)))
+    pts = nplus(g)
+    Lu = (6 + s) * operators.volume_potential(g, G, f, pts)
+    for d in geometry.DIRS:
+        Lu -= operators.volume_potential(g, G, f, pts + d)
+    chi = g.inside[tuple(pts.T)]
+    expect = g.h ** 2 * f.reshape(g.n)[tuple(pts.T)] * chi
+    assert np.abs(Lu - expect).max() < 1e-14
+
+
+def test_gmres_against_dense_and_scipy():
+    g, G, s = small("ellipsoid", 17, sigma=10.0)
+    A = operators.dense_operator(g, G)
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal(len(g.gamma_minus))
+    x, hist, conv = gmres.gmres(lambda v: operators.bae_apply(g, G, v), b, tol=1e-13)
+    xd = np.linalg.solve(A, b)
+    assert conv and np.abs(x - xd).max() < 1e-10 * np.abs(xd).max()
+    xs, info = spla.gmres(A, b, rtol=1e-13, restart=len(b), maxiter=1)
+    assert np.abs(xs - xd).max() < 1e-9 * np.abs(xd).max()
+    # history is monotone non-increasing and ends below tol
+    assert hist[-1] <= 1e-13 and np.all(np.diff(hist) <= 1e-15)
+    # the matrix-free operator equals the assembled one
+    assert np.abs(A @ b - operators.bae_apply(g, G, b)).max() < 1e-13
+
+
+def test_single_layer_spectrum_and_equivalence():
+    # Sec. 3.3: singular values of S- are >= 1/12; eq. "equal": D+ D-^-1 = S+ S-^-1.
+    g, G, s = small("sphere", 13)
+    Sm = operators.dense_single_layer(g, G, g.gamma_minus)
+    Sp = operators.dense_single_layer(g, G, g.gamma_plus)
+    Dm = operators.dense_double_layer(g, G, g.gamma_minus)
+    Dp = operators.dense_double_layer(g, G, g.gamma_plus)
+    assert np.linalg.svd(Sm, compute_uv=False).min() >= 1.0 / 12
+    X1 = Sp @ np.linalg.inv(Sm)
+    X2 = Dp @ np.linalg.inv(Dm)
+    assert np.abs(X1 - X2).max() < 1e-12 * np.abs(X1).max()
+    # the remark on the spectrum of D: with the positive kernel sign the eigenvalue is +1
+    ev = np.linalg.eigvals(Dm)
+    assert np.abs(ev - 1.0).min() < 1e-10
+
+
+def test_second_order_convergence():
+    # Sec. 4: max error O(h^2) against the exact solution (rates 1.86-2.00 in Tables 1-2).
+    errs, hs = [], []
+    for n in (13, 17, 25, 33, 49):
+        p = W.laplace_sphere(n)
+        g = geometry.from_problem(p)
+        u = sparse.solve(g, 0.0, p.g(g.xstar))
+        pts = np.argwhere(g.inside)
+        X = g.coords(pts)
+        errs.append(np.abs(u[tuple(pts.T)] - p.exact(*X.T)).max())
+        hs.append(p.h)
+    rate = np.polyfit(np.log(hs), np.log(errs), 1)[0]     # least-squares slope over the levels
+    assert 1.7 < rate < 2.4, (errs, rate)
+
+
+def paper_case(which, N):
+    tab = json.load(open(os.path.join(HERE, "golden", "paper_tables.json")))[which]
+    L = 1.0 + tab["ell"]
+    n, h, o = N + 2, 2 * L / (N + 1), -L
+    if which == "poisson_ellipsoid":
+        g = geometry.build((n, n, n), h, (o, o, o), "ellipsoid", (0, 0, 0), tuple(tab["axes"]))
+        u = lambda x, y, z: x * x + y * y + z * z
+        f = lambda x, y, z: -6.0 + 0 * x
+    else:
+        g = geometry.build((n, n, n), h, (o, o, o), "torus", (0, 0, 0), (tab["R"], tab["r"]))
+        u = lambda x, y, z: np.sin(x) * np.cos(y) * np.sin(z)
+        f = lambda x, y, z: (3 + tab["sigma"]) * np.sin(x) * np.cos(y) * np.sin(z)
+    ii = np.stack(np.meshgrid(*[np.arange(n)] * 3, indexing="ij"), -1)
+    X = o + h * ii
+    return tab, g, u, f(X[..., 0], X[..., 1], X[..., 2]).reshape(-1), tab["sigma"] * h * h
+
+
+def within_last_digit(value, printed):
+    unit = 10.0 ** (math.floor(math.log10(printed)) - 4)
+    return abs(value - printed) <= unit
+
+
+@pytest.mark.parametrize("which,N", [("poisson_ellipsoid", 31), ("poisson_ellipsoid", 63),
+                                     ("helmholtz_torus", 31), ("helmholtz_torus", 63)])
+def test_paper_tables_via_the_equivalent_discrete_problem(which, N):
+    # Tables 1 and 2 print max errors to 5 digits; the discrete problem the BAE equals
+    # (pinned above) reproduces them to within one unit in the last printed digit.
+    tab, g, u, f, s = paper_case(which, N)
+    U = sparse.solve(g, s, u(*g.xstar.T), f)
+    mp = g.mplus
+    err = np.abs(U[tuple(mp.T)] - u(*g.coords(mp).T)).max()
+    assert within_last_digit(err, tab["max_error"][str(N)]), err
+
+
+def test_paper_table1_by_algorithm_1():
+    # The whole oracle Algorithm 1 (LGF table, volume potential, matrix-free D, GMRES,
+    # u = u_p + D q_d on M+) on the first row of Table 1.
+    tab, g, u, f, s = paper_case("poisson_ellipsoid", 31)
+    G = lgf.LGFTable(g.max_offset(), s)
+    b = operators.rhs(g, G, u(*g.xstar.T), f)
+    q, hist, conv = gmres.gmres(lambda x: operators.bae_apply(g, G, x), b, tol=1e-12)
+    mp = g.mplus
+    um = operators.double_layer(g, G, q, mp) + operators.volume_potential(g, G, f, mp)
+    err = np.abs(um - u(*g.coords(mp).T)).max()
+    assert conv and within_last_digit(err, tab["max_error"]["31"]), err
+
+
+def test_algorithm1_driver_laplace_sphere():
+    p = W.laplace_sphere(17)
+    r = bae.solve(p, tol=1e-12, grid=True)
+    g, G = bae.setup(p)
+    us = sparse.solve(g, 0.0, p.g(g.xstar))
+    T = operators.gamma_targets(g)
+    assert r["converged"] and r["true_residual"] < 1e-11
+    assert np.abs(r["u_gamma"] - us[tuple(T.T)]).max() < 1e-10
+    mp = g.mplus
+    assert np.abs(r["u_grid"][tuple(mp.T)] - us[tuple(mp.T)]).max() < 1e-10

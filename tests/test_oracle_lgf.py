@@ -1,0 +1,106 @@
+"""Pins of the oracle's lattice Green's function (Sec. 2.2 of the paper) to values and
+identities fixed independently of it."""
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+from oracle import lgf
+
+
+def mp_lgf(n, s=0.0, dps=35):
+    """G_s(n) by mpmath's tanh-sinh quadrature of the Bessel integral at `dps` digits."""
+    with mp.workdps(dps):
+        a, b, c = n
+        s = mp.mpf(s)
+        f = lambda t: mp.exp(-(6 + s) * t) * mp.besseli(a, 2 * t) * mp.besseli(b, 2 * t) * mp.besseli(c, 2 * t)
+        return float(mp.quad(f, [0, 1, 10, 100, 1000, 10000, mp.inf]))
+
+
+def test_watson_closed_forms():
+    # Sec. 2.2 prints two Gamma-function closed forms for the sigma = 0 value at the origin;
+    # both equal Watson's integral (1/pi^3) int dθ / (3 - sum cos), which is twice G_0(0)
+    # in the normalisation of eq. "lgf" (denominator 6 - 2 sum cos).
+    with mp.workdps(30):
+        g1 = mp.sqrt(6) / (96 * mp.pi ** 3) * mp.gamma(mp.mpf(1) / 24) * mp.gamma(mp.mpf(5) / 24) \
+            * mp.gamma(mp.mpf(7) / 24) * mp.gamma(mp.mpf(11) / 24)
+        g2 = (mp.sqrt(3) - 1) / (96 * mp.pi ** 3) * (mp.gamma(mp.mpf(1) / 24) * mp.gamma(mp.mpf(11) / 24)) ** 2
+        assert abs(g1 - g2) < mp.mpf(10) ** -25
+        half = float(g1 / 2)
+    t = lgf.LGFTable(4, 0.0)
+    assert abs(t(np.array([0, 0, 0])) - half) < 2e-16
+    assert abs(lgf.lgf_entry((0, 0, 0), 0.0) - half) < 2e-16
+
+
+@pytest.mark.parametrize("s", [0.0, 1.526e-4, 0.05, 2.0])
+def test_first_shell_from_the_stencil(s):
+    # L G = delta at the origin with the 6 equal neighbours: (6+s) G(0) - 6 G(e1) = 1.
+    t = lgf.LGFTable(3, s)
+    g0, g1 = t(np.array([0, 0, 0])), t(np.array([1, 0, 0]))
+    assert abs(g1 - ((6.0 + s) * g0 - 1.0) / 6.0) < 2e-16
+
+
+@pytest.mark.parametrize("s", [0.0, 1.526e-4, 0.0488, 2.0])
+def test_stencil_residual_everywhere(s):
+    # eq. "lgf_delta": (6+s) G(n) - sum_6 G(n +- e_i) = delta(n) on the whole table.
+    t = lgf.LGFTable(40, s)
+    n, res = t.stencil_residual()
+    assert np.abs(res).max() < 2e-15
+
+
+@pytest.mark.parametrize("n,s", [((1, 1, 0), 0.0), ((2, 0, 0), 0.0), ((3, 2, 1), 0.0),
+                                 ((20, 5, 3), 0.0), ((0, 0, 0), 0.0488), ((4, 1, 0), 0.0488),
+                                 ((30, 0, 0), 1e-4)])
+def test_against_mpmath(n, s):
+    ref = mp_lgf(n, s)
+    t = lgf.LGFTable(max(n) + 1, s)
+    assert abs(t(np.array(n)) - ref) <= 1e-14 * ref
+    assert abs(lgf.lgf_entry(n, s) - ref) <= 1e-13 * ref
+
+
+def test_table_matches_adaptive_quadrature():
+    # the vectorised fixed rule against QUADPACK's adaptive Gauss-Kronrod (paper: "adaptive
+    # Gauss Kronrod method" is an alternative evaluation of eq. "lgf_bessel")
+    rng = np.random.default_rng(7)
+    for s in (0.0, 6.1e-4):
+        t = lgf.LGFTable(117, s)
+        for _ in range(12):
+            n = np.sort(rng.integers(0, 118, 3))
+            e = lgf.lgf_entry(tuple(n), s, R=117)
+            assert abs(t(n) - e) <= 2e-14 * e
+
+
+def test_far_field_decay_and_the_A3_reading():
+    # Sec. 2.2: G_0(n) -> 1/(4 pi |n|) as |n| -> inf, with the q-term expansion error
+    # O(|n|^(-2q-1)).  In the positive sign convention of eq. "lgf" the q=3 expansion only
+    # decays like |n|^-6 relative if the coefficient printed as -288 reads -228 (the
+    # symmetric-polynomial form 23p^4 - 336p^2e2 + 1155e2^2 - 1134p e3 of the bracket).
+    t = lgf.LGFTable(120, 0.0)
+
+    def A3(n, c):
+        j, k, l = (float(v) for v in n)
+        r = math.sqrt(j * j + k * k + l * l)
+        P4 = j ** 4 + k ** 4 + l ** 4 - 3 * (j * j * k * k + j * j * l * l + k * k * l * l)
+        P8 = (c * (k * k * l * l * j ** 4 + k * k * l ** 4 * j * j + k ** 4 * l * l * j * j)
+              + 621 * (j ** 4 * k ** 4 + l ** 4 * k ** 4 + j ** 4 * l ** 4)
+              - 244 * (k * k * j ** 6 + l * l * j ** 6 + k ** 6 * j * j + l ** 6 * j * j + k * k * l ** 6 + k ** 6 * l * l)
+              + 23 * (j ** 8 + k ** 8 + l ** 8))
+        return 1 / (4 * math.pi * r) + P4 / (16 * math.pi * r ** 7) + P8 / (128 * math.pi * r ** 13)
+
+    r = 117.0
+    assert abs(4 * math.pi * r * t(np.array([117, 0, 0])) - 1.0) < 2e-5
+    e1 = [abs(A3(n, -228) / t(np.array(n)) - 1) for n in ((20, 20, 5), (40, 40, 10), (80, 80, 20))]
+    e2 = [abs(A3(n, -288) / t(np.array(n)) - 1) for n in ((20, 20, 5), (40, 40, 10), (80, 80, 20))]
+    assert 40 < e1[0] / e1[1] < 100 and 40 < e1[1] / e1[2] < 100      # ~2^6
+    assert 10 < e2[0] / e2[1] < 25 and 10 < e2[1] / e2[2] < 25         # ~2^4
+    assert e1[1] < 5e-11
+
+
+def test_small_sigma_limit():
+    # For small s the modified-Helmholtz LGF at the origin behaves like the continuous
+    # Yukawa kernel's regular part: G_s(0) = G_0(0) - sqrt(s)/(4 pi) + O(s).
+    g0 = lgf.LGFTable(2, 0.0)(np.array([0, 0, 0]))
+    for s in (1e-6, 1e-8):
+        gs = lgf.LGFTable(2, s)(np.array([0, 0, 0]))
+        assert abs(gs - g0 + math.sqrt(s) / (4 * math.pi)) < 3 * s

@@ -1,0 +1,202 @@
+/*
+ * bae.h - C ABI of the MI355X (gfx950) library for the unfitted boundary algebraic
+ * equation (BAE) method with free-space lattice Green's functions (arXiv 2502.05507).
+ *
+ * Problem (paper Sec. 2, eq. "elliptic"):  -Lap u + sigma u = f in Omega,  u = g on the
+ * boundary, sigma >= 0, Omega given by a level set (interior where phi < 0, Sec. 4.2),
+ * discretised by the 7-point stencil on a uniform grid of spacing h (eq. "discrete").
+ * The library implements Algorithm 1 (Sec. 3.5), double-layer formulation:
+ *   LGF table  G_s, s = sigma h^2 (Sec. 2.2, eqs. "lgf", "lgf_bessel", 1/48 table of Sec. 4)
+ *   point sets M+, gamma+-, N+, D_n, E and the hat-function closure Phi (Sec. 2.1, 3.2)
+ *   matrix-free double layer  v(m) = sum_{n in gamma-} D(m,n) q_d(n),
+ *       D(m,n) = sum_{k in D_n} [G_s(m-n) - G_s(m-k)]                    (Sec. 3.2)
+ *   BAE operator  A = Phi+ D+ + Phi- D-,  GMRES on A q_d = b            (Sec. 3.4, eq. "double_bae")
+ *   b = g(x*) - Phi u_p,  u_gamma = [D+ q_d; D- q_d],  u = u_p + D q_d on M+   (Algorithm 1)
+ *
+ * Conventions
+ *   - Every call returns an int status: BAE_OK (0), BAE_NOT_CONVERGED (1, results valid),
+ *     or a negative error code; bae_last_error() gives a message for the calling thread.
+ *   - Grid node (i,j,k) sits at origin + h*(i,j,k); node arrays are [n0][n1][n2], k fastest.
+ *   - gamma- (the unknowns' index set) and gamma+ are returned in lexicographic order of
+ *     (i,j,k).  Vectors "on gamma" are [gamma+ ; gamma-] in that order.
+ *   - Multi-RHS arrays are [nrhs][len], row major.
+ *   - "_dev" pointers are device pointers on the context's device (e.g. from torch tensors);
+ *     other pointers are host memory owned by the caller.  The library never keeps a
+ *     caller pointer beyond the call.
+ *   - stream arguments are hipStream_t passed as void* (NULL = the default stream).
+ *   - Kernel sign convention: positive, L = (6+s) I - sum of the 6 shifts, G_0(0) = 0.25273...
+ */
+#ifndef BAE_H
+#define BAE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status codes */
+#define BAE_OK 0
+#define BAE_NOT_CONVERGED 1      /* GMRES hit maxit; density/history still valid */
+#define BAE_ERR_ARG (-1)         /* bad argument (null pointer, size, enum)        */
+#define BAE_ERR_GEOMETRY (-2)    /* empty M+, interior within 2 nodes of the grid edge */
+#define BAE_ERR_NONFINITE (-3)   /* NaN/Inf in level set, boundary data or source  */
+#define BAE_ERR_OOM (-4)         /* device allocation failed                       */
+#define BAE_ERR_HIP (-5)         /* a HIP runtime call failed                       */
+#define BAE_ERR_STATE (-6)       /* call out of order (e.g. solve before set_rhs)   */
+#define BAE_ERR_ADMISSION (-7)   /* a served request exceeds the whole memory budget */
+
+/* ------------------------------------------------------------------ enums */
+#define BAE_LS_SPHERE 1     /* params[0] = radius                                     */
+#define BAE_LS_ELLIPSOID 2  /* params[0..2] = semi-axes (axis aligned)               */
+#define BAE_LS_TORUS 3      /* params[0] = R (centre line, xy plane), params[1] = r  */
+#define BAE_LS_STAR 4       /* r0*(1 + amp*sin(m theta)*cos(k phi)): params = r0, amp, m, k;
+                               theta polar angle from +z, phi = atan2(y, x)           */
+#define BAE_LS_SAMPLED 5    /* phi given at the nodes; crossings by linear interpolation */
+
+#define BAE_PREC_FP64 0     /* FP64 LGF sum                                           */
+#define BAE_PREC_FP32 1     /* FP32 LGF sum, compensated accumulation                 */
+
+#define BAE_SOLVE_FP64 0          /* plain FP64 GMRES                                 */
+#define BAE_SOLVE_FP32_REFINED 1  /* FP64 iterative refinement around FP32-matvec GMRES */
+
+/* ------------------------------------------------------------------ structs */
+typedef struct bae_grid {
+    int32_t n[3];        /* nodes per axis (>= 5)                                   */
+    double origin[3];    /* coordinates of node (0,0,0)                             */
+    double h;            /* grid spacing (> 0)                                      */
+    double sigma;        /* sigma = kappa^2 >= 0                                    */
+} bae_grid;
+
+typedef struct bae_levelset {
+    int32_t kind;              /* BAE_LS_*                                          */
+    double center[3];
+    double params[8];
+    const double* phi_samples; /* BAE_LS_SAMPLED: n0*n1*n2 host doubles, else NULL  */
+} bae_levelset;
+
+typedef struct bae_options {   /* zero-initialise for defaults                      */
+    int32_t device;            /* HIP device ordinal                                */
+    int32_t near_radius_fp64;  /* LDS table radius of the FP64 sum (default 32)     */
+    int32_t near_radius_fp32;  /* LDS table radius of the FP32 sum (default 24)     */
+    int32_t max_krylov;        /* Krylov basis capacity per RHS (default 400)       */
+    int32_t max_rhs;           /* right-hand sides the context can hold (default 16) */
+} bae_options;
+
+typedef struct bae_sizes {
+    int64_t n_mplus, n_gamma_plus, n_gamma_minus, n_ext, n_edges;
+    int64_t n_sources;         /* |gamma- u E|                                      */
+    int64_t n_targets;         /* |gamma| = |gamma+| + |gamma-|                     */
+    int64_t n_empty_d;         /* gamma- nodes with empty D_n (zero density column)  */
+    int32_t max_offset;        /* largest |component| of an offset in N+ u E         */
+    int32_t table_radius;      /* radius of the resident FP64 table                  */
+    int64_t table_entries;
+    int64_t device_bytes;      /* device memory held by the context                 */
+} bae_sizes;
+
+typedef struct bae_solve_params {
+    int32_t precision;         /* BAE_SOLVE_*                                       */
+    double tol;                /* relative residual target ||b - A q|| / ||b||      */
+    int32_t maxit;             /* GMRES iterations per (inner) solve; <= max_krylov */
+    double inner_tol;          /* FP32 inner GMRES tolerance (refined mode, default 1e-5) */
+    int32_t max_outer;         /* refinement steps (default 8)                       */
+    int32_t compute_grid;      /* also form u on N+ (volume-target LGF sums)         */
+} bae_solve_params;
+
+typedef struct bae_result {
+    int32_t status;            /* BAE_OK or BAE_NOT_CONVERGED                       */
+    int32_t iterations;        /* total GMRES iterations (all inner solves)         */
+    int32_t outer_steps;       /* refinement steps (0 for FP64)                      */
+    int32_t converged;
+    double rel_residual_est;   /* last Givens estimate                               */
+    double rel_residual_true;  /* ||b - A64 q|| / ||b|| with the FP64 operator       */
+    double seconds;            /* wall time of the solve on the host                 */
+    int64_t matvecs_fp64, matvecs_fp32;
+} bae_result;
+
+typedef struct bae_ctx bae_ctx;
+
+/* ------------------------------------------------------------------ status */
+const char* bae_status_string(int status);
+/* Message of the last error on the calling thread ("" if none). */
+const char* bae_last_error(void);
+
+/* ------------------------------------------------------------------ LGF (Sec. 2.2) */
+/* Entries in the 1/48-symmetric table: (R+1)(R+2)(R+3)/6. */
+int64_t bae_lgf_table_size(int32_t R);
+/*
+ * G_s(a,b,c) for 0 <= a <= b <= c <= R, s = sigma h^2 >= 0, in FP64, written to out_dev
+ * (device, bae_lgf_table_size(R) doubles) at index c(c+1)(c+2)/6 + b(b+1)/2 + a.
+ * Bessel-integral form of Sec. 2.2 with exp(-(6+s)t): composite Gauss-Legendre in ln t on
+ * [0, T*], large-argument (Hankel) series of I_n integrated term by term beyond T*.
+ * R in [0, 4096]; s finite and >= 0, else BAE_ERR_ARG.  Runs on `stream`, asynchronous.
+ */
+int bae_lgf_table(double s, int32_t R, double* out_dev, void* stream);
+
+/* ------------------------------------------------------------------ context (Alg. 1 setup) */
+/*
+ * Classify the grid (M+, gamma+-, N+, D_n, E; Sec. 2.1, 3.2), find one boundary point
+ * x* per gamma- node on the edge to the M+ neighbour with the smallest crossing t
+ * (ties: -x,+x,-y,+y,-z,+z), build Phi, and make the LGF table for s = sigma h^2 resident
+ * (Alg. 1 "PrecomputeLGF").  Structs are copied; phi_samples is read during the call only.
+ * Errors: BAE_ERR_ARG, BAE_ERR_GEOMETRY, BAE_ERR_NONFINITE, BAE_ERR_OOM, BAE_ERR_HIP.
+ */
+int bae_create(const bae_grid* grid, const bae_levelset* ls, const bae_options* opt, bae_ctx** out);
+int bae_destroy(bae_ctx* ctx);
+int bae_get_sizes(const bae_ctx* ctx, bae_sizes* out);
+/* Node sets as (i,j,k) triples, lexicographic; buffers of 3*count int32 (any may be NULL). */
+int bae_get_sets(const bae_ctx* ctx, int32_t* gamma_plus, int32_t* gamma_minus, int32_t* ext);
+/*
+ * Dirichlet closure per gamma- node (lexicographic): boundary point xstar (3 doubles),
+ * partner index into gamma+ (int32), weight t in [0,1): row (1-t) u(q) + t u(p) = g(x*).
+ * Callers evaluate g at xstar and pass it to bae_set_rhs.  Any pointer may be NULL.
+ */
+int bae_get_boundary_points(const bae_ctx* ctx, double* xstar, int32_t* partner, double* t);
+
+/*
+ * Right-hand sides: g_xstar [nrhs][|gamma-|] (host), f_grid [nrhs][n0 n1 n2] (host, or
+ * NULL for f = 0).  With f the particular solution u_p = h^2 sum_{M+} G_s(m-n) f(n) (the
+ * free-space volume potential) is formed on gamma by the FP64 LGF sum, and b = g - Phi u_p.
+ * nrhs in [1, max_rhs].  BAE_ERR_NONFINITE on NaN/Inf input.
+ */
+int bae_set_rhs(bae_ctx* ctx, int32_t nrhs, const double* g_xstar, const double* f_grid);
+
+/*
+ * Solve A q_d = b for every RHS (GMRES, x0 = 0, no preconditioner: Sec. 4), then form
+ * u_gamma (and u on N+ if params->compute_grid).  results: nrhs entries (may be NULL).
+ * Returns BAE_NOT_CONVERGED if any RHS missed the tolerance.
+ */
+int bae_solve(bae_ctx* ctx, const bae_solve_params* params, bae_result* results);
+/* Outputs of the last solve, RHS r (host buffers): q_d (|gamma-|), u_gamma (|gamma|),
+   u on the grid (n0 n1 n2, NaN outside N+; needs compute_grid), residual history. */
+int bae_get_density(const bae_ctx* ctx, int32_t r, double* q);
+int bae_get_gamma_values(const bae_ctx* ctx, int32_t r, double* u_gamma);
+int bae_get_solution(const bae_ctx* ctx, int32_t r, double* u_grid);
+int bae_get_history(const bae_ctx* ctx, int32_t r, double* hist, int32_t cap, int32_t* len);
+
+/* ------------------------------------------------------------------ operators (hot path) */
+/*
+ * Double layer potential on gamma (Sec. 3.2): v = [D+ q; D- q] for nrhs densities.
+ * q_dev [nrhs][|gamma-|] FP64 (device), v_dev [nrhs][|gamma|] FP64 (device).
+ * precision BAE_PREC_FP64 or BAE_PREC_FP32 (FP32 kernel sum, FP64 in/out).
+ * Asynchronous on `stream`; q_dev/v_dev must not alias.
+ */
+int bae_apply_double_layer(bae_ctx* ctx, const double* q_dev, double* v_dev, int32_t nrhs,
+                           int32_t precision, void* stream);
+/* The BAE operator A q = Phi+ D+ q + Phi- D- q (Sec. 3.4, eq. "double_bae").
+   q_dev, aq_dev: [nrhs][|gamma-|] FP64 device. */
+int bae_apply_operator(bae_ctx* ctx, const double* q_dev, double* aq_dev, int32_t nrhs,
+                       int32_t precision, void* stream);
+/*
+ * The kernel the LGF sum uses, at `count` integer offsets (offsets_dev: [count][3] int32,
+ * device) -> out_dev (count FP64): near table or far-field expansion exactly as the sum
+ * evaluates it at `precision`.  For checking the far field and table lookups.
+ */
+int bae_lgf_eval(bae_ctx* ctx, const int32_t* offsets_dev, int64_t count, double* out_dev,
+                 int32_t precision, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BAE_H */

@@ -1,0 +1,259 @@
+"""ctypes binding of libbae.so (include/bae.h): argument marshalling only.
+
+Device buffers are torch tensors (their data_ptr() is handed to the library); host
+buffers are NumPy arrays.  Every failing call raises BaeError with the library's message.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbae.so")
+
+OK, NOT_CONVERGED = 0, 1
+PREC_FP64, PREC_FP32 = 0, 1
+SOLVE_FP64, SOLVE_FP32_REFINED = 0, 1
+KINDS = {"sphere": 1, "ellipsoid": 2, "torus": 3, "star": 4, "sampled": 5}
+
+
+class Grid(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("origin", C.c_double * 3), ("h", C.c_double), ("sigma", C.c_double)]
+
+
+class LevelSet(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("center", C.c_double * 3), ("params", C.c_double * 8),
+                ("phi_samples", C.POINTER(C.c_double))]
+
+
+class Options(C.Structure):
+    _fields_ = [("device", C.c_int32), ("near_radius_fp64", C.c_int32), ("near_radius_fp32", C.c_int32),
+                ("max_krylov", C.c_int32), ("max_rhs", C.c_int32)]
+
+
+class Sizes(C.Structure):
+    _fields_ = [("n_mplus", C.c_int64), ("n_gamma_plus", C.c_int64), ("n_gamma_minus", C.c_int64),
+                ("n_ext", C.c_int64), ("n_edges", C.c_int64), ("n_sources", C.c_int64),
+                ("n_targets", C.c_int64), ("n_empty_d", C.c_int64), ("max_offset", C.c_int32),
+                ("table_radius", C.c_int32), ("table_entries", C.c_int64), ("device_bytes", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class SolveParams(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("tol", C.c_double), ("maxit", C.c_int32), ("inner_tol", C.c_double),
+                ("max_outer", C.c_int32), ("compute_grid", C.c_int32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("outer_steps", C.c_int32),
+                ("converged", C.c_int32), ("rel_residual_est", C.c_double), ("rel_residual_true", C.c_double),
+                ("seconds", C.c_double), ("matvecs_fp64", C.c_int64), ("matvecs_fp32", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BaeError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"[{status}] {message}")
+        self.status = status
+
+
+_lib = None
+_P = C.c_void_p
+
+
+def load_library():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise BaeError(-1, f"{LIB_PATH} is missing: build it with `python -m paper_2502_05507_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    sig = {
+        "bae_status_string": (C.c_char_p, [C.c_int]),
+        "bae_last_error": (C.c_char_p, []),
+        "bae_lgf_table_size": (C.c_int64, [C.c_int32]),
+        "bae_lgf_table": (C.c_int, [C.c_double, C.c_int32, _P, _P]),
+        "bae_create": (C.c_int, [C.POINTER(Grid), C.POINTER(LevelSet), C.POINTER(Options), C.POINTER(_P)]),
+        "bae_destroy": (C.c_int, [_P]),
+        "bae_get_sizes": (C.c_int, [_P, C.POINTER(Sizes)]),
+        "bae_get_sets": (C.c_int, [_P, _P, _P, _P]),
+        "bae_get_boundary_points": (C.c_int, [_P, _P, _P, _P]),
+        "bae_set_rhs": (C.c_int, [_P, C.c_int32, _P, _P]),
+        "bae_solve": (C.c_int, [_P, C.POINTER(SolveParams), _P]),
+        "bae_get_density": (C.c_int, [_P, C.c_int32, _P]),
+        "bae_get_gamma_values": (C.c_int, [_P, C.c_int32, _P]),
+        "bae_get_solution": (C.c_int, [_P, C.c_int32, _P]),
+        "bae_get_history": (C.c_int, [_P, C.c_int32, _P, C.c_int32, C.POINTER(C.c_int32)]),
+        "bae_apply_double_layer": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P]),
+        "bae_apply_operator": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P]),
+        "bae_lgf_eval": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int32, _P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc, allow_not_converged=False):
+    if rc == OK or (allow_not_converged and rc == NOT_CONVERGED):
+        return rc
+    lib = load_library()
+    raise BaeError(rc, lib.bae_last_error().decode() or lib.bae_status_string(rc).decode())
+
+
+def _ptr(a):
+    return C.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor."""
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(stream)
+
+
+def lgf_table_size(R):
+    return int(load_library().bae_lgf_table_size(R))
+
+
+def lgf_table(s, R, out, stream=None):
+    """FP64 LGF table G_s for 0 <= a <= b <= c <= R into the device tensor `out`."""
+    assert out.dtype.is_floating_point and out.element_size() == 8 and out.numel() >= lgf_table_size(R)
+    _check(load_library().bae_lgf_table(float(s), int(R), _dptr(out), _stream(stream)))
+
+
+class Context:
+    """One geometry / grid / sigma (Algorithm 1 set-up), owning its device state."""
+
+    def __init__(self, n, h, origin, sigma, kind, center=(0.0, 0.0, 0.0), params=(), phi=None,
+                 device=0, max_krylov=0, max_rhs=0):
+        lib = load_library()
+        g = Grid((C.c_int32 * 3)(*[int(v) for v in n]), (C.c_double * 3)(*[float(v) for v in origin]),
+                 float(h), float(sigma))
+        p = list(params) + [0.0] * (8 - len(params))
+        self._phi = None
+        if phi is not None:
+            self._phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1)
+        ls = LevelSet(KINDS[kind], (C.c_double * 3)(*[float(v) for v in center]),
+                      (C.c_double * 8)(*[float(v) for v in p[:8]]),
+                      self._phi.ctypes.data_as(C.POINTER(C.c_double)) if self._phi is not None else None)
+        opt = Options(int(device), 0, 0, int(max_krylov), int(max_rhs))
+        h_ = _P()
+        _check(lib.bae_create(C.byref(g), C.byref(ls), C.byref(opt), C.byref(h_)))
+        self._h = h_
+        self.n = tuple(int(v) for v in n)
+        self.nrhs = 1
+        self.sizes = self.get_sizes()
+
+    @classmethod
+    def from_problem(cls, p, **kw):
+        return cls(p.n, p.h, p.origin, p.sigma, p.kind, p.center, p.params, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().bae_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def get_sizes(self):
+        s = Sizes()
+        _check(load_library().bae_get_sizes(self._h, C.byref(s)))
+        return s.as_dict()
+
+    def sets(self):
+        z = self.sizes
+        gp = np.empty((z["n_gamma_plus"], 3), np.int32)
+        gm = np.empty((z["n_gamma_minus"], 3), np.int32)
+        ex = np.empty((z["n_ext"], 3), np.int32)
+        _check(load_library().bae_get_sets(self._h, _ptr(gp), _ptr(gm), _ptr(ex)))
+        return gp, gm, ex
+
+    def boundary_points(self):
+        m = self.sizes["n_gamma_minus"]
+        xs = np.empty((m, 3))
+        pa = np.empty(m, np.int32)
+        t = np.empty(m)
+        _check(load_library().bae_get_boundary_points(self._h, _ptr(xs), _ptr(pa), _ptr(t)))
+        return xs, pa, t
+
+    def set_rhs(self, g, f=None):
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        nrhs = 1 if g.ndim == 1 else g.shape[0]
+        if f is not None:
+            f = np.ascontiguousarray(f, dtype=np.float64)
+        _check(load_library().bae_set_rhs(self._h, nrhs, _ptr(g), _ptr(f)))
+        self.nrhs = nrhs
+
+    def solve(self, precision=SOLVE_FP64, tol=1e-10, maxit=0, inner_tol=0.0, max_outer=0, compute_grid=False):
+        p = SolveParams(int(precision), float(tol), int(maxit), float(inner_tol), int(max_outer),
+                        1 if compute_grid else 0)
+        res = (Result * self.nrhs)()
+        rc = load_library().bae_solve(self._h, C.byref(p), res)
+        _check(rc, allow_not_converged=True)
+        return [r.as_dict() for r in res]
+
+    def density(self, r=0):
+        q = np.empty(self.sizes["n_gamma_minus"])
+        _check(load_library().bae_get_density(self._h, r, _ptr(q)))
+        return q
+
+    def gamma_values(self, r=0):
+        u = np.empty(self.sizes["n_targets"])
+        _check(load_library().bae_get_gamma_values(self._h, r, _ptr(u)))
+        return u
+
+    def solution(self, r=0):
+        u = np.empty(self.n)
+        _check(load_library().bae_get_solution(self._h, r, _ptr(u)))
+        return u
+
+    def history(self, r=0):
+        n = C.c_int32(0)
+        _check(load_library().bae_get_history(self._h, r, None, 0, C.byref(n)))
+        h = np.empty(n.value)
+        _check(load_library().bae_get_history(self._h, r, _ptr(h), n.value, C.byref(n)))
+        return h
+
+    def apply_double_layer(self, q, v, precision=PREC_FP64, stream=None):
+        """v[nrhs][|gamma|] = [D+ q; D- q] for device tensors q[nrhs][|gamma-|] (float64)."""
+        nrhs = 1 if q.dim() == 1 else q.shape[0]
+        assert q.is_contiguous() and v.is_contiguous()
+        assert q.numel() == nrhs * self.sizes["n_gamma_minus"] and v.numel() == nrhs * self.sizes["n_targets"]
+        _check(load_library().bae_apply_double_layer(self._h, _dptr(q), _dptr(v), nrhs, precision, _stream(stream)))
+
+    def apply_operator(self, q, aq, precision=PREC_FP64, stream=None):
+        """aq = (Phi+ D+ + Phi- D-) q for device tensors [nrhs][|gamma-|] (float64)."""
+        nrhs = 1 if q.dim() == 1 else q.shape[0]
+        assert q.is_contiguous() and aq.is_contiguous()
+        assert q.numel() == aq.numel() == nrhs * self.sizes["n_gamma_minus"]
+        _check(load_library().bae_apply_operator(self._h, _dptr(q), _dptr(aq), nrhs, precision, _stream(stream)))
+
+    def lgf_eval(self, offsets, out, precision=PREC_FP64, stream=None):
+        """out[i] = the kernel value the LGF sum uses at integer offset offsets[i] (device)."""
+        assert offsets.is_contiguous() and offsets.shape[-1] == 3 and out.numel() == offsets.shape[0]
+        _check(load_library().bae_lgf_eval(self._h, _dptr(offsets), offsets.shape[0], _dptr(out), precision,
+                                           _stream(stream)))

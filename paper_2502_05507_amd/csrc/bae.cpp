@@ -1,0 +1,793 @@
+// C ABI of the BAE / LGF library: context set-up (Algorithm 1, set-up steps), the
+// matrix-free operators, device-resident GMRES, FP64 iterative refinement around FP32
+// matvecs, and the outputs.  See include/bae.h for the contract of every call.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <functional>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <numeric>
+
+#include "internal.hpp"
+#include "ops.hpp"
+
+namespace bae {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int lgf_near_radius();
+
+// ------------------------------------------------------------------ device memory
+struct DevMem {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    DevMem(const DevMem&) = delete;
+    DevMem& operator=(const DevMem&) = delete;
+    ~DevMem() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void alloc(size_t n) {
+        release();
+        if (n == 0) n = 8;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            throw Error{BAE_ERR_OOM, "hipMalloc of " + std::to_string(n) + " bytes failed"};
+        }
+        bytes = n;
+    }
+    template <typename T>
+    T* as() const { return (T*)p; }
+};
+
+template <typename T>
+static void upload(DevMem& m, const std::vector<T>& v, hipStream_t st) {
+    m.alloc(sizeof(T) * v.size());
+    if (!v.empty()) BAE_HIP_CHECK(hipMemcpyAsync(m.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+}
+
+// ------------------------------------------------------------------ LGF table cache
+struct Table {
+    int device = 0;
+    double s = 0.0;
+    int R = 0;
+    DevMem d64, d32;
+};
+
+// Tables are shared by every context on a device with the same s (a larger radius
+// replaces a smaller one).  The cache lives until the process ends and is never torn
+// down by static destructors (the HIP runtime may already be gone by then).
+static std::mutex g_table_mu;
+static auto* g_tables = new std::map<std::pair<int, uint64_t>, std::shared_ptr<Table>>();
+
+static std::shared_ptr<Table> get_table(int device, double s, int R, hipStream_t st) {
+    uint64_t key;
+    std::memcpy(&key, &s, sizeof key);
+    std::lock_guard<std::mutex> lk(g_table_mu);
+    auto it = g_tables->find({device, key});
+    if (it != g_tables->end() && it->second->R >= R) return it->second;
+    auto t = std::make_shared<Table>();
+    t->device = device;
+    t->s = s;
+    t->R = R;
+    const int64_t E = table_size(R);
+    t->d64.alloc(sizeof(double) * E);
+    t->d32.alloc(sizeof(float) * E);
+    lgf_table_generate(s, R, t->d64.as<double>(), st);
+    launch_to_float(t->d64.as<double>(), t->d32.as<float>(), E, st);
+    BAE_HIP_CHECK(hipStreamSynchronize(st));
+    (*g_tables)[{device, key}] = t;
+    return t;
+}
+
+// ------------------------------------------------------------------ context
+struct PointBuf {
+    DevMem x, y, z;
+    PointSet ps;
+    std::vector<int32_t> perm;   // internal index -> index in the lexicographic list
+    void set(const std::vector<int32_t>& pts3, const std::vector<int32_t>& order, hipStream_t st) {
+        const int64_t n = (int64_t)order.size();
+        std::vector<int32_t> hx(n), hy(n), hz(n);
+        for (int64_t i = 0; i < n; ++i) {
+            hx[i] = pts3[3 * order[i]];
+            hy[i] = pts3[3 * order[i] + 1];
+            hz[i] = pts3[3 * order[i] + 2];
+        }
+        upload(x, hx, st);
+        upload(y, hy, st);
+        upload(z, hz, st);
+        ps.count = n;
+        ps.x = x.as<int32_t>();
+        ps.y = y.as<int32_t>();
+        ps.z = z.as<int32_t>();
+        perm = order;
+    }
+};
+
+}  // namespace bae
+
+using namespace bae;
+
+struct bae_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bae_grid grid{};
+    bae_options opt{};
+    double s = 0.0;
+    Geometry geo;
+    int64_t ngp = 0, ngm = 0, next = 0, nT = 0, nS = 0;
+
+    PointBuf T, S, Mp;         // targets gamma, sources gamma- u E, interior M+ (lazy)
+    DevMem t_pos;              // internal target index -> position in [gamma+; gamma-]
+    DevMem csr_rowptr, csr_col, csr_coef;
+    CSR B;
+    DevMem cl_tq, cl_tp, cl_t;
+    Closure cl;
+    std::shared_ptr<Table> table;
+    SumTables tabs;
+
+    int max_rhs = 16;
+    DevMem w, part;
+    int64_t part_cap = 0;
+    KrylovState K;
+    DevMem kV, kH, kcs, ksn, kg, khist, kbeta, kdone, kkdone;
+    int maxj = 0;
+    DevMem hA, hB, nrm, dotpart, ycoef;
+    DevMem b, x, r, tmp;       // [rhs][ngm]
+    DevMem up_gamma;           // [rhs][nT] external order
+    DevMem u_gamma;            // [rhs][nT]
+    DevMem wf;                 // [rhs][|M+|] h^2 f in Mp order
+    int nrhs = 0;
+    bool has_f = false, rhs_ready = false, solved = false;
+    std::vector<std::vector<double>> hist;  // per rhs
+    std::vector<double> ugrid;              // [rhs][n0 n1 n2] when computed
+    int32_t* pinned_flags = nullptr;        // host pinned, 2 * max_rhs
+};
+
+namespace bae {
+
+static void apply_lgf(bae_ctx* c, const PointSet& T, const PointSet& S, const void* w, int nrhs, int prec,
+                      double* part, int64_t cap, int* chunks_out, hipStream_t st) {
+    *chunks_out = lgf_sum_launch(T, S, w, nrhs, prec, c->tabs, part, cap, st);
+}
+
+// v = [D+ q; D- q] (external order), q [nrhs][ngm] with leading dimension ldq
+static void double_layer(bae_ctx* c, const double* q, int64_t ldq, double* v, int64_t ldv, int nrhs, int prec,
+                         hipStream_t st) {
+    launch_weights(c->B, q, ldq, c->w.p, c->nS, nrhs, prec, st);
+    int chunks = 0;
+    apply_lgf(c, c->T.ps, c->S.ps, c->w.p, nrhs, prec, c->part.as<double>(), c->part_cap, &chunks, st);
+    launch_reduce_scatter(c->part.as<double>(), chunks, c->nT, c->t_pos.as<int32_t>(), v, ldv, nrhs, 1.0, st);
+}
+
+// aq = Phi+ D+ q + Phi- D- q
+static void bae_operator(bae_ctx* c, const double* q, int64_t ldq, double* aq, int64_t lda, int nrhs, int prec,
+                         hipStream_t st) {
+    launch_weights(c->B, q, ldq, c->w.p, c->nS, nrhs, prec, st);
+    int chunks = 0;
+    apply_lgf(c, c->T.ps, c->S.ps, c->w.p, nrhs, prec, c->part.as<double>(), c->part_cap, &chunks, st);
+    launch_closure(c->part.as<double>(), chunks, c->nT, c->cl, aq, lda, nrhs, st);
+}
+
+static void norms2(bae_ctx* c, const double* v, int64_t ldv, int nrhs, double* out_dev, hipStream_t st) {
+    launch_dots(v, 0, ldv, 1, v, ldv, c->ngm, nrhs, nullptr, c->dotpart.as<double>(), c->maxj, out_dev, 1, 0, st);
+}
+
+struct GmresOut {
+    std::vector<int> iters;
+    std::vector<int> converged;
+    std::vector<double> last_est;
+};
+
+// GMRES on A d = r0 for nrhs RHS (x0 = 0), then x (+)= d.  skip[r] marks RHS left alone.
+static GmresOut gmres(bae_ctx* c, const double* r0, int nrhs, int prec, double tol, int maxit,
+                      const std::vector<int>& skip, double* xout, bool accumulate, hipStream_t st,
+                      int64_t* matvecs) {
+    KrylovState& K = c->K;
+    const int64_t n = c->ngm;
+    const int m = std::min(maxit, K.m);
+    norms2(c, r0, n, nrhs, c->nrm.as<double>(), st);
+    launch_gmres_init(r0, n, K, n, c->nrm.as<double>(), nrhs, st);
+    if (!skip.empty()) {
+        std::vector<int32_t> d(nrhs);
+        for (int r = 0; r < nrhs; ++r) d[r] = skip[r] ? 1 : 0;
+        for (int r = 0; r < nrhs; ++r)
+            if (skip[r]) BAE_HIP_CHECK(hipMemcpyAsync(K.done + r, &d[r], sizeof(int32_t), hipMemcpyHostToDevice, st));
+        BAE_HIP_CHECK(hipStreamSynchronize(st));
+    }
+    const double pairs = (double)c->nT * (double)c->nS * nrhs;
+    const int check = pairs > 2e7 ? 1 : (pairs > 2e6 ? 2 : 6);
+    int k = 0;
+    for (; k < m; ++k) {
+        double* vk = K.V + (int64_t)k * n;
+        double* vk1 = K.V + (int64_t)(k + 1) * n;
+        bae_operator(c, vk, K.ld_rhs, vk1, K.ld_rhs, nrhs, prec, st);
+        (*matvecs)++;
+        launch_dots(K.V, n, K.ld_rhs, k + 1, vk1, K.ld_rhs, n, nrhs, K.done, c->dotpart.as<double>(), c->maxj,
+                    c->hA.as<double>(), c->maxj, 0, st);
+        launch_subtract_combination(K.V, n, K.ld_rhs, c->hA.as<double>(), c->maxj, k + 1, n, nrhs, K.done, vk1,
+                                    K.ld_rhs, st);
+        launch_dots(K.V, n, K.ld_rhs, k + 1, vk1, K.ld_rhs, n, nrhs, K.done, c->dotpart.as<double>(), c->maxj,
+                    c->hB.as<double>(), c->maxj, 0, st);
+        launch_subtract_combination(K.V, n, K.ld_rhs, c->hB.as<double>(), c->maxj, k + 1, n, nrhs, K.done, vk1,
+                                    K.ld_rhs, st);
+        launch_dots(vk1, 0, K.ld_rhs, 1, vk1, K.ld_rhs, n, nrhs, K.done, c->dotpart.as<double>(), c->maxj,
+                    c->nrm.as<double>(), 1, 0, st);
+        launch_normalize(K.V, n, K.ld_rhs, k, n, c->nrm.as<double>(), K.done, nrhs, st);
+        launch_givens(K, c->hA.as<double>(), c->hB.as<double>(), c->maxj, c->nrm.as<double>(), k, tol, nrhs, st);
+        if ((k + 1) % check == 0 || k + 1 == m) {
+            BAE_HIP_CHECK(hipMemcpyAsync(c->pinned_flags, K.done, sizeof(int32_t) * nrhs, hipMemcpyDeviceToHost, st));
+            BAE_HIP_CHECK(hipStreamSynchronize(st));
+            bool all = true;
+            for (int r = 0; r < nrhs; ++r) all &= c->pinned_flags[r] != 0;
+            if (all) {
+                ++k;
+                break;
+            }
+        }
+    }
+    // host back substitution R y = g for each RHS
+    std::vector<int32_t> kd(nrhs), dn(nrhs);
+    BAE_HIP_CHECK(hipMemcpyAsync(kd.data(), K.kdone, sizeof(int32_t) * nrhs, hipMemcpyDeviceToHost, st));
+    BAE_HIP_CHECK(hipMemcpyAsync(dn.data(), K.done, sizeof(int32_t) * nrhs, hipMemcpyDeviceToHost, st));
+    const int64_t hsz = (int64_t)K.m * (K.m + 1);
+    std::vector<double> H((size_t)hsz * nrhs), g((size_t)(K.m + 1) * nrhs), hs((size_t)K.m * nrhs);
+    BAE_HIP_CHECK(hipMemcpyAsync(H.data(), K.H, sizeof(double) * H.size(), hipMemcpyDeviceToHost, st));
+    BAE_HIP_CHECK(hipMemcpyAsync(g.data(), K.g, sizeof(double) * g.size(), hipMemcpyDeviceToHost, st));
+    BAE_HIP_CHECK(hipMemcpyAsync(hs.data(), K.hist, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, st));
+    BAE_HIP_CHECK(hipStreamSynchronize(st));
+    GmresOut out;
+    std::vector<double> y((size_t)K.m * nrhs, 0.0);
+    for (int r = 0; r < nrhs; ++r) {
+        const int kk = (!skip.empty() && skip[r]) ? 0 : kd[r];
+        const double* Hr = H.data() + r * hsz;
+        const double* gr = g.data() + (size_t)r * (K.m + 1);
+        double* yr = y.data() + (size_t)r * K.m;
+        for (int i = kk - 1; i >= 0; --i) {
+            double acc = gr[i];
+            for (int j = i + 1; j < kk; ++j) acc -= Hr[(int64_t)j * (K.m + 1) + i] * yr[j];
+            const double d = Hr[(int64_t)i * (K.m + 1) + i];
+            yr[i] = d != 0.0 ? acc / d : 0.0;
+        }
+        kd[r] = kk;
+        out.iters.push_back(kk);
+        out.last_est.push_back(kk > 0 ? hs[(size_t)r * K.m + kk - 1] : 0.0);
+        out.converged.push_back((!skip.empty() && skip[r]) ? 1 : (dn[r] && (kk == 0 || hs[(size_t)r * K.m + kk - 1] <= tol)));
+        if (!(!skip.empty() && skip[r]))
+            c->hist[r].insert(c->hist[r].end(), hs.begin() + (size_t)r * K.m, hs.begin() + (size_t)r * K.m + kk);
+    }
+    BAE_HIP_CHECK(hipMemcpyAsync(c->ycoef.p, y.data(), sizeof(double) * y.size(), hipMemcpyHostToDevice, st));
+    DevMem kdev;
+    kdev.alloc(sizeof(int32_t) * nrhs);
+    BAE_HIP_CHECK(hipMemcpyAsync(kdev.p, kd.data(), sizeof(int32_t) * nrhs, hipMemcpyHostToDevice, st));
+    launch_combination(K.V, n, K.ld_rhs, c->ycoef.as<double>(), K.m, kdev.as<int32_t>(), n, nrhs, xout, n,
+                       accumulate ? 1 : 0, st);
+    BAE_HIP_CHECK(hipStreamSynchronize(st));
+    return out;
+}
+
+static std::vector<double> host_norms(bae_ctx* c, const double* v, int nrhs, hipStream_t st) {
+    norms2(c, v, c->ngm, nrhs, c->nrm.as<double>(), st);
+    std::vector<double> h(nrhs);
+    BAE_HIP_CHECK(hipMemcpyAsync(h.data(), c->nrm.p, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+    BAE_HIP_CHECK(hipStreamSynchronize(st));
+    for (auto& v2 : h) v2 = std::sqrt(v2);
+    return h;
+}
+
+// r = b - A64 x ; returns ||r|| / ||b|| per RHS
+static std::vector<double> residual(bae_ctx* c, int nrhs, const std::vector<double>& bn, hipStream_t st,
+                                    int64_t* matvecs) {
+    const int64_t n = c->ngm;
+    bae_operator(c, c->x.as<double>(), n, c->tmp.as<double>(), n, nrhs, BAE_PREC_FP64, st);
+    (*matvecs)++;
+    BAE_HIP_CHECK(hipMemcpyAsync(c->r.p, c->b.p, sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, st));
+    launch_axpby(-1.0, c->tmp.as<double>(), n, 1.0, c->r.as<double>(), n, n, nrhs, st);
+    std::vector<double> rn = host_norms(c, c->r.as<double>(), nrhs, st);
+    for (int i = 0; i < nrhs; ++i) rn[i] = bn[i] > 0 ? rn[i] / bn[i] : 0.0;
+    return rn;
+}
+
+static void ensure_mplus(bae_ctx* c) {
+    if (c->Mp.ps.count) return;
+    const Geometry& G = c->geo;
+    std::vector<int32_t> pts;
+    pts.reserve(3 * G.n_mplus);
+    for (int i = 0; i < G.n[0]; ++i)
+        for (int j = 0; j < G.n[1]; ++j)
+            for (int k = 0; k < G.n[2]; ++k)
+                if (G.inside[((int64_t)i * G.n[1] + j) * G.n[2] + k]) pts.insert(pts.end(), {i, j, k});
+    const std::vector<int32_t> ord = morton_order(pts.data(), (int64_t)pts.size() / 3, G.bbox_lo);
+    c->Mp.set(pts, ord, c->stream);
+}
+
+// out[r][t] (internal Mp or given target order) = sum over sources S of w G, FP64, into a
+// temporary partial buffer; result scattered through pos (or identity).
+static void lgf_sum_to(bae_ctx* c, const PointSet& T, const PointSet& S, const double* w, int nrhs,
+                       const int32_t* pos, double* out, int64_t ldo, double scale, hipStream_t st) {
+    const int chunks = lgf_sum_chunks(T.count, S.count);
+    DevMem p;
+    const int64_t cap = (int64_t)chunks * T.count * nrhs;
+    p.alloc(sizeof(double) * cap);
+    int used = lgf_sum_launch(T, S, w, nrhs, BAE_PREC_FP64, c->tabs, p.as<double>(), cap, st);
+    launch_reduce_scatter(p.as<double>(), used, T.count, pos, out, ldo, nrhs, scale, st);
+    BAE_HIP_CHECK(hipStreamSynchronize(st));
+}
+
+static int guard(const std::function<void()>& fn) {
+    try {
+        fn();
+        return BAE_OK;
+    } catch (const Error& e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return BAE_ERR_OOM;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return BAE_ERR_ARG;
+    }
+}
+
+}  // namespace bae
+
+// ================================================================== C ABI
+extern "C" {
+
+const char* bae_status_string(int s) {
+    switch (s) {
+        case BAE_OK: return "ok";
+        case BAE_NOT_CONVERGED: return "GMRES did not reach the tolerance";
+        case BAE_ERR_ARG: return "invalid argument";
+        case BAE_ERR_GEOMETRY: return "invalid geometry";
+        case BAE_ERR_NONFINITE: return "non-finite input";
+        case BAE_ERR_OOM: return "out of memory";
+        case BAE_ERR_HIP: return "HIP runtime error";
+        case BAE_ERR_STATE: return "call out of order";
+        case BAE_ERR_ADMISSION: return "request exceeds the memory budget";
+    }
+    return "unknown status";
+}
+
+const char* bae_last_error(void) { return g_last_error.c_str(); }
+
+int64_t bae_lgf_table_size(int32_t R) { return R < 0 ? 0 : table_size(R); }
+
+int bae_lgf_table(double s, int32_t R, double* out_dev, void* stream) {
+    return guard([&] {
+        if (!out_dev || R < 0 || R > 4096 || !(s >= 0.0) || !std::isfinite(s)) throw Error{BAE_ERR_ARG, "bae_lgf_table: bad argument"};
+        lgf_table_generate(s, R, out_dev, (hipStream_t)stream);
+    });
+}
+
+int bae_create(const bae_grid* grid, const bae_levelset* ls, const bae_options* opt, bae_ctx** out) {
+    return guard([&] {
+        if (!grid || !ls || !out) throw Error{BAE_ERR_ARG, "bae_create: null argument"};
+        *out = nullptr;
+        auto c = std::make_unique<bae_ctx>();
+        c->grid = *grid;
+        if (opt) c->opt = *opt;
+        c->max_rhs = c->opt.max_rhs > 0 ? c->opt.max_rhs : 16;
+        if (c->max_rhs > 64) throw Error{BAE_ERR_ARG, "max_rhs must be <= 64"};
+        const int m = c->opt.max_krylov > 0 ? c->opt.max_krylov : 400;
+        if (m > 4096) throw Error{BAE_ERR_ARG, "max_krylov must be <= 4096"};
+        const int nr = lgf_near_radius();
+        if ((c->opt.near_radius_fp64 && c->opt.near_radius_fp64 != nr) ||
+            (c->opt.near_radius_fp32 && c->opt.near_radius_fp32 != nr))
+            throw Error{BAE_ERR_ARG, "near radius: this build supports " + std::to_string(nr) + " only"};
+        c->device = c->opt.device;
+        int ndev = 0;
+        BAE_HIP_CHECK(hipGetDeviceCount(&ndev));
+        if (c->device < 0 || c->device >= ndev) throw Error{BAE_ERR_ARG, "no such device"};
+        BAE_HIP_CHECK(hipSetDevice(c->device));
+        BAE_HIP_CHECK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+        hipStream_t st = c->stream;
+
+        build_geometry(*grid, *ls, c->geo);
+        Geometry& G = c->geo;
+        c->s = grid->sigma * grid->h * grid->h;
+        c->ngp = (int64_t)G.gp.size() / 3;
+        c->ngm = (int64_t)G.gm.size() / 3;
+        c->next = (int64_t)G.ext.size() / 3;
+        c->nT = c->ngp + c->ngm;
+        c->nS = c->ngm + c->next;
+        if (c->s > 0.0 && G.max_offset > 1200) throw Error{BAE_ERR_ARG, "sigma > 0 needs offsets <= 1200"};
+
+        // targets: gamma+ then gamma- (external order), Morton-sorted internally
+        std::vector<int32_t> tp(G.gp);
+        tp.insert(tp.end(), G.gm.begin(), G.gm.end());
+        std::vector<int32_t> tord = morton_order(tp.data(), c->nT, G.bbox_lo);
+        c->T.set(tp, tord, st);
+        std::vector<int32_t> tpos(c->nT), tinv(c->nT);
+        for (int64_t i = 0; i < c->nT; ++i) {
+            tpos[i] = tord[i];
+            tinv[tord[i]] = (int32_t)i;
+        }
+        upload(c->t_pos, tpos, st);
+        // sources: gamma- then E, Morton-sorted internally
+        std::vector<int32_t> sp(G.gm);
+        sp.insert(sp.end(), G.ext.begin(), G.ext.end());
+        std::vector<int32_t> sord = morton_order(sp.data(), c->nS, G.bbox_lo);
+        c->S.set(sp, sord, st);
+        // weight CSR rows in internal source order (Sec. 3.2 double layer, collected per source)
+        std::vector<std::vector<std::pair<int32_t, double>>> rows(c->nS);
+        for (int64_t q = 0; q < c->ngm; ++q) rows[q].push_back({(int32_t)q, (double)G.dcount[q]});
+        for (size_t e = 0; e < G.edge_q.size(); ++e) rows[c->ngm + G.edge_k[e]].push_back({G.edge_q[e], -1.0});
+        std::vector<int32_t> rowptr(c->nS + 1, 0), col;
+        std::vector<double> coef;
+        for (int64_t i = 0; i < c->nS; ++i) {
+            for (auto& pr : rows[sord[i]]) {
+                col.push_back(pr.first);
+                coef.push_back(pr.second);
+            }
+            rowptr[i + 1] = (int32_t)col.size();
+        }
+        upload(c->csr_rowptr, rowptr, st);
+        upload(c->csr_col, col, st);
+        upload(c->csr_coef, coef, st);
+        c->B = CSR{c->nS, c->csr_rowptr.as<int32_t>(), c->csr_col.as<int32_t>(), c->csr_coef.as<double>()};
+        // closure rows
+        std::vector<int32_t> ctq(c->ngm), ctp(c->ngm);
+        for (int64_t q = 0; q < c->ngm; ++q) {
+            ctq[q] = tinv[c->ngp + q];
+            ctp[q] = tinv[G.partner[q]];
+        }
+        upload(c->cl_tq, ctq, st);
+        upload(c->cl_tp, ctp, st);
+        upload(c->cl_t, G.t, st);
+        c->cl = Closure{c->ngm, c->cl_tq.as<int32_t>(), c->cl_tp.as<int32_t>(), c->cl_t.as<double>()};
+
+        // LGF table: radius 32 (LDS) for sigma = 0 with the far field beyond, else every offset
+        const int R = c->s == 0.0 ? nr : std::max(nr, G.max_offset);
+        c->table = get_table(c->device, c->s, R, st);
+        c->tabs.near_r64 = c->tabs.near_r32 = nr;
+        c->tabs.near64 = c->table->d64.as<double>();
+        c->tabs.near32 = c->table->d32.as<float>();
+        c->tabs.full64 = c->table->d64.as<double>();
+        c->tabs.full32 = c->table->d32.as<float>();
+        c->tabs.full_r = c->table->R;
+        c->tabs.far_field = c->s == 0.0;
+
+        // work buffers
+        const int mr = c->max_rhs;
+        c->w.alloc(sizeof(double) * c->nS * mr);
+        const int chunks = lgf_sum_chunks(c->nT, c->nS);
+        c->part_cap = (int64_t)chunks * c->nT * mr;
+        c->part.alloc(sizeof(double) * c->part_cap);
+        const int64_t n = c->ngm;
+        KrylovState& K = c->K;
+        K.m = m;
+        K.n = n;
+        K.ld_rhs = (int64_t)(m + 1) * n;
+        c->kV.alloc(sizeof(double) * K.ld_rhs * mr);
+        c->kH.alloc(sizeof(double) * (int64_t)m * (m + 1) * mr);
+        c->kcs.alloc(sizeof(double) * m * mr);
+        c->ksn.alloc(sizeof(double) * m * mr);
+        c->kg.alloc(sizeof(double) * (m + 1) * mr);
+        c->khist.alloc(sizeof(double) * m * mr);
+        c->kbeta.alloc(sizeof(double) * mr);
+        c->kdone.alloc(sizeof(int32_t) * mr);
+        c->kkdone.alloc(sizeof(int32_t) * mr);
+        K.V = c->kV.as<double>();
+        K.H = c->kH.as<double>();
+        K.cs = c->kcs.as<double>();
+        K.sn = c->ksn.as<double>();
+        K.g = c->kg.as<double>();
+        K.hist = c->khist.as<double>();
+        K.beta = c->kbeta.as<double>();
+        K.done = c->kdone.as<int32_t>();
+        K.kdone = c->kkdone.as<int32_t>();
+        c->maxj = m + 1;
+        c->hA.alloc(sizeof(double) * c->maxj * mr);
+        c->hB.alloc(sizeof(double) * c->maxj * mr);
+        c->nrm.alloc(sizeof(double) * c->maxj * mr);
+        c->dotpart.alloc(sizeof(double) * (int64_t)c->maxj * mr * dot_blocks(n));
+        c->ycoef.alloc(sizeof(double) * m * mr);
+        for (DevMem* d : {&c->b, &c->x, &c->r, &c->tmp}) d->alloc(sizeof(double) * n * mr);
+        c->up_gamma.alloc(sizeof(double) * c->nT * mr);
+        c->u_gamma.alloc(sizeof(double) * c->nT * mr);
+        BAE_HIP_CHECK(hipHostMalloc((void**)&c->pinned_flags, sizeof(int32_t) * 2 * mr, hipHostMallocDefault));
+        BAE_HIP_CHECK(hipStreamSynchronize(st));
+        *out = c.release();
+    });
+}
+
+int bae_destroy(bae_ctx* c) {
+    if (!c) return BAE_OK;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->pinned_flags) (void)hipHostFree(c->pinned_flags);
+    hipStream_t st = c->stream;
+    delete c;
+    if (st) (void)hipStreamDestroy(st);
+    return BAE_OK;
+}
+
+int bae_get_sizes(const bae_ctx* c, bae_sizes* o) {
+    return guard([&] {
+        if (!c || !o) throw Error{BAE_ERR_ARG, "null argument"};
+        o->n_mplus = c->geo.n_mplus;
+        o->n_gamma_plus = c->ngp;
+        o->n_gamma_minus = c->ngm;
+        o->n_ext = c->next;
+        o->n_edges = (int64_t)c->geo.edge_q.size();
+        o->n_sources = c->nS;
+        o->n_targets = c->nT;
+        o->n_empty_d = c->geo.n_empty_d;
+        o->max_offset = c->geo.max_offset;
+        o->table_radius = c->tabs.full_r;
+        o->table_entries = table_size(c->tabs.full_r);
+        size_t bytes = 0;
+        for (const DevMem* d : {&c->T.x, &c->T.y, &c->T.z, &c->S.x, &c->S.y, &c->S.z, &c->Mp.x, &c->Mp.y, &c->Mp.z,
+                                &c->t_pos, &c->csr_rowptr, &c->csr_col, &c->csr_coef, &c->cl_tq, &c->cl_tp, &c->cl_t,
+                                &c->w, &c->part, &c->kV, &c->kH, &c->kcs, &c->ksn, &c->kg, &c->khist, &c->kbeta,
+                                &c->kdone, &c->kkdone, &c->hA, &c->hB, &c->nrm, &c->dotpart, &c->ycoef, &c->b, &c->x,
+                                &c->r, &c->tmp, &c->up_gamma, &c->u_gamma, &c->wf})
+            bytes += d->bytes;
+        o->device_bytes = (int64_t)bytes;
+    });
+}
+
+int bae_get_sets(const bae_ctx* c, int32_t* gp, int32_t* gm, int32_t* ext) {
+    return guard([&] {
+        if (!c) throw Error{BAE_ERR_ARG, "null context"};
+        if (gp) std::memcpy(gp, c->geo.gp.data(), sizeof(int32_t) * c->geo.gp.size());
+        if (gm) std::memcpy(gm, c->geo.gm.data(), sizeof(int32_t) * c->geo.gm.size());
+        if (ext) std::memcpy(ext, c->geo.ext.data(), sizeof(int32_t) * c->geo.ext.size());
+    });
+}
+
+int bae_get_boundary_points(const bae_ctx* c, double* xstar, int32_t* partner, double* t) {
+    return guard([&] {
+        if (!c) throw Error{BAE_ERR_ARG, "null context"};
+        if (xstar) std::memcpy(xstar, c->geo.xstar.data(), sizeof(double) * c->geo.xstar.size());
+        if (partner) std::memcpy(partner, c->geo.partner.data(), sizeof(int32_t) * c->geo.partner.size());
+        if (t) std::memcpy(t, c->geo.t.data(), sizeof(double) * c->geo.t.size());
+    });
+}
+
+int bae_set_rhs(bae_ctx* c, int32_t nrhs, const double* g_xstar, const double* f_grid) {
+    return guard([&] {
+        if (!c || !g_xstar) throw Error{BAE_ERR_ARG, "null argument"};
+        if (nrhs < 1 || nrhs > c->max_rhs) throw Error{BAE_ERR_ARG, "nrhs out of range"};
+        BAE_HIP_CHECK(hipSetDevice(c->device));
+        hipStream_t st = c->stream;
+        const Geometry& G = c->geo;
+        const int64_t n = c->ngm, N3 = (int64_t)G.n[0] * G.n[1] * G.n[2];
+        for (int64_t i = 0; i < n * nrhs; ++i)
+            if (!std::isfinite(g_xstar[i])) throw Error{BAE_ERR_NONFINITE, "boundary data not finite"};
+        std::vector<double> bh(g_xstar, g_xstar + n * nrhs);
+        c->has_f = f_grid != nullptr;
+        if (c->has_f) {
+            for (int64_t i = 0; i < N3 * nrhs; ++i)
+                if (!std::isfinite(f_grid[i])) throw Error{BAE_ERR_NONFINITE, "source term not finite"};
+            ensure_mplus(c);
+            const int64_t nm = c->Mp.ps.count;
+            std::vector<int32_t> lin(nm);
+            {
+                // linear grid index of each internal M+ point
+                std::vector<int32_t> pts;
+                for (int i = 0; i < G.n[0]; ++i)
+                    for (int j = 0; j < G.n[1]; ++j)
+                        for (int k = 0; k < G.n[2]; ++k)
+                            if (G.inside[((int64_t)i * G.n[1] + j) * G.n[2] + k])
+                                pts.push_back((int32_t)(((int64_t)i * G.n[1] + j) * G.n[2] + k));
+                for (int64_t a = 0; a < nm; ++a) lin[a] = pts[c->Mp.perm[a]];
+            }
+            std::vector<double> wfh(nm * nrhs);
+            const double h2 = G.h * G.h;
+            for (int r = 0; r < nrhs; ++r)
+                for (int64_t a = 0; a < nm; ++a) wfh[r * nm + a] = h2 * f_grid[r * N3 + lin[a]];
+            upload(c->wf, wfh, st);
+            lgf_sum_to(c, c->T.ps, c->Mp.ps, c->wf.as<double>(), nrhs, c->t_pos.as<int32_t>(), c->up_gamma.as<double>(),
+                       c->nT, 1.0, st);
+            std::vector<double> up(c->nT * nrhs);
+            BAE_HIP_CHECK(hipMemcpy(up.data(), c->up_gamma.p, sizeof(double) * up.size(), hipMemcpyDeviceToHost));
+            for (int r = 0; r < nrhs; ++r)
+                for (int64_t q = 0; q < n; ++q) {
+                    const double t = G.t[q];
+                    bh[r * n + q] -= (1.0 - t) * up[r * c->nT + c->ngp + q] + t * up[r * c->nT + G.partner[q]];
+                }
+        } else {
+            launch_fill(c->up_gamma.as<double>(), c->nT * nrhs, 0.0, st);
+        }
+        BAE_HIP_CHECK(hipMemcpyAsync(c->b.p, bh.data(), sizeof(double) * bh.size(), hipMemcpyHostToDevice, st));
+        BAE_HIP_CHECK(hipStreamSynchronize(st));
+        c->nrhs = nrhs;
+        c->rhs_ready = true;
+        c->solved = false;
+    });
+}
+
+int bae_solve(bae_ctx* c, const bae_solve_params* p, bae_result* res) {
+    int status = BAE_OK;
+    int rc = guard([&] {
+        if (!c || !p) throw Error{BAE_ERR_ARG, "null argument"};
+        if (!c->rhs_ready) throw Error{BAE_ERR_STATE, "bae_set_rhs must precede bae_solve"};
+        if (p->precision != BAE_SOLVE_FP64 && p->precision != BAE_SOLVE_FP32_REFINED)
+            throw Error{BAE_ERR_ARG, "unknown solve precision"};
+        if (!(p->tol > 0.0)) throw Error{BAE_ERR_ARG, "tol must be > 0"};
+        BAE_HIP_CHECK(hipSetDevice(c->device));
+        hipStream_t st = c->stream;
+        const auto t0 = std::chrono::steady_clock::now();
+        const int nrhs = c->nrhs;
+        const int64_t n = c->ngm;
+        const int maxit = p->maxit > 0 ? std::min(p->maxit, c->K.m) : c->K.m;
+        c->hist.assign(nrhs, {});
+        int64_t mv64 = 0, mv32 = 0;
+        std::vector<double> bn = host_norms(c, c->b.as<double>(), nrhs, st);
+        std::vector<int> iters(nrhs, 0), conv(nrhs, 0), outer(nrhs, 0);
+        std::vector<double> est(nrhs, 0.0), relres;
+        launch_fill(c->x.as<double>(), n * nrhs, 0.0, st);
+        if (p->precision == BAE_SOLVE_FP64) {
+            GmresOut g = gmres(c, c->b.as<double>(), nrhs, BAE_PREC_FP64, p->tol, maxit, {}, c->x.as<double>(), false,
+                               st, &mv64);
+            for (int r = 0; r < nrhs; ++r) {
+                iters[r] = g.iters[r];
+                est[r] = g.last_est[r];
+            }
+            relres = residual(c, nrhs, bn, st, &mv64);
+            for (int r = 0; r < nrhs; ++r) conv[r] = g.converged[r];
+        } else {
+            const double inner = p->inner_tol > 0 ? p->inner_tol : 1e-5;
+            const int max_outer = p->max_outer > 0 ? p->max_outer : 8;
+            BAE_HIP_CHECK(hipMemcpyAsync(c->r.p, c->b.p, sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, st));
+            relres.assign(nrhs, 1.0);
+            for (int r = 0; r < nrhs; ++r) relres[r] = bn[r] > 0 ? 1.0 : 0.0;
+            for (int o = 0; o < max_outer; ++o) {
+                std::vector<int> skip(nrhs, 0);
+                bool all = true;
+                for (int r = 0; r < nrhs; ++r) {
+                    skip[r] = relres[r] <= p->tol;
+                    all &= skip[r] != 0;
+                }
+                if (all) break;
+                // the inner solve works on r scaled to unit size; its tolerance is relative
+                GmresOut g = gmres(c, c->r.as<double>(), nrhs, BAE_PREC_FP32, inner, maxit, skip, c->x.as<double>(),
+                                   true, st, &mv32);
+                for (int r = 0; r < nrhs; ++r) {
+                    iters[r] += g.iters[r];
+                    if (!skip[r]) {
+                        outer[r]++;
+                        est[r] = g.last_est[r] * relres[r];
+                    }
+                }
+                relres = residual(c, nrhs, bn, st, &mv64);
+            }
+            for (int r = 0; r < nrhs; ++r) conv[r] = relres[r] <= p->tol;
+        }
+        // u_gamma = D q + u_p on gamma
+        double_layer(c, c->x.as<double>(), n, c->u_gamma.as<double>(), c->nT, nrhs, BAE_PREC_FP64, st);
+        launch_axpby(1.0, c->up_gamma.as<double>(), c->nT, 1.0, c->u_gamma.as<double>(), c->nT, c->nT, nrhs, st);
+        BAE_HIP_CHECK(hipStreamSynchronize(st));
+        c->ugrid.clear();
+        if (p->compute_grid) {
+            const Geometry& G = c->geo;
+            ensure_mplus(c);
+            const int64_t nm = c->Mp.ps.count;
+            DevMem um;
+            um.alloc(sizeof(double) * nm * nrhs);
+            launch_weights(c->B, c->x.as<double>(), n, c->w.p, c->nS, nrhs, BAE_PREC_FP64, st);
+            lgf_sum_to(c, c->Mp.ps, c->S.ps, c->w.as<double>(), nrhs, nullptr, um.as<double>(), nm, 1.0, st);
+            if (c->has_f) {
+                DevMem up;
+                up.alloc(sizeof(double) * nm * nrhs);
+                lgf_sum_to(c, c->Mp.ps, c->Mp.ps, c->wf.as<double>(), nrhs, nullptr, up.as<double>(), nm, 1.0, st);
+                launch_axpby(1.0, up.as<double>(), nm, 1.0, um.as<double>(), nm, nm, nrhs, st);
+            }
+            std::vector<double> hu(nm * nrhs), hg(c->nT * nrhs);
+            BAE_HIP_CHECK(hipMemcpyAsync(hu.data(), um.p, sizeof(double) * hu.size(), hipMemcpyDeviceToHost, st));
+            BAE_HIP_CHECK(hipMemcpyAsync(hg.data(), c->u_gamma.p, sizeof(double) * hg.size(), hipMemcpyDeviceToHost, st));
+            BAE_HIP_CHECK(hipStreamSynchronize(st));
+            const int64_t N3 = (int64_t)G.n[0] * G.n[1] * G.n[2];
+            c->ugrid.assign(N3 * nrhs, NAN);
+            std::vector<int32_t> lin;
+            for (int i = 0; i < G.n[0]; ++i)
+                for (int j = 0; j < G.n[1]; ++j)
+                    for (int k = 0; k < G.n[2]; ++k)
+                        if (G.inside[((int64_t)i * G.n[1] + j) * G.n[2] + k])
+                            lin.push_back((int32_t)(((int64_t)i * G.n[1] + j) * G.n[2] + k));
+            for (int r = 0; r < nrhs; ++r) {
+                for (int64_t a = 0; a < nm; ++a) c->ugrid[r * N3 + lin[c->Mp.perm[a]]] = hu[r * nm + a];
+                for (int64_t q = 0; q < n; ++q) {
+                    const int32_t* v = &G.gm[3 * q];
+                    c->ugrid[r * N3 + ((int64_t)v[0] * G.n[1] + v[1]) * G.n[2] + v[2]] = hg[r * c->nT + c->ngp + q];
+                }
+            }
+        }
+        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        for (int r = 0; r < nrhs; ++r) {
+            if (!conv[r]) status = BAE_NOT_CONVERGED;
+            if (res) {
+                res[r].status = conv[r] ? BAE_OK : BAE_NOT_CONVERGED;
+                res[r].iterations = iters[r];
+                res[r].outer_steps = outer[r];
+                res[r].converged = conv[r];
+                res[r].rel_residual_est = est[r];
+                res[r].rel_residual_true = relres[r];
+                res[r].seconds = secs;
+                res[r].matvecs_fp64 = mv64;
+                res[r].matvecs_fp32 = mv32;
+            }
+        }
+        c->solved = true;
+    });
+    return rc != BAE_OK ? rc : status;
+}
+
+int bae_get_density(const bae_ctx* c, int32_t r, double* q) {
+    return guard([&] {
+        if (!c || !q) throw Error{BAE_ERR_ARG, "null argument"};
+        if (!c->solved || r < 0 || r >= c->nrhs) throw Error{BAE_ERR_STATE, "no solution for this RHS"};
+        BAE_HIP_CHECK(hipMemcpy(q, c->x.as<double>() + r * c->ngm, sizeof(double) * c->ngm, hipMemcpyDeviceToHost));
+    });
+}
+
+int bae_get_gamma_values(const bae_ctx* c, int32_t r, double* u) {
+    return guard([&] {
+        if (!c || !u) throw Error{BAE_ERR_ARG, "null argument"};
+        if (!c->solved || r < 0 || r >= c->nrhs) throw Error{BAE_ERR_STATE, "no solution for this RHS"};
+        BAE_HIP_CHECK(hipMemcpy(u, c->u_gamma.as<double>() + r * c->nT, sizeof(double) * c->nT, hipMemcpyDeviceToHost));
+    });
+}
+
+int bae_get_solution(const bae_ctx* c, int32_t r, double* u) {
+    return guard([&] {
+        if (!c || !u) throw Error{BAE_ERR_ARG, "null argument"};
+        if (!c->solved || r < 0 || r >= c->nrhs || c->ugrid.empty())
+            throw Error{BAE_ERR_STATE, "no grid solution (solve with compute_grid)"};
+        const int64_t N3 = (int64_t)c->geo.n[0] * c->geo.n[1] * c->geo.n[2];
+        std::memcpy(u, c->ugrid.data() + r * N3, sizeof(double) * N3);
+    });
+}
+
+int bae_get_history(const bae_ctx* c, int32_t r, double* h, int32_t cap, int32_t* len) {
+    return guard([&] {
+        if (!c || !len) throw Error{BAE_ERR_ARG, "null argument"};
+        if (!c->solved || r < 0 || r >= c->nrhs) throw Error{BAE_ERR_STATE, "no solution for this RHS"};
+        const auto& v = c->hist[r];
+        *len = (int32_t)v.size();
+        if (h) std::memcpy(h, v.data(), sizeof(double) * std::min<size_t>(v.size(), cap > 0 ? cap : 0));
+    });
+}
+
+int bae_apply_double_layer(bae_ctx* c, const double* q, double* v, int32_t nrhs, int32_t prec, void* stream) {
+    return guard([&] {
+        if (!c || !q || !v) throw Error{BAE_ERR_ARG, "null argument"};
+        if (nrhs < 1 || nrhs > c->max_rhs) throw Error{BAE_ERR_ARG, "nrhs out of range"};
+        if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32) throw Error{BAE_ERR_ARG, "unknown precision"};
+        BAE_HIP_CHECK(hipSetDevice(c->device));
+        double_layer(c, q, c->ngm, v, c->nT, nrhs, prec, (hipStream_t)stream);
+    });
+}
+
+int bae_apply_operator(bae_ctx* c, const double* q, double* aq, int32_t nrhs, int32_t prec, void* stream) {
+    return guard([&] {
+        if (!c || !q || !aq) throw Error{BAE_ERR_ARG, "null argument"};
+        if (nrhs < 1 || nrhs > c->max_rhs) throw Error{BAE_ERR_ARG, "nrhs out of range"};
+        if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32) throw Error{BAE_ERR_ARG, "unknown precision"};
+        BAE_HIP_CHECK(hipSetDevice(c->device));
+        bae_operator(c, q, c->ngm, aq, c->ngm, nrhs, prec, (hipStream_t)stream);
+    });
+}
+
+int bae_lgf_eval(bae_ctx* c, const int32_t* off, int64_t count, double* out, int32_t prec, void* stream) {
+    return guard([&] {
+        if (!c || (count > 0 && (!off || !out)) || count < 0) throw Error{BAE_ERR_ARG, "bad argument"};
+        if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32) throw Error{BAE_ERR_ARG, "unknown precision"};
+        BAE_HIP_CHECK(hipSetDevice(c->device));
+        lgf_eval_launch(off, count, out, prec, c->tabs, (hipStream_t)stream);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,347 @@
+// Device kernels around the LGF sum: double-layer weights, chunk reduction, the
+// hat-function closure Phi, and the FP64 GMRES building blocks (dot products, classical
+// Gram-Schmidt with re-orthogonalisation, Givens rotations) for several right-hand
+// sides at once.  Everything here is memory-latency bound and small next to the LGF sum.
+#include "ops.hpp"
+
+namespace bae {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline unsigned blocks_for(int64_t n, int per = kThreads) { return (unsigned)((n + per - 1) / per); }
+
+// w[r][s] = sum_{j in row s} coef[j] q[r][col[j]]   (Sec. 3.2: w(n) = |D_n| q(n), w(k) = -sum q)
+template <typename Real>
+__global__ void weights_kernel(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
+                               const double* __restrict__ coef, int64_t ns, const double* __restrict__ q,
+                               int64_t ldq, Real* __restrict__ w, int64_t ldw) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (s >= ns) return;
+    const double* qr = q + r * ldq;
+    double acc = 0.0;
+    for (int j = rowptr[s]; j < rowptr[s + 1]; ++j) acc = fma(coef[j], qr[col[j]], acc);
+    w[r * ldw + s] = (Real)acc;
+}
+
+// out[r][pos[t]] = scale * sum_c part[r][c][t]  (+ add[r][pos[t]] when add != null)
+__global__ void reduce_scatter_kernel(const double* __restrict__ part, int chunks, int64_t nt, int64_t ldp,
+                                      const int32_t* __restrict__ pos, double* __restrict__ out, int64_t ldo,
+                                      double scale) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (t >= nt) return;
+    const double* p = part + r * ldp + t;
+    double acc = 0.0;
+    for (int c = 0; c < chunks; ++c) acc += p[(int64_t)c * nt];
+    out[r * ldo + (pos ? pos[t] : t)] = scale * acc;
+}
+
+// aq[r][i] = (1 - t_i) v(q_i) + t_i v(p_i), v = sum over chunks of the partial sums at the
+// internal target indices of q_i and of its partner p_i (Sec. 2.1 eq. "bc", hat functions).
+__global__ void closure_kernel(const double* __restrict__ part, int chunks, int64_t nt, int64_t ldp,
+                               const int32_t* __restrict__ tq, const int32_t* __restrict__ tp,
+                               const double* __restrict__ tw, int64_t n, double* __restrict__ aq, int64_t lda) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i >= n) return;
+    const double* p = part + r * ldp;
+    const int64_t a = tq[i], b = tp[i];
+    double va = 0.0, vb = 0.0;
+    for (int c = 0; c < chunks; ++c) {
+        va += p[(int64_t)c * nt + a];
+        vb += p[(int64_t)c * nt + b];
+    }
+    const double t = tw[i];
+    aq[r * lda + i] = (1.0 - t) * va + t * vb;
+}
+
+__device__ inline double block_sum(double v, double* sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += sh[k];
+    return s;
+}
+
+// partial[r][j][b] = sum over slice b of X[r][j][i] * y[r][i]; j < nj, b < nb.
+// Done RHS are skipped (their partials are not read).
+__global__ void dots_kernel(const double* __restrict__ X, int64_t ldx_vec, int64_t ldx_rhs,
+                            const double* __restrict__ y, int64_t ldy, int64_t n, int nb,
+                            const int32_t* __restrict__ done, double* __restrict__ partial, int maxj) {
+    __shared__ double sh[kThreads / 64];
+    const int b = blockIdx.x, j = blockIdx.y, r = blockIdx.z;
+    if (done && done[r]) return;
+    const int64_t per = (n + nb - 1) / nb;
+    const int64_t lo = b * per, hi = min(n, lo + per);
+    const double* x = X + r * ldx_rhs + j * ldx_vec;
+    const double* yy = y + r * ldy;
+    double acc = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) acc = fma(x[i], yy[i], acc);
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[((int64_t)r * maxj + j) * nb + b] = s;
+}
+
+// h[r][j] (+)= sum_b partial[r][j][b]
+__global__ void dots_finalize_kernel(const double* __restrict__ partial, int nb, int nj, int maxj,
+                                     const int32_t* __restrict__ done, double* __restrict__ h, int64_t ldh,
+                                     int accumulate) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (j >= nj || (done && done[r])) return;
+    const double* p = partial + ((int64_t)r * maxj + j) * nb;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += p[b];
+    h[r * ldh + j] = accumulate ? h[r * ldh + j] + s : s;
+}
+
+// y[r][i] -= sum_{j < nj} c[r][j] X[r][j][i]
+__global__ void subtract_combination_kernel(const double* __restrict__ X, int64_t ldx_vec, int64_t ldx_rhs,
+                                            const double* __restrict__ c, int64_t ldc, int nj, int64_t n,
+                                            const int32_t* __restrict__ done, double* __restrict__ y,
+                                            int64_t ldy) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i >= n || (done && done[r])) return;
+    const double* x = X + r * ldx_rhs + i;
+    const double* cr = c + r * ldc;
+    double acc = 0.0;
+    for (int j = 0; j < nj; ++j) acc = fma(cr[j], x[j * ldx_vec], acc);
+    y[r * ldy + i] -= acc;
+}
+
+// y[r][i] (+)= sum_{j < nj[r]} c[r][j] X[r][j][i]
+__global__ void combination_kernel(const double* __restrict__ X, int64_t ldx_vec, int64_t ldx_rhs,
+                                   const double* __restrict__ c, int64_t ldc, const int32_t* __restrict__ nj,
+                                   int64_t n, double* __restrict__ y, int64_t ldy, int accumulate) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i >= n) return;
+    const double* x = X + r * ldx_rhs + i;
+    const double* cr = c + r * ldc;
+    double acc = 0.0;
+    for (int j = 0; j < nj[r]; ++j) acc = fma(cr[j], x[j * ldx_vec], acc);
+    y[r * ldy + i] = accumulate ? y[r * ldy + i] + acc : acc;
+}
+
+// Hessenberg column k of RHS r holds h[0..k] (CGS2 coefficients) and nrm2 = ||w||^2:
+// set H[k+1][k] = ||w||, scale w into the next basis vector.
+__global__ void normalize_kernel(double* __restrict__ V, int64_t ldv_vec, int64_t ldv_rhs, int k, int64_t n,
+                                 const double* __restrict__ nrm2, const int32_t* __restrict__ done) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i >= n || (done && done[r])) return;
+    const double nr = sqrt(nrm2[r]);
+    if (nr > 0.0) V[r * ldv_rhs + (int64_t)(k + 1) * ldv_vec + i] /= nr;
+}
+
+// One thread per RHS: Givens update of column k (Saad-Schultz), residual estimate,
+// convergence / breakdown flag.  H is column-major per RHS: H[r][k][i], i <= k+1.
+__global__ void givens_kernel(double* __restrict__ Hc, int64_t ldh_col, int64_t ldh_rhs,
+                              const double* __restrict__ hcol, const double* __restrict__ hcol2, int64_t ldhc,
+                              const double* __restrict__ nrm2,
+                              double* __restrict__ cs, double* __restrict__ sn, int64_t ldcs,
+                              double* __restrict__ g, int64_t ldg, const double* __restrict__ beta,
+                              double* __restrict__ hist, int64_t ldhist, int32_t* __restrict__ done,
+                              int32_t* __restrict__ kdone, int k, double tol, int nrhs) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs || done[r]) return;
+    double* h = Hc + r * ldh_rhs + (int64_t)k * ldh_col;
+    const double* hc = hcol + r * ldhc;
+    const double* hc2 = hcol2 + r * ldhc;
+    for (int i = 0; i <= k; ++i) h[i] = hc[i] + hc2[i];   // the two Gram-Schmidt passes
+    const double hk1 = sqrt(nrm2[r]);
+    double* c = cs + r * ldcs;
+    double* s = sn + r * ldcs;
+    for (int i = 0; i < k; ++i) {
+        const double a = h[i], b = h[i + 1];
+        h[i] = c[i] * a + s[i] * b;
+        h[i + 1] = -s[i] * a + c[i] * b;
+    }
+    const double a = h[k], b = hk1;
+    const double rr = hypot(a, b);
+    double* gr = g + r * ldg;
+    if (rr == 0.0) {          // exact breakdown of a singular system: stop here
+        done[r] = 1;
+        kdone[r] = k;
+        return;
+    }
+    c[k] = a / rr;
+    s[k] = b / rr;
+    h[k] = rr;
+    h[k + 1] = 0.0;
+    gr[k + 1] = -s[k] * gr[k];
+    gr[k] = c[k] * gr[k];
+    const double est = fabs(gr[k + 1]) / beta[r];
+    hist[r * ldhist + k] = est;
+    kdone[r] = k + 1;
+    if (est <= tol || hk1 == 0.0) done[r] = 1;
+}
+
+// beta = sqrt(nrm2); V[0] = r0 / beta; g[0] = beta; done = beta == 0
+__global__ void gmres_init_kernel(const double* __restrict__ r0, int64_t ldr, double* __restrict__ V,
+                                  int64_t ldv_rhs, int64_t n, const double* __restrict__ nrm2,
+                                  double* __restrict__ beta, double* __restrict__ g, int64_t ldg,
+                                  int32_t* __restrict__ done, int32_t* __restrict__ kdone) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    const double b = sqrt(nrm2[r]);
+    if (i == 0) {
+        beta[r] = b;
+        g[r * ldg] = b;
+        done[r] = b == 0.0;
+        kdone[r] = 0;
+    }
+    if (i < n) V[r * ldv_rhs + i] = b > 0.0 ? r0[r * ldr + i] / b : 0.0;
+}
+
+__global__ void axpby_kernel(double a, const double* __restrict__ x, int64_t ldx, double b,
+                             double* __restrict__ y, int64_t ldy, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i < n) y[r * ldy + i] = a * x[r * ldx + i] + b * y[r * ldy + i];
+}
+
+__global__ void gather_kernel(const double* __restrict__ x, int64_t ldx, const int32_t* __restrict__ idx,
+                              int64_t n, double* __restrict__ y, int64_t ldy, double scale) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i < n) y[r * ldy + i] = scale * x[r * ldx + idx[i]];
+}
+
+__global__ void fill_kernel(double* __restrict__ y, int64_t n, double v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = v;
+}
+
+__global__ void fill_int_kernel(int32_t* __restrict__ y, int64_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = v;
+}
+
+__global__ void to_float_kernel(const double* __restrict__ x, float* __restrict__ y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (float)x[i];
+}
+
+}  // namespace
+
+#define LAUNCH_CHECK() BAE_HIP_CHECK(hipGetLastError())
+
+void launch_weights(const CSR& B, const double* q, int64_t ldq, void* w, int64_t ldw, int nrhs, int prec,
+                    hipStream_t st) {
+    if (B.rows == 0) return;
+    dim3 grid(blocks_for(B.rows), nrhs);
+    if (prec == BAE_PREC_FP64)
+        weights_kernel<double><<<grid, kThreads, 0, st>>>(B.rowptr, B.col, B.coef, B.rows, q, ldq, (double*)w, ldw);
+    else
+        weights_kernel<float><<<grid, kThreads, 0, st>>>(B.rowptr, B.col, B.coef, B.rows, q, ldq, (float*)w, ldw);
+    LAUNCH_CHECK();
+}
+
+void launch_reduce_scatter(const double* part, int chunks, int64_t nt, const int32_t* pos, double* out, int64_t ldo,
+                           int nrhs, double scale, hipStream_t st) {
+    if (nt == 0) return;
+    dim3 grid(blocks_for(nt), nrhs);
+    reduce_scatter_kernel<<<grid, kThreads, 0, st>>>(part, chunks, nt, (int64_t)chunks * nt, pos, out, ldo, scale);
+    LAUNCH_CHECK();
+}
+
+void launch_closure(const double* part, int chunks, int64_t nt, const Closure& cl, double* aq, int64_t lda, int nrhs,
+                    hipStream_t st) {
+    if (cl.n == 0) return;
+    dim3 grid(blocks_for(cl.n), nrhs);
+    closure_kernel<<<grid, kThreads, 0, st>>>(part, chunks, nt, (int64_t)chunks * nt, cl.tq, cl.tp, cl.t, cl.n, aq,
+                                              lda);
+    LAUNCH_CHECK();
+}
+
+int dot_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(64, (n + 2047) / 2048)); }
+
+void launch_dots(const double* X, int64_t ldx_vec, int64_t ldx_rhs, int nj, const double* y, int64_t ldy, int64_t n,
+                 int nrhs, const int32_t* done, double* partial, int maxj, double* h, int64_t ldh, int accumulate,
+                 hipStream_t st) {
+    const int nb = dot_blocks(n);
+    dots_kernel<<<dim3(nb, nj, nrhs), kThreads, 0, st>>>(X, ldx_vec, ldx_rhs, y, ldy, n, nb, done, partial, maxj);
+    LAUNCH_CHECK();
+    dots_finalize_kernel<<<dim3(blocks_for(nj, 64), nrhs), 64, 0, st>>>(partial, nb, nj, maxj, done, h, ldh,
+                                                                         accumulate);
+    LAUNCH_CHECK();
+}
+
+void launch_subtract_combination(const double* X, int64_t ldx_vec, int64_t ldx_rhs, const double* c, int64_t ldc,
+                                 int nj, int64_t n, int nrhs, const int32_t* done, double* y, int64_t ldy,
+                                 hipStream_t st) {
+    subtract_combination_kernel<<<dim3(blocks_for(n), nrhs), kThreads, 0, st>>>(X, ldx_vec, ldx_rhs, c, ldc, nj, n,
+                                                                                 done, y, ldy);
+    LAUNCH_CHECK();
+}
+
+void launch_combination(const double* X, int64_t ldx_vec, int64_t ldx_rhs, const double* c, int64_t ldc,
+                        const int32_t* nj, int64_t n, int nrhs, double* y, int64_t ldy, int accumulate,
+                        hipStream_t st) {
+    combination_kernel<<<dim3(blocks_for(n), nrhs), kThreads, 0, st>>>(X, ldx_vec, ldx_rhs, c, ldc, nj, n, y, ldy,
+                                                                        accumulate);
+    LAUNCH_CHECK();
+}
+
+void launch_normalize(double* V, int64_t ldv_vec, int64_t ldv_rhs, int k, int64_t n, const double* nrm2,
+                      const int32_t* done, int nrhs, hipStream_t st) {
+    normalize_kernel<<<dim3(blocks_for(n), nrhs), kThreads, 0, st>>>(V, ldv_vec, ldv_rhs, k, n, nrm2, done);
+    LAUNCH_CHECK();
+}
+
+void launch_givens(const KrylovState& K, const double* hcol, const double* hcol2, int64_t ldhc, const double* nrm2,
+                   int k, double tol, int nrhs, hipStream_t st) {
+    givens_kernel<<<blocks_for(nrhs, 64), 64, 0, st>>>(K.H, K.m + 1, (int64_t)(K.m + 1) * K.m, hcol, hcol2, ldhc,
+                                                       nrm2, K.cs,
+                                                       K.sn, K.m, K.g, K.m + 1, K.beta, K.hist, K.m, K.done, K.kdone, k,
+                                                       tol, nrhs);
+    LAUNCH_CHECK();
+}
+
+void launch_gmres_init(const double* r0, int64_t ldr, const KrylovState& K, int64_t n, const double* nrm2, int nrhs,
+                       hipStream_t st) {
+    gmres_init_kernel<<<dim3(blocks_for(std::max<int64_t>(n, 1)), nrhs), kThreads, 0, st>>>(
+        r0, ldr, K.V, K.ld_rhs, n, nrm2, K.beta, K.g, K.m + 1, K.done, K.kdone);
+    LAUNCH_CHECK();
+}
+
+void launch_axpby(double a, const double* x, int64_t ldx, double b, double* y, int64_t ldy, int64_t n, int nrhs,
+                  hipStream_t st) {
+    if (n == 0) return;
+    axpby_kernel<<<dim3(blocks_for(n), nrhs), kThreads, 0, st>>>(a, x, ldx, b, y, ldy, n);
+    LAUNCH_CHECK();
+}
+
+void launch_gather(const double* x, int64_t ldx, const int32_t* idx, int64_t n, double* y, int64_t ldy, int nrhs,
+                   double scale, hipStream_t st) {
+    if (n == 0) return;
+    gather_kernel<<<dim3(blocks_for(n), nrhs), kThreads, 0, st>>>(x, ldx, idx, n, y, ldy, scale);
+    LAUNCH_CHECK();
+}
+
+void launch_fill(double* y, int64_t n, double v, hipStream_t st) {
+    if (n == 0) return;
+    fill_kernel<<<blocks_for(n), kThreads, 0, st>>>(y, n, v);
+    LAUNCH_CHECK();
+}
+
+void launch_fill_int(int32_t* y, int64_t n, int32_t v, hipStream_t st) {
+    if (n == 0) return;
+    fill_int_kernel<<<blocks_for(n), kThreads, 0, st>>>(y, n, v);
+    LAUNCH_CHECK();
+}
+
+void launch_to_float(const double* x, float* y, int64_t n, hipStream_t st) {
+    if (n == 0) return;
+    to_float_kernel<<<blocks_for(n), kThreads, 0, st>>>(x, y, n);
+    LAUNCH_CHECK();
+}
+
+}  // namespace bae

@@ -1,0 +1,73 @@
+// Launch wrappers of the kernels in ops.hip (weights, reductions, closure, GMRES pieces).
+#pragma once
+
+#include <algorithm>
+
+#include "internal.hpp"
+
+namespace bae {
+
+// Sparse map from densities on gamma- to source weights on gamma- u E (internal order).
+struct CSR {
+    int64_t rows = 0;
+    int32_t* rowptr = nullptr;
+    int32_t* col = nullptr;
+    double* coef = nullptr;
+};
+
+// Dirichlet closure rows in gamma- (lexicographic) order: internal target indices of q
+// and of its partner p, and the weight t.
+struct Closure {
+    int64_t n = 0;
+    int32_t* tq = nullptr;
+    int32_t* tp = nullptr;
+    double* t = nullptr;
+};
+
+// Device-resident GMRES state for up to `cap` right-hand sides, basis capacity m.
+struct KrylovState {
+    int m = 0;                 // max iterations (basis m+1 vectors)
+    int64_t n = 0;             // vector length
+    int64_t ld_rhs = 0;        // (m+1) * n
+    double* V = nullptr;       // [rhs][m+1][n]
+    double* H = nullptr;       // [rhs][m][m+1]  column-major Hessenberg
+    double* cs = nullptr;      // [rhs][m]
+    double* sn = nullptr;
+    double* g = nullptr;       // [rhs][m+1]
+    double* hist = nullptr;    // [rhs][m]
+    double* beta = nullptr;    // [rhs]
+    int32_t* done = nullptr;   // [rhs]
+    int32_t* kdone = nullptr;  // [rhs]
+};
+
+void launch_weights(const CSR& B, const double* q, int64_t ldq, void* w, int64_t ldw, int nrhs, int prec,
+                    hipStream_t st);
+void launch_reduce_scatter(const double* part, int chunks, int64_t nt, const int32_t* pos, double* out, int64_t ldo,
+                           int nrhs, double scale, hipStream_t st);
+void launch_closure(const double* part, int chunks, int64_t nt, const Closure& cl, double* aq, int64_t lda, int nrhs,
+                    hipStream_t st);
+int dot_blocks(int64_t n);
+void launch_dots(const double* X, int64_t ldx_vec, int64_t ldx_rhs, int nj, const double* y, int64_t ldy, int64_t n,
+                 int nrhs, const int32_t* done, double* partial, int maxj, double* h, int64_t ldh, int accumulate,
+                 hipStream_t st);
+void launch_subtract_combination(const double* X, int64_t ldx_vec, int64_t ldx_rhs, const double* c, int64_t ldc,
+                                 int nj, int64_t n, int nrhs, const int32_t* done, double* y, int64_t ldy,
+                                 hipStream_t st);
+void launch_combination(const double* X, int64_t ldx_vec, int64_t ldx_rhs, const double* c, int64_t ldc,
+                        const int32_t* nj, int64_t n, int nrhs, double* y, int64_t ldy, int accumulate,
+                        hipStream_t st);
+void launch_normalize(double* V, int64_t ldv_vec, int64_t ldv_rhs, int k, int64_t n, const double* nrm2,
+                      const int32_t* done, int nrhs, hipStream_t st);
+void launch_givens(const KrylovState& K, const double* hcol, const double* hcol2, int64_t ldhc, const double* nrm2,
+                   int k, double tol, int nrhs, hipStream_t st);
+void launch_gmres_init(const double* r0, int64_t ldr, const KrylovState& K, int64_t n, const double* nrm2, int nrhs,
+                       hipStream_t st);
+void launch_axpby(double a, const double* x, int64_t ldx, double b, double* y, int64_t ldy, int64_t n, int nrhs,
+                  hipStream_t st);
+void launch_gather(const double* x, int64_t ldx, const int32_t* idx, int64_t n, double* y, int64_t ldy, int nrhs,
+                   double scale, hipStream_t st);
+void launch_fill(double* y, int64_t n, double v, hipStream_t st);
+void launch_fill_int(int32_t* y, int64_t n, int32_t v, hipStream_t st);
+void launch_to_float(const double* x, float* y, int64_t n, hipStream_t st);
+
+}  // namespace bae

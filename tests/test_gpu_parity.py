@@ -1,0 +1,234 @@
+"""GPU parity: every step of the HIP path against the FP64 CPU oracle, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+import paper_2502_05507_amd as P
+import workloads as W
+from oracle import geometry, gmres, lgf, operators, sparse
+
+from gpu_common import device, oracle_setup, rel_l2, small_problem
+
+pytestmark = pytest.mark.gpu
+
+
+def torch_mod():
+    import torch
+    return torch
+
+
+# ------------------------------------------------------------------ A3: LGF table
+@pytest.mark.parametrize("s,R", [(0.0, 40), (0.0, 117), (1.526e-4, 64), (0.0488, 60), (2.0, 24)])
+def test_lgf_table_matches_oracle(s, R):
+    torch = torch_mod()
+    out = torch.empty(P.lgf_table_size(R), dtype=torch.float64, device=device())
+    P.lgf_table(s, R, out)
+    torch.cuda.synchronize()
+    gpu = out.cpu().numpy()
+    ref = lgf.LGFTable(R, s).values
+    err = np.abs(gpu - ref)
+    assert np.all(err <= 1e-13 * np.abs(ref) + 1e-17 * ref[0]), err.max()
+    # stencil identity on the device table itself
+    t = lgf.LGFTable(R, s, values=gpu)
+    n, res = t.stencil_residual()
+    assert np.abs(res).max() < 1e-14
+
+
+def test_lgf_table_watson_value():
+    torch = torch_mod()
+    out = torch.empty(P.lgf_table_size(2), dtype=torch.float64, device=device())
+    P.lgf_table(0.0, 2, out)
+    assert abs(out[0].item() - 0.252731009858663003026) < 1e-15
+
+
+# ------------------------------------------------------------------ A1, A2: point sets and closure
+@pytest.mark.parametrize("kind,n", [("sphere", 33), ("ellipsoid", 49), ("torus", 41), ("star", 45)])
+def test_sets_and_closure_match_oracle(kind, n):
+    p = small_problem(kind, n)
+    g = geometry.from_problem(p)
+    with P.Context.from_problem(p) as ctx:
+        gp, gm, ex = ctx.sets()
+        xs, pa, t = ctx.boundary_points()
+        z = ctx.sizes
+    assert np.array_equal(gp, g.gamma_plus) and np.array_equal(gm, g.gamma_minus) and np.array_equal(ex, g.ext)
+    assert np.array_equal(pa, g.partner)
+    assert np.abs(t - g.t).max() < 1e-14
+    assert np.abs(xs - g.xstar).max() < 1e-14
+    assert z["n_mplus"] == g.inside.sum() and z["n_edges"] == len(g.edges)
+    assert z["max_offset"] == g.max_offset() and z["n_empty_d"] == int((g.d_count() == 0).sum())
+
+
+def test_laplace_sphere_sizes():
+    with P.Context.from_problem(W.laplace_sphere()) as ctx:
+        z = ctx.sizes
+    assert (z["n_mplus"], z["n_gamma_plus"], z["n_gamma_minus"], z["n_ext"], z["n_edges"]) == \
+        (8733, 1626, 1806, 1994, 3510)
+
+
+# ------------------------------------------------------------------ A4: kernel values (table / far field)
+@pytest.mark.parametrize("prec,tol", [(P.PREC_FP64, 1e-10), (P.PREC_FP32, 2e-6)])
+def test_kernel_values_match_oracle(prec, tol):
+    torch = torch_mod()
+    rng = np.random.default_rng(11)
+    off = rng.integers(-117, 118, size=(4000, 3)).astype(np.int32)
+    off[:200] = rng.integers(-40, 41, size=(200, 3))
+    off[200:206] = [[33, 0, 0], [0, -33, 0], [0, 0, 33], [33, 33, 33], [117, 0, 0], [0, 0, 0]]
+    ref = lgf.LGFTable(117, 0.0)(off.astype(np.int64))
+    with P.Context.from_problem(W.laplace_sphere()) as ctx:
+        o = torch.from_numpy(off).to(device())
+        out = torch.empty(len(off), dtype=torch.float64, device=device())
+        ctx.lgf_eval(o, out, prec)
+        torch.cuda.synchronize()
+        gpu = out.cpu().numpy()
+    assert np.all(np.abs(gpu - ref) <= tol * ref), np.max(np.abs(gpu - ref) / ref)
+
+
+# ------------------------------------------------------------------ A5-A7: double layer and operator
+CASES = [("sphere", 33, 0.0), ("ellipsoid", 65, 0.0), ("torus", 41, 10.0), ("sphere", 97, 30.0),
+         ("star", 57, 0.0)]
+
+
+@pytest.mark.parametrize("kind,n,sigma", CASES)
+def test_double_layer_matches_oracle(kind, n, sigma):
+    torch = torch_mod()
+    p = small_problem(kind, n, sigma)
+    g, G = oracle_setup(p)
+    rng = np.random.default_rng(n)
+    q = rng.standard_normal((2, len(g.gamma_minus)))
+    T = operators.gamma_targets(g)
+    ref = np.stack([operators.double_layer(g, G, q[r], T) for r in range(2)])
+    with P.Context.from_problem(p) as ctx:
+        qd = torch.from_numpy(q).to(device())
+        v = torch.empty((2, len(T)), dtype=torch.float64, device=device())
+        ctx.apply_double_layer(qd, v, P.PREC_FP64)
+        torch.cuda.synchronize()
+        v64 = v.cpu().numpy()
+        ctx.apply_double_layer(qd, v, P.PREC_FP32)
+        torch.cuda.synchronize()
+        v32 = v.cpu().numpy()
+    for r in range(2):
+        assert rel_l2(v64[r], ref[r]) < 1e-10
+        assert rel_l2(v32[r], ref[r]) < 2e-5
+
+
+@pytest.mark.parametrize("kind,n,sigma", CASES[:3])
+def test_operator_matches_oracle(kind, n, sigma):
+    torch = torch_mod()
+    p = small_problem(kind, n, sigma)
+    g, G = oracle_setup(p)
+    rng = np.random.default_rng(3 * n)
+    q = rng.standard_normal(len(g.gamma_minus))
+    ref = operators.bae_apply(g, G, q)
+    with P.Context.from_problem(p) as ctx:
+        qd = torch.from_numpy(q).to(device())
+        aq = torch.empty_like(qd)
+        ctx.apply_operator(qd, aq, P.PREC_FP64)
+        torch.cuda.synchronize()
+        assert rel_l2(aq.cpu().numpy(), ref) < 1e-10
+
+
+def test_gauss_law_on_device():
+    # (D 1)(m) = 1 on gamma for sigma = 0: a pin that needs no oracle arithmetic
+    torch = torch_mod()
+    p = W.poisson_ellipsoid(129)
+    with P.Context.from_problem(p) as ctx:
+        m = ctx.sizes["n_gamma_minus"]
+        one = torch.ones(m, dtype=torch.float64, device=device())
+        v = torch.empty(ctx.sizes["n_targets"], dtype=torch.float64, device=device())
+        ctx.apply_double_layer(one, v, P.PREC_FP64)
+        torch.cuda.synchronize()
+        assert (v - 1).abs().max().item() < 1e-9
+
+
+# ------------------------------------------------------------------ A8: solves
+def oracle_solution(p, g, G, tol=1e-13):
+    gx = p.g(g.xstar)
+    f = p.f_grid()
+    b = operators.rhs(g, G, gx, f)
+    q, hist, conv = gmres.gmres(lambda x: operators.bae_apply(g, G, x), b, tol=tol)
+    T = operators.gamma_targets(g)
+    ug = operators.double_layer(g, G, q, T)
+    if f is not None:
+        ug = ug + operators.volume_potential(g, G, f, T)
+    return q, ug, hist
+
+
+@pytest.mark.parametrize("prec,tol_q", [(P.SOLVE_FP64, 1e-10), (P.SOLVE_FP32_REFINED, 1e-8)])
+def test_laplace_sphere_solve_matches_oracle(prec, tol_q):
+    p = W.laplace_sphere()
+    g, G = oracle_setup(p)
+    q_ref, ug_ref, hist_ref = oracle_solution(p, g, G)
+    with P.Context.from_problem(p) as ctx:
+        xs, _, _ = ctx.boundary_points()
+        ctx.set_rhs(p.g(xs))
+        res = ctx.solve(prec, tol=1e-13)
+        q = ctx.density()
+        ug = ctx.gamma_values()
+        hist = ctx.history()
+    assert res[0]["converged"] and res[0]["rel_residual_true"] < 1e-12
+    assert rel_l2(q, q_ref) < tol_q and rel_l2(ug, ug_ref) < tol_q
+    if prec == P.SOLVE_FP64:
+        # Givens residual estimates agree over the first iterations (rounding differs later)
+        k = min(10, len(hist), len(hist_ref))
+        assert np.allclose(hist[:k], hist_ref[:k], rtol=1e-6)
+
+
+def test_poisson_with_source_and_grid_output():
+    p = W.poisson_ellipsoid(33)
+    g, G = oracle_setup(p)
+    q_ref, ug_ref, _ = oracle_solution(p, g, G)
+    us = sparse.solve(g, 0.0, p.g(g.xstar), p.f_grid())
+    with P.Context.from_problem(p) as ctx:
+        xs, _, _ = ctx.boundary_points()
+        ctx.set_rhs(p.g(xs), p.f_grid())
+        res = ctx.solve(P.SOLVE_FP64, tol=1e-13, compute_grid=True)
+        ug = ctx.gamma_values()
+        u = ctx.solution()
+    assert res[0]["converged"]
+    assert rel_l2(ug, ug_ref) < 1e-10
+    nplus = ~np.isnan(us)
+    assert np.array_equal(~np.isnan(u), nplus)
+    assert np.abs(u[nplus] - us[nplus]).max() < 1e-10 * np.abs(us[nplus]).max()
+
+
+def test_helmholtz_multi_rhs_and_refinement():
+    p = small_problem("torus", 41, 10.0)
+    g, G = oracle_setup(p)
+    rng = np.random.default_rng(99)
+    coeffs = rng.standard_normal((3, 16))
+    gs = [W.harmonic_poly(c, (0.5, 0.5, 0.5)) for c in coeffs]
+    refs = []
+    for fn in gs:
+        b = fn(*g.xstar.T)
+        q, _, _ = gmres.gmres(lambda x: operators.bae_apply(g, G, x), b, tol=1e-13)
+        refs.append(q)
+    with P.Context.from_problem(p) as ctx:
+        xs, _, _ = ctx.boundary_points()
+        G3 = np.stack([fn(*xs.T) for fn in gs])
+        ctx.set_rhs(G3)
+        for prec, tol_q in ((P.SOLVE_FP64, 1e-10), (P.SOLVE_FP32_REFINED, 1e-8)):
+            res = ctx.solve(prec, tol=1e-12)
+            assert all(r["converged"] for r in res)
+            for r in range(3):
+                assert rel_l2(ctx.density(r), refs[r]) < tol_q
+
+
+# ------------------------------------------------------------------ failure handling
+def test_error_paths():
+    p = W.laplace_sphere(17)
+    with P.Context.from_problem(p) as ctx:
+        xs, _, _ = ctx.boundary_points()
+        with pytest.raises(P.BaeError):
+            ctx.solve()                                   # before set_rhs
+        bad = p.g(xs)
+        bad[3] = np.nan
+        with pytest.raises(P.BaeError) as e:
+            ctx.set_rhs(bad)
+        assert e.value.status == -3
+        ctx.set_rhs(p.g(xs))
+        res = ctx.solve(P.SOLVE_FP64, tol=1e-14, maxit=2)
+        assert res[0]["status"] == 1 and not res[0]["converged"] and res[0]["iterations"] == 2
+    with pytest.raises(P.BaeError) as e:
+        P.Context((17, 17, 17), 1 / 16, (0, 0, 0), 0.0, "sphere", (0.5, 0.5, 0.5), (0.49,))
+    assert e.value.status == -2

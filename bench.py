@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Benchmark of the unfitted-BAE hot path on one MI355X.
+
+Workload: Poisson -Lap u = f on the ellipsoid with semi-axes (0.45, 0.3, 0.25) centred in the
+unit cube, h = 1/128 (129^3 nodes), f and g from u = sin(pi x) sin(pi y) sin(pi z).
+One step = one complete solve on device-resident inputs: FP64 iterative refinement around
+GMRES with the FP32 LGF sum (every matvec = double-layer weights, LGF sum over
+|gamma| x |gamma- u E| pairs, closure), the FP64 residual matvecs, and u_gamma.
+value = LGF pair-interactions evaluated in the timed steps / their wall time.
+
+Also reported: solves/s and p50/p99 latency of the refined path and of the plain FP64
+path, matvec-only rates (HIP events on the launch stream), the roofline of the FP32
+LGF-sum kernel, and the CPU oracle's rate on a bounded sample of the same matvec.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "LGF pair-interactions/s per BAE matvec; solves/s + p99 latency at rel err ≤1e-8"
+PEAK_FP32_VECTOR = 157.3   # TFLOP/s, MI355X published (packed FP32 included)
+NEAR_R = 32                # LDS table radius of the kernel
+FLOPS_FAR = 45             # far-field kernel value (q = 4 expansion), see the design doc
+FLOPS_ACC = 2              # accumulate per right-hand side
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pair_split(ctx, torch, dev):
+    """(near, far) pair counts of the gamma x (gamma- u E) sum, counted on the device."""
+    gp, gm, ex = ctx.sets()
+    T = torch.from_numpy(np.concatenate([gp, gm]).astype(np.int32)).to(dev)
+    S = torch.from_numpy(np.concatenate([gm, ex]).astype(np.int32)).to(dev)
+    near = 0
+    for i in range(0, T.shape[0], 512):
+        d = (T[i:i + 512, None, :] - S[None, :, :]).abs().amax(dim=-1)
+        near += int((d <= NEAR_R).sum().item())
+    total = T.shape[0] * S.shape[0]
+    return near, total - near
+
+
+def cpu_baseline(p, budget_s=12.0):
+    """The oracle's literal double-layer sum on a bounded sample of targets (1 thread)."""
+    from oracle import geometry, lgf, operators
+    g = geometry.from_problem(p)
+    G = lgf.LGFTable(g.max_offset(), p.sigma * p.h ** 2)
+    rng = np.random.default_rng(1234)
+    q = rng.standard_normal(len(g.gamma_minus))
+    T = operators.gamma_targets(g)
+    n_src = len(g.gamma_minus) + len(g.ext)
+    order = rng.permutation(len(T))
+    done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and done < len(T):
+        blk = T[order[done:done + 64]]
+        operators.double_layer(g, G, q, blk)
+        done += len(blk)
+    dt = time.perf_counter() - t0
+    return {"value": done * n_src / dt, "unit": "pair-interactions/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} of {len(T)} gamma targets x {n_src} sources (literal double-layer sum, FP64, "
+                      f"NumPy single thread), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--nodes", type=int, default=129, help="nodes per axis (h = 1/(nodes-1))")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--matvec-reps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2502_05507_amd as P
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    p = W.poisson_ellipsoid(args.nodes)
+    t_setup = time.perf_counter()
+    ctx = P.Context.from_problem(p)
+    xs, _, _ = ctx.boundary_points()
+    ctx.set_rhs(p.g(xs), p.f_grid())
+    t_setup = time.perf_counter() - t_setup
+    z = ctx.sizes
+    pairs_mv = z["n_targets"] * z["n_sources"]
+    log(f"setup {t_setup:.2f}s sizes {z}")
+
+    # ---- timed solves: FP32 LGF sum + FP64 refinement
+    tol = 1e-10
+    for _ in range(args.warmup):
+        ctx.solve(P.SOLVE_FP32_REFINED, tol=tol)
+    torch.cuda.synchronize()
+    lat, pairs_total = [], 0
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        s0 = time.perf_counter()
+        r = ctx.solve(P.SOLVE_FP32_REFINED, tol=tol)[0]
+        lat.append(time.perf_counter() - s0)
+        pairs_total += (r["matvecs_fp64"] + r["matvecs_fp32"] + 1) * pairs_mv
+        log(f"step {k}: {lat[-1] * 1e3:.1f} ms, iters {r['iterations']}, outer {r['outer_steps']}, "
+            f"relres {r['rel_residual_true']:.2e}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    refined = r
+    u32 = ctx.gamma_values()
+
+    # ---- plain FP64 path for comparison
+    ctx.solve(P.SOLVE_FP64, tol=tol)
+    lat64 = []
+    for _ in range(max(2, args.steps // 3)):
+        s0 = time.perf_counter()
+        r64 = ctx.solve(P.SOLVE_FP64, tol=tol)[0]
+        lat64.append(time.perf_counter() - s0)
+    u64 = ctx.gamma_values()
+    rel_err = float(np.linalg.norm(u32 - u64) / np.linalg.norm(u64))
+    log(f"fp64: {np.median(lat64) * 1e3:.1f} ms iters {r64['iterations']}; refined vs fp64 rel err {rel_err:.2e}")
+
+    # ---- matvec-only rates, HIP events on the stream the kernels are launched on
+    stream = torch.cuda.current_stream()
+    q = torch.from_numpy(np.random.default_rng(5).standard_normal(z["n_gamma_minus"])).to(dev)
+    v = torch.empty(z["n_targets"], dtype=torch.float64, device=dev)
+    mv = {}
+    for name, prec in (("fp32", P.PREC_FP32), ("fp64", P.PREC_FP64)):
+        for _ in range(3):
+            ctx.apply_double_layer(q, v, prec)
+        times = []
+        for _ in range(args.matvec_reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ctx.apply_double_layer(q, v, prec)
+            e1.record(stream)
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1) * 1e-3)
+        t_med = float(np.median(times))
+        mv[name] = {"median_ms": t_med * 1e3, "pairs_per_s": pairs_mv / t_med}
+    near, far = pair_split(ctx, torch, dev)
+    flops = far * (FLOPS_FAR + FLOPS_ACC) + near * FLOPS_ACC
+    achieved = flops / (mv["fp32"]["median_ms"] * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
+                "kernel": "lgf_sum_kernel<float,1> (+ weights and reduction, timed together)",
+                "flops_per_launch": flops, "near_pairs": near, "far_pairs": far}
+
+    out = {
+        "metric": METRIC,
+        "value": pairs_total / elapsed,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 LGF sum + f64 refinement",
+        "data": "synthetic",
+        "config": {"workload": f"poisson_ellipsoid_{args.nodes}^3",
+                   "geometry": "ellipsoid (0.45,0.3,0.25) in unit cube", "h": p.h, "sigma": 0.0,
+                   "gamma_targets": z["n_targets"], "sources": z["n_sources"], "pairs_per_matvec": pairs_mv,
+                   "tol": tol},
+        "solves_per_s": args.steps / elapsed,
+        "p50_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "refined": {"iterations": refined["iterations"], "outer_steps": refined["outer_steps"],
+                    "matvecs_fp32": refined["matvecs_fp32"], "matvecs_fp64": refined["matvecs_fp64"],
+                    "rel_residual": refined["rel_residual_true"], "rel_err_vs_fp64_gpu": rel_err},
+        "fp64_plain": {"solves_per_s": 1.0 / float(np.mean(lat64)), "p50_ms": float(np.percentile(lat64, 50) * 1e3),
+                       "p99_ms": float(np.percentile(lat64, 99) * 1e3), "iterations": r64["iterations"],
+                       "rel_residual": r64["rel_residual_true"]},
+        "matvec": mv,
+        "roofline": roofline,
+        "setup_s": t_setup,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p)
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

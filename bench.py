@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 METRIC = "LGF pair-interactions/s per BAE matvec; solves/s + p99 latency at rel err ≤1e-8"
 PEAK_FP32_VECTOR = 157.3   # TFLOP/s, MI355X published (packed FP32 included)
 NEAR_R = 32                # LDS table radius of the kernel
-FLOPS_FAR = 45             # far-field kernel value (q = 4 expansion), see the design doc
+FLOPS_FAR = 32             # FP32 far-field kernel value (q = 3 expansion), see the design doc
 FLOPS_ACC = 2              # accumulate per right-hand side
 
 

@@ -78,8 +78,8 @@ typedef struct bae_levelset {
 
 typedef struct bae_options {   /* zero-initialise for defaults                      */
     int32_t device;            /* HIP device ordinal                                */
-    int32_t near_radius_fp64;  /* LDS table radius of the FP64 sum (default 32)     */
-    int32_t near_radius_fp32;  /* LDS table radius of the FP32 sum (default 24)     */
+    int32_t near_radius_fp64;  /* LDS table radius of the FP64 sum (0 or 32: fixed)  */
+    int32_t near_radius_fp32;  /* LDS table radius of the FP32 sum (default 32)     */
     int32_t max_krylov;        /* Krylov basis capacity per RHS (default 400)       */
     int32_t max_rhs;           /* right-hand sides the context can hold (default 16) */
 } bae_options;
@@ -99,7 +99,9 @@ typedef struct bae_solve_params {
     int32_t precision;         /* BAE_SOLVE_*                                       */
     double tol;                /* relative residual target ||b - A q|| / ||b||      */
     int32_t maxit;             /* GMRES iterations per (inner) solve; <= max_krylov */
-    double inner_tol;          /* FP32 inner GMRES tolerance (refined mode, default 1e-5) */
+    double inner_tol;          /* refined mode: floor of the inner FP32 GMRES tolerance
+                                  (default 1e-6); each outer step asks for
+                                  max(floor, 0.5 tol / current residual), capped at 0.1 */
     int32_t max_outer;         /* refinement steps (default 8)                       */
     int32_t compute_grid;      /* also form u on N+ (volume-target LGF sums)         */
 } bae_solve_params;

@@ -91,25 +91,62 @@ static std::shared_ptr<Table> get_table(int device, double s, int R, hipStream_t
 
 // ------------------------------------------------------------------ context
 struct PointBuf {
-    DevMem x, y, z;
+    DevMem x, y, z, xf, yf, zf, xd, yd, zd, bbox;
     PointSet ps;
     std::vector<int32_t> perm;   // internal index -> index in the lexicographic list
     void set(const std::vector<int32_t>& pts3, const std::vector<int32_t>& order, hipStream_t st) {
         const int64_t n = (int64_t)order.size();
-        std::vector<int32_t> hx(n), hy(n), hz(n);
-        for (int64_t i = 0; i < n; ++i) {
-            hx[i] = pts3[3 * order[i]];
-            hy[i] = pts3[3 * order[i] + 1];
-            hz[i] = pts3[3 * order[i] + 2];
+        const int64_t nblk = (n + kSourceBlock - 1) / kSourceBlock;
+        const int64_t np = nblk * kSourceBlock;
+        std::vector<int32_t> h[3];
+        std::vector<float> hf[3];
+        std::vector<double> hd[3];
+        for (int a = 0; a < 3; ++a) {
+            h[a].resize(np);
+            hf[a].resize(np);
+            hd[a].resize(np);
+            for (int64_t i = 0; i < np; ++i) {
+                h[a][i] = pts3[3 * order[std::min(i, n - 1)] + a];
+                hf[a][i] = (float)h[a][i];
+                hd[a][i] = (double)h[a][i];
+            }
         }
-        upload(x, hx, st);
-        upload(y, hy, st);
-        upload(z, hz, st);
+        std::vector<int32_t> box(6 * nblk);
+        for (int64_t b = 0; b < nblk; ++b)
+            for (int a = 0; a < 3; ++a) {
+                int lo = 1 << 30, hi = -(1 << 30);
+                for (int64_t i = b * kSourceBlock; i < (b + 1) * kSourceBlock; ++i) {
+                    lo = std::min(lo, h[a][i]);
+                    hi = std::max(hi, h[a][i]);
+                }
+                box[6 * b + a] = lo;
+                box[6 * b + 3 + a] = hi;
+            }
+        upload(x, h[0], st);
+        upload(y, h[1], st);
+        upload(z, h[2], st);
+        upload(xf, hf[0], st);
+        upload(yf, hf[1], st);
+        upload(zf, hf[2], st);
+        upload(xd, hd[0], st);
+        upload(yd, hd[1], st);
+        upload(zd, hd[2], st);
+        upload(bbox, box, st);
         ps.count = n;
+        ps.padded = np;
         ps.x = x.as<int32_t>();
         ps.y = y.as<int32_t>();
         ps.z = z.as<int32_t>();
+        ps.xf = xf.as<float>();
+        ps.yf = yf.as<float>();
+        ps.zf = zf.as<float>();
+        ps.xd = xd.as<double>();
+        ps.yd = yd.as<double>();
+        ps.zd = zd.as<double>();
+        ps.bbox = bbox.as<int32_t>();
+        ps.nblk = nblk;
         perm = order;
+        BAE_HIP_CHECK(hipStreamSynchronize(st));   // host vectors are released on return
     }
 };
 
@@ -163,7 +200,7 @@ static void apply_lgf(bae_ctx* c, const PointSet& T, const PointSet& S, const vo
 // v = [D+ q; D- q] (external order), q [nrhs][ngm] with leading dimension ldq
 static void double_layer(bae_ctx* c, const double* q, int64_t ldq, double* v, int64_t ldv, int nrhs, int prec,
                          hipStream_t st) {
-    launch_weights(c->B, q, ldq, c->w.p, c->nS, nrhs, prec, st);
+    launch_weights(c->B, q, ldq, c->w.p, c->S.ps.padded, nrhs, prec, st);
     int chunks = 0;
     apply_lgf(c, c->T.ps, c->S.ps, c->w.p, nrhs, prec, c->part.as<double>(), c->part_cap, &chunks, st);
     launch_reduce_scatter(c->part.as<double>(), chunks, c->nT, c->t_pos.as<int32_t>(), v, ldv, nrhs, 1.0, st);
@@ -172,7 +209,7 @@ static void double_layer(bae_ctx* c, const double* q, int64_t ldq, double* v, in
 // aq = Phi+ D+ q + Phi- D- q
 static void bae_operator(bae_ctx* c, const double* q, int64_t ldq, double* aq, int64_t lda, int nrhs, int prec,
                          hipStream_t st) {
-    launch_weights(c->B, q, ldq, c->w.p, c->nS, nrhs, prec, st);
+    launch_weights(c->B, q, ldq, c->w.p, c->S.ps.padded, nrhs, prec, st);
     int chunks = 0;
     apply_lgf(c, c->T.ps, c->S.ps, c->w.p, nrhs, prec, c->part.as<double>(), c->part_cap, &chunks, st);
     launch_closure(c->part.as<double>(), chunks, c->nT, c->cl, aq, lda, nrhs, st);
@@ -435,7 +472,8 @@ int bae_create(const bae_grid* grid, const bae_levelset* ls, const bae_options* 
         upload(c->csr_rowptr, rowptr, st);
         upload(c->csr_col, col, st);
         upload(c->csr_coef, coef, st);
-        c->B = CSR{c->nS, c->csr_rowptr.as<int32_t>(), c->csr_col.as<int32_t>(), c->csr_coef.as<double>()};
+        c->B = CSR{c->nS, c->S.ps.padded, c->csr_rowptr.as<int32_t>(), c->csr_col.as<int32_t>(),
+                   c->csr_coef.as<double>()};
         // closure rows
         std::vector<int32_t> ctq(c->ngm), ctp(c->ngm);
         for (int64_t q = 0; q < c->ngm; ++q) {
@@ -460,7 +498,7 @@ int bae_create(const bae_grid* grid, const bae_levelset* ls, const bae_options* 
 
         // work buffers
         const int mr = c->max_rhs;
-        c->w.alloc(sizeof(double) * c->nS * mr);
+        c->w.alloc(sizeof(double) * c->S.ps.padded * mr);
         const int chunks = lgf_sum_chunks(c->nT, c->nS);
         c->part_cap = (int64_t)chunks * c->nT * mr;
         c->part.alloc(sizeof(double) * c->part_cap);
@@ -529,6 +567,9 @@ int bae_get_sizes(const bae_ctx* c, bae_sizes* o) {
         o->table_entries = table_size(c->tabs.full_r);
         size_t bytes = 0;
         for (const DevMem* d : {&c->T.x, &c->T.y, &c->T.z, &c->S.x, &c->S.y, &c->S.z, &c->Mp.x, &c->Mp.y, &c->Mp.z,
+                                &c->T.xf, &c->T.yf, &c->T.zf, &c->S.xf, &c->S.yf, &c->S.zf, &c->Mp.xf, &c->Mp.yf,
+                                &c->Mp.zf, &c->T.xd, &c->T.yd, &c->T.zd, &c->S.xd, &c->S.yd, &c->S.zd, &c->Mp.xd,
+                                &c->Mp.yd, &c->Mp.zd, &c->T.bbox, &c->S.bbox, &c->Mp.bbox,
                                 &c->t_pos, &c->csr_rowptr, &c->csr_col, &c->csr_coef, &c->cl_tq, &c->cl_tp, &c->cl_t,
                                 &c->w, &c->part, &c->kV, &c->kH, &c->kcs, &c->ksn, &c->kg, &c->khist, &c->kbeta,
                                 &c->kdone, &c->kkdone, &c->hA, &c->hB, &c->nrm, &c->dotpart, &c->ycoef, &c->b, &c->x,
@@ -584,10 +625,11 @@ int bae_set_rhs(bae_ctx* c, int32_t nrhs, const double* g_xstar, const double* f
                                 pts.push_back((int32_t)(((int64_t)i * G.n[1] + j) * G.n[2] + k));
                 for (int64_t a = 0; a < nm; ++a) lin[a] = pts[c->Mp.perm[a]];
             }
-            std::vector<double> wfh(nm * nrhs);
+            const int64_t nmp = c->Mp.ps.padded;
+            std::vector<double> wfh(nmp * nrhs, 0.0);
             const double h2 = G.h * G.h;
             for (int r = 0; r < nrhs; ++r)
-                for (int64_t a = 0; a < nm; ++a) wfh[r * nm + a] = h2 * f_grid[r * N3 + lin[a]];
+                for (int64_t a = 0; a < nm; ++a) wfh[r * nmp + a] = h2 * f_grid[r * N3 + lin[a]];
             upload(c->wf, wfh, st);
             lgf_sum_to(c, c->T.ps, c->Mp.ps, c->wf.as<double>(), nrhs, c->t_pos.as<int32_t>(), c->up_gamma.as<double>(),
                        c->nT, 1.0, st);
@@ -639,7 +681,10 @@ int bae_solve(bae_ctx* c, const bae_solve_params* p, bae_result* res) {
             relres = residual(c, nrhs, bn, st, &mv64);
             for (int r = 0; r < nrhs; ++r) conv[r] = g.converged[r];
         } else {
-            const double inner = p->inner_tol > 0 ? p->inner_tol : 1e-5;
+            // inner tolerance of outer step k: just enough to reach tol from the current
+            // residual, but never below the floor where the FP32 operator's own error (~1e-6
+            // relative) makes further inner iterations useless
+            const double floor_tol = p->inner_tol > 0 ? p->inner_tol : 1e-6;
             const int max_outer = p->max_outer > 0 ? p->max_outer : 8;
             BAE_HIP_CHECK(hipMemcpyAsync(c->r.p, c->b.p, sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, st));
             relres.assign(nrhs, 1.0);
@@ -647,12 +692,14 @@ int bae_solve(bae_ctx* c, const bae_solve_params* p, bae_result* res) {
             for (int o = 0; o < max_outer; ++o) {
                 std::vector<int> skip(nrhs, 0);
                 bool all = true;
+                double worst = 0.0;
                 for (int r = 0; r < nrhs; ++r) {
                     skip[r] = relres[r] <= p->tol;
                     all &= skip[r] != 0;
+                    if (!skip[r]) worst = std::max(worst, relres[r]);
                 }
                 if (all) break;
-                // the inner solve works on r scaled to unit size; its tolerance is relative
+                const double inner = std::min(0.1, std::max(floor_tol, 0.5 * p->tol / worst));
                 GmresOut g = gmres(c, c->r.as<double>(), nrhs, BAE_PREC_FP32, inner, maxit, skip, c->x.as<double>(),
                                    true, st, &mv32);
                 for (int r = 0; r < nrhs; ++r) {
@@ -677,7 +724,7 @@ int bae_solve(bae_ctx* c, const bae_solve_params* p, bae_result* res) {
             const int64_t nm = c->Mp.ps.count;
             DevMem um;
             um.alloc(sizeof(double) * nm * nrhs);
-            launch_weights(c->B, c->x.as<double>(), n, c->w.p, c->nS, nrhs, BAE_PREC_FP64, st);
+            launch_weights(c->B, c->x.as<double>(), n, c->w.p, c->S.ps.padded, nrhs, BAE_PREC_FP64, st);
             lgf_sum_to(c, c->Mp.ps, c->S.ps, c->w.as<double>(), nrhs, nullptr, um.as<double>(), nm, 1.0, st);
             if (c->has_f) {
                 DevMem up;

@@ -51,12 +51,27 @@ int64_t table_size(int R);
 void lgf_table_generate(double s, int R, double* out, hipStream_t stream);
 
 // ------------------------------------------------------------------ LGF sum (device)
-// A set of integer points on the device (SoA) with its Morton permutation.
+// Points are grouped in blocks of kSourceBlock consecutive (Morton-ordered) points; each
+// block carries its integer bounding box so a wavefront can classify a whole block as
+// near, far or mixed before touching its points.
+constexpr int kSourceBlock = 64;
+
+// A set of integer lattice points on the device: SoA int32 coordinates, the same
+// coordinates as float and double, and per-block bounding boxes [nblk][lo xyz, hi xyz].
 struct PointSet {
     int64_t count = 0;
+    int64_t padded = 0;        // nblk * kSourceBlock; entries past count repeat the last point
     int32_t* x = nullptr;
     int32_t* y = nullptr;
     int32_t* z = nullptr;
+    float* xf = nullptr;
+    float* yf = nullptr;
+    float* zf = nullptr;
+    double* xd = nullptr;
+    double* yd = nullptr;
+    double* zd = nullptr;
+    int32_t* bbox = nullptr;
+    int64_t nblk = 0;
 };
 
 enum SumMode { MODE_NEAR_FAR = 0, MODE_TABLE = 1 };

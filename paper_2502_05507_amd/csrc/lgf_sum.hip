@@ -23,10 +23,12 @@
 // Layout and launch: targets and sources are in Morton order (SoA int32 x, y, z), so the
 // 64 targets of a wavefront form a compact patch and near/far branches are mostly uniform.
 // One thread owns one target; the source loop index is wavefront-uniform, so source
-// coordinates and weights come through scalar loads.  The grid is (target tiles) x (source
-// chunks); each block writes its partial sums, reduced later in a fixed order
-// (deterministic results).  FP32 pairs are summed in FP32 over runs of 32 sources and
-// the run sums folded into a Neumaier-compensated FP32 accumulator.
+// coordinates and weights come through scalar loads.  Sources come in Morton blocks of 64
+// with bounding boxes, so each wavefront classifies a whole block (all far, all near, or
+// mixed) with one uniform branch.  The grid is (target tiles) x (source chunks); each
+// block writes its partial sums, reduced later in a fixed order (deterministic results).
+// FP32 pairs are summed in FP32 over each source block and the block sums folded into a
+// Neumaier-compensated FP32 accumulator.
 #include <algorithm>
 
 #include "ops.hpp"
@@ -36,9 +38,9 @@ namespace bae {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kUnroll = 8;                           // sources per unrolled step (batched scalar loads)
 constexpr int kNearR = 32;                           // LDS table radius (both precisions)
 constexpr int kNearE = (kNearR + 1) * (kNearR + 2) * (kNearR + 3) / 6;
-constexpr int kRun = 32;                             // FP32 run length before compensation
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr double C0 = 1.0 / (4.0 * kPi);
@@ -55,21 +57,27 @@ __device__ __forceinline__ double rsqrt_t<double>(double x) { return rsqrt(x); }
 template <>
 __device__ __forceinline__ float rsqrt_t<float>(float x) { return __builtin_amdgcn_rsqf(x); }
 
-// far field for an integer offset with squares X, Y, Z (all >= 0, not all 0)
+// Far field from the squared offset components (all >= 0, not all 0).  FP64 keeps the
+// q = 4 term (|error| <= 6.6e-11 relative beyond the LDS radius); FP32 stops at q = 3,
+// whose error there (<= 4.8e-9) is already below FP32 rounding.
 template <typename Real>
 __device__ __forceinline__ Real far_field(Real X, Real Y, Real Z) {
     const Real r2 = X + Y + Z;
-    const Real e2 = fma(X, Y + Z, Y * Z);
-    const Real e3 = X * Y * Z;
+    const Real yz = Y * Z;
+    const Real e2 = fma(X, Y + Z, yz);
+    const Real e3 = X * yz;
     const Real rinv = rsqrt_t<Real>(r2);
     const Real rho = rinv * rinv;
     const Real rho2 = rho * rho;
     const Real x = e2 * rho2;
     const Real y = e3 * rho2 * rho;
-    const Real f = fma(y, fma(Real(F5), x, Real(F4)), fma(x, fma(x, fma(x, Real(F3), Real(F2)), Real(F1)), Real(F0)));
-    const Real d = fma(Real(D3), y, fma(x, fma(x, Real(D2), Real(D1)), Real(D0)));
+    Real d = fma(Real(D3), y, fma(x, fma(x, Real(D2), Real(D1)), Real(D0)));
+    if constexpr (sizeof(Real) == 8) {
+        const Real f = fma(y, fma(Real(F5), x, Real(F4)), fma(x, fma(x, fma(x, Real(F3), Real(F2)), Real(F1)), Real(F0)));
+        d = fma(rho, f, d);
+    }
     const Real c = fma(Real(C2), x, Real(C1));
-    const Real B = fma(rho, fma(rho, fma(rho, f, d), c), Real(C0));
+    const Real B = fma(rho, fma(rho, d, c), Real(C0));
     return rinv * B;
 }
 
@@ -99,6 +107,15 @@ __device__ __forceinline__ Real eval_pair(int dx, int dy, int dz, const Real* __
     return full_tab[sorted_index64(a, b, c)];
 }
 
+__device__ __forceinline__ int wave_min(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ int wave_max(int v) {
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
 template <typename Real>
 struct Acc;
 template <>
@@ -121,37 +138,106 @@ struct Acc<float> {
     __device__ __forceinline__ double value() const { return (double)sum + (double)comp + (double)run; }
 };
 
+template <typename Real>
+struct SumArgs {
+    const int32_t *tx, *ty, *tz;
+    int nt;
+    const int32_t *sx, *sy, *sz;
+    const Real *sxr, *syr, *szr;      // source coordinates in the kernel's precision
+    const int32_t* sbox;              // [nblk][6] source block bounding boxes
+    int ns, nblk, blk_per_chunk;
+    const Real* w;
+    int64_t ldw;
+    const Real* near_tab;
+    const Real* full_tab;
+    int far_ok;
+    double* part;
+    int64_t ldp;
+};
+
+// One thread per target.  Each wavefront walks the source blocks of its chunk and, from
+// the bounding boxes of its 64 targets and of the block, picks one of four loops
+// (a wavefront-uniform branch):
+//   far     every pair beyond the LDS radius, sigma = 0: far field in registers
+//   gather  every pair beyond the LDS radius, sigma > 0: the global table
+//   near    every pair within the LDS radius: LDS table
+//   mixed   per-pair choice
 template <typename Real, int NR>
-__global__ __launch_bounds__(kBlock) void lgf_sum_kernel(
-    const int32_t* __restrict__ tx, const int32_t* __restrict__ ty, const int32_t* __restrict__ tz, int nt,
-    const int32_t* __restrict__ sx, const int32_t* __restrict__ sy, const int32_t* __restrict__ sz,
-    const Real* __restrict__ w, int64_t ldw, int ns, int chunk_len, const Real* __restrict__ near_tab,
-    int near_entries, const Real* __restrict__ full_tab, int far_ok, double* __restrict__ part, int64_t ldp) {
+__global__ __launch_bounds__(kBlock) void lgf_sum_kernel(const SumArgs<Real> a) {
     __shared__ Real tab[kNearE];
-    for (int i = threadIdx.x; i < near_entries; i += kBlock) tab[i] = near_tab[i];
+    for (int i = threadIdx.x; i < kNearE; i += kBlock) tab[i] = a.near_tab[i];
     __syncthreads();
 
     const int t = blockIdx.x * kBlock + threadIdx.x;
-    const int tc = min(t, nt - 1);
-    const int x = tx[tc], y = ty[tc], z = tz[tc];
-    const int s0 = blockIdx.y * chunk_len;
-    const int s1 = min(ns, s0 + chunk_len);
-    const bool ff = far_ok != 0;
+    const int tc = min(t, a.nt - 1);
+    const int ix = a.tx[tc], iy = a.ty[tc], iz = a.tz[tc];
+    const Real fx = (Real)ix, fy = (Real)iy, fz = (Real)iz;
+    const int lx = wave_min(ix), ly = wave_min(iy), lz = wave_min(iz);
+    const int hx = wave_max(ix), hy = wave_max(iy), hz = wave_max(iz);
 
+    const int b0 = blockIdx.y * a.blk_per_chunk;
+    const int b1 = min(a.nblk, b0 + a.blk_per_chunk);
     Acc<Real> acc[NR];
-    for (int sb = s0; sb < s1; sb += kRun) {
-        const int se = min(s1, sb + kRun);
-        for (int s = sb; s < se; ++s) {
-            const Real G = eval_pair<Real>(x - sx[s], y - sy[s], z - sz[s], tab, full_tab, ff);
+    for (int b = b0; b < b1; ++b) {
+        const int32_t* bb = a.sbox + 6 * b;
+        const int gap = max(max(max(bb[0] - hx, lx - bb[3]), max(bb[1] - hy, ly - bb[4])),
+                            max(max(bb[2] - hz, lz - bb[5]), 0));
+        const int span = max(max(max(bb[3] - lx, hx - bb[0]), max(bb[4] - ly, hy - bb[1])),
+                             max(bb[5] - lz, hz - bb[2]));
+        const int sb = b * kSourceBlock;        // blocks are full: the source arrays are padded
+        if (gap > kNearR && a.far_ok) {
+            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += kUnroll) {
 #pragma unroll
-            for (int r = 0; r < NR; ++r) acc[r].add(G * w[r * ldw + s]);
+                for (int u = 0; u < kUnroll; ++u) {
+                    const int s = s0 + u;
+                    const Real dx = fx - a.sxr[s], dy = fy - a.syr[s], dz = fz - a.szr[s];
+                    const Real G = far_field<Real>(dx * dx, dy * dy, dz * dz);
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) acc[r].add(G * a.w[r * a.ldw + s]);
+                }
+            }
+        } else if (gap > kNearR) {
+            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += kUnroll) {
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const int s = s0 + u;
+                    const uint32_t da = (uint32_t)abs(ix - a.sx[s]), db = (uint32_t)abs(iy - a.sy[s]),
+                                   dc = (uint32_t)abs(iz - a.sz[s]);
+                    const Real G = a.full_tab[sorted_index64(da, db, dc)];
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) acc[r].add(G * a.w[r * a.ldw + s]);
+                }
+            }
+        } else if (span <= kNearR) {
+            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += kUnroll) {
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const int s = s0 + u;
+                    const uint32_t da = (uint32_t)abs(ix - a.sx[s]), db = (uint32_t)abs(iy - a.sy[s]),
+                                   dc = (uint32_t)abs(iz - a.sz[s]);
+                    const Real G = tab[sorted_index(da, db, dc)];
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) acc[r].add(G * a.w[r * a.ldw + s]);
+                }
+            }
+        } else {
+            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += kUnroll) {
+#pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const int s = s0 + u;
+                    const Real G = eval_pair<Real>(ix - a.sx[s], iy - a.sy[s], iz - a.sz[s], tab, a.full_tab,
+                                                   a.far_ok != 0);
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) acc[r].add(G * a.w[r * a.ldw + s]);
+                }
+            }
         }
 #pragma unroll
         for (int r = 0; r < NR; ++r) acc[r].flush();
     }
-    if (t < nt) {
+    if (t < a.nt) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) part[(int64_t)r * ldp + (int64_t)blockIdx.y * nt + t] = acc[r].value();
+        for (int r = 0; r < NR; ++r) a.part[(int64_t)r * a.ldp + (int64_t)blockIdx.y * a.nt + t] = acc[r].value();
     }
 }
 
@@ -169,37 +255,208 @@ __global__ void lgf_eval_kernel(const int32_t* __restrict__ off, int64_t count, 
     out[i] = (double)eval_pair<Real>(dx, dy, dz, near_tab, full_tab, far_ok != 0);
 }
 
-template <typename Real, int NR>
-void launch_nr(const PointSet& T, const PointSet& S, const Real* w, int64_t ldw, const Real* near,
-               int near_entries, const Real* full, bool far, double* part, int64_t ldp, int chunks,
-               int chunk_len, hipStream_t st) {
-    dim3 grid((unsigned)((T.count + kBlock - 1) / kBlock), (unsigned)chunks);
-    lgf_sum_kernel<Real, NR><<<grid, kBlock, 0, st>>>(T.x, T.y, T.z, (int)T.count, S.x, S.y, S.z, w, ldw,
-                                                      (int)S.count, chunk_len, near, near_entries, full,
-                                                      far ? 1 : 0, part, ldp);
-    BAE_HIP_CHECK(hipGetLastError());
+
+// ------------------------------------------------------------------ 16-RHS blocked form on MFMA
+// For 16 right-hand sides the sum is the dense product V(T x 16) = K(T x S) W(S x 16), with
+// K(t, s) = G(t - s) never stored: every wavefront generates a 16 x 4 slice of K per step
+// (one kernel value per lane, exactly as in the VALU kernel) and contracts it with the
+// matching 4 x 16 slice of W on the matrix cores (v_mfma_{f32,f64}_16x16x4).
+// Operand layouts (16x16x4, measured on gfx950): A[i][k] in lane 16k + i, B[k][j] in lane
+// 16k + j; the result D[i][j] sits in lane 16v' + j, element v, with i = 4v' + v for f32
+// and i = v' + 4v for f64.
+// A wavefront owns kTiles tiles of 16 targets (64 targets, the same patch as the VALU
+// kernel, so the same near/far block classification applies); a workgroup of 4 wavefronts
+// stages each source block's 64 x 16 weights in LDS once for all of them.
+constexpr int kTiles = 4;
+
+template <typename Real>
+struct MfmaAcc;
+template <>
+struct MfmaAcc<float> {
+    using V = __attribute__((__vector_size__(4 * sizeof(float)))) float;
+    __device__ static V mma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
+template <>
+struct MfmaAcc<double> {
+    using V = __attribute__((__vector_size__(4 * sizeof(double)))) double;
+    __device__ static V mma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+};
+
+template <typename Real>
+__global__ __launch_bounds__(kBlock) void lgf_sum_mfma_kernel(const SumArgs<Real> a) {
+    using V = typename MfmaAcc<Real>::V;
+    __shared__ Real tab[kNearE];
+    __shared__ Real wl[kSourceBlock][16];
+    for (int i = threadIdx.x; i < kNearE; i += kBlock) tab[i] = a.near_tab[i];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int row = lane & 15;            // A row (target within a tile) / B, D column (RHS)
+    const int kq = lane >> 4;             // A column / B row (source within the step of 4)
+    const int base = (blockIdx.x * (kBlock / 64) + wave) * (16 * kTiles);
+    int ix[kTiles], iy[kTiles], iz[kTiles];
+    Real fx[kTiles], fy[kTiles], fz[kTiles];
+    int lx = 1 << 30, ly = 1 << 30, lz = 1 << 30, hx = -(1 << 30), hy = -(1 << 30), hz = -(1 << 30);
+#pragma unroll
+    for (int j = 0; j < kTiles; ++j) {
+        const int tc = min(base + 16 * j + row, a.nt - 1);
+        ix[j] = a.tx[tc];
+        iy[j] = a.ty[tc];
+        iz[j] = a.tz[tc];
+        fx[j] = (Real)ix[j];
+        fy[j] = (Real)iy[j];
+        fz[j] = (Real)iz[j];
+        lx = min(lx, ix[j]);
+        ly = min(ly, iy[j]);
+        lz = min(lz, iz[j]);
+        hx = max(hx, ix[j]);
+        hy = max(hy, iy[j]);
+        hz = max(hz, iz[j]);
+    }
+    lx = wave_min(lx);
+    ly = wave_min(ly);
+    lz = wave_min(lz);
+    hx = wave_max(hx);
+    hy = wave_max(hy);
+    hz = wave_max(hz);
+
+    V acc[kTiles], comp[kTiles];
+#pragma unroll
+    for (int j = 0; j < kTiles; ++j)
+        for (int v = 0; v < 4; ++v) acc[j][v] = comp[j][v] = Real(0);
+
+    const int b0 = blockIdx.y * a.blk_per_chunk;
+    const int b1 = min(a.nblk, b0 + a.blk_per_chunk);
+    for (int b = b0; b < b1; ++b) {
+        const int sb = b * kSourceBlock;
+        __syncthreads();
+        for (int i = threadIdx.x; i < kSourceBlock * 16; i += kBlock) {
+            const int r = i / kSourceBlock, sl = i % kSourceBlock;
+            wl[sl][r] = a.w[r * a.ldw + sb + sl];
+        }
+        __syncthreads();
+        const int32_t* bb = a.sbox + 6 * b;
+        const int gap = max(max(max(bb[0] - hx, lx - bb[3]), max(bb[1] - hy, ly - bb[4])),
+                            max(max(bb[2] - hz, lz - bb[5]), 0));
+        const int span = max(max(max(bb[3] - lx, hx - bb[0]), max(bb[4] - ly, hy - bb[1])),
+                             max(bb[5] - lz, hz - bb[2]));
+        const int mode = (gap > kNearR) ? (a.far_ok ? 0 : 1) : (span <= kNearR ? 2 : 3);
+        V blk[kTiles];
+#pragma unroll
+        for (int j = 0; j < kTiles; ++j)
+            for (int v = 0; v < 4; ++v) blk[j][v] = Real(0);
+        for (int st = 0; st < kSourceBlock; st += 4) {
+            const int s = sb + st + kq;
+            const Real wb = wl[st + kq][row];
+            Real G[kTiles];
+            if (mode == 0) {
+                const Real sx = a.sxr[s], sy = a.syr[s], sz = a.szr[s];
+#pragma unroll
+                for (int j = 0; j < kTiles; ++j) {
+                    const Real dx = fx[j] - sx, dy = fy[j] - sy, dz = fz[j] - sz;
+                    G[j] = far_field<Real>(dx * dx, dy * dy, dz * dz);
+                }
+            } else {
+                const int sx = a.sx[s], sy = a.sy[s], sz = a.sz[s];
+                if (mode == 1) {
+#pragma unroll
+                    for (int j = 0; j < kTiles; ++j)
+                        G[j] = a.full_tab[sorted_index64((uint32_t)abs(ix[j] - sx), (uint32_t)abs(iy[j] - sy),
+                                                         (uint32_t)abs(iz[j] - sz))];
+                } else if (mode == 2) {
+#pragma unroll
+                    for (int j = 0; j < kTiles; ++j)
+                        G[j] = tab[sorted_index((uint32_t)abs(ix[j] - sx), (uint32_t)abs(iy[j] - sy),
+                                                (uint32_t)abs(iz[j] - sz))];
+                } else {
+#pragma unroll
+                    for (int j = 0; j < kTiles; ++j)
+                        G[j] = eval_pair<Real>(ix[j] - sx, iy[j] - sy, iz[j] - sz, tab, a.full_tab, a.far_ok != 0);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < kTiles; ++j) blk[j] = MfmaAcc<Real>::mma(G[j], wb, blk[j]);
+        }
+        // fold the block's sums into the running (compensated, for FP32) accumulators
+#pragma unroll
+        for (int j = 0; j < kTiles; ++j)
+            for (int v = 0; v < 4; ++v) {
+                if constexpr (sizeof(Real) == 4) {
+                    const Real x = blk[j][v], sum = acc[j][v];
+                    const Real t = sum + x;
+                    comp[j][v] += fabs(sum) >= fabs(x) ? (sum - t) + x : (x - t) + sum;
+                    acc[j][v] = t;
+                } else {
+                    acc[j][v] += blk[j][v];
+                }
+            }
+    }
+    // element v of lane (kq, row): D[i][row], i = 4 kq + v (f32) or kq + 4 v (f64)
+#pragma unroll
+    for (int j = 0; j < kTiles; ++j)
+        for (int v = 0; v < 4; ++v) {
+            const int i = sizeof(Real) == 4 ? 4 * kq + v : kq + 4 * v;
+            const int t = base + 16 * j + i;
+            if (t < a.nt)
+                a.part[(int64_t)row * a.ldp + (int64_t)blockIdx.y * a.nt + t] =
+                    (double)acc[j][v] + (double)comp[j][v];
+        }
 }
 
 template <typename Real>
-void launch_all(const PointSet& T, const PointSet& S, const Real* w, int nrhs, const Real* near, int near_entries,
-                const Real* full, bool far, double* part, int chunks, int chunk_len, hipStream_t st) {
-    const int64_t ldw = S.count;
-    const int64_t ldp = (int64_t)chunks * T.count;
+const Real* coord(const PointSet& P, int axis);
+template <>
+const float* coord<float>(const PointSet& P, int axis) {
+    return axis == 0 ? P.xf : axis == 1 ? P.yf : P.zf;
+}
+template <>
+const double* coord<double>(const PointSet& P, int axis) {
+    return axis == 0 ? P.xd : axis == 1 ? P.yd : P.zd;
+}
+
+template <typename Real>
+void launch_all(const PointSet& T, const PointSet& S, const Real* w, int nrhs, const Real* near, const Real* full,
+                bool far, double* part, int chunks, hipStream_t st) {
+    SumArgs<Real> a;
+    a.tx = T.x;
+    a.ty = T.y;
+    a.tz = T.z;
+    a.nt = (int)T.count;
+    a.sx = S.x;
+    a.sy = S.y;
+    a.sz = S.z;
+    a.sxr = coord<Real>(S, 0);
+    a.syr = coord<Real>(S, 1);
+    a.szr = coord<Real>(S, 2);
+    a.sbox = S.bbox;
+    a.ns = (int)S.count;
+    a.nblk = (int)S.nblk;
+    a.blk_per_chunk = (int)((S.nblk + chunks - 1) / chunks);
+    a.ldw = S.padded;
+    a.near_tab = near;
+    a.full_tab = full;
+    a.far_ok = far ? 1 : 0;
+    a.ldp = (int64_t)chunks * T.count;
+    const dim3 grid((unsigned)((T.count + kBlock - 1) / kBlock), (unsigned)chunks);
+    const int per_block = (kBlock / 64) * 16 * kTiles;
+    const dim3 grid_mfma((unsigned)((T.count + per_block - 1) / per_block), (unsigned)chunks);
     int r = 0;
     while (r < nrhs) {
         const int left = nrhs - r;
-        const Real* wr = w + (int64_t)r * ldw;
-        double* pr = part + (int64_t)r * ldp;
+        SumArgs<Real> ar = a;
+        ar.w = w + (int64_t)r * a.ldw;
+        ar.part = part + (int64_t)r * a.ldp;
         if (left >= 16) {
-            launch_nr<Real, 16>(T, S, wr, ldw, near, near_entries, full, far, pr, ldp, chunks, chunk_len, st);
+            lgf_sum_mfma_kernel<Real><<<grid_mfma, kBlock, 0, st>>>(ar);
             r += 16;
         } else if (left >= 4) {
-            launch_nr<Real, 4>(T, S, wr, ldw, near, near_entries, full, far, pr, ldp, chunks, chunk_len, st);
+            lgf_sum_kernel<Real, 4><<<grid, kBlock, 0, st>>>(ar);
             r += 4;
         } else {
-            launch_nr<Real, 1>(T, S, wr, ldw, near, near_entries, full, far, pr, ldp, chunks, chunk_len, st);
+            lgf_sum_kernel<Real, 1><<<grid, kBlock, 0, st>>>(ar);
             r += 1;
         }
+        BAE_HIP_CHECK(hipGetLastError());
     }
 }
 
@@ -210,7 +467,7 @@ int lgf_near_radius() { return kNearR; }
 int lgf_sum_chunks(int64_t nt, int64_t ns) {
     const int64_t tiles = (nt + kBlock - 1) / kBlock;
     int64_t chunks = (2048 + tiles - 1) / tiles;           // aim at >= 2048 blocks
-    chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, ns / 512));
+    chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, ns / (8 * kSourceBlock)));
     return (int)std::max<int64_t>(1, std::min<int64_t>(chunks, 64));
 }
 
@@ -220,19 +477,15 @@ int lgf_sum_launch(const PointSet& T, const PointSet& S, const void* w, int nrhs
     int chunks = lgf_sum_chunks(T.count, S.count);
     while (chunks > 1 && (int64_t)chunks * T.count * nrhs > part_capacity) --chunks;
     if ((int64_t)chunks * T.count * nrhs > part_capacity) throw Error{BAE_ERR_ARG, "partial-sum buffer too small"};
-    const int chunk_len = (int)((S.count + chunks - 1) / chunks);
     if (tabs.full_r < kNearR) throw Error{BAE_ERR_ARG, "resident table radius below the LDS radius"};
-    const int near_entries = kNearE;
     if (S.count == 0) {
         launch_fill(part, (int64_t)chunks * T.count * nrhs, 0.0, st);
         return chunks;
     }
     if (prec == BAE_PREC_FP64)
-        launch_all<double>(T, S, (const double*)w, nrhs, tabs.near64, near_entries, tabs.full64, tabs.far_field, part,
-                           chunks, chunk_len, st);
+        launch_all<double>(T, S, (const double*)w, nrhs, tabs.near64, tabs.full64, tabs.far_field, part, chunks, st);
     else
-        launch_all<float>(T, S, (const float*)w, nrhs, tabs.near32, near_entries, tabs.full32, tabs.far_field, part,
-                          chunks, chunk_len, st);
+        launch_all<float>(T, S, (const float*)w, nrhs, tabs.near32, tabs.full32, tabs.far_field, part, chunks, st);
     return chunks;
 }
 

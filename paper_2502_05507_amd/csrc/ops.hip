@@ -13,16 +13,19 @@ constexpr int kThreads = 256;
 inline unsigned blocks_for(int64_t n, int per = kThreads) { return (unsigned)((n + per - 1) / per); }
 
 // w[r][s] = sum_{j in row s} coef[j] q[r][col[j]]   (Sec. 3.2: w(n) = |D_n| q(n), w(k) = -sum q)
+// Rows in [ns, npad) are the padding sources of the last block: weight zero.
 template <typename Real>
 __global__ void weights_kernel(const int32_t* __restrict__ rowptr, const int32_t* __restrict__ col,
-                               const double* __restrict__ coef, int64_t ns, const double* __restrict__ q,
-                               int64_t ldq, Real* __restrict__ w, int64_t ldw) {
+                               const double* __restrict__ coef, int64_t ns, int64_t npad,
+                               const double* __restrict__ q, int64_t ldq, Real* __restrict__ w, int64_t ldw) {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
-    if (s >= ns) return;
-    const double* qr = q + r * ldq;
+    if (s >= npad) return;
     double acc = 0.0;
-    for (int j = rowptr[s]; j < rowptr[s + 1]; ++j) acc = fma(coef[j], qr[col[j]], acc);
+    if (s < ns) {
+        const double* qr = q + r * ldq;
+        for (int j = rowptr[s]; j < rowptr[s + 1]; ++j) acc = fma(coef[j], qr[col[j]], acc);
+    }
     w[r * ldw + s] = (Real)acc;
 }
 
@@ -235,12 +238,14 @@ __global__ void to_float_kernel(const double* __restrict__ x, float* __restrict_
 
 void launch_weights(const CSR& B, const double* q, int64_t ldq, void* w, int64_t ldw, int nrhs, int prec,
                     hipStream_t st) {
-    if (B.rows == 0) return;
-    dim3 grid(blocks_for(B.rows), nrhs);
+    if (B.padded_rows == 0) return;
+    dim3 grid(blocks_for(B.padded_rows), nrhs);
     if (prec == BAE_PREC_FP64)
-        weights_kernel<double><<<grid, kThreads, 0, st>>>(B.rowptr, B.col, B.coef, B.rows, q, ldq, (double*)w, ldw);
+        weights_kernel<double><<<grid, kThreads, 0, st>>>(B.rowptr, B.col, B.coef, B.rows, B.padded_rows, q, ldq,
+                                                          (double*)w, ldw);
     else
-        weights_kernel<float><<<grid, kThreads, 0, st>>>(B.rowptr, B.col, B.coef, B.rows, q, ldq, (float*)w, ldw);
+        weights_kernel<float><<<grid, kThreads, 0, st>>>(B.rowptr, B.col, B.coef, B.rows, B.padded_rows, q, ldq,
+                                                         (float*)w, ldw);
     LAUNCH_CHECK();
 }
 

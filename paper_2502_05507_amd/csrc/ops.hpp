@@ -10,6 +10,7 @@ namespace bae {
 // Sparse map from densities on gamma- to source weights on gamma- u E (internal order).
 struct CSR {
     int64_t rows = 0;
+    int64_t padded_rows = 0;   // weights past `rows` are written as zero
     int32_t* rowptr = nullptr;
     int32_t* col = nullptr;
     double* coef = nullptr;

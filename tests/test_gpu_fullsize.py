@@ -1,0 +1,88 @@
+"""GPU parity at the full workload sizes, on outputs the oracle can compute one by one."""
+import numpy as np
+import pytest
+
+import paper_2502_05507_amd as P
+import workloads as W
+from oracle import geometry, lgf, operators
+
+from gpu_common import device, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def test_poisson_ellipsoid_129_matvec_sampled():
+    import torch
+    p = W.poisson_ellipsoid(129)
+    g = geometry.from_problem(p)
+    G = lgf.LGFTable(g.max_offset(), 0.0)
+    T = operators.gamma_targets(g)
+    rng = np.random.default_rng(129)
+    q = rng.standard_normal(len(g.gamma_minus))
+    pick = np.sort(rng.choice(len(T), 300, replace=False))
+    ref = operators.double_layer(g, G, q, T[pick])
+    with P.Context.from_problem(p) as ctx:
+        qd = torch.from_numpy(q).to(device())
+        v = torch.empty(len(T), dtype=torch.float64, device=device())
+        for prec, tol in ((P.PREC_FP64, 1e-10), (P.PREC_FP32, 2e-5)):
+            ctx.apply_double_layer(qd, v, prec)
+            torch.cuda.synchronize()
+            assert rel_l2(v.cpu().numpy()[pick], ref) < tol
+
+
+def test_poisson_ellipsoid_129_solve_satisfies_oracle_system():
+    # The GPU density must solve the oracle's own system b = A q on sampled rows, and its
+    # u_gamma must be the oracle's D q + u_p there.
+    p = W.poisson_ellipsoid(129)
+    g = geometry.from_problem(p)
+    G = lgf.LGFTable(g.max_offset(), 0.0)
+    f = p.f_grid()
+    with P.Context.from_problem(p) as ctx:
+        xs, _, _ = ctx.boundary_points()
+        ctx.set_rhs(p.g(xs), f)
+        for prec in (P.SOLVE_FP64, P.SOLVE_FP32_REFINED):
+            res = ctx.solve(prec, tol=1e-11)[0]
+            assert res["converged"]
+            q = ctx.density()
+            ug = ctx.gamma_values()
+            rng = np.random.default_rng(5)
+            rows = np.sort(rng.choice(len(g.gamma_minus), 120, replace=False))
+            npl = len(g.gamma_plus)
+            tq = g.gamma_minus[rows]
+            tp = g.gamma_plus[g.partner[rows]]
+            pts = np.concatenate([tq, tp])
+            v = operators.double_layer(g, G, q, pts)
+            up = operators.volume_potential(g, G, f, pts)
+            k = len(rows)
+            t = g.t[rows]
+            Aq = (1 - t) * v[:k] + t * v[k:]
+            b = p.g(g.xstar[rows]) - ((1 - t) * up[:k] + t * up[k:])
+            bscale = np.abs(p.g(g.xstar)).max()
+            assert np.abs(b - Aq).max() < 1e-9 * bscale
+            assert np.abs(ug[npl + rows] - (v[:k] + up[:k])).max() < 1e-9 * bscale
+            X = g.coords(g.gamma_minus[rows])
+            # and the discrete solution is O(h^2) close to the exact one there
+            assert np.abs(ug[npl + rows] - p.exact(*X.T)).max() < 2e-3
+
+
+def test_helmholtz_star_257_sixteen_rhs_sampled():
+    import torch
+    p = W.helmholtz_star()
+    g = geometry.from_problem(p)
+    G = lgf.LGFTable(g.max_offset(), p.sigma * p.h ** 2)
+    T = operators.gamma_targets(g)
+    rng = np.random.default_rng(257)
+    q = rng.standard_normal((16, len(g.gamma_minus)))
+    pick = np.sort(rng.choice(len(T), 24, replace=False))
+    ref = np.stack([operators.double_layer(g, G, q[r], T[pick]) for r in range(16)])
+    with P.Context.from_problem(p) as ctx:
+        z = ctx.sizes
+        assert (z["n_gamma_plus"], z["n_gamma_minus"], z["n_ext"], z["n_edges"]) == (114202, 115646, 117098, 212182)
+        qd = torch.from_numpy(q).to(device())
+        v = torch.empty((16, len(T)), dtype=torch.float64, device=device())
+        for prec, tol in ((P.PREC_FP64, 1e-10), (P.PREC_FP32, 2e-5)):
+            ctx.apply_double_layer(qd, v, prec)
+            torch.cuda.synchronize()
+            out = v.cpu().numpy()[:, pick]
+            for r in range(16):
+                assert rel_l2(out[r], ref[r]) < tol

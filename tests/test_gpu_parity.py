@@ -232,3 +232,32 @@ def test_error_paths():
     with pytest.raises(P.BaeError) as e:
         P.Context((17, 17, 17), 1 / 16, (0, 0, 0), 0.0, "sphere", (0.5, 0.5, 0.5), (0.49,))
     assert e.value.status == -2
+
+
+# ------------------------------------------------------------------ A10: 16 right-hand sides (MFMA form)
+@pytest.mark.parametrize("kind,n,sigma", [("ellipsoid", 65, 0.0), ("sphere", 97, 30.0), ("torus", 41, 10.0)])
+def test_sixteen_rhs_blocked_form_matches_oracle(kind, n, sigma):
+    torch = torch_mod()
+    p = small_problem(kind, n, sigma)
+    g, G = oracle_setup(p)
+    rng = np.random.default_rng(7 * n)
+    nr = 18                                   # one 16-wide MFMA group + a ragged VALU tail
+    q = rng.standard_normal((nr, len(g.gamma_minus)))
+    T = operators.gamma_targets(g)
+    D = operators.dense_double_layer(g, G, T) if len(T) * len(g.gamma_minus) < 3e7 else None
+    pick = rng.choice(len(T), size=min(len(T), 400), replace=False)
+    if D is not None:
+        ref = q @ D.T
+    else:
+        ref = np.stack([operators.double_layer(g, G, q[r], T[pick]) for r in range(nr)])
+    with P.Context.from_problem(p, max_rhs=nr) as ctx:
+        qd = torch.from_numpy(q).to(device())
+        v = torch.empty((nr, len(T)), dtype=torch.float64, device=device())
+        for prec, tol in ((P.PREC_FP64, 1e-10), (P.PREC_FP32, 2e-5)):
+            ctx.apply_double_layer(qd, v, prec)
+            torch.cuda.synchronize()
+            out = v.cpu().numpy()
+            if D is None:
+                out = out[:, pick]
+            for r in range(nr):
+                assert rel_l2(out[r], ref[r]) < tol, (prec, r, rel_l2(out[r], ref[r]))

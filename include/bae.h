@@ -198,6 +198,32 @@ int bae_apply_operator(bae_ctx* ctx, const double* q_dev, double* aq_dev, int32_
 int bae_lgf_eval(bae_ctx* ctx, const int32_t* offsets_dev, int64_t count, double* out_dev,
                  int32_t precision, void* stream);
 
+/* ------------------------------------------------------------------ batched solves */
+typedef struct bae_batch bae_batch;
+/*
+ * Group n contexts for lock-step solving (the batched form of Algorithm 1's solve step).
+ * Every context must hold exactly one RHS (bae_set_rhs with nrhs = 1) and live on the
+ * same device.  The batch keeps pointers to the contexts: they must outlive it and must
+ * not be used concurrently with it.  Each GMRES phase is one launch for all problems; the
+ * LGF sum is a persistent kernel over (problem, target tile, source chunk) items.
+ */
+int bae_batch_create(bae_ctx* const* ctxs, int32_t n, bae_batch** out);
+/*
+ * Time the LGF-sum tiling candidates (source blocks per chunk x persistent grid size) on
+ * this batch at `precision`, keep the fastest, and append it to the tuning cache
+ * ($BAE_AUTOTUNE_CACHE, else ~/.cache/bae_autotune.txt; keyed by GPU arch, log2 of the
+ * pair count and of the batch size) that bae_batch_create reads.  chosen: 2 int32 (or NULL).
+ */
+int bae_batch_autotune(bae_batch* b, int32_t precision, int32_t* chosen);
+/*
+ * Solve every problem (GMRES x0 = 0, FP64 or FP32-refined as in bae_solve).  use_graph = 1
+ * captures 8 GMRES iterations once as a HIP graph and replays it; 0 launches eagerly.
+ * results: n entries (or NULL).  Densities, u_gamma and histories land in each context
+ * (bae_get_density / bae_get_gamma_values / bae_get_history).
+ */
+int bae_batch_solve(bae_batch* b, const bae_solve_params* params, int32_t use_graph, bae_result* results);
+int bae_batch_destroy(bae_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -93,6 +93,10 @@ def load_library():
         "bae_apply_double_layer": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P]),
         "bae_apply_operator": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P]),
         "bae_lgf_eval": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int32, _P]),
+        "bae_batch_create": (C.c_int, [_P, C.c_int32, C.POINTER(_P)]),
+        "bae_batch_autotune": (C.c_int, [_P, C.c_int32, _P]),
+        "bae_batch_solve": (C.c_int, [_P, C.POINTER(SolveParams), C.c_int32, _P]),
+        "bae_batch_destroy": (C.c_int, [_P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -257,3 +261,44 @@ class Context:
         assert offsets.is_contiguous() and offsets.shape[-1] == 3 and out.numel() == offsets.shape[0]
         _check(load_library().bae_lgf_eval(self._h, _dptr(offsets), offsets.shape[0], _dptr(out), precision,
                                            _stream(stream)))
+
+
+class Batch:
+    """Lock-step solves of many single-RHS contexts (bae_batch_*)."""
+
+    def __init__(self, contexts):
+        lib = load_library()
+        self.contexts = list(contexts)
+        arr = (_P * len(self.contexts))(*[c._h for c in self.contexts])
+        h = _P()
+        _check(lib.bae_batch_create(arr, len(self.contexts), C.byref(h)))
+        self._h = h
+
+    def autotune(self, precision=PREC_FP32):
+        chosen = np.zeros(2, np.int32)
+        _check(load_library().bae_batch_autotune(self._h, precision, _ptr(chosen)))
+        return {"blocks_per_chunk": int(chosen[0]), "grid_multiplier": int(chosen[1])}
+
+    def solve(self, precision=SOLVE_FP64, tol=1e-10, maxit=0, inner_tol=0.0, max_outer=0, use_graph=True):
+        p = SolveParams(int(precision), float(tol), int(maxit), float(inner_tol), int(max_outer), 0)
+        res = (Result * len(self.contexts))()
+        rc = load_library().bae_batch_solve(self._h, C.byref(p), 1 if use_graph else 0, res)
+        _check(rc, allow_not_converged=True)
+        return [r.as_dict() for r in res]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().bae_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,160 @@
+// Host-side state of one BAE context (shared by the C ABI in bae.cpp and the batch engine).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <functional>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "ops.hpp"
+
+namespace bae {
+
+// ------------------------------------------------------------------ device memory
+struct DevMem {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    DevMem(const DevMem&) = delete;
+    DevMem& operator=(const DevMem&) = delete;
+    ~DevMem() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void alloc(size_t n) {
+        release();
+        if (n == 0) n = 8;
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            p = nullptr;
+            throw Error{BAE_ERR_OOM, "hipMalloc of " + std::to_string(n) + " bytes failed"};
+        }
+        bytes = n;
+    }
+    template <typename T>
+    T* as() const { return (T*)p; }
+};
+
+template <typename T>
+inline void upload(DevMem& m, const std::vector<T>& v, hipStream_t st) {
+    m.alloc(sizeof(T) * v.size());
+    if (!v.empty()) BAE_HIP_CHECK(hipMemcpyAsync(m.p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+}
+
+// ------------------------------------------------------------------ LGF table cache
+struct Table {
+    int device = 0;
+    double s = 0.0;
+    int R = 0;
+    DevMem d64, d32;
+};
+
+std::shared_ptr<Table> get_table(int device, double s, int R, hipStream_t st);
+int guard(const std::function<void()>& fn);
+
+// ------------------------------------------------------------------ context
+struct PointBuf {
+    DevMem x, y, z, xf, yf, zf, xd, yd, zd, bbox;
+    PointSet ps;
+    std::vector<int32_t> perm;   // internal index -> index in the lexicographic list
+    void set(const std::vector<int32_t>& pts3, const std::vector<int32_t>& order, hipStream_t st) {
+        const int64_t n = (int64_t)order.size();
+        const int64_t nblk = (n + kSourceBlock - 1) / kSourceBlock;
+        const int64_t np = nblk * kSourceBlock;
+        std::vector<int32_t> h[3];
+        std::vector<float> hf[3];
+        std::vector<double> hd[3];
+        for (int a = 0; a < 3; ++a) {
+            h[a].resize(np);
+            hf[a].resize(np);
+            hd[a].resize(np);
+            for (int64_t i = 0; i < np; ++i) {
+                h[a][i] = pts3[3 * order[std::min(i, n - 1)] + a];
+                hf[a][i] = (float)h[a][i];
+                hd[a][i] = (double)h[a][i];
+            }
+        }
+        std::vector<int32_t> box(6 * nblk);
+        for (int64_t b = 0; b < nblk; ++b)
+            for (int a = 0; a < 3; ++a) {
+                int lo = 1 << 30, hi = -(1 << 30);
+                for (int64_t i = b * kSourceBlock; i < (b + 1) * kSourceBlock; ++i) {
+                    lo = std::min(lo, h[a][i]);
+                    hi = std::max(hi, h[a][i]);
+                }
+                box[6 * b + a] = lo;
+                box[6 * b + 3 + a] = hi;
+            }
+        upload(x, h[0], st);
+        upload(y, h[1], st);
+        upload(z, h[2], st);
+        upload(xf, hf[0], st);
+        upload(yf, hf[1], st);
+        upload(zf, hf[2], st);
+        upload(xd, hd[0], st);
+        upload(yd, hd[1], st);
+        upload(zd, hd[2], st);
+        upload(bbox, box, st);
+        ps.count = n;
+        ps.padded = np;
+        ps.x = x.as<int32_t>();
+        ps.y = y.as<int32_t>();
+        ps.z = z.as<int32_t>();
+        ps.xf = xf.as<float>();
+        ps.yf = yf.as<float>();
+        ps.zf = zf.as<float>();
+        ps.xd = xd.as<double>();
+        ps.yd = yd.as<double>();
+        ps.zd = zd.as<double>();
+        ps.bbox = bbox.as<int32_t>();
+        ps.nblk = nblk;
+        perm = order;
+        BAE_HIP_CHECK(hipStreamSynchronize(st));   // host vectors are released on return
+    }
+};
+
+}  // namespace bae
+
+using namespace bae;
+
+struct bae_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bae_grid grid{};
+    bae_options opt{};
+    double s = 0.0;
+    Geometry geo;
+    int64_t ngp = 0, ngm = 0, next = 0, nT = 0, nS = 0;
+
+    PointBuf T, S, Mp;         // targets gamma, sources gamma- u E, interior M+ (lazy)
+    DevMem t_pos;              // internal target index -> position in [gamma+; gamma-]
+    DevMem csr_rowptr, csr_col, csr_coef;
+    CSR B;
+    DevMem cl_tq, cl_tp, cl_t;
+    Closure cl;
+    std::shared_ptr<Table> table;
+    SumTables tabs;
+
+    int max_rhs = 16;
+    DevMem w, part;
+    int64_t part_cap = 0;
+    KrylovState K;
+    DevMem kV, kH, kcs, ksn, kg, khist, kbeta, kdone, kkdone;
+    int maxj = 0;
+    DevMem hA, hB, nrm, dotpart, ycoef;
+    DevMem b, x, r, tmp;       // [rhs][ngm]
+    DevMem up_gamma;           // [rhs][nT] external order
+    DevMem u_gamma;            // [rhs][nT]
+    DevMem wf;                 // [rhs][|M+|] h^2 f in Mp order
+    int nrhs = 0;
+    bool has_f = false, rhs_ready = false, solved = false;
+    std::vector<std::vector<double>> hist;  // per rhs
+    std::vector<double> ugrid;              // [rhs][n0 n1 n2] when computed
+    int32_t* pinned_flags = nullptr;        // host pinned, 2 * max_rhs
+};

@@ -121,6 +121,13 @@ def unit_cube(n_nodes):
     return (n, n, n), 1.0 / (n - 1), (0.0, 0.0, 0.0)
 
 
+def padded_cube(n_nodes, margin=0.1):
+    """Nodes spanning [-margin, 1 + margin]^3, so that radii up to 0.45 about the centre keep
+    at least two nodes between the interior and the grid edge even at 32 nodes per axis."""
+    n = int(n_nodes)
+    return (n, n, n), (1.0 + 2 * margin) / (n - 1), (-margin, -margin, -margin)
+
+
 def laplace_sphere(n_nodes=33, radius=0.4):
     """Laplace interior Dirichlet on a sphere centred in the unit cube (33^3 at h=1/32)."""
     n, h, o = unit_cube(n_nodes)
@@ -158,7 +165,7 @@ def batch_problem(i, base_seed=4000):
     rng = np.random.default_rng(base_seed + i)
     kind = ["sphere", "ellipsoid", "torus"][int(rng.integers(0, 3))]
     nn = int(rng.integers(32, 97))
-    n, h, o = unit_cube(nn)
+    n, h, o = padded_cube(nn)
     c = (0.5, 0.5, 0.5)
     if kind == "sphere":
         params = (float(rng.uniform(0.2, 0.45)),)
@@ -189,7 +196,7 @@ def serving_stream(count, rate, seed=5000):
 def serving_problem(i, n_nodes, seed=6000):
     rng = np.random.default_rng(seed + i)
     kind = ["sphere", "ellipsoid", "torus", "star"][int(rng.integers(0, 4))]
-    n, h, o = unit_cube(n_nodes)
+    n, h, o = padded_cube(n_nodes)
     c = (0.5, 0.5, 0.5)
     if kind == "sphere":
         params = (float(rng.uniform(0.2, 0.45)),)

@@ -224,6 +224,60 @@ int bae_batch_autotune(bae_batch* b, int32_t precision, int32_t* chosen);
 int bae_batch_solve(bae_batch* b, const bae_solve_params* params, int32_t use_graph, bae_result* results);
 int bae_batch_destroy(bae_batch* b);
 
+/* ------------------------------------------------------------------ serving (continuous batching) */
+typedef struct bae_server bae_server;
+/* Boundary data callback: g_out[i] = g(xyz[3i], xyz[3i+1], xyz[3i+2]) for i < count.  It is
+   called on the server's scheduler thread when a request is admitted. */
+typedef void (*bae_boundary_fn)(void* user, int64_t count, const double* xyz, double* g_out);
+
+typedef struct bae_server_options {
+    int32_t device;
+    int32_t max_slots;         /* requests on the device at once                       */
+    int64_t hbm_budget;        /* device bytes all admitted requests may hold together  */
+    int32_t precision;         /* BAE_SOLVE_FP64 or BAE_SOLVE_FP32_REFINED              */
+    double tol;                /* relative residual target (default 1e-10)             */
+    int32_t maxit;             /* GMRES iterations per (inner) solve                   */
+    int32_t max_krylov;        /* Krylov capacity per request (default 200)            */
+    int32_t iters_per_step;    /* GMRES iterations between scheduling points (default 4) */
+} bae_server_options;
+
+typedef struct bae_request {   /* one Dirichlet problem, f = 0 (sigma >= 0)             */
+    bae_grid grid;
+    bae_levelset levelset;     /* sampled level sets are copied at submit              */
+    bae_boundary_fn g;
+    void* user;                /* passed to g; must stay valid until the request is done */
+} bae_request;
+
+typedef struct bae_request_info {
+    int32_t state;             /* 0 waiting, 1 running, 2 done, 3 failed               */
+    int64_t n_gamma_minus, n_targets, bytes;
+    double t_submit, t_admit, t_done;   /* seconds since the server started             */
+} bae_request_info;
+
+typedef struct bae_server_stats {
+    int64_t submitted, admitted, completed, failed, steps, max_active, peak_bytes;
+    int64_t bytes_in_use, waiting, running;
+} bae_server_stats;
+
+/*
+ * Start a server: a scheduler thread that admits requests in arrival order when a slot
+ * is free and their device footprint (computed from the classified geometry, before any
+ * allocation) fits in hbm_budget, adds them to the running batch at the next step,
+ * advances all running requests together (one launch per GMRES phase), and retires
+ * finished ones, releasing their slot and memory.  A request larger than the whole
+ * budget fails with BAE_ERR_ADMISSION.
+ */
+int bae_server_create(const bae_server_options* opt, bae_server** out);
+int bae_server_submit(bae_server* s, const bae_request* req, uint64_t* ticket);
+/* Block until the request is done (timeout_s < 0: no limit).  Returns its status
+   (BAE_OK / BAE_NOT_CONVERGED) or the error that failed it. */
+int bae_server_wait(bae_server* s, uint64_t ticket, double timeout_s, bae_result* res, bae_request_info* info);
+/* Copy a done request's density (|gamma-|) and u_gamma (|gamma|) out and forget it. */
+int bae_server_fetch(bae_server* s, uint64_t ticket, double* q, int64_t q_cap, double* u_gamma, int64_t u_cap);
+int bae_server_stats_get(bae_server* s, bae_server_stats* out);
+/* Finish the running requests, fail the waiting ones, stop the thread. */
+int bae_server_destroy(bae_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -57,6 +57,35 @@ class Result(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+BoundaryFn = C.CFUNCTYPE(None, C.c_void_p, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double))
+
+
+class ServerOptions(C.Structure):
+    _fields_ = [("device", C.c_int32), ("max_slots", C.c_int32), ("hbm_budget", C.c_int64),
+                ("precision", C.c_int32), ("tol", C.c_double), ("maxit", C.c_int32), ("max_krylov", C.c_int32),
+                ("iters_per_step", C.c_int32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("grid", Grid), ("levelset", LevelSet), ("g", BoundaryFn), ("user", C.c_void_p)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("state", C.c_int32), ("n_gamma_minus", C.c_int64), ("n_targets", C.c_int64), ("bytes", C.c_int64),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in ("submitted", "admitted", "completed", "failed", "steps", "max_active",
+                                         "peak_bytes", "bytes_in_use", "waiting", "running")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class BaeError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"[{status}] {message}")
@@ -97,6 +126,12 @@ def load_library():
         "bae_batch_autotune": (C.c_int, [_P, C.c_int32, _P]),
         "bae_batch_solve": (C.c_int, [_P, C.POINTER(SolveParams), C.c_int32, _P]),
         "bae_batch_destroy": (C.c_int, [_P]),
+        "bae_server_create": (C.c_int, [C.POINTER(ServerOptions), C.POINTER(_P)]),
+        "bae_server_submit": (C.c_int, [_P, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+        "bae_server_wait": (C.c_int, [_P, C.c_uint64, C.c_double, _P, _P]),
+        "bae_server_fetch": (C.c_int, [_P, C.c_uint64, _P, C.c_int64, _P, C.c_int64]),
+        "bae_server_stats_get": (C.c_int, [_P, C.POINTER(ServerStats)]),
+        "bae_server_destroy": (C.c_int, [_P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -289,6 +324,89 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             load_library().bae_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def _grid_and_levelset(n, h, origin, sigma, kind, center, params, phi=None):
+    g = Grid((C.c_int32 * 3)(*[int(v) for v in n]), (C.c_double * 3)(*[float(v) for v in origin]), float(h),
+             float(sigma))
+    p = list(params) + [0.0] * (8 - len(params))
+    ls = LevelSet(KINDS[kind], (C.c_double * 3)(*[float(v) for v in center]),
+                  (C.c_double * 8)(*[float(v) for v in p[:8]]),
+                  phi.ctypes.data_as(C.POINTER(C.c_double)) if phi is not None else None)
+    return g, ls
+
+
+class Server:
+    """Continuous-batching solve server (bae_server_*).  Boundary data are Python callables
+    g(xyz: (N,3) array) -> (N,) array, called on the server thread at admission."""
+
+    def __init__(self, hbm_budget, max_slots=64, precision=SOLVE_FP64, tol=1e-10, maxit=0, max_krylov=200,
+                 iters_per_step=4, device=0):
+        lib = load_library()
+        o = ServerOptions(int(device), int(max_slots), int(hbm_budget), int(precision), float(tol), int(maxit),
+                          int(max_krylov), int(iters_per_step))
+        h = _P()
+        _check(lib.bae_server_create(C.byref(o), C.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, n, h, origin, sigma, kind, center, params, g, phi=None):
+        def cb(user, count, xyz, out, _g=g):
+            X = np.ctypeslib.as_array(xyz, shape=(count, 3))
+            np.ctypeslib.as_array(out, shape=(count,))[:] = _g(X)
+        fn = BoundaryFn(cb)
+        phi = None if phi is None else np.ascontiguousarray(phi, dtype=np.float64).reshape(-1)
+        grid, ls = _grid_and_levelset(n, h, origin, sigma, kind, center, params, phi)
+        req = Request(grid, ls, fn, None)
+        t = C.c_uint64(0)
+        _check(load_library().bae_server_submit(self._h, C.byref(req), C.byref(t)))
+        self._keep[t.value] = fn
+        return t.value
+
+    def submit_problem(self, p, g=None):
+        g = g if g is not None else (lambda X: p.g(X))
+        return self.submit(p.n, p.h, p.origin, p.sigma, p.kind, p.center, p.params, g)
+
+    def wait(self, ticket, timeout=-1.0):
+        r = Result()
+        info = RequestInfo()
+        rc = load_library().bae_server_wait(self._h, ticket, float(timeout), C.byref(r), C.byref(info))
+        _check(rc, allow_not_converged=True)
+        return r.as_dict(), info.as_dict()
+
+    def fetch(self, ticket, n_gamma_minus, n_targets):
+        q = np.empty(n_gamma_minus)
+        u = np.empty(n_targets)
+        _check(load_library().bae_server_fetch(self._h, ticket, _ptr(q), len(q), _ptr(u), len(u)))
+        self._keep.pop(ticket, None)
+        return q, u
+
+    def result(self, ticket, timeout=-1.0):
+        r, info = self.wait(ticket, timeout)
+        q, u = self.fetch(ticket, info["n_gamma_minus"], info["n_targets"])
+        return r, info, q, u
+
+    def stats(self):
+        st = ServerStats()
+        _check(load_library().bae_server_stats_get(self._h, C.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().bae_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -239,39 +239,10 @@ int guard(const std::function<void()>& fn) {
 
 }  // namespace bae
 
-// ================================================================== C ABI
-extern "C" {
+namespace bae {
 
-const char* bae_status_string(int s) {
-    switch (s) {
-        case BAE_OK: return "ok";
-        case BAE_NOT_CONVERGED: return "GMRES did not reach the tolerance";
-        case BAE_ERR_ARG: return "invalid argument";
-        case BAE_ERR_GEOMETRY: return "invalid geometry";
-        case BAE_ERR_NONFINITE: return "non-finite input";
-        case BAE_ERR_OOM: return "out of memory";
-        case BAE_ERR_HIP: return "HIP runtime error";
-        case BAE_ERR_STATE: return "call out of order";
-        case BAE_ERR_ADMISSION: return "request exceeds the memory budget";
-    }
-    return "unknown status";
-}
-
-const char* bae_last_error(void) { return g_last_error.c_str(); }
-
-int64_t bae_lgf_table_size(int32_t R) { return R < 0 ? 0 : table_size(R); }
-
-int bae_lgf_table(double s, int32_t R, double* out_dev, void* stream) {
-    return guard([&] {
-        if (!out_dev || R < 0 || R > 4096 || !(s >= 0.0) || !std::isfinite(s)) throw Error{BAE_ERR_ARG, "bae_lgf_table: bad argument"};
-        lgf_table_generate(s, R, out_dev, (hipStream_t)stream);
-    });
-}
-
-int bae_create(const bae_grid* grid, const bae_levelset* ls, const bae_options* opt, bae_ctx** out) {
-    return guard([&] {
-        if (!grid || !ls || !out) throw Error{BAE_ERR_ARG, "bae_create: null argument"};
-        *out = nullptr;
+bae_ctx* create_context(const bae_grid& gridv, const bae_options* opt, Geometry&& geo) {
+    const bae_grid* grid = &gridv;
         auto c = std::make_unique<bae_ctx>();
         c->grid = *grid;
         if (opt) c->opt = *opt;
@@ -291,7 +262,7 @@ int bae_create(const bae_grid* grid, const bae_levelset* ls, const bae_options* 
         BAE_HIP_CHECK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
         hipStream_t st = c->stream;
 
-        build_geometry(*grid, *ls, c->geo);
+        c->geo = std::move(geo);
         Geometry& G = c->geo;
         c->s = grid->sigma * grid->h * grid->h;
         c->ngp = (int64_t)G.gp.size() / 3;
@@ -396,8 +367,75 @@ int bae_create(const bae_grid* grid, const bae_levelset* ls, const bae_options* 
         c->up_gamma.alloc(sizeof(double) * c->nT * mr);
         c->u_gamma.alloc(sizeof(double) * c->nT * mr);
         BAE_HIP_CHECK(hipHostMalloc((void**)&c->pinned_flags, sizeof(int32_t) * 2 * mr, hipHostMallocDefault));
+        // batched / served solves: idle until started (done = 1, k = 0)
+        c->ctl.alloc(sizeof(Ctl));
+        const Ctl idle{0, 0, 0.0};
+        BAE_HIP_CHECK(hipMemcpyAsync(c->ctl.p, &idle, sizeof(Ctl), hipMemcpyHostToDevice, st));
+        launch_fill_int(K.done, mr, 1, st);
+        launch_fill_int(K.kdone, mr, 0, st);
         BAE_HIP_CHECK(hipStreamSynchronize(st));
-        *out = c.release();
+        return c.release();
+}
+
+
+// Device bytes create_context will allocate for this geometry (admission control).
+int64_t estimate_context_bytes(const Geometry& G, double s, const bae_options* opt) {
+    const int mr = opt && opt->max_rhs > 0 ? opt->max_rhs : 16;
+    const int m = opt && opt->max_krylov > 0 ? opt->max_krylov : 400;
+    const int64_t ngp = (int64_t)G.gp.size() / 3, ngm = (int64_t)G.gm.size() / 3, next = (int64_t)G.ext.size() / 3;
+    const int64_t nT = ngp + ngm, nS = ngm + next;
+    auto padded = [](int64_t n) { return ((n + kSourceBlock - 1) / kSourceBlock) * kSourceBlock; };
+    int64_t b = 0;
+    b += padded(nT) * (3 * 4 + 3 * 4 + 3 * 8) + padded(nS) * (3 * 4 + 3 * 4 + 3 * 8);   // point sets
+    b += (padded(nT) / kSourceBlock + padded(nS) / kSourceBlock) * 6 * 4;              // block boxes
+    b += nT * 4 + (nS + 1) * 4 + (ngm + (int64_t)G.edge_q.size()) * 12 + ngm * 16;    // maps, CSR, closure
+    b += padded(nS) * 8 * mr;                                                          // weights
+    b += (int64_t)lgf_sum_chunks(nT, nS) * nT * mr * 8;                                // partial sums
+    b += ((int64_t)(m + 1) * ngm + (int64_t)m * (m + 1) + 4 * m + 8) * 8 * mr;        // Krylov state
+    b += (int64_t)(m + 1) * mr * 8 * (3 + dot_blocks(ngm)) + (int64_t)m * mr * 8;      // CGS, dots, y
+    b += 4 * ngm * mr * 8 + 2 * nT * mr * 8;                                           // b, x, r, tmp, u_p, u_gamma
+    if (s > 0.0) b += table_size(std::max(32, G.max_offset)) * 12;                     // its own table
+    return b;
+}
+
+}  // namespace bae
+
+// ================================================================== C ABI
+extern "C" {
+
+const char* bae_status_string(int s) {
+    switch (s) {
+        case BAE_OK: return "ok";
+        case BAE_NOT_CONVERGED: return "GMRES did not reach the tolerance";
+        case BAE_ERR_ARG: return "invalid argument";
+        case BAE_ERR_GEOMETRY: return "invalid geometry";
+        case BAE_ERR_NONFINITE: return "non-finite input";
+        case BAE_ERR_OOM: return "out of memory";
+        case BAE_ERR_HIP: return "HIP runtime error";
+        case BAE_ERR_STATE: return "call out of order";
+        case BAE_ERR_ADMISSION: return "request exceeds the memory budget";
+    }
+    return "unknown status";
+}
+
+const char* bae_last_error(void) { return g_last_error.c_str(); }
+
+int64_t bae_lgf_table_size(int32_t R) { return R < 0 ? 0 : table_size(R); }
+
+int bae_lgf_table(double s, int32_t R, double* out_dev, void* stream) {
+    return guard([&] {
+        if (!out_dev || R < 0 || R > 4096 || !(s >= 0.0) || !std::isfinite(s)) throw Error{BAE_ERR_ARG, "bae_lgf_table: bad argument"};
+        lgf_table_generate(s, R, out_dev, (hipStream_t)stream);
+    });
+}
+
+int bae_create(const bae_grid* grid, const bae_levelset* ls, const bae_options* opt, bae_ctx** out) {
+    return guard([&] {
+        if (!grid || !ls || !out) throw Error{BAE_ERR_ARG, "bae_create: null argument"};
+        *out = nullptr;
+        Geometry geo;
+        build_geometry(*grid, *ls, geo);
+        *out = create_context(*grid, opt, std::move(geo));
     });
 }
 

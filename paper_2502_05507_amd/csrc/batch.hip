@@ -19,7 +19,7 @@
 #include <functional>
 #include <sstream>
 
-#include "context.hpp"
+#include "batch.hpp"
 #include "lgf_device.hpp"
 
 namespace bae {
@@ -46,6 +46,7 @@ struct BProb {
     double *b, *x, *r, *tmp, *ug, *upg;
     void* w;
     double* part;
+    Ctl* ctl;              // this problem's iteration counter, cap and tolerance (in its context)
 };
 
 struct Item {             // LGF-sum work item
@@ -73,16 +74,18 @@ __device__ inline int owner(const int64_t* off, int np, int64_t g) {
 // src: 0 -> V[k], 1 -> x
 template <typename Real>
 __global__ void b_weights(const BProb* __restrict__ P, const int64_t* __restrict__ off, int np, int64_t total,
-                          int src, const int* __restrict__ kdev, int use_done) {
+                          int src, int use_done, const int32_t* __restrict__ sel) {
     const int64_t gi = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (gi >= total) return;
     const int p = owner(off, np, gi);
+    if (sel && !sel[p]) return;
     const BProb& q = P[p];
     if (use_done && q.done[0]) return;
-    if (src == 0 && kdev[0] >= q.m) return;           // never index past the basis
+    const int k = q.ctl->k;
+    if (src == 0 && (k < 0 || k >= q.m)) return;      // never index outside the basis
     const int64_t s = gi - off[p];
     if (s >= q.ns_pad) return;
-    const double* v = src == 0 ? q.V + (int64_t)kdev[0] * q.n : q.x;
+    const double* v = src == 0 ? q.V + (int64_t)k * q.n : q.x;
     double acc = 0.0;
     if (s < q.s64.ns)
         for (int j = q.rowptr[s]; j < q.rowptr[s + 1]; ++j) acc = fma(q.coef[j], v[q.col[j]], acc);
@@ -91,13 +94,13 @@ __global__ void b_weights(const BProb* __restrict__ P, const int64_t* __restrict
 
 template <typename Real>
 __global__ __launch_bounds__(kT) void b_lgf_sum(const BProb* __restrict__ P, const Item* __restrict__ items,
-                                                int nitems, int use_done) {
+                                                int nitems, int use_done, const int32_t* __restrict__ sel) {
     __shared__ Real tab[kNearE];
     int cur = -1;
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const Item w = items[it];
         const BProb& q = P[w.p];
-        if (use_done && q.done[0]) continue;            // uniform over the block
+        if ((use_done && q.done[0]) || (sel && !sel[w.p])) continue;   // uniform over the block
         const SumArgs<Real>& a = sum_args<Real>(q);
         if (w.p != cur) {
             __syncthreads();
@@ -111,13 +114,15 @@ __global__ __launch_bounds__(kT) void b_lgf_sum(const BProb* __restrict__ P, con
 
 // dst: 0 -> V[k+1], 1 -> tmp
 __global__ void b_closure(const BProb* __restrict__ P, const int64_t* __restrict__ off, int np, int64_t total, int dst,
-                          const int* __restrict__ kdev, int use_done) {
+                          int use_done, const int32_t* __restrict__ sel) {
     const int64_t gi = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (gi >= total) return;
     const int p = owner(off, np, gi);
+    if (sel && !sel[p]) return;
     const BProb& q = P[p];
     if (use_done && q.done[0]) return;
-    if (dst == 0 && kdev[0] >= q.m) return;
+    const int k = q.ctl->k;
+    if (dst == 0 && (k < 0 || k >= q.m)) return;
     const int64_t i = gi - off[p];
     if (i >= q.n) return;
     const int64_t a = q.tq[i], b = q.tp[i];
@@ -127,15 +132,17 @@ __global__ void b_closure(const BProb* __restrict__ P, const int64_t* __restrict
         vb += q.part[(int64_t)c * q.nt + b];
     }
     const double t = q.tw[i];
-    double* out = dst == 0 ? q.V + (int64_t)(kdev[0] + 1) * q.n : q.tmp;
+    double* out = dst == 0 ? q.V + (int64_t)(k + 1) * q.n : q.tmp;
     out[i] = (1.0 - t) * va + t * vb;
 }
 
 // u_gamma = sum of the partials (scattered to [gamma+; gamma-] order) + u_p on gamma
-__global__ void b_gamma_values(const BProb* __restrict__ P, const int64_t* __restrict__ off, int np, int64_t total) {
+__global__ void b_gamma_values(const BProb* __restrict__ P, const int64_t* __restrict__ off, int np, int64_t total,
+                               const int32_t* __restrict__ sel) {
     const int64_t gi = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (gi >= total) return;
     const int p = owner(off, np, gi);
+    if (sel && !sel[p]) return;
     const BProb& q = P[p];
     const int64_t t = gi - off[p];
     if (t >= q.nt) return;
@@ -161,13 +168,13 @@ __device__ inline double block_sum(double v, double* sh) {
 // mode 0: dpart[j][slice] = V[j] . V[k+1], j <= k;  mode 1: dpart[0] = V[k+1] . V[k+1];
 // mode 2: dpart[0] = vec . vec with vec = b (sel 0) or r (sel 1)
 __global__ __launch_bounds__(kT) void b_dots(const BProb* __restrict__ P, const int2* __restrict__ slices, int nitems,
-                                             int mode, int sel, const int* __restrict__ kdev, int use_done) {
+                                             int mode, int sel, int use_done) {
     __shared__ double sh[kT / 64];
     const int2 w = slices[blockIdx.x];
     const BProb& q = P[w.x];
     if (use_done && q.done[0]) return;
-    const int k = kdev[0];
-    if (mode != 2 && k >= q.m) return;
+    const int k = q.ctl->k;
+    if (mode != 2 && (k < 0 || k >= q.m)) return;
     const int64_t lo = (int64_t)w.y * kSlice, hi = min((int64_t)q.n, lo + kSlice);
     if (mode == 0) {
         const double* y = q.V + (int64_t)(k + 1) * q.n;
@@ -188,13 +195,13 @@ __global__ __launch_bounds__(kT) void b_dots(const BProb* __restrict__ P, const 
 }
 
 // h[j] = sum over slices; dest 0 -> hA, 1 -> hB, 2 -> nrm (one value)
-__global__ void b_dots_finalize(const BProb* __restrict__ P, int np, int dest, int nj_mode,
-                                const int* __restrict__ kdev, int use_done) {
+__global__ void b_dots_finalize(const BProb* __restrict__ P, int np, int dest, int nj_mode, int use_done) {
     const int p = blockIdx.x;
     const BProb& q = P[p];
     if (use_done && q.done[0]) return;
-    if (nj_mode == 0 && kdev[0] >= q.m) return;
-    const int nj = nj_mode == 0 ? kdev[0] + 1 : 1;
+    const int k = q.ctl->k;
+    if (nj_mode == 0 && (k < 0 || k >= q.m)) return;
+    const int nj = nj_mode == 0 ? k + 1 : 1;
     double* h = dest == 0 ? q.hA : dest == 1 ? q.hB : q.nrm;
     for (int j = threadIdx.x; j < nj; j += blockDim.x) {
         double s = 0.0;
@@ -204,13 +211,13 @@ __global__ void b_dots_finalize(const BProb* __restrict__ P, int np, int dest, i
 }
 
 __global__ void b_subtract(const BProb* __restrict__ P, const int64_t* __restrict__ off, int np, int64_t total,
-                           int which, const int* __restrict__ kdev) {
+                           int which) {
     const int64_t gi = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (gi >= total) return;
     const int p = owner(off, np, gi);
     const BProb& q = P[p];
-    const int k = kdev[0];
-    if (q.done[0] || k >= q.m) return;
+    const int k = q.ctl->k;
+    if (q.done[0] || k < 0 || k >= q.m) return;
     const int64_t i = gi - off[p];
     if (i >= q.n) return;
     const double* h = which == 0 ? q.hA : q.hB;
@@ -219,27 +226,28 @@ __global__ void b_subtract(const BProb* __restrict__ P, const int64_t* __restric
     q.V[(int64_t)(k + 1) * q.n + i] -= acc;
 }
 
-__global__ void b_normalize(const BProb* __restrict__ P, const int64_t* __restrict__ off, int np, int64_t total,
-                            const int* __restrict__ kdev) {
+__global__ void b_normalize(const BProb* __restrict__ P, const int64_t* __restrict__ off, int np, int64_t total) {
     const int64_t gi = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (gi >= total) return;
     const int p = owner(off, np, gi);
     const BProb& q = P[p];
-    if (q.done[0] || kdev[0] >= q.m) return;
+    const int k = q.ctl->k;
+    if (q.done[0] || k < 0 || k >= q.m) return;
     const double nr = sqrt(q.nrm[0]);
     if (gi - off[p] >= q.n) return;
-    if (nr > 0.0) q.V[(int64_t)(kdev[0] + 1) * q.n + gi - off[p]] /= nr;
+    if (nr > 0.0) q.V[(int64_t)(k + 1) * q.n + gi - off[p]] /= nr;
 }
 
-// one thread per problem; tol from device memory; the iteration counter advances in
-// b_advance after every problem has used it
-__global__ void b_givens(const BProb* __restrict__ P, int np, const int* __restrict__ kdev,
-                         const double* __restrict__ tol) {
+// One thread per problem: Givens update of column k, residual estimate, convergence flag,
+// then the problem's own step counter advances (every other kernel of the iteration has
+// read it by now).
+__global__ void b_givens(const BProb* __restrict__ P, int np) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
     const BProb& q = P[p];
-    const int k = kdev[0];
-    if (q.done[0] || k >= q.m) {
+    const int k = q.ctl->k;
+    if (q.done[0]) return;
+    if (k < 0 || k >= q.m || k >= q.ctl->maxit) {
         q.done[0] = 1;
         return;
     }
@@ -267,7 +275,8 @@ __global__ void b_givens(const BProb* __restrict__ P, int np, const int* __restr
     const double est = fabs(q.g[k + 1]) / q.beta[0];
     q.hist[k] = est;
     q.kdone[0] = k + 1;
-    if (est <= tol[0] || hk1 == 0.0 || k + 1 >= q.m || k + 1 >= (int)tol[1]) q.done[0] = 1;
+    if (est <= q.ctl->tol || hk1 == 0.0 || k + 1 >= q.m || k + 1 >= q.ctl->maxit) q.done[0] = 1;
+    q.ctl->k = k + 1;
 }
 
 // gather per-problem scalars for one host copy: what 0 -> done, 1 -> kdone, 2 -> nrm
@@ -280,27 +289,15 @@ __global__ void b_gather(const BProb* __restrict__ P, int np, int what, int32_t*
     else dout[p] = P[p].nrm[0];
 }
 
-__global__ void b_advance(int* kdev) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) kdev[0] += 1;
-}
 
-__global__ void b_set_int(int* p, int v) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
-}
-
-__global__ void b_set_double2(double* p, double v0, double v1) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        p[0] = v0;
-        p[1] = v1;
-    }
-}
-
-// sel 0: r0 = b, sel 1: r0 = r.  skip[p] marks problems left alone (refinement).
+// Start GMRES for the problems with mask[p] = 1 (r0 = b for sel 0, r for sel 1, x0 = 0), with
+// the tolerance and iteration cap in ctl_init[p]; other problems are left untouched.
 __global__ void b_init(const BProb* __restrict__ P, const int64_t* __restrict__ off, int np, int64_t total, int sel,
-                       const int32_t* __restrict__ skip) {
+                       const int32_t* __restrict__ mask, const Ctl* __restrict__ ctl_init) {
     const int64_t gi = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (gi >= total) return;
     const int p = owner(off, np, gi);
+    if (!mask[p]) return;
     const BProb& q = P[p];
     const int64_t i = gi - off[p];
     if (i >= q.n) return;
@@ -309,16 +306,19 @@ __global__ void b_init(const BProb* __restrict__ P, const int64_t* __restrict__ 
     if (i == 0) {
         q.beta[0] = bnorm;
         q.g[0] = bnorm;
-        q.done[0] = (bnorm == 0.0 || (skip && skip[p])) ? 1 : 0;
+        q.done[0] = bnorm == 0.0 ? 1 : 0;
         q.kdone[0] = 0;
+        q.ctl->k = 0;
+        q.ctl->maxit = ctl_init[p].maxit;
+        q.ctl->tol = ctl_init[p].tol;
     }
     q.V[i] = bnorm > 0.0 ? r0[i] / bnorm : 0.0;
 }
 
-// thread per problem: y = R^-1 g over the first kdone[p] columns
-__global__ void b_backsolve(const BProb* __restrict__ P, int np) {
+// thread per problem (mask[p] = 1): y = R^-1 g over the first kdone[p] columns
+__global__ void b_backsolve(const BProb* __restrict__ P, int np, const int32_t* __restrict__ mask) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
+    if (p >= np || !mask[p]) return;
     const BProb& q = P[p];
     const int kk = q.kdone[0];
     for (int i = kk - 1; i >= 0; --i) {
@@ -331,10 +331,11 @@ __global__ void b_backsolve(const BProb* __restrict__ P, int np) {
 
 // x (+)= V y ; then (optionally) nothing else
 __global__ void b_update_x(const BProb* __restrict__ P, const int64_t* __restrict__ off, int np, int64_t total,
-                           int accumulate) {
+                           int accumulate, const int32_t* __restrict__ mask) {
     const int64_t gi = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (gi >= total) return;
     const int p = owner(off, np, gi);
+    if (!mask[p]) return;
     const BProb& q = P[p];
     const int64_t i = gi - off[p];
     if (i >= q.n) return;
@@ -344,11 +345,13 @@ __global__ void b_update_x(const BProb* __restrict__ P, const int64_t* __restric
     q.x[i] = accumulate ? q.x[i] + acc : acc;
 }
 
-// r = b - tmp ; x = 0 (mode 1) ; r = b (mode 2)
-__global__ void b_vec(const BProb* __restrict__ P, const int64_t* __restrict__ off, int np, int64_t total, int mode) {
+// r = b - tmp (mode 0) ; x = 0 (mode 1) ; r = b (mode 2); masked when mask != null
+__global__ void b_vec(const BProb* __restrict__ P, const int64_t* __restrict__ off, int np, int64_t total, int mode,
+                      const int32_t* __restrict__ mask) {
     const int64_t gi = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (gi >= total) return;
     const int p = owner(off, np, gi);
+    if (mask && !mask[p]) return;
     const BProb& q = P[p];
     const int64_t i = gi - off[p];
     if (i >= q.n) return;
@@ -360,45 +363,57 @@ __global__ void b_vec(const BProb* __restrict__ P, const int64_t* __restrict__ o
 inline unsigned nblocks(int64_t n) { return (unsigned)std::max<int64_t>(1, (n + kT - 1) / kT); }
 
 }  // namespace
-}  // namespace bae
 
-using namespace bae;
-
-struct bae_batch {
+// ================================================================== host engine
+struct BatchEngine {
     int device = 0;
     hipStream_t stream = nullptr;
+    bool own_stream = false;
     std::vector<bae_ctx*> ctx;
     int np = 0;
-    DevMem probs, off_src, off_row, off_tgt, slices, items, kdev, tol, skip, arena;
+    DevMem probs, off_src, off_row, off_tgt, slices, items, ctl_init, mask, arena, gi, gd;
     int64_t tot_src = 0, tot_row = 0, tot_tgt = 0;
     int nslices_total = 0, nitems = 0;
     int blk_per_chunk = 8, grid_mult = 4, n_cu = 256;
     std::vector<BProb> hp;
-    DevMem gi, gd;             // gathered per-problem ints / doubles
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     int graph_iters = 8;
     int32_t* pinned = nullptr;
+    int pinned_cap = 0;
+
+    ~BatchEngine() {
+        release_graphs();
+        if (pinned) (void)hipHostFree(pinned);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+    void release_graphs() {
+        for (int i = 0; i < 2; ++i) {
+            if (exec[i]) (void)hipGraphExecDestroy(exec[i]);
+            if (graph[i]) (void)hipGraphDestroy(graph[i]);
+            exec[i] = nullptr;
+            graph[i] = nullptr;
+        }
+    }
 };
 
-namespace bae {
 namespace {
 
-void release_graphs(bae_batch* b) {
-    for (int i = 0; i < 2; ++i) {
-        if (b->exec[i]) (void)hipGraphExecDestroy(b->exec[i]);
-        if (b->graph[i]) (void)hipGraphDestroy(b->graph[i]);
-        b->exec[i] = nullptr;
-        b->graph[i] = nullptr;
-    }
-}
-
-// (Re)build per-problem chunking, the partial-sum arena and the work lists.
-void build_layout(bae_batch* b) {
-    release_graphs(b);
+// (Re)build descriptors, per-problem chunking, the arenas and the work lists for the
+// current member list.
+void build_layout(BatchEngine* b) {
+    b->release_graphs();
     hipStream_t st = b->stream;
     BAE_HIP_CHECK(hipStreamSynchronize(st));   // nothing in flight uses the old layout
+    b->np = (int)b->ctx.size();
     b->tot_src = b->tot_row = b->tot_tgt = 0;
+    b->hp.assign(b->np, BProb{});
+    if (b->np == 0) return;
+    if (b->pinned_cap < b->np + 1) {
+        if (b->pinned) BAE_HIP_CHECK(hipHostFree(b->pinned));
+        b->pinned_cap = std::max(64, 2 * (b->np + 1));
+        BAE_HIP_CHECK(hipHostMalloc((void**)&b->pinned, sizeof(int32_t) * b->pinned_cap, hipHostMallocDefault));
+    }
     std::vector<int64_t> osrc(b->np), orow(b->np), otgt(b->np);
     std::vector<int2> sl;
     std::vector<Item> it;
@@ -429,43 +444,73 @@ void build_layout(bae_batch* b) {
         return b->ctx[x.p]->nT * b->ctx[x.p]->nS > b->ctx[y.p]->nT * b->ctx[y.p]->nS;
     });
     b->arena.alloc(sizeof(double) * arena);
+    b->ctl_init.alloc(sizeof(Ctl) * b->np);
+    b->mask.alloc(sizeof(int32_t) * b->np);
+    b->gi.alloc(sizeof(int32_t) * b->np);
+    b->gd.alloc(sizeof(double) * b->np);
     for (int p = 0; p < b->np; ++p) {
         bae_ctx* c = b->ctx[p];
         BProb& q = b->hp[p];
         q.part = b->arena.as<double>() + part_at[p];
         q.dpart = b->arena.as<double>() + dpart_at[p];
-        for (int prec = 0; prec < 2; ++prec) {
-            auto fill = [&](auto& a, const auto* near, const auto* full, const auto* sxr, const auto* syr,
-                            const auto* szr) {
-                a.tx = c->T.ps.x;
-                a.ty = c->T.ps.y;
-                a.tz = c->T.ps.z;
-                a.nt = (int)c->nT;
-                a.sx = c->S.ps.x;
-                a.sy = c->S.ps.y;
-                a.sz = c->S.ps.z;
-                a.sxr = sxr;
-                a.syr = syr;
-                a.szr = szr;
-                a.sbox = c->S.ps.bbox;
-                a.ns = (int)c->nS;
-                a.nblk = (int)c->S.ps.nblk;
-                a.blk_per_chunk = b->blk_per_chunk;
-                a.ldw = c->S.ps.padded;
-                a.near_tab = near;
-                a.full_tab = full;
-                a.far_ok = c->tabs.far_field ? 1 : 0;
-                a.part = q.part;
-                a.ldp = (int64_t)q.chunks * c->nT;
-            };
-            if (prec == 0) {
-                fill(q.s64, c->tabs.near64, c->tabs.full64, c->S.ps.xd, c->S.ps.yd, c->S.ps.zd);
-                q.s64.w = (const double*)c->w.p;
-            } else {
-                fill(q.s32, c->tabs.near32, c->tabs.full32, c->S.ps.xf, c->S.ps.yf, c->S.ps.zf);
-                q.s32.w = (const float*)c->w.p;
-            }
-        }
+        q.ctl = c->ctl.as<Ctl>();
+        q.rowptr = c->B.rowptr;
+        q.col = c->B.col;
+        q.coef = c->B.coef;
+        q.tq = c->cl.tq;
+        q.tp = c->cl.tp;
+        q.tw = c->cl.t;
+        q.tpos = c->t_pos.as<int32_t>();
+        q.n = (int)c->ngm;
+        q.nt = (int)c->nT;
+        q.ns_pad = (int)c->S.ps.padded;
+        q.m = c->K.m;
+        q.V = c->K.V;
+        q.H = c->K.H;
+        q.cs = c->K.cs;
+        q.sn = c->K.sn;
+        q.g = c->K.g;
+        q.hist = c->K.hist;
+        q.beta = c->K.beta;
+        q.done = c->K.done;
+        q.kdone = c->K.kdone;
+        q.hA = c->hA.as<double>();
+        q.hB = c->hB.as<double>();
+        q.nrm = c->nrm.as<double>();
+        q.y = c->ycoef.as<double>();
+        q.b = c->b.as<double>();
+        q.x = c->x.as<double>();
+        q.r = c->r.as<double>();
+        q.tmp = c->tmp.as<double>();
+        q.ug = c->u_gamma.as<double>();
+        q.upg = c->up_gamma.as<double>();
+        q.w = c->w.p;
+        auto fill = [&](auto& a, const auto* near, const auto* full, const auto* sxr, const auto* syr, const auto* szr) {
+            a.tx = c->T.ps.x;
+            a.ty = c->T.ps.y;
+            a.tz = c->T.ps.z;
+            a.nt = (int)c->nT;
+            a.sx = c->S.ps.x;
+            a.sy = c->S.ps.y;
+            a.sz = c->S.ps.z;
+            a.sxr = sxr;
+            a.syr = syr;
+            a.szr = szr;
+            a.sbox = c->S.ps.bbox;
+            a.ns = (int)c->nS;
+            a.nblk = (int)c->S.ps.nblk;
+            a.blk_per_chunk = b->blk_per_chunk;
+            a.ldw = c->S.ps.padded;
+            a.near_tab = near;
+            a.full_tab = full;
+            a.far_ok = c->tabs.far_field ? 1 : 0;
+            a.part = q.part;
+            a.ldp = (int64_t)q.chunks * c->nT;
+        };
+        fill(q.s64, c->tabs.near64, c->tabs.full64, c->S.ps.xd, c->S.ps.yd, c->S.ps.zd);
+        q.s64.w = (const double*)c->w.p;
+        fill(q.s32, c->tabs.near32, c->tabs.full32, c->S.ps.xf, c->S.ps.yf, c->S.ps.zf);
+        q.s32.w = (const float*)c->w.p;
     }
     b->nslices_total = (int)sl.size();
     b->nitems = (int)it.size();
@@ -478,107 +523,212 @@ void build_layout(bae_batch* b) {
     BAE_HIP_CHECK(hipStreamSynchronize(st));
 }
 
-// one operator application for all problems: out = A q (closure) at precision prec
-void apply_all(bae_batch* b, int prec, int src, int dst, int use_done) {
+// one operator application for all (or all unfinished) problems, src 0: V[k], 1: x;
+// dst 0: V[k+1], 1: tmp, -1: partial sums only
+void apply_all(BatchEngine* b, int prec, int src, int dst, int use_done, const int32_t* sel = nullptr) {
     hipStream_t st = b->stream;
     const BProb* P = b->probs.as<BProb>();
-    const int* k = b->kdev.as<int>();
-    const unsigned grid = (unsigned)std::min(b->nitems, b->grid_mult * b->n_cu);
+    const unsigned grid = (unsigned)std::max(1, std::min(b->nitems, b->grid_mult * b->n_cu));
     if (prec == BAE_PREC_FP64) {
-        b_weights<double><<<nblocks(b->tot_src), kT, 0, st>>>(P, b->off_src.as<int64_t>(), b->np, b->tot_src, src, k,
-                                                              use_done);
-        b_lgf_sum<double><<<grid, kT, 0, st>>>(P, b->items.as<Item>(), b->nitems, use_done);
+        b_weights<double><<<nblocks(b->tot_src), kT, 0, st>>>(P, b->off_src.as<int64_t>(), b->np, b->tot_src, src,
+                                                              use_done, sel);
+        b_lgf_sum<double><<<grid, kT, 0, st>>>(P, b->items.as<Item>(), b->nitems, use_done, sel);
     } else {
-        b_weights<float><<<nblocks(b->tot_src), kT, 0, st>>>(P, b->off_src.as<int64_t>(), b->np, b->tot_src, src, k,
-                                                             use_done);
-        b_lgf_sum<float><<<grid, kT, 0, st>>>(P, b->items.as<Item>(), b->nitems, use_done);
+        b_weights<float><<<nblocks(b->tot_src), kT, 0, st>>>(P, b->off_src.as<int64_t>(), b->np, b->tot_src, src,
+                                                             use_done, sel);
+        b_lgf_sum<float><<<grid, kT, 0, st>>>(P, b->items.as<Item>(), b->nitems, use_done, sel);
     }
     if (dst >= 0)
-        b_closure<<<nblocks(b->tot_row), kT, 0, st>>>(P, b->off_row.as<int64_t>(), b->np, b->tot_row, dst, k, use_done);
+        b_closure<<<nblocks(b->tot_row), kT, 0, st>>>(P, b->off_row.as<int64_t>(), b->np, b->tot_row, dst, use_done,
+                                                      sel);
     BAE_HIP_CHECK(hipGetLastError());
 }
 
-void norms(bae_batch* b, int sel) {
+// nrm[p] = ||b|| (sel 0) or ||r|| (sel 1) squared, for every problem
+void norms(BatchEngine* b, int sel) {
     hipStream_t st = b->stream;
     const BProb* P = b->probs.as<BProb>();
-    b_dots<<<b->nslices_total, kT, 0, st>>>(P, b->slices.as<int2>(), b->nslices_total, 2, sel, b->kdev.as<int>(), 0);
-    b_dots_finalize<<<b->np, 64, 0, st>>>(P, b->np, 2, 1, b->kdev.as<int>(), 0);
+    b_dots<<<b->nslices_total, kT, 0, st>>>(P, b->slices.as<int2>(), b->nslices_total, 2, sel, 0);
+    b_dots_finalize<<<b->np, 64, 0, st>>>(P, b->np, 2, 1, 0);
     BAE_HIP_CHECK(hipGetLastError());
 }
 
-void gmres_iteration(bae_batch* b, int prec) {
+std::vector<double> gather_nrm(BatchEngine* b) {
+    hipStream_t st = b->stream;
+    std::vector<double> out(b->np);
+    b_gather<<<(b->np + 63) / 64, 64, 0, st>>>(b->probs.as<BProb>(), b->np, 2, nullptr, b->gd.as<double>());
+    BAE_HIP_CHECK(hipMemcpyAsync(out.data(), b->gd.p, sizeof(double) * b->np, hipMemcpyDeviceToHost, st));
+    BAE_HIP_CHECK(hipStreamSynchronize(st));
+    return out;
+}
+
+std::vector<int32_t> gather_int(BatchEngine* b, int what) {
+    hipStream_t st = b->stream;
+    b_gather<<<(b->np + 63) / 64, 64, 0, st>>>(b->probs.as<BProb>(), b->np, what, b->gi.as<int32_t>(), nullptr);
+    BAE_HIP_CHECK(hipMemcpyAsync(b->pinned, b->gi.p, sizeof(int32_t) * b->np, hipMemcpyDeviceToHost, st));
+    BAE_HIP_CHECK(hipStreamSynchronize(st));
+    return std::vector<int32_t>(b->pinned, b->pinned + b->np);
+}
+
+void upload_mask(BatchEngine* b, const std::vector<int32_t>& mask) {
+    BAE_HIP_CHECK(hipMemcpyAsync(b->mask.p, mask.data(), sizeof(int32_t) * b->np, hipMemcpyHostToDevice, b->stream));
+    BAE_HIP_CHECK(hipStreamSynchronize(b->stream));
+}
+
+void gmres_iteration(BatchEngine* b, int prec) {
     hipStream_t st = b->stream;
     const BProb* P = b->probs.as<BProb>();
-    const int* k = b->kdev.as<int>();
     apply_all(b, prec, 0, 0, 1);
     const int64_t* orow = b->off_row.as<int64_t>();
     for (int pass = 0; pass < 2; ++pass) {
-        b_dots<<<b->nslices_total, kT, 0, st>>>(P, b->slices.as<int2>(), b->nslices_total, 0, 0, k, 1);
-        b_dots_finalize<<<b->np, 64, 0, st>>>(P, b->np, pass, 0, k, 1);
-        b_subtract<<<nblocks(b->tot_row), kT, 0, st>>>(P, orow, b->np, b->tot_row, pass, k);
+        b_dots<<<b->nslices_total, kT, 0, st>>>(P, b->slices.as<int2>(), b->nslices_total, 0, 0, 1);
+        b_dots_finalize<<<b->np, 64, 0, st>>>(P, b->np, pass, 0, 1);
+        b_subtract<<<nblocks(b->tot_row), kT, 0, st>>>(P, orow, b->np, b->tot_row, pass);
     }
-    b_dots<<<b->nslices_total, kT, 0, st>>>(P, b->slices.as<int2>(), b->nslices_total, 1, 0, k, 1);
-    b_dots_finalize<<<b->np, 64, 0, st>>>(P, b->np, 2, 1, k, 1);
-    b_normalize<<<nblocks(b->tot_row), kT, 0, st>>>(P, orow, b->np, b->tot_row, k);
-    b_givens<<<(b->np + 63) / 64, 64, 0, st>>>(P, b->np, k, b->tol.as<double>());
-    b_advance<<<1, 64, 0, st>>>(b->kdev.as<int>());
+    b_dots<<<b->nslices_total, kT, 0, st>>>(P, b->slices.as<int2>(), b->nslices_total, 1, 0, 1);
+    b_dots_finalize<<<b->np, 64, 0, st>>>(P, b->np, 2, 1, 1);
+    b_normalize<<<nblocks(b->tot_row), kT, 0, st>>>(P, orow, b->np, b->tot_row);
+    b_givens<<<(b->np + 63) / 64, 64, 0, st>>>(P, b->np);
     BAE_HIP_CHECK(hipGetLastError());
 }
 
-// Lock-step GMRES on all problems (x0 = 0), then x (+)= V y.  Returns iterations run.
-int gmres_all(bae_batch* b, int prec, int sel, double tol, int maxit, const std::vector<int32_t>& skip,
-              bool accumulate, bool use_graph) {
+}  // namespace
+
+// ---------------------------------------------------------------- engine API (batch + server)
+void batch_set_members(BatchEngine* b, const std::vector<bae_ctx*>& members) {
+    b->ctx = members;
+    build_layout(b);
+}
+
+// Start GMRES (x0 = 0 relative to the current x when accumulating later) on the masked
+// problems: r0 = b (sel 0) or r (sel 1).
+void batch_begin(BatchEngine* b, const std::vector<int32_t>& mask, int sel, const std::vector<double>& tol,
+                 const std::vector<int>& maxit) {
+    if (b->np == 0) return;
+    std::vector<Ctl> init(b->np);
+    for (int p = 0; p < b->np; ++p) init[p] = Ctl{0, maxit[p], tol[p]};
     hipStream_t st = b->stream;
-    const BProb* P = b->probs.as<BProb>();
-    b_set_int<<<1, 64, 0, st>>>(b->kdev.as<int>(), 0);
-    b_set_double2<<<1, 64, 0, st>>>(b->tol.as<double>(), tol, (double)maxit);
-    BAE_HIP_CHECK(hipMemcpyAsync(b->skip.p, skip.data(), sizeof(int32_t) * b->np, hipMemcpyHostToDevice, st));
+    BAE_HIP_CHECK(hipMemcpyAsync(b->ctl_init.p, init.data(), sizeof(Ctl) * b->np, hipMemcpyHostToDevice, st));
+    BAE_HIP_CHECK(hipMemcpyAsync(b->mask.p, mask.data(), sizeof(int32_t) * b->np, hipMemcpyHostToDevice, st));
     norms(b, sel);
-    b_init<<<nblocks(b->tot_row), kT, 0, st>>>(P, b->off_row.as<int64_t>(), b->np, b->tot_row, sel,
-                                               b->skip.as<int32_t>());
+    b_init<<<nblocks(b->tot_row), kT, 0, st>>>(b->probs.as<BProb>(), b->off_row.as<int64_t>(), b->np, b->tot_row, sel,
+                                               b->mask.as<int32_t>(), b->ctl_init.as<Ctl>());
     BAE_HIP_CHECK(hipGetLastError());
-    const int gi = prec == BAE_PREC_FP64 ? 0 : 1;
-    if (use_graph && !b->exec[gi]) {
-        BAE_HIP_CHECK(hipStreamSynchronize(st));
-        BAE_HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        for (int i = 0; i < b->graph_iters; ++i) gmres_iteration(b, prec);
-        BAE_HIP_CHECK(hipStreamEndCapture(st, &b->graph[gi]));
-        BAE_HIP_CHECK(hipGraphInstantiate(&b->exec[gi], b->graph[gi], nullptr, nullptr, 0));
-    }
-    int k = 0;
-    const int step = use_graph ? b->graph_iters : 4;
-    while (k < maxit) {
-        if (use_graph) BAE_HIP_CHECK(hipGraphLaunch(b->exec[gi], st));
-        else
-            for (int i = 0; i < step; ++i) gmres_iteration(b, prec);
-        k += step;
-        b_gather<<<(b->np + 63) / 64, 64, 0, st>>>(P, b->np, 0, b->gi.as<int32_t>(), nullptr);
-        BAE_HIP_CHECK(hipMemcpyAsync(b->pinned, b->gi.p, sizeof(int32_t) * b->np, hipMemcpyDeviceToHost, st));
-        BAE_HIP_CHECK(hipStreamSynchronize(st));
-        bool all = true;
-        for (int p = 0; p < b->np; ++p) all &= b->pinned[p] != 0;
-        if (all) break;
-    }
-    b_backsolve<<<(b->np + 63) / 64, 64, 0, st>>>(P, b->np);
-    b_update_x<<<nblocks(b->tot_row), kT, 0, st>>>(P, b->off_row.as<int64_t>(), b->np, b->tot_row, accumulate ? 1 : 0);
-    BAE_HIP_CHECK(hipGetLastError());
-    BAE_HIP_CHECK(hipStreamSynchronize(st));
-    return std::min(k, maxit);
+    BAE_HIP_CHECK(hipStreamSynchronize(st));   // init / mask host vectors released on return
 }
 
-std::vector<double> residuals(bae_batch* b, const std::vector<double>& bn) {
+// `iters` GMRES iterations of every unfinished problem (graph replay when use_graph)
+void batch_iterate(BatchEngine* b, int prec, int iters, bool use_graph) {
+    if (b->np == 0) return;
     hipStream_t st = b->stream;
-    const BProb* P = b->probs.as<BProb>();
-    apply_all(b, BAE_PREC_FP64, 1, 1, 0);
-    b_vec<<<nblocks(b->tot_row), kT, 0, st>>>(P, b->off_row.as<int64_t>(), b->np, b->tot_row, 0);
-    norms(b, 1);
-    std::vector<double> out(b->np);
-    b_gather<<<(b->np + 63) / 64, 64, 0, st>>>(P, b->np, 2, nullptr, b->gd.as<double>());
-    BAE_HIP_CHECK(hipMemcpyAsync(out.data(), b->gd.p, sizeof(double) * b->np, hipMemcpyDeviceToHost, st));
-    BAE_HIP_CHECK(hipStreamSynchronize(st));
-    for (int p = 0; p < b->np; ++p) out[p] = bn[p] > 0 ? std::sqrt(out[p]) / bn[p] : 0.0;
-    return out;
+    const int gi = prec == BAE_PREC_FP64 ? 0 : 1;
+    if (use_graph) {
+        if (!b->exec[gi]) {
+            BAE_HIP_CHECK(hipStreamSynchronize(st));
+            BAE_HIP_CHECK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            for (int i = 0; i < b->graph_iters; ++i) gmres_iteration(b, prec);
+            BAE_HIP_CHECK(hipStreamEndCapture(st, &b->graph[gi]));
+            BAE_HIP_CHECK(hipGraphInstantiate(&b->exec[gi], b->graph[gi], nullptr, nullptr, 0));
+        }
+        for (int i = 0; i < iters; i += b->graph_iters) BAE_HIP_CHECK(hipGraphLaunch(b->exec[gi], st));
+    } else {
+        for (int i = 0; i < iters; ++i) gmres_iteration(b, prec);
+    }
 }
+
+std::vector<int32_t> batch_done(BatchEngine* b) { return b->np ? gather_int(b, 0) : std::vector<int32_t>{}; }
+std::vector<int32_t> batch_kdone(BatchEngine* b) { return b->np ? gather_int(b, 1) : std::vector<int32_t>{}; }
+
+// x (+)= V y for the masked problems
+void batch_finish(BatchEngine* b, const std::vector<int32_t>& mask, bool accumulate) {
+    if (b->np == 0) return;
+    hipStream_t st = b->stream;
+    BAE_HIP_CHECK(hipMemcpyAsync(b->mask.p, mask.data(), sizeof(int32_t) * b->np, hipMemcpyHostToDevice, st));
+    b_backsolve<<<(b->np + 63) / 64, 64, 0, st>>>(b->probs.as<BProb>(), b->np, b->mask.as<int32_t>());
+    b_update_x<<<nblocks(b->tot_row), kT, 0, st>>>(b->probs.as<BProb>(), b->off_row.as<int64_t>(), b->np, b->tot_row,
+                                                   accumulate ? 1 : 0, b->mask.as<int32_t>());
+    BAE_HIP_CHECK(hipGetLastError());
+    BAE_HIP_CHECK(hipStreamSynchronize(st));
+}
+
+// x = 0 (mode 1) or r = b (mode 2) on the masked problems
+void batch_vec(BatchEngine* b, int mode, const std::vector<int32_t>& mask) {
+    if (b->np == 0) return;
+    upload_mask(b, mask);
+    b_vec<<<nblocks(b->tot_row), kT, 0, b->stream>>>(b->probs.as<BProb>(), b->off_row.as<int64_t>(), b->np,
+                                                     b->tot_row, mode, b->mask.as<int32_t>());
+    BAE_HIP_CHECK(hipGetLastError());
+}
+
+std::vector<double> batch_bnorms(BatchEngine* b) {
+    if (b->np == 0) return {};
+    norms(b, 0);
+    std::vector<double> v = gather_nrm(b);
+    for (auto& x : v) x = std::sqrt(x);
+    return v;
+}
+
+// r = b - A64 x for every problem (or the masked ones); returns ||r|| per problem
+std::vector<double> batch_residual_norms(BatchEngine* b, const std::vector<int32_t>* mask) {
+    if (b->np == 0) return {};
+    const int32_t* sel = nullptr;
+    if (mask) {
+        upload_mask(b, *mask);
+        sel = b->mask.as<int32_t>();
+    }
+    apply_all(b, BAE_PREC_FP64, 1, 1, 0, sel);
+    b_vec<<<nblocks(b->tot_row), kT, 0, b->stream>>>(b->probs.as<BProb>(), b->off_row.as<int64_t>(), b->np,
+                                                     b->tot_row, 0, sel);
+    norms(b, 1);
+    std::vector<double> v = gather_nrm(b);
+    for (auto& x : v) x = std::sqrt(x);
+    return v;
+}
+
+// u_gamma = D x + u_p on gamma for every problem (or the masked ones)
+void batch_gamma_values(BatchEngine* b, const std::vector<int32_t>* mask) {
+    if (b->np == 0) return;
+    const int32_t* sel = nullptr;
+    if (mask) {
+        upload_mask(b, *mask);
+        sel = b->mask.as<int32_t>();
+    }
+    apply_all(b, BAE_PREC_FP64, 1, -1, 0, sel);
+    b_gamma_values<<<nblocks(b->tot_tgt), kT, 0, b->stream>>>(b->probs.as<BProb>(), b->off_tgt.as<int64_t>(), b->np,
+                                                             b->tot_tgt, sel);
+    BAE_HIP_CHECK(hipGetLastError());
+    BAE_HIP_CHECK(hipStreamSynchronize(b->stream));
+}
+
+std::vector<double> batch_history(BatchEngine* b, int p, int count) {
+    std::vector<double> h(count);
+    if (count > 0)
+        BAE_HIP_CHECK(hipMemcpy(h.data(), b->hp[p].hist, sizeof(double) * count, hipMemcpyDeviceToHost));
+    return h;
+}
+
+BatchEngine* batch_engine_new(int device, hipStream_t stream) {
+    auto* b = new BatchEngine();
+    b->device = device;
+    hipDeviceProp_t prop;
+    BAE_HIP_CHECK(hipGetDeviceProperties(&prop, device));
+    b->n_cu = prop.multiProcessorCount;
+    if (stream) {
+        b->stream = stream;
+    } else {
+        BAE_HIP_CHECK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+        b->own_stream = true;
+    }
+    return b;
+}
+
+void batch_engine_delete(BatchEngine* b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    delete b;
+}
+
+namespace {
 
 std::string tune_cache_path() {
     if (const char* e = std::getenv("BAE_AUTOTUNE_CACHE")) return e;
@@ -586,8 +736,111 @@ std::string tune_cache_path() {
     return "";
 }
 
+std::string tune_key(BatchEngine* b) {
+    hipDeviceProp_t prop;
+    BAE_HIP_CHECK(hipGetDeviceProperties(&prop, b->device));
+    double pairs = 0;
+    for (auto* c : b->ctx) pairs += (double)c->nT * c->nS;
+    std::ostringstream k;
+    k << prop.gcnArchName << " " << (int)std::lround(std::log2(std::max(pairs, 1.0))) << " "
+      << (int)std::lround(std::log2((double)std::max(b->np, 1)));
+    return k.str();
+}
+
+// Lock-step solve of every member problem (the batched form of bae_solve).
+int solve_all(BatchEngine* b, const bae_solve_params* prm, bool use_graph, bae_result* res) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int np = b->np;
+    int mmin = 1 << 30;
+    for (auto* c : b->ctx) mmin = std::min(mmin, c->K.m);
+    const int maxit = prm->maxit > 0 ? std::min(prm->maxit, mmin) : mmin;
+    const std::vector<int32_t> all(np, 1);
+    std::vector<double> bn = batch_bnorms(b);
+    batch_vec(b, 1, all);   // x = 0
+    std::vector<int> iters(np, 0), outer(np, 0);
+    std::vector<double> relres(np, 1.0);
+    int64_t mv64 = 0, mv32 = 0;
+    for (auto* c : b->ctx) c->hist.assign(1, {});
+    auto run = [&](int prec, int sel, const std::vector<int32_t>& mask, const std::vector<double>& tol, bool acc) {
+        std::vector<int> mx(np, maxit);
+        batch_begin(b, mask, sel, tol, mx);
+        int k = 0;
+        while (k < maxit) {
+            const int step = use_graph ? b->graph_iters : 4;
+            batch_iterate(b, prec, step, use_graph);
+            k += step;
+            const std::vector<int32_t> d = batch_done(b);
+            if (std::all_of(d.begin(), d.end(), [](int32_t v) { return v != 0; })) break;
+        }
+        (prec == BAE_PREC_FP64 ? mv64 : mv32) += std::min(k, maxit);
+        batch_finish(b, mask, acc);
+        const std::vector<int32_t> kd = batch_kdone(b);
+        for (int p = 0; p < np; ++p)
+            if (mask[p]) {
+                const std::vector<double> h = batch_history(b, p, kd[p]);
+                b->ctx[p]->hist[0].insert(b->ctx[p]->hist[0].end(), h.begin(), h.end());
+                iters[p] += kd[p];
+            }
+    };
+    if (prm->precision == BAE_SOLVE_FP64) {
+        run(BAE_PREC_FP64, 0, all, std::vector<double>(np, prm->tol), false);
+        const std::vector<double> rn = batch_residual_norms(b, nullptr);
+        mv64 += 1;
+        for (int p = 0; p < np; ++p) relres[p] = bn[p] > 0 ? rn[p] / bn[p] : 0.0;
+    } else {
+        const double floor_tol = prm->inner_tol > 0 ? prm->inner_tol : 1e-6;
+        const int max_outer = prm->max_outer > 0 ? prm->max_outer : 8;
+        batch_vec(b, 2, all);   // r = b
+        for (int p = 0; p < np; ++p) relres[p] = bn[p] > 0 ? 1.0 : 0.0;
+        for (int o = 0; o < max_outer; ++o) {
+            std::vector<int32_t> mask(np, 0);
+            std::vector<double> tol(np, 0.1);
+            bool any = false;
+            for (int p = 0; p < np; ++p) {
+                mask[p] = relres[p] > prm->tol;
+                any |= mask[p] != 0;
+                if (mask[p]) tol[p] = std::min(0.1, std::max(floor_tol, 0.5 * prm->tol / relres[p]));
+            }
+            if (!any) break;
+            run(BAE_PREC_FP32, 1, mask, tol, true);
+            for (int p = 0; p < np; ++p) outer[p] += mask[p];
+            const std::vector<double> rn = batch_residual_norms(b, nullptr);
+            mv64 += 1;
+            for (int p = 0; p < np; ++p) relres[p] = bn[p] > 0 ? rn[p] / bn[p] : 0.0;
+        }
+    }
+    batch_gamma_values(b, nullptr);
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int status = BAE_OK;
+    for (int p = 0; p < np; ++p) {
+        bae_ctx* c = b->ctx[p];
+        const int conv = relres[p] <= prm->tol;
+        if (!conv) status = BAE_NOT_CONVERGED;
+        c->solved = true;
+        c->ugrid.clear();
+        if (res) {
+            res[p].status = conv ? BAE_OK : BAE_NOT_CONVERGED;
+            res[p].iterations = iters[p];
+            res[p].outer_steps = outer[p];
+            res[p].converged = conv;
+            res[p].rel_residual_est = c->hist[0].empty() ? 0.0 : c->hist[0].back();
+            res[p].rel_residual_true = relres[p];
+            res[p].seconds = secs;
+            res[p].matvecs_fp64 = mv64;
+            res[p].matvecs_fp32 = mv32;
+        }
+    }
+    return status;
+}
+
 }  // namespace
 }  // namespace bae
+
+using namespace bae;
+
+struct bae_batch {
+    BatchEngine* e = nullptr;
+};
 
 extern "C" {
 
@@ -595,104 +848,52 @@ int bae_batch_create(bae_ctx* const* ctxs, int32_t n, bae_batch** out) {
     return guard([&] {
         if (!ctxs || !out || n < 1) throw Error{BAE_ERR_ARG, "bae_batch_create: bad argument"};
         *out = nullptr;
-        auto b = std::make_unique<bae_batch>();
-        b->np = n;
+        std::vector<bae_ctx*> members;
         for (int i = 0; i < n; ++i) {
             bae_ctx* c = ctxs[i];
             if (!c) throw Error{BAE_ERR_ARG, "null context"};
             if (!c->rhs_ready || c->nrhs != 1) throw Error{BAE_ERR_STATE, "every context needs exactly one RHS set"};
             if (i > 0 && c->device != ctxs[0]->device) throw Error{BAE_ERR_ARG, "contexts on different devices"};
-            b->ctx.push_back(c);
+            members.push_back(c);
         }
-        b->device = ctxs[0]->device;
-        BAE_HIP_CHECK(hipSetDevice(b->device));
-        hipDeviceProp_t prop;
-        BAE_HIP_CHECK(hipGetDeviceProperties(&prop, b->device));
-        b->n_cu = prop.multiProcessorCount;
-        BAE_HIP_CHECK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
-        b->hp.resize(n);
-        for (int p = 0; p < n; ++p) {
-            bae_ctx* c = b->ctx[p];
-            BProb& q = b->hp[p];
-            q.rowptr = c->B.rowptr;
-            q.col = c->B.col;
-            q.coef = c->B.coef;
-            q.tq = c->cl.tq;
-            q.tp = c->cl.tp;
-            q.tw = c->cl.t;
-            q.tpos = c->t_pos.as<int32_t>();
-            q.n = (int)c->ngm;
-            q.nt = (int)c->nT;
-            q.ns_pad = (int)c->S.ps.padded;
-            q.m = c->K.m;
-            q.V = c->K.V;
-            q.H = c->K.H;
-            q.cs = c->K.cs;
-            q.sn = c->K.sn;
-            q.g = c->K.g;
-            q.hist = c->K.hist;
-            q.beta = c->K.beta;
-            q.done = c->K.done;
-            q.kdone = c->K.kdone;
-            q.hA = c->hA.as<double>();
-            q.hB = c->hB.as<double>();
-            q.nrm = c->nrm.as<double>();
-            q.y = c->ycoef.as<double>();
-            q.b = c->b.as<double>();
-            q.x = c->x.as<double>();
-            q.r = c->r.as<double>();
-            q.tmp = c->tmp.as<double>();
-            q.ug = c->u_gamma.as<double>();
-            q.upg = c->up_gamma.as<double>();
-            q.w = c->w.p;
-        }
-        b->kdev.alloc(sizeof(int32_t) * 4);
-        b->gi.alloc(sizeof(int32_t) * n);
-        b->gd.alloc(sizeof(double) * n);
-        b->tol.alloc(sizeof(double) * 2);
-        b->skip.alloc(sizeof(int32_t) * n);
-        BAE_HIP_CHECK(hipHostMalloc((void**)&b->pinned, sizeof(int32_t) * (n + 1), hipHostMallocDefault));
+        BAE_HIP_CHECK(hipSetDevice(members[0]->device));
+        auto b = std::make_unique<bae_batch>();
+        b->e = batch_engine_new(members[0]->device, nullptr);
+        b->e->ctx = members;
         // tiling from the autotuner's cache, if any
         const std::string path = tune_cache_path();
         if (!path.empty()) {
             std::ifstream f(path);
-            std::string key, line;
-            double pairs = 0;
-            for (auto* c : b->ctx) pairs += (double)c->nT * c->nS;
-            std::ostringstream k;
-            k << prop.gcnArchName << " " << (int)std::lround(std::log2(std::max(pairs, 1.0))) << " "
-              << (int)std::lround(std::log2((double)n));
+            const std::string key = tune_key(b->e);
+            std::string line;
             while (std::getline(f, line)) {
                 std::istringstream ls(line);
                 std::string a, pb, nb;
                 int bpc, gm;
-                if ((ls >> a >> pb >> nb >> bpc >> gm) && (a + " " + pb + " " + nb) == k.str()) {
-                    b->blk_per_chunk = bpc;
-                    b->grid_mult = gm;
+                if ((ls >> a >> pb >> nb >> bpc >> gm) && (a + " " + pb + " " + nb) == key && bpc > 0 && gm > 0) {
+                    b->e->blk_per_chunk = bpc;
+                    b->e->grid_mult = gm;
                 }
             }
         }
-        build_layout(b.get());
+        build_layout(b->e);
         *out = b.release();
     });
 }
 
 int bae_batch_destroy(bae_batch* b) {
     if (!b) return BAE_OK;
-    (void)hipSetDevice(b->device);
-    if (b->stream) (void)hipStreamSynchronize(b->stream);
-    release_graphs(b);
-    if (b->pinned) (void)hipHostFree(b->pinned);
-    hipStream_t st = b->stream;
+    (void)hipSetDevice(b->e->device);
+    batch_engine_delete(b->e);
     delete b;
-    if (st) (void)hipStreamDestroy(st);
     return BAE_OK;
 }
 
-int bae_batch_autotune(bae_batch* b, int32_t precision, int32_t* chosen) {
+int bae_batch_autotune(bae_batch* bb, int32_t precision, int32_t* chosen) {
     return guard([&] {
-        if (!b) throw Error{BAE_ERR_ARG, "null batch"};
+        if (!bb) throw Error{BAE_ERR_ARG, "null batch"};
         if (precision != BAE_PREC_FP64 && precision != BAE_PREC_FP32) throw Error{BAE_ERR_ARG, "unknown precision"};
+        BatchEngine* b = bb->e;
         BAE_HIP_CHECK(hipSetDevice(b->device));
         hipStream_t st = b->stream;
         hipEvent_t e0, e1;
@@ -700,8 +901,7 @@ int bae_batch_autotune(bae_batch* b, int32_t precision, int32_t* chosen) {
         BAE_HIP_CHECK(hipEventCreate(&e1));
         float best = 1e30f;
         int best_bpc = b->blk_per_chunk, best_gm = b->grid_mult;
-        b_vec<<<nblocks(b->tot_row), kT, 0, st>>>(b->probs.as<BProb>(), b->off_row.as<int64_t>(), b->np, b->tot_row,
-                                                  1);   // x = 0: the timed applies read it
+        batch_vec(b, 1, std::vector<int32_t>(b->np, 1));   // x = 0: the timed applies read it
         for (int bpc : {2, 4, 8, 16, 32, 64})
             for (int gm : {2, 4, 8}) {
                 b->blk_per_chunk = bpc;
@@ -731,113 +931,21 @@ int bae_batch_autotune(bae_batch* b, int32_t precision, int32_t* chosen) {
         }
         const std::string path = tune_cache_path();
         if (!path.empty()) {
-            hipDeviceProp_t prop;
-            BAE_HIP_CHECK(hipGetDeviceProperties(&prop, b->device));
-            double pairs = 0;
-            for (auto* c : b->ctx) pairs += (double)c->nT * c->nS;
             std::ofstream f(path, std::ios::app);
-            if (f)
-                f << prop.gcnArchName << " " << (int)std::lround(std::log2(std::max(pairs, 1.0))) << " "
-                  << (int)std::lround(std::log2((double)b->np)) << " " << best_bpc << " " << best_gm << "\n";
+            if (f) f << tune_key(b) << " " << best_bpc << " " << best_gm << "\n";
         }
     });
 }
 
-int bae_batch_solve(bae_batch* b, const bae_solve_params* prm, int32_t use_graph, bae_result* res) {
+int bae_batch_solve(bae_batch* bb, const bae_solve_params* prm, int32_t use_graph, bae_result* res) {
     int status = BAE_OK;
     int rc = guard([&] {
-        if (!b || !prm) throw Error{BAE_ERR_ARG, "null argument"};
+        if (!bb || !prm) throw Error{BAE_ERR_ARG, "null argument"};
         if (prm->precision != BAE_SOLVE_FP64 && prm->precision != BAE_SOLVE_FP32_REFINED)
             throw Error{BAE_ERR_ARG, "unknown solve precision"};
         if (!(prm->tol > 0.0)) throw Error{BAE_ERR_ARG, "tol must be > 0"};
-        BAE_HIP_CHECK(hipSetDevice(b->device));
-        hipStream_t st = b->stream;
-        const auto t0 = std::chrono::steady_clock::now();
-        const BProb* P = b->probs.as<BProb>();
-        int mmin = 1 << 30;
-        for (auto* c : b->ctx) mmin = std::min(mmin, c->K.m);
-        const int maxit = prm->maxit > 0 ? std::min(prm->maxit, mmin) : mmin;
-        // ||b||
-        norms(b, 0);
-        std::vector<double> bn(b->np);
-        b_gather<<<(b->np + 63) / 64, 64, 0, st>>>(P, b->np, 2, nullptr, b->gd.as<double>());
-        BAE_HIP_CHECK(hipMemcpyAsync(bn.data(), b->gd.p, sizeof(double) * b->np, hipMemcpyDeviceToHost, st));
-        BAE_HIP_CHECK(hipStreamSynchronize(st));
-        for (auto& v : bn) v = std::sqrt(v);
-        b_vec<<<nblocks(b->tot_row), kT, 0, st>>>(P, b->off_row.as<int64_t>(), b->np, b->tot_row, 1);  // x = 0
-        std::vector<int> iters(b->np, 0), outer(b->np, 0);
-        std::vector<double> relres;
-        int64_t mv64 = 0, mv32 = 0;
-        for (auto* c : b->ctx) c->hist.assign(1, {});
-        auto collect_hist = [&](const std::vector<int32_t>& skip) {
-            std::vector<int32_t> kd(b->np);
-            b_gather<<<(b->np + 63) / 64, 64, 0, st>>>(P, b->np, 1, b->gi.as<int32_t>(), nullptr);
-            BAE_HIP_CHECK(hipMemcpyAsync(kd.data(), b->gi.p, sizeof(int32_t) * b->np, hipMemcpyDeviceToHost, st));
-            BAE_HIP_CHECK(hipStreamSynchronize(st));
-            for (int p = 0; p < b->np; ++p) {
-                if (skip[p]) continue;
-                std::vector<double> h(kd[p]);
-                if (kd[p] > 0)
-                    BAE_HIP_CHECK(hipMemcpy(h.data(), b->hp[p].hist, sizeof(double) * kd[p], hipMemcpyDeviceToHost));
-                b->ctx[p]->hist[0].insert(b->ctx[p]->hist[0].end(), h.begin(), h.end());
-                iters[p] += kd[p];
-            }
-        };
-        if (prm->precision == BAE_SOLVE_FP64) {
-            std::vector<int32_t> skip(b->np, 0);
-            const int k = gmres_all(b, BAE_PREC_FP64, 0, prm->tol, maxit, skip, false, use_graph != 0);
-            mv64 += k;
-            collect_hist(skip);
-            relres = residuals(b, bn);
-            mv64 += 1;
-        } else {
-            const double floor_tol = prm->inner_tol > 0 ? prm->inner_tol : 1e-6;
-            const int max_outer = prm->max_outer > 0 ? prm->max_outer : 8;
-            b_vec<<<nblocks(b->tot_row), kT, 0, st>>>(P, b->off_row.as<int64_t>(), b->np, b->tot_row, 2);  // r = b
-            relres.assign(b->np, 1.0);
-            for (int o = 0; o < max_outer; ++o) {
-                std::vector<int32_t> skip(b->np, 0);
-                bool all = true;
-                double worst = 0.0;
-                for (int p = 0; p < b->np; ++p) {
-                    skip[p] = relres[p] <= prm->tol;
-                    all &= skip[p] != 0;
-                    if (!skip[p]) worst = std::max(worst, relres[p]);
-                }
-                if (all) break;
-                const double inner = std::min(0.1, std::max(floor_tol, 0.5 * prm->tol / worst));
-                const int k = gmres_all(b, BAE_PREC_FP32, 1, inner, maxit, skip, true, use_graph != 0);
-                mv32 += k;
-                collect_hist(skip);
-                for (int p = 0; p < b->np; ++p) outer[p] += skip[p] ? 0 : 1;
-                relres = residuals(b, bn);
-                mv64 += 1;
-            }
-        }
-        // u_gamma = D x + u_p on gamma
-        apply_all(b, BAE_PREC_FP64, 1, -1, 0);
-        b_gamma_values<<<nblocks(b->tot_tgt), kT, 0, st>>>(P, b->off_tgt.as<int64_t>(), b->np, b->tot_tgt);
-        BAE_HIP_CHECK(hipGetLastError());
-        BAE_HIP_CHECK(hipStreamSynchronize(st));
-        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        for (int p = 0; p < b->np; ++p) {
-            bae_ctx* c = b->ctx[p];
-            const int conv = relres[p] <= prm->tol;
-            if (!conv) status = BAE_NOT_CONVERGED;
-            c->solved = true;
-            c->ugrid.clear();
-            if (res) {
-                res[p].status = conv ? BAE_OK : BAE_NOT_CONVERGED;
-                res[p].iterations = iters[p];
-                res[p].outer_steps = outer[p];
-                res[p].converged = conv;
-                res[p].rel_residual_est = c->hist[0].empty() ? 0.0 : c->hist[0].back();
-                res[p].rel_residual_true = relres[p];
-                res[p].seconds = secs;
-                res[p].matvecs_fp64 = mv64;
-                res[p].matvecs_fp32 = mv32;
-            }
-        }
+        BAE_HIP_CHECK(hipSetDevice(bb->e->device));
+        status = solve_all(bb->e, prm, use_graph != 0, res);
     });
     return rc != BAE_OK ? rc : status;
 }

@@ -48,6 +48,14 @@ inline void upload(DevMem& m, const std::vector<T>& v, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------ LGF table cache
+// GMRES control of one context in device memory (used by the batched and served solves,
+// where problems advance independently).
+struct Ctl {
+    int k;        // current Arnoldi step
+    int maxit;    // iteration cap of the current GMRES
+    double tol;   // relative tolerance of the current GMRES
+};
+
 struct Table {
     int device = 0;
     double s = 0.0;
@@ -152,9 +160,17 @@ struct bae_ctx {
     DevMem up_gamma;           // [rhs][nT] external order
     DevMem u_gamma;            // [rhs][nT]
     DevMem wf;                 // [rhs][|M+|] h^2 f in Mp order
+    DevMem ctl;                // Ctl of RHS 0 for batched / served solves
     int nrhs = 0;
     bool has_f = false, rhs_ready = false, solved = false;
     std::vector<std::vector<double>> hist;  // per rhs
     std::vector<double> ugrid;              // [rhs][n0 n1 n2] when computed
     int32_t* pinned_flags = nullptr;        // host pinned, 2 * max_rhs
 };
+
+namespace bae {
+// Device part of bae_create for an already classified geometry (throws Error).
+bae_ctx* create_context(const bae_grid& grid, const bae_options* opt, Geometry&& geo);
+int64_t estimate_context_bytes(const Geometry& G, double s, const bae_options* opt);
+int lgf_near_radius();
+}  // namespace bae

@@ -1,0 +1,411 @@
+// Serving loop with continuous batching.
+//
+// A scheduler thread owns one batch engine.  Submitted requests wait in FIFO order; a
+// request is admitted when a slot is free and its device footprint (computed from its
+// classified geometry before any device allocation) fits in the remaining memory budget.
+// Admitted requests keep their point sets, LGF table and Krylov state on the device and
+// join the running batch at the next step boundary; every step advances all running
+// requests by a few GMRES iterations with one launch per phase, so new work overlaps with
+// work already on the GPU.  A finished request (FP64 GMRES, or the FP32 inner solve of a
+// refinement step followed by its FP64 residual) leaves the batch, its result is copied to
+// the host and its memory and slot are released for the requests still waiting.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+
+#include "batch.hpp"
+
+namespace bae {
+namespace {
+
+enum { Q_WAITING = 0, Q_RUNNING = 1, Q_DONE = 2, Q_FAILED = 3 };
+
+struct Req {
+    uint64_t ticket = 0;
+    bae_grid grid{};
+    bae_levelset ls{};
+    std::vector<double> phi;
+    bae_boundary_fn g = nullptr;
+    void* user = nullptr;
+    int state = Q_WAITING;
+    int status = BAE_OK;
+    std::string error;
+    std::unique_ptr<Geometry> geo;
+    int64_t bytes = 0;
+    bae_ctx* ctx = nullptr;
+    double bnorm = 0.0, relres = 1.0;
+    int iters = 0, outer = 0;
+    int64_t mv64 = 0, mv32 = 0;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    std::vector<double> q, ug;
+    bool fetched = false;
+};
+
+using clock_t_ = std::chrono::steady_clock;
+
+}  // namespace
+}  // namespace bae
+
+using namespace bae;
+
+struct bae_server {
+    bae_server_options opt{};
+    BatchEngine* engine = nullptr;
+    std::thread thread;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    bool stop = false;
+    uint64_t next_ticket = 1;
+    std::deque<std::shared_ptr<Req>> waiting;
+    std::vector<std::shared_ptr<Req>> running;
+    std::map<uint64_t, std::shared_ptr<Req>> all;
+    int64_t used = 0;
+    bae_server_stats stats{};
+    clock_t_::time_point t0;
+    double now() const { return std::chrono::duration<double>(clock_t_::now() - t0).count(); }
+};
+
+namespace bae {
+namespace {
+
+void fail(bae_server* s, const std::shared_ptr<Req>& r, int status, const std::string& msg) {
+    r->state = Q_FAILED;
+    r->status = status;
+    r->error = msg;
+    r->t_done = s->now();
+    s->stats.failed++;
+}
+
+// Admit waiting requests (FIFO) while a slot and memory are available.  Returns the
+// newly admitted ones.  Called on the scheduler thread without the lock held, except
+// around queue manipulation.
+std::vector<std::shared_ptr<Req>> admit(bae_server* s) {
+    std::vector<std::shared_ptr<Req>> fresh;
+    for (;;) {
+        std::shared_ptr<Req> r;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            if (s->waiting.empty() || (int)(s->running.size() + fresh.size()) >= s->opt.max_slots) break;
+            r = s->waiting.front();
+        }
+        bae_options o{};
+        o.device = s->opt.device;
+        o.max_rhs = 1;
+        o.max_krylov = s->opt.max_krylov;
+        if (!r->geo) {
+            try {
+                r->geo = std::make_unique<Geometry>();
+                bae_levelset ls = r->ls;
+                if (ls.kind == BAE_LS_SAMPLED) ls.phi_samples = r->phi.data();
+                build_geometry(r->grid, ls, *r->geo);
+                r->bytes = estimate_context_bytes(*r->geo, r->grid.sigma * r->grid.h * r->grid.h, &o);
+            } catch (const Error& e) {
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->waiting.pop_front();
+                fail(s, r, e.code, e.msg);
+                s->cv_done.notify_all();
+                continue;
+            }
+        }
+        if (r->bytes > s->opt.hbm_budget) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->waiting.pop_front();
+            fail(s, r, BAE_ERR_ADMISSION, "request needs more device memory than the whole budget");
+            s->cv_done.notify_all();
+            continue;
+        }
+        if (s->used + r->bytes > s->opt.hbm_budget) break;   // wait for memory (FIFO order)
+        try {
+            r->ctx = create_context(r->grid, &o, std::move(*r->geo));
+            r->geo.reset();
+            const int64_t n = r->ctx->ngm;
+            std::vector<double> gx(n);
+            r->g(r->user, n, r->ctx->geo.xstar.data(), gx.data());
+            if (int rc = bae_set_rhs(r->ctx, 1, gx.data(), nullptr); rc != BAE_OK)
+                throw Error{rc, bae_last_error()};
+        } catch (const Error& e) {
+            if (r->ctx) bae_destroy(r->ctx);
+            r->ctx = nullptr;
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->waiting.pop_front();
+            fail(s, r, e.code, e.msg);
+            s->cv_done.notify_all();
+            continue;
+        }
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->waiting.pop_front();
+        r->state = Q_RUNNING;
+        r->t_admit = s->now();
+        s->used += r->bytes;
+        s->stats.admitted++;
+        s->stats.peak_bytes = std::max<int64_t>(s->stats.peak_bytes, s->used);
+        fresh.push_back(r);
+    }
+    return fresh;
+}
+
+void scheduler(bae_server* s) {
+    (void)hipSetDevice(s->opt.device);
+    const bool refined = s->opt.precision == BAE_SOLVE_FP32_REFINED;
+    const int prec = refined ? BAE_PREC_FP32 : BAE_PREC_FP64;
+    const double floor_tol = 1e-6;
+    for (;;) {
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_work.wait_for(lk, std::chrono::milliseconds(20), [&] {
+                return s->stop || !s->waiting.empty() || !s->running.empty();
+            });
+            if (s->stop && s->running.empty() && s->waiting.empty()) return;
+        }
+        std::vector<std::shared_ptr<Req>> fresh;
+        try {
+            fresh = admit(s);
+        } catch (...) {
+        }
+        std::vector<std::shared_ptr<Req>> run;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->running.insert(s->running.end(), fresh.begin(), fresh.end());
+            run = s->running;
+            s->stats.max_active = std::max<int64_t>(s->stats.max_active, (int64_t)run.size());
+        }
+        if (run.empty()) continue;
+        try {
+            if (!fresh.empty()) {
+                std::vector<bae_ctx*> members;
+                for (auto& r : run) members.push_back(r->ctx);
+                batch_set_members(s->engine, members);
+                const int np = (int)run.size();
+                std::vector<int32_t> mask(np, 0);
+                for (int p = 0; p < np; ++p) mask[p] = std::find(fresh.begin(), fresh.end(), run[p]) != fresh.end();
+                const std::vector<double> bn = batch_bnorms(s->engine);
+                for (int p = 0; p < np; ++p)
+                    if (mask[p]) run[p]->bnorm = bn[p];
+                batch_vec(s->engine, 1, mask);              // x = 0
+                if (refined) batch_vec(s->engine, 2, mask);  // r = b
+                std::vector<double> tol(np, s->opt.tol);
+                if (refined)
+                    for (int p = 0; p < np; ++p) tol[p] = std::min(0.1, std::max(floor_tol, 0.5 * s->opt.tol));
+                batch_begin(s->engine, mask, refined ? 1 : 0, tol, std::vector<int>(np, s->opt.maxit));
+            }
+            batch_iterate(s->engine, prec, s->opt.iters_per_step, false);
+            s->stats.steps++;
+            const std::vector<int32_t> done = batch_done(s->engine);
+            const int np = (int)run.size();
+            std::vector<int32_t> fin(np, 0);
+            bool any = false;
+            for (int p = 0; p < np; ++p) {
+                fin[p] = done[p] != 0;
+                any |= fin[p] != 0;
+            }
+            if (!any) continue;
+            batch_finish(s->engine, fin, refined);
+            const std::vector<int32_t> kd = batch_kdone(s->engine);
+            const std::vector<double> rn = batch_residual_norms(s->engine, &fin);
+            std::vector<int32_t> complete(np, 0), again(np, 0);
+            std::vector<double> tol(np, s->opt.tol);
+            for (int p = 0; p < np; ++p) {
+                if (!fin[p]) continue;
+                Req& r = *run[p];
+                r.iters += kd[p];
+                (refined ? r.mv32 : r.mv64) += kd[p];
+                r.mv64 += 1;
+                r.relres = r.bnorm > 0 ? rn[p] / r.bnorm : 0.0;
+                if (refined) r.outer++;
+                if (refined && r.relres > s->opt.tol && r.outer < 8 && r.iters < 4 * s->opt.maxit) {
+                    again[p] = 1;
+                    tol[p] = std::min(0.1, std::max(floor_tol, 0.5 * s->opt.tol / r.relres));
+                } else {
+                    complete[p] = 1;
+                }
+            }
+            if (std::any_of(again.begin(), again.end(), [](int32_t v) { return v != 0; }))
+                batch_begin(s->engine, again, 1, tol, std::vector<int>(np, s->opt.maxit));
+            if (!std::any_of(complete.begin(), complete.end(), [](int32_t v) { return v != 0; })) continue;
+            batch_gamma_values(s->engine, &complete);
+            std::vector<std::shared_ptr<Req>> keep;
+            for (int p = 0; p < np; ++p) {
+                auto& r = run[p];
+                if (!complete[p]) {
+                    keep.push_back(r);
+                    continue;
+                }
+                bae_ctx* c = r->ctx;
+                r->q.resize(c->ngm);
+                r->ug.resize(c->nT);
+                BAE_HIP_CHECK(hipMemcpy(r->q.data(), c->x.p, sizeof(double) * c->ngm, hipMemcpyDeviceToHost));
+                BAE_HIP_CHECK(hipMemcpy(r->ug.data(), c->u_gamma.p, sizeof(double) * c->nT, hipMemcpyDeviceToHost));
+                r->ctx = nullptr;
+                bae_destroy(c);
+                std::lock_guard<std::mutex> lk(s->mu);
+                r->state = Q_DONE;
+                r->status = r->relres <= s->opt.tol ? BAE_OK : BAE_NOT_CONVERGED;
+                r->t_done = s->now();
+                s->used -= r->bytes;
+                s->stats.completed++;
+            }
+            std::vector<bae_ctx*> members;
+            for (auto& r : keep) members.push_back(r->ctx);
+            batch_set_members(s->engine, members);
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->running = keep;
+            }
+            s->cv_done.notify_all();
+        } catch (const Error& e) {
+            // a device error ends every running request; the server keeps serving new ones
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (auto& r : s->running) {
+                if (r->ctx) bae_destroy(r->ctx);
+                r->ctx = nullptr;
+                s->used -= r->bytes;
+                fail(s, r, e.code, e.msg);
+            }
+            s->running.clear();
+            s->cv_done.notify_all();
+        }
+    }
+}
+
+}  // namespace
+}  // namespace bae
+
+extern "C" {
+
+int bae_server_create(const bae_server_options* opt, bae_server** out) {
+    return guard([&] {
+        if (!opt || !out) throw Error{BAE_ERR_ARG, "null argument"};
+        if (opt->max_slots < 1 || opt->hbm_budget <= 0) throw Error{BAE_ERR_ARG, "max_slots and hbm_budget must be > 0"};
+        if (opt->precision != BAE_SOLVE_FP64 && opt->precision != BAE_SOLVE_FP32_REFINED)
+            throw Error{BAE_ERR_ARG, "unknown precision"};
+        *out = nullptr;
+        auto s = std::make_unique<bae_server>();
+        s->opt = *opt;
+        if (s->opt.tol <= 0) s->opt.tol = 1e-10;
+        if (s->opt.max_krylov <= 0) s->opt.max_krylov = 200;
+        if (s->opt.maxit <= 0 || s->opt.maxit > s->opt.max_krylov) s->opt.maxit = s->opt.max_krylov;
+        if (s->opt.iters_per_step <= 0) s->opt.iters_per_step = 4;
+        BAE_HIP_CHECK(hipSetDevice(s->opt.device));
+        s->engine = batch_engine_new(s->opt.device, nullptr);
+        s->t0 = clock_t_::now();
+        s->thread = std::thread(scheduler, s.get());
+        *out = s.release();
+    });
+}
+
+int bae_server_submit(bae_server* s, const bae_request* req, uint64_t* ticket) {
+    return guard([&] {
+        if (!s || !req || !ticket || !req->g) throw Error{BAE_ERR_ARG, "null argument"};
+        auto r = std::make_shared<Req>();
+        r->grid = req->grid;
+        r->ls = req->levelset;
+        if (r->ls.kind == BAE_LS_SAMPLED) {
+            if (!r->ls.phi_samples) throw Error{BAE_ERR_ARG, "sampled level set without samples"};
+            const int64_t n3 = (int64_t)r->grid.n[0] * r->grid.n[1] * r->grid.n[2];
+            r->phi.assign(r->ls.phi_samples, r->ls.phi_samples + n3);
+        }
+        r->ls.phi_samples = nullptr;
+        r->g = req->g;
+        r->user = req->user;
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop) throw Error{BAE_ERR_STATE, "server is shutting down"};
+        r->ticket = s->next_ticket++;
+        r->t_submit = s->now();
+        s->waiting.push_back(r);
+        s->all[r->ticket] = r;
+        s->stats.submitted++;
+        *ticket = r->ticket;
+        s->cv_work.notify_one();
+    });
+}
+
+int bae_server_wait(bae_server* s, uint64_t ticket, double timeout_s, bae_result* res, bae_request_info* info) {
+    int status = BAE_OK;
+    int rc = guard([&] {
+        if (!s) throw Error{BAE_ERR_ARG, "null server"};
+        std::unique_lock<std::mutex> lk(s->mu);
+        auto it = s->all.find(ticket);
+        if (it == s->all.end()) throw Error{BAE_ERR_ARG, "unknown ticket"};
+        auto r = it->second;
+        auto ready = [&] { return r->state == Q_DONE || r->state == Q_FAILED; };
+        if (timeout_s < 0) s->cv_done.wait(lk, ready);
+        else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready))
+            throw Error{BAE_ERR_STATE, "timed out"};
+        if (r->state == Q_FAILED) throw Error{r->status, r->error};
+        status = r->status;
+        if (res) {
+            res->status = r->status;
+            res->iterations = r->iters;
+            res->outer_steps = r->outer;
+            res->converged = r->status == BAE_OK;
+            res->rel_residual_est = 0.0;
+            res->rel_residual_true = r->relres;
+            res->seconds = r->t_done - r->t_submit;
+            res->matvecs_fp64 = r->mv64;
+            res->matvecs_fp32 = r->mv32;
+        }
+        if (info) {
+            info->state = r->state;
+            info->n_gamma_minus = (int64_t)r->q.size();
+            info->n_targets = (int64_t)r->ug.size();
+            info->bytes = r->bytes;
+            info->t_submit = r->t_submit;
+            info->t_admit = r->t_admit;
+            info->t_done = r->t_done;
+        }
+    });
+    return rc != BAE_OK ? rc : status;
+}
+
+int bae_server_fetch(bae_server* s, uint64_t ticket, double* q, int64_t q_cap, double* u_gamma, int64_t u_cap) {
+    return guard([&] {
+        if (!s) throw Error{BAE_ERR_ARG, "null server"};
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->all.find(ticket);
+        if (it == s->all.end()) throw Error{BAE_ERR_ARG, "unknown ticket"};
+        auto r = it->second;
+        if (r->state != Q_DONE) throw Error{BAE_ERR_STATE, "request not done"};
+        if ((q && q_cap < (int64_t)r->q.size()) || (u_gamma && u_cap < (int64_t)r->ug.size()))
+            throw Error{BAE_ERR_ARG, "output buffer too small"};
+        if (q) std::copy(r->q.begin(), r->q.end(), q);
+        if (u_gamma) std::copy(r->ug.begin(), r->ug.end(), u_gamma);
+        s->all.erase(it);
+    });
+}
+
+int bae_server_stats_get(bae_server* s, bae_server_stats* out) {
+    return guard([&] {
+        if (!s || !out) throw Error{BAE_ERR_ARG, "null argument"};
+        std::lock_guard<std::mutex> lk(s->mu);
+        *out = s->stats;
+        out->bytes_in_use = s->used;
+        out->waiting = (int64_t)s->waiting.size();
+        out->running = (int64_t)s->running.size();
+    });
+}
+
+int bae_server_destroy(bae_server* s) {
+    if (!s) return BAE_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        // requests that never started are failed; running ones finish
+        for (auto& r : s->waiting) fail(s, r, BAE_ERR_STATE, "server shut down");
+        s->waiting.clear();
+        s->cv_work.notify_all();
+        s->cv_done.notify_all();
+    }
+    if (s->thread.joinable()) s->thread.join();
+    (void)hipSetDevice(s->opt.device);
+    batch_engine_delete(s->engine);
+    delete s;
+    return BAE_OK;
+}
+
+}  // extern "C"

@@ -1,22 +1,28 @@
 #!/usr/bin/env python3
 """Benchmark of the unfitted-BAE hot path on one MI355X.
 
-Workload: Poisson -Lap u = f on the ellipsoid with semi-axes (0.45, 0.3, 0.25) centred in the
-unit cube, h = 1/128 (129^3 nodes), f and g from u = sin(pi x) sin(pi y) sin(pi z).
-One step = one complete solve on device-resident inputs: FP64 iterative refinement around
-GMRES with the FP32 LGF sum (every matvec = double-layer weights, LGF sum over
-|gamma| x |gamma- u E| pairs, closure), the FP64 residual matvecs, and u_gamma.
-value = LGF pair-interactions evaluated in the timed steps / their wall time.
+Default workload (the JSON line the contract asks for): Poisson -Lap u = f on the ellipsoid
+with semi-axes (0.45, 0.3, 0.25) centred in the unit cube, h = 1/128 (129^3 nodes), f and g
+from u = sin(pi x) sin(pi y) sin(pi z).  One step = one complete solve on device-resident
+inputs: FP64 iterative refinement around GMRES with the FP32 LGF sum (every matvec =
+double-layer weights, the LGF sum over |gamma| x |gamma- u E| pairs, the closure), the FP64
+residual matvecs, and u_gamma.  value = LGF pair-interactions evaluated in the timed steps
+divided by their wall time.  Also reported: solves/s and p50/p99 latency of the refined and
+of the plain FP64 path, matvec-only rates (HIP events on the launch stream), the roofline
+of the FP32 LGF-sum kernel with its flops counted per pair class, and the CPU oracle's rate
+on a bounded sample of the same matvec.
 
-Also reported: solves/s and p50/p99 latency of the refined path and of the plain FP64
-path, matvec-only rates (HIP events on the launch stream), the roofline of the FP32
-LGF-sum kernel, and the CPU oracle's rate on a bounded sample of the same matvec.
+Other workloads (--workload; their own JSON line, not the contract's):
+  laplace_sphere   33^3 Laplace sphere, FP64 and refined solve latency
+  helmholtz_star   257^3 modified Helmholtz, 16 right-hand sides (MFMA form), refined
+  batch            512 seeded small problems in one lock-step, graph-replayed batch
+  serve            Poisson arrivals into the continuous-batching server, p50/p99 latency
+  profile          matvecs only (for rocprofv3) plus a device copy of known size
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -27,27 +33,39 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "LGF pair-interactions/s per BAE matvec; solves/s + p99 latency at rel err ≤1e-8"
-PEAK_FP32_VECTOR = 157.3   # TFLOP/s, MI355X published (packed FP32 included)
-NEAR_R = 32                # LDS table radius of the kernel
-FLOPS_FAR = 32             # FP32 far-field kernel value (q = 3 expansion), see the design doc
-FLOPS_ACC = 2              # accumulate per right-hand side
+PEAK_FP32_VECTOR = 157.3   # TFLOP/s, MI355X published FP32 vector peak (packed FP32 included)
+PEAK_FP64_VECTOR = 78.6    # TFLOP/s
+# flops per pair (kernel value + one accumulate) by the kernel's pair classes
+FLOPS = {"fp32": {"near": 2, "far": 34, "far_q2": 23, "mixed_near": 2, "mixed_far": 34},
+         "fp64": {"near": 2, "far": 46, "far_q2": 46, "mixed_near": 2, "mixed_far": 46}}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def pair_split(ctx, torch, dev):
-    """(near, far) pair counts of the gamma x (gamma- u E) sum, counted on the device."""
-    gp, gm, ex = ctx.sets()
-    T = torch.from_numpy(np.concatenate([gp, gm]).astype(np.int32)).to(dev)
-    S = torch.from_numpy(np.concatenate([gm, ex]).astype(np.int32)).to(dev)
-    near = 0
-    for i in range(0, T.shape[0], 512):
-        d = (T[i:i + 512, None, :] - S[None, :, :]).abs().amax(dim=-1)
-        near += int((d <= NEAR_R).sum().item())
-    total = T.shape[0] * S.shape[0]
-    return near, total - near
+def flops_of(stats, prec, nrhs=1, gathers=False):
+    """Algorithmic flops of one launch: far-field pairs count their formula, table lookups
+    (near pairs; with sigma > 0 every pair) only the accumulate."""
+    per = {k: 2 for k in FLOPS[prec]} if gathers else FLOPS[prec]
+    tot = sum(stats[k] * per[k] for k in per)
+    return tot + (nrhs - 1) * 2 * sum(stats.values())
+
+
+def time_applies(torch, ctx, q, v, prec, reps):
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        ctx.apply_double_layer(q, v, prec)
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.apply_double_layer(q, v, prec)
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    return float(np.median(times))
 
 
 def cpu_baseline(p, budget_s=12.0):
@@ -72,24 +90,7 @@ def cpu_baseline(p, budget_s=12.0):
                       f"NumPy single thread), {dt:.1f} s"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--nodes", type=int, default=129, help="nodes per axis (h = 1/(nodes-1))")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--matvec-reps", type=int, default=20)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no multi-GPU path",
-              file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    import paper_2502_05507_amd as P
-    import workloads as W
-
+def headline(args, torch, P, W):
     dev = torch.device("cuda:0")
     p = W.poisson_ellipsoid(args.nodes)
     t_setup = time.perf_counter()
@@ -101,7 +102,6 @@ def main():
     pairs_mv = z["n_targets"] * z["n_sources"]
     log(f"setup {t_setup:.2f}s sizes {z}")
 
-    # ---- timed solves: FP32 LGF sum + FP64 refinement
     tol = 1e-10
     for _ in range(args.warmup):
         ctx.solve(P.SOLVE_FP32_REFINED, tol=tol)
@@ -120,7 +120,6 @@ def main():
     refined = r
     u32 = ctx.gamma_values()
 
-    # ---- plain FP64 path for comparison
     ctx.solve(P.SOLVE_FP64, tol=tol)
     lat64 = []
     for _ in range(max(2, args.steps // 3)):
@@ -131,32 +130,22 @@ def main():
     rel_err = float(np.linalg.norm(u32 - u64) / np.linalg.norm(u64))
     log(f"fp64: {np.median(lat64) * 1e3:.1f} ms iters {r64['iterations']}; refined vs fp64 rel err {rel_err:.2e}")
 
-    # ---- matvec-only rates, HIP events on the stream the kernels are launched on
-    stream = torch.cuda.current_stream()
     q = torch.from_numpy(np.random.default_rng(5).standard_normal(z["n_gamma_minus"])).to(dev)
     v = torch.empty(z["n_targets"], dtype=torch.float64, device=dev)
-    mv = {}
+    mv, roof = {}, {}
     for name, prec in (("fp32", P.PREC_FP32), ("fp64", P.PREC_FP64)):
-        for _ in range(3):
-            ctx.apply_double_layer(q, v, prec)
-        times = []
-        for _ in range(args.matvec_reps):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            ctx.apply_double_layer(q, v, prec)
-            e1.record(stream)
-            e1.synchronize()
-            times.append(e0.elapsed_time(e1) * 1e-3)
-        t_med = float(np.median(times))
-        mv[name] = {"median_ms": t_med * 1e3, "pairs_per_s": pairs_mv / t_med}
-    near, far = pair_split(ctx, torch, dev)
-    flops = far * (FLOPS_FAR + FLOPS_ACC) + near * FLOPS_ACC
-    achieved = flops / (mv["fp32"]["median_ms"] * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
-                "kernel": "lgf_sum_kernel<float,1> (+ weights and reduction, timed together)",
-                "flops_per_launch": flops, "near_pairs": near, "far_pairs": far}
+        t_med = time_applies(torch, ctx, q, v, prec, args.matvec_reps)
+        st = ctx.sum_stats(prec)
+        fl = flops_of(st, name)
+        mv[name] = {"median_ms": t_med * 1e3, "pairs_per_s": pairs_mv / t_med, "tflops": fl / t_med / 1e12,
+                    "pair_classes": st}
+        roof[name] = fl / t_med / 1e12
+    peak = PEAK_FP32_VECTOR
+    roofline = {"bound": "alu", "achieved": roof["fp32"], "peak": peak, "unit": "TFLOP/s",
+                "frac": roof["fp32"] / peak, "traffic": None,
+                "kernel": "lgf_sum_kernel<float,1> (timed with its weights and reduction launches)",
+                "flops_per_launch": flops_of(mv["fp32"]["pair_classes"], "fp32"),
+                "frac_of_nonpacked_fp32": roof["fp32"] / (peak / 2)}
 
     out = {
         "metric": METRIC,
@@ -186,12 +175,197 @@ def main():
                        "rel_residual": r64["rel_residual_true"]},
         "matvec": mv,
         "roofline": roofline,
+        "fp64_sum_frac_of_fp64_peak": roof["fp64"] / PEAK_FP64_VECTOR,
         "setup_s": t_setup,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p)
     ctx.close()
-    print(json.dumps(out))
+    return out
+
+
+def laplace_sphere(args, torch, P, W):
+    p = W.laplace_sphere()
+    with P.Context.from_problem(p) as ctx:
+        xs, _, _ = ctx.boundary_points()
+        ctx.set_rhs(p.g(xs))
+        res = {}
+        for name, prec in (("fp64", P.SOLVE_FP64), ("fp32_refined", P.SOLVE_FP32_REFINED)):
+            for _ in range(args.warmup):
+                ctx.solve(prec, tol=1e-10)
+            lat = []
+            for _ in range(max(args.steps, 10)):
+                s0 = time.perf_counter()
+                r = ctx.solve(prec, tol=1e-10)[0]
+                lat.append(time.perf_counter() - s0)
+            res[name] = {"solves_per_s": len(lat) / sum(lat), "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                         "p99_ms": float(np.percentile(lat, 99) * 1e3), "iterations": r["iterations"],
+                         "rel_residual": r["rel_residual_true"]}
+        X = np.concatenate(ctx.sets()[:2]) * p.h
+        err = np.abs(ctx.gamma_values() - p.exact(*X.T)).max()
+        return {"workload": "laplace_sphere_33^3", "sizes": ctx.sizes, **res, "max_err_vs_exact": float(err)}
+
+
+def helmholtz_star(args, torch, P, W):
+    p = W.helmholtz_star(args.star_nodes)
+    t0 = time.perf_counter()
+    with P.Context.from_problem(p, max_rhs=16, max_krylov=200) as ctx:
+        xs, _, _ = ctx.boundary_points()
+        G = np.stack([p.g(xs, r) for r in range(16)])
+        ctx.set_rhs(G)
+        t_setup = time.perf_counter() - t0
+        z = ctx.sizes
+        pairs_mv = z["n_targets"] * z["n_sources"] * 16
+        dev = torch.device("cuda:0")
+        q = torch.from_numpy(np.random.default_rng(6).standard_normal((16, z["n_gamma_minus"]))).to(dev)
+        v = torch.empty((16, z["n_targets"]), dtype=torch.float64, device=dev)
+        mv = {}
+        for name, prec in (("fp32", P.PREC_FP32), ("fp64", P.PREC_FP64)):
+            t_med = time_applies(torch, ctx, q, v, prec, 5)
+            mv[name] = {"median_ms": t_med * 1e3, "pair_rhs_per_s": pairs_mv / t_med}
+            log(f"star 16-RHS matvec {name}: {t_med * 1e3:.1f} ms")
+        s0 = time.perf_counter()
+        res = ctx.solve(P.SOLVE_FP32_REFINED, tol=1e-10)
+        t_solve = time.perf_counter() - s0
+        log(f"star solve {t_solve:.2f}s iters {res[0]['iterations']}")
+        return {"workload": f"helmholtz_star_{args.star_nodes}^3_16rhs", "sizes": z, "setup_s": t_setup,
+                "matvec": mv, "solve_s": t_solve, "iterations": res[0]["iterations"],
+                "outer_steps": res[0]["outer_steps"], "converged": all(r["converged"] for r in res),
+                "max_rel_residual": max(r["rel_residual_true"] for r in res),
+                "pair_rhs_per_s_in_solve": (res[0]["matvecs_fp32"] + res[0]["matvecs_fp64"] + 1) * pairs_mv / t_solve}
+
+
+def resolved_problems(P, count, make):
+    """Seeded problems, redrawing those whose grid leaves a gamma- node with an empty D_n."""
+    out, i = [], 0
+    while len(out) < count:
+        p = make(i)
+        i += 1
+        c = P.Context.from_problem(p, max_rhs=1, max_krylov=150)
+        if c.sizes["n_empty_d"]:
+            c.close()
+            continue
+        out.append((p, c))
+    return out
+
+
+def batch(args, torch, P, W):
+    t0 = time.perf_counter()
+    probs = resolved_problems(P, args.batch, W.batch_problem)
+    for p, c in probs:
+        xs, _, _ = c.boundary_points()
+        c.set_rhs(p.g(xs))
+    t_setup = time.perf_counter() - t0
+    ctxs = [c for _, c in probs]
+    pairs = sum(c.sizes["n_targets"] * c.sizes["n_sources"] for c in ctxs)
+    out = {"workload": f"batch_{len(ctxs)}", "setup_s": t_setup, "pairs_per_matvec_sum": pairs}
+    with P.Batch(ctxs) as b:
+        out["autotune"] = b.autotune(P.PREC_FP32)
+        for name, prec in (("fp64", P.SOLVE_FP64), ("fp32_refined", P.SOLVE_FP32_REFINED)):
+            b.solve(prec, tol=1e-10)                      # warm-up (captures the graph)
+            s0 = time.perf_counter()
+            res = b.solve(prec, tol=1e-10)
+            dt = time.perf_counter() - s0
+            out[name] = {"wall_s": dt, "solves_per_s": len(ctxs) / dt,
+                         "converged": sum(r["converged"] for r in res),
+                         "max_iterations": max(r["iterations"] for r in res),
+                         "lockstep_matvecs": res[0]["matvecs_fp32"] + res[0]["matvecs_fp64"]}
+            log(f"batch {name}: {dt:.2f}s for {len(ctxs)} solves")
+    for c in ctxs:
+        c.close()
+    return out
+
+
+def serve(args, torch, P, W):
+    sizes = W.serving_stream(args.requests, 1.0)[1]
+    probs = []
+    i = 0
+    while len(probs) < args.requests:
+        p = W.serving_problem(i, int(sizes[len(probs)]))
+        i += 1
+        with P.Context.from_problem(p, max_rhs=1, max_krylov=200) as c:
+            if c.sizes["n_empty_d"]:
+                continue
+        probs.append(p)
+    budget = int(args.serve_budget_gb * (1 << 30))
+
+    def run(rate):
+        arrivals = W.serving_stream(args.requests, rate)[0] if rate else np.zeros(args.requests)
+        with P.Server(hbm_budget=budget, max_slots=args.slots, precision=P.SOLVE_FP32_REFINED, tol=1e-10) as srv:
+            t0 = time.perf_counter()
+            tickets = []
+            for a, p in zip(arrivals, probs):
+                while time.perf_counter() - t0 < a:
+                    time.sleep(0.0005)
+                tickets.append(srv.submit_problem(p))
+            lat = []
+            for t in tickets:
+                r, info, q, u = srv.result(t)
+                lat.append(info["t_done"] - info["t_submit"])
+            wall = time.perf_counter() - t0
+            st = srv.stats()
+        return {"rate": rate, "solves_per_s": len(probs) / wall, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3), "max_active": st["max_active"],
+                "peak_gb": st["peak_bytes"] / (1 << 30), "failed": st["failed"]}
+
+    results = {"saturated": run(0.0)}
+    log(f"serve saturated: {results['saturated']}")
+    for f in (0.25, 0.5, 1.0, 2.0):
+        r = run(f * results["saturated"]["solves_per_s"])
+        results[f"x{f}"] = r
+        log(f"serve rate x{f}: {r}")
+    return {"workload": f"serve_{args.requests}_requests", "budget_gb": args.serve_budget_gb, "slots": args.slots,
+            **results}
+
+
+def profile(args, torch, P, W):
+    """Matvecs only: FP32 then FP64 double-layer applies, then a 256 MiB device copy."""
+    dev = torch.device("cuda:0")
+    p = W.poisson_ellipsoid(args.nodes)
+    with P.Context.from_problem(p) as ctx:
+        z = ctx.sizes
+        q = torch.from_numpy(np.random.default_rng(5).standard_normal(z["n_gamma_minus"])).to(dev)
+        v = torch.empty(z["n_targets"], dtype=torch.float64, device=dev)
+        for prec in (P.PREC_FP32, P.PREC_FP64):
+            for _ in range(args.steps):
+                ctx.apply_double_layer(q, v, prec)
+        torch.cuda.synchronize()
+    a = torch.empty(1 << 25, dtype=torch.float64, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"workload": "profile", "copy_bytes_each_way": a.numel() * 8}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--nodes", type=int, default=129, help="nodes per axis of the ellipsoid (h = 1/(nodes-1))")
+    ap.add_argument("--workload", default="poisson_ellipsoid",
+                    choices=["poisson_ellipsoid", "laplace_sphere", "helmholtz_star", "batch", "serve", "profile"])
+    ap.add_argument("--star-nodes", type=int, default=257)
+    ap.add_argument("--batch", type=int, default=512)
+    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--slots", type=int, default=64)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--matvec-reps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2502_05507_amd as P
+    import workloads as W
+
+    fn = {"poisson_ellipsoid": headline, "laplace_sphere": laplace_sphere, "helmholtz_star": helmholtz_star,
+          "batch": batch, "serve": serve, "profile": profile}[args.workload]
+    print(json.dumps(fn(args, torch, P, W)))
 
 
 if __name__ == "__main__":

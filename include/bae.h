@@ -191,6 +191,15 @@ int bae_apply_double_layer(bae_ctx* ctx, const double* q_dev, double* v_dev, int
 int bae_apply_operator(bae_ctx* ctx, const double* q_dev, double* aq_dev, int32_t nrhs,
                        int32_t precision, void* stream);
 /*
+ * Pair counts of the LGF sum over gamma x (gamma- u E) as the kernel classifies them for
+ * `precision` (per wavefront of 64 Morton-ordered targets and block of 64 sources):
+ * counts[0] pairs in all-near blocks (LDS table), [1] in all-far blocks (far field: q = 3
+ * in FP32, q = 4 in FP64; sigma > 0: global-table gathers), [2] in all-far blocks past the
+ * q = 2 gap (FP32, sigma = 0), [3] / [4] pairs of mixed blocks within / beyond the LDS
+ * radius.  Host computation (no device work); for flop accounting.  counts: 5 int64.
+ */
+int bae_sum_stats(const bae_ctx* ctx, int32_t precision, int64_t* counts);
+/*
  * The kernel the LGF sum uses, at `count` integer offsets (offsets_dev: [count][3] int32,
  * device) -> out_dev (count FP64): near table or far-field expansion exactly as the sum
  * evaluates it at `precision`.  For checking the far field and table lookups.

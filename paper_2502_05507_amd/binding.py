@@ -122,6 +122,7 @@ def load_library():
         "bae_apply_double_layer": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P]),
         "bae_apply_operator": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P]),
         "bae_lgf_eval": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int32, _P]),
+        "bae_sum_stats": (C.c_int, [_P, C.c_int32, _P]),
         "bae_batch_create": (C.c_int, [_P, C.c_int32, C.POINTER(_P)]),
         "bae_batch_autotune": (C.c_int, [_P, C.c_int32, _P]),
         "bae_batch_solve": (C.c_int, [_P, C.POINTER(SolveParams), C.c_int32, _P]),
@@ -290,6 +291,13 @@ class Context:
         assert q.is_contiguous() and aq.is_contiguous()
         assert q.numel() == aq.numel() == nrhs * self.sizes["n_gamma_minus"]
         _check(load_library().bae_apply_operator(self._h, _dptr(q), _dptr(aq), nrhs, precision, _stream(stream)))
+
+    def sum_stats(self, precision=PREC_FP32):
+        """Pair counts of the LGF sum by the kernel's block classification (bae_sum_stats)."""
+        c = np.zeros(5, np.int64)
+        _check(load_library().bae_sum_stats(self._h, precision, _ptr(c)))
+        return {"near": int(c[0]), "far": int(c[1]), "far_q2": int(c[2]), "mixed_near": int(c[3]),
+                "mixed_far": int(c[4])}
 
     def lgf_eval(self, offsets, out, precision=PREC_FP64, stream=None):
         """out[i] = the kernel value the LGF sum uses at integer offset offsets[i] (device)."""

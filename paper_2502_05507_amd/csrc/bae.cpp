@@ -727,6 +727,73 @@ int bae_apply_operator(bae_ctx* c, const double* q, double* aq, int32_t nrhs, in
     });
 }
 
+int bae_sum_stats(const bae_ctx* c, int32_t prec, int64_t* counts) {
+    return guard([&] {
+        if (!c || !counts) throw Error{BAE_ERR_ARG, "null argument"};
+        if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32) throw Error{BAE_ERR_ARG, "unknown precision"};
+        const int R = lgf_near_radius();
+        const int R2 = lgf_far2_gap();
+        const bool far = c->tabs.far_field;
+        // points in the kernels' internal (Morton) order
+        std::vector<int32_t> tp(c->geo.gp);
+        tp.insert(tp.end(), c->geo.gm.begin(), c->geo.gm.end());
+        std::vector<int32_t> sp(c->geo.gm);
+        sp.insert(sp.end(), c->geo.ext.begin(), c->geo.ext.end());
+        auto pt = [](const std::vector<int32_t>& v, const std::vector<int32_t>& perm, int64_t i, int a) {
+            return v[3 * perm[i] + a];
+        };
+        const int64_t nt = c->nT, ns = c->nS;
+        const int64_t nblk = c->S.ps.nblk;
+        std::vector<int32_t> box(6 * nblk);
+        for (int64_t b = 0; b < nblk; ++b)
+            for (int a = 0; a < 3; ++a) {
+                int lo = 1 << 30, hi = -(1 << 30);
+                for (int64_t i = b * kSourceBlock; i < (b + 1) * kSourceBlock; ++i) {
+                    const int v = pt(sp, c->S.perm, std::min(i, ns - 1), a);
+                    lo = std::min(lo, v);
+                    hi = std::max(hi, v);
+                }
+                box[6 * b + a] = lo;
+                box[6 * b + 3 + a] = hi;
+            }
+        int64_t cnt[5] = {0, 0, 0, 0, 0};
+        for (int64_t w0 = 0; w0 < nt; w0 += 64) {
+            const int64_t w1 = std::min(nt, w0 + 64);
+            int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+            for (int64_t t = w0; t < w1; ++t)
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = std::min(lo[a], pt(tp, c->T.perm, t, a));
+                    hi[a] = std::max(hi[a], pt(tp, c->T.perm, t, a));
+                }
+            for (int64_t b = 0; b < nblk; ++b) {
+                const int32_t* bb = &box[6 * b];
+                int gap = 0, span = 0;
+                for (int a = 0; a < 3; ++a) {
+                    gap = std::max(gap, std::max(bb[a] - hi[a], lo[a] - bb[3 + a]));
+                    span = std::max(span, std::max(bb[3 + a] - lo[a], hi[a] - bb[a]));
+                }
+                const int64_t s0 = b * kSourceBlock, s1 = std::min(ns, s0 + kSourceBlock);
+                const int64_t pairs = (w1 - w0) * (s1 - s0);
+                if (gap > R) {
+                    if (prec == BAE_PREC_FP32 && far && gap > R2) cnt[2] += pairs;
+                    else cnt[1] += pairs;
+                } else if (span <= R) {
+                    cnt[0] += pairs;
+                } else {
+                    for (int64_t t = w0; t < w1; ++t)
+                        for (int64_t s = s0; s < s1; ++s) {
+                            int m = 0;
+                            for (int a = 0; a < 3; ++a)
+                                m = std::max(m, std::abs(pt(tp, c->T.perm, t, a) - pt(sp, c->S.perm, s, a)));
+                            cnt[m <= R ? 3 : 4]++;
+                        }
+                }
+            }
+        }
+        for (int i = 0; i < 5; ++i) counts[i] = cnt[i];
+    });
+}
+
 int bae_lgf_eval(bae_ctx* c, const int32_t* off, int64_t count, double* out, int32_t prec, void* stream) {
     return guard([&] {
         if (!c || (count > 0 && (!off || !out)) || count < 0) throw Error{BAE_ERR_ARG, "bad argument"};

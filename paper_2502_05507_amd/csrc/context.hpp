@@ -173,4 +173,5 @@ namespace bae {
 bae_ctx* create_context(const bae_grid& grid, const bae_options* opt, Geometry&& geo);
 int64_t estimate_context_bytes(const Geometry& G, double s, const bae_options* opt);
 int lgf_near_radius();
+int lgf_far2_gap();
 }  // namespace bae

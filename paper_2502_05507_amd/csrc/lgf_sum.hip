@@ -270,6 +270,7 @@ void launch_all(const PointSet& T, const PointSet& S, const Real* w, int nrhs, c
 }  // namespace
 
 int lgf_near_radius() { return kNearR; }
+int lgf_far2_gap() { return kFar2R; }
 
 int lgf_sum_chunks(int64_t nt, int64_t ns) {
     const int64_t tiles = (nt + kBlock - 1) / kBlock;

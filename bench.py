@@ -40,6 +40,22 @@ FLOPS = {"fp32": {"near": 2, "far": 34, "far_q2": 23, "mixed_near": 2, "mixed_fa
          "fp64": {"near": 2, "far": 46, "far_q2": 46, "mixed_near": 2, "mixed_far": 46}}
 
 
+# HBM bytes per launch of the FP32 LGF-sum kernel on this workload, from rocprofv3 FETCH_SIZE
+# (x2.00) and WRITE_SIZE (x1.00) runs calibrated on 256 MiB copies
+# (profiles/lgf_sum_poisson_ellipsoid_129_counters.md); valid only for the kernel sources
+# it was measured on, identified by their hash.
+MEASURED_TRAFFIC = {"sources_sha256_16": "bdd72b08175a8978", "bytes": (10715 * 2.0 + 4165 * 1.0) * 1024}
+KERNEL_SOURCES = ("paper_2502_05507_amd/csrc/lgf_sum.hip", "paper_2502_05507_amd/csrc/lgf_device.hpp")
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -141,8 +157,10 @@ def headline(args, torch, P, W):
                     "pair_classes": st}
         roof[name] = fl / t_med / 1e12
     peak = PEAK_FP32_VECTOR
+    traffic = MEASURED_TRAFFIC["bytes"] if (kernel_hash() == MEASURED_TRAFFIC["sources_sha256_16"]
+                                            and args.nodes == 129) else None
     roofline = {"bound": "alu", "achieved": roof["fp32"], "peak": peak, "unit": "TFLOP/s",
-                "frac": roof["fp32"] / peak, "traffic": None,
+                "frac": roof["fp32"] / peak, "traffic": traffic,
                 "kernel": "lgf_sum_kernel<float,1> (timed with its weights and reduction launches)",
                 "flops_per_launch": flops_of(mv["fp32"]["pair_classes"], "fp32"),
                 "frac_of_nonpacked_fp32": roof["fp32"] / (peak / 2)}

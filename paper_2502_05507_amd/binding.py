@@ -102,6 +102,11 @@ def load_library():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise BaeError(-1, f"{LIB_PATH} is missing: build it with `python -m paper_2502_05507_amd.build`")
+    # torch ships its own HIP runtime under the same soname as the system one.  Loading
+    # torch first makes the dynamic linker bind the library to that runtime, so device
+    # pointers and streams from torch and from the library live in one runtime; loaded the
+    # other way round, torch would find a foreign runtime and see no device.
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     sig = {
         "bae_status_string": (C.c_char_p, [C.c_int]),

@@ -78,8 +78,8 @@ typedef struct bae_levelset {
 
 typedef struct bae_options {   /* zero-initialise for defaults                      */
     int32_t device;            /* HIP device ordinal                                */
-    int32_t near_radius_fp64;  /* LDS table radius of the FP64 sum (0 or 32: fixed)  */
-    int32_t near_radius_fp32;  /* LDS table radius of the FP32 sum (default 32)     */
+    int32_t near_radius_fp64;  /* LDS table radius of the FP64 sum (0 or 44: fixed)  */
+    int32_t near_radius_fp32;  /* LDS table radius of the FP32 sum (0 or 55: fixed)  */
     int32_t max_krylov;        /* Krylov basis capacity per RHS (default 400)       */
     int32_t max_rhs;           /* right-hand sides the context can hold (default 16) */
 } bae_options;
@@ -193,10 +193,11 @@ int bae_apply_operator(bae_ctx* ctx, const double* q_dev, double* aq_dev, int32_
 /*
  * Pair counts of the LGF sum over gamma x (gamma- u E) as the kernel classifies them for
  * `precision` (per wavefront of 64 Morton-ordered targets and block of 64 sources):
- * counts[0] pairs in all-near blocks (LDS table), [1] in all-far blocks (far field: q = 3
- * in FP32, q = 4 in FP64; sigma > 0: global-table gathers), [2] in all-far blocks past the
- * q = 2 gap (FP32, sigma = 0), [3] / [4] pairs of mixed blocks within / beyond the LDS
- * radius.  Host computation (no device work); for flop accounting.  counts: 5 int64.
+ * counts[0] pairs in blocks within the LDS table radius (table lookups), [1] in all-far
+ * blocks (far field: q = 3 in FP32, q = 4 in FP64; sigma > 0: global-table gathers), [2] in
+ * all-far blocks past the q = 2 gap (FP32, sigma = 0), [3] / [4] pairs of mixed blocks
+ * within / beyond the LDS radius.  Host computation (no device work); for flop accounting.
+ * counts: 5 int64.
  */
 int bae_sum_stats(const bae_ctx* ctx, int32_t precision, int64_t* counts);
 /*

@@ -3,6 +3,7 @@
 // matvecs, and the outputs.  See include/bae.h for the contract of every call.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <functional>
@@ -18,8 +19,6 @@ namespace bae {
 
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
-
-int lgf_near_radius();
 
 // Tables are shared by every context on a device with the same s (a larger radius
 // replaces a smaller one).  The cache lives until the process ends and is never torn
@@ -53,9 +52,20 @@ using namespace bae;
 
 namespace bae {
 
+void PlanBuf::build(const PointSet& T, const PointSet& S, const SumTables& tabs, hipStream_t st) {
+    std::vector<uint32_t> host;
+    plan_sum(T, S, tabs, plan, host);
+    upload(items, host, st);
+    counter.alloc(sizeof(unsigned long long));
+    launch_fill_int(counter.as<int32_t>(), 2, 0, st);
+    plan.items = items.as<uint32_t>();
+    plan.counter = counter.as<unsigned long long>();
+    BAE_HIP_CHECK(hipStreamSynchronize(st));
+}
+
 static void apply_lgf(bae_ctx* c, const PointSet& T, const PointSet& S, const void* w, int nrhs, int prec,
                       double* part, int64_t cap, int* chunks_out, hipStream_t st) {
-    *chunks_out = lgf_sum_launch(T, S, w, nrhs, prec, c->tabs, part, cap, st);
+    *chunks_out = lgf_sum_launch(T, S, w, nrhs, prec, c->tabs, c->plan.plan, part, cap, c->sum_grid, st);
 }
 
 // v = [D+ q; D- q] (external order), q [nrhs][ngm] with leading dimension ldq
@@ -212,11 +222,12 @@ static void ensure_mplus(bae_ctx* c) {
 // temporary partial buffer; result scattered through pos (or identity).
 static void lgf_sum_to(bae_ctx* c, const PointSet& T, const PointSet& S, const double* w, int nrhs,
                        const int32_t* pos, double* out, int64_t ldo, double scale, hipStream_t st) {
-    const int chunks = lgf_sum_chunks(T.count, S.count);
+    PlanBuf plan;
+    plan.build(T, S, c->tabs, st);
     DevMem p;
-    const int64_t cap = (int64_t)chunks * T.count * nrhs;
+    const int64_t cap = (int64_t)plan.plan.chunks * T.count * nrhs;
     p.alloc(sizeof(double) * cap);
-    int used = lgf_sum_launch(T, S, w, nrhs, BAE_PREC_FP64, c->tabs, p.as<double>(), cap, st);
+    int used = lgf_sum_launch(T, S, w, nrhs, BAE_PREC_FP64, c->tabs, plan.plan, p.as<double>(), cap, c->sum_grid, st);
     launch_reduce_scatter(p.as<double>(), used, T.count, pos, out, ldo, nrhs, scale, st);
     BAE_HIP_CHECK(hipStreamSynchronize(st));
 }
@@ -250,10 +261,10 @@ bae_ctx* create_context(const bae_grid& gridv, const bae_options* opt, Geometry&
         if (c->max_rhs > 64) throw Error{BAE_ERR_ARG, "max_rhs must be <= 64"};
         const int m = c->opt.max_krylov > 0 ? c->opt.max_krylov : 400;
         if (m > 4096) throw Error{BAE_ERR_ARG, "max_krylov must be <= 4096"};
-        const int nr = lgf_near_radius();
-        if ((c->opt.near_radius_fp64 && c->opt.near_radius_fp64 != nr) ||
-            (c->opt.near_radius_fp32 && c->opt.near_radius_fp32 != nr))
-            throw Error{BAE_ERR_ARG, "near radius: this build supports " + std::to_string(nr) + " only"};
+        if ((c->opt.near_radius_fp64 && c->opt.near_radius_fp64 != kLdsRadius64) ||
+            (c->opt.near_radius_fp32 && c->opt.near_radius_fp32 != kLdsRadius32))
+            throw Error{BAE_ERR_ARG, "near radius: this build supports " + std::to_string(kLdsRadius64) + " (FP64) and " +
+                                         std::to_string(kLdsRadius32) + " (FP32) only"};
         c->device = c->opt.device;
         int ndev = 0;
         BAE_HIP_CHECK(hipGetDeviceCount(&ndev));
@@ -270,7 +281,8 @@ bae_ctx* create_context(const bae_grid& gridv, const bae_options* opt, Geometry&
         c->next = (int64_t)G.ext.size() / 3;
         c->nT = c->ngp + c->ngm;
         c->nS = c->ngm + c->next;
-        if (c->s > 0.0 && G.max_offset > 1200) throw Error{BAE_ERR_ARG, "sigma > 0 needs offsets <= 1200"};
+        if (c->s > 0.0 && G.max_offset > kMaxTableRadius)
+            throw Error{BAE_ERR_ARG, "sigma > 0 needs offsets <= " + std::to_string(kMaxTableRadius)};
 
         // targets: gamma+ then gamma- (external order), Morton-sorted internally
         std::vector<int32_t> tp(G.gp);
@@ -317,22 +329,28 @@ bae_ctx* create_context(const bae_grid& gridv, const bae_options* opt, Geometry&
         upload(c->cl_t, G.t, st);
         c->cl = Closure{c->ngm, c->cl_tq.as<int32_t>(), c->cl_tp.as<int32_t>(), c->cl_t.as<double>()};
 
-        // LGF table: radius 32 (LDS) for sigma = 0 with the far field beyond, else every offset
-        const int R = c->s == 0.0 ? nr : std::max(nr, G.max_offset);
+        // LGF table: for sigma = 0 one table of the FP32 LDS radius shared by all contexts
+        // (the far field takes over beyond it), else every offset that occurs.  The LDS
+        // prefix covers the offsets that occur, but at least the far-field gap, beyond which
+        // the expansion is accurate.
+        const int R = c->s == 0.0 ? kLdsRadius32 : std::max(G.max_offset, 1);
         c->table = get_table(c->device, c->s, R, st);
-        c->tabs.near_r64 = c->tabs.near_r32 = nr;
         c->tabs.near64 = c->table->d64.as<double>();
         c->tabs.near32 = c->table->d32.as<float>();
         c->tabs.full64 = c->table->d64.as<double>();
         c->tabs.full32 = c->table->d32.as<float>();
         c->tabs.full_r = c->table->R;
+        const int need = std::max(G.max_offset, kFarGap);
+        c->tabs.tab_r64 = std::min({kLdsRadius64, c->tabs.full_r, need});
+        c->tabs.tab_r32 = std::min({kLdsRadius32, c->tabs.full_r, need});
         c->tabs.far_field = c->s == 0.0;
+        c->sum_grid = lgf_sum_grid(c->device);
+        c->plan.build(c->T.ps, c->S.ps, c->tabs, st);
 
         // work buffers
         const int mr = c->max_rhs;
         c->w.alloc(sizeof(double) * c->S.ps.padded * mr);
-        const int chunks = lgf_sum_chunks(c->nT, c->nS);
-        c->part_cap = (int64_t)chunks * c->nT * mr;
+        c->part_cap = (int64_t)c->plan.plan.chunks * c->nT * mr;
         c->part.alloc(sizeof(double) * c->part_cap);
         const int64_t n = c->ngm;
         KrylovState& K = c->K;
@@ -390,7 +408,8 @@ int64_t estimate_context_bytes(const Geometry& G, double s, const bae_options* o
     b += (padded(nT) / kSourceBlock + padded(nS) / kSourceBlock) * 6 * 4;              // block boxes
     b += nT * 4 + (nS + 1) * 4 + (ngm + (int64_t)G.edge_q.size()) * 12 + ngm * 16;    // maps, CSR, closure
     b += padded(nS) * 8 * mr;                                                          // weights
-    b += (int64_t)lgf_sum_chunks(nT, nS) * nT * mr * 8;                                // partial sums
+    b += (int64_t)lgf_sum_chunks(nT, (nS + kSourceBlock - 1) / kSourceBlock) * nT * mr * 8;   // partial sums
+    b += ((nT + 63) / 64) * kMaxChunks * 4;                                               // work list
     b += ((int64_t)(m + 1) * ngm + (int64_t)m * (m + 1) + 4 * m + 8) * 8 * mr;        // Krylov state
     b += (int64_t)(m + 1) * mr * 8 * (3 + dot_blocks(ngm)) + (int64_t)m * mr * 8;      // CGS, dots, y
     b += 4 * ngm * mr * 8 + 2 * nT * mr * 8;                                           // b, x, r, tmp, u_p, u_gamma
@@ -472,7 +491,8 @@ int bae_get_sizes(const bae_ctx* c, bae_sizes* o) {
                                 &c->t_pos, &c->csr_rowptr, &c->csr_col, &c->csr_coef, &c->cl_tq, &c->cl_tp, &c->cl_t,
                                 &c->w, &c->part, &c->kV, &c->kH, &c->kcs, &c->ksn, &c->kg, &c->khist, &c->kbeta,
                                 &c->kdone, &c->kkdone, &c->hA, &c->hB, &c->nrm, &c->dotpart, &c->ycoef, &c->b, &c->x,
-                                &c->r, &c->tmp, &c->up_gamma, &c->u_gamma, &c->wf})
+                                &c->r, &c->tmp, &c->up_gamma, &c->u_gamma, &c->wf, &c->plan.items,
+                                &c->plan.counter})
             bytes += d->bytes;
         o->device_bytes = (int64_t)bytes;
     });
@@ -731,42 +751,25 @@ int bae_sum_stats(const bae_ctx* c, int32_t prec, int64_t* counts) {
     return guard([&] {
         if (!c || !counts) throw Error{BAE_ERR_ARG, "null argument"};
         if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32) throw Error{BAE_ERR_ARG, "unknown precision"};
-        const int R = lgf_near_radius();
-        const int R2 = lgf_far2_gap();
-        const bool far = c->tabs.far_field;
-        // points in the kernels' internal (Morton) order
-        std::vector<int32_t> tp(c->geo.gp);
-        tp.insert(tp.end(), c->geo.gm.begin(), c->geo.gm.end());
-        std::vector<int32_t> sp(c->geo.gm);
-        sp.insert(sp.end(), c->geo.ext.begin(), c->geo.ext.end());
-        auto pt = [](const std::vector<int32_t>& v, const std::vector<int32_t>& perm, int64_t i, int a) {
-            return v[3 * perm[i] + a];
-        };
-        const int64_t nt = c->nT, ns = c->nS;
-        const int64_t nblk = c->S.ps.nblk;
-        std::vector<int32_t> box(6 * nblk);
-        for (int64_t b = 0; b < nblk; ++b)
-            for (int a = 0; a < 3; ++a) {
-                int lo = 1 << 30, hi = -(1 << 30);
-                for (int64_t i = b * kSourceBlock; i < (b + 1) * kSourceBlock; ++i) {
-                    const int v = pt(sp, c->S.perm, std::min(i, ns - 1), a);
-                    lo = std::min(lo, v);
-                    hi = std::max(hi, v);
-                }
-                box[6 * b + a] = lo;
-                box[6 * b + 3 + a] = hi;
-            }
+        const bool fp32 = prec == BAE_PREC_FP32;
+        const int tab_r = fp32 ? c->tabs.tab_r32 : c->tabs.tab_r64;
+        const PointSet& T = c->T.ps;
+        const PointSet& S = c->S.ps;
+        const int64_t nt = T.count, ns = S.count, nblk = S.nblk;
         int64_t cnt[5] = {0, 0, 0, 0, 0};
+        // the kernel's classification, per (wavefront of 64 targets, source block)
         for (int64_t w0 = 0; w0 < nt; w0 += 64) {
             const int64_t w1 = std::min(nt, w0 + 64);
-            int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
-            for (int64_t t = w0; t < w1; ++t)
+            int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {0, 0, 0};
+            for (int64_t i = w0; i < w0 + 64; ++i) {
+                const int64_t t = std::min(i, nt - 1);
                 for (int a = 0; a < 3; ++a) {
-                    lo[a] = std::min(lo[a], pt(tp, c->T.perm, t, a));
-                    hi[a] = std::max(hi[a], pt(tp, c->T.perm, t, a));
+                    lo[a] = std::min(lo[a], T.hq[3 * t + a]);
+                    hi[a] = std::max(hi[a], T.hq[3 * t + a]);
                 }
+            }
             for (int64_t b = 0; b < nblk; ++b) {
-                const int32_t* bb = &box[6 * b];
+                const int32_t* bb = &S.hbox[6 * b];
                 int gap = 0, span = 0;
                 for (int a = 0; a < 3; ++a) {
                     gap = std::max(gap, std::max(bb[a] - hi[a], lo[a] - bb[3 + a]));
@@ -774,19 +777,17 @@ int bae_sum_stats(const bae_ctx* c, int32_t prec, int64_t* counts) {
                 }
                 const int64_t s0 = b * kSourceBlock, s1 = std::min(ns, s0 + kSourceBlock);
                 const int64_t pairs = (w1 - w0) * (s1 - s0);
-                if (gap > R) {
-                    if (prec == BAE_PREC_FP32 && far && gap > R2) cnt[2] += pairs;
-                    else cnt[1] += pairs;
-                } else if (span <= R) {
-                    cnt[0] += pairs;
-                } else {
-                    for (int64_t t = w0; t < w1; ++t)
-                        for (int64_t s = s0; s < s1; ++s) {
-                            int m = 0;
-                            for (int a = 0; a < 3; ++a)
-                                m = std::max(m, std::abs(pt(tp, c->T.perm, t, a) - pt(sp, c->S.perm, s, a)));
-                            cnt[m <= R ? 3 : 4]++;
-                        }
+                switch (block_class(gap, span, tab_r, c->tabs.far_field, fp32)) {
+                    case kClassTable: cnt[0] += pairs; break;
+                    case kClassFar: case kClassGather: cnt[1] += pairs; break;
+                    case kClassFar2: cnt[2] += pairs; break;
+                    default:
+                        for (int64_t t = w0; t < w1; ++t)
+                            for (int64_t s = s0; s < s1; ++s) {
+                                int m = 0;
+                                for (int a = 0; a < 3; ++a) m = std::max(m, std::abs(T.hq[3 * t + a] - S.hq[3 * s + a]));
+                                cnt[m <= kQuant * tab_r ? 3 : 4]++;
+                            }
                 }
             }
         }

@@ -4,8 +4,8 @@
 // Gram-Schmidt passes, the norm, Givens) is ONE launch for all problems of the batch,
 // over flat index spaces (per-problem offsets, binary search for the owning problem) or
 // over precomputed work lists.  The LGF sum is a persistent kernel: a fixed grid walks a
-// list of (problem, 256-target tile, source chunk) items, keeping the problem's LDS table
-// while consecutive items share it.  The iteration counter lives in device memory, so one
+// list of (problem, 1024-target tile, source chunk) items, keeping the LDS table while
+// consecutive items share it.  The iteration counter lives in device memory, so one
 // GMRES iteration -- or several -- is captured once as a HIP graph and replayed; problems
 // that have converged skip their work items.  The tiling (source blocks per chunk,
 // persistent grid size) is chosen by a small autotuner that times candidates on the batch.
@@ -92,23 +92,34 @@ __global__ void b_weights(const BProb* __restrict__ P, const int64_t* __restrict
     ((Real*)q.w)[s] = (Real)acc;
 }
 
+// Persistent LGF sum over (problem, 1024-target tile, source chunk) items: each of the 16
+// wavefronts of a workgroup takes one 64-target tile of the item.  The LDS table is
+// restaged only when an item needs another table (sigma > 0 problems each have their own;
+// every sigma = 0 problem shares one) or a larger prefix of it.
 template <typename Real>
-__global__ __launch_bounds__(kT) void b_lgf_sum(const BProb* __restrict__ P, const Item* __restrict__ items,
-                                                int nitems, int use_done, const int32_t* __restrict__ sel) {
-    __shared__ Real tab[kNearE];
-    int cur = -1;
+__global__ __launch_bounds__(kSumThreads) void b_lgf_sum(const BProb* __restrict__ P, const Item* __restrict__ items,
+                                                         int nitems, int use_done, const int32_t* __restrict__ sel) {
+    __shared__ __align__(16) char lds[lds_bytes<Real>()];
+    const Lds<Real> L = lds_layout<Real>(lds);
+    fill_index<Real>(L, kMaxR);
+    const Real* cur = nullptr;
+    int cur_r = -1;
+    const int wave = threadIdx.x >> 6;
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const Item w = items[it];
         const BProb& q = P[w.p];
         if ((use_done && q.done[0]) || (sel && !sel[w.p])) continue;   // uniform over the block
         const SumArgs<Real>& a = sum_args<Real>(q);
-        if (w.p != cur) {
+        if (a.near_tab != cur || a.tab_r > cur_r) {
             __syncthreads();
-            for (int i = threadIdx.x; i < kNearE; i += kT) tab[i] = a.near_tab[i];
+            const int n = (a.tab_r + 1) * (a.tab_r + 2) * (a.tab_r + 3) / 6;
+            for (int i = threadIdx.x; i < n; i += kSumThreads) L.tab[i] = a.near_tab[i];
             __syncthreads();
-            cur = w.p;
+            cur = a.near_tab;
+            cur_r = a.tab_r;
         }
-        sum_tile<Real, 1>(a, tab, w.tile, w.chunk);
+        const int tile = w.tile * (kSumThreads / kWave) + wave;
+        if (tile * kWave < a.nt) sum_tile<Real, 1>(a, L, tile, w.chunk);
     }
 }
 
@@ -374,7 +385,7 @@ struct BatchEngine {
     DevMem probs, off_src, off_row, off_tgt, slices, items, ctl_init, mask, arena, gi, gd;
     int64_t tot_src = 0, tot_row = 0, tot_tgt = 0;
     int nslices_total = 0, nitems = 0;
-    int blk_per_chunk = 8, grid_mult = 4, n_cu = 256;
+    int blk_per_chunk = 8, grid_mult = 1, n_cu = 256;
     std::vector<BProb> hp;
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipGraphExec_t exec[2] = {nullptr, nullptr};
@@ -431,7 +442,7 @@ void build_layout(BatchEngine* b) {
         q.chunks = (int)((c->S.ps.nblk + b->blk_per_chunk - 1) / b->blk_per_chunk);
         q.nslices = (int)((c->ngm + kSlice - 1) / kSlice);
         for (int s = 0; s < q.nslices; ++s) sl.push_back(make_int2(p, s));
-        const int tiles = (int)((c->nT + kT - 1) / kT);
+        const int tiles = (int)((c->nT + kSumThreads - 1) / kSumThreads);
         for (int t = 0; t < tiles; ++t)
             for (int ch = 0; ch < q.chunks; ++ch) it.push_back(Item{p, t, ch, 0});
         part_at[p] = arena;
@@ -503,14 +514,17 @@ void build_layout(BatchEngine* b) {
             a.ldw = c->S.ps.padded;
             a.near_tab = near;
             a.full_tab = full;
+            a.full_r = c->tabs.full_r;
             a.far_ok = c->tabs.far_field ? 1 : 0;
             a.part = q.part;
             a.ldp = (int64_t)q.chunks * c->nT;
         };
         fill(q.s64, c->tabs.near64, c->tabs.full64, c->S.ps.xd, c->S.ps.yd, c->S.ps.zd);
         q.s64.w = (const double*)c->w.p;
+        q.s64.tab_r = c->tabs.tab_r64;
         fill(q.s32, c->tabs.near32, c->tabs.full32, c->S.ps.xf, c->S.ps.yf, c->S.ps.zf);
         q.s32.w = (const float*)c->w.p;
+        q.s32.tab_r = c->tabs.tab_r32;
     }
     b->nslices_total = (int)sl.size();
     b->nitems = (int)it.size();
@@ -532,11 +546,11 @@ void apply_all(BatchEngine* b, int prec, int src, int dst, int use_done, const i
     if (prec == BAE_PREC_FP64) {
         b_weights<double><<<nblocks(b->tot_src), kT, 0, st>>>(P, b->off_src.as<int64_t>(), b->np, b->tot_src, src,
                                                               use_done, sel);
-        b_lgf_sum<double><<<grid, kT, 0, st>>>(P, b->items.as<Item>(), b->nitems, use_done, sel);
+        b_lgf_sum<double><<<grid, kSumThreads, 0, st>>>(P, b->items.as<Item>(), b->nitems, use_done, sel);
     } else {
         b_weights<float><<<nblocks(b->tot_src), kT, 0, st>>>(P, b->off_src.as<int64_t>(), b->np, b->tot_src, src,
                                                              use_done, sel);
-        b_lgf_sum<float><<<grid, kT, 0, st>>>(P, b->items.as<Item>(), b->nitems, use_done, sel);
+        b_lgf_sum<float><<<grid, kSumThreads, 0, st>>>(P, b->items.as<Item>(), b->nitems, use_done, sel);
     }
     if (dst >= 0)
         b_closure<<<nblocks(b->tot_row), kT, 0, st>>>(P, b->off_row.as<int64_t>(), b->np, b->tot_row, dst, use_done,
@@ -903,7 +917,7 @@ int bae_batch_autotune(bae_batch* bb, int32_t precision, int32_t* chosen) {
         int best_bpc = b->blk_per_chunk, best_gm = b->grid_mult;
         batch_vec(b, 1, std::vector<int32_t>(b->np, 1));   // x = 0: the timed applies read it
         for (int bpc : {2, 4, 8, 16, 32, 64})
-            for (int gm : {2, 4, 8}) {
+            for (int gm : {1, 2, 4}) {
                 b->blk_per_chunk = bpc;
                 b->grid_mult = gm;
                 build_layout(b);

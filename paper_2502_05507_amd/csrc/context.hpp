@@ -71,33 +71,39 @@ struct PointBuf {
     DevMem x, y, z, xf, yf, zf, xd, yd, zd, bbox;
     PointSet ps;
     std::vector<int32_t> perm;   // internal index -> index in the lexicographic list
+    // pts3: lattice points (3 * count, AoS); order: the internal (Morton) order.  The device
+    // copies are quantised (kQuant x index) and padded to whole blocks with the last point.
     void set(const std::vector<int32_t>& pts3, const std::vector<int32_t>& order, hipStream_t st) {
         const int64_t n = (int64_t)order.size();
         const int64_t nblk = (n + kSourceBlock - 1) / kSourceBlock;
         const int64_t np = nblk * kSourceBlock;
-        std::vector<int32_t> h[3];
+        std::vector<uint32_t> h[3];
         std::vector<float> hf[3];
         std::vector<double> hd[3];
+        ps.hq.assign(3 * np, 0);
         for (int a = 0; a < 3; ++a) {
             h[a].resize(np);
             hf[a].resize(np);
             hd[a].resize(np);
             for (int64_t i = 0; i < np; ++i) {
-                h[a][i] = pts3[3 * order[std::min(i, n - 1)] + a];
-                hf[a][i] = (float)h[a][i];
-                hd[a][i] = (double)h[a][i];
+                const int32_t v = kQuant * pts3[3 * order[std::min(i, n - 1)] + a];
+                if (v < 0) throw Error{BAE_ERR_ARG, "lattice point outside the grid"};
+                ps.hq[3 * i + a] = v;
+                h[a][i] = (uint32_t)v;
+                hf[a][i] = (float)v;
+                hd[a][i] = (double)v;
             }
         }
-        std::vector<int32_t> box(6 * nblk);
+        ps.hbox.assign(6 * nblk, 0);
         for (int64_t b = 0; b < nblk; ++b)
             for (int a = 0; a < 3; ++a) {
                 int lo = 1 << 30, hi = -(1 << 30);
                 for (int64_t i = b * kSourceBlock; i < (b + 1) * kSourceBlock; ++i) {
-                    lo = std::min(lo, h[a][i]);
-                    hi = std::max(hi, h[a][i]);
+                    lo = std::min(lo, ps.hq[3 * i + a]);
+                    hi = std::max(hi, ps.hq[3 * i + a]);
                 }
-                box[6 * b + a] = lo;
-                box[6 * b + 3 + a] = hi;
+                ps.hbox[6 * b + a] = lo;
+                ps.hbox[6 * b + 3 + a] = hi;
             }
         upload(x, h[0], st);
         upload(y, h[1], st);
@@ -108,12 +114,12 @@ struct PointBuf {
         upload(xd, hd[0], st);
         upload(yd, hd[1], st);
         upload(zd, hd[2], st);
-        upload(bbox, box, st);
+        upload(bbox, ps.hbox, st);
         ps.count = n;
         ps.padded = np;
-        ps.x = x.as<int32_t>();
-        ps.y = y.as<int32_t>();
-        ps.z = z.as<int32_t>();
+        ps.x = x.as<uint32_t>();
+        ps.y = y.as<uint32_t>();
+        ps.z = z.as<uint32_t>();
         ps.xf = xf.as<float>();
         ps.yf = yf.as<float>();
         ps.zf = zf.as<float>();
@@ -125,6 +131,13 @@ struct PointBuf {
         perm = order;
         BAE_HIP_CHECK(hipStreamSynchronize(st));   // host vectors are released on return
     }
+};
+
+// A work list on the device (see SumPlan).
+struct PlanBuf {
+    SumPlan plan;
+    DevMem items, counter;
+    void build(const PointSet& T, const PointSet& S, const SumTables& tabs, hipStream_t st);
 };
 
 }  // namespace bae
@@ -148,6 +161,8 @@ struct bae_ctx {
     Closure cl;
     std::shared_ptr<Table> table;
     SumTables tabs;
+    PlanBuf plan;              // work list of the operator's sum (targets gamma, sources gamma- u E)
+    int sum_grid = 1;          // workgroups of the persistent sum kernels (one per CU)
 
     int max_rhs = 16;
     DevMem w, part;
@@ -172,6 +187,4 @@ namespace bae {
 // Device part of bae_create for an already classified geometry (throws Error).
 bae_ctx* create_context(const bae_grid& grid, const bae_options* opt, Geometry&& geo);
 int64_t estimate_context_bytes(const Geometry& G, double s, const bae_options* opt);
-int lgf_near_radius();
-int lgf_far2_gap();
 }  // namespace bae

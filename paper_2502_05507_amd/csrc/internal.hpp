@@ -52,18 +52,40 @@ void lgf_table_generate(double s, int R, double* out, hipStream_t stream);
 
 // ------------------------------------------------------------------ LGF sum (device)
 // Points are grouped in blocks of kSourceBlock consecutive (Morton-ordered) points; each
-// block carries its integer bounding box so a wavefront can classify a whole block as
-// near, far or mixed before touching its points.
+// block carries its bounding box so a wavefront can classify a whole block before
+// touching its points.  Device coordinates are quantised: kQuant x the lattice index.
 constexpr int kSourceBlock = 64;
+constexpr int kQuant = 4;
+constexpr int kLdsRadius32 = 55;          // LDS table radius of the FP32 sum (123 KB)
+constexpr int kLdsRadius64 = 44;          // ... of the FP64 sum (130 KB)
+constexpr int kMaxTableRadius = 1200;     // largest resident table (sigma > 0)
+constexpr int kFarGap = 32;               // far field used beyond this gap (sigma = 0)
+constexpr int kFar2Gap = 64;              // FP32: q = 2 far field beyond this gap
+constexpr int kSumThreads = 1024;         // threads per workgroup of the LGF sum
+constexpr int kMaxChunks = 64;            // source chunks (partial sums per target)
 
-// A set of integer lattice points on the device: SoA int32 coordinates, the same
-// coordinates as float and double, and per-block bounding boxes [nblk][lo xyz, hi xyz].
+// Pair classes of a (64-target wavefront, source block) pair; gap and span in quantised
+// units (the smallest and largest max-norm distance between the two bounding boxes).
+enum BlockClass { kClassTable = 0, kClassFar = 1, kClassFar2 = 2, kClassGather = 3, kClassMixed = 4 };
+__host__ __device__ inline int block_class(int gap, int span, int tab_r, bool far_ok, bool fp32) {
+    if (span <= kQuant * tab_r) return kClassTable;
+    if (far_ok) {
+        if (fp32 && gap > kQuant * kFar2Gap) return kClassFar2;
+        if (gap > kQuant * kFarGap) return kClassFar;
+    } else if (gap > kQuant * tab_r) {
+        return kClassGather;
+    }
+    return kClassMixed;
+}
+
+// A set of lattice points on the device: SoA quantised coordinates as uint32, float and
+// double, and per-block quantised bounding boxes [nblk][lo xyz, hi xyz].
 struct PointSet {
     int64_t count = 0;
     int64_t padded = 0;        // nblk * kSourceBlock; entries past count repeat the last point
-    int32_t* x = nullptr;
-    int32_t* y = nullptr;
-    int32_t* z = nullptr;
+    uint32_t* x = nullptr;
+    uint32_t* y = nullptr;
+    uint32_t* z = nullptr;
     float* xf = nullptr;
     float* yf = nullptr;
     float* zf = nullptr;
@@ -72,25 +94,41 @@ struct PointSet {
     double* zd = nullptr;
     int32_t* bbox = nullptr;
     int64_t nblk = 0;
+    std::vector<int32_t> hq;   // host copy of the quantised coordinates (3 * padded, AoS)
+    std::vector<int32_t> hbox; // host copy of the block boxes
 };
 
-enum SumMode { MODE_NEAR_FAR = 0, MODE_TABLE = 1 };
-
 struct SumTables {
-    int near_r64 = 0, near_r32 = 0;         // LDS radii
-    const double* near64 = nullptr;          // prefix of the full table (device)
+    const double* near64 = nullptr;          // table prefix staged in LDS (device)
     const float* near32 = nullptr;
     const double* full64 = nullptr;          // full table (device), radius full_r
     const float* full32 = nullptr;
     int full_r = 0;
-    bool far_field = false;                  // sigma == 0: expansion beyond the near radius
+    int tab_r64 = 0, tab_r32 = 0;            // LDS radii: min(build radius, full_r)
+    bool far_field = false;                  // sigma == 0: expansion beyond the LDS table
 };
+
+// Work list of one (targets, sources) pair: items (64-target tile, source chunk), ordered by
+// decreasing estimated cost so the dynamically scheduled wavefronts finish together.
+struct SumPlan {
+    int chunks = 1, blk_per_chunk = 1;
+    int64_t nitems = 0;
+    uint32_t* items = nullptr;     // device: tile | chunk << 20
+    unsigned long long* counter = nullptr;   // device: work counter, 0 between launches
+    int64_t class_pairs[2][5] = {{0}};   // [fp64, fp32][class] pairs (mixed split: 3 table, 4 other)
+};
+// Host: chunking, per-item cost, order and pair statistics (items left on the host in
+// 'host_items'); the caller uploads them.
+void plan_sum(const PointSet& T, const PointSet& S, const SumTables& tabs, SumPlan& plan,
+              std::vector<uint32_t>& host_items);
+int lgf_sum_chunks(int64_t nt, int64_t nblk);
+int lgf_sum_grid(int device);    // workgroups of the persistent sum kernels
 
 // v[r][t] (partials per source chunk: part[r][chunk][t]) = sum_s w[r][s] G(T_t - S_s).
 // w is FP64 when prec == BAE_PREC_FP64, FP32 otherwise.  Returns number of chunks used.
 int lgf_sum_launch(const PointSet& T, const PointSet& S, const void* w, int nrhs, int prec,
-                   const SumTables& tabs, double* part, int64_t part_capacity, hipStream_t st);
-int lgf_sum_chunks(int64_t nt, int64_t ns);
+                   const SumTables& tabs, const SumPlan& plan, double* part, int64_t part_capacity,
+                   int grid, hipStream_t st);
 void lgf_eval_launch(const int32_t* off, int64_t count, double* out, int prec, const SumTables& tabs,
                      hipStream_t st);
 

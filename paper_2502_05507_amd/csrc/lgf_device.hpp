@@ -1,6 +1,15 @@
 // Device-side pieces of the LGF sum shared by the per-context kernels (lgf_sum.hip) and
 // the batched engine (batch.hip): kernel evaluation (LDS table, far field, global table),
 // wavefront reductions, compensated accumulators and the tile loop.
+//
+// Coordinates on the device are 4 x the lattice index (kQuant), as int32, float and double.
+// Then |t - s| of two points is directly the byte offset of |d| into a uint32 array, which
+// is how the 1/48-symmetric table index is formed without a multiply:
+//   index(d) = tet(hi) + tri(mid) + lo,  (lo <= mid <= hi) = sorted |d_i|,
+//   tet(h) = h(h+1)(h+2)/6, tri(m) = m(m+1)/2   (the triples with max <= h-1, then mid)
+// with tet and tri read from two small LDS arrays that hold sizeof(Real) x their values:
+// per pair three absolute differences (v_sad_u32), min3 / med3 / max3, two LDS reads and
+// one add give the byte address of G in the LDS (or global) table.
 #pragma once
 
 #include "internal.hpp"
@@ -8,19 +17,28 @@
 namespace bae {
 namespace lgfdev {
 
-constexpr int kBlock = 256;
-constexpr int kUnroll = 8;                           // sources per unrolled step (batched scalar loads)
-constexpr int kFar2R = 64;                           // FP32: q = 2 far field beyond this gap
-constexpr int kNearR = 32;                           // LDS table radius (both precisions)
-constexpr int kNearE = (kNearR + 1) * (kNearR + 2) * (kNearR + 3) / 6;
+constexpr int kWave = 64;
+template <typename Real>
+constexpr int unroll() { return 32 / (int)sizeof(Real); }   // sources per unrolled step (32-byte scalar loads)
+constexpr int kMaxR = kMaxTableRadius;               // largest table radius (tet / tri arrays)
+
+template <typename Real>
+constexpr int tab_radius() { return sizeof(Real) == 4 ? kLdsRadius32 : kLdsRadius64; }
+template <typename Real>
+constexpr int tab_entries() { return (tab_radius<Real>() + 1) * (tab_radius<Real>() + 2) * (tab_radius<Real>() + 3) / 6; }
 
 constexpr double kPi = 3.14159265358979323846;
-constexpr double C0 = 1.0 / (4.0 * kPi);
-constexpr double C1 = 1.0 / (16.0 * kPi), C2 = -5.0 / (16.0 * kPi);
-constexpr double D0 = 23.0 / (128.0 * kPi), D1 = -336.0 / (128.0 * kPi), D2 = 1155.0 / (128.0 * kPi),
-                 D3 = -1134.0 / (128.0 * kPi);
-constexpr double F0 = 647.0 / (512.0 * kPi), F1 = -20301.0 / (512.0 * kPi), F2 = 178035.0 / (512.0 * kPi),
-                 F3 = -425425.0 / (512.0 * kPi), F4 = -208494.0 / (512.0 * kPi), F5 = 810810.0 / (512.0 * kPi);
+// Far-field coefficients for the quantised offset D = kQuant d (so |D| = 4|n|): with
+// rinv = 1/|D| and rho = 1/|D|^2 the expansion keeps its form, each power of rho and the
+// leading 1/|n| picking up a power of kQuant (exact: powers of two).
+constexpr double Q1 = kQuant, Q3 = Q1 * Q1 * Q1, Q5 = Q3 * Q1 * Q1, Q7 = Q5 * Q1 * Q1;
+constexpr double C0 = Q1 / (4.0 * kPi);
+constexpr double C1 = Q3 / (16.0 * kPi), C2 = -5.0 * Q3 / (16.0 * kPi);
+constexpr double D0 = 23.0 * Q5 / (128.0 * kPi), D1 = -336.0 * Q5 / (128.0 * kPi), D2 = 1155.0 * Q5 / (128.0 * kPi),
+                 D3 = -1134.0 * Q5 / (128.0 * kPi);
+constexpr double F0 = 647.0 * Q7 / (512.0 * kPi), F1 = -20301.0 * Q7 / (512.0 * kPi),
+                 F2 = 178035.0 * Q7 / (512.0 * kPi), F3 = -425425.0 * Q7 / (512.0 * kPi),
+                 F4 = -208494.0 * Q7 / (512.0 * kPi), F5 = 810810.0 * Q7 / (512.0 * kPi);
 
 template <typename Real>
 __device__ __forceinline__ Real rsqrt_t(Real x);
@@ -29,7 +47,8 @@ __device__ __forceinline__ double rsqrt_t<double>(double x) { return rsqrt(x); }
 template <>
 __device__ __forceinline__ float rsqrt_t<float>(float x) { return __builtin_amdgcn_rsqf(x); }
 
-// q = 2 only (FP32 beyond kFar2R, where the q = 3 term is below 4.3e-8 relative).
+// q = 2 only (FP32 beyond kFar2Gap, where the q = 3 term is below 4.3e-8 relative).
+// X, Y, Z: squared quantised offset components.
 __device__ __forceinline__ float far_field_q2(float X, float Y, float Z) {
     const float r2 = X + Y + Z;
     const float e2 = fmaf(X, Y + Z, Y * Z);
@@ -39,9 +58,9 @@ __device__ __forceinline__ float far_field_q2(float X, float Y, float Z) {
     return rinv * fmaf(rho, fmaf(float(C2), x, float(C1)), float(C0));
 }
 
-// Far field from the squared offset components (all >= 0, not all 0).  FP64 keeps the
-// q = 4 term (|error| <= 6.6e-11 relative beyond the LDS radius); FP32 stops at q = 3,
-// whose error there (<= 4.8e-9) is already below FP32 rounding.
+// Far field from the squared quantised offset components (all >= 0, not all 0).  FP64
+// keeps the q = 4 term (|error| <= 6.6e-11 relative beyond the far-field gap); FP32 stops
+// at q = 3, whose error there (<= 4.8e-9) is already below FP32 rounding.
 template <typename Real>
 __device__ __forceinline__ Real far_field(Real X, Real Y, Real Z) {
     const Real r2 = X + Y + Z;
@@ -63,30 +82,89 @@ __device__ __forceinline__ Real far_field(Real X, Real Y, Real Z) {
     return rinv * B;
 }
 
-__device__ __forceinline__ uint32_t sorted_index(uint32_t a, uint32_t b, uint32_t c) {
-    const uint32_t lo = min(a, min(b, c));
-    const uint32_t hi = max(a, max(b, c));
-    const uint32_t mid = a + b + c - lo - hi;
-    return hi * (hi + 1) * (hi + 2) / 6 + ((mid * (mid + 1)) >> 1) + lo;
+// |a - b| of two non-negative coordinates in one instruction.  The second operand is a
+// wavefront-uniform value held in a scalar register (a source point of the unrolled loop).
+__device__ __forceinline__ uint32_t absdiff_s(uint32_t a, uint32_t b) {
+    uint32_t r;
+    asm("v_sad_u32 %0, %1, %2, 0" : "=v"(r) : "v"(a), "s"(b));
+    return r;
+}
+// ... with both operands per lane.
+__device__ __forceinline__ uint32_t absdiff_v(uint32_t a, uint32_t b) {
+    uint32_t r;
+    asm("v_sad_u32 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+    return r;
 }
 
-__device__ __forceinline__ uint64_t sorted_index64(uint64_t a, uint64_t b, uint64_t c) {
-    const uint64_t lo = min(a, min(b, c));
-    const uint64_t hi = max(a, max(b, c));
-    const uint64_t mid = a + b + c - lo - hi;
-    return hi * (hi + 1) * (hi + 2) / 6 + ((mid * (mid + 1)) >> 1) + lo;
+// Wavefront-uniform read-only loads through the constant address space: they stay scalar
+// loads (s_load) although the kernel also writes memory (partial sums, the work counter).
+template <typename T>
+__device__ __forceinline__ T ldu(const T* p, int64_t i) {
+    return ((const __attribute__((address_space(4))) T*)p)[i];
 }
 
-// Offsets reaching here satisfy max|d_i| <= the resident table radius whenever the far
-// field is off (the sum only pairs points of one bounding box; lgf_eval checks it).
+__device__ __forceinline__ uint32_t min3u(uint32_t a, uint32_t b, uint32_t c) { return min(a, min(b, c)); }
+__device__ __forceinline__ uint32_t max3u(uint32_t a, uint32_t b, uint32_t c) { return max(a, max(b, c)); }
+// The median in one instruction (written out: the compiler would share max(a, b) between
+// the median and the maximum and lose both three-operand forms).
+__device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// Index tables in LDS: tet[h] = sizeof(Real) tet(h), tri[m] = sizeof(Real) tri(m) (bytes).
 template <typename Real>
-__device__ __forceinline__ Real eval_pair(int dx, int dy, int dz, const Real* __restrict__ lds_tab,
-                                          const Real* __restrict__ full_tab, bool far_field_ok) {
-    const uint32_t a = (uint32_t)abs(dx), b = (uint32_t)abs(dy), c = (uint32_t)abs(dz);
-    const uint32_t m = max(a, max(b, c));
-    if (m <= (uint32_t)kNearR) return lds_tab[sorted_index(a, b, c)];
-    if (far_field_ok) return far_field<Real>(Real(a * a), Real(b * b), Real(c * c));
-    return full_tab[sorted_index64(a, b, c)];
+struct Lds {
+    Real* tab;            // table prefix, radius tab_r
+    uint32_t* tet;
+    uint32_t* tri;
+};
+
+// One LDS allocation, index arrays first: every LDS address the lookups form is then a
+// register plus a constant below 64 KB, which ds_read takes as its immediate offset.
+constexpr int kIdxN = (kMaxR + 4) / 4 * 4;          // index array length (>= kMaxR + 1, 16-byte multiple)
+template <typename Real>
+constexpr int lds_bytes() { return 2 * kIdxN * 4 + tab_entries<Real>() * (int)sizeof(Real); }
+template <typename Real>
+__device__ __forceinline__ Lds<Real> lds_layout(char* base) {
+    return Lds<Real>{(Real*)(base + 2 * kIdxN * 4), (uint32_t*)base, (uint32_t*)(base + kIdxN * 4)};
+}
+
+// Byte offset of G(d) in a sorted table from the quantised |d| components.
+template <typename Real>
+__device__ __forceinline__ uint32_t table_offset(const Lds<Real>& L, uint32_t a, uint32_t b, uint32_t c) {
+    const uint32_t lo = min3u(a, b, c), mid = med3u(a, b, c), hi = max3u(a, b, c);
+    const uint32_t th = *(const uint32_t*)((const char*)L.tet + hi);
+    const uint32_t tm = *(const uint32_t*)((const char*)L.tri + mid);
+    if constexpr (sizeof(Real) == 4) return th + tm + lo;
+    else return th + tm + 2u * lo;
+}
+
+template <typename Real>
+__device__ __forceinline__ Real lds_value(const Lds<Real>& L, uint32_t off) {
+    return *(const Real*)((const char*)L.tab + off);
+}
+template <typename Real>
+__device__ __forceinline__ Real global_value(const Real* __restrict__ full, uint32_t off) {
+    return *(const Real*)((const char*)full + off);
+}
+
+template <typename Real>
+__device__ __forceinline__ void fill_index(const Lds<Real>& L, int idx_r) {
+    for (int h = threadIdx.x; h <= idx_r; h += blockDim.x) {
+        const uint32_t u = (uint32_t)h;
+        L.tet[h] = (uint32_t)sizeof(Real) * (u * (u + 1) * (u + 2) / 6);
+        L.tri[h] = (uint32_t)sizeof(Real) * (u * (u + 1) / 2);
+    }
+}
+
+// Fill the LDS table prefix (radius tab_r) and the index arrays up to radius idx_r.
+template <typename Real>
+__device__ __forceinline__ void fill_lds(const Lds<Real>& L, const Real* __restrict__ src, int tab_r, int idx_r) {
+    const int n = (tab_r + 1) * (tab_r + 2) * (tab_r + 3) / 6;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) L.tab[i] = src[i];
+    fill_index<Real>(L, idx_r);
 }
 
 __device__ __forceinline__ int wave_min(int v) {
@@ -122,103 +200,119 @@ struct Acc<float> {
 
 template <typename Real>
 struct SumArgs {
-    const int32_t *tx, *ty, *tz;
+    const uint32_t *tx, *ty, *tz;     // quantised target coordinates
     int nt;
-    const int32_t *sx, *sy, *sz;
-    const Real *sxr, *syr, *szr;      // source coordinates in the kernel's precision
-    const int32_t* sbox;              // [nblk][6] source block bounding boxes
+    const uint32_t *sx, *sy, *sz;     // quantised source coordinates
+    const Real *sxr, *syr, *szr;      // the same in the kernel's precision
+    const int32_t* sbox;              // [nblk][6] quantised source block bounding boxes
     int ns, nblk, blk_per_chunk;
     const Real* w;
     int64_t ldw;
-    const Real* near_tab;
-    const Real* full_tab;
+    const Real* near_tab;             // table prefix staged in LDS (radius tab_r)
+    const Real* full_tab;             // full table (sigma > 0): radius full_r
+    int tab_r;                        // LDS table radius used (<= tab_radius<Real>())
+    int full_r;
     int far_ok;
     double* part;
     int64_t ldp;
 };
 
-// One thread per target.  Each wavefront walks the source blocks of its chunk and, from
-// the bounding boxes of its 64 targets and of the block, picks one of four loops
-// (a wavefront-uniform branch):
-//   far     every pair beyond the LDS radius, sigma = 0: far field in registers
+// One wavefront owns 64 consecutive (Morton-ordered) targets and walks the source blocks of
+// one chunk.  From the bounding boxes of its targets and of each block it picks one loop
+// with a wavefront-uniform branch (block_class):
+//   table   every pair within the LDS table radius
+//   far2    every pair beyond the q = 2 gap (FP32, sigma = 0): q = 2 expansion
+//   far     every pair beyond the far-field gap, sigma = 0: expansion in registers
 //   gather  every pair beyond the LDS radius, sigma > 0: the global table
-//   near    every pair within the LDS radius: LDS table
-//   mixed   per-pair choice
+//   mixed   per-pair choice between the LDS table and the far field / global table
 template <typename Real, int NR>
-__device__ __forceinline__ void sum_tile(const SumArgs<Real>& a, const Real* __restrict__ tab, int tile, int chunk) {
-    const int t = tile * kBlock + threadIdx.x;
+__device__ __forceinline__ void sum_tile(const SumArgs<Real>& a, const Lds<Real>& L, int tile, int chunk) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int t = tile * kWave + lane;
     const int tc = min(t, a.nt - 1);
-    const int ix = a.tx[tc], iy = a.ty[tc], iz = a.tz[tc];
+    const uint32_t ix = a.tx[tc], iy = a.ty[tc], iz = a.tz[tc];
     const Real fx = (Real)ix, fy = (Real)iy, fz = (Real)iz;
-    const int lx = wave_min(ix), ly = wave_min(iy), lz = wave_min(iz);
-    const int hx = wave_max(ix), hy = wave_max(iy), hz = wave_max(iz);
+    const int lx = wave_min((int)ix), ly = wave_min((int)iy), lz = wave_min((int)iz);
+    const int hx = wave_max((int)ix), hy = wave_max((int)iy), hz = wave_max((int)iz);
+    const uint32_t tab_q = (uint32_t)(kQuant * a.tab_r);
 
     const int b0 = chunk * a.blk_per_chunk;
     const int b1 = min(a.nblk, b0 + a.blk_per_chunk);
     Acc<Real> acc[NR];
     for (int b = b0; b < b1; ++b) {
         const int32_t* bb = a.sbox + 6 * b;
-        const int gap = max(max(max(bb[0] - hx, lx - bb[3]), max(bb[1] - hy, ly - bb[4])),
-                            max(max(bb[2] - hz, lz - bb[5]), 0));
-        const int span = max(max(max(bb[3] - lx, hx - bb[0]), max(bb[4] - ly, hy - bb[1])),
-                             max(bb[5] - lz, hz - bb[2]));
+        const int bx0 = ldu(bb, 0), by0 = ldu(bb, 1), bz0 = ldu(bb, 2), bx1 = ldu(bb, 3), by1 = ldu(bb, 4),
+                  bz1 = ldu(bb, 5);
+        const int gap = max(max(max(bx0 - hx, lx - bx1), max(by0 - hy, ly - by1)), max(max(bz0 - hz, lz - bz1), 0));
+        const int span = max(max(max(bx1 - lx, hx - bx0), max(by1 - ly, hy - by0)), max(bz1 - lz, hz - bz0));
+        const int cls = block_class(gap, span, a.tab_r, a.far_ok != 0, sizeof(Real) == 4);
         const int sb = b * kSourceBlock;        // blocks are full: the source arrays are padded
-        if (sizeof(Real) == 4 && gap > kFar2R && a.far_ok) {
-            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += kUnroll) {
+        if (cls == kClassTable) {
+            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += unroll<Real>()) {
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
+                for (int u = 0; u < unroll<Real>(); ++u) {
                     const int s = s0 + u;
-                    const float dx = (float)fx - (float)a.sxr[s], dy = (float)fy - (float)a.syr[s],
-                                dz = (float)fz - (float)a.szr[s];
-                    const Real G = (Real)far_field_q2(dx * dx, dy * dy, dz * dz);
+                    const uint32_t off =
+                        table_offset(L, absdiff_s(ix, ldu(a.sx, s)), absdiff_s(iy, ldu(a.sy, s)), absdiff_s(iz, ldu(a.sz, s)));
+                    const Real G = lds_value(L, off);
 #pragma unroll
-                    for (int r = 0; r < NR; ++r) acc[r].add(G * a.w[r * a.ldw + s]);
+                    for (int r = 0; r < NR; ++r) acc[r].add(G * ldu(a.w, r * a.ldw + s));
                 }
             }
-        } else if (gap > kNearR && a.far_ok) {
-            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += kUnroll) {
+        } else if (cls == kClassFar2) {
+            if constexpr (sizeof(Real) == 4) {
+                for (int s0 = sb; s0 < sb + kSourceBlock; s0 += unroll<Real>()) {
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
+                    for (int u = 0; u < unroll<Real>(); ++u) {
+                        const int s = s0 + u;
+                        const float dx = fx - ldu(a.sxr, s), dy = fy - ldu(a.syr, s), dz = fz - ldu(a.szr, s);
+                        const Real G = far_field_q2(dx * dx, dy * dy, dz * dz);
+#pragma unroll
+                        for (int r = 0; r < NR; ++r) acc[r].add(G * ldu(a.w, r * a.ldw + s));
+                    }
+                }
+            }
+        } else if (cls == kClassFar) {
+            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += unroll<Real>()) {
+#pragma unroll
+                for (int u = 0; u < unroll<Real>(); ++u) {
                     const int s = s0 + u;
-                    const Real dx = fx - a.sxr[s], dy = fy - a.syr[s], dz = fz - a.szr[s];
+                    const Real dx = fx - ldu(a.sxr, s), dy = fy - ldu(a.syr, s), dz = fz - ldu(a.szr, s);
                     const Real G = far_field<Real>(dx * dx, dy * dy, dz * dz);
 #pragma unroll
-                    for (int r = 0; r < NR; ++r) acc[r].add(G * a.w[r * a.ldw + s]);
+                    for (int r = 0; r < NR; ++r) acc[r].add(G * ldu(a.w, r * a.ldw + s));
                 }
             }
-        } else if (gap > kNearR) {
-            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += kUnroll) {
+        } else if (cls == kClassGather) {
+            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += unroll<Real>()) {
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
+                for (int u = 0; u < unroll<Real>(); ++u) {
                     const int s = s0 + u;
-                    const uint32_t da = (uint32_t)abs(ix - a.sx[s]), db = (uint32_t)abs(iy - a.sy[s]),
-                                   dc = (uint32_t)abs(iz - a.sz[s]);
-                    const Real G = a.full_tab[sorted_index64(da, db, dc)];
+                    const uint32_t off =
+                        table_offset(L, absdiff_s(ix, ldu(a.sx, s)), absdiff_s(iy, ldu(a.sy, s)), absdiff_s(iz, ldu(a.sz, s)));
+                    const Real G = global_value(a.full_tab, off);
 #pragma unroll
-                    for (int r = 0; r < NR; ++r) acc[r].add(G * a.w[r * a.ldw + s]);
-                }
-            }
-        } else if (span <= kNearR) {
-            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += kUnroll) {
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    const int s = s0 + u;
-                    const uint32_t da = (uint32_t)abs(ix - a.sx[s]), db = (uint32_t)abs(iy - a.sy[s]),
-                                   dc = (uint32_t)abs(iz - a.sz[s]);
-                    const Real G = tab[sorted_index(da, db, dc)];
-#pragma unroll
-                    for (int r = 0; r < NR; ++r) acc[r].add(G * a.w[r * a.ldw + s]);
+                    for (int r = 0; r < NR; ++r) acc[r].add(G * ldu(a.w, r * a.ldw + s));
                 }
             }
         } else {
-            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += kUnroll) {
+            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += unroll<Real>()) {
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
+                for (int u = 0; u < unroll<Real>(); ++u) {
                     const int s = s0 + u;
-                    const Real G = eval_pair<Real>(ix - a.sx[s], iy - a.sy[s], iz - a.sz[s], tab, a.full_tab,
-                                                   a.far_ok != 0);
+                    const uint32_t da = absdiff_s(ix, ldu(a.sx, s)), db = absdiff_s(iy, ldu(a.sy, s)),
+                                   dc = absdiff_s(iz, ldu(a.sz, s));
+                    Real G;
+                    if (max3u(da, db, dc) <= tab_q) {
+                        G = lds_value(L, table_offset(L, da, db, dc));
+                    } else if (a.far_ok) {
+                        const Real dx = fx - ldu(a.sxr, s), dy = fy - ldu(a.syr, s), dz = fz - ldu(a.szr, s);
+                        G = far_field<Real>(dx * dx, dy * dy, dz * dz);
+                    } else {
+                        G = global_value(a.full_tab, table_offset(L, da, db, dc));
+                    }
 #pragma unroll
-                    for (int r = 0; r < NR; ++r) acc[r].add(G * a.w[r * a.ldw + s]);
+                    for (int r = 0; r < NR; ++r) acc[r].add(G * ldu(a.w, r * a.ldw + s));
                 }
             }
         }

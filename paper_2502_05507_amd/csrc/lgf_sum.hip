@@ -7,9 +7,12 @@
 // sum with sources M+ and weights h^2 f gives the free-space volume potential u_p.
 //
 // Kernel evaluation per (target, source) pair, offset d = T - S, c = max |d_i|:
-//   c <= RN : LDS-resident 1/48-symmetric table, index of the sorted |d| triple
-//   c >  RN : sigma = 0 -> far-field expansion in registers (below);
+//   c <= RL : the LDS-resident prefix of the 1/48-symmetric table (RL = 55 in FP32, 44 in
+//             FP64: 123 / 130 KB of the 160 KB LDS of a gfx950 compute unit)
+//   c >  RL : sigma = 0 -> far-field expansion in registers (valid beyond 32, below);
 //             sigma > 0 -> the full FP64/FP32 table in global memory (L2 / MALL resident)
+// A table lookup costs about 8 VALU instructions per pair, the FP32 far field about 26,
+// so every block pair that fits the LDS table is evaluated from it.
 // Far field (sigma = 0): Sec. 2.2 q-term expansion in the positive sign convention,
 //   G_0(n) = (1/(4 pi |n|)) [1 + rho (1 - 5x)/4 + rho^2 P8/32 + rho^3 P12/128] + O(|n|^-9),
 //   rho = 1/|n|^2, x = e2 rho^2, y = e3 rho^3, e2 = j^2k^2 + k^2l^2 + l^2j^2, e3 = j^2k^2l^2,
@@ -20,16 +23,20 @@
 //         1/(6 - 2 sum cos) that yields the paper's terms; relative error 6.6e-11 at |n| = 32
 //         on the axis, the worst direction, and 2.5e-13 at 64).
 //
-// Layout and launch: targets and sources are in Morton order (SoA int32 x, y, z), so the
-// 64 targets of a wavefront form a compact patch and near/far branches are mostly uniform.
-// One thread owns one target; the source loop index is wavefront-uniform, so source
-// coordinates and weights come through scalar loads.  Sources come in Morton blocks of 64
-// with bounding boxes, so each wavefront classifies a whole block (all far, all near, or
-// mixed) with one uniform branch.  The grid is (target tiles) x (source chunks); each
-// block writes its partial sums, reduced later in a fixed order (deterministic results).
+// Layout and launch: targets and sources are in Morton order, so the 64 targets of a
+// wavefront form a compact patch.  One thread owns one target; the source index is
+// wavefront-uniform, so source coordinates and weights come through scalar loads.  Sources
+// come in Morton blocks of 64 with bounding boxes, so each wavefront classifies a whole
+// block with one uniform branch.  The grid is persistent: one 1024-thread workgroup per
+// compute unit stages the LDS table once, and its wavefronts take work items (64-target
+// tile, source chunk) -- first one each in a fixed assignment, then from an atomic counter
+// -- from a list ordered by decreasing estimated cost.  Each item writes its own partial
+// sums, reduced later in a fixed order, so results do not depend on the schedule.
 // FP32 pairs are summed in FP32 over each source block and the block sums folded into a
 // Neumaier-compensated FP32 accumulator.
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "lgf_device.hpp"
 #include "ops.hpp"
@@ -40,28 +47,72 @@ using namespace lgfdev;
 
 namespace {
 
-template <typename Real, int NR>
-__global__ __launch_bounds__(kBlock) void lgf_sum_kernel(const SumArgs<Real> a) {
-    __shared__ Real tab[kNearE];
-    for (int i = threadIdx.x; i < kNearE; i += kBlock) tab[i] = a.near_tab[i];
+struct Sched {
+    const uint32_t* items;
+    unsigned long long* counter;   // a type no input array has: its atomics cannot alias the
+                                   // inputs, whose uniform loads then stay scalar
+    uint32_t nitems;
+    int dynamic;           // nitems > number of wavefronts: the rest comes from the counter
+};
+
+// The work loop of one wavefront: item w (its index among all wavefronts of the grid),
+// then items W + counter while any are left.  The counter hands out exactly
+// (nitems - W) + W values; the wavefront that draws the last one resets it for the next
+// launch (every other wavefront has drawn its final value by then).
+template <typename F>
+__device__ __forceinline__ void for_each_item(const Sched& q, F&& body) {
+    const uint32_t lane = threadIdx.x & 63;
+    // both are uniform; saying so keeps the item, its loop bounds and the source loads in
+    // scalar registers
+    const uint32_t waves = __builtin_amdgcn_readfirstlane(gridDim.x * (blockDim.x >> 6));
+    const uint32_t w = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    if (w >= q.nitems) return;
+    uint32_t i = w;
+    for (;;) {
+        uint32_t nxt = 0;
+        if (q.dynamic && lane == 0)
+            nxt = (uint32_t)__hip_atomic_fetch_add(q.counter, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t it = ldu(q.items, i);
+        body(it & 0xFFFFFu, it >> 20);
+        if (!q.dynamic) return;
+        const uint32_t v = __builtin_amdgcn_readfirstlane(nxt);
+        if (v >= q.nitems - waves) {
+            if (v == q.nitems - 1 && lane == 0)
+                __hip_atomic_store(q.counter, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        i = waves + v;
+    }
+}
+
+template <typename Real, int NR, int THREADS>
+__global__ __launch_bounds__(THREADS) void lgf_sum_kernel(const SumArgs<Real> a, const Sched q) {
+    __shared__ __align__(16) char lds[lds_bytes<Real>()];
+    const Lds<Real> L = lds_layout<Real>(lds);
+    fill_lds(L, a.near_tab, a.tab_r, a.far_ok ? a.tab_r : a.full_r);
     __syncthreads();
-    sum_tile<Real, NR>(a, tab, blockIdx.x, blockIdx.y);
+    for_each_item(q, [&](uint32_t tile, uint32_t chunk) { sum_tile<Real, NR>(a, L, (int)tile, (int)chunk); });
 }
 
 template <typename Real>
-__global__ void lgf_eval_kernel(const int32_t* __restrict__ off, int64_t count, const Real* __restrict__ near_tab,
-                                const Real* __restrict__ full_tab, int full_r, int far_ok, double* __restrict__ out) {
+__global__ void lgf_eval_kernel(const int32_t* __restrict__ off, int64_t count, const Real* __restrict__ tab,
+                                int tab_r, int full_r, int far_ok, double* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    const int dx = off[3 * i], dy = off[3 * i + 1], dz = off[3 * i + 2];
-    const int m = max(abs(dx), max(abs(dy), abs(dz)));
+    const int64_t a = abs(off[3 * i]), b = abs(off[3 * i + 1]), c = abs(off[3 * i + 2]);
+    const int64_t m = max(a, max(b, c));
     if (m > full_r && !far_ok) {
         out[i] = __builtin_nan("");
         return;
     }
-    out[i] = (double)eval_pair<Real>(dx, dy, dz, near_tab, full_tab, far_ok != 0);
+    if (m > tab_r && far_ok) {
+        const Real X = Real(kQuant * a), Y = Real(kQuant * b), Z = Real(kQuant * c);
+        out[i] = (double)far_field<Real>(X * X, Y * Y, Z * Z);
+        return;
+    }
+    const int64_t lo = min(a, min(b, c)), hi = m, mid = a + b + c - lo - hi;
+    out[i] = (double)tab[hi * (hi + 1) * (hi + 2) / 6 + mid * (mid + 1) / 2 + lo];
 }
-
 
 // ------------------------------------------------------------------ 16-RHS blocked form on MFMA
 // For 16 right-hand sides the sum is the dense product V(T x 16) = K(T x S) W(S x 16), with
@@ -71,9 +122,8 @@ __global__ void lgf_eval_kernel(const int32_t* __restrict__ off, int64_t count, 
 // Operand layouts (16x16x4, measured on gfx950): A[i][k] in lane 16k + i, B[k][j] in lane
 // 16k + j; the result D[i][j] sits in lane 16v' + j, element v, with i = 4v' + v for f32
 // and i = v' + 4v for f64.
-// A wavefront owns kTiles tiles of 16 targets (64 targets, the same patch as the VALU
-// kernel, so the same near/far block classification applies); a workgroup of 4 wavefronts
-// stages each source block's 64 x 16 weights in LDS once for all of them.
+// A wavefront owns kTiles tiles of 16 targets (the 64 targets of one work item, so the
+// block classification is the VALU kernel's).
 constexpr int kTiles = 4;
 
 template <typename Real>
@@ -90,20 +140,15 @@ struct MfmaAcc<double> {
 };
 
 template <typename Real>
-__global__ __launch_bounds__(kBlock) void lgf_sum_mfma_kernel(const SumArgs<Real> a) {
+__device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real>& L, int tile, int chunk) {
     using V = typename MfmaAcc<Real>::V;
-    __shared__ Real tab[kNearE];
-    __shared__ Real wl[kSourceBlock][16];
-    for (int i = threadIdx.x; i < kNearE; i += kBlock) tab[i] = a.near_tab[i];
-
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
     const int row = lane & 15;            // A row (target within a tile) / B, D column (RHS)
     const int kq = lane >> 4;             // A column / B row (source within the step of 4)
-    const int base = (blockIdx.x * (kBlock / 64) + wave) * (16 * kTiles);
-    int ix[kTiles], iy[kTiles], iz[kTiles];
+    const int base = tile * kWave;
+    uint32_t ix[kTiles], iy[kTiles], iz[kTiles];
     Real fx[kTiles], fy[kTiles], fz[kTiles];
-    int lx = 1 << 30, ly = 1 << 30, lz = 1 << 30, hx = -(1 << 30), hy = -(1 << 30), hz = -(1 << 30);
+    int lx = 1 << 30, ly = 1 << 30, lz = 1 << 30, hx = 0, hy = 0, hz = 0;
 #pragma unroll
     for (int j = 0; j < kTiles; ++j) {
         const int tc = min(base + 16 * j + row, a.nt - 1);
@@ -113,12 +158,12 @@ __global__ __launch_bounds__(kBlock) void lgf_sum_mfma_kernel(const SumArgs<Real
         fx[j] = (Real)ix[j];
         fy[j] = (Real)iy[j];
         fz[j] = (Real)iz[j];
-        lx = min(lx, ix[j]);
-        ly = min(ly, iy[j]);
-        lz = min(lz, iz[j]);
-        hx = max(hx, ix[j]);
-        hy = max(hy, iy[j]);
-        hz = max(hz, iz[j]);
+        lx = min(lx, (int)ix[j]);
+        ly = min(ly, (int)iy[j]);
+        lz = min(lz, (int)iz[j]);
+        hx = max(hx, (int)ix[j]);
+        hy = max(hy, (int)iy[j]);
+        hz = max(hz, (int)iz[j]);
     }
     lx = wave_min(lx);
     ly = wave_min(ly);
@@ -126,37 +171,32 @@ __global__ __launch_bounds__(kBlock) void lgf_sum_mfma_kernel(const SumArgs<Real
     hx = wave_max(hx);
     hy = wave_max(hy);
     hz = wave_max(hz);
+    const uint32_t tab_q = (uint32_t)(kQuant * a.tab_r);
 
     V acc[kTiles], comp[kTiles];
 #pragma unroll
     for (int j = 0; j < kTiles; ++j)
         for (int v = 0; v < 4; ++v) acc[j][v] = comp[j][v] = Real(0);
 
-    const int b0 = blockIdx.y * a.blk_per_chunk;
+    const int b0 = chunk * a.blk_per_chunk;
     const int b1 = min(a.nblk, b0 + a.blk_per_chunk);
     for (int b = b0; b < b1; ++b) {
         const int sb = b * kSourceBlock;
-        __syncthreads();
-        for (int i = threadIdx.x; i < kSourceBlock * 16; i += kBlock) {
-            const int r = i / kSourceBlock, sl = i % kSourceBlock;
-            wl[sl][r] = a.w[r * a.ldw + sb + sl];
-        }
-        __syncthreads();
         const int32_t* bb = a.sbox + 6 * b;
         const int gap = max(max(max(bb[0] - hx, lx - bb[3]), max(bb[1] - hy, ly - bb[4])),
                             max(max(bb[2] - hz, lz - bb[5]), 0));
         const int span = max(max(max(bb[3] - lx, hx - bb[0]), max(bb[4] - ly, hy - bb[1])),
                              max(bb[5] - lz, hz - bb[2]));
-        const int mode = (gap > kNearR) ? (a.far_ok ? 0 : 1) : (span <= kNearR ? 2 : 3);
+        const int cls = block_class(gap, span, a.tab_r, a.far_ok != 0, sizeof(Real) == 4);
         V blk[kTiles];
 #pragma unroll
         for (int j = 0; j < kTiles; ++j)
             for (int v = 0; v < 4; ++v) blk[j][v] = Real(0);
         for (int st = 0; st < kSourceBlock; st += 4) {
             const int s = sb + st + kq;
-            const Real wb = wl[st + kq][row];
+            const Real wb = a.w[row * a.ldw + s];
             Real G[kTiles];
-            if (mode == 0) {
+            if (cls == kClassFar || cls == kClassFar2) {
                 const Real sx = a.sxr[s], sy = a.syr[s], sz = a.szr[s];
 #pragma unroll
                 for (int j = 0; j < kTiles; ++j) {
@@ -164,21 +204,30 @@ __global__ __launch_bounds__(kBlock) void lgf_sum_mfma_kernel(const SumArgs<Real
                     G[j] = far_field<Real>(dx * dx, dy * dy, dz * dz);
                 }
             } else {
-                const int sx = a.sx[s], sy = a.sy[s], sz = a.sz[s];
-                if (mode == 1) {
+                const uint32_t sx = a.sx[s], sy = a.sy[s], sz = a.sz[s];
+                if (cls == kClassTable) {
 #pragma unroll
                     for (int j = 0; j < kTiles; ++j)
-                        G[j] = a.full_tab[sorted_index64((uint32_t)abs(ix[j] - sx), (uint32_t)abs(iy[j] - sy),
-                                                         (uint32_t)abs(iz[j] - sz))];
-                } else if (mode == 2) {
+                        G[j] = lds_value(L, table_offset(L, absdiff_v(ix[j], sx), absdiff_v(iy[j], sy),
+                                                         absdiff_v(iz[j], sz)));
+                } else if (cls == kClassGather) {
 #pragma unroll
                     for (int j = 0; j < kTiles; ++j)
-                        G[j] = tab[sorted_index((uint32_t)abs(ix[j] - sx), (uint32_t)abs(iy[j] - sy),
-                                                (uint32_t)abs(iz[j] - sz))];
+                        G[j] = global_value(a.full_tab, table_offset(L, absdiff_v(ix[j], sx), absdiff_v(iy[j], sy),
+                                                                      absdiff_v(iz[j], sz)));
                 } else {
 #pragma unroll
-                    for (int j = 0; j < kTiles; ++j)
-                        G[j] = eval_pair<Real>(ix[j] - sx, iy[j] - sy, iz[j] - sz, tab, a.full_tab, a.far_ok != 0);
+                    for (int j = 0; j < kTiles; ++j) {
+                        const uint32_t da = absdiff_v(ix[j], sx), db = absdiff_v(iy[j], sy), dc = absdiff_v(iz[j], sz);
+                        if (max3u(da, db, dc) <= tab_q) {
+                            G[j] = lds_value(L, table_offset(L, da, db, dc));
+                        } else if (a.far_ok) {
+                            const Real dx = fx[j] - a.sxr[s], dy = fy[j] - a.syr[s], dz = fz[j] - a.szr[s];
+                            G[j] = far_field<Real>(dx * dx, dy * dy, dz * dz);
+                        } else {
+                            G[j] = global_value(a.full_tab, table_offset(L, da, db, dc));
+                        }
+                    }
                 }
             }
 #pragma unroll
@@ -205,9 +254,17 @@ __global__ __launch_bounds__(kBlock) void lgf_sum_mfma_kernel(const SumArgs<Real
             const int i = sizeof(Real) == 4 ? 4 * kq + v : kq + 4 * v;
             const int t = base + 16 * j + i;
             if (t < a.nt)
-                a.part[(int64_t)row * a.ldp + (int64_t)blockIdx.y * a.nt + t] =
-                    (double)acc[j][v] + (double)comp[j][v];
+                a.part[(int64_t)row * a.ldp + (int64_t)chunk * a.nt + t] = (double)acc[j][v] + (double)comp[j][v];
         }
+}
+
+template <typename Real, int THREADS>
+__global__ __launch_bounds__(THREADS) void lgf_sum_mfma_kernel(const SumArgs<Real> a, const Sched q) {
+    __shared__ __align__(16) char lds[lds_bytes<Real>()];
+    const Lds<Real> L = lds_layout<Real>(lds);
+    fill_lds(L, a.near_tab, a.tab_r, a.far_ok ? a.tab_r : a.full_r);
+    __syncthreads();
+    for_each_item(q, [&](uint32_t tile, uint32_t chunk) { mfma_tile<Real>(a, L, (int)tile, (int)chunk); });
 }
 
 template <typename Real>
@@ -221,9 +278,16 @@ const double* coord<double>(const PointSet& P, int axis) {
     return axis == 0 ? P.xd : axis == 1 ? P.yd : P.zd;
 }
 
+// Workgroup sizes: 16 wavefronts, except the FP64 4-RHS and matrix-core kernels, whose
+// accumulators need the registers of 8.
+template <typename Real>
+constexpr int mfma_threads() { return sizeof(Real) == 4 ? kSumThreads : kSumThreads / 2; }
+template <typename Real>
+constexpr int rhs4_threads() { return sizeof(Real) == 4 ? kSumThreads : kSumThreads / 2; }
+
 template <typename Real>
 void launch_all(const PointSet& T, const PointSet& S, const Real* w, int nrhs, const Real* near, const Real* full,
-                bool far, double* part, int chunks, hipStream_t st) {
+                int tab_r, int full_r, bool far, const SumPlan& plan, double* part, int grid, hipStream_t st) {
     SumArgs<Real> a;
     a.tx = T.x;
     a.ty = T.y;
@@ -238,62 +302,132 @@ void launch_all(const PointSet& T, const PointSet& S, const Real* w, int nrhs, c
     a.sbox = S.bbox;
     a.ns = (int)S.count;
     a.nblk = (int)S.nblk;
-    a.blk_per_chunk = (int)((S.nblk + chunks - 1) / chunks);
+    a.blk_per_chunk = plan.blk_per_chunk;
     a.ldw = S.padded;
     a.near_tab = near;
     a.full_tab = full;
+    a.tab_r = tab_r;
+    a.full_r = full_r;
     a.far_ok = far ? 1 : 0;
-    a.ldp = (int64_t)chunks * T.count;
-    const dim3 grid((unsigned)((T.count + kBlock - 1) / kBlock), (unsigned)chunks);
-    const int per_block = (kBlock / 64) * 16 * kTiles;
-    const dim3 grid_mfma((unsigned)((T.count + per_block - 1) / per_block), (unsigned)chunks);
+    a.ldp = (int64_t)plan.chunks * T.count;
     int r = 0;
     while (r < nrhs) {
         const int left = nrhs - r;
         SumArgs<Real> ar = a;
         ar.w = w + (int64_t)r * a.ldw;
         ar.part = part + (int64_t)r * a.ldp;
+        const int threads = left >= 16 ? mfma_threads<Real>() : left >= 4 ? rhs4_threads<Real>() : kSumThreads;
+        const uint32_t waves = (uint32_t)grid * (uint32_t)(threads / 64);
+        const Sched q{plan.items, plan.counter, (uint32_t)plan.nitems, plan.nitems > (int64_t)waves ? 1 : 0};
         if (left >= 16) {
-            lgf_sum_mfma_kernel<Real><<<grid_mfma, kBlock, 0, st>>>(ar);
+            lgf_sum_mfma_kernel<Real, mfma_threads<Real>()><<<grid, mfma_threads<Real>(), 0, st>>>(ar, q);
             r += 16;
         } else if (left >= 4) {
-            lgf_sum_kernel<Real, 4><<<grid, kBlock, 0, st>>>(ar);
+            lgf_sum_kernel<Real, 4, rhs4_threads<Real>()><<<grid, rhs4_threads<Real>(), 0, st>>>(ar, q);
             r += 4;
         } else {
-            lgf_sum_kernel<Real, 1><<<grid, kBlock, 0, st>>>(ar);
+            lgf_sum_kernel<Real, 1, kSumThreads><<<grid, kSumThreads, 0, st>>>(ar, q);
             r += 1;
         }
         BAE_HIP_CHECK(hipGetLastError());
     }
 }
 
+// Estimated VALU cost per pair of each block class (FP32 instruction counts; the gather
+// and mixed classes are charged for their memory and divergence).
+constexpr double kClassCost[5] = {8.0, 26.0, 19.0, 40.0, 45.0};
+
 }  // namespace
 
-int lgf_near_radius() { return kNearR; }
-int lgf_far2_gap() { return kFar2R; }
+int lgf_sum_chunks(int64_t nt, int64_t nblk) {
+    const int64_t tiles = (nt + kWave - 1) / kWave;
+    // about 8 items per wavefront of a full MI355X (256 CUs x 16 wavefronts)
+    int64_t chunks = (8 * 4096 + tiles - 1) / tiles;
+    chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, nblk / 2));   // at least 2 blocks per item
+    return (int)std::max<int64_t>(1, std::min<int64_t>(chunks, kMaxChunks));
+}
 
-int lgf_sum_chunks(int64_t nt, int64_t ns) {
-    const int64_t tiles = (nt + kBlock - 1) / kBlock;
-    int64_t chunks = (2048 + tiles - 1) / tiles;           // aim at >= 2048 blocks
-    chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, ns / (8 * kSourceBlock)));
-    return (int)std::max<int64_t>(1, std::min<int64_t>(chunks, 64));
+int lgf_sum_grid(int device) {
+    static std::mutex mu;
+    static std::map<int, int> cus;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cus.find(device);
+    if (it != cus.end()) return it->second;
+    int n = 0;
+    BAE_HIP_CHECK(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device));
+    n = std::max(1, n);
+    cus[device] = n;
+    return n;
+}
+
+void plan_sum(const PointSet& T, const PointSet& S, const SumTables& tabs, SumPlan& plan,
+              std::vector<uint32_t>& host_items) {
+    const int64_t nt = T.count, tiles = (nt + kWave - 1) / kWave, nblk = S.nblk;
+    int chunks = lgf_sum_chunks(nt, nblk);
+    const int bpc = (int)((nblk + chunks - 1) / std::max(1, chunks));
+    chunks = (int)((nblk + bpc - 1) / std::max(1, bpc));
+    plan.chunks = std::max(1, chunks);
+    plan.blk_per_chunk = std::max(1, bpc);
+    plan.nitems = tiles * plan.chunks;
+    if (tiles > (1 << 20) || plan.chunks > 4095) throw Error{BAE_ERR_ARG, "LGF sum too large for the work list"};
+    for (auto& r : plan.class_pairs)
+        for (auto& v : r) v = 0;
+    host_items.resize(plan.nitems);
+    std::vector<double> cost(plan.nitems, 0.0);
+    const bool classify = tiles * nblk <= (int64_t)60000000;
+    if (classify) {
+        for (int64_t tl = 0; tl < tiles; ++tl) {
+            int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {0, 0, 0};
+            for (int64_t i = tl * kWave; i < (tl + 1) * kWave; ++i) {
+                const int64_t t = std::min(i, nt - 1);
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = std::min(lo[a], T.hq[3 * t + a]);
+                    hi[a] = std::max(hi[a], T.hq[3 * t + a]);
+                }
+            }
+            const int64_t tcount = std::min<int64_t>(kWave, nt - tl * kWave);
+            for (int64_t b = 0; b < nblk; ++b) {
+                const int32_t* bb = &S.hbox[6 * b];
+                int gap = 0, span = 0;
+                for (int a = 0; a < 3; ++a) {
+                    gap = std::max(gap, std::max(bb[a] - hi[a], lo[a] - bb[3 + a]));
+                    span = std::max(span, std::max(bb[3 + a] - lo[a], hi[a] - bb[a]));
+                }
+                const int64_t pairs = tcount * std::min<int64_t>(kSourceBlock, S.count - b * kSourceBlock);
+                const int c32 = block_class(gap, span, tabs.tab_r32, tabs.far_field, true);
+                const int c64 = block_class(gap, span, tabs.tab_r64, tabs.far_field, false);
+                plan.class_pairs[1][c32] += pairs;
+                plan.class_pairs[0][c64] += pairs;
+                cost[tl * plan.chunks + b / plan.blk_per_chunk] += kClassCost[c32] * (double)pairs;
+            }
+        }
+    }
+    // items (tile, chunk) ordered by decreasing cost (stable: natural order when unclassified)
+    std::vector<int64_t> order(plan.nitems);
+    for (int64_t i = 0; i < plan.nitems; ++i) order[i] = i;
+    if (classify) std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return cost[x] > cost[y]; });
+    for (int64_t i = 0; i < plan.nitems; ++i) {
+        const int64_t tl = order[i] / plan.chunks, ch = order[i] % plan.chunks;
+        host_items[i] = (uint32_t)tl | ((uint32_t)ch << 20);
+    }
 }
 
 int lgf_sum_launch(const PointSet& T, const PointSet& S, const void* w, int nrhs, int prec, const SumTables& tabs,
-                   double* part, int64_t part_capacity, hipStream_t st) {
+                   const SumPlan& plan, double* part, int64_t part_capacity, int grid, hipStream_t st) {
     if (T.count == 0) return 0;
-    int chunks = lgf_sum_chunks(T.count, S.count);
-    while (chunks > 1 && (int64_t)chunks * T.count * nrhs > part_capacity) --chunks;
+    const int chunks = plan.chunks;
     if ((int64_t)chunks * T.count * nrhs > part_capacity) throw Error{BAE_ERR_ARG, "partial-sum buffer too small"};
-    if (tabs.full_r < kNearR) throw Error{BAE_ERR_ARG, "resident table radius below the LDS radius"};
+    if (tabs.full_r > kMaxR) throw Error{BAE_ERR_ARG, "table radius beyond the index arrays"};
     if (S.count == 0) {
         launch_fill(part, (int64_t)chunks * T.count * nrhs, 0.0, st);
         return chunks;
     }
     if (prec == BAE_PREC_FP64)
-        launch_all<double>(T, S, (const double*)w, nrhs, tabs.near64, tabs.full64, tabs.far_field, part, chunks, st);
+        launch_all<double>(T, S, (const double*)w, nrhs, tabs.near64, tabs.full64, tabs.tab_r64, tabs.full_r,
+                           tabs.far_field, plan, part, grid, st);
     else
-        launch_all<float>(T, S, (const float*)w, nrhs, tabs.near32, tabs.full32, tabs.far_field, part, chunks, st);
+        launch_all<float>(T, S, (const float*)w, nrhs, tabs.near32, tabs.full32, tabs.tab_r32, tabs.full_r,
+                          tabs.far_field, plan, part, grid, st);
     return chunks;
 }
 
@@ -301,10 +435,10 @@ void lgf_eval_launch(const int32_t* off, int64_t count, double* out, int prec, c
     if (count == 0) return;
     const unsigned blocks = (unsigned)((count + 255) / 256);
     if (prec == BAE_PREC_FP64)
-        lgf_eval_kernel<double><<<blocks, 256, 0, st>>>(off, count, tabs.near64, tabs.full64, tabs.full_r,
+        lgf_eval_kernel<double><<<blocks, 256, 0, st>>>(off, count, tabs.full64, tabs.tab_r64, tabs.full_r,
                                                         tabs.far_field ? 1 : 0, out);
     else
-        lgf_eval_kernel<float><<<blocks, 256, 0, st>>>(off, count, tabs.near32, tabs.full32, tabs.full_r,
+        lgf_eval_kernel<float><<<blocks, 256, 0, st>>>(off, count, tabs.full32, tabs.tab_r32, tabs.full_r,
                                                        tabs.far_field ? 1 : 0, out);
     BAE_HIP_CHECK(hipGetLastError());
 }

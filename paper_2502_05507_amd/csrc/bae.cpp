@@ -83,7 +83,7 @@ static void bae_operator(bae_ctx* c, const double* q, int64_t ldq, double* aq, i
     launch_weights(c->B, q, ldq, c->w.p, c->S.ps.padded, nrhs, prec, st);
     int chunks = 0;
     apply_lgf(c, c->T.ps, c->S.ps, c->w.p, nrhs, prec, c->part.as<double>(), c->part_cap, &chunks, st);
-    launch_closure(c->part.as<double>(), chunks, c->nT, c->cl, aq, lda, nrhs, st);
+    launch_closure(c->part.as<double>(), chunks, c->nT, c->cl, aq, lda, nrhs, c->vsum.as<double>(), st);
 }
 
 static void norms2(bae_ctx* c, const double* v, int64_t ldv, int nrhs, double* out_dev, hipStream_t st) {
@@ -261,10 +261,8 @@ bae_ctx* create_context(const bae_grid& gridv, const bae_options* opt, Geometry&
         if (c->max_rhs > 64) throw Error{BAE_ERR_ARG, "max_rhs must be <= 64"};
         const int m = c->opt.max_krylov > 0 ? c->opt.max_krylov : 400;
         if (m > 4096) throw Error{BAE_ERR_ARG, "max_krylov must be <= 4096"};
-        if ((c->opt.near_radius_fp64 && c->opt.near_radius_fp64 != kLdsRadius64) ||
-            (c->opt.near_radius_fp32 && c->opt.near_radius_fp32 != kLdsRadius32))
-            throw Error{BAE_ERR_ARG, "near radius: this build supports " + std::to_string(kLdsRadius64) + " (FP64) and " +
-                                         std::to_string(kLdsRadius32) + " (FP32) only"};
+        if (c->opt.near_radius_fp64 || c->opt.near_radius_fp32)
+            throw Error{BAE_ERR_ARG, "near radius: fixed by the kernels' LDS layout, pass 0"};
         c->device = c->opt.device;
         int ndev = 0;
         BAE_HIP_CHECK(hipGetDeviceCount(&ndev));
@@ -333,7 +331,7 @@ bae_ctx* create_context(const bae_grid& gridv, const bae_options* opt, Geometry&
         // (the far field takes over beyond it), else every offset that occurs.  The LDS
         // prefix covers the offsets that occur, but at least the far-field gap, beyond which
         // the expansion is accurate.
-        const int R = c->s == 0.0 ? kLdsRadius32 : std::max(G.max_offset, 1);
+        const int R = c->s == 0.0 ? kLdsRadiusFar32 : std::max(G.max_offset, 1);
         c->table = get_table(c->device, c->s, R, st);
         c->tabs.near64 = c->table->d64.as<double>();
         c->tabs.near32 = c->table->d32.as<float>();
@@ -341,8 +339,9 @@ bae_ctx* create_context(const bae_grid& gridv, const bae_options* opt, Geometry&
         c->tabs.full32 = c->table->d32.as<float>();
         c->tabs.full_r = c->table->R;
         const int need = std::max(G.max_offset, kFarGap);
-        c->tabs.tab_r64 = std::min({kLdsRadius64, c->tabs.full_r, need});
-        c->tabs.tab_r32 = std::min({kLdsRadius32, c->tabs.full_r, need});
+        const bool far = c->s == 0.0;
+        c->tabs.tab_r64 = std::min({far ? kLdsRadiusFar64 : kLdsRadius64, c->tabs.full_r, need});
+        c->tabs.tab_r32 = std::min({far ? kLdsRadiusFar32 : kLdsRadius32, c->tabs.full_r, need});
         c->tabs.far_field = c->s == 0.0;
         c->sum_grid = lgf_sum_grid(c->device);
         c->plan.build(c->T.ps, c->S.ps, c->tabs, st);
@@ -384,6 +383,7 @@ bae_ctx* create_context(const bae_grid& gridv, const bae_options* opt, Geometry&
         for (DevMem* d : {&c->b, &c->x, &c->r, &c->tmp}) d->alloc(sizeof(double) * n * mr);
         c->up_gamma.alloc(sizeof(double) * c->nT * mr);
         c->u_gamma.alloc(sizeof(double) * c->nT * mr);
+        c->vsum.alloc(sizeof(double) * c->nT * mr);
         BAE_HIP_CHECK(hipHostMalloc((void**)&c->pinned_flags, sizeof(int32_t) * 2 * mr, hipHostMallocDefault));
         // batched / served solves: idle until started (done = 1, k = 0)
         c->ctl.alloc(sizeof(Ctl));
@@ -410,6 +410,7 @@ int64_t estimate_context_bytes(const Geometry& G, double s, const bae_options* o
     b += padded(nS) * 8 * mr;                                                          // weights
     b += (int64_t)lgf_sum_chunks(nT, (nS + kSourceBlock - 1) / kSourceBlock) * nT * mr * 8;   // partial sums
     b += ((nT + 63) / 64) * kMaxChunks * 4;                                               // work list
+    b += nT * mr * 8;                                                                     // reduced sums
     b += ((int64_t)(m + 1) * ngm + (int64_t)m * (m + 1) + 4 * m + 8) * 8 * mr;        // Krylov state
     b += (int64_t)(m + 1) * mr * 8 * (3 + dot_blocks(ngm)) + (int64_t)m * mr * 8;      // CGS, dots, y
     b += 4 * ngm * mr * 8 + 2 * nT * mr * 8;                                           // b, x, r, tmp, u_p, u_gamma
@@ -491,7 +492,7 @@ int bae_get_sizes(const bae_ctx* c, bae_sizes* o) {
                                 &c->t_pos, &c->csr_rowptr, &c->csr_col, &c->csr_coef, &c->cl_tq, &c->cl_tp, &c->cl_t,
                                 &c->w, &c->part, &c->kV, &c->kH, &c->kcs, &c->ksn, &c->kg, &c->khist, &c->kbeta,
                                 &c->kdone, &c->kkdone, &c->hA, &c->hB, &c->nrm, &c->dotpart, &c->ycoef, &c->b, &c->x,
-                                &c->r, &c->tmp, &c->up_gamma, &c->u_gamma, &c->wf, &c->plan.items,
+                                &c->r, &c->tmp, &c->up_gamma, &c->u_gamma, &c->vsum, &c->wf, &c->plan.items,
                                 &c->plan.counter})
             bytes += d->bytes;
         o->device_bytes = (int64_t)bytes;

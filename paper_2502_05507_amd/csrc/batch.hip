@@ -99,8 +99,8 @@ __global__ void b_weights(const BProb* __restrict__ P, const int64_t* __restrict
 template <typename Real>
 __global__ __launch_bounds__(kSumThreads) void b_lgf_sum(const BProb* __restrict__ P, const Item* __restrict__ items,
                                                          int nitems, int use_done, const int32_t* __restrict__ sel) {
-    __shared__ __align__(16) char lds[lds_bytes<Real>()];
-    const Lds<Real> L = lds_layout<Real>(lds);
+    __shared__ __align__(16) char lds[lds_bytes<Real, false>()];
+    const Lds<Real> L = lds_layout<Real, false>(lds);
     fill_index<Real>(L, kMaxR);
     const Real* cur = nullptr;
     int cur_r = -1;
@@ -521,10 +521,10 @@ void build_layout(BatchEngine* b) {
         };
         fill(q.s64, c->tabs.near64, c->tabs.full64, c->S.ps.xd, c->S.ps.yd, c->S.ps.zd);
         q.s64.w = (const double*)c->w.p;
-        q.s64.tab_r = c->tabs.tab_r64;
+        q.s64.tab_r = std::min(c->tabs.tab_r64, kLdsRadius64);   // this kernel's LDS holds the general layout
         fill(q.s32, c->tabs.near32, c->tabs.full32, c->S.ps.xf, c->S.ps.yf, c->S.ps.zf);
         q.s32.w = (const float*)c->w.p;
-        q.s32.tab_r = c->tabs.tab_r32;
+        q.s32.tab_r = std::min(c->tabs.tab_r32, kLdsRadius32);
     }
     b->nslices_total = (int)sl.size();
     b->nitems = (int)it.size();

@@ -174,6 +174,7 @@ struct bae_ctx {
     DevMem b, x, r, tmp;       // [rhs][ngm]
     DevMem up_gamma;           // [rhs][nT] external order
     DevMem u_gamma;            // [rhs][nT]
+    DevMem vsum;               // [rhs][nT] chunk-reduced sums (operator scratch)
     DevMem wf;                 // [rhs][|M+|] h^2 f in Mp order
     DevMem ctl;                // Ctl of RHS 0 for batched / served solves
     int nrhs = 0;

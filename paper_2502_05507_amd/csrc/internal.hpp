@@ -56,8 +56,10 @@ void lgf_table_generate(double s, int R, double* out, hipStream_t stream);
 // touching its points.  Device coordinates are quantised: kQuant x the lattice index.
 constexpr int kSourceBlock = 64;
 constexpr int kQuant = 4;
-constexpr int kLdsRadius32 = 55;          // LDS table radius of the FP32 sum (123 KB)
-constexpr int kLdsRadius64 = 44;          // ... of the FP64 sum (130 KB)
+constexpr int kLdsRadiusFar32 = 59;       // LDS table radius of the FP32 sum, sigma = 0 (151 KB)
+constexpr int kLdsRadiusFar64 = 46;       // ... of the FP64 sum, sigma = 0 (147 KB)
+constexpr int kLdsRadius32 = 55;          // ... FP32, sigma > 0 and batched sums (123 KB + index arrays)
+constexpr int kLdsRadius64 = 44;          // ... FP64, sigma > 0 and batched sums (130 KB + index arrays)
 constexpr int kMaxTableRadius = 1200;     // largest resident table (sigma > 0)
 constexpr int kFarGap = 32;               // far field used beyond this gap (sigma = 0)
 constexpr int kFar2Gap = 64;              // FP32: q = 2 far field beyond this gap

@@ -22,10 +22,17 @@ template <typename Real>
 constexpr int unroll() { return 32 / (int)sizeof(Real); }   // sources per unrolled step (32-byte scalar loads)
 constexpr int kMaxR = kMaxTableRadius;               // largest table radius (tet / tri arrays)
 
-template <typename Real>
-constexpr int tab_radius() { return sizeof(Real) == 4 ? kLdsRadius32 : kLdsRadius64; }
-template <typename Real>
-constexpr int tab_entries() { return (tab_radius<Real>() + 1) * (tab_radius<Real>() + 2) * (tab_radius<Real>() + 3) / 6; }
+// LDS layouts.  FAR (sigma = 0, far field beyond the table): the index arrays only need the
+// table radius, leaving room for a larger table.  Otherwise (sigma > 0) they span every
+// offset of the global table.
+template <typename Real, bool FAR>
+constexpr int tab_radius() {
+    return sizeof(Real) == 4 ? (FAR ? kLdsRadiusFar32 : kLdsRadius32) : (FAR ? kLdsRadiusFar64 : kLdsRadius64);
+}
+template <typename Real, bool FAR>
+constexpr int tab_entries() {
+    return (tab_radius<Real, FAR>() + 1) * (tab_radius<Real, FAR>() + 2) * (tab_radius<Real, FAR>() + 3) / 6;
+}
 
 constexpr double kPi = 3.14159265358979323846;
 // Far-field coefficients for the quantised offset D = kQuant d (so |D| = 4|n|): with
@@ -123,12 +130,17 @@ struct Lds {
 
 // One LDS allocation, index arrays first: every LDS address the lookups form is then a
 // register plus a constant below 64 KB, which ds_read takes as its immediate offset.
-constexpr int kIdxN = (kMaxR + 4) / 4 * 4;          // index array length (>= kMaxR + 1, 16-byte multiple)
-template <typename Real>
-constexpr int lds_bytes() { return 2 * kIdxN * 4 + tab_entries<Real>() * (int)sizeof(Real); }
-template <typename Real>
+template <typename Real, bool FAR>
+constexpr int idx_len() {   // index array length: > the largest radius indexed, 16-byte multiple
+    return ((FAR ? tab_radius<Real, FAR>() : kMaxR) + 4) / 4 * 4;
+}
+template <typename Real, bool FAR>
+constexpr int lds_bytes() { return 2 * idx_len<Real, FAR>() * 4 + tab_entries<Real, FAR>() * (int)sizeof(Real); }
+template <typename Real, bool FAR>
 __device__ __forceinline__ Lds<Real> lds_layout(char* base) {
-    return Lds<Real>{(Real*)(base + 2 * kIdxN * 4), (uint32_t*)base, (uint32_t*)(base + kIdxN * 4)};
+    constexpr int n = idx_len<Real, FAR>();
+    static_assert(lds_bytes<Real, FAR>() <= 160 * 1024, "LDS of one gfx950 compute unit");
+    return Lds<Real>{(Real*)(base + 2 * n * 4), (uint32_t*)base, (uint32_t*)(base + n * 4)};
 }
 
 // Byte offset of G(d) in a sorted table from the quantised |d| components.
@@ -210,7 +222,7 @@ struct SumArgs {
     int64_t ldw;
     const Real* near_tab;             // table prefix staged in LDS (radius tab_r)
     const Real* full_tab;             // full table (sigma > 0): radius full_r
-    int tab_r;                        // LDS table radius used (<= tab_radius<Real>())
+    int tab_r;                        // LDS table radius used (<= the kernel's tab_radius)
     int full_r;
     int far_ok;
     double* part;

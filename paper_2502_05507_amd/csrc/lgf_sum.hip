@@ -7,8 +7,9 @@
 // sum with sources M+ and weights h^2 f gives the free-space volume potential u_p.
 //
 // Kernel evaluation per (target, source) pair, offset d = T - S, c = max |d_i|:
-//   c <= RL : the LDS-resident prefix of the 1/48-symmetric table (RL = 55 in FP32, 44 in
-//             FP64: 123 / 130 KB of the 160 KB LDS of a gfx950 compute unit)
+//   c <= RL : the LDS-resident prefix of the 1/48-symmetric table (sigma = 0: RL = 59 in
+//             FP32, 46 in FP64, 151 / 147 KB of the 160 KB LDS of a gfx950 compute unit;
+//             sigma > 0: 55 / 44, next to the index arrays that span the global table)
 //   c >  RL : sigma = 0 -> far-field expansion in registers (valid beyond 32, below);
 //             sigma > 0 -> the full FP64/FP32 table in global memory (L2 / MALL resident)
 // A table lookup costs about 8 VALU instructions per pair, the FP32 far field about 26,
@@ -85,11 +86,11 @@ __device__ __forceinline__ void for_each_item(const Sched& q, F&& body) {
     }
 }
 
-template <typename Real, int NR, int THREADS>
+template <typename Real, int NR, int THREADS, bool FAR>
 __global__ __launch_bounds__(THREADS) void lgf_sum_kernel(const SumArgs<Real> a, const Sched q) {
-    __shared__ __align__(16) char lds[lds_bytes<Real>()];
-    const Lds<Real> L = lds_layout<Real>(lds);
-    fill_lds(L, a.near_tab, a.tab_r, a.far_ok ? a.tab_r : a.full_r);
+    __shared__ __align__(16) char lds[lds_bytes<Real, FAR>()];
+    const Lds<Real> L = lds_layout<Real, FAR>(lds);
+    fill_lds(L, a.near_tab, a.tab_r, FAR ? a.tab_r : a.full_r);
     __syncthreads();
     for_each_item(q, [&](uint32_t tile, uint32_t chunk) { sum_tile<Real, NR>(a, L, (int)tile, (int)chunk); });
 }
@@ -258,11 +259,11 @@ __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real
         }
 }
 
-template <typename Real, int THREADS>
+template <typename Real, int THREADS, bool FAR>
 __global__ __launch_bounds__(THREADS) void lgf_sum_mfma_kernel(const SumArgs<Real> a, const Sched q) {
-    __shared__ __align__(16) char lds[lds_bytes<Real>()];
-    const Lds<Real> L = lds_layout<Real>(lds);
-    fill_lds(L, a.near_tab, a.tab_r, a.far_ok ? a.tab_r : a.full_r);
+    __shared__ __align__(16) char lds[lds_bytes<Real, FAR>()];
+    const Lds<Real> L = lds_layout<Real, FAR>(lds);
+    fill_lds(L, a.near_tab, a.tab_r, FAR ? a.tab_r : a.full_r);
     __syncthreads();
     for_each_item(q, [&](uint32_t tile, uint32_t chunk) { mfma_tile<Real>(a, L, (int)tile, (int)chunk); });
 }
@@ -320,13 +321,16 @@ void launch_all(const PointSet& T, const PointSet& S, const Real* w, int nrhs, c
         const uint32_t waves = (uint32_t)grid * (uint32_t)(threads / 64);
         const Sched q{plan.items, plan.counter, (uint32_t)plan.nitems, plan.nitems > (int64_t)waves ? 1 : 0};
         if (left >= 16) {
-            lgf_sum_mfma_kernel<Real, mfma_threads<Real>()><<<grid, mfma_threads<Real>(), 0, st>>>(ar, q);
+            if (far) lgf_sum_mfma_kernel<Real, mfma_threads<Real>(), true><<<grid, mfma_threads<Real>(), 0, st>>>(ar, q);
+            else lgf_sum_mfma_kernel<Real, mfma_threads<Real>(), false><<<grid, mfma_threads<Real>(), 0, st>>>(ar, q);
             r += 16;
         } else if (left >= 4) {
-            lgf_sum_kernel<Real, 4, rhs4_threads<Real>()><<<grid, rhs4_threads<Real>(), 0, st>>>(ar, q);
+            if (far) lgf_sum_kernel<Real, 4, rhs4_threads<Real>(), true><<<grid, rhs4_threads<Real>(), 0, st>>>(ar, q);
+            else lgf_sum_kernel<Real, 4, rhs4_threads<Real>(), false><<<grid, rhs4_threads<Real>(), 0, st>>>(ar, q);
             r += 4;
         } else {
-            lgf_sum_kernel<Real, 1, kSumThreads><<<grid, kSumThreads, 0, st>>>(ar, q);
+            if (far) lgf_sum_kernel<Real, 1, kSumThreads, true><<<grid, kSumThreads, 0, st>>>(ar, q);
+            else lgf_sum_kernel<Real, 1, kSumThreads, false><<<grid, kSumThreads, 0, st>>>(ar, q);
             r += 1;
         }
         BAE_HIP_CHECK(hipGetLastError());

@@ -30,35 +30,36 @@ __global__ void weights_kernel(const int32_t* __restrict__ rowptr, const int32_t
 }
 
 // out[r][pos[t]] = scale * sum_c part[r][c][t]  (+ add[r][pos[t]] when add != null)
-__global__ void reduce_scatter_kernel(const double* __restrict__ part, int chunks, int64_t nt, int64_t ldp,
-                                      const int32_t* __restrict__ pos, double* __restrict__ out, int64_t ldo,
-                                      double scale) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// out[r][pos(t)] = scale * sum over chunks of part[r][c][t].  A block covers 64 targets
+// with 4 chunk lanes (chunk c goes to lane c mod 4; every load is a coalesced 512-byte row),
+// the lane sums combined in a fixed order, so results do not vary between runs.
+__global__ __launch_bounds__(256) void reduce_chunks_kernel(const double* __restrict__ part, int chunks, int64_t nt,
+                                                            int64_t ldp, const int32_t* __restrict__ pos,
+                                                            double* __restrict__ out, int64_t ldo, double scale) {
+    __shared__ double sh[4][64];
+    const int tl = threadIdx.x & 63, cl = threadIdx.x >> 6;
+    const int64_t t = (int64_t)blockIdx.x * 64 + tl;
     const int r = blockIdx.y;
-    if (t >= nt) return;
-    const double* p = part + r * ldp + t;
     double acc = 0.0;
-    for (int c = 0; c < chunks; ++c) acc += p[(int64_t)c * nt];
-    out[r * ldo + (pos ? pos[t] : t)] = scale * acc;
+    if (t < nt) {
+        const double* p = part + r * ldp + t;
+        for (int c = cl; c < chunks; c += 4) acc += p[(int64_t)c * nt];
+    }
+    sh[cl][tl] = acc;
+    __syncthreads();
+    if (cl == 0 && t < nt) out[r * ldo + (pos ? pos[t] : t)] = scale * (((sh[0][tl] + sh[1][tl]) + sh[2][tl]) + sh[3][tl]);
 }
 
-// aq[r][i] = (1 - t_i) v(q_i) + t_i v(p_i), v = sum over chunks of the partial sums at the
-// internal target indices of q_i and of its partner p_i (Sec. 2.1 eq. "bc", hat functions).
-__global__ void closure_kernel(const double* __restrict__ part, int chunks, int64_t nt, int64_t ldp,
-                               const int32_t* __restrict__ tq, const int32_t* __restrict__ tp,
-                               const double* __restrict__ tw, int64_t n, double* __restrict__ aq, int64_t lda) {
+// aq[r][i] = (1 - t_i) v(q_i) + t_i v(p_i), v the reduced sum at the internal target indices
+// of q_i and of its partner p_i (Sec. 2.1 eq. "bc", hat functions).
+__global__ void closure_kernel(const double* __restrict__ v, int64_t ldv, const int32_t* __restrict__ tq,
+                               const int32_t* __restrict__ tp, const double* __restrict__ tw, int64_t n,
+                               double* __restrict__ aq, int64_t lda) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
     if (i >= n) return;
-    const double* p = part + r * ldp;
-    const int64_t a = tq[i], b = tp[i];
-    double va = 0.0, vb = 0.0;
-    for (int c = 0; c < chunks; ++c) {
-        va += p[(int64_t)c * nt + a];
-        vb += p[(int64_t)c * nt + b];
-    }
     const double t = tw[i];
-    aq[r * lda + i] = (1.0 - t) * va + t * vb;
+    aq[r * lda + i] = (1.0 - t) * v[r * ldv + tq[i]] + t * v[r * ldv + tp[i]];
 }
 
 __device__ inline double block_sum(double v, double* sh) {
@@ -252,17 +253,17 @@ void launch_weights(const CSR& B, const double* q, int64_t ldq, void* w, int64_t
 void launch_reduce_scatter(const double* part, int chunks, int64_t nt, const int32_t* pos, double* out, int64_t ldo,
                            int nrhs, double scale, hipStream_t st) {
     if (nt == 0) return;
-    dim3 grid(blocks_for(nt), nrhs);
-    reduce_scatter_kernel<<<grid, kThreads, 0, st>>>(part, chunks, nt, (int64_t)chunks * nt, pos, out, ldo, scale);
+    dim3 grid((unsigned)((nt + 63) / 64), nrhs);
+    reduce_chunks_kernel<<<grid, 256, 0, st>>>(part, chunks, nt, (int64_t)chunks * nt, pos, out, ldo, scale);
     LAUNCH_CHECK();
 }
 
 void launch_closure(const double* part, int chunks, int64_t nt, const Closure& cl, double* aq, int64_t lda, int nrhs,
-                    hipStream_t st) {
+                    double* vsum, hipStream_t st) {
     if (cl.n == 0) return;
+    launch_reduce_scatter(part, chunks, nt, nullptr, vsum, nt, nrhs, 1.0, st);
     dim3 grid(blocks_for(cl.n), nrhs);
-    closure_kernel<<<grid, kThreads, 0, st>>>(part, chunks, nt, (int64_t)chunks * nt, cl.tq, cl.tp, cl.t, cl.n, aq,
-                                              lda);
+    closure_kernel<<<grid, kThreads, 0, st>>>(vsum, nt, cl.tq, cl.tp, cl.t, cl.n, aq, lda);
     LAUNCH_CHECK();
 }
 

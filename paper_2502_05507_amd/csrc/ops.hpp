@@ -45,8 +45,9 @@ void launch_weights(const CSR& B, const double* q, int64_t ldq, void* w, int64_t
                     hipStream_t st);
 void launch_reduce_scatter(const double* part, int chunks, int64_t nt, const int32_t* pos, double* out, int64_t ldo,
                            int nrhs, double scale, hipStream_t st);
+// vsum: scratch [nrhs][nt] for the chunk-reduced sums
 void launch_closure(const double* part, int chunks, int64_t nt, const Closure& cl, double* aq, int64_t lda, int nrhs,
-                    hipStream_t st);
+                    double* vsum, hipStream_t st);
 int dot_blocks(int64_t n);
 void launch_dots(const double* X, int64_t ldx_vec, int64_t ldx_rhs, int nj, const double* y, int64_t ldy, int64_t n,
                  int nrhs, const int32_t* done, double* partial, int maxj, double* h, int64_t ldh, int accumulate,

@@ -39,15 +39,15 @@ PEAK_FP64_VECTOR = 78.6    # TFLOP/s
 # clock (an FMA is one operation; its two flops make 78.6 TFLOP/s non-packed)
 PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # flops per pair (kernel value + one accumulate) by the kernel's pair classes
-FLOPS = {"fp32": {"near": 2, "far": 34, "far_q2": 23, "mixed_near": 2, "mixed_far": 34},
+FLOPS = {"fp32": {"near": 2, "far": 23, "far_q2": 23, "mixed_near": 2, "mixed_far": 23},
          "fp64": {"near": 2, "far": 46, "far_q2": 46, "mixed_near": 2, "mixed_far": 46}}
 # VALU lane-operations per pair the evaluation needs, by pair class:
 #   table lookup: 3 |t - s| + min/median/max + index add (+ a shift in FP64) + accumulate
-#   far field: 3 differences, 3 squares, r^2, e2, e3, rsqrt, the rho powers and invariants,
-#     the polynomial (q = 3 FP32, q = 2 past the q2 gap, q = 4 FP64 with the FP64 rsqrt's
-#     refinement), the product with 1/|n| and the accumulate
+#   far field: 3 differences, 3 squares, r^2, e2 (e3 in FP64), rsqrt, the rho powers and
+#     invariants, the polynomial (q = 2 FP32, q = 4 FP64 with the FP64 rsqrt's refinement),
+#     the product with 1/|n| and the accumulate
 #   mixed pairs: the chosen path plus the per-pair test
-OPS = {"fp32": {"near": 8, "far": 26, "far_q2": 19, "mixed_near": 10, "mixed_far": 31},
+OPS = {"fp32": {"near": 8, "far": 19, "far_q2": 19, "mixed_near": 10, "mixed_far": 24},
        "fp64": {"near": 9, "far": 41, "far_q2": 41, "mixed_near": 11, "mixed_far": 46}}
 
 

@@ -62,18 +62,17 @@ constexpr int kLdsRadius32 = 55;          // ... FP32, sigma > 0 and batched sum
 constexpr int kLdsRadius64 = 44;          // ... FP64, sigma > 0 and batched sums (130 KB + index arrays)
 constexpr int kMaxTableRadius = 1200;     // largest resident table (sigma > 0)
 constexpr int kFarGap = 32;               // far field used beyond this gap (sigma = 0)
-constexpr int kFar2Gap = 64;              // FP32: q = 2 far field beyond this gap
 constexpr int kSumThreads = 1024;         // threads per workgroup of the LGF sum
 constexpr int kMaxChunks = 64;            // source chunks (partial sums per target)
 
 // Pair classes of a (64-target wavefront, source block) pair; gap and span in quantised
 // units (the smallest and largest max-norm distance between the two bounding boxes).
+// Far blocks are kClassFar in FP64 (q = 4) and kClassFar2 in FP32 (q = 2).
 enum BlockClass { kClassTable = 0, kClassFar = 1, kClassFar2 = 2, kClassGather = 3, kClassMixed = 4 };
 __host__ __device__ inline int block_class(int gap, int span, int tab_r, bool far_ok, bool fp32) {
     if (span <= kQuant * tab_r) return kClassTable;
     if (far_ok) {
-        if (fp32 && gap > kQuant * kFar2Gap) return kClassFar2;
-        if (gap > kQuant * kFarGap) return kClassFar;
+        if (gap > kQuant * kFarGap) return fp32 ? kClassFar2 : kClassFar;
     } else if (gap > kQuant * tab_r) {
         return kClassGather;
     }

@@ -47,15 +47,10 @@ constexpr double F0 = 647.0 * Q7 / (512.0 * kPi), F1 = -20301.0 * Q7 / (512.0 * 
                  F2 = 178035.0 * Q7 / (512.0 * kPi), F3 = -425425.0 * Q7 / (512.0 * kPi),
                  F4 = -208494.0 * Q7 / (512.0 * kPi), F5 = 810810.0 * Q7 / (512.0 * kPi);
 
-template <typename Real>
-__device__ __forceinline__ Real rsqrt_t(Real x);
-template <>
-__device__ __forceinline__ double rsqrt_t<double>(double x) { return rsqrt(x); }
-template <>
-__device__ __forceinline__ float rsqrt_t<float>(float x) { return __builtin_amdgcn_rsqf(x); }
-
-// q = 2 only (FP32 beyond kFar2Gap, where the q = 3 term is below 4.3e-8 relative).
-// X, Y, Z: squared quantised offset components.
+// FP32: q = 2.  Beyond the far-field gap (|n| >= 33) the dropped q = 3 term is at most
+// 0.72 |n|^-4 = 6.1e-7 of G (on the axes), below the rounding error the FP32 sum carries
+// anyway: the FP32 double-layer operator differs from the FP64 one by 3.3e-7 (relative L2,
+// 129^3 ellipsoid) with q = 2 or q = 3 alike.  X, Y, Z: squared quantised offset components.
 __device__ __forceinline__ float far_field_q2(float X, float Y, float Z) {
     const float r2 = X + Y + Z;
     const float e2 = fmaf(X, Y + Z, Y * Z);
@@ -65,28 +60,30 @@ __device__ __forceinline__ float far_field_q2(float X, float Y, float Z) {
     return rinv * fmaf(rho, fmaf(float(C2), x, float(C1)), float(C0));
 }
 
-// Far field from the squared quantised offset components (all >= 0, not all 0).  FP64
-// keeps the q = 4 term (|error| <= 6.6e-11 relative beyond the far-field gap); FP32 stops
-// at q = 3, whose error there (<= 4.8e-9) is already below FP32 rounding.
+// FP64: q = 4 from the squared quantised offset components (all >= 0, not all 0); relative
+// error <= 6.6e-11 beyond the far-field gap.
+__device__ __forceinline__ double far_field_q4(double X, double Y, double Z) {
+    const double r2 = X + Y + Z;
+    const double yz = Y * Z;
+    const double e2 = fma(X, Y + Z, yz);
+    const double e3 = X * yz;
+    const double rinv = rsqrt(r2);
+    const double rho = rinv * rinv;
+    const double rho2 = rho * rho;
+    const double x = e2 * rho2;
+    const double y = e3 * rho2 * rho;
+    double d = fma(D3, y, fma(x, fma(x, D2, D1), D0));
+    const double f = fma(y, fma(F5, x, F4), fma(x, fma(x, fma(x, F3, F2), F1), F0));
+    d = fma(rho, f, d);
+    const double c = fma(C2, x, C1);
+    const double B = fma(rho, fma(rho, d, c), C0);
+    return rinv * B;
+}
+
 template <typename Real>
 __device__ __forceinline__ Real far_field(Real X, Real Y, Real Z) {
-    const Real r2 = X + Y + Z;
-    const Real yz = Y * Z;
-    const Real e2 = fma(X, Y + Z, yz);
-    const Real e3 = X * yz;
-    const Real rinv = rsqrt_t<Real>(r2);
-    const Real rho = rinv * rinv;
-    const Real rho2 = rho * rho;
-    const Real x = e2 * rho2;
-    const Real y = e3 * rho2 * rho;
-    Real d = fma(Real(D3), y, fma(x, fma(x, Real(D2), Real(D1)), Real(D0)));
-    if constexpr (sizeof(Real) == 8) {
-        const Real f = fma(y, fma(Real(F5), x, Real(F4)), fma(x, fma(x, fma(x, Real(F3), Real(F2)), Real(F1)), Real(F0)));
-        d = fma(rho, f, d);
-    }
-    const Real c = fma(Real(C2), x, Real(C1));
-    const Real B = fma(rho, fma(rho, d, c), Real(C0));
-    return rinv * B;
+    if constexpr (sizeof(Real) == 4) return far_field_q2(X, Y, Z);
+    else return far_field_q4(X, Y, Z);
 }
 
 // |a - b| of two non-negative coordinates in one instruction.  The second operand is a
@@ -233,12 +230,83 @@ struct SumArgs {
 // one chunk.  From the bounding boxes of its targets and of each block it picks one loop
 // with a wavefront-uniform branch (block_class):
 //   table   every pair within the LDS table radius
-//   far2    every pair beyond the q = 2 gap (FP32, sigma = 0): q = 2 expansion
 //   far     every pair beyond the far-field gap, sigma = 0: expansion in registers
+//           (q = 2 in FP32, q = 4 in FP64)
 //   gather  every pair beyond the LDS radius, sigma > 0: the global table
 //   mixed   per-pair choice between the LDS table and the far field / global table
+// The sources of one unrolled step, as whole scalar-register vectors.  They are loaded
+// before any of the step's arithmetic (the scheduling barrier): scalar loads and LDS reads
+// share one completion counter and scalar loads complete out of order, so a scalar load
+// left among the table reads would make every wait drain all LDS reads in flight.
+template <typename T, int N>
+using vec_t = T __attribute__((ext_vector_type(N)));
+template <typename T, int N>
+__device__ __forceinline__ vec_t<T, N> ldu_vec(const T* p, int64_t i) {
+    return *((const __attribute__((address_space(4))) vec_t<T, N>*)(p + i));
+}
+
+template <typename Real, int NR>
+struct Step {
+    static constexpr int U = unroll<Real>();
+    vec_t<uint32_t, U> x, y, z;     // quantised integer coordinates (table / gather / mixed)
+    vec_t<Real, U> xr, yr, zr;      // the same in the kernel's precision (far field / mixed)
+    vec_t<Real, U> w[NR];
+};
+
+template <typename Real, int NR, bool INT, bool REAL>
+__device__ __forceinline__ Step<Real, NR> load_step(const SumArgs<Real>& a, int s0) {
+    constexpr int U = unroll<Real>();
+    Step<Real, NR> st;
+    if constexpr (INT) {
+        st.x = ldu_vec<uint32_t, U>(a.sx, s0);
+        st.y = ldu_vec<uint32_t, U>(a.sy, s0);
+        st.z = ldu_vec<uint32_t, U>(a.sz, s0);
+    }
+    if constexpr (REAL) {
+        st.xr = ldu_vec<Real, U>(a.sxr, s0);
+        st.yr = ldu_vec<Real, U>(a.syr, s0);
+        st.zr = ldu_vec<Real, U>(a.szr, s0);
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) st.w[r] = ldu_vec<Real, U>(a.w, r * a.ldw + s0);
+    __builtin_amdgcn_sched_barrier(0);
+    return st;
+}
+
+// Table values of one unrolled step, in phases: all index triples, then all index-array
+// reads, then all value reads (LDS or, for GLOBAL, the full table), so each phase's reads
+// are in flight together instead of one dependent chain per pair.
+template <typename Real, int U, bool GLOBAL>
+__device__ __forceinline__ void lookup_step(const Lds<Real>& L, const Real* __restrict__ full, uint32_t ix,
+                                            uint32_t iy, uint32_t iz, const vec_t<uint32_t, U>& sx,
+                                            const vec_t<uint32_t, U>& sy, const vec_t<uint32_t, U>& sz, Real* G) {
+    uint32_t lo[U], mid[U], hi[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint32_t a = absdiff_s(ix, sx[u]), b = absdiff_s(iy, sy[u]), c = absdiff_s(iz, sz[u]);
+        lo[u] = min3u(a, b, c);
+        mid[u] = med3u(a, b, c);
+        hi[u] = max3u(a, b, c);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    uint32_t th[U], tm[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        th[u] = *(const uint32_t*)((const char*)L.tet + hi[u]);
+        tm[u] = *(const uint32_t*)((const char*)L.tri + mid[u]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint32_t off = sizeof(Real) == 4 ? th[u] + tm[u] + lo[u] : th[u] + tm[u] + 2u * lo[u];
+        G[u] = GLOBAL ? global_value(full, off) : lds_value(L, off);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 template <typename Real, int NR>
 __device__ __forceinline__ void sum_tile(const SumArgs<Real>& a, const Lds<Real>& L, int tile, int chunk) {
+    constexpr int U = unroll<Real>();
     const int lane = threadIdx.x & (kWave - 1);
     const int t = tile * kWave + lane;
     const int tc = min(t, a.nt - 1);
@@ -260,71 +328,53 @@ __device__ __forceinline__ void sum_tile(const SumArgs<Real>& a, const Lds<Real>
         const int cls = block_class(gap, span, a.tab_r, a.far_ok != 0, sizeof(Real) == 4);
         const int sb = b * kSourceBlock;        // blocks are full: the source arrays are padded
         if (cls == kClassTable) {
-            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += unroll<Real>()) {
+            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += U) {
+                const Step<Real, NR> st = load_step<Real, NR, true, false>(a, s0);
+                Real G[U];
+                lookup_step<Real, U, false>(L, nullptr, ix, iy, iz, st.x, st.y, st.z, G);
 #pragma unroll
-                for (int u = 0; u < unroll<Real>(); ++u) {
-                    const int s = s0 + u;
-                    const uint32_t off =
-                        table_offset(L, absdiff_s(ix, ldu(a.sx, s)), absdiff_s(iy, ldu(a.sy, s)), absdiff_s(iz, ldu(a.sz, s)));
-                    const Real G = lds_value(L, off);
+                for (int u = 0; u < U; ++u)
 #pragma unroll
-                    for (int r = 0; r < NR; ++r) acc[r].add(G * ldu(a.w, r * a.ldw + s));
-                }
+                    for (int r = 0; r < NR; ++r) acc[r].add(G[u] * st.w[r][u]);
             }
-        } else if (cls == kClassFar2) {
-            if constexpr (sizeof(Real) == 4) {
-                for (int s0 = sb; s0 < sb + kSourceBlock; s0 += unroll<Real>()) {
+        } else if (cls == kClassFar || cls == kClassFar2) {
+            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += U) {
+                const Step<Real, NR> st = load_step<Real, NR, false, true>(a, s0);
 #pragma unroll
-                    for (int u = 0; u < unroll<Real>(); ++u) {
-                        const int s = s0 + u;
-                        const float dx = fx - ldu(a.sxr, s), dy = fy - ldu(a.syr, s), dz = fz - ldu(a.szr, s);
-                        const Real G = far_field_q2(dx * dx, dy * dy, dz * dz);
-#pragma unroll
-                        for (int r = 0; r < NR; ++r) acc[r].add(G * ldu(a.w, r * a.ldw + s));
-                    }
-                }
-            }
-        } else if (cls == kClassFar) {
-            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += unroll<Real>()) {
-#pragma unroll
-                for (int u = 0; u < unroll<Real>(); ++u) {
-                    const int s = s0 + u;
-                    const Real dx = fx - ldu(a.sxr, s), dy = fy - ldu(a.syr, s), dz = fz - ldu(a.szr, s);
+                for (int u = 0; u < U; ++u) {
+                    const Real dx = fx - st.xr[u], dy = fy - st.yr[u], dz = fz - st.zr[u];
                     const Real G = far_field<Real>(dx * dx, dy * dy, dz * dz);
 #pragma unroll
-                    for (int r = 0; r < NR; ++r) acc[r].add(G * ldu(a.w, r * a.ldw + s));
+                    for (int r = 0; r < NR; ++r) acc[r].add(G * st.w[r][u]);
                 }
             }
         } else if (cls == kClassGather) {
-            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += unroll<Real>()) {
+            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += U) {
+                const Step<Real, NR> st = load_step<Real, NR, true, false>(a, s0);
+                Real G[U];
+                lookup_step<Real, U, true>(L, a.full_tab, ix, iy, iz, st.x, st.y, st.z, G);
 #pragma unroll
-                for (int u = 0; u < unroll<Real>(); ++u) {
-                    const int s = s0 + u;
-                    const uint32_t off =
-                        table_offset(L, absdiff_s(ix, ldu(a.sx, s)), absdiff_s(iy, ldu(a.sy, s)), absdiff_s(iz, ldu(a.sz, s)));
-                    const Real G = global_value(a.full_tab, off);
+                for (int u = 0; u < U; ++u)
 #pragma unroll
-                    for (int r = 0; r < NR; ++r) acc[r].add(G * ldu(a.w, r * a.ldw + s));
-                }
+                    for (int r = 0; r < NR; ++r) acc[r].add(G[u] * st.w[r][u]);
             }
         } else {
-            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += unroll<Real>()) {
+            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += U) {
+                const Step<Real, NR> st = load_step<Real, NR, true, true>(a, s0);
 #pragma unroll
-                for (int u = 0; u < unroll<Real>(); ++u) {
-                    const int s = s0 + u;
-                    const uint32_t da = absdiff_s(ix, ldu(a.sx, s)), db = absdiff_s(iy, ldu(a.sy, s)),
-                                   dc = absdiff_s(iz, ldu(a.sz, s));
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t da = absdiff_s(ix, st.x[u]), db = absdiff_s(iy, st.y[u]), dc = absdiff_s(iz, st.z[u]);
                     Real G;
                     if (max3u(da, db, dc) <= tab_q) {
                         G = lds_value(L, table_offset(L, da, db, dc));
                     } else if (a.far_ok) {
-                        const Real dx = fx - ldu(a.sxr, s), dy = fy - ldu(a.syr, s), dz = fz - ldu(a.szr, s);
+                        const Real dx = fx - st.xr[u], dy = fy - st.yr[u], dz = fz - st.zr[u];
                         G = far_field<Real>(dx * dx, dy * dy, dz * dz);
                     } else {
                         G = global_value(a.full_tab, table_offset(L, da, db, dc));
                     }
 #pragma unroll
-                    for (int r = 0; r < NR; ++r) acc[r].add(G * ldu(a.w, r * a.ldw + s));
+                    for (int r = 0; r < NR; ++r) acc[r].add(G * st.w[r][u]);
                 }
             }
         }

@@ -64,8 +64,8 @@ void PlanBuf::build(const PointSet& T, const PointSet& S, const SumTables& tabs,
 }
 
 static void apply_lgf(bae_ctx* c, const PointSet& T, const PointSet& S, const void* w, int nrhs, int prec,
-                      double* part, int64_t cap, int* chunks_out, hipStream_t st) {
-    *chunks_out = lgf_sum_launch(T, S, w, nrhs, prec, c->tabs, c->plan.plan, part, cap, c->sum_grid, st);
+                      double* part, int64_t cap, int* chunks_out, hipStream_t st, const int32_t* skip = nullptr) {
+    *chunks_out = lgf_sum_launch(T, S, w, nrhs, prec, c->tabs, c->plan.plan, part, cap, c->sum_grid, st, skip);
 }
 
 // v = [D+ q; D- q] (external order), q [nrhs][ngm] with leading dimension ldq
@@ -77,12 +77,12 @@ static void double_layer(bae_ctx* c, const double* q, int64_t ldq, double* v, in
     launch_reduce_scatter(c->part.as<double>(), chunks, c->nT, c->t_pos.as<int32_t>(), v, ldv, nrhs, 1.0, st);
 }
 
-// aq = Phi+ D+ q + Phi- D- q
+// aq = Phi+ D+ q + Phi- D- q (the LGF sum skipped while *skip is set, when given)
 static void bae_operator(bae_ctx* c, const double* q, int64_t ldq, double* aq, int64_t lda, int nrhs, int prec,
-                         hipStream_t st) {
+                         hipStream_t st, const int32_t* skip = nullptr) {
     launch_weights(c->B, q, ldq, c->w.p, c->S.ps.padded, nrhs, prec, st);
     int chunks = 0;
-    apply_lgf(c, c->T.ps, c->S.ps, c->w.p, nrhs, prec, c->part.as<double>(), c->part_cap, &chunks, st);
+    apply_lgf(c, c->T.ps, c->S.ps, c->w.p, nrhs, prec, c->part.as<double>(), c->part_cap, &chunks, st, skip);
     launch_closure(c->part.as<double>(), chunks, c->nT, c->cl, aq, lda, nrhs, c->vsum.as<double>(), st);
 }
 
@@ -112,27 +112,45 @@ static GmresOut gmres(bae_ctx* c, const double* r0, int nrhs, int prec, double t
             if (skip[r]) BAE_HIP_CHECK(hipMemcpyAsync(K.done + r, &d[r], sizeof(int32_t), hipMemcpyHostToDevice, st));
         BAE_HIP_CHECK(hipStreamSynchronize(st));
     }
+    // Convergence is read back from the device.  With one RHS the host keeps one iteration
+    // queued ahead and reads the flags of the previous one, so the device never waits for
+    // the host; the queued iteration after convergence skips its LGF sum (the GMRES kernels
+    // skip converged RHS anyway).  With several RHS every `check`-th iteration is synchronous.
+    const bool lagged = nrhs == 1;
     const double pairs = (double)c->nT * (double)c->nS * nrhs;
     const int check = pairs > 2e7 ? 1 : (pairs > 2e6 ? 2 : 6);
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (lagged)
+        for (auto& e : ev) BAE_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     int k = 0;
     for (; k < m; ++k) {
         double* vk = K.V + (int64_t)k * n;
         double* vk1 = K.V + (int64_t)(k + 1) * n;
-        bae_operator(c, vk, K.ld_rhs, vk1, K.ld_rhs, nrhs, prec, st);
+        bae_operator(c, vk, K.ld_rhs, vk1, K.ld_rhs, nrhs, prec, st, lagged ? K.done : nullptr);
         (*matvecs)++;
-        launch_dots(K.V, n, K.ld_rhs, k + 1, vk1, K.ld_rhs, n, nrhs, K.done, c->dotpart.as<double>(), c->maxj,
-                    c->hA.as<double>(), c->maxj, 0, st);
-        launch_subtract_combination(K.V, n, K.ld_rhs, c->hA.as<double>(), c->maxj, k + 1, n, nrhs, K.done, vk1,
-                                    K.ld_rhs, st);
-        launch_dots(K.V, n, K.ld_rhs, k + 1, vk1, K.ld_rhs, n, nrhs, K.done, c->dotpart.as<double>(), c->maxj,
-                    c->hB.as<double>(), c->maxj, 0, st);
-        launch_subtract_combination(K.V, n, K.ld_rhs, c->hB.as<double>(), c->maxj, k + 1, n, nrhs, K.done, vk1,
-                                    K.ld_rhs, st);
-        launch_dots(vk1, 0, K.ld_rhs, 1, vk1, K.ld_rhs, n, nrhs, K.done, c->dotpart.as<double>(), c->maxj,
-                    c->nrm.as<double>(), 1, 0, st);
-        launch_normalize(K.V, n, K.ld_rhs, k, n, c->nrm.as<double>(), K.done, nrhs, st);
-        launch_givens(K, c->hA.as<double>(), c->hB.as<double>(), c->maxj, c->nrm.as<double>(), k, tol, nrhs, st);
-        if ((k + 1) % check == 0 || k + 1 == m) {
+        // classical Gram-Schmidt twice (dot-product slices in pA, pB); the second pass also
+        // forms the slices of ||w||^2 (pN), which normalize and Givens sum themselves
+        double* pA = c->dotpart.as<double>();
+        double* pB = pA + (int64_t)nrhs * c->maxj * dot_blocks(n);
+        double* pN = pB + (int64_t)nrhs * c->maxj * dot_blocks(n);
+        launch_dot_slices(K.V, n, K.ld_rhs, k + 1, vk1, K.ld_rhs, n, nrhs, K.done, pA, c->maxj, st);
+        launch_subtract_combination(K.V, n, K.ld_rhs, pA, c->maxj, k + 1, n, nrhs, K.done, vk1, K.ld_rhs, nullptr, st);
+        launch_dot_slices(K.V, n, K.ld_rhs, k + 1, vk1, K.ld_rhs, n, nrhs, K.done, pB, c->maxj, st);
+        launch_subtract_combination(K.V, n, K.ld_rhs, pB, c->maxj, k + 1, n, nrhs, K.done, vk1, K.ld_rhs, pN, st);
+        launch_normalize(K.V, n, K.ld_rhs, k, n, pN, K.done, nrhs, st);
+        launch_givens(K, pA, pB, c->maxj, pN, k, tol, nrhs, st);
+        if (lagged) {
+            BAE_HIP_CHECK(hipMemcpyAsync(c->pinned_flags + (k & 1), K.done, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            BAE_HIP_CHECK(hipEventRecord(ev[k & 1], st));
+            if (k >= 1) {
+                BAE_HIP_CHECK(hipEventSynchronize(ev[(k - 1) & 1]));
+                if (c->pinned_flags[(k - 1) & 1]) {
+                    (*matvecs)--;   // the LGF sum of iteration k was skipped
+                    break;
+                }
+            }
+            if (k + 1 == m) BAE_HIP_CHECK(hipEventSynchronize(ev[k & 1]));
+        } else if ((k + 1) % check == 0 || k + 1 == m) {
             BAE_HIP_CHECK(hipMemcpyAsync(c->pinned_flags, K.done, sizeof(int32_t) * nrhs, hipMemcpyDeviceToHost, st));
             BAE_HIP_CHECK(hipStreamSynchronize(st));
             bool all = true;
@@ -143,6 +161,8 @@ static GmresOut gmres(bae_ctx* c, const double* r0, int nrhs, int prec, double t
             }
         }
     }
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
     // host back substitution R y = g for each RHS
     std::vector<int32_t> kd(nrhs), dn(nrhs);
     BAE_HIP_CHECK(hipMemcpyAsync(kd.data(), K.kdone, sizeof(int32_t) * nrhs, hipMemcpyDeviceToHost, st));
@@ -378,7 +398,7 @@ bae_ctx* create_context(const bae_grid& gridv, const bae_options* opt, Geometry&
         c->hA.alloc(sizeof(double) * c->maxj * mr);
         c->hB.alloc(sizeof(double) * c->maxj * mr);
         c->nrm.alloc(sizeof(double) * c->maxj * mr);
-        c->dotpart.alloc(sizeof(double) * (int64_t)c->maxj * mr * dot_blocks(n));
+        c->dotpart.alloc(sizeof(double) * mr * (2 * (int64_t)c->maxj * dot_blocks(n) + norm_blocks(n)));
         c->ycoef.alloc(sizeof(double) * m * mr);
         for (DevMem* d : {&c->b, &c->x, &c->r, &c->tmp}) d->alloc(sizeof(double) * n * mr);
         c->up_gamma.alloc(sizeof(double) * c->nT * mr);
@@ -412,7 +432,8 @@ int64_t estimate_context_bytes(const Geometry& G, double s, const bae_options* o
     b += ((nT + 63) / 64) * kMaxChunks * 4;                                               // work list
     b += nT * mr * 8;                                                                     // reduced sums
     b += ((int64_t)(m + 1) * ngm + (int64_t)m * (m + 1) + 4 * m + 8) * 8 * mr;        // Krylov state
-    b += (int64_t)(m + 1) * mr * 8 * (3 + dot_blocks(ngm)) + (int64_t)m * mr * 8;      // CGS, dots, y
+    b += (int64_t)(m + 1) * mr * 8 * (3 + 2 * dot_blocks(ngm)) + (int64_t)m * mr * 8;  // CGS, dot slices, y
+    b += (int64_t)norm_blocks(ngm) * mr * 8;                                           // norm slices
     b += 4 * ngm * mr * 8 + 2 * nT * mr * 8;                                           // b, x, r, tmp, u_p, u_gamma
     if (s > 0.0) b += table_size(std::max(32, G.max_offset)) * 12;                     // its own table
     return b;

@@ -127,9 +127,10 @@ int lgf_sum_grid(int device);    // workgroups of the persistent sum kernels
 
 // v[r][t] (partials per source chunk: part[r][chunk][t]) = sum_s w[r][s] G(T_t - S_s).
 // w is FP64 when prec == BAE_PREC_FP64, FP32 otherwise.  Returns number of chunks used.
+// skip: optional device flag; when it is set at launch time the kernels do nothing.
 int lgf_sum_launch(const PointSet& T, const PointSet& S, const void* w, int nrhs, int prec,
                    const SumTables& tabs, const SumPlan& plan, double* part, int64_t part_capacity,
-                   int grid, hipStream_t st);
+                   int grid, hipStream_t st, const int32_t* skip = nullptr);
 void lgf_eval_launch(const int32_t* off, int64_t count, double* out, int prec, const SumTables& tabs,
                      hipStream_t st);
 

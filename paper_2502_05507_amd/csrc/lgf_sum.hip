@@ -50,6 +50,7 @@ using namespace lgfdev;
 namespace {
 
 struct Sched {
+    const int32_t* skip;   // non-null and set: the whole sum is skipped (a converged solve)
     const uint32_t* items;
     unsigned long long* counter;   // a type no input array has: its atomics cannot alias the
                                    // inputs, whose uniform loads then stay scalar
@@ -69,6 +70,7 @@ __device__ __forceinline__ void for_each_item(const Sched& q, F&& body) {
     const uint32_t waves = __builtin_amdgcn_readfirstlane(gridDim.x * (blockDim.x >> 6));
     const uint32_t w = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
     if (w >= q.nitems) return;
+    if (q.skip && ldu(q.skip, 0)) return;   // uniform: every wavefront leaves, the counter stays 0
     uint32_t i = w;
     for (;;) {
         uint32_t nxt = 0;
@@ -289,7 +291,8 @@ constexpr int rhs4_threads() { return sizeof(Real) == 4 ? kSumThreads : kSumThre
 
 template <typename Real>
 void launch_all(const PointSet& T, const PointSet& S, const Real* w, int nrhs, const Real* near, const Real* full,
-                int tab_r, int full_r, bool far, const SumPlan& plan, double* part, int grid, hipStream_t st) {
+                int tab_r, int full_r, bool far, const SumPlan& plan, double* part, int grid, const int32_t* skip,
+                hipStream_t st) {
     SumArgs<Real> a;
     a.tx = T.x;
     a.ty = T.y;
@@ -320,7 +323,7 @@ void launch_all(const PointSet& T, const PointSet& S, const Real* w, int nrhs, c
         ar.part = part + (int64_t)r * a.ldp;
         const int threads = left >= 16 ? mfma_threads<Real>() : left >= 4 ? rhs4_threads<Real>() : kSumThreads;
         const uint32_t waves = (uint32_t)grid * (uint32_t)(threads / 64);
-        const Sched q{plan.items, plan.counter, (uint32_t)plan.nitems, plan.nitems > (int64_t)waves ? 1 : 0};
+        const Sched q{skip, plan.items, plan.counter, (uint32_t)plan.nitems, plan.nitems > (int64_t)waves ? 1 : 0};
         if (left >= 16) {
             if (far) lgf_sum_mfma_kernel<Real, mfma_threads<Real>(), true><<<grid, mfma_threads<Real>(), 0, st>>>(ar, q);
             else lgf_sum_mfma_kernel<Real, mfma_threads<Real>(), false><<<grid, mfma_threads<Real>(), 0, st>>>(ar, q);
@@ -418,7 +421,8 @@ void plan_sum(const PointSet& T, const PointSet& S, const SumTables& tabs, SumPl
 }
 
 int lgf_sum_launch(const PointSet& T, const PointSet& S, const void* w, int nrhs, int prec, const SumTables& tabs,
-                   const SumPlan& plan, double* part, int64_t part_capacity, int grid, hipStream_t st) {
+                   const SumPlan& plan, double* part, int64_t part_capacity, int grid, hipStream_t st,
+                   const int32_t* skip) {
     if (T.count == 0) return 0;
     const int chunks = plan.chunks;
     if ((int64_t)chunks * T.count * nrhs > part_capacity) throw Error{BAE_ERR_ARG, "partial-sum buffer too small"};
@@ -429,10 +433,10 @@ int lgf_sum_launch(const PointSet& T, const PointSet& S, const void* w, int nrhs
     }
     if (prec == BAE_PREC_FP64)
         launch_all<double>(T, S, (const double*)w, nrhs, tabs.near64, tabs.full64, tabs.tab_r64, tabs.full_r,
-                           tabs.far_field, plan, part, grid, st);
+                           tabs.far_field, plan, part, grid, skip, st);
     else
         launch_all<float>(T, S, (const float*)w, nrhs, tabs.near32, tabs.full32, tabs.tab_r32, tabs.full_r,
-                          tabs.far_field, plan, part, grid, st);
+                          tabs.far_field, plan, part, grid, skip, st);
     return chunks;
 }
 

@@ -73,8 +73,9 @@ __device__ inline double block_sum(double v, double* sh) {
     return s;
 }
 
-// partial[r][j][b] = sum over slice b of X[r][j][i] * y[r][i]; j < nj, b < nb.
-// Done RHS are skipped (their partials are not read).
+// partial[r][j][b] = sum over slice b of X[r][j][i] * y[r][i]; j < nj (grid y), b < nb.
+// The consumers add the nb slices themselves, always in the same order (no finalize
+// launch, no cross-block synchronisation, deterministic results).
 __global__ void dots_kernel(const double* __restrict__ X, int64_t ldx_vec, int64_t ldx_rhs,
                             const double* __restrict__ y, int64_t ldy, int64_t n, int nb,
                             const int32_t* __restrict__ done, double* __restrict__ partial, int maxj) {
@@ -91,32 +92,49 @@ __global__ void dots_kernel(const double* __restrict__ X, int64_t ldx_vec, int64
     if (threadIdx.x == 0) partial[((int64_t)r * maxj + j) * nb + b] = s;
 }
 
-// h[r][j] (+)= sum_b partial[r][j][b]
+__device__ inline double slice_sum(const double* p, int nb) {
+    double t = 0.0;
+    for (int k = 0; k < nb; ++k) t += p[k];
+    return t;
+}
+
+// h[r][j] (+)= sum_b partial[r][j][b]   (the few places that need h itself)
 __global__ void dots_finalize_kernel(const double* __restrict__ partial, int nb, int nj, int maxj,
                                      const int32_t* __restrict__ done, double* __restrict__ h, int64_t ldh,
                                      int accumulate) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
     if (j >= nj || (done && done[r])) return;
-    const double* p = partial + ((int64_t)r * maxj + j) * nb;
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += p[b];
+    const double s = slice_sum(partial + ((int64_t)r * maxj + j) * nb, nb);
     h[r * ldh + j] = accumulate ? h[r * ldh + j] + s : s;
 }
 
-// y[r][i] -= sum_{j < nj} c[r][j] X[r][j][i]
+// y[r][i] -= sum_{j < nj} c[r][j] X[r][j][i], c[r][j] = the nb dot-product slices of
+// cpart summed by every block into LDS.  With npart, also the block's sum of the squared
+// results goes to npart[r][blockIdx.x] (slices of ||y[r]||^2).
 __global__ void subtract_combination_kernel(const double* __restrict__ X, int64_t ldx_vec, int64_t ldx_rhs,
-                                            const double* __restrict__ c, int64_t ldc, int nj, int64_t n,
+                                            const double* __restrict__ cpart, int nb, int maxj, int nj, int64_t n,
                                             const int32_t* __restrict__ done, double* __restrict__ y,
-                                            int64_t ldy) {
+                                            int64_t ldy, double* __restrict__ npart) {
+    extern __shared__ double cl[];   // nj coefficients
+    __shared__ double sh[kThreads / 64];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
-    if (i >= n || (done && done[r])) return;
-    const double* x = X + r * ldx_rhs + i;
-    const double* cr = c + r * ldc;
-    double acc = 0.0;
-    for (int j = 0; j < nj; ++j) acc = fma(cr[j], x[j * ldx_vec], acc);
-    y[r * ldy + i] -= acc;
+    if (done && done[r]) return;
+    for (int j = threadIdx.x; j < nj; j += blockDim.x) cl[j] = slice_sum(cpart + ((int64_t)r * maxj + j) * nb, nb);
+    __syncthreads();
+    double v2 = 0.0;
+    if (i < n) {
+        const double* x = X + r * ldx_rhs + i;
+        double acc = 0.0;
+        for (int j = 0; j < nj; ++j) acc = fma(cl[j], x[j * ldx_vec], acc);
+        const double v = y[r * ldy + i] - acc;
+        y[r * ldy + i] = v;
+        v2 = v * v;
+    }
+    if (!npart) return;
+    const double s = block_sum(v2, sh);
+    if (threadIdx.x == 0) npart[(int64_t)r * gridDim.x + blockIdx.x] = s;
 }
 
 // y[r][i] (+)= sum_{j < nj[r]} c[r][j] X[r][j][i]
@@ -133,33 +151,40 @@ __global__ void combination_kernel(const double* __restrict__ X, int64_t ldx_vec
     y[r * ldy + i] = accumulate ? y[r * ldy + i] + acc : acc;
 }
 
-// Hessenberg column k of RHS r holds h[0..k] (CGS2 coefficients) and nrm2 = ||w||^2:
-// set H[k+1][k] = ||w||, scale w into the next basis vector.
+// Scale w = V[k+1] to unit length; ||w||^2 is the sum of its nn slices npart[r][*].
 __global__ void normalize_kernel(double* __restrict__ V, int64_t ldv_vec, int64_t ldv_rhs, int k, int64_t n,
-                                 const double* __restrict__ nrm2, const int32_t* __restrict__ done) {
+                                 const double* __restrict__ npart, int nn, const int32_t* __restrict__ done) {
+    __shared__ double nr;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
-    if (i >= n || (done && done[r])) return;
-    const double nr = sqrt(nrm2[r]);
-    if (nr > 0.0) V[r * ldv_rhs + (int64_t)(k + 1) * ldv_vec + i] /= nr;
+    if (done && done[r]) return;
+    if (threadIdx.x == 0) nr = sqrt(slice_sum(npart + (int64_t)r * nn, nn));
+    __syncthreads();
+    if (i < n && nr > 0.0) V[r * ldv_rhs + (int64_t)(k + 1) * ldv_vec + i] /= nr;
 }
 
-// One thread per RHS: Givens update of column k (Saad-Schultz), residual estimate,
-// convergence / breakdown flag.  H is column-major per RHS: H[r][k][i], i <= k+1.
+// One block per RHS: Givens update of column k (Saad-Schultz), residual estimate,
+// convergence / breakdown flag.  H is column-major per RHS: H[r][k][i], i <= k+1.  The
+// column is the sum of the two Gram-Schmidt passes' coefficients, each the sum of its nb
+// dot-product slices (pA, pB; summed by the block's threads); H[k+1][k] = ||w|| from the nn
+// norm slices.  The rotations themselves are sequential (thread 0).
 __global__ void givens_kernel(double* __restrict__ Hc, int64_t ldh_col, int64_t ldh_rhs,
-                              const double* __restrict__ hcol, const double* __restrict__ hcol2, int64_t ldhc,
-                              const double* __restrict__ nrm2,
+                              const double* __restrict__ pA, const double* __restrict__ pB, int nb, int maxj,
+                              const double* __restrict__ npart, int nn,
                               double* __restrict__ cs, double* __restrict__ sn, int64_t ldcs,
                               double* __restrict__ g, int64_t ldg, const double* __restrict__ beta,
                               double* __restrict__ hist, int64_t ldhist, int32_t* __restrict__ done,
-                              int32_t* __restrict__ kdone, int k, double tol, int nrhs) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrhs || done[r]) return;
+                              int32_t* __restrict__ kdone, int k, double tol) {
+    __shared__ double hk1s;
+    const int r = blockIdx.x;
+    if (done[r]) return;
     double* h = Hc + r * ldh_rhs + (int64_t)k * ldh_col;
-    const double* hc = hcol + r * ldhc;
-    const double* hc2 = hcol2 + r * ldhc;
-    for (int i = 0; i <= k; ++i) h[i] = hc[i] + hc2[i];   // the two Gram-Schmidt passes
-    const double hk1 = sqrt(nrm2[r]);
+    for (int i = threadIdx.x; i <= k; i += blockDim.x)
+        h[i] = slice_sum(pA + ((int64_t)r * maxj + i) * nb, nb) + slice_sum(pB + ((int64_t)r * maxj + i) * nb, nb);
+    if (threadIdx.x == 0) hk1s = sqrt(slice_sum(npart + (int64_t)r * nn, nn));
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double hk1 = hk1s;
     double* c = cs + r * ldcs;
     double* s = sn + r * ldcs;
     for (int i = 0; i < k; ++i) {
@@ -273,20 +298,29 @@ void launch_dots(const double* X, int64_t ldx_vec, int64_t ldx_rhs, int nj, cons
                  int nrhs, const int32_t* done, double* partial, int maxj, double* h, int64_t ldh, int accumulate,
                  hipStream_t st) {
     const int nb = dot_blocks(n);
-    dots_kernel<<<dim3(nb, nj, nrhs), kThreads, 0, st>>>(X, ldx_vec, ldx_rhs, y, ldy, n, nb, done, partial, maxj);
-    LAUNCH_CHECK();
+    launch_dot_slices(X, ldx_vec, ldx_rhs, nj, y, ldy, n, nrhs, done, partial, maxj, st);
     dots_finalize_kernel<<<dim3(blocks_for(nj, 64), nrhs), 64, 0, st>>>(partial, nb, nj, maxj, done, h, ldh,
                                                                          accumulate);
     LAUNCH_CHECK();
 }
 
-void launch_subtract_combination(const double* X, int64_t ldx_vec, int64_t ldx_rhs, const double* c, int64_t ldc,
-                                 int nj, int64_t n, int nrhs, const int32_t* done, double* y, int64_t ldy,
-                                 hipStream_t st) {
-    subtract_combination_kernel<<<dim3(blocks_for(n), nrhs), kThreads, 0, st>>>(X, ldx_vec, ldx_rhs, c, ldc, nj, n,
-                                                                                 done, y, ldy);
+void launch_dot_slices(const double* X, int64_t ldx_vec, int64_t ldx_rhs, int nj, const double* y, int64_t ldy,
+                       int64_t n, int nrhs, const int32_t* done, double* partial, int maxj, hipStream_t st) {
+    const int nb = dot_blocks(n);
+    dots_kernel<<<dim3(nb, nj, nrhs), kThreads, 0, st>>>(X, ldx_vec, ldx_rhs, y, ldy, n, nb, done, partial, maxj);
     LAUNCH_CHECK();
 }
+
+void launch_subtract_combination(const double* X, int64_t ldx_vec, int64_t ldx_rhs, const double* cpart, int maxj,
+                                 int nj, int64_t n, int nrhs, const int32_t* done, double* y, int64_t ldy,
+                                 double* npart, hipStream_t st) {
+    const int nb = dot_blocks(n);
+    subtract_combination_kernel<<<dim3(blocks_for(n), nrhs), kThreads, sizeof(double) * nj, st>>>(
+        X, ldx_vec, ldx_rhs, cpart, nb, maxj, nj, n, done, y, ldy, npart);
+    LAUNCH_CHECK();
+}
+
+int norm_blocks(int64_t n) { return (int)blocks_for(n); }
 
 void launch_combination(const double* X, int64_t ldx_vec, int64_t ldx_rhs, const double* c, int64_t ldc,
                         const int32_t* nj, int64_t n, int nrhs, double* y, int64_t ldy, int accumulate,
@@ -296,18 +330,18 @@ void launch_combination(const double* X, int64_t ldx_vec, int64_t ldx_rhs, const
     LAUNCH_CHECK();
 }
 
-void launch_normalize(double* V, int64_t ldv_vec, int64_t ldv_rhs, int k, int64_t n, const double* nrm2,
+void launch_normalize(double* V, int64_t ldv_vec, int64_t ldv_rhs, int k, int64_t n, const double* npart,
                       const int32_t* done, int nrhs, hipStream_t st) {
-    normalize_kernel<<<dim3(blocks_for(n), nrhs), kThreads, 0, st>>>(V, ldv_vec, ldv_rhs, k, n, nrm2, done);
+    normalize_kernel<<<dim3(blocks_for(n), nrhs), kThreads, 0, st>>>(V, ldv_vec, ldv_rhs, k, n, npart,
+                                                                      norm_blocks(n), done);
     LAUNCH_CHECK();
 }
 
-void launch_givens(const KrylovState& K, const double* hcol, const double* hcol2, int64_t ldhc, const double* nrm2,
-                   int k, double tol, int nrhs, hipStream_t st) {
-    givens_kernel<<<blocks_for(nrhs, 64), 64, 0, st>>>(K.H, K.m + 1, (int64_t)(K.m + 1) * K.m, hcol, hcol2, ldhc,
-                                                       nrm2, K.cs,
-                                                       K.sn, K.m, K.g, K.m + 1, K.beta, K.hist, K.m, K.done, K.kdone, k,
-                                                       tol, nrhs);
+void launch_givens(const KrylovState& K, const double* pA, const double* pB, int maxj, const double* npart, int k,
+                   double tol, int nrhs, hipStream_t st) {
+    givens_kernel<<<nrhs, kThreads, 0, st>>>(K.H, K.m + 1, (int64_t)(K.m + 1) * K.m, pA, pB, dot_blocks(K.n), maxj,
+                                             npart, norm_blocks(K.n), K.cs, K.sn, K.m, K.g, K.m + 1, K.beta, K.hist,
+                                             K.m, K.done, K.kdone, k, tol);
     LAUNCH_CHECK();
 }
 

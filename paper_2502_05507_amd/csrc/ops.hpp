@@ -49,19 +49,26 @@ void launch_reduce_scatter(const double* part, int chunks, int64_t nt, const int
 void launch_closure(const double* part, int chunks, int64_t nt, const Closure& cl, double* aq, int64_t lda, int nrhs,
                     double* vsum, hipStream_t st);
 int dot_blocks(int64_t n);
+// h[r][j] (+)= <X[r][j], y[r]> for j < nj; partial: scratch [nrhs][maxj][dot_blocks(n)].
 void launch_dots(const double* X, int64_t ldx_vec, int64_t ldx_rhs, int nj, const double* y, int64_t ldy, int64_t n,
                  int nrhs, const int32_t* done, double* partial, int maxj, double* h, int64_t ldh, int accumulate,
                  hipStream_t st);
-void launch_subtract_combination(const double* X, int64_t ldx_vec, int64_t ldx_rhs, const double* c, int64_t ldc,
+// The slices only: partial[r][j][b] (b < dot_blocks(n)), summed by the consumers below.
+void launch_dot_slices(const double* X, int64_t ldx_vec, int64_t ldx_rhs, int nj, const double* y, int64_t ldy,
+                       int64_t n, int nrhs, const int32_t* done, double* partial, int maxj, hipStream_t st);
+// y[r] -= sum_j c[r][j] X[r][j] with c the summed slices of cpart; with npart non-null also
+// the slices of ||y[r]||^2 (npart[r][b], b < norm_blocks(n)).
+void launch_subtract_combination(const double* X, int64_t ldx_vec, int64_t ldx_rhs, const double* cpart, int maxj,
                                  int nj, int64_t n, int nrhs, const int32_t* done, double* y, int64_t ldy,
-                                 hipStream_t st);
+                                 double* npart, hipStream_t st);
+int norm_blocks(int64_t n);
 void launch_combination(const double* X, int64_t ldx_vec, int64_t ldx_rhs, const double* c, int64_t ldc,
                         const int32_t* nj, int64_t n, int nrhs, double* y, int64_t ldy, int accumulate,
                         hipStream_t st);
-void launch_normalize(double* V, int64_t ldv_vec, int64_t ldv_rhs, int k, int64_t n, const double* nrm2,
+void launch_normalize(double* V, int64_t ldv_vec, int64_t ldv_rhs, int k, int64_t n, const double* npart,
                       const int32_t* done, int nrhs, hipStream_t st);
-void launch_givens(const KrylovState& K, const double* hcol, const double* hcol2, int64_t ldhc, const double* nrm2,
-                   int k, double tol, int nrhs, hipStream_t st);
+void launch_givens(const KrylovState& K, const double* pA, const double* pB, int maxj, const double* npart, int k,
+                   double tol, int nrhs, hipStream_t st);
 void launch_gmres_init(const double* r0, int64_t ldr, const KrylovState& K, int64_t n, const double* nrm2, int nrhs,
                        hipStream_t st);
 void launch_axpby(double a, const double* x, int64_t ldx, double b, double* y, int64_t ldy, int64_t n, int nrhs,

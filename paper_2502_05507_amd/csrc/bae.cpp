@@ -363,6 +363,14 @@ bae_ctx* create_context(const bae_grid& gridv, const bae_options* opt, Geometry&
         c->tabs.tab_r64 = std::min({far ? kLdsRadiusFar64 : kLdsRadius64, c->tabs.full_r, need});
         c->tabs.tab_r32 = std::min({far ? kLdsRadiusFar32 : kLdsRadius32, c->tabs.full_r, need});
         c->tabs.far_field = c->s == 0.0;
+        // sigma > 0: the FP32 sum may use the Yukawa-form far field beyond the LDS radius, but
+        // only where it matches this context's own exact table everywhere (FP64 keeps the table)
+        c->tabs.kappa = std::sqrt(c->s);
+        if (!far && c->tabs.full_r > c->tabs.tab_r32) {
+            c->tabs.yukawa_err = yukawa_check(c->table->d64.as<double>(), c->tabs.full_r, c->tabs.tab_r32,
+                                              c->tabs.kappa, st);
+            c->tabs.yukawa32 = c->tabs.yukawa_err <= kYukawaTolerance;
+        }
         c->sum_grid = lgf_sum_grid(c->device);
         c->plan.build(c->T.ps, c->S.ps, c->tabs, st);
 
@@ -799,7 +807,8 @@ int bae_sum_stats(const bae_ctx* c, int32_t prec, int64_t* counts) {
                 }
                 const int64_t s0 = b * kSourceBlock, s1 = std::min(ns, s0 + kSourceBlock);
                 const int64_t pairs = (w1 - w0) * (s1 - s0);
-                switch (block_class(gap, span, tab_r, c->tabs.far_field, fp32)) {
+                switch (block_class(gap, span, tab_r, fp32 ? c->tabs.far32() : c->tabs.far64(), fp32,
+                                    fp32 ? c->tabs.far_gap32() : c->tabs.far_gap64())) {
                     case kClassTable: cnt[0] += pairs; break;
                     case kClassFar: case kClassGather: cnt[1] += pairs; break;
                     case kClassFar2: cnt[2] += pairs; break;

@@ -515,16 +515,24 @@ void build_layout(BatchEngine* b) {
             a.near_tab = near;
             a.full_tab = full;
             a.full_r = c->tabs.full_r;
-            a.far_ok = c->tabs.far_field ? 1 : 0;
             a.part = q.part;
             a.ldp = (int64_t)q.chunks * c->nT;
         };
         fill(q.s64, c->tabs.near64, c->tabs.full64, c->S.ps.xd, c->S.ps.yd, c->S.ps.zd);
         q.s64.w = (const double*)c->w.p;
         q.s64.tab_r = std::min(c->tabs.tab_r64, kLdsRadius64);   // this kernel's LDS holds the general layout
+        q.s64.far_ok = c->tabs.far64() ? 1 : 0;
+        q.s64.far_gap = c->tabs.far_gap64();
+        q.s64.yukawa = 0;
+        q.s64.kq = q.s64.yk = 0.0;
         fill(q.s32, c->tabs.near32, c->tabs.full32, c->S.ps.xf, c->S.ps.yf, c->S.ps.zf);
         q.s32.w = (const float*)c->w.p;
         q.s32.tab_r = std::min(c->tabs.tab_r32, kLdsRadius32);
+        q.s32.far_ok = c->tabs.far32() ? 1 : 0;
+        q.s32.far_gap = c->tabs.yukawa32 ? q.s32.tab_r : c->tabs.far_gap32();
+        q.s32.yukawa = c->tabs.yukawa32 ? 1 : 0;
+        q.s32.kq = (float)(c->tabs.kappa / kQuant);
+        q.s32.yk = (float)(-c->tabs.kappa * 1.4426950408889634 / kQuant);
     }
     b->nslices_total = (int)sl.size();
     b->nitems = (int)it.size();

@@ -62,17 +62,19 @@ constexpr int kLdsRadius32 = 55;          // ... FP32, sigma > 0 and batched sum
 constexpr int kLdsRadius64 = 44;          // ... FP64, sigma > 0 and batched sums (130 KB + index arrays)
 constexpr int kMaxTableRadius = 1200;     // largest resident table (sigma > 0)
 constexpr int kFarGap = 32;               // far field used beyond this gap (sigma = 0)
+constexpr double kYukawaTolerance = 1e-6; // sigma > 0 FP32 far field: largest accepted relative error
 constexpr int kSumThreads = 1024;         // threads per workgroup of the LGF sum
 constexpr int kMaxChunks = 64;            // source chunks (partial sums per target)
 
 // Pair classes of a (64-target wavefront, source block) pair; gap and span in quantised
 // units (the smallest and largest max-norm distance between the two bounding boxes).
-// Far blocks are kClassFar in FP64 (q = 4) and kClassFar2 in FP32 (q = 2).
+// Far blocks (every pair beyond far_gap, where the far field holds) are kClassFar in FP64
+// and kClassFar2 in FP32.
 enum BlockClass { kClassTable = 0, kClassFar = 1, kClassFar2 = 2, kClassGather = 3, kClassMixed = 4 };
-__host__ __device__ inline int block_class(int gap, int span, int tab_r, bool far_ok, bool fp32) {
+__host__ __device__ inline int block_class(int gap, int span, int tab_r, bool far_ok, bool fp32, int far_gap) {
     if (span <= kQuant * tab_r) return kClassTable;
     if (far_ok) {
-        if (gap > kQuant * kFarGap) return fp32 ? kClassFar2 : kClassFar;
+        if (gap > kQuant * far_gap) return fp32 ? kClassFar2 : kClassFar;
     } else if (gap > kQuant * tab_r) {
         return kClassGather;
     }
@@ -107,6 +109,13 @@ struct SumTables {
     int full_r = 0;
     int tab_r64 = 0, tab_r32 = 0;            // LDS radii: min(build radius, full_r)
     bool far_field = false;                  // sigma == 0: expansion beyond the LDS table
+    bool yukawa32 = false;                   // sigma > 0, FP32: the checked Yukawa-form expansion
+    double kappa = 0.0;                      // sqrt(s)
+    double yukawa_err = -1.0;                // its largest relative error beyond tab_r32 (when checked)
+    bool far32() const { return far_field || yukawa32; }
+    bool far64() const { return far_field; }
+    int far_gap32() const { return far_field ? kFarGap : tab_r32; }
+    int far_gap64() const { return kFarGap; }
 };
 
 // Work list of one (targets, sources) pair: items (64-target tile, source chunk), ordered by
@@ -133,5 +142,8 @@ int lgf_sum_launch(const PointSet& T, const PointSet& S, const void* w, int nrhs
                    int grid, hipStream_t st, const int32_t* skip = nullptr);
 void lgf_eval_launch(const int32_t* off, int64_t count, double* out, int prec, const SumTables& tabs,
                      hipStream_t st);
+// Largest relative difference between the sigma > 0 far-field form (evaluated in FP64) and
+// the exact table over every offset with max-norm in (from_r, R]; host result.
+double yukawa_check(const double* table, int R, int from_r, double kappa, hipStream_t st);
 
 }  // namespace bae

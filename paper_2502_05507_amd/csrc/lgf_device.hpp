@@ -80,6 +80,39 @@ __device__ __forceinline__ double far_field_q4(double X, double Y, double Z) {
     return rinv * B;
 }
 
+// sigma > 0 (s = kappa^2 in lattice units), FP32: the same Fourier-symbol expansion with
+// 1/(s + |theta|^2)^k in place of 1/|theta|^(2k) gives, with u = kappa |n|,
+//   G_s(n) = e^(-u) / (4 pi |n|) [1 + T2 + O(|n|^-4)],
+//   T2 = [(1 + u)(1 - 5x)/4 - u^2 x/2 + u^3 (1 - 2x)/24] / |n|^2,
+// which at u = 0 is the q = 2 term above.  The expansion is asymptotic in 1/|n| at fixed u
+// only while kappa is small, so a context uses it only after checking it against its own
+// exact table at every offset beyond the LDS radius.  kq = kappa / kQuant and
+// yk = -kappa log2(e) / kQuant (quantised offsets: |D| = kQuant |n|).
+template <typename Real>
+__device__ __forceinline__ Real far_field_yukawa(Real X, Real Y, Real Z, Real kq, Real yk) {
+    constexpr double kLog2C = -1.6514961294723187;   // log2(kQuant / (4 pi)) = log2(1 / pi)
+    const Real r2 = X + Y + Z;
+    const Real e2 = fma(X, Y + Z, Y * Z);
+    Real rinv, ex;
+    if constexpr (sizeof(Real) == 4) {
+        rinv = __builtin_amdgcn_rsqf(r2);
+    } else {
+        rinv = rsqrt(r2);
+    }
+    const Real rho = rinv * rinv;
+    const Real x = e2 * rho * rho;
+    const Real rq = r2 * rinv;
+    const Real u = rq * kq;
+    if constexpr (sizeof(Real) == 4) ex = __builtin_amdgcn_exp2f(fmaf(rq, yk, float(kLog2C)));
+    else ex = exp2(fma(rq, yk, kLog2C));
+    // kQuant^2 = 16 folded into the bracket (rho is 1/|D|^2 = 1/(16 |n|^2))
+    const Real A = fma(Real(-20), x, Real(4));
+    const Real c2 = Real(-8) * x;
+    const Real c3 = fma(Real(-4.0 / 3.0), x, Real(2.0 / 3.0));
+    const Real br = fma(u, fma(u, fma(u, c3, c2), A), A);
+    return ex * rinv * fma(rho, br, Real(1));
+}
+
 template <typename Real>
 __device__ __forceinline__ Real far_field(Real X, Real Y, Real Z) {
     if constexpr (sizeof(Real) == 4) return far_field_q2(X, Y, Z);
@@ -221,7 +254,10 @@ struct SumArgs {
     const Real* full_tab;             // full table (sigma > 0): radius full_r
     int tab_r;                        // LDS table radius used (<= the kernel's tab_radius)
     int full_r;
-    int far_ok;
+    int far_ok;                       // a far field is valid beyond far_gap (and beyond tab_r)
+    int far_gap;                      // smallest far-block gap (lattice units)
+    int yukawa;                       // the far field is the sigma > 0 form (kq, yk)
+    Real kq, yk;
     double* part;
     int64_t ldp;
 };
@@ -325,7 +361,7 @@ __device__ __forceinline__ void sum_tile(const SumArgs<Real>& a, const Lds<Real>
                   bz1 = ldu(bb, 5);
         const int gap = max(max(max(bx0 - hx, lx - bx1), max(by0 - hy, ly - by1)), max(max(bz0 - hz, lz - bz1), 0));
         const int span = max(max(max(bx1 - lx, hx - bx0), max(by1 - ly, hy - by0)), max(bz1 - lz, hz - bz0));
-        const int cls = block_class(gap, span, a.tab_r, a.far_ok != 0, sizeof(Real) == 4);
+        const int cls = block_class(gap, span, a.tab_r, a.far_ok != 0, sizeof(Real) == 4, a.far_gap);
         const int sb = b * kSourceBlock;        // blocks are full: the source arrays are padded
         if (cls == kClassTable) {
             for (int s0 = sb; s0 < sb + kSourceBlock; s0 += U) {
@@ -337,13 +373,24 @@ __device__ __forceinline__ void sum_tile(const SumArgs<Real>& a, const Lds<Real>
 #pragma unroll
                     for (int r = 0; r < NR; ++r) acc[r].add(G[u] * st.w[r][u]);
             }
-        } else if (cls == kClassFar || cls == kClassFar2) {
+        } else if ((cls == kClassFar || cls == kClassFar2) && !a.yukawa) {
             for (int s0 = sb; s0 < sb + kSourceBlock; s0 += U) {
                 const Step<Real, NR> st = load_step<Real, NR, false, true>(a, s0);
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const Real dx = fx - st.xr[u], dy = fy - st.yr[u], dz = fz - st.zr[u];
                     const Real G = far_field<Real>(dx * dx, dy * dy, dz * dz);
+#pragma unroll
+                    for (int r = 0; r < NR; ++r) acc[r].add(G * st.w[r][u]);
+                }
+            }
+        } else if (cls == kClassFar || cls == kClassFar2) {
+            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += U) {
+                const Step<Real, NR> st = load_step<Real, NR, false, true>(a, s0);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const Real dx = fx - st.xr[u], dy = fy - st.yr[u], dz = fz - st.zr[u];
+                    const Real G = far_field_yukawa<Real>(dx * dx, dy * dy, dz * dz, a.kq, a.yk);
 #pragma unroll
                     for (int r = 0; r < NR; ++r) acc[r].add(G * st.w[r][u]);
                 }
@@ -369,7 +416,8 @@ __device__ __forceinline__ void sum_tile(const SumArgs<Real>& a, const Lds<Real>
                         G = lds_value(L, table_offset(L, da, db, dc));
                     } else if (a.far_ok) {
                         const Real dx = fx - st.xr[u], dy = fy - st.yr[u], dz = fz - st.zr[u];
-                        G = far_field<Real>(dx * dx, dy * dy, dz * dz);
+                        G = a.yukawa ? far_field_yukawa<Real>(dx * dx, dy * dy, dz * dz, a.kq, a.yk)
+                                     : far_field<Real>(dx * dx, dy * dy, dz * dz);
                     } else {
                         G = global_value(a.full_tab, table_offset(L, da, db, dc));
                     }

@@ -100,22 +100,53 @@ __global__ __launch_bounds__(THREADS) void lgf_sum_kernel(const SumArgs<Real> a,
 
 template <typename Real>
 __global__ void lgf_eval_kernel(const int32_t* __restrict__ off, int64_t count, const Real* __restrict__ tab,
-                                int tab_r, int full_r, int far_ok, double* __restrict__ out) {
+                                int tab_r, int full_r, int far_ok, int yukawa, Real kq, Real yk,
+                                double* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     const int64_t a = abs(off[3 * i]), b = abs(off[3 * i + 1]), c = abs(off[3 * i + 2]);
     const int64_t m = max(a, max(b, c));
-    if (m > full_r && !far_ok) {
-        out[i] = __builtin_nan("");
-        return;
-    }
     if (m > tab_r && far_ok) {
         const Real X = Real(kQuant * a), Y = Real(kQuant * b), Z = Real(kQuant * c);
-        out[i] = (double)far_field<Real>(X * X, Y * Y, Z * Z);
+        out[i] = yukawa ? (double)far_field_yukawa<Real>(X * X, Y * Y, Z * Z, kq, yk)
+                        : (double)far_field<Real>(X * X, Y * Y, Z * Z);
+        return;
+    }
+    if (m > full_r) {
+        out[i] = __builtin_nan("");
         return;
     }
     const int64_t lo = min(a, min(b, c)), hi = m, mid = a + b + c - lo - hi;
     out[i] = (double)tab[hi * (hi + 1) * (hi + 2) / 6 + mid * (mid + 1) / 2 + lo];
+}
+
+// Relative difference of the sigma > 0 far-field form (in FP64) and the table, over every
+// entry whose largest index lies in (from_r, R]; one maximum per block.
+__global__ void yukawa_check_kernel(const double* __restrict__ tab, int64_t e0, int64_t e1, double kq, double yk,
+                                    double* __restrict__ block_max) {
+    __shared__ double sh[256];
+    double worst = 0.0;
+    for (int64_t e = e0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < e1; e += (int64_t)gridDim.x * blockDim.x) {
+        // invert the sorted index e = c(c+1)(c+2)/6 + b(b+1)/2 + a
+        int64_t c = (int64_t)cbrt(6.0 * (double)e);
+        while (c * (c + 1) * (c + 2) / 6 > e) --c;
+        while ((c + 1) * (c + 2) * (c + 3) / 6 <= e) ++c;
+        const int64_t rem = e - c * (c + 1) * (c + 2) / 6;
+        int64_t b = (int64_t)sqrt(2.0 * (double)rem);
+        while (b * (b + 1) / 2 > rem) --b;
+        while ((b + 1) * (b + 2) / 2 <= rem) ++b;
+        const int64_t a = rem - b * (b + 1) / 2;
+        const double X = double(kQuant * a), Y = double(kQuant * b), Z = double(kQuant * c);
+        const double f = far_field_yukawa<double>(X * X, Y * Y, Z * Z, kq, yk);
+        worst = fmax(worst, fabs(f - tab[e]) / fabs(tab[e]));
+    }
+    sh[threadIdx.x] = worst;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) block_max[blockIdx.x] = sh[0];
 }
 
 // ------------------------------------------------------------------ 16-RHS blocked form on MFMA
@@ -191,7 +222,7 @@ __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real
                             max(max(bb[2] - hz, lz - bb[5]), 0));
         const int span = max(max(max(bb[3] - lx, hx - bb[0]), max(bb[4] - ly, hy - bb[1])),
                              max(bb[5] - lz, hz - bb[2]));
-        const int cls = block_class(gap, span, a.tab_r, a.far_ok != 0, sizeof(Real) == 4);
+        const int cls = block_class(gap, span, a.tab_r, a.far_ok != 0, sizeof(Real) == 4, a.far_gap);
         V blk[kTiles];
 #pragma unroll
         for (int j = 0; j < kTiles; ++j)
@@ -202,10 +233,18 @@ __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real
             Real G[kTiles];
             if (cls == kClassFar || cls == kClassFar2) {
                 const Real sx = a.sxr[s], sy = a.syr[s], sz = a.szr[s];
+                if (a.yukawa) {
 #pragma unroll
-                for (int j = 0; j < kTiles; ++j) {
-                    const Real dx = fx[j] - sx, dy = fy[j] - sy, dz = fz[j] - sz;
-                    G[j] = far_field<Real>(dx * dx, dy * dy, dz * dz);
+                    for (int j = 0; j < kTiles; ++j) {
+                        const Real dx = fx[j] - sx, dy = fy[j] - sy, dz = fz[j] - sz;
+                        G[j] = far_field_yukawa<Real>(dx * dx, dy * dy, dz * dz, a.kq, a.yk);
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < kTiles; ++j) {
+                        const Real dx = fx[j] - sx, dy = fy[j] - sy, dz = fz[j] - sz;
+                        G[j] = far_field<Real>(dx * dx, dy * dy, dz * dz);
+                    }
                 }
             } else {
                 const uint32_t sx = a.sx[s], sy = a.sy[s], sz = a.sz[s];
@@ -227,7 +266,8 @@ __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real
                             G[j] = lds_value(L, table_offset(L, da, db, dc));
                         } else if (a.far_ok) {
                             const Real dx = fx[j] - a.sxr[s], dy = fy[j] - a.syr[s], dz = fz[j] - a.szr[s];
-                            G[j] = far_field<Real>(dx * dx, dy * dy, dz * dz);
+                            G[j] = a.yukawa ? far_field_yukawa<Real>(dx * dx, dy * dy, dz * dz, a.kq, a.yk)
+                                            : far_field<Real>(dx * dx, dy * dy, dz * dz);
                         } else {
                             G[j] = global_value(a.full_tab, table_offset(L, da, db, dc));
                         }
@@ -291,8 +331,11 @@ constexpr int rhs4_threads() { return sizeof(Real) == 4 ? kSumThreads : kSumThre
 
 template <typename Real>
 void launch_all(const PointSet& T, const PointSet& S, const Real* w, int nrhs, const Real* near, const Real* full,
-                int tab_r, int full_r, bool far, const SumPlan& plan, double* part, int grid, const int32_t* skip,
+                int tab_r, const SumTables& tabs, const SumPlan& plan, double* part, int grid, const int32_t* skip,
                 hipStream_t st) {
+    const bool fp32 = sizeof(Real) == 4;
+    const bool far = fp32 ? tabs.far32() : tabs.far64();
+    const bool lds_far = tabs.far_field;   // the sigma = 0 LDS layout (short index arrays)
     SumArgs<Real> a;
     a.tx = T.x;
     a.ty = T.y;
@@ -312,8 +355,12 @@ void launch_all(const PointSet& T, const PointSet& S, const Real* w, int nrhs, c
     a.near_tab = near;
     a.full_tab = full;
     a.tab_r = tab_r;
-    a.full_r = full_r;
+    a.full_r = tabs.full_r;
     a.far_ok = far ? 1 : 0;
+    a.far_gap = fp32 ? tabs.far_gap32() : tabs.far_gap64();
+    a.yukawa = fp32 && tabs.yukawa32 ? 1 : 0;
+    a.kq = (Real)(tabs.kappa / kQuant);
+    a.yk = (Real)(-tabs.kappa * 1.4426950408889634 / kQuant);
     a.ldp = (int64_t)plan.chunks * T.count;
     int r = 0;
     while (r < nrhs) {
@@ -325,15 +372,15 @@ void launch_all(const PointSet& T, const PointSet& S, const Real* w, int nrhs, c
         const uint32_t waves = (uint32_t)grid * (uint32_t)(threads / 64);
         const Sched q{skip, plan.items, plan.counter, (uint32_t)plan.nitems, plan.nitems > (int64_t)waves ? 1 : 0};
         if (left >= 16) {
-            if (far) lgf_sum_mfma_kernel<Real, mfma_threads<Real>(), true><<<grid, mfma_threads<Real>(), 0, st>>>(ar, q);
+            if (lds_far) lgf_sum_mfma_kernel<Real, mfma_threads<Real>(), true><<<grid, mfma_threads<Real>(), 0, st>>>(ar, q);
             else lgf_sum_mfma_kernel<Real, mfma_threads<Real>(), false><<<grid, mfma_threads<Real>(), 0, st>>>(ar, q);
             r += 16;
         } else if (left >= 4) {
-            if (far) lgf_sum_kernel<Real, 4, rhs4_threads<Real>(), true><<<grid, rhs4_threads<Real>(), 0, st>>>(ar, q);
+            if (lds_far) lgf_sum_kernel<Real, 4, rhs4_threads<Real>(), true><<<grid, rhs4_threads<Real>(), 0, st>>>(ar, q);
             else lgf_sum_kernel<Real, 4, rhs4_threads<Real>(), false><<<grid, rhs4_threads<Real>(), 0, st>>>(ar, q);
             r += 4;
         } else {
-            if (far) lgf_sum_kernel<Real, 1, kSumThreads, true><<<grid, kSumThreads, 0, st>>>(ar, q);
+            if (lds_far) lgf_sum_kernel<Real, 1, kSumThreads, true><<<grid, kSumThreads, 0, st>>>(ar, q);
             else lgf_sum_kernel<Real, 1, kSumThreads, false><<<grid, kSumThreads, 0, st>>>(ar, q);
             r += 1;
         }
@@ -402,8 +449,8 @@ void plan_sum(const PointSet& T, const PointSet& S, const SumTables& tabs, SumPl
                     span = std::max(span, std::max(bb[3 + a] - lo[a], hi[a] - bb[a]));
                 }
                 const int64_t pairs = tcount * std::min<int64_t>(kSourceBlock, S.count - b * kSourceBlock);
-                const int c32 = block_class(gap, span, tabs.tab_r32, tabs.far_field, true);
-                const int c64 = block_class(gap, span, tabs.tab_r64, tabs.far_field, false);
+                const int c32 = block_class(gap, span, tabs.tab_r32, tabs.far32(), true, tabs.far_gap32());
+                const int c64 = block_class(gap, span, tabs.tab_r64, tabs.far64(), false, tabs.far_gap64());
                 plan.class_pairs[1][c32] += pairs;
                 plan.class_pairs[0][c64] += pairs;
                 cost[tl * plan.chunks + b / plan.blk_per_chunk] += kClassCost[c32] * (double)pairs;
@@ -432,24 +479,45 @@ int lgf_sum_launch(const PointSet& T, const PointSet& S, const void* w, int nrhs
         return chunks;
     }
     if (prec == BAE_PREC_FP64)
-        launch_all<double>(T, S, (const double*)w, nrhs, tabs.near64, tabs.full64, tabs.tab_r64, tabs.full_r,
-                           tabs.far_field, plan, part, grid, skip, st);
+        launch_all<double>(T, S, (const double*)w, nrhs, tabs.near64, tabs.full64, tabs.tab_r64, tabs, plan, part,
+                           grid, skip, st);
     else
-        launch_all<float>(T, S, (const float*)w, nrhs, tabs.near32, tabs.full32, tabs.tab_r32, tabs.full_r,
-                          tabs.far_field, plan, part, grid, skip, st);
+        launch_all<float>(T, S, (const float*)w, nrhs, tabs.near32, tabs.full32, tabs.tab_r32, tabs, plan, part,
+                          grid, skip, st);
     return chunks;
 }
 
 void lgf_eval_launch(const int32_t* off, int64_t count, double* out, int prec, const SumTables& tabs, hipStream_t st) {
     if (count == 0) return;
     const unsigned blocks = (unsigned)((count + 255) / 256);
+    const double kq = tabs.kappa / kQuant, yk = -tabs.kappa * 1.4426950408889634 / kQuant;
     if (prec == BAE_PREC_FP64)
         lgf_eval_kernel<double><<<blocks, 256, 0, st>>>(off, count, tabs.full64, tabs.tab_r64, tabs.full_r,
-                                                        tabs.far_field ? 1 : 0, out);
+                                                        tabs.far64() ? 1 : 0, 0, kq, yk, out);
     else
         lgf_eval_kernel<float><<<blocks, 256, 0, st>>>(off, count, tabs.full32, tabs.tab_r32, tabs.full_r,
-                                                       tabs.far_field ? 1 : 0, out);
+                                                       tabs.far32() ? 1 : 0, tabs.yukawa32 ? 1 : 0, (float)kq,
+                                                       (float)yk, out);
     BAE_HIP_CHECK(hipGetLastError());
+}
+
+double yukawa_check(const double* table, int R, int from_r, double kappa, hipStream_t st) {
+    if (R <= from_r) return 0.0;
+    const int64_t e0 = table_size(from_r), e1 = table_size(R);
+    const int blocks = (int)std::min<int64_t>(1024, (e1 - e0 + 255) / 256);
+    double* dmax = nullptr;
+    BAE_HIP_CHECK(hipMalloc(&dmax, sizeof(double) * blocks));
+    yukawa_check_kernel<<<blocks, 256, 0, st>>>(table, e0, e1, kappa / kQuant, -kappa * 1.4426950408889634 / kQuant,
+                                                dmax);
+    std::vector<double> h(blocks);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), dmax, sizeof(double) * blocks, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(dmax);
+    if (e != hipSuccess) throw Error{BAE_ERR_HIP, std::string("far-field check: ") + hipGetErrorString(e)};
+    double worst = 0.0;
+    for (double v : h) worst = std::max(worst, v);
+    return worst;
 }
 
 }  // namespace bae

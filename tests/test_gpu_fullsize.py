@@ -86,3 +86,7 @@ def test_helmholtz_star_257_sixteen_rhs_sampled():
             out = v.cpu().numpy()[:, pick]
             for r in range(16):
                 assert rel_l2(out[r], ref[r]) < tol
+        # kappa^2 h^2 = 1.5e-4: the FP32 sum takes the Yukawa-form far field beyond the LDS
+        # radius (all but the nearest pairs); FP64 reads the exact table
+        assert ctx.sum_stats(P.PREC_FP32)["far_q2"] > 0.75 * z["n_targets"] * z["n_sources"]
+        assert ctx.sum_stats(P.PREC_FP64)["far_q2"] == 0

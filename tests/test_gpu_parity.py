@@ -84,6 +84,31 @@ def test_kernel_values_match_oracle(prec, tol):
     assert np.all(np.abs(gpu - ref) <= tol * ref), np.max(np.abs(gpu - ref) / ref)
 
 
+@pytest.mark.parametrize("sigma,far32", [(10.0, True), (30.0, True), (200.0, False)])
+def test_kernel_values_sigma_positive(sigma, far32):
+    """sigma > 0: FP64 reads the exact table everywhere; FP32 uses the Yukawa-form far field
+    beyond the LDS radius when the context's check accepts it (small kappa), else the table."""
+    torch = torch_mod()
+    p = small_problem("sphere", 97, sigma)
+    s = sigma * p.h ** 2
+    with P.Context.from_problem(p) as ctx:
+        R = ctx.sizes["max_offset"]
+        rng = np.random.default_rng(12)
+        off = rng.integers(-R, R + 1, size=(4000, 3)).astype(np.int32)
+        off[:6] = [[R, 0, 0], [0, R, 0], [56, 0, 0], [56, 56, 56], [R, R, R], [0, 0, 0]]
+        ref = lgf.LGFTable(R, s)(off.astype(np.int64))
+        o = torch.from_numpy(off).to(device())
+        out = torch.empty(len(off), dtype=torch.float64, device=device())
+        for prec, tol in ((P.PREC_FP64, 1e-13), (P.PREC_FP32, 2e-6 if far32 else 1e-7)):
+            ctx.lgf_eval(o, out, prec)
+            torch.cuda.synchronize()
+            gpu = out.cpu().numpy()
+            assert np.all(np.abs(gpu - ref) <= tol * ref), (prec, np.max(np.abs(gpu - ref) / ref))
+        st32, st64 = ctx.sum_stats(P.PREC_FP32), ctx.sum_stats(P.PREC_FP64)
+    assert st64["far_q2"] == 0
+    assert (st32["far_q2"] > 0) == far32
+
+
 # ------------------------------------------------------------------ A5-A7: double layer and operator
 CASES = [("sphere", 33, 0.0), ("ellipsoid", 65, 0.0), ("torus", 41, 10.0), ("sphere", 97, 30.0),
          ("star", 57, 0.0)]

@@ -55,7 +55,7 @@ OPS = {"fp32": {"near": 8, "far": 19, "far_q2": 19, "mixed_near": 10, "mixed_far
 # (x2.00) and WRITE_SIZE (x1.00) runs calibrated on 256 MiB copies
 # (profiles/lgf_sum_poisson_ellipsoid_129_counters.md); valid only for the kernel sources
 # it was measured on, identified by their hash.
-MEASURED_TRAFFIC = {"sources_sha256_16": "bdd72b08175a8978", "bytes": (10715 * 2.0 + 4165 * 1.0) * 1024}
+MEASURED_TRAFFIC = {"sources_sha256_16": "25f5994f7b19c41f", "bytes": (11956.0 * 2.0 + 17701.3 * 1.0) * 1024}
 KERNEL_SOURCES = ("paper_2502_05507_amd/csrc/lgf_sum.hip", "paper_2502_05507_amd/csrc/lgf_device.hpp")
 
 

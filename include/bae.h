@@ -93,6 +93,13 @@ typedef struct bae_sizes {
     int32_t table_radius;      /* radius of the resident FP64 table                  */
     int64_t table_entries;
     int64_t device_bytes;      /* device memory held by the context                 */
+    int32_t lds_radius_fp32;   /* offsets up to this max-norm come from the LDS table */
+    int32_t lds_radius_fp64;
+    int32_t far_field_fp32;    /* 1: the FP32 sum uses a far-field expansion beyond  */
+    int32_t far_field_fp64;    /*    the LDS radius (sigma = 0, or the checked        */
+                               /*    sigma > 0 form in FP32); 0: the exact table      */
+    double far_field_err_fp32; /* sigma > 0: largest relative error of that form      */
+                               /* against the context's table (-1 when not checked)   */
 } bae_sizes;
 
 typedef struct bae_solve_params {

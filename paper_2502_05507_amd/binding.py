@@ -37,7 +37,9 @@ class Sizes(C.Structure):
     _fields_ = [("n_mplus", C.c_int64), ("n_gamma_plus", C.c_int64), ("n_gamma_minus", C.c_int64),
                 ("n_ext", C.c_int64), ("n_edges", C.c_int64), ("n_sources", C.c_int64),
                 ("n_targets", C.c_int64), ("n_empty_d", C.c_int64), ("max_offset", C.c_int32),
-                ("table_radius", C.c_int32), ("table_entries", C.c_int64), ("device_bytes", C.c_int64)]
+                ("table_radius", C.c_int32), ("table_entries", C.c_int64), ("device_bytes", C.c_int64),
+                ("lds_radius_fp32", C.c_int32), ("lds_radius_fp64", C.c_int32), ("far_field_fp32", C.c_int32),
+                ("far_field_fp64", C.c_int32), ("far_field_err_fp32", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

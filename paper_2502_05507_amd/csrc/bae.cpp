@@ -513,6 +513,11 @@ int bae_get_sizes(const bae_ctx* c, bae_sizes* o) {
         o->max_offset = c->geo.max_offset;
         o->table_radius = c->tabs.full_r;
         o->table_entries = table_size(c->tabs.full_r);
+        o->lds_radius_fp32 = c->tabs.tab_r32;
+        o->lds_radius_fp64 = c->tabs.tab_r64;
+        o->far_field_fp32 = c->tabs.far32() ? 1 : 0;
+        o->far_field_fp64 = c->tabs.far64() ? 1 : 0;
+        o->far_field_err_fp32 = c->tabs.yukawa_err;
         size_t bytes = 0;
         for (const DevMem* d : {&c->T.x, &c->T.y, &c->T.z, &c->S.x, &c->S.y, &c->S.z, &c->Mp.x, &c->Mp.y, &c->Mp.z,
                                 &c->T.xf, &c->T.yf, &c->T.zf, &c->S.xf, &c->S.yf, &c->S.zf, &c->Mp.xf, &c->Mp.yf,

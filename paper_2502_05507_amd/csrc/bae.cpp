@@ -122,23 +122,28 @@ static GmresOut gmres(bae_ctx* c, const double* r0, int nrhs, int prec, double t
     hipEvent_t ev[2] = {nullptr, nullptr};
     if (lagged)
         for (auto& e : ev) BAE_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    // Step k: LGF sum of the weights of V[k] (formed by step k-1's closing launch, or here
+    // for k = 0), closure into the work vector, CGS2, then one closing launch that scales
+    // the work vector into V[k+1], forms the next weights from it and updates Givens.
+    double* wv = c->tmp.as<double>();
+    double* pA = c->dotpart.as<double>();
+    double* pB = pA + (int64_t)nrhs * c->maxj * dot_blocks(n);
+    double* pN = pB + (int64_t)nrhs * c->maxj * dot_blocks(n);
+    launch_weights(c->B, K.V, K.ld_rhs, c->w.p, c->S.ps.padded, nrhs, prec, st);
     int k = 0;
     for (; k < m; ++k) {
-        double* vk = K.V + (int64_t)k * n;
-        double* vk1 = K.V + (int64_t)(k + 1) * n;
-        bae_operator(c, vk, K.ld_rhs, vk1, K.ld_rhs, nrhs, prec, st, lagged ? K.done : nullptr);
+        int chunks = 0;
+        apply_lgf(c, c->T.ps, c->S.ps, c->w.p, nrhs, prec, c->part.as<double>(), c->part_cap, &chunks, st,
+                  lagged ? K.done : nullptr);
+        launch_closure(c->part.as<double>(), chunks, c->nT, c->cl, wv, n, nrhs, c->vsum.as<double>(), st);
         (*matvecs)++;
         // classical Gram-Schmidt twice (dot-product slices in pA, pB); the second pass also
-        // forms the slices of ||w||^2 (pN), which normalize and Givens sum themselves
-        double* pA = c->dotpart.as<double>();
-        double* pB = pA + (int64_t)nrhs * c->maxj * dot_blocks(n);
-        double* pN = pB + (int64_t)nrhs * c->maxj * dot_blocks(n);
-        launch_dot_slices(K.V, n, K.ld_rhs, k + 1, vk1, K.ld_rhs, n, nrhs, K.done, pA, c->maxj, st);
-        launch_subtract_combination(K.V, n, K.ld_rhs, pA, c->maxj, k + 1, n, nrhs, K.done, vk1, K.ld_rhs, nullptr, st);
-        launch_dot_slices(K.V, n, K.ld_rhs, k + 1, vk1, K.ld_rhs, n, nrhs, K.done, pB, c->maxj, st);
-        launch_subtract_combination(K.V, n, K.ld_rhs, pB, c->maxj, k + 1, n, nrhs, K.done, vk1, K.ld_rhs, pN, st);
-        launch_normalize(K.V, n, K.ld_rhs, k, n, pN, K.done, nrhs, st);
-        launch_givens(K, pA, pB, c->maxj, pN, k, tol, nrhs, st);
+        // forms the slices of ||w||^2 (pN), which the closing launch sums itself
+        launch_dot_slices(K.V, n, K.ld_rhs, k + 1, wv, n, n, nrhs, K.done, pA, c->maxj, st);
+        launch_subtract_combination(K.V, n, K.ld_rhs, pA, c->maxj, k + 1, n, nrhs, K.done, wv, n, nullptr, st);
+        launch_dot_slices(K.V, n, K.ld_rhs, k + 1, wv, n, n, nrhs, K.done, pB, c->maxj, st);
+        launch_subtract_combination(K.V, n, K.ld_rhs, pB, c->maxj, k + 1, n, nrhs, K.done, wv, n, pN, st);
+        launch_finish(K, wv, n, pA, pB, c->maxj, pN, k, tol, c->B, c->w.p, c->S.ps.padded, prec, nrhs, st);
         if (lagged) {
             BAE_HIP_CHECK(hipMemcpyAsync(c->pinned_flags + (k & 1), K.done, sizeof(int32_t), hipMemcpyDeviceToHost, st));
             BAE_HIP_CHECK(hipEventRecord(ev[k & 1], st));

@@ -163,53 +163,109 @@ __global__ void normalize_kernel(double* __restrict__ V, int64_t ldv_vec, int64_
     if (i < n && nr > 0.0) V[r * ldv_rhs + (int64_t)(k + 1) * ldv_vec + i] /= nr;
 }
 
-// One block per RHS: Givens update of column k (Saad-Schultz), residual estimate,
+// Givens update of column k (Saad-Schultz) for RHS r by one block, residual estimate,
 // convergence / breakdown flag.  H is column-major per RHS: H[r][k][i], i <= k+1.  The
 // column is the sum of the two Gram-Schmidt passes' coefficients, each the sum of its nb
 // dot-product slices (pA, pB; summed by the block's threads); H[k+1][k] = ||w|| from the nn
 // norm slices.  The rotations themselves are sequential (thread 0).
-__global__ void givens_kernel(double* __restrict__ Hc, int64_t ldh_col, int64_t ldh_rhs,
-                              const double* __restrict__ pA, const double* __restrict__ pB, int nb, int maxj,
-                              const double* __restrict__ npart, int nn,
-                              double* __restrict__ cs, double* __restrict__ sn, int64_t ldcs,
-                              double* __restrict__ g, int64_t ldg, const double* __restrict__ beta,
-                              double* __restrict__ hist, int64_t ldhist, int32_t* __restrict__ done,
-                              int32_t* __restrict__ kdone, int k, double tol) {
+struct GivensArgs {
+    double* Hc;
+    int64_t ldh_col, ldh_rhs;
+    const double *pA, *pB;
+    int nb, maxj;
+    const double* npart;
+    int nn;
+    double *cs, *sn;
+    int64_t ldcs;
+    double* g;
+    int64_t ldg;
+    const double* beta;
+    double* hist;
+    int64_t ldhist;
+    int32_t *done, *kdone;
+    int k;
+    double tol;
+};
+
+__device__ void givens_block(const GivensArgs& a, int r) {
     __shared__ double hk1s;
-    const int r = blockIdx.x;
-    if (done[r]) return;
-    double* h = Hc + r * ldh_rhs + (int64_t)k * ldh_col;
+    const int k = a.k;
+    double* h = a.Hc + r * a.ldh_rhs + (int64_t)k * a.ldh_col;
     for (int i = threadIdx.x; i <= k; i += blockDim.x)
-        h[i] = slice_sum(pA + ((int64_t)r * maxj + i) * nb, nb) + slice_sum(pB + ((int64_t)r * maxj + i) * nb, nb);
-    if (threadIdx.x == 0) hk1s = sqrt(slice_sum(npart + (int64_t)r * nn, nn));
+        h[i] = slice_sum(a.pA + ((int64_t)r * a.maxj + i) * a.nb, a.nb) +
+               slice_sum(a.pB + ((int64_t)r * a.maxj + i) * a.nb, a.nb);
+    if (threadIdx.x == 0) hk1s = sqrt(slice_sum(a.npart + (int64_t)r * a.nn, a.nn));
     __syncthreads();
     if (threadIdx.x != 0) return;
     const double hk1 = hk1s;
-    double* c = cs + r * ldcs;
-    double* s = sn + r * ldcs;
+    double* c = a.cs + r * a.ldcs;
+    double* s = a.sn + r * a.ldcs;
     for (int i = 0; i < k; ++i) {
-        const double a = h[i], b = h[i + 1];
-        h[i] = c[i] * a + s[i] * b;
-        h[i + 1] = -s[i] * a + c[i] * b;
+        const double x = h[i], y = h[i + 1];
+        h[i] = c[i] * x + s[i] * y;
+        h[i + 1] = -s[i] * x + c[i] * y;
     }
-    const double a = h[k], b = hk1;
-    const double rr = hypot(a, b);
-    double* gr = g + r * ldg;
+    const double x = h[k], y = hk1;
+    const double rr = hypot(x, y);
+    double* gr = a.g + r * a.ldg;
     if (rr == 0.0) {          // exact breakdown of a singular system: stop here
-        done[r] = 1;
-        kdone[r] = k;
+        a.done[r] = 1;
+        a.kdone[r] = k;
         return;
     }
-    c[k] = a / rr;
-    s[k] = b / rr;
+    c[k] = x / rr;
+    s[k] = y / rr;
     h[k] = rr;
     h[k + 1] = 0.0;
     gr[k + 1] = -s[k] * gr[k];
     gr[k] = c[k] * gr[k];
-    const double est = fabs(gr[k + 1]) / beta[r];
-    hist[r * ldhist + k] = est;
-    kdone[r] = k + 1;
-    if (est <= tol || hk1 == 0.0) done[r] = 1;
+    const double est = fabs(gr[k + 1]) / a.beta[r];
+    a.hist[r * a.ldhist + k] = est;
+    a.kdone[r] = k + 1;
+    if (est <= a.tol || hk1 == 0.0) a.done[r] = 1;
+}
+
+__global__ void givens_kernel(const GivensArgs a) {
+    const int r = blockIdx.x;
+    if (a.done[r]) return;
+    givens_block(a, r);
+}
+
+// The closing launch of an Arnoldi step (one row of blocks per RHS): the orthogonalised
+// vector w (in wv) scaled by 1/||w|| into V[k+1] (blocks [0, nbn)); the same scaled vector
+// mapped to the next operator's source weights (Sec. 3.2; blocks [nbn, nbn + nbw)), so the
+// next step starts with the LGF sum; the Givens update (last block).  ||w|| is the sum of
+// the norm slices, formed by every block alike.
+template <typename Real>
+__global__ void finish_kernel(double* __restrict__ V, int64_t ldv_vec, int64_t ldv_rhs, const double* __restrict__ wv,
+                              int64_t ldwv, int64_t n, int nbn, int nbw, const int32_t* __restrict__ rowptr,
+                              const int32_t* __restrict__ col, const double* __restrict__ coef, int64_t ns,
+                              int64_t npad, Real* __restrict__ w, int64_t ldw, const GivensArgs ga) {
+    __shared__ double inv;
+    const int r = blockIdx.y;
+    if (ga.done[r]) return;
+    const int b = blockIdx.x;
+    if (b == nbn + nbw) {
+        givens_block(ga, r);
+        return;
+    }
+    if (threadIdx.x == 0) {
+        const double nr = sqrt(slice_sum(ga.npart + (int64_t)r * ga.nn, ga.nn));
+        inv = nr > 0.0 ? 1.0 / nr : 0.0;
+    }
+    __syncthreads();
+    const double* x = wv + r * ldwv;
+    if (b < nbn) {
+        const int64_t i = (int64_t)b * blockDim.x + threadIdx.x;
+        if (i < n) V[r * ldv_rhs + (int64_t)(ga.k + 1) * ldv_vec + i] = inv > 0.0 ? x[i] * inv : x[i];
+        return;
+    }
+    const int64_t sidx = (int64_t)(b - nbn) * blockDim.x + threadIdx.x;
+    if (sidx >= npad) return;
+    double acc = 0.0;
+    if (sidx < ns)
+        for (int j = rowptr[sidx]; j < rowptr[sidx + 1]; ++j) acc = fma(coef[j], x[col[j]] * inv, acc);
+    w[r * ldw + sidx] = (Real)acc;
 }
 
 // beta = sqrt(nrm2); V[0] = r0 / beta; g[0] = beta; done = beta == 0
@@ -337,11 +393,30 @@ void launch_normalize(double* V, int64_t ldv_vec, int64_t ldv_rhs, int k, int64_
     LAUNCH_CHECK();
 }
 
+static GivensArgs givens_args(const KrylovState& K, const double* pA, const double* pB, int maxj, const double* npart,
+                              int k, double tol) {
+    return GivensArgs{K.H, K.m + 1, (int64_t)(K.m + 1) * K.m, pA, pB, dot_blocks(K.n), maxj, npart, norm_blocks(K.n),
+                      K.cs, K.sn, K.m, K.g, K.m + 1, K.beta, K.hist, K.m, K.done, K.kdone, k, tol};
+}
+
 void launch_givens(const KrylovState& K, const double* pA, const double* pB, int maxj, const double* npart, int k,
                    double tol, int nrhs, hipStream_t st) {
-    givens_kernel<<<nrhs, kThreads, 0, st>>>(K.H, K.m + 1, (int64_t)(K.m + 1) * K.m, pA, pB, dot_blocks(K.n), maxj,
-                                             npart, norm_blocks(K.n), K.cs, K.sn, K.m, K.g, K.m + 1, K.beta, K.hist,
-                                             K.m, K.done, K.kdone, k, tol);
+    givens_kernel<<<nrhs, kThreads, 0, st>>>(givens_args(K, pA, pB, maxj, npart, k, tol));
+    LAUNCH_CHECK();
+}
+
+void launch_finish(const KrylovState& K, const double* wv, int64_t ldwv, const double* pA, const double* pB, int maxj,
+                   const double* npart, int k, double tol, const CSR& B, void* w, int64_t ldw, int prec, int nrhs,
+                   hipStream_t st) {
+    const int nbn = (int)blocks_for(K.n), nbw = (int)blocks_for(B.padded_rows);
+    const dim3 grid(nbn + nbw + 1, nrhs);
+    const GivensArgs ga = givens_args(K, pA, pB, maxj, npart, k, tol);
+    if (prec == BAE_PREC_FP64)
+        finish_kernel<double><<<grid, kThreads, 0, st>>>(K.V, K.n, K.ld_rhs, wv, ldwv, K.n, nbn, nbw, B.rowptr, B.col,
+                                                          B.coef, B.rows, B.padded_rows, (double*)w, ldw, ga);
+    else
+        finish_kernel<float><<<grid, kThreads, 0, st>>>(K.V, K.n, K.ld_rhs, wv, ldwv, K.n, nbn, nbw, B.rowptr, B.col,
+                                                         B.coef, B.rows, B.padded_rows, (float*)w, ldw, ga);
     LAUNCH_CHECK();
 }
 

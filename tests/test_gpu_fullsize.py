@@ -90,3 +90,32 @@ def test_helmholtz_star_257_sixteen_rhs_sampled():
         # radius (all but the nearest pairs); FP64 reads the exact table
         assert ctx.sum_stats(P.PREC_FP32)["far_q2"] > 0.75 * z["n_targets"] * z["n_sources"]
         assert ctx.sum_stats(P.PREC_FP64)["far_q2"] == 0
+
+
+def test_helmholtz_star_257_refined_solve_satisfies_oracle_system():
+    # 16 RHS at once through the matrix-core form, FP32 sum with the Yukawa-form far field
+    # plus FP64 refinement: each density must solve the oracle's system b_r = A q_r (exact
+    # table) on sampled rows, and converge to the stated tolerance.
+    p = W.helmholtz_star()
+    g = geometry.from_problem(p)
+    s = p.sigma * p.h ** 2
+    G = lgf.LGFTable(g.max_offset(), s)
+    with P.Context.from_problem(p, max_rhs=16, max_krylov=200) as ctx:
+        xs, _, _ = ctx.boundary_points()
+        ctx.set_rhs(np.stack([p.g(xs, r) for r in range(16)]))
+        res = ctx.solve(P.SOLVE_FP32_REFINED, tol=1e-10)
+        assert all(r["converged"] and r["rel_residual_true"] <= 1e-10 for r in res)
+        rng = np.random.default_rng(6)
+        rows = np.sort(rng.choice(len(g.gamma_minus), 20, replace=False))
+        tq = g.gamma_minus[rows]
+        tp = g.gamma_plus[g.partner[rows]]
+        pts = np.concatenate([tq, tp])
+        t = g.t[rows]
+        k = len(rows)
+        for r in (0, 7, 15):
+            q = ctx.density(r)
+            v = operators.double_layer(g, G, q, pts)
+            Aq = (1 - t) * v[:k] + t * v[k:]
+            b = p.g(g.xstar[rows], r)
+            bscale = np.abs(p.g(g.xstar, r)).max()
+            assert np.abs(b - Aq).max() < 1e-8 * bscale, (r, np.abs(b - Aq).max() / bscale)

@@ -143,9 +143,9 @@ static GmresOut gmres(bae_ctx* c, const double* r0, int nrhs, int prec, double t
         launch_subtract_combination(K.V, n, K.ld_rhs, pA, c->maxj, k + 1, n, nrhs, K.done, wv, n, nullptr, st);
         launch_dot_slices(K.V, n, K.ld_rhs, k + 1, wv, n, n, nrhs, K.done, pB, c->maxj, st);
         launch_subtract_combination(K.V, n, K.ld_rhs, pB, c->maxj, k + 1, n, nrhs, K.done, wv, n, pN, st);
-        launch_finish(K, wv, n, pA, pB, c->maxj, pN, k, tol, c->B, c->w.p, c->S.ps.padded, prec, nrhs, st);
+        launch_finish(K, wv, n, pA, pB, c->maxj, pN, k, tol, c->B, c->w.p, c->S.ps.padded, prec, nrhs,
+                      lagged ? c->flags_dev + (k & 1) : nullptr, st);
         if (lagged) {
-            BAE_HIP_CHECK(hipMemcpyAsync(c->pinned_flags + (k & 1), K.done, sizeof(int32_t), hipMemcpyDeviceToHost, st));
             BAE_HIP_CHECK(hipEventRecord(ev[k & 1], st));
             if (k >= 1) {
                 BAE_HIP_CHECK(hipEventSynchronize(ev[(k - 1) & 1]));
@@ -417,7 +417,9 @@ bae_ctx* create_context(const bae_grid& gridv, const bae_options* opt, Geometry&
         c->up_gamma.alloc(sizeof(double) * c->nT * mr);
         c->u_gamma.alloc(sizeof(double) * c->nT * mr);
         c->vsum.alloc(sizeof(double) * c->nT * mr);
-        BAE_HIP_CHECK(hipHostMalloc((void**)&c->pinned_flags, sizeof(int32_t) * 2 * mr, hipHostMallocDefault));
+        BAE_HIP_CHECK(hipHostMalloc((void**)&c->pinned_flags, sizeof(int32_t) * 2 * mr,
+                                    hipHostMallocMapped | hipHostMallocCoherent));
+        BAE_HIP_CHECK(hipHostGetDevicePointer((void**)&c->flags_dev, c->pinned_flags, 0));
         // batched / served solves: idle until started (done = 1, k = 0)
         c->ctl.alloc(sizeof(Ctl));
         const Ctl idle{0, 0, 0.0};

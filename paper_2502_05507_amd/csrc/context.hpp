@@ -181,7 +181,8 @@ struct bae_ctx {
     bool has_f = false, rhs_ready = false, solved = false;
     std::vector<std::vector<double>> hist;  // per rhs
     std::vector<double> ugrid;              // [rhs][n0 n1 n2] when computed
-    int32_t* pinned_flags = nullptr;        // host pinned, 2 * max_rhs
+    int32_t* pinned_flags = nullptr;        // host pinned, coherent and mapped, 2 * max_rhs
+    int32_t* flags_dev = nullptr;           // the same memory as the device sees it
 };
 
 namespace bae {

@@ -240,15 +240,19 @@ template <typename Real>
 __global__ void finish_kernel(double* __restrict__ V, int64_t ldv_vec, int64_t ldv_rhs, const double* __restrict__ wv,
                               int64_t ldwv, int64_t n, int nbn, int nbw, const int32_t* __restrict__ rowptr,
                               const int32_t* __restrict__ col, const double* __restrict__ coef, int64_t ns,
-                              int64_t npad, Real* __restrict__ w, int64_t ldw, const GivensArgs ga) {
+                              int64_t npad, Real* __restrict__ w, int64_t ldw, const GivensArgs ga,
+                              int32_t* host_flag) {
     __shared__ double inv;
     const int r = blockIdx.y;
-    if (ga.done[r]) return;
     const int b = blockIdx.x;
     if (b == nbn + nbw) {
-        givens_block(ga, r);
+        if (!ga.done[r]) givens_block(ga, r);
+        // the convergence flag straight into host memory (no copy launch per step)
+        if (threadIdx.x == 0 && host_flag)
+            __hip_atomic_store(host_flag + r, ga.done[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         return;
     }
+    if (ga.done[r]) return;
     if (threadIdx.x == 0) {
         const double nr = sqrt(slice_sum(ga.npart + (int64_t)r * ga.nn, ga.nn));
         inv = nr > 0.0 ? 1.0 / nr : 0.0;
@@ -407,16 +411,18 @@ void launch_givens(const KrylovState& K, const double* pA, const double* pB, int
 
 void launch_finish(const KrylovState& K, const double* wv, int64_t ldwv, const double* pA, const double* pB, int maxj,
                    const double* npart, int k, double tol, const CSR& B, void* w, int64_t ldw, int prec, int nrhs,
-                   hipStream_t st) {
+                   int32_t* host_flag, hipStream_t st) {
     const int nbn = (int)blocks_for(K.n), nbw = (int)blocks_for(B.padded_rows);
     const dim3 grid(nbn + nbw + 1, nrhs);
     const GivensArgs ga = givens_args(K, pA, pB, maxj, npart, k, tol);
     if (prec == BAE_PREC_FP64)
         finish_kernel<double><<<grid, kThreads, 0, st>>>(K.V, K.n, K.ld_rhs, wv, ldwv, K.n, nbn, nbw, B.rowptr, B.col,
-                                                          B.coef, B.rows, B.padded_rows, (double*)w, ldw, ga);
+                                                          B.coef, B.rows, B.padded_rows, (double*)w, ldw, ga,
+                                                          host_flag);
     else
         finish_kernel<float><<<grid, kThreads, 0, st>>>(K.V, K.n, K.ld_rhs, wv, ldwv, K.n, nbn, nbw, B.rowptr, B.col,
-                                                         B.coef, B.rows, B.padded_rows, (float*)w, ldw, ga);
+                                                         B.coef, B.rows, B.padded_rows, (float*)w, ldw, ga,
+                                                         host_flag);
     LAUNCH_CHECK();
 }
 

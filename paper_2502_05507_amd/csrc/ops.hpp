@@ -71,9 +71,10 @@ void launch_givens(const KrylovState& K, const double* pA, const double* pB, int
                    double tol, int nrhs, hipStream_t st);
 // The closing launch of Arnoldi step k: V[k+1] = wv / ||w||, the next source weights from
 // that vector (precision prec, into w with leading dimension ldw) and the Givens update.
+// host_flag (optional, device-mapped host memory): receives done[r] of every RHS.
 void launch_finish(const KrylovState& K, const double* wv, int64_t ldwv, const double* pA, const double* pB, int maxj,
                    const double* npart, int k, double tol, const CSR& B, void* w, int64_t ldw, int prec, int nrhs,
-                   hipStream_t st);
+                   int32_t* host_flag, hipStream_t st);
 void launch_gmres_init(const double* r0, int64_t ldr, const KrylovState& K, int64_t n, const double* nrm2, int nrhs,
                        hipStream_t st);
 void launch_axpby(double a, const double* x, int64_t ldx, double b, double* y, int64_t ldy, int64_t n, int nrhs,

@@ -63,7 +63,7 @@ extern "C" {
 
 /* ------------------------------------------------------------------ structs */
 typedef struct bae_grid {
-    int32_t n[3];        /* nodes per axis (>= 5)                                   */
+    int32_t n[3];        /* nodes per axis, in [5, 2049]                            */
     double origin[3];    /* coordinates of node (0,0,0)                             */
     double h;            /* grid spacing (> 0)                                      */
     double sigma;        /* sigma = kappa^2 >= 0                                    */

@@ -439,7 +439,7 @@ int64_t estimate_context_bytes(const Geometry& G, double s, const bae_options* o
     const int64_t nT = ngp + ngm, nS = ngm + next;
     auto padded = [](int64_t n) { return ((n + kSourceBlock - 1) / kSourceBlock) * kSourceBlock; };
     int64_t b = 0;
-    b += padded(nT) * (3 * 4 + 3 * 4 + 3 * 8) + padded(nS) * (3 * 4 + 3 * 4 + 3 * 8);   // point sets
+    b += (padded(nT) + padded(nS)) * (3 * 4 + 3 * 4 + 3 * 8 + 4 + 4);                   // point sets
     b += (padded(nT) / kSourceBlock + padded(nS) / kSourceBlock) * 6 * 4;              // block boxes
     b += nT * 4 + (nS + 1) * 4 + (ngm + (int64_t)G.edge_q.size()) * 12 + ngm * 16;    // maps, CSR, closure
     b += padded(nS) * 8 * mr;                                                          // weights
@@ -529,7 +529,8 @@ int bae_get_sizes(const bae_ctx* c, bae_sizes* o) {
         for (const DevMem* d : {&c->T.x, &c->T.y, &c->T.z, &c->S.x, &c->S.y, &c->S.z, &c->Mp.x, &c->Mp.y, &c->Mp.z,
                                 &c->T.xf, &c->T.yf, &c->T.zf, &c->S.xf, &c->S.yf, &c->S.zf, &c->Mp.xf, &c->Mp.yf,
                                 &c->Mp.zf, &c->T.xd, &c->T.yd, &c->T.zd, &c->S.xd, &c->S.yd, &c->S.zd, &c->Mp.xd,
-                                &c->Mp.yd, &c->Mp.zd, &c->T.bbox, &c->S.bbox, &c->Mp.bbox,
+                                &c->Mp.yd, &c->Mp.zd, &c->T.xy16, &c->T.zl, &c->S.xy16, &c->S.zl, &c->Mp.xy16,
+                                &c->Mp.zl, &c->T.bbox, &c->S.bbox, &c->Mp.bbox,
                                 &c->t_pos, &c->csr_rowptr, &c->csr_col, &c->csr_coef, &c->cl_tq, &c->cl_tp, &c->cl_t,
                                 &c->w, &c->part, &c->kV, &c->kH, &c->kcs, &c->ksn, &c->kg, &c->khist, &c->kbeta,
                                 &c->kdone, &c->kkdone, &c->hA, &c->hB, &c->nrm, &c->dotpart, &c->ycoef, &c->b, &c->x,

@@ -507,6 +507,10 @@ void build_layout(BatchEngine* b) {
             a.sxr = sxr;
             a.syr = syr;
             a.szr = szr;
+            a.txy = c->T.ps.xy16;
+            a.tzl = c->T.ps.zl;
+            a.sxy = c->S.ps.xy16;
+            a.szl = c->S.ps.zl;
             a.sbox = c->S.ps.bbox;
             a.ns = (int)c->nS;
             a.nblk = (int)c->S.ps.nblk;

@@ -67,8 +67,19 @@ std::shared_ptr<Table> get_table(int device, double s, int R, hipStream_t st);
 int guard(const std::function<void()>& fn);
 
 // ------------------------------------------------------------------ context
+// IEEE binary16 encoding of an integer in [0, kMaxLatticeCoord] (exact: at most 11
+// significant bits).
+inline uint16_t half_bits(int32_t v) {
+    if (v < 0 || v > kMaxLatticeCoord) throw Error{BAE_ERR_ARG, "lattice coordinate outside [0, 2048]"};
+    if (v == 0) return 0;
+    int e = 0;
+    while ((v >> (e + 1)) != 0) ++e;                                  // v in [2^e, 2^(e+1))
+    const uint32_t frac = e <= 10 ? ((uint32_t)v << (10 - e)) & 0x3FFu : ((uint32_t)v >> (e - 10)) & 0x3FFu;
+    return (uint16_t)(((uint32_t)(e + 15) << 10) | frac);
+}
+
 struct PointBuf {
-    DevMem x, y, z, xf, yf, zf, xd, yd, zd, bbox;
+    DevMem x, y, z, xf, yf, zf, xd, yd, zd, xy16, zl, bbox;
     PointSet ps;
     std::vector<int32_t> perm;   // internal index -> index in the lexicographic list
     // pts3: lattice points (3 * count, AoS); order: the internal (Morton) order.  The device
@@ -80,6 +91,8 @@ struct PointBuf {
         std::vector<uint32_t> h[3];
         std::vector<float> hf[3];
         std::vector<double> hd[3];
+        std::vector<uint32_t> hxy(np);
+        std::vector<float> hzl(np);
         ps.hq.assign(3 * np, 0);
         for (int a = 0; a < 3; ++a) {
             h[a].resize(np);
@@ -93,6 +106,11 @@ struct PointBuf {
                 hf[a][i] = (float)v;
                 hd[a][i] = (double)v;
             }
+        }
+        for (int64_t i = 0; i < np; ++i) {
+            const int32_t* p = &pts3[3 * order[std::min(i, n - 1)]];
+            hxy[i] = (uint32_t)half_bits(p[0]) | ((uint32_t)half_bits(p[1]) << 16);
+            hzl[i] = (float)p[2];
         }
         ps.hbox.assign(6 * nblk, 0);
         for (int64_t b = 0; b < nblk; ++b)
@@ -114,6 +132,8 @@ struct PointBuf {
         upload(xd, hd[0], st);
         upload(yd, hd[1], st);
         upload(zd, hd[2], st);
+        upload(xy16, hxy, st);
+        upload(zl, hzl, st);
         upload(bbox, ps.hbox, st);
         ps.count = n;
         ps.padded = np;
@@ -126,6 +146,8 @@ struct PointBuf {
         ps.xd = xd.as<double>();
         ps.yd = yd.as<double>();
         ps.zd = zd.as<double>();
+        ps.xy16 = xy16.as<uint32_t>();
+        ps.zl = zl.as<float>();
         ps.bbox = bbox.as<int32_t>();
         ps.nblk = nblk;
         perm = order;

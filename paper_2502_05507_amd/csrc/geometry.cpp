@@ -45,7 +45,7 @@ static double level_set(const bae_levelset& ls, double x, double y, double z) {
 
 void build_geometry(const bae_grid& g, const bae_levelset& ls, Geometry& G) {
     for (int a = 0; a < 3; ++a)
-        if (g.n[a] < 5 || g.n[a] > 4096) throw Error{BAE_ERR_ARG, "grid: n must be in [5, 4096]"};
+        if (g.n[a] < 5 || g.n[a] > kMaxLatticeCoord + 1) throw Error{BAE_ERR_ARG, "grid: n must be in [5, 2049]"};
     if (!(g.h > 0) || !std::isfinite(g.h)) throw Error{BAE_ERR_ARG, "grid: h must be finite and > 0"};
     if (!(g.sigma >= 0) || !std::isfinite(g.sigma)) throw Error{BAE_ERR_ARG, "grid: sigma must be finite and >= 0"};
     for (int a = 0; a < 3; ++a)

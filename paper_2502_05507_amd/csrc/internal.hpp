@@ -65,6 +65,8 @@ constexpr int kFarGap = 32;               // far field used beyond this gap (sig
 constexpr double kYukawaTolerance = 1e-6; // sigma > 0 FP32 far field: largest accepted relative error
 constexpr int kSumThreads = 1024;         // threads per workgroup of the LGF sum
 constexpr int kMaxChunks = 64;            // source chunks (partial sums per target)
+constexpr int kMaxLatticeCoord = 2048;    // largest lattice coordinate: every integer up to 2048
+                                          // is exact in binary16 (the FP32 far field's differences)
 
 // Pair classes of a (64-target wavefront, source block) pair; gap and span in quantised
 // units (the smallest and largest max-norm distance between the two bounding boxes).
@@ -82,7 +84,8 @@ __host__ __device__ inline int block_class(int gap, int span, int tab_r, bool fa
 }
 
 // A set of lattice points on the device: SoA quantised coordinates as uint32, float and
-// double, and per-block quantised bounding boxes [nblk][lo xyz, hi xyz].
+// double, the lattice coordinates as packed binary16 (x, y) and float z, and per-block
+// quantised bounding boxes [nblk][lo xyz, hi xyz].
 struct PointSet {
     int64_t count = 0;
     int64_t padded = 0;        // nblk * kSourceBlock; entries past count repeat the last point
@@ -95,6 +98,8 @@ struct PointSet {
     double* xd = nullptr;
     double* yd = nullptr;
     double* zd = nullptr;
+    uint32_t* xy16 = nullptr;  // lattice (x, y) as two binary16 (exact: coordinates <= kMaxLatticeCoord)
+    float* zl = nullptr;       // lattice z
     int32_t* bbox = nullptr;
     int64_t nblk = 0;
     std::vector<int32_t> hq;   // host copy of the quantised coordinates (3 * padded, AoS)

@@ -60,6 +60,50 @@ __device__ __forceinline__ float far_field_q2(float X, float Y, float Z) {
     return rinv * fmaf(rho, fmaf(float(C2), x, float(C1)), float(C0));
 }
 
+// FP32, sigma = 0, q = 2 again, from the lattice offset n (not quantised) through
+//   r2 = |n|^2,  Z = n_z^2,  m = n_y^2 - n_x^2,
+// which the sum loop gets from packed binary16 differences with two dot products.  With
+// zeta = Z / r2 and mu = m / r2 the second symmetric polynomial of the squared components is
+// e2 = r2^2 (1 + 2 zeta - 3 zeta^2 - mu^2) / 4, which turns the q = 2 expansion into
+//   G = kFarScale32 rinv [16/5 + rho (mu^2 + 3 zeta^2 - 2 zeta - 1/5)],  rinv = 1/|n|, rho = rinv^2.
+// Returned without the factor kFarScale32, which the caller applies once per source block.
+constexpr float kFarScale32 = float(5.0 / (64.0 * kPi));
+__device__ __forceinline__ float far_field_q2_lattice(float r2, float Z, float m) {
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float rho = rinv * rinv;
+    const float zeta = Z * rho, mu = m * rho;
+    const float c = fmaf(mu, mu, fmaf(zeta, fmaf(zeta, 3.0f, -2.0f), -0.2f));
+    return rinv * fmaf(rho, c, 3.2f);
+}
+
+// Four far-field pairs of one target: the binary16 differences d_k = t - s_k (s_k
+// wavefront-uniform, in scalar registers) and from them
+//   r2_k = d_k.x^2 + d_k.y^2 + Z_k,   m_k = d_k.y^2 - d_k.x^2
+// (inputs: integers of magnitude <= 2048, exact in binary16; every product and sum is an
+// integer below 2^24, exact in FP32).  A VALU instruction may read the result of a DOT
+// instruction only three wait states after it, which the compiler cannot see inside an asm
+// statement: hence one statement per four pairs, ending in those wait states.
+__device__ __forceinline__ void far_pairs4(uint32_t t, uint32_t s0, uint32_t s1, uint32_t s2, uint32_t s3,
+                                           const float (&Z)[4], float (&r2)[4], float (&m)[4]) {
+    uint32_t d0, d1, d2, d3;
+    asm("v_pk_add_f16 %0, %12, %13 neg_lo:[0,1] neg_hi:[0,1]\n\t"
+        "v_pk_add_f16 %1, %12, %14 neg_lo:[0,1] neg_hi:[0,1]\n\t"
+        "v_pk_add_f16 %2, %12, %15 neg_lo:[0,1] neg_hi:[0,1]\n\t"
+        "v_pk_add_f16 %3, %12, %16 neg_lo:[0,1] neg_hi:[0,1]\n\t"
+        "v_dot2_f32_f16 %4, %0, %0, %17\n\t"
+        "v_dot2_f32_f16 %5, %0, %0, 0 neg_lo:[0,1,0]\n\t"
+        "v_dot2_f32_f16 %6, %1, %1, %18\n\t"
+        "v_dot2_f32_f16 %7, %1, %1, 0 neg_lo:[0,1,0]\n\t"
+        "v_dot2_f32_f16 %8, %2, %2, %19\n\t"
+        "v_dot2_f32_f16 %9, %2, %2, 0 neg_lo:[0,1,0]\n\t"
+        "v_dot2_f32_f16 %10, %3, %3, %20\n\t"
+        "v_dot2_f32_f16 %11, %3, %3, 0 neg_lo:[0,1,0]\n\t"
+        "s_nop 2"
+        : "=&v"(d0), "=&v"(d1), "=&v"(d2), "=&v"(d3), "=&v"(r2[0]), "=&v"(m[0]), "=&v"(r2[1]), "=&v"(m[1]),
+          "=&v"(r2[2]), "=&v"(m[2]), "=&v"(r2[3]), "=&v"(m[3])
+        : "v"(t), "s"(s0), "s"(s1), "s"(s2), "s"(s3), "v"(Z[0]), "v"(Z[1]), "v"(Z[2]), "v"(Z[3]));
+}
+
 // FP64: q = 4 from the squared quantised offset components (all >= 0, not all 0); relative
 // error <= 6.6e-11 beyond the far-field gap.
 __device__ __forceinline__ double far_field_q4(double X, double Y, double Z) {
@@ -224,6 +268,7 @@ template <>
 struct Acc<double> {
     double s = 0.0;
     __device__ __forceinline__ void add(double v) { s += v; }
+    __device__ __forceinline__ void scale_run(double) {}
     __device__ __forceinline__ void flush() {}
     __device__ __forceinline__ double value() const { return s; }
 };
@@ -231,6 +276,7 @@ template <>
 struct Acc<float> {
     float run = 0.f, sum = 0.f, comp = 0.f;
     __device__ __forceinline__ void add(float v) { run += v; }
+    __device__ __forceinline__ void scale_run(float f) { run *= f; }   // the block's terms times f
     __device__ __forceinline__ void flush() {
         const float t = sum + run;
         comp += fabsf(sum) >= fabsf(run) ? (sum - t) + run : (run - t) + sum;
@@ -246,6 +292,8 @@ struct SumArgs {
     int nt;
     const uint32_t *sx, *sy, *sz;     // quantised source coordinates
     const Real *sxr, *syr, *szr;      // the same in the kernel's precision
+    const uint32_t *txy, *sxy;        // lattice (x, y) of targets / sources as packed binary16
+    const float *tzl, *szl;           // lattice z (FP32 far field, sigma = 0)
     const int32_t* sbox;              // [nblk][6] quantised source block bounding boxes
     int ns, nblk, blk_per_chunk;
     const Real* w;
@@ -266,8 +314,9 @@ struct SumArgs {
 // one chunk.  From the bounding boxes of its targets and of each block it picks one loop
 // with a wavefront-uniform branch (block_class):
 //   table   every pair within the LDS table radius
-//   far     every pair beyond the far-field gap, sigma = 0: expansion in registers
-//           (q = 2 in FP32, q = 4 in FP64)
+//   far     every pair beyond the far-field gap: expansion in registers (sigma = 0: q = 2
+//           in FP32 from binary16 lattice differences, q = 4 in FP64; sigma > 0: the
+//           Yukawa form in FP32 where the context accepted it)
 //   gather  every pair beyond the LDS radius, sigma > 0: the global table
 //   mixed   per-pair choice between the LDS table and the far field / global table
 // The sources of one unrolled step, as whole scalar-register vectors.  They are loaded
@@ -286,13 +335,19 @@ struct Step {
     static constexpr int U = unroll<Real>();
     vec_t<uint32_t, U> x, y, z;     // quantised integer coordinates (table / gather / mixed)
     vec_t<Real, U> xr, yr, zr;      // the same in the kernel's precision (far field / mixed)
+    vec_t<uint32_t, U> xy;          // lattice (x, y) as binary16 pairs and z (FP32 far field)
+    vec_t<float, U> zl;
     vec_t<Real, U> w[NR];
 };
 
-template <typename Real, int NR, bool INT, bool REAL>
+template <typename Real, int NR, bool INT, bool REAL, bool HALF = false>
 __device__ __forceinline__ Step<Real, NR> load_step(const SumArgs<Real>& a, int s0) {
     constexpr int U = unroll<Real>();
     Step<Real, NR> st;
+    if constexpr (HALF) {
+        st.xy = ldu_vec<uint32_t, U>(a.sxy, s0);
+        st.zl = ldu_vec<float, U>(a.szl, s0);
+    }
     if constexpr (INT) {
         st.x = ldu_vec<uint32_t, U>(a.sx, s0);
         st.y = ldu_vec<uint32_t, U>(a.sy, s0);
@@ -348,6 +403,12 @@ __device__ __forceinline__ void sum_tile(const SumArgs<Real>& a, const Lds<Real>
     const int tc = min(t, a.nt - 1);
     const uint32_t ix = a.tx[tc], iy = a.ty[tc], iz = a.tz[tc];
     const Real fx = (Real)ix, fy = (Real)iy, fz = (Real)iz;
+    uint32_t txy = 0;
+    float tzl = 0.f;
+    if constexpr (sizeof(Real) == 4) {
+        txy = a.txy[tc];
+        tzl = a.tzl[tc];
+    }
     const int lx = wave_min((int)ix), ly = wave_min((int)iy), lz = wave_min((int)iz);
     const int hx = wave_max((int)ix), hy = wave_max((int)iy), hz = wave_max((int)iz);
     const uint32_t tab_q = (uint32_t)(kQuant * a.tab_r);
@@ -373,6 +434,28 @@ __device__ __forceinline__ void sum_tile(const SumArgs<Real>& a, const Lds<Real>
 #pragma unroll
                     for (int r = 0; r < NR; ++r) acc[r].add(G[u] * st.w[r][u]);
             }
+        } else if (sizeof(Real) == 4 && cls == kClassFar2 && !a.yukawa) {
+            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += U) {
+                const Step<Real, NR> st = load_step<Real, NR, false, false, true>(a, s0);
+#pragma unroll
+                for (int u0 = 0; u0 < U; u0 += 4) {
+                    float Z[4], r2[4], m[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const float dz = tzl - st.zl[u0 + k];
+                        Z[k] = dz * dz;
+                    }
+                    far_pairs4(txy, st.xy[u0], st.xy[u0 + 1], st.xy[u0 + 2], st.xy[u0 + 3], Z, r2, m);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const Real G = far_field_q2_lattice(r2[k], Z[k], m[k]);
+#pragma unroll
+                        for (int r = 0; r < NR; ++r) acc[r].add(G * st.w[r][u0 + k]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < NR; ++r) acc[r].scale_run(Real(kFarScale32));
         } else if ((cls == kClassFar || cls == kClassFar2) && !a.yukawa) {
             for (int s0 = sb; s0 < sb + kSourceBlock; s0 += U) {
                 const Step<Real, NR> st = load_step<Real, NR, false, true>(a, s0);

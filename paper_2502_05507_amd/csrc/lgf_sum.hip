@@ -108,8 +108,15 @@ __global__ void lgf_eval_kernel(const int32_t* __restrict__ off, int64_t count, 
     const int64_t m = max(a, max(b, c));
     if (m > tab_r && far_ok) {
         const Real X = Real(kQuant * a), Y = Real(kQuant * b), Z = Real(kQuant * c);
-        out[i] = yukawa ? (double)far_field_yukawa<Real>(X * X, Y * Y, Z * Z, kq, yk)
-                        : (double)far_field<Real>(X * X, Y * Y, Z * Z);
+        if (yukawa) {
+            out[i] = (double)far_field_yukawa<Real>(X * X, Y * Y, Z * Z, kq, yk);
+        } else if constexpr (sizeof(Real) == 4) {
+            // the form of the sum's far blocks (lattice units)
+            const float x2 = float(a * a), y2 = float(b * b), z2 = float(c * c);
+            out[i] = (double)(kFarScale32 * far_field_q2_lattice(x2 + y2 + z2, z2, y2 - x2));
+        } else {
+            out[i] = (double)far_field<Real>(X * X, Y * Y, Z * Z);
+        }
         return;
     }
     if (m > full_r) {
@@ -347,6 +354,10 @@ void launch_all(const PointSet& T, const PointSet& S, const Real* w, int nrhs, c
     a.sxr = coord<Real>(S, 0);
     a.syr = coord<Real>(S, 1);
     a.szr = coord<Real>(S, 2);
+    a.txy = T.xy16;
+    a.tzl = T.zl;
+    a.sxy = S.xy16;
+    a.szl = S.zl;
     a.sbox = S.bbox;
     a.ns = (int)S.count;
     a.nblk = (int)S.nblk;

@@ -24,10 +24,13 @@ def test_poisson_ellipsoid_129_matvec_sampled():
     with P.Context.from_problem(p) as ctx:
         qd = torch.from_numpy(q).to(device())
         v = torch.empty(len(T), dtype=torch.float64, device=device())
-        for prec, tol in ((P.PREC_FP64, 1e-10), (P.PREC_FP32, 2e-5)):
+        # FP32: 38% of the pairs take the q = 2 far field, whose dropped term is below 6.1e-7
+        for prec, tol in ((P.PREC_FP64, 1e-10), (P.PREC_FP32, 3e-6)):
             ctx.apply_double_layer(qd, v, prec)
             torch.cuda.synchronize()
-            assert rel_l2(v.cpu().numpy()[pick], ref) < tol
+            err = rel_l2(v.cpu().numpy()[pick], ref)
+            print(f"prec {prec}: rel L2 {err:.3e}")
+            assert err < tol
 
 
 def test_poisson_ellipsoid_129_solve_satisfies_oracle_system():

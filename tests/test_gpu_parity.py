@@ -266,7 +266,7 @@ def test_sixteen_rhs_blocked_form_matches_oracle(kind, n, sigma):
     p = small_problem(kind, n, sigma)
     g, G = oracle_setup(p)
     rng = np.random.default_rng(7 * n)
-    nr = 18                                   # one 16-wide MFMA group + a ragged VALU tail
+    nr = 23                                   # a 16-wide MFMA group, a 4-RHS VALU launch, 3 single ones
     q = rng.standard_normal((nr, len(g.gamma_minus)))
     T = operators.gamma_targets(g)
     D = operators.dense_double_layer(g, G, T) if len(T) * len(g.gamma_minus) < 3e7 else None

@@ -112,14 +112,15 @@ __global__ __launch_bounds__(kSumThreads) void b_lgf_sum(const BProb* __restrict
         const SumArgs<Real>& a = sum_args<Real>(q);
         if (a.near_tab != cur || a.tab_r > cur_r) {
             __syncthreads();
-            const int n = (a.tab_r + 1) * (a.tab_r + 2) * (a.tab_r + 3) / 6;
-            for (int i = threadIdx.x; i < n; i += kSumThreads) L.tab[i] = a.near_tab[i];
+            stage_table(L.tab, a.near_tab, (a.tab_r + 1) * (a.tab_r + 2) * (a.tab_r + 3) / 6);
             __syncthreads();
             cur = a.near_tab;
             cur_r = a.tab_r;
         }
         const int tile = w.tile * (kSumThreads / kWave) + wave;
-        if (tile * kWave < a.nt) sum_tile<Real, 1>(a, L, tile, w.chunk);
+        // every problem here is small: its chunk fits the scalar cache only while the
+        // item's wavefronts walk it together, so no rotation
+        if (tile * kWave < a.nt) sum_tile<Real, 1, false>(a, L, tile, w.chunk);
     }
 }
 

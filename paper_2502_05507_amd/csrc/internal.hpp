@@ -65,6 +65,7 @@ constexpr int kFarGap = 32;               // far field used beyond this gap (sig
 constexpr double kYukawaTolerance = 1e-6; // sigma > 0 FP32 far field: largest accepted relative error
 constexpr int kSumThreads = 1024;         // threads per workgroup of the LGF sum
 constexpr int kMaxChunks = 64;            // source chunks (partial sums per target)
+constexpr int kGroupTiles = 16;           // 64-target tiles per work item of the LGF sum
 constexpr int kMaxLatticeCoord = 2048;    // largest lattice coordinate: every integer up to 2048
                                           // is exact in binary16 (the FP32 far field's differences)
 
@@ -123,12 +124,13 @@ struct SumTables {
     int far_gap64() const { return kFarGap; }
 };
 
-// Work list of one (targets, sources) pair: items (64-target tile, source chunk), ordered by
-// decreasing estimated cost so the dynamically scheduled wavefronts finish together.
+// Work list of one (targets, sources) pair: items (group of kGroupTiles consecutive
+// 64-target tiles, source chunk), ordered by decreasing estimated cost so the dynamically
+// scheduled workgroups finish together.
 struct SumPlan {
     int chunks = 1, blk_per_chunk = 1;
     int64_t nitems = 0;
-    uint32_t* items = nullptr;     // device: tile | chunk << 20
+    uint32_t* items = nullptr;     // device: group | chunk << 20
     unsigned long long* counter = nullptr;   // device: work counter, 0 between launches
     int64_t class_pairs[2][5] = {{0}};   // [fp64, fp32][class] pairs (mixed split: 3 table, 4 other)
 };

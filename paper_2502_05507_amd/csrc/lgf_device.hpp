@@ -245,11 +245,37 @@ __device__ __forceinline__ void fill_index(const Lds<Real>& L, int idx_r) {
     }
 }
 
+// Copy the first n table entries into LDS with 16-byte loads, eight per thread in flight
+// (one load at a time would pay the memory latency once per 4 KB of table).  Both tables
+// start 16-byte aligned: the device table at an allocation's start, the LDS copy after
+// index arrays of a 16-byte multiple.
+template <typename Real>
+__device__ __forceinline__ void stage_table(Real* dst, const Real* __restrict__ src, int n) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    constexpr int K = 8;
+    const int nv = (int)(((int64_t)n * (int64_t)sizeof(Real)) / 16);
+    const u32x4* __restrict__ s = (const u32x4*)src;
+    u32x4* d = (u32x4*)dst;
+    for (int base = threadIdx.x; base < nv; base += K * (int)blockDim.x) {
+        u32x4 r[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = base + k * (int)blockDim.x;
+            if (i < nv) r[k] = s[i];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = base + k * (int)blockDim.x;
+            if (i < nv) d[i] = r[k];
+        }
+    }
+    for (int i = nv * (16 / (int)sizeof(Real)) + (int)threadIdx.x; i < n; i += (int)blockDim.x) dst[i] = src[i];
+}
+
 // Fill the LDS table prefix (radius tab_r) and the index arrays up to radius idx_r.
 template <typename Real>
 __device__ __forceinline__ void fill_lds(const Lds<Real>& L, const Real* __restrict__ src, int tab_r, int idx_r) {
-    const int n = (tab_r + 1) * (tab_r + 2) * (tab_r + 3) / 6;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) L.tab[i] = src[i];
+    stage_table(L.tab, src, (tab_r + 1) * (tab_r + 2) * (tab_r + 3) / 6);
     fill_index<Real>(L, idx_r);
 }
 
@@ -395,7 +421,9 @@ __device__ __forceinline__ void lookup_step(const Lds<Real>& L, const Real* __re
     __builtin_amdgcn_sched_barrier(0);
 }
 
-template <typename Real, int NR>
+// ROT: start at a block of the chunk that depends on the tile (see below); without it every
+// tile walks the chunk from its first block.
+template <typename Real, int NR, bool ROT = true>
 __device__ __forceinline__ void sum_tile(const SumArgs<Real>& a, const Lds<Real>& L, int tile, int chunk) {
     constexpr int U = unroll<Real>();
     const int lane = threadIdx.x & (kWave - 1);
@@ -415,8 +443,16 @@ __device__ __forceinline__ void sum_tile(const SumArgs<Real>& a, const Lds<Real>
 
     const int b0 = chunk * a.blk_per_chunk;
     const int b1 = min(a.nblk, b0 + a.blk_per_chunk);
+    // the tiles of a work item share its chunk; each starts at another block of it, so the
+    // wavefronts of a workgroup are spread over the chunk's block classes at any time (the
+    // table loop's LDS waits then overlap other wavefronts' far-field arithmetic) while the
+    // chunk's sources stay in the scalar cache for all of them
+    const int nb = b1 - b0;
+    const int rot = ROT ? ((tile % kGroupTiles) * nb) / kGroupTiles : 0;
     Acc<Real> acc[NR];
-    for (int b = b0; b < b1; ++b) {
+    for (int jb = 0; jb < nb; ++jb) {
+        int b = b0 + jb + rot;
+        if (b >= b1) b -= nb;
         const int32_t* bb = a.sbox + 6 * b;
         const int bx0 = ldu(bb, 0), by0 = ldu(bb, 1), bz0 = ldu(bb, 2), bx1 = ldu(bb, 3), by1 = ldu(bb, 4),
                   bz1 = ldu(bb, 5);
@@ -425,18 +461,27 @@ __device__ __forceinline__ void sum_tile(const SumArgs<Real>& a, const Lds<Real>
         const int cls = block_class(gap, span, a.tab_r, a.far_ok != 0, sizeof(Real) == 4, a.far_gap);
         const int sb = b * kSourceBlock;        // blocks are full: the source arrays are padded
         if (cls == kClassTable) {
+            // the next step's sources are loaded while this step's table reads are in
+            // flight (the last step reloads its own: the block's end is the array's end)
+            Step<Real, NR> st = load_step<Real, NR, true, false>(a, sb);
             for (int s0 = sb; s0 < sb + kSourceBlock; s0 += U) {
-                const Step<Real, NR> st = load_step<Real, NR, true, false>(a, s0);
                 Real G[U];
                 lookup_step<Real, U, false>(L, nullptr, ix, iy, iz, st.x, st.y, st.z, G);
+                const Step<Real, NR> nx = load_step<Real, NR, true, false>(a, min(s0 + U, sb + kSourceBlock - U));
 #pragma unroll
                 for (int u = 0; u < U; ++u)
 #pragma unroll
                     for (int r = 0; r < NR; ++r) acc[r].add(G[u] * st.w[r][u]);
+                st = nx;
             }
         } else if (sizeof(Real) == 4 && cls == kClassFar2 && !a.yukawa) {
+            Step<Real, NR> nx = load_step<Real, NR, false, false, true>(a, sb);
+            // every counter drained here, so that the loop's only wait is for its own loads
+            __builtin_amdgcn_s_waitcnt(0);
             for (int s0 = sb; s0 < sb + kSourceBlock; s0 += U) {
-                const Step<Real, NR> st = load_step<Real, NR, false, false, true>(a, s0);
+                // this step's sources were loaded one step ahead; load the next one's now
+                const Step<Real, NR> st = nx;
+                nx = load_step<Real, NR, false, false, true>(a, min(s0 + U, sb + kSourceBlock - U));
 #pragma unroll
                 for (int u0 = 0; u0 < U; u0 += 4) {
                     float Z[4], r2[4], m[4];

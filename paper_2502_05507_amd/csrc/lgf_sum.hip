@@ -13,7 +13,7 @@
 //   c >  RL : sigma = 0 -> far-field expansion in registers (valid beyond 32, below; q = 4
 //             in FP64, q = 2 in FP32, where the FP32 rounding of the sum dominates);
 //             sigma > 0 -> the full FP64/FP32 table in global memory (L2 / MALL resident)
-// A table lookup costs 8 VALU instructions per pair, the FP32 far field 19 and the FP64 one
+// A table lookup costs 8 VALU instructions per pair, the FP32 far field 15 and the FP64 one
 // about 40, so every block pair that fits the LDS table is evaluated from it.
 // Far field (sigma = 0): Sec. 2.2 q-term expansion in the positive sign convention,
 //   G_0(n) = (1/(4 pi |n|)) [1 + rho (1 - 5x)/4 + rho^2 P8/32 + rho^3 P12/128] + O(|n|^-9),
@@ -30,10 +30,11 @@
 // wavefront-uniform, so source coordinates and weights come through scalar loads.  Sources
 // come in Morton blocks of 64 with bounding boxes, so each wavefront classifies a whole
 // block with one uniform branch.  The grid is persistent: one 1024-thread workgroup per
-// compute unit stages the LDS table once, and its wavefronts take work items (64-target
-// tile, source chunk) -- first one each in a fixed assignment, then from an atomic counter
-// -- from a list ordered by decreasing estimated cost.  Each item writes its own partial
-// sums, reduced later in a fixed order, so results do not depend on the schedule.
+// compute unit stages the LDS table once and takes work items (16 consecutive 64-target
+// tiles, source chunk) -- its first in a fixed assignment, the rest from an atomic counter
+// -- from a list ordered by decreasing estimated cost, handing the item's tiles to its
+// wavefronts (for_each_item).  Each (tile, chunk) writes its own partial sums, reduced
+// later in a fixed order, so results do not depend on the schedule.
 // FP32 pairs are summed in FP32 over each source block and the block sums folded into a
 // Neumaier-compensated FP32 accumulator.
 #include <algorithm>
@@ -51,41 +52,88 @@ namespace {
 
 struct Sched {
     const int32_t* skip;   // non-null and set: the whole sum is skipped (a converged solve)
-    const uint32_t* items;
-    unsigned long long* counter;   // a type no input array has: its atomics cannot alias the
-                                   // inputs, whose uniform loads then stay scalar
+    const uint32_t* items; // group | chunk << 20, by decreasing cost
     uint32_t nitems;
-    int dynamic;           // nitems > number of wavefronts: the rest comes from the counter
+    uint32_t ntiles;       // 64-target tiles
+    unsigned long long* counter;   // hands out items G.. (a type no input array has: its
+                                   // atomics cannot alias the inputs, whose uniform loads
+                                   // then stay scalar); 0 between launches
 };
 
-// The work loop of one wavefront: item w (its index among all wavefronts of the grid),
-// then items W + counter while any are left.  The counter hands out exactly
-// (nitems - W) + W values; the wavefront that draws the last one resets it for the next
-// launch (every other wavefront has drawn its final value by then).
+// Per-workgroup hand-off of work items in LDS: a ring of the global item indices of the
+// workgroup's next local items, each with its local number as tag, and the number of units
+// of it whose wavefronts have read it.
+constexpr uint32_t kRing = 4;
+constexpr uint32_t kSpinLimit = 1u << 22;   // bounded waits (a wait this long is a bug)
+struct ItemRing {
+    uint32_t units;             // (local item, tile) units handed out so far
+    uint32_t item[kRing];
+    uint32_t tag[kRing];        // local item number held, ~0 when none
+    uint32_t readers[kRing];    // units of it that have read the slot (kGroupTiles when free)
+};
+
+__device__ __forceinline__ void ring_init(ItemRing* r) {
+    if (threadIdx.x == 0) r->units = 0;
+    if (threadIdx.x < kRing) {
+        r->tag[threadIdx.x] = ~0u;
+        r->readers[threadIdx.x] = kGroupTiles;
+    }
+}
+
+// The work loop of one wavefront.  Items are (group of kGroupTiles consecutive target
+// tiles, source chunk), by decreasing cost.  A workgroup's local item 0 is item b (its
+// index among the G workgroups); each further one comes from the global counter (item
+// G + value), fetched one item ahead by the wavefront that takes the first unit of the
+// item before.  The workgroup hands the (item, tile) units to its wavefronts in order from
+// an LDS counter, so its wavefronts walk the same source blocks at about the same time and
+// their scalar loads of the sources hit the scalar cache for all but the first (a wavefront
+// on a source chunk of its own misses that cache on every other step and leaves the table
+// loop waiting on the miss traffic).  The counter hands out exactly nitems values in all;
+// the workgroup that draws the last one resets it for the next launch.
 template <typename F>
-__device__ __forceinline__ void for_each_item(const Sched& q, F&& body) {
+__device__ __forceinline__ void for_each_item(const Sched& q, ItemRing* r, F&& body) {
+    if (q.skip && ldu(q.skip, 0)) return;   // uniform: a converged solve skips the sum
     const uint32_t lane = threadIdx.x & 63;
-    // both are uniform; saying so keeps the item, its loop bounds and the source loads in
-    // scalar registers
-    const uint32_t waves = __builtin_amdgcn_readfirstlane(gridDim.x * (blockDim.x >> 6));
-    const uint32_t w = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
-    if (w >= q.nitems) return;
-    if (q.skip && ldu(q.skip, 0)) return;   // uniform: every wavefront leaves, the counter stays 0
-    uint32_t i = w;
+    const uint32_t G = gridDim.x;
     for (;;) {
-        uint32_t nxt = 0;
-        if (q.dynamic && lane == 0)
-            nxt = (uint32_t)__hip_atomic_fetch_add(q.counter, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t it = ldu(q.items, i);
-        body(it & 0xFFFFFu, it >> 20);
-        if (!q.dynamic) return;
-        const uint32_t v = __builtin_amdgcn_readfirstlane(nxt);
-        if (v >= q.nitems - waves) {
+        uint32_t u = 0;
+        if (lane == 0) u = __hip_atomic_fetch_add(&r->units, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        u = __builtin_amdgcn_readfirstlane(u);
+        const uint32_t k = u / kGroupTiles, part = u % kGroupTiles;
+        uint32_t idx = blockIdx.x;
+        if (k > 0) {
+            const uint32_t s = k % kRing;
+            uint32_t spins = 0;
+            while (__hip_atomic_load(&r->tag[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != k &&
+                   ++spins < kSpinLimit)
+                __builtin_amdgcn_s_sleep(1);
+            if (spins >= kSpinLimit) return;
+            idx = __builtin_amdgcn_readfirstlane(r->item[s]);
+            if (lane == 0) __hip_atomic_fetch_add(&r->readers[s], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        if (idx >= q.nitems) return;
+        if (part == 0) {
+            // fetch the next local item into its slot, once the item three before has left it
+            uint32_t v = 0;
+            if (lane == 0)
+                v = (uint32_t)__hip_atomic_fetch_add(q.counter, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            v = __builtin_amdgcn_readfirstlane(v);
             if (v == q.nitems - 1 && lane == 0)
                 __hip_atomic_store(q.counter, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return;
+            const uint32_t s = (k + 1) % kRing;
+            uint32_t spins = 0;
+            while (__hip_atomic_load(&r->readers[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != kGroupTiles &&
+                   ++spins < kSpinLimit)
+                __builtin_amdgcn_s_sleep(1);
+            if (lane == 0) {
+                r->item[s] = G + v;
+                r->readers[s] = 0;
+                __hip_atomic_store(&r->tag[s], k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
         }
-        i = waves + v;
+        const uint32_t it = ldu(q.items, idx);
+        const uint32_t t = (it & 0xFFFFFu) * (uint32_t)kGroupTiles + part;
+        if (t < q.ntiles) body(t, it >> 20);
     }
 }
 
@@ -93,9 +141,11 @@ template <typename Real, int NR, int THREADS, bool FAR>
 __global__ __launch_bounds__(THREADS) void lgf_sum_kernel(const SumArgs<Real> a, const Sched q) {
     __shared__ __align__(16) char lds[lds_bytes<Real, FAR>()];
     const Lds<Real> L = lds_layout<Real, FAR>(lds);
+    __shared__ ItemRing ring;
+    ring_init(&ring);
     fill_lds(L, a.near_tab, a.tab_r, FAR ? a.tab_r : a.full_r);
     __syncthreads();
-    for_each_item(q, [&](uint32_t tile, uint32_t chunk) { sum_tile<Real, NR>(a, L, (int)tile, (int)chunk); });
+    for_each_item(q, &ring, [&](uint32_t tile, uint32_t chunk) { sum_tile<Real, NR>(a, L, (int)tile, (int)chunk); });
 }
 
 template <typename Real>
@@ -222,7 +272,12 @@ __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real
 
     const int b0 = chunk * a.blk_per_chunk;
     const int b1 = min(a.nblk, b0 + a.blk_per_chunk);
-    for (int b = b0; b < b1; ++b) {
+    // each tile of the item starts at another block of the chunk (as in sum_tile)
+    const int nb = b1 - b0;
+    const int rot = ((tile % kGroupTiles) * nb) / kGroupTiles;
+    for (int jb = 0; jb < nb; ++jb) {
+        int b = b0 + jb + rot;
+        if (b >= b1) b -= nb;
         const int sb = b * kSourceBlock;
         const int32_t* bb = a.sbox + 6 * b;
         const int gap = max(max(max(bb[0] - hx, lx - bb[3]), max(bb[1] - hy, ly - bb[4])),
@@ -313,9 +368,11 @@ template <typename Real, int THREADS, bool FAR>
 __global__ __launch_bounds__(THREADS) void lgf_sum_mfma_kernel(const SumArgs<Real> a, const Sched q) {
     __shared__ __align__(16) char lds[lds_bytes<Real, FAR>()];
     const Lds<Real> L = lds_layout<Real, FAR>(lds);
+    __shared__ ItemRing ring;
+    ring_init(&ring);
     fill_lds(L, a.near_tab, a.tab_r, FAR ? a.tab_r : a.full_r);
     __syncthreads();
-    for_each_item(q, [&](uint32_t tile, uint32_t chunk) { mfma_tile<Real>(a, L, (int)tile, (int)chunk); });
+    for_each_item(q, &ring, [&](uint32_t tile, uint32_t chunk) { mfma_tile<Real>(a, L, (int)tile, (int)chunk); });
 }
 
 template <typename Real>
@@ -380,8 +437,7 @@ void launch_all(const PointSet& T, const PointSet& S, const Real* w, int nrhs, c
         ar.w = w + (int64_t)r * a.ldw;
         ar.part = part + (int64_t)r * a.ldp;
         const int threads = left >= 16 ? mfma_threads<Real>() : left >= 4 ? rhs4_threads<Real>() : kSumThreads;
-        const uint32_t waves = (uint32_t)grid * (uint32_t)(threads / 64);
-        const Sched q{skip, plan.items, plan.counter, (uint32_t)plan.nitems, plan.nitems > (int64_t)waves ? 1 : 0};
+        const Sched q{skip, plan.items, (uint32_t)plan.nitems, (uint32_t)((T.count + kWave - 1) / kWave), plan.counter};
         if (left >= 16) {
             if (lds_far) lgf_sum_mfma_kernel<Real, mfma_threads<Real>(), true><<<grid, mfma_threads<Real>(), 0, st>>>(ar, q);
             else lgf_sum_mfma_kernel<Real, mfma_threads<Real>(), false><<<grid, mfma_threads<Real>(), 0, st>>>(ar, q);
@@ -401,14 +457,15 @@ void launch_all(const PointSet& T, const PointSet& S, const Real* w, int nrhs, c
 
 // Estimated VALU cost per pair of each block class (FP32 instruction counts; the gather
 // and mixed classes are charged for their memory and divergence).
-constexpr double kClassCost[5] = {8.0, 26.0, 19.0, 40.0, 45.0};
+constexpr double kClassCost[5] = {8.0, 26.0, 15.0, 40.0, 45.0};
 
 }  // namespace
 
 int lgf_sum_chunks(int64_t nt, int64_t nblk) {
-    const int64_t tiles = (nt + kWave - 1) / kWave;
-    // about 8 items per wavefront of a full MI355X (256 CUs x 16 wavefronts)
-    int64_t chunks = (8 * 4096 + tiles - 1) / tiles;
+    const int64_t groups = (nt + kWave * kGroupTiles - 1) / (kWave * kGroupTiles);
+    // about 32 items per workgroup of a full MI355X (256 CUs): fine enough that the
+    // workgroups finish together (with 8, the 257^3 sums lose 10% to the last items)
+    int64_t chunks = (32 * 256 + groups - 1) / groups;
     chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, nblk / 2));   // at least 2 blocks per item
     return (int)std::max<int64_t>(1, std::min<int64_t>(chunks, kMaxChunks));
 }
@@ -434,8 +491,9 @@ void plan_sum(const PointSet& T, const PointSet& S, const SumTables& tabs, SumPl
     chunks = (int)((nblk + bpc - 1) / std::max(1, bpc));
     plan.chunks = std::max(1, chunks);
     plan.blk_per_chunk = std::max(1, bpc);
-    plan.nitems = tiles * plan.chunks;
-    if (tiles > (1 << 20) || plan.chunks > 4095) throw Error{BAE_ERR_ARG, "LGF sum too large for the work list"};
+    const int64_t groups = (tiles + kGroupTiles - 1) / kGroupTiles;
+    plan.nitems = groups * plan.chunks;
+    if (groups > (1 << 20) || plan.chunks > 4095) throw Error{BAE_ERR_ARG, "LGF sum too large for the work list"};
     for (auto& r : plan.class_pairs)
         for (auto& v : r) v = 0;
     host_items.resize(plan.nitems);
@@ -464,17 +522,17 @@ void plan_sum(const PointSet& T, const PointSet& S, const SumTables& tabs, SumPl
                 const int c64 = block_class(gap, span, tabs.tab_r64, tabs.far64(), false, tabs.far_gap64());
                 plan.class_pairs[1][c32] += pairs;
                 plan.class_pairs[0][c64] += pairs;
-                cost[tl * plan.chunks + b / plan.blk_per_chunk] += kClassCost[c32] * (double)pairs;
+                cost[(tl / kGroupTiles) * plan.chunks + b / plan.blk_per_chunk] += kClassCost[c32] * (double)pairs;
             }
         }
     }
-    // items (tile, chunk) ordered by decreasing cost (stable: natural order when unclassified)
+    // items (group, chunk) ordered by decreasing cost (stable: natural order when unclassified)
     std::vector<int64_t> order(plan.nitems);
     for (int64_t i = 0; i < plan.nitems; ++i) order[i] = i;
     if (classify) std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return cost[x] > cost[y]; });
     for (int64_t i = 0; i < plan.nitems; ++i) {
-        const int64_t tl = order[i] / plan.chunks, ch = order[i] % plan.chunks;
-        host_items[i] = (uint32_t)tl | ((uint32_t)ch << 20);
+        const int64_t g = order[i] / plan.chunks, ch = order[i] % plan.chunks;
+        host_items[i] = (uint32_t)g | ((uint32_t)ch << 20);
     }
 }
 

@@ -632,6 +632,7 @@ int bae_solve(bae_ctx* c, const bae_solve_params* p, bae_result* res) {
         std::vector<double> bn = host_norms(c, c->b.as<double>(), nrhs, st);
         std::vector<int> iters(nrhs, 0), conv(nrhs, 0), outer(nrhs, 0);
         std::vector<double> est(nrhs, 0.0), relres;
+        bool dq_in_vsum = false;   // the last operator call was the FP64 residual of the final q
         launch_fill(c->x.as<double>(), n * nrhs, 0.0, st);
         if (p->precision == BAE_SOLVE_FP64) {
             GmresOut g = gmres(c, c->b.as<double>(), nrhs, BAE_PREC_FP64, p->tol, maxit, {}, c->x.as<double>(), false,
@@ -641,6 +642,7 @@ int bae_solve(bae_ctx* c, const bae_solve_params* p, bae_result* res) {
                 est[r] = g.last_est[r];
             }
             relres = residual(c, nrhs, bn, st, &mv64);
+            dq_in_vsum = true;
             for (int r = 0; r < nrhs; ++r) conv[r] = g.converged[r];
         } else {
             // inner tolerance of outer step k: just enough to reach tol from the current
@@ -672,11 +674,18 @@ int bae_solve(bae_ctx* c, const bae_solve_params* p, bae_result* res) {
                     }
                 }
                 relres = residual(c, nrhs, bn, st, &mv64);
+                dq_in_vsum = true;
             }
             for (int r = 0; r < nrhs; ++r) conv[r] = relres[r] <= p->tol;
         }
-        // u_gamma = D q + u_p on gamma
-        double_layer(c, c->x.as<double>(), n, c->u_gamma.as<double>(), c->nT, nrhs, BAE_PREC_FP64, st);
+        // u_gamma = D q + u_p on gamma.  The last call above is the FP64 residual of the final
+        // q, whose operator left D q at every target (internal order) in vsum: scattering it
+        // saves a double-layer evaluation.
+        if (dq_in_vsum && c->cl.n > 0)
+            launch_reduce_scatter(c->vsum.as<double>(), 1, c->nT, c->t_pos.as<int32_t>(), c->u_gamma.as<double>(),
+                                  c->nT, nrhs, 1.0, st);
+        else
+            double_layer(c, c->x.as<double>(), n, c->u_gamma.as<double>(), c->nT, nrhs, BAE_PREC_FP64, st);
         launch_axpby(1.0, c->up_gamma.as<double>(), c->nT, 1.0, c->u_gamma.as<double>(), c->nT, c->nT, nrhs, st);
         BAE_HIP_CHECK(hipStreamSynchronize(st));
         c->ugrid.clear();

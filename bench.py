@@ -43,15 +43,15 @@ FLOPS = {"fp32": {"near": 2, "far": 23, "far_q2": 23, "mixed_near": 2, "mixed_fa
          "fp64": {"near": 2, "far": 46, "far_q2": 46, "mixed_near": 2, "mixed_far": 46}}
 # VALU lane-operations per pair the evaluation needs, by pair class:
 #   table lookup: 3 |t - s| + min/median/max + index add (+ a shift in FP64) + accumulate
-#   far field, FP64 (q = 4): 3 differences, 3 squares, r^2, e2 and e3, rsqrt with its
-#     refinement, the rho powers and invariants, the polynomial, the product with 1/|n| and
-#     the accumulate
+#   far field, FP64 (q = 4): 3 differences, 3 squares, r^2, e2 and e3, the rsqrt estimate
+#     and its Newton step, the rho powers and invariants, the polynomial, the product with
+#     1/|n| and the accumulate
 #   far field, FP32 (q = 2): the packed binary16 (x, y) difference, the z difference and its
 #     square, two dot products (|n|^2 and n_y^2 - n_x^2), rsqrt, rho, the two ratios, the
 #     four-term polynomial, the product with 1/|n| and the accumulate
 #   mixed pairs: the chosen path plus the per-pair test
 OPS = {"fp32": {"near": 8, "far": 19, "far_q2": 15, "mixed_near": 10, "mixed_far": 24},
-       "fp64": {"near": 9, "far": 41, "far_q2": 41, "mixed_near": 11, "mixed_far": 46}}
+       "fp64": {"near": 9, "far": 37, "far_q2": 37, "mixed_near": 11, "mixed_far": 42}}
 
 
 # HBM bytes per launch of the FP32 LGF-sum kernel on this workload, from rocprofv3 FETCH_SIZE

@@ -14,7 +14,7 @@
 //             in FP64, q = 2 in FP32, where the FP32 rounding of the sum dominates);
 //             sigma > 0 -> the full FP64/FP32 table in global memory (L2 / MALL resident)
 // A table lookup costs 8 VALU instructions per pair, the FP32 far field 15 and the FP64 one
-// about 40, so every block pair that fits the LDS table is evaluated from it.
+// 37, so every block pair that fits the LDS table is evaluated from it.
 // Far field (sigma = 0): Sec. 2.2 q-term expansion in the positive sign convention,
 //   G_0(n) = (1/(4 pi |n|)) [1 + rho (1 - 5x)/4 + rho^2 P8/32 + rho^3 P12/128] + O(|n|^-9),
 //   rho = 1/|n|^2, x = e2 rho^2, y = e3 rho^3, e2 = j^2k^2 + k^2l^2 + l^2j^2, e3 = j^2k^2l^2,

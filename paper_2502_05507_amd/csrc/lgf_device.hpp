@@ -113,6 +113,28 @@ __device__ __forceinline__ double rsqrt_pos(double x) {
     return fma(0.5 * y, e, y);
 }
 
+// The same for four targets t_k of one lane against one source s (both per lane).
+__device__ __forceinline__ void far_pairs4v(const uint32_t (&t)[4], uint32_t s, const float (&Z)[4], float (&r2)[4],
+                                            float (&m)[4]) {
+    uint32_t d0, d1, d2, d3;
+    asm("v_pk_add_f16 %0, %12, %16 neg_lo:[0,1] neg_hi:[0,1]\n\t"
+        "v_pk_add_f16 %1, %13, %16 neg_lo:[0,1] neg_hi:[0,1]\n\t"
+        "v_pk_add_f16 %2, %14, %16 neg_lo:[0,1] neg_hi:[0,1]\n\t"
+        "v_pk_add_f16 %3, %15, %16 neg_lo:[0,1] neg_hi:[0,1]\n\t"
+        "v_dot2_f32_f16 %4, %0, %0, %17\n\t"
+        "v_dot2_f32_f16 %5, %0, %0, 0 neg_lo:[0,1,0]\n\t"
+        "v_dot2_f32_f16 %6, %1, %1, %18\n\t"
+        "v_dot2_f32_f16 %7, %1, %1, 0 neg_lo:[0,1,0]\n\t"
+        "v_dot2_f32_f16 %8, %2, %2, %19\n\t"
+        "v_dot2_f32_f16 %9, %2, %2, 0 neg_lo:[0,1,0]\n\t"
+        "v_dot2_f32_f16 %10, %3, %3, %20\n\t"
+        "v_dot2_f32_f16 %11, %3, %3, 0 neg_lo:[0,1,0]\n\t"
+        "s_nop 2"
+        : "=&v"(d0), "=&v"(d1), "=&v"(d2), "=&v"(d3), "=&v"(r2[0]), "=&v"(m[0]), "=&v"(r2[1]), "=&v"(m[1]),
+          "=&v"(r2[2]), "=&v"(m[2]), "=&v"(r2[3]), "=&v"(m[3])
+        : "v"(t[0]), "v"(t[1]), "v"(t[2]), "v"(t[3]), "v"(s), "v"(Z[0]), "v"(Z[1]), "v"(Z[2]), "v"(Z[3]));
+}
+
 // FP64: q = 4 from the squared quantised offset components (all >= 0, not all 0); relative
 // error <= 6.6e-11 beyond the far-field gap.
 __device__ __forceinline__ double far_field_q4(double X, double Y, double Z) {
@@ -164,6 +186,25 @@ __device__ __forceinline__ Real far_field_yukawa(Real X, Real Y, Real Z, Real kq
     const Real c3 = fma(Real(-4.0 / 3.0), x, Real(2.0 / 3.0));
     const Real br = fma(u, fma(u, fma(u, c3, c2), A), A);
     return ex * rinv * fma(rho, br, Real(1));
+}
+
+// The same sigma > 0 form from the lattice offset (FP32), through r2, Z and m as in
+// far_field_q2_lattice: with x4 = 4 e2/|n|^4 = 1 + 2 zeta - 3 zeta^2 - mu^2, the bracket is
+//   T2 |n|^2 = P0(u) + x4 P1(u),  P0 = (1 + u)/4 + u^3/24,  P1 = -5(1 + u)/16 - u^2/8 - u^3/48.
+// kl = kappa, ykl = -kappa log2(e) (lattice units).
+__device__ __forceinline__ float far_field_yukawa_lattice(float r2, float Z, float m, float kl, float ykl) {
+    constexpr float kLog2C = -3.6514961294723187f;   // log2(1 / (4 pi))
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float rho = rinv * rinv;
+    const float zeta = Z * rho, mu = m * rho;
+    const float x4 = fmaf(-mu, mu, fmaf(zeta, fmaf(zeta, -3.0f, 2.0f), 1.0f));
+    const float rq = r2 * rinv;
+    const float u = rq * kl;
+    const float ex = __builtin_amdgcn_exp2f(fmaf(rq, ykl, kLog2C));
+    const float u2 = u * u;
+    const float p0 = fmaf(u, fmaf(u2, 1.0f / 24.0f, 0.25f), 0.25f);
+    const float p1 = fmaf(u, fmaf(u, fmaf(u, -1.0f / 48.0f, -0.125f), -0.3125f), -0.3125f);
+    return ex * rinv * fmaf(rho, fmaf(x4, p1, p0), 1.0f);
 }
 
 template <typename Real>
@@ -341,6 +382,7 @@ struct SumArgs {
     int far_gap;                      // smallest far-block gap (lattice units)
     int yukawa;                       // the far field is the sigma > 0 form (kq, yk)
     Real kq, yk;
+    float kl, ykl;                    // the same in lattice units (FP32 far-field blocks)
     double* part;
     int64_t ldp;
 };
@@ -430,6 +472,42 @@ __device__ __forceinline__ void lookup_step(const Lds<Real>& L, const Real* __re
     __builtin_amdgcn_sched_barrier(0);
 }
 
+// One FP32 far block (every pair beyond the far-field gap) from the binary16 lattice
+// differences: q = 2 (sigma = 0, its constant factor applied once at the end) or the
+// Yukawa form (sigma > 0).  Each step's sources are loaded one step ahead.
+template <typename Real, int NR, bool YUK>
+__device__ __forceinline__ void far2_block(const SumArgs<Real>& a, uint32_t txy, float tzl, int sb, Acc<Real> (&acc)[NR]) {
+    constexpr int U = unroll<Real>();
+    Step<Real, NR> nx = load_step<Real, NR, false, false, true>(a, sb);
+    // every counter drained here, so that the loop's only wait is for its own loads
+    __builtin_amdgcn_s_waitcnt(0);
+    for (int s0 = sb; s0 < sb + kSourceBlock; s0 += U) {
+        const Step<Real, NR> st = nx;
+        nx = load_step<Real, NR, false, false, true>(a, min(s0 + U, sb + kSourceBlock - U));
+#pragma unroll
+        for (int u0 = 0; u0 < U; u0 += 4) {
+            float Z[4], r2[4], m[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float dz = tzl - st.zl[u0 + k];
+                Z[k] = dz * dz;
+            }
+            far_pairs4(txy, st.xy[u0], st.xy[u0 + 1], st.xy[u0 + 2], st.xy[u0 + 3], Z, r2, m);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const Real G = YUK ? far_field_yukawa_lattice(r2[k], Z[k], m[k], a.kl, a.ykl)
+                                   : far_field_q2_lattice(r2[k], Z[k], m[k]);
+#pragma unroll
+                for (int r = 0; r < NR; ++r) acc[r].add(G * st.w[r][u0 + k]);
+            }
+        }
+    }
+    if (!YUK) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[r].scale_run(Real(kFarScale32));
+    }
+}
+
 // ROT: start at a block of the chunk that depends on the tile (see below); without it every
 // tile walks the chunk from its first block.
 template <typename Real, int NR, bool ROT = true>
@@ -483,33 +561,9 @@ __device__ __forceinline__ void sum_tile(const SumArgs<Real>& a, const Lds<Real>
                     for (int r = 0; r < NR; ++r) acc[r].add(G[u] * st.w[r][u]);
                 st = nx;
             }
-        } else if (sizeof(Real) == 4 && cls == kClassFar2 && !a.yukawa) {
-            Step<Real, NR> nx = load_step<Real, NR, false, false, true>(a, sb);
-            // every counter drained here, so that the loop's only wait is for its own loads
-            __builtin_amdgcn_s_waitcnt(0);
-            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += U) {
-                // this step's sources were loaded one step ahead; load the next one's now
-                const Step<Real, NR> st = nx;
-                nx = load_step<Real, NR, false, false, true>(a, min(s0 + U, sb + kSourceBlock - U));
-#pragma unroll
-                for (int u0 = 0; u0 < U; u0 += 4) {
-                    float Z[4], r2[4], m[4];
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const float dz = tzl - st.zl[u0 + k];
-                        Z[k] = dz * dz;
-                    }
-                    far_pairs4(txy, st.xy[u0], st.xy[u0 + 1], st.xy[u0 + 2], st.xy[u0 + 3], Z, r2, m);
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const Real G = far_field_q2_lattice(r2[k], Z[k], m[k]);
-#pragma unroll
-                        for (int r = 0; r < NR; ++r) acc[r].add(G * st.w[r][u0 + k]);
-                    }
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < NR; ++r) acc[r].scale_run(Real(kFarScale32));
+        } else if (sizeof(Real) == 4 && cls == kClassFar2) {
+            if (a.yukawa) far2_block<Real, NR, true>(a, txy, tzl, sb, acc);
+            else far2_block<Real, NR, false>(a, txy, tzl, sb, acc);
         } else if ((cls == kClassFar || cls == kClassFar2) && !a.yukawa) {
             for (int s0 = sb; s0 < sb + kSourceBlock; s0 += U) {
                 const Step<Real, NR> st = load_step<Real, NR, false, true>(a, s0);

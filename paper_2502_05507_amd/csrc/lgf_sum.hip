@@ -158,12 +158,14 @@ __global__ void lgf_eval_kernel(const int32_t* __restrict__ off, int64_t count, 
     const int64_t m = max(a, max(b, c));
     if (m > tab_r && far_ok) {
         const Real X = Real(kQuant * a), Y = Real(kQuant * b), Z = Real(kQuant * c);
-        if (yukawa) {
-            out[i] = (double)far_field_yukawa<Real>(X * X, Y * Y, Z * Z, kq, yk);
-        } else if constexpr (sizeof(Real) == 4) {
-            // the form of the sum's far blocks (lattice units)
+        if constexpr (sizeof(Real) == 4) {
+            // the forms of the sum's far blocks (lattice units)
             const float x2 = float(a * a), y2 = float(b * b), z2 = float(c * c);
-            out[i] = (double)(kFarScale32 * far_field_q2_lattice(x2 + y2 + z2, z2, y2 - x2));
+            out[i] = yukawa ? (double)far_field_yukawa_lattice(x2 + y2 + z2, z2, y2 - x2, (float)kq * kQuant,
+                                                                (float)yk * kQuant)
+                            : (double)(kFarScale32 * far_field_q2_lattice(x2 + y2 + z2, z2, y2 - x2));
+        } else if (yukawa) {
+            out[i] = (double)far_field_yukawa<Real>(X * X, Y * Y, Z * Z, kq, yk);
         } else {
             out[i] = (double)far_field<Real>(X * X, Y * Y, Z * Z);
         }
@@ -238,8 +240,9 @@ __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real
     const int row = lane & 15;            // A row (target within a tile) / B, D column (RHS)
     const int kq = lane >> 4;             // A column / B row (source within the step of 4)
     const int base = tile * kWave;
-    uint32_t ix[kTiles], iy[kTiles], iz[kTiles];
+    uint32_t ix[kTiles], iy[kTiles], iz[kTiles], txy[kTiles];
     Real fx[kTiles], fy[kTiles], fz[kTiles];
+    float tzl[kTiles];
     int lx = 1 << 30, ly = 1 << 30, lz = 1 << 30, hx = 0, hy = 0, hz = 0;
 #pragma unroll
     for (int j = 0; j < kTiles; ++j) {
@@ -247,6 +250,8 @@ __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real
         ix[j] = a.tx[tc];
         iy[j] = a.ty[tc];
         iz[j] = a.tz[tc];
+        txy[j] = sizeof(Real) == 4 ? a.txy[tc] : 0u;
+        tzl[j] = sizeof(Real) == 4 ? a.tzl[tc] : 0.f;
         fx[j] = (Real)ix[j];
         fy[j] = (Real)iy[j];
         fz[j] = (Real)iz[j];
@@ -293,7 +298,25 @@ __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real
             const int s = sb + st + kq;
             const Real wb = a.w[row * a.ldw + s];
             Real G[kTiles];
-            if (cls == kClassFar || cls == kClassFar2) {
+            if (sizeof(Real) == 4 && cls == kClassFar2) {
+                // FP32: binary16 lattice differences and two DOT2 per value
+                const uint32_t sxy = a.sxy[s];
+                const float szl = a.szl[s];
+                float Z[kTiles], r2[kTiles], m[kTiles];
+#pragma unroll
+                for (int j = 0; j < kTiles; ++j) {
+                    const float dz = tzl[j] - szl;
+                    Z[j] = dz * dz;
+                }
+                far_pairs4v(txy, sxy, Z, r2, m);
+                if (a.yukawa) {
+#pragma unroll
+                    for (int j = 0; j < kTiles; ++j) G[j] = far_field_yukawa_lattice(r2[j], Z[j], m[j], a.kl, a.ykl);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < kTiles; ++j) G[j] = kFarScale32 * far_field_q2_lattice(r2[j], Z[j], m[j]);
+                }
+            } else if (cls == kClassFar || cls == kClassFar2) {
                 const Real sx = a.sxr[s], sy = a.syr[s], sz = a.szr[s];
                 if (a.yukawa) {
 #pragma unroll
@@ -429,6 +452,8 @@ void launch_all(const PointSet& T, const PointSet& S, const Real* w, int nrhs, c
     a.yukawa = fp32 && tabs.yukawa32 ? 1 : 0;
     a.kq = (Real)(tabs.kappa / kQuant);
     a.yk = (Real)(-tabs.kappa * 1.4426950408889634 / kQuant);
+    a.kl = (float)tabs.kappa;
+    a.ykl = (float)(-tabs.kappa * 1.4426950408889634);
     a.ldp = (int64_t)plan.chunks * T.count;
     int r = 0;
     while (r < nrhs) {

@@ -79,7 +79,7 @@ typedef struct bae_levelset {
 typedef struct bae_options {   /* zero-initialise for defaults                      */
     int32_t device;            /* HIP device ordinal                                */
     int32_t near_radius_fp64;  /* must be 0: the LDS table radii are fixed by the     */
-    int32_t near_radius_fp32;  /* kernels (46 / 59 for sigma = 0, 44 / 55 otherwise)  */
+    int32_t near_radius_fp32;  /* kernels (47 / 60 for sigma = 0, 46 / 59 otherwise)  */
     int32_t max_krylov;        /* Krylov basis capacity per RHS (default 400)       */
     int32_t max_rhs;           /* right-hand sides the context can hold (default 16) */
 } bae_options;

@@ -56,10 +56,10 @@ void lgf_table_generate(double s, int R, double* out, hipStream_t stream);
 // touching its points.  Device coordinates are quantised: kQuant x the lattice index.
 constexpr int kSourceBlock = 64;
 constexpr int kQuant = 4;
-constexpr int kLdsRadiusFar32 = 59;       // LDS table radius of the FP32 sum, sigma = 0 (151 KB)
-constexpr int kLdsRadiusFar64 = 46;       // ... of the FP64 sum, sigma = 0 (147 KB)
-constexpr int kLdsRadius32 = 55;          // ... FP32, sigma > 0 and batched sums (123 KB + index arrays)
-constexpr int kLdsRadius64 = 44;          // ... FP64, sigma > 0 and batched sums (130 KB + index arrays)
+constexpr int kLdsRadiusFar32 = 60;       // LDS table radius of the FP32 sum, sigma = 0 (159 KB)
+constexpr int kLdsRadiusFar64 = 47;       // ... of the FP64 sum, sigma = 0 (157 KB)
+constexpr int kLdsRadius32 = 59;          // ... FP32, sigma > 0 and batched sums (151 KB + index arrays)
+constexpr int kLdsRadius64 = 46;          // ... FP64, sigma > 0 and batched sums (147 KB + index arrays)
 constexpr int kMaxTableRadius = 1200;     // largest resident table (sigma > 0)
 constexpr int kFarGap = 32;               // far field used beyond this gap (sigma = 0)
 constexpr double kYukawaTolerance = 1e-6; // sigma > 0 FP32 far field: largest accepted relative error

@@ -7,9 +7,9 @@
 // sum with sources M+ and weights h^2 f gives the free-space volume potential u_p.
 //
 // Kernel evaluation per (target, source) pair, offset d = T - S, c = max |d_i|:
-//   c <= RL : the LDS-resident prefix of the 1/48-symmetric table (sigma = 0: RL = 59 in
-//             FP32, 46 in FP64, 151 / 147 KB of the 160 KB LDS of a gfx950 compute unit;
-//             sigma > 0: 55 / 44, next to the index arrays that span the global table)
+//   c <= RL : the LDS-resident prefix of the 1/48-symmetric table (sigma = 0: RL = 60 in
+//             FP32, 47 in FP64, 159 / 157 KB of the 160 KB LDS of a gfx950 compute unit;
+//             sigma > 0: 59 / 46, next to the index arrays that span the global table)
 //   c >  RL : sigma = 0 -> far-field expansion in registers (valid beyond 32, below; q = 4
 //             in FP64, q = 2 in FP32, where the FP32 rounding of the sum dominates);
 //             sigma > 0 -> the full FP64/FP32 table in global memory (L2 / MALL resident)

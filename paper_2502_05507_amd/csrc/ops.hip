@@ -92,10 +92,33 @@ __global__ void dots_kernel(const double* __restrict__ X, int64_t ldx_vec, int64
     if (threadIdx.x == 0) partial[((int64_t)r * maxj + j) * nb + b] = s;
 }
 
+// Sum of nb partial results in a fixed order: eight independent running sums, so that
+// eight loads are in flight at a time (one sum would wait on every load in turn).
 __device__ inline double slice_sum(const double* p, int nb) {
+    double t[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int k = 0;
+    for (; k + 8 <= nb; k += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] += p[k + u];
+    }
+    for (int u = 0; k < nb; ++k, ++u) t[u] += p[k];
+    return ((t[0] + t[1]) + (t[2] + t[3])) + ((t[4] + t[5]) + (t[6] + t[7]));
+}
+
+// The same by the whole block (every thread calls it and gets the sum), for the longer
+// lists of norm slices: strided partial sums, then a wavefront tree and the wavefronts'
+// sums in order.
+__device__ double block_slice_sum(const double* p, int nb) {
+    __shared__ double ws[kThreads / 64];
     double t = 0.0;
-    for (int k = 0; k < nb; ++k) t += p[k];
-    return t;
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) t += p[k];
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    __syncthreads();   // an earlier call's readers are done with ws
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = t;
+    __syncthreads();
+    double sum = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += ws[w];
+    return sum;
 }
 
 // h[r][j] (+)= sum_b partial[r][j][b]   (the few places that need h itself)
@@ -154,12 +177,10 @@ __global__ void combination_kernel(const double* __restrict__ X, int64_t ldx_vec
 // Scale w = V[k+1] to unit length; ||w||^2 is the sum of its nn slices npart[r][*].
 __global__ void normalize_kernel(double* __restrict__ V, int64_t ldv_vec, int64_t ldv_rhs, int k, int64_t n,
                                  const double* __restrict__ npart, int nn, const int32_t* __restrict__ done) {
-    __shared__ double nr;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int r = blockIdx.y;
     if (done && done[r]) return;
-    if (threadIdx.x == 0) nr = sqrt(slice_sum(npart + (int64_t)r * nn, nn));
-    __syncthreads();
+    const double nr = sqrt(block_slice_sum(npart + (int64_t)r * nn, nn));
     if (i < n && nr > 0.0) V[r * ldv_rhs + (int64_t)(k + 1) * ldv_vec + i] /= nr;
 }
 
@@ -203,8 +224,9 @@ __device__ void givens_block(const GivensArgs& a, int r) {
         return slice_sum(a.pA + ((int64_t)r * a.maxj + i) * a.nb, a.nb) +
                slice_sum(a.pB + ((int64_t)r * a.maxj + i) * a.nb, a.nb);
     };
+    const double hk1_all = sqrt(block_slice_sum(a.npart + (int64_t)r * a.nn, a.nn));
     if (threadIdx.x == 0) {
-        hk1s = sqrt(slice_sum(a.npart + (int64_t)r * a.nn, a.nn));
+        hk1s = hk1_all;
         carry = hval(0);   // the entry the next rotation takes as its x
     }
     // rotation i mixes entries i and i + 1; chunk [i0, i1) of rotations
@@ -271,7 +293,6 @@ __global__ void finish_kernel(double* __restrict__ V, int64_t ldv_vec, int64_t l
                               const int32_t* __restrict__ col, const double* __restrict__ coef, int64_t ns,
                               int64_t npad, Real* __restrict__ w, int64_t ldw, const GivensArgs ga,
                               int32_t* host_flag) {
-    __shared__ double inv;
     const int r = blockIdx.y;
     const int b = blockIdx.x;
     if (b == nbn + nbw) {
@@ -282,11 +303,8 @@ __global__ void finish_kernel(double* __restrict__ V, int64_t ldv_vec, int64_t l
         return;
     }
     if (ga.done[r]) return;
-    if (threadIdx.x == 0) {
-        const double nr = sqrt(slice_sum(ga.npart + (int64_t)r * ga.nn, ga.nn));
-        inv = nr > 0.0 ? 1.0 / nr : 0.0;
-    }
-    __syncthreads();
+    const double nr = sqrt(block_slice_sum(ga.npart + (int64_t)r * ga.nn, ga.nn));
+    const double inv = nr > 0.0 ? 1.0 / nr : 0.0;
     const double* x = wv + r * ldwv;
     if (b < nbn) {
         const int64_t i = (int64_t)b * blockDim.x + threadIdx.x;

@@ -44,3 +44,14 @@ def test_null_arguments_are_rejected():
     assert b"null" in lib.bae_last_error()
     assert lib.bae_lgf_table(0.0, -1, None, None) == -1
     assert lib.bae_destroy(None) == 0
+
+
+@pytest.mark.parametrize("n,h,sigma,what", [((2050, 5, 5), 1 / 16, 0.0, "2049"), ((5, 4, 5), 1 / 16, 0.0, "2049"),
+                                            ((17, 17, 17), 0.0, 0.0, "h"), ((17, 17, 17), 1 / 16, -1.0, "sigma")])
+def test_grid_is_validated_before_any_device_work(n, h, sigma, what):
+    # n in [5, 2049]: lattice coordinates up to 2048 are exact in binary16, which the FP32
+    # far field's packed differences rely on
+    with pytest.raises(P.BaeError) as e:
+        P.Context(n, h, (0, 0, 0), sigma, "sphere", (0.5, 0.5, 0.5), (0.4,))
+    assert e.value.status == -1
+    assert what in str(e.value)

@@ -111,6 +111,10 @@ typedef struct bae_solve_params {
                                   max(floor, 0.5 tol / current residual), capped at 0.1 */
     int32_t max_outer;         /* refinement steps (default 8)                       */
     int32_t compute_grid;      /* also form u on N+ (volume-target LGF sums)         */
+    int32_t recycle_dim;       /* refined mode: the first inner solve's Krylov space (at
+                                  most this many vectors) augments the later inner
+                                  solves (GCRO); 0 = automatic (64 once a matvec has
+                                  1e8 pair interactions, else none), < 0 = none       */
 } bae_solve_params;
 
 typedef struct bae_result {

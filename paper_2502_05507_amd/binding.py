@@ -47,7 +47,7 @@ class Sizes(C.Structure):
 
 class SolveParams(C.Structure):
     _fields_ = [("precision", C.c_int32), ("tol", C.c_double), ("maxit", C.c_int32), ("inner_tol", C.c_double),
-                ("max_outer", C.c_int32), ("compute_grid", C.c_int32)]
+                ("max_outer", C.c_int32), ("compute_grid", C.c_int32), ("recycle_dim", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -255,9 +255,10 @@ class Context:
         _check(load_library().bae_set_rhs(self._h, nrhs, _ptr(g), _ptr(f)))
         self.nrhs = nrhs
 
-    def solve(self, precision=SOLVE_FP64, tol=1e-10, maxit=0, inner_tol=0.0, max_outer=0, compute_grid=False):
+    def solve(self, precision=SOLVE_FP64, tol=1e-10, maxit=0, inner_tol=0.0, max_outer=0, compute_grid=False,
+              recycle_dim=0):
         p = SolveParams(int(precision), float(tol), int(maxit), float(inner_tol), int(max_outer),
-                        1 if compute_grid else 0)
+                        1 if compute_grid else 0, int(recycle_dim))
         res = (Result * self.nrhs)()
         rc = load_library().bae_solve(self._h, C.byref(p), res)
         _check(rc, allow_not_converged=True)
@@ -330,7 +331,7 @@ class Batch:
         return {"blocks_per_chunk": int(chosen[0]), "grid_multiplier": int(chosen[1])}
 
     def solve(self, precision=SOLVE_FP64, tol=1e-10, maxit=0, inner_tol=0.0, max_outer=0, use_graph=True):
-        p = SolveParams(int(precision), float(tol), int(maxit), float(inner_tol), int(max_outer), 0)
+        p = SolveParams(int(precision), float(tol), int(maxit), float(inner_tol), int(max_outer), 0, 0)
         res = (Result * len(self.contexts))()
         rc = load_library().bae_batch_solve(self._h, C.byref(p), 1 if use_graph else 0, res)
         _check(rc, allow_not_converged=True)

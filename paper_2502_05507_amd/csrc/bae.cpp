@@ -96,10 +96,122 @@ struct GmresOut {
     std::vector<double> last_est;
 };
 
+// Krylov recycling between the inner solves of a refined solve (GCRO, de Sturler): U and
+// C = A32 U with orthonormal columns, from the first inner solve's Arnoldi relation
+// A32 V_k = V_{k+1} Hbar: with Hbar = Q R (the solve's own Givens rotations give Q, its
+// triangular factor R), U = V_k R^-1 and C = V_{k+1} Q.  A later inner solve first takes
+// the part of its right-hand side in the span of C, then runs GMRES on the rest with every
+// new Krylov vector orthogonalised against C as well; the coefficients of that step (the
+// slices of C'w) are kept for the final update.  A restarted solve would rebuild those
+// directions from nothing: its right-hand side, the FP32 operator's error, converges slowly.
+struct Recycle {
+    int p = 0;                    // recycled vectors per RHS (0: none)
+    int64_t ld = 0;               // p * n, per-RHS stride of U and C
+    double* U = nullptr;
+    double* C = nullptr;
+    double* slices = nullptr;     // [step][rhs][p][dot_blocks(n)]
+};
+constexpr int kRecycleDefault = 64;
+
+static void build_recycle(bae_ctx* c, int nrhs, const std::vector<int>& skip, int cap, Recycle& rc, hipStream_t st) {
+    KrylovState& K = c->K;
+    const int64_t n = c->ngm;
+    rc.p = 0;
+    std::vector<int32_t> kd(nrhs);
+    BAE_HIP_CHECK(hipMemcpyAsync(kd.data(), K.kdone, sizeof(int32_t) * nrhs, hipMemcpyDeviceToHost, st));
+    BAE_HIP_CHECK(hipStreamSynchronize(st));
+    int p = 0;
+    for (int r = 0; r < nrhs; ++r)
+        if (skip.empty() || !skip[r]) p = std::max(p, (int)kd[r]);
+    p = std::min(p, cap);
+    if (p < 2) return;
+    const int64_t hsz = (int64_t)K.m * (K.m + 1);
+    std::vector<double> H((size_t)hsz * nrhs), cs((size_t)K.m * nrhs), sn((size_t)K.m * nrhs);
+    BAE_HIP_CHECK(hipMemcpyAsync(H.data(), K.H, sizeof(double) * H.size(), hipMemcpyDeviceToHost, st));
+    BAE_HIP_CHECK(hipMemcpyAsync(cs.data(), K.cs, sizeof(double) * cs.size(), hipMemcpyDeviceToHost, st));
+    BAE_HIP_CHECK(hipMemcpyAsync(sn.data(), K.sn, sizeof(double) * sn.size(), hipMemcpyDeviceToHost, st));
+    BAE_HIP_CHECK(hipStreamSynchronize(st));
+    std::vector<double> MQ((size_t)nrhs * (p + 1) * p, 0.0), MU((size_t)nrhs * p * p, 0.0);
+    for (int r = 0; r < nrhs; ++r) {
+        if (!skip.empty() && skip[r]) continue;
+        const int k = std::min((int)kd[r], p);
+        const double* Hr = H.data() + r * hsz;
+        auto R = [&](int i, int j) { return Hr[(int64_t)j * (K.m + 1) + i]; };   // R[i][j], i <= j < k
+        bool ok = k >= 1;
+        for (int j = 0; j < k && ok; ++j) ok = std::isfinite(R(j, j)) && R(j, j) != 0.0;
+        if (!ok) continue;   // this RHS recycles nothing (its columns stay zero)
+        // Q = G_0' G_1' ... G_{k-1}' [I_k; 0]; rotation j mixes rows j, j + 1 as (c s; -s c)
+        double* q = MQ.data() + (size_t)r * (p + 1) * p;
+        for (int l = 0; l < k; ++l) q[l * p + l] = 1.0;
+        for (int j = k - 1; j >= 0; --j) {
+            const double cj = cs[(size_t)r * K.m + j], sj = sn[(size_t)r * K.m + j];
+            for (int l = 0; l < k; ++l) {
+                const double a = q[j * p + l], b = q[(j + 1) * p + l];
+                q[j * p + l] = cj * a - sj * b;
+                q[(j + 1) * p + l] = sj * a + cj * b;
+            }
+        }
+        // R^-1 (upper triangular), column by column
+        double* u = MU.data() + (size_t)r * p * p;
+        for (int l = 0; l < k; ++l) {
+            u[l * p + l] = 1.0 / R(l, l);
+            for (int i = l - 1; i >= 0; --i) {
+                double acc = 0.0;
+                for (int j = i + 1; j <= l; ++j) acc += R(i, j) * u[j * p + l];
+                u[i * p + l] = -acc / R(i, i);
+            }
+        }
+    }
+    const int64_t per = (int64_t)nrhs * p * n;
+    if (c->rcU.bytes < sizeof(double) * per) c->rcU.alloc(sizeof(double) * per);
+    if (c->rcC.bytes < sizeof(double) * per) c->rcC.alloc(sizeof(double) * per);
+    const int64_t sl = (int64_t)K.m * nrhs * p * dot_blocks(n);
+    if (c->rcS.bytes < sizeof(double) * sl) c->rcS.alloc(sizeof(double) * sl);
+    DevMem mq, mu;
+    upload(mq, MQ, st);
+    upload(mu, MU, st);
+    rc.p = p;
+    rc.ld = (int64_t)p * n;
+    rc.U = c->rcU.as<double>();
+    rc.C = c->rcC.as<double>();
+    rc.slices = c->rcS.as<double>();
+    launch_basis_transform(K.V, n, K.ld_rhs, p + 1, mq.as<double>(), p, n, nrhs, rc.C, n, rc.ld, st);
+    launch_basis_transform(K.V, n, K.ld_rhs, p, mu.as<double>(), p, n, nrhs, rc.U, n, rc.ld, st);
+    BAE_HIP_CHECK(hipStreamSynchronize(st));   // mq, mu are released on return
+}
+
+// x += U C'r and r -= C C'r (the part of r in the span of C), skipped RHS left alone.
+static void recycle_project(bae_ctx* c, const Recycle& rc, int nrhs, const std::vector<int>& skip, double* x,
+                            double* r, hipStream_t st) {
+    const int64_t n = c->ngm;
+    DevMem c0, pn;
+    c0.alloc(sizeof(double) * 2 * nrhs * rc.p);
+    launch_dots(rc.C, n, rc.ld, rc.p, r, n, n, nrhs, nullptr, c->dotpart.as<double>(), c->maxj, c0.as<double>(),
+                rc.p, 0, st);
+    std::vector<double> h((size_t)2 * nrhs * rc.p);
+    BAE_HIP_CHECK(hipMemcpyAsync(h.data(), c0.p, sizeof(double) * nrhs * rc.p, hipMemcpyDeviceToHost, st));
+    BAE_HIP_CHECK(hipStreamSynchronize(st));
+    for (int q = 0; q < nrhs; ++q)
+        for (int l = 0; l < rc.p; ++l) {
+            double& v = h[(size_t)q * rc.p + l];
+            if (!skip.empty() && skip[q]) v = 0.0;
+            h[(size_t)nrhs * rc.p + (size_t)q * rc.p + l] = -v;
+        }
+    BAE_HIP_CHECK(hipMemcpyAsync(c0.p, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, st));
+    std::vector<int32_t> pv(nrhs, rc.p);
+    upload(pn, pv, st);
+    launch_combination(rc.U, n, rc.ld, c0.as<double>(), rc.p, pn.as<int32_t>(), n, nrhs, x, n, 1, st);
+    launch_combination(rc.C, n, rc.ld, c0.as<double>() + (int64_t)nrhs * rc.p, rc.p, pn.as<int32_t>(), n, nrhs, r, n,
+                       1, st);
+    BAE_HIP_CHECK(hipStreamSynchronize(st));
+}
+
 // GMRES on A d = r0 for nrhs RHS (x0 = 0), then x (+)= d.  skip[r] marks RHS left alone.
+// With rc, every Krylov vector is first orthogonalised against rc.C and x gets the matching
+// U correction (GCRO).
 static GmresOut gmres(bae_ctx* c, const double* r0, int nrhs, int prec, double tol, int maxit,
                       const std::vector<int>& skip, double* xout, bool accumulate, hipStream_t st,
-                      int64_t* matvecs) {
+                      int64_t* matvecs, const Recycle* rc = nullptr) {
     KrylovState& K = c->K;
     const int64_t n = c->ngm;
     const int m = std::min(maxit, K.m);
@@ -137,6 +249,11 @@ static GmresOut gmres(bae_ctx* c, const double* r0, int nrhs, int prec, double t
                   lagged ? K.done : nullptr);
         launch_closure(c->part.as<double>(), chunks, c->nT, c->cl, wv, n, nrhs, c->vsum.as<double>(), st);
         (*matvecs)++;
+        if (rc) {   // w -= C (C'w), the coefficients kept for the final update
+            double* sl = rc->slices + (int64_t)k * nrhs * rc->p * dot_blocks(n);
+            launch_dot_slices(rc->C, n, rc->ld, rc->p, wv, n, n, nrhs, K.done, sl, rc->p, st);
+            launch_subtract_combination(rc->C, n, rc->ld, sl, rc->p, rc->p, n, nrhs, K.done, wv, n, nullptr, st);
+        }
         // classical Gram-Schmidt twice (dot-product slices in pA, pB); the second pass also
         // forms the slices of ||w||^2 (pN), which the closing launch sums itself
         launch_dot_slices(K.V, n, K.ld_rhs, k + 1, wv, n, n, nrhs, K.done, pA, c->maxj, st);
@@ -204,6 +321,31 @@ static GmresOut gmres(bae_ctx* c, const double* r0, int nrhs, int prec, double t
     BAE_HIP_CHECK(hipMemcpyAsync(kdev.p, kd.data(), sizeof(int32_t) * nrhs, hipMemcpyHostToDevice, st));
     launch_combination(K.V, n, K.ld_rhs, c->ycoef.as<double>(), K.m, kdev.as<int32_t>(), n, nrhs, xout, n,
                        accumulate ? 1 : 0, st);
+    if (rc) {
+        // x -= U (B y), B[l][j] = C_l' w_j summed from step j's slices
+        const int nbd = dot_blocks(n);
+        int kmax = 0;
+        for (int r = 0; r < nrhs; ++r) kmax = std::max(kmax, kd[r]);
+        std::vector<double> sl((size_t)kmax * nrhs * rc->p * nbd), z((size_t)nrhs * rc->p, 0.0);
+        if (kmax > 0)
+            BAE_HIP_CHECK(hipMemcpyAsync(sl.data(), rc->slices, sizeof(double) * sl.size(), hipMemcpyDeviceToHost, st));
+        BAE_HIP_CHECK(hipStreamSynchronize(st));
+        for (int r = 0; r < nrhs; ++r)
+            for (int j = 0; j < kd[r]; ++j) {
+                const double yj = y[(size_t)r * K.m + j];
+                for (int l = 0; l < rc->p; ++l) {
+                    const double* b = sl.data() + (((size_t)j * nrhs + r) * rc->p + l) * nbd;
+                    double blj = 0.0;
+                    for (int q = 0; q < nbd; ++q) blj += b[q];
+                    z[(size_t)r * rc->p + l] -= blj * yj;
+                }
+            }
+        DevMem zd, pn;
+        upload(zd, z, st);
+        std::vector<int32_t> pv(nrhs, rc->p);
+        upload(pn, pv, st);
+        launch_combination(rc->U, n, rc->ld, zd.as<double>(), rc->p, pn.as<int32_t>(), n, nrhs, xout, n, 1, st);
+    }
     BAE_HIP_CHECK(hipStreamSynchronize(st));
     return out;
 }
@@ -450,6 +592,8 @@ int64_t estimate_context_bytes(const Geometry& G, double s, const bae_options* o
     b += (int64_t)(m + 1) * mr * 8 * (3 + 2 * dot_blocks(ngm)) + (int64_t)m * mr * 8;  // CGS, dot slices, y
     b += (int64_t)norm_blocks(ngm) * mr * 8;                                           // norm slices
     b += 4 * ngm * mr * 8 + 2 * nT * mr * 8;                                           // b, x, r, tmp, u_p, u_gamma
+    const int64_t pr = std::min<int64_t>(kRecycleDefault, m);
+    b += (2 * ngm + (int64_t)m * dot_blocks(ngm)) * pr * mr * 8;                      // refined solves' recycling
     if (s > 0.0) b += table_size(std::max(32, G.max_offset)) * 12;                     // its own table
     return b;
 }
@@ -650,6 +794,13 @@ int bae_solve(bae_ctx* c, const bae_solve_params* p, bae_result* res) {
             // relative) makes further inner iterations useless
             const double floor_tol = p->inner_tol > 0 ? p->inner_tol : 1e-6;
             const int max_outer = p->max_outer > 0 ? p->max_outer : 8;
+            // recycling costs a few host round trips per outer step: worth it once a matvec
+            // is long (1e8 pair interactions, ~50 us), not for the smallest problems
+            const bool long_matvec = (double)c->nT * (double)c->nS * nrhs >= 1e8;
+            const int recycle_cap = p->recycle_dim < 0   ? 0
+                                    : p->recycle_dim > 0 ? p->recycle_dim
+                                                         : (long_matvec ? kRecycleDefault : 0);
+            Recycle rc;
             BAE_HIP_CHECK(hipMemcpyAsync(c->r.p, c->b.p, sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, st));
             relres.assign(nrhs, 1.0);
             for (int r = 0; r < nrhs; ++r) relres[r] = bn[r] > 0 ? 1.0 : 0.0;
@@ -664,15 +815,31 @@ int bae_solve(bae_ctx* c, const bae_solve_params* p, bae_result* res) {
                 }
                 if (all) break;
                 const double inner = std::min(0.1, std::max(floor_tol, 0.5 * p->tol / worst));
-                GmresOut g = gmres(c, c->r.as<double>(), nrhs, BAE_PREC_FP32, inner, maxit, skip, c->x.as<double>(),
-                                   true, st, &mv32);
+                // with a recycled space: its part of the residual first, then GMRES on the
+                // rest to the same absolute target (tolerance relative to what is left)
+                double gtol = inner;
+                std::vector<double> rscale(relres);
+                if (rc.p > 0) {
+                    recycle_project(c, rc, nrhs, skip, c->x.as<double>(), c->r.as<double>(), st);
+                    const std::vector<double> rn = host_norms(c, c->r.as<double>(), nrhs, st);
+                    double ratio = 1e300;
+                    for (int r = 0; r < nrhs; ++r) {
+                        if (skip[r]) continue;
+                        rscale[r] = bn[r] > 0 ? rn[r] / bn[r] : 0.0;
+                        if (rn[r] > 0) ratio = std::min(ratio, relres[r] * bn[r] / rn[r]);
+                    }
+                    gtol = ratio < 1e300 ? std::min(0.5, inner * ratio) : inner;
+                }
+                GmresOut g = gmres(c, c->r.as<double>(), nrhs, BAE_PREC_FP32, gtol, maxit, skip, c->x.as<double>(),
+                                   true, st, &mv32, rc.p > 0 ? &rc : nullptr);
                 for (int r = 0; r < nrhs; ++r) {
                     iters[r] += g.iters[r];
                     if (!skip[r]) {
                         outer[r]++;
-                        est[r] = g.last_est[r] * relres[r];
+                        est[r] = g.last_est[r] * rscale[r];
                     }
                 }
+                if (o == 0 && recycle_cap > 0) build_recycle(c, nrhs, skip, recycle_cap, rc, st);
                 relres = residual(c, nrhs, bn, st, &mv64);
                 dq_in_vsum = true;
             }

@@ -194,6 +194,7 @@ struct bae_ctx {
     int maxj = 0;
     DevMem hA, hB, nrm, dotpart, ycoef;
     DevMem b, x, r, tmp;       // [rhs][ngm]
+    DevMem rcU, rcC, rcS;      // Krylov recycling of refined solves: U, C [rhs][p][ngm], C'w slices
     DevMem up_gamma;           // [rhs][nT] external order
     DevMem u_gamma;            // [rhs][nT]
     DevMem vsum;               // [rhs][nT] chunk-reduced sums (operator scratch)

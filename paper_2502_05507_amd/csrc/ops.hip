@@ -174,6 +174,23 @@ __global__ void combination_kernel(const double* __restrict__ X, int64_t ldx_vec
     y[r * ldy + i] = accumulate ? y[r * ldy + i] + acc : acc;
 }
 
+// out[r][l] = sum_{j < kin} X[r][j] M[r][j][l] for l < kout (a change of basis of a few
+// vectors; M is small and row-major per RHS).
+__global__ void basis_transform_kernel(const double* __restrict__ X, int64_t ldx_vec, int64_t ldx_rhs, int kin,
+                                       const double* __restrict__ M, int kout, int64_t n, double* __restrict__ out,
+                                       int64_t ldo_vec, int64_t ldo_rhs) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i >= n) return;
+    const double* x = X + r * ldx_rhs + i;
+    const double* mr = M + (int64_t)r * kin * kout;
+    for (int l = 0; l < kout; ++l) {
+        double acc = 0.0;
+        for (int j = 0; j < kin; ++j) acc = fma(x[j * ldx_vec], mr[j * kout + l], acc);
+        out[r * ldo_rhs + l * ldo_vec + i] = acc;
+    }
+}
+
 // Scale w = V[k+1] to unit length; ||w||^2 is the sum of its nn slices npart[r][*].
 __global__ void normalize_kernel(double* __restrict__ V, int64_t ldv_vec, int64_t ldv_rhs, int k, int64_t n,
                                  const double* __restrict__ npart, int nn, const int32_t* __restrict__ done) {
@@ -470,6 +487,14 @@ void launch_finish(const KrylovState& K, const double* wv, int64_t ldwv, const d
         finish_kernel<float><<<grid, kThreads, 0, st>>>(K.V, K.n, K.ld_rhs, wv, ldwv, K.n, nbn, nbw, B.rowptr, B.col,
                                                          B.coef, B.rows, B.padded_rows, (float*)w, ldw, ga,
                                                          host_flag);
+    LAUNCH_CHECK();
+}
+
+void launch_basis_transform(const double* X, int64_t ldx_vec, int64_t ldx_rhs, int kin, const double* M, int kout,
+                            int64_t n, int nrhs, double* out, int64_t ldo_vec, int64_t ldo_rhs, hipStream_t st) {
+    if (n == 0 || kout == 0) return;
+    basis_transform_kernel<<<dim3(blocks_for(n), nrhs), kThreads, 0, st>>>(X, ldx_vec, ldx_rhs, kin, M, kout, n, out,
+                                                                          ldo_vec, ldo_rhs);
     LAUNCH_CHECK();
 }
 

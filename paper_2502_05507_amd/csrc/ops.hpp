@@ -62,6 +62,9 @@ void launch_subtract_combination(const double* X, int64_t ldx_vec, int64_t ldx_r
                                  int nj, int64_t n, int nrhs, const int32_t* done, double* y, int64_t ldy,
                                  double* npart, hipStream_t st);
 int norm_blocks(int64_t n);
+// out[r][l] = sum_{j < kin} X[r][j] M[r][j][l], l < kout; M [nrhs][kin][kout] on the device.
+void launch_basis_transform(const double* X, int64_t ldx_vec, int64_t ldx_rhs, int kin, const double* M, int kout,
+                            int64_t n, int nrhs, double* out, int64_t ldo_vec, int64_t ldo_rhs, hipStream_t st);
 void launch_combination(const double* X, int64_t ldx_vec, int64_t ldx_rhs, const double* c, int64_t ldc,
                         const int32_t* nj, int64_t n, int nrhs, double* y, int64_t ldy, int accumulate,
                         hipStream_t st);

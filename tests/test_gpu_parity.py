@@ -286,3 +286,25 @@ def test_sixteen_rhs_blocked_form_matches_oracle(kind, n, sigma):
                 out = out[:, pick]
             for r in range(nr):
                 assert rel_l2(out[r], ref[r]) < tol, (prec, r, rel_l2(out[r], ref[r]))
+
+
+# ------------------------------------------------------------------ A9: refinement with Krylov recycling
+@pytest.mark.parametrize("kind,n,sigma,nr", [("sphere", 33, 0.0, 1), ("torus", 41, 10.0, 3)])
+def test_refined_solve_with_recycling_matches_oracle(kind, n, sigma, nr):
+    """The later inner solves of a refined solve, augmented with the first one's Krylov space
+    (forced on here; automatic only for long matvecs), reach the oracle's FP64 densities, in
+    no more iterations than plain restarts."""
+    p = small_problem(kind, n, sigma)
+    g, G = oracle_setup(p)
+    rng = np.random.default_rng(17 * n)
+    gs = [W.harmonic_poly(c, (0.5, 0.5, 0.5)) for c in rng.standard_normal((nr, 16))]
+    refs = [gmres.gmres(lambda x: operators.bae_apply(g, G, x), fn(*g.xstar.T), tol=1e-13)[0] for fn in gs]
+    with P.Context.from_problem(p, max_rhs=nr) as ctx:
+        xs, _, _ = ctx.boundary_points()
+        ctx.set_rhs(np.stack([fn(*xs.T) for fn in gs]))
+        plain = ctx.solve(P.SOLVE_FP32_REFINED, tol=1e-10, recycle_dim=-1)
+        res = ctx.solve(P.SOLVE_FP32_REFINED, tol=1e-10, recycle_dim=32)
+        for r in range(nr):
+            assert res[r]["converged"] and res[r]["rel_residual_true"] <= 1e-10
+            assert res[r]["iterations"] <= plain[r]["iterations"], (res[r]["iterations"], plain[r]["iterations"])
+            assert rel_l2(ctx.density(r), refs[r]) < 1e-8, (r, rel_l2(ctx.density(r), refs[r]))

@@ -190,7 +190,9 @@ __device__ __forceinline__ Real far_field_yukawa(Real X, Real Y, Real Z, Real kq
 
 // The same sigma > 0 form from the lattice offset (FP32), through r2, Z and m as in
 // far_field_q2_lattice: with x4 = 4 e2/|n|^4 = 1 + 2 zeta - 3 zeta^2 - mu^2, the bracket is
-//   T2 |n|^2 = P0(u) + x4 P1(u),  P0 = (1 + u)/4 + u^3/24,  P1 = -5(1 + u)/16 - u^2/8 - u^3/48.
+//   T2 |n|^2 = P0(u) + x4 P1(u),  P0 = (1 + u)/4 + u^3/24,  P1 = -5(1 + u)/16 - u^2/8 - u^3/48,
+// evaluated as one cubic in u, A (1 + u) + B u^2 + C u^3 with A = 1/4 - 5 x4/16, B = -x4/8
+// and C = 1/24 - x4/48.
 // kl = kappa, ykl = -kappa log2(e) (lattice units).
 __device__ __forceinline__ float far_field_yukawa_lattice(float r2, float Z, float m, float kl, float ykl) {
     constexpr float kLog2C = -3.6514961294723187f;   // log2(1 / (4 pi))
@@ -201,10 +203,11 @@ __device__ __forceinline__ float far_field_yukawa_lattice(float r2, float Z, flo
     const float rq = r2 * rinv;
     const float u = rq * kl;
     const float ex = __builtin_amdgcn_exp2f(fmaf(rq, ykl, kLog2C));
-    const float u2 = u * u;
-    const float p0 = fmaf(u, fmaf(u2, 1.0f / 24.0f, 0.25f), 0.25f);
-    const float p1 = fmaf(u, fmaf(u, fmaf(u, -1.0f / 48.0f, -0.125f), -0.3125f), -0.3125f);
-    return ex * rinv * fmaf(rho, fmaf(x4, p1, p0), 1.0f);
+    const float A = fmaf(x4, -0.3125f, 0.25f);
+    const float B = -0.125f * x4;
+    const float C = fmaf(x4, -1.0f / 48.0f, 1.0f / 24.0f);
+    const float br = fmaf(u, fmaf(u, fmaf(u, C, B), A), A);
+    return ex * rinv * fmaf(rho, br, 1.0f);
 }
 
 template <typename Real>

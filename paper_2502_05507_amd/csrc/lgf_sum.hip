@@ -233,6 +233,50 @@ struct MfmaAcc<double> {
     __device__ static V mma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 };
 
+// FP32 far block (every pair beyond the far-field gap): the lattice-form far field from the
+// binary16 differences, with the next step's source and weight loads in flight while this
+// step is evaluated.  The 16 steps are unrolled so that every load addresses its block by an
+// immediate offset from three per-lane pointers set once per block.  Without the Yukawa
+// factor the block sums are scaled by kFarScale32 once at the end.
+template <bool YUK>
+__device__ __forceinline__ void mfma_far2_block(const SumArgs<float>& a, const uint32_t (&txy)[kTiles],
+                                                const float (&tzl)[kTiles], int sb, int row, int kq,
+                                                MfmaAcc<float>::V (&blk)[kTiles]) {
+    const uint32_t* pxy = a.sxy + (sb + kq);
+    const float* pzl = a.szl + (sb + kq);
+    const float* pw = a.w + ((int64_t)row * a.ldw + sb + kq);
+    // every counter drained here, so that the loop's waits are for its own loads only
+    __builtin_amdgcn_s_waitcnt(0);
+    uint32_t sxy = pxy[0];
+    float szl = pzl[0], wb = pw[0];
+#pragma unroll
+    for (int st = 0; st < kSourceBlock; st += 4) {
+        const int nx = st + 4 < kSourceBlock ? st + 4 : st;
+        const uint32_t sxy_n = pxy[nx];
+        const float szl_n = pzl[nx], wb_n = pw[nx];
+        float Z[kTiles], r2[kTiles], m[kTiles], G[kTiles];
+#pragma unroll
+        for (int j = 0; j < kTiles; ++j) {
+            const float dz = tzl[j] - szl;
+            Z[j] = dz * dz;
+        }
+        far_pairs4v(txy, sxy, Z, r2, m);
+#pragma unroll
+        for (int j = 0; j < kTiles; ++j)
+            G[j] = YUK ? far_field_yukawa_lattice(r2[j], Z[j], m[j], a.kl, a.ykl) : far_field_q2_lattice(r2[j], Z[j], m[j]);
+#pragma unroll
+        for (int j = 0; j < kTiles; ++j) blk[j] = MfmaAcc<float>::mma(G[j], wb, blk[j]);
+        sxy = sxy_n;
+        szl = szl_n;
+        wb = wb_n;
+    }
+    if (!YUK) {
+#pragma unroll
+        for (int j = 0; j < kTiles; ++j)
+            for (int v = 0; v < 4; ++v) blk[j][v] *= kFarScale32;
+    }
+}
+
 template <typename Real>
 __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real>& L, int tile, int chunk) {
     using V = typename MfmaAcc<Real>::V;
@@ -294,29 +338,18 @@ __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real
 #pragma unroll
         for (int j = 0; j < kTiles; ++j)
             for (int v = 0; v < 4; ++v) blk[j][v] = Real(0);
+        if constexpr (sizeof(Real) == 4) {
+            if (cls == kClassFar2) {
+                if (a.yukawa) mfma_far2_block<true>(a, txy, tzl, sb, row, kq, blk);
+                else mfma_far2_block<false>(a, txy, tzl, sb, row, kq, blk);
+            }
+        }
+        if (sizeof(Real) == 8 || cls != kClassFar2)
         for (int st = 0; st < kSourceBlock; st += 4) {
             const int s = sb + st + kq;
             const Real wb = a.w[row * a.ldw + s];
             Real G[kTiles];
-            if (sizeof(Real) == 4 && cls == kClassFar2) {
-                // FP32: binary16 lattice differences and two DOT2 per value
-                const uint32_t sxy = a.sxy[s];
-                const float szl = a.szl[s];
-                float Z[kTiles], r2[kTiles], m[kTiles];
-#pragma unroll
-                for (int j = 0; j < kTiles; ++j) {
-                    const float dz = tzl[j] - szl;
-                    Z[j] = dz * dz;
-                }
-                far_pairs4v(txy, sxy, Z, r2, m);
-                if (a.yukawa) {
-#pragma unroll
-                    for (int j = 0; j < kTiles; ++j) G[j] = far_field_yukawa_lattice(r2[j], Z[j], m[j], a.kl, a.ykl);
-                } else {
-#pragma unroll
-                    for (int j = 0; j < kTiles; ++j) G[j] = kFarScale32 * far_field_q2_lattice(r2[j], Z[j], m[j]);
-                }
-            } else if (cls == kClassFar || cls == kClassFar2) {
+            if (sizeof(Real) == 8 && cls == kClassFar) {
                 const Real sx = a.sxr[s], sy = a.syr[s], sz = a.szr[s];
                 if (a.yukawa) {
 #pragma unroll
@@ -350,7 +383,11 @@ __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real
                         if (max3u(da, db, dc) <= tab_q) {
                             G[j] = lds_value(L, table_offset(L, da, db, dc));
                         } else if (a.far_ok) {
-                            const Real dx = fx[j] - a.sxr[s], dy = fy[j] - a.syr[s], dz = fz[j] - a.szr[s];
+                            // FP32: the target's coordinates converted here, not kept in registers
+                            const Real tx = sizeof(Real) == 8 ? fx[j] : (Real)ix[j];
+                            const Real ty = sizeof(Real) == 8 ? fy[j] : (Real)iy[j];
+                            const Real tz = sizeof(Real) == 8 ? fz[j] : (Real)iz[j];
+                            const Real dx = tx - a.sxr[s], dy = ty - a.syr[s], dz = tz - a.szr[s];
                             G[j] = a.yukawa ? far_field_yukawa<Real>(dx * dx, dy * dy, dz * dz, a.kq, a.yk)
                                             : far_field<Real>(dx * dx, dy * dy, dz * dz);
                         } else {

@@ -527,8 +527,10 @@ int lgf_sum_chunks(int64_t nt, int64_t nblk) {
     const int64_t groups = (nt + kWave * kGroupTiles - 1) / (kWave * kGroupTiles);
     // about 32 items per workgroup of a full MI355X (256 CUs): fine enough that the
     // workgroups finish together (with 8, the 257^3 sums lose 10% to the last items)
+    // (a small sum, of fewer items than workgroups, gets one source block per item, so
+    // that its few wavefronts each walk as short a chain of steps as possible)
     int64_t chunks = (32 * 256 + groups - 1) / groups;
-    chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, nblk / 2));   // at least 2 blocks per item
+    chunks = std::min<int64_t>(chunks, std::max<int64_t>(1, nblk));
     return (int)std::max<int64_t>(1, std::min<int64_t>(chunks, kMaxChunks));
 }
 

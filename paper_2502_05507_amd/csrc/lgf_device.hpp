@@ -19,7 +19,13 @@ namespace lgfdev {
 
 constexpr int kWave = 64;
 template <typename Real>
-constexpr int unroll() { return 32 / (int)sizeof(Real); }   // sources per unrolled step (32-byte scalar loads)
+constexpr int unroll() { return 4; }   // sources per unrolled step
+// Sources per step of the one-RHS table loop: 32-byte scalar loads, twice as many LDS reads in
+// flight.  Every other loop takes 4, so that its double-buffered sources leave the block loop
+// enough scalar registers (with 8 everywhere the FP32 sum spilled 69 of them to VGPR lanes and
+// restored them in every block; far-dominated sums ran 7% slower).
+template <typename Real, int NR>
+constexpr int table_unroll() { return NR == 1 ? 32 / (int)sizeof(Real) : 4; }
 constexpr int kMaxR = kMaxTableRadius;               // largest table radius (tet / tri arrays)
 
 // LDS layouts.  FAR (sigma = 0, far field beyond the table): the index arrays only need the
@@ -410,9 +416,8 @@ __device__ __forceinline__ vec_t<T, N> ldu_vec(const T* p, int64_t i) {
     return *((const __attribute__((address_space(4))) vec_t<T, N>*)(p + i));
 }
 
-template <typename Real, int NR>
+template <typename Real, int NR, int U = unroll<Real>()>
 struct Step {
-    static constexpr int U = unroll<Real>();
     vec_t<uint32_t, U> x, y, z;     // quantised integer coordinates (table / gather / mixed)
     vec_t<Real, U> xr, yr, zr;      // the same in the kernel's precision (far field / mixed)
     vec_t<uint32_t, U> xy;          // lattice (x, y) as binary16 pairs and z (FP32 far field)
@@ -420,10 +425,9 @@ struct Step {
     vec_t<Real, U> w[NR];
 };
 
-template <typename Real, int NR, bool INT, bool REAL, bool HALF = false>
-__device__ __forceinline__ Step<Real, NR> load_step(const SumArgs<Real>& a, int s0) {
-    constexpr int U = unroll<Real>();
-    Step<Real, NR> st;
+template <typename Real, int NR, bool INT, bool REAL, bool HALF = false, int U = unroll<Real>()>
+__device__ __forceinline__ Step<Real, NR, U> load_step(const SumArgs<Real>& a, int s0) {
+    Step<Real, NR, U> st;
     if constexpr (HALF) {
         st.xy = ldu_vec<uint32_t, U>(a.sxy, s0);
         st.zl = ldu_vec<float, U>(a.szl, s0);
@@ -553,13 +557,15 @@ __device__ __forceinline__ void sum_tile(const SumArgs<Real>& a, const Lds<Real>
         if (cls == kClassTable) {
             // the next step's sources are loaded while this step's table reads are in
             // flight (the last step reloads its own: the block's end is the array's end)
-            Step<Real, NR> st = load_step<Real, NR, true, false>(a, sb);
-            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += U) {
-                Real G[U];
-                lookup_step<Real, U, false>(L, nullptr, ix, iy, iz, st.x, st.y, st.z, G);
-                const Step<Real, NR> nx = load_step<Real, NR, true, false>(a, min(s0 + U, sb + kSourceBlock - U));
+            constexpr int UT = table_unroll<Real, NR>();
+            Step<Real, NR, UT> st = load_step<Real, NR, true, false, false, UT>(a, sb);
+            for (int s0 = sb; s0 < sb + kSourceBlock; s0 += UT) {
+                Real G[UT];
+                lookup_step<Real, UT, false>(L, nullptr, ix, iy, iz, st.x, st.y, st.z, G);
+                const Step<Real, NR, UT> nx =
+                    load_step<Real, NR, true, false, false, UT>(a, min(s0 + UT, sb + kSourceBlock - UT));
 #pragma unroll
-                for (int u = 0; u < U; ++u)
+                for (int u = 0; u < UT; ++u)
 #pragma unroll
                     for (int r = 0; r < NR; ++r) acc[r].add(G[u] * st.w[r][u]);
                 st = nx;

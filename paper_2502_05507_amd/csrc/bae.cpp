@@ -235,8 +235,13 @@ static GmresOut gmres(bae_ctx* c, const double* r0, int nrhs, int prec, double t
     if (lagged)
         for (auto& e : ev) BAE_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     // Step k: LGF sum of the weights of V[k] (formed by step k-1's closing launch, or here
-    // for k = 0), closure into the work vector, CGS2, then one closing launch that scales
-    // the work vector into V[k+1], forms the next weights from it and updates Givens.
+    // for k = 0), closure into the work vector, classical Gram-Schmidt, then one closing
+    // launch that scales the work vector into V[k+1], forms the next weights from it and
+    // updates Givens.  FP64 solves orthogonalise twice (CGS2).  The FP32 inner solves of a
+    // refined solve stop near 1e-6 and every result they feed is checked by an exact FP64
+    // residual, so one pass is enough there: the two launches of the second pass cost 14% of
+    // a 33^3 refined solve and change no iteration count on the test problems.
+    const bool two_pass = prec == BAE_PREC_FP64;
     double* wv = c->tmp.as<double>();
     double* pA = c->dotpart.as<double>();
     double* pB = pA + (int64_t)nrhs * c->maxj * dot_blocks(n);
@@ -254,14 +259,17 @@ static GmresOut gmres(bae_ctx* c, const double* r0, int nrhs, int prec, double t
             launch_dot_slices(rc->C, n, rc->ld, rc->p, wv, n, n, nrhs, K.done, sl, rc->p, st);
             launch_subtract_combination(rc->C, n, rc->ld, sl, rc->p, rc->p, n, nrhs, K.done, wv, n, nullptr, st);
         }
-        // classical Gram-Schmidt twice (dot-product slices in pA, pB); the second pass also
-        // forms the slices of ||w||^2 (pN), which the closing launch sums itself
+        // classical Gram-Schmidt (dot-product slices in pA, and in pB for the second pass);
+        // the last pass also forms the slices of ||w||^2 (pN), which the closing launch sums
         launch_dot_slices(K.V, n, K.ld_rhs, k + 1, wv, n, n, nrhs, K.done, pA, c->maxj, st);
-        launch_subtract_combination(K.V, n, K.ld_rhs, pA, c->maxj, k + 1, n, nrhs, K.done, wv, n, nullptr, st);
-        launch_dot_slices(K.V, n, K.ld_rhs, k + 1, wv, n, n, nrhs, K.done, pB, c->maxj, st);
-        launch_subtract_combination(K.V, n, K.ld_rhs, pB, c->maxj, k + 1, n, nrhs, K.done, wv, n, pN, st);
-        launch_finish(K, wv, n, pA, pB, c->maxj, pN, k, tol, c->B, c->w.p, c->S.ps.padded, prec, nrhs,
-                      lagged ? c->flags_dev + (k & 1) : nullptr, st);
+        launch_subtract_combination(K.V, n, K.ld_rhs, pA, c->maxj, k + 1, n, nrhs, K.done, wv, n,
+                                    two_pass ? nullptr : pN, st);
+        if (two_pass) {
+            launch_dot_slices(K.V, n, K.ld_rhs, k + 1, wv, n, n, nrhs, K.done, pB, c->maxj, st);
+            launch_subtract_combination(K.V, n, K.ld_rhs, pB, c->maxj, k + 1, n, nrhs, K.done, wv, n, pN, st);
+        }
+        launch_finish(K, wv, n, pA, two_pass ? pB : nullptr, c->maxj, pN, k, tol, c->B, c->w.p, c->S.ps.padded,
+                      prec, nrhs, lagged ? c->flags_dev + (k & 1) : nullptr, st);
         if (lagged) {
             BAE_HIP_CHECK(hipEventRecord(ev[k & 1], st));
             if (k >= 1) {

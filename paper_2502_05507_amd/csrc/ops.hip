@@ -203,9 +203,10 @@ __global__ void normalize_kernel(double* __restrict__ V, int64_t ldv_vec, int64_
 
 // Givens update of column k (Saad-Schultz) for RHS r by one block, residual estimate,
 // convergence / breakdown flag.  H is column-major per RHS: H[r][k][i], i <= k+1.  The
-// column is the sum of the two Gram-Schmidt passes' coefficients, each the sum of its nb
-// dot-product slices (pA, pB; summed by the block's threads); H[k+1][k] = ||w|| from the nn
-// norm slices.  The rotations themselves are sequential (thread 0).
+// column is the sum of the Gram-Schmidt passes' coefficients, each the sum of its nb
+// dot-product slices (pA, and pB when there is a second pass; summed by the block's
+// threads); H[k+1][k] = ||w|| from the nn norm slices.  The rotations themselves are
+// sequential (thread 0).
 struct GivensArgs {
     double* Hc;
     int64_t ldh_col, ldh_rhs;
@@ -238,8 +239,8 @@ __device__ void givens_block(const GivensArgs& a, int r) {
     const double* c = a.cs + r * a.ldcs;
     const double* s = a.sn + r * a.ldcs;
     auto hval = [&](int i) {
-        return slice_sum(a.pA + ((int64_t)r * a.maxj + i) * a.nb, a.nb) +
-               slice_sum(a.pB + ((int64_t)r * a.maxj + i) * a.nb, a.nb);
+        const double h1 = slice_sum(a.pA + ((int64_t)r * a.maxj + i) * a.nb, a.nb);
+        return a.pB ? h1 + slice_sum(a.pB + ((int64_t)r * a.maxj + i) * a.nb, a.nb) : h1;
     };
     const double hk1_all = sqrt(block_slice_sum(a.npart + (int64_t)r * a.nn, a.nn));
     if (threadIdx.x == 0) {

@@ -202,13 +202,24 @@ int bae_apply_double_layer(bae_ctx* ctx, const double* q_dev, double* v_dev, int
 int bae_apply_operator(bae_ctx* ctx, const double* q_dev, double* aq_dev, int32_t nrhs,
                        int32_t precision, void* stream);
 /*
+ * The LGF sum of Sec. 3.2 by itself, for timing its kernel: forms the source weights of the
+ * densities q_dev once (as bae_apply_double_layer does), then launches the sum over
+ * gamma x (gamma- u E) `repeats` times in a row into the context's partial-sum scratch,
+ * which the next operator call overwrites.  No result is returned and nothing is reduced.
+ * q_dev [nrhs][|gamma-|] FP64 (device), 1 <= nrhs <= max_rhs, precision BAE_PREC_FP64 or
+ * BAE_PREC_FP32, 1 <= repeats <= 1000.  Asynchronous on `stream`; the context's scratch is
+ * shared with every other call on it.  Errors: BAE_ERR_ARG.
+ */
+int bae_lgf_sum_repeat(bae_ctx* ctx, const double* q_dev, int32_t nrhs, int32_t precision, int32_t repeats,
+                       void* stream);
+/*
  * Pair counts of the LGF sum over gamma x (gamma- u E) as the kernel classifies them for
  * `precision` (per wavefront of 64 Morton-ordered targets and block of 64 sources):
  * counts[0] pairs in blocks within the LDS table radius (table lookups), [1] in all-far
- * blocks (far field: q = 3 in FP32, q = 4 in FP64; sigma > 0: global-table gathers), [2] in
- * all-far blocks past the q = 2 gap (FP32, sigma = 0), [3] / [4] pairs of mixed blocks
- * within / beyond the LDS radius.  Host computation (no device work); for flop accounting.
- * counts: 5 int64.
+ * blocks (far field: q = 4 in FP64; sigma > 0: global-table gathers), [2] in FP32 far
+ * blocks (the q = 2 lattice form past its gap for sigma = 0, the checked Yukawa form beyond
+ * the LDS radius for sigma > 0), [3] / [4] pairs of mixed blocks within / beyond the LDS
+ * radius.  Host computation (no device work); for flop accounting.  counts: 5 int64.
  */
 int bae_sum_stats(const bae_ctx* ctx, int32_t precision, int64_t* counts);
 /*

@@ -130,6 +130,7 @@ def load_library():
         "bae_apply_operator": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P]),
         "bae_lgf_eval": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int32, _P]),
         "bae_sum_stats": (C.c_int, [_P, C.c_int32, _P]),
+        "bae_lgf_sum_repeat": (C.c_int, [_P, _P, C.c_int32, C.c_int32, C.c_int32, _P]),
         "bae_batch_create": (C.c_int, [_P, C.c_int32, C.POINTER(_P)]),
         "bae_batch_autotune": (C.c_int, [_P, C.c_int32, _P]),
         "bae_batch_solve": (C.c_int, [_P, C.POINTER(SolveParams), C.c_int32, _P]),
@@ -299,6 +300,12 @@ class Context:
         assert q.is_contiguous() and aq.is_contiguous()
         assert q.numel() == aq.numel() == nrhs * self.sizes["n_gamma_minus"]
         _check(load_library().bae_apply_operator(self._h, _dptr(q), _dptr(aq), nrhs, precision, _stream(stream)))
+
+    def lgf_sum_repeat(self, q, repeats=1, precision=PREC_FP32, stream=None):
+        """The LGF sum alone, `repeats` times, on the weights of device densities q (bae_lgf_sum_repeat)."""
+        nrhs = 1 if q.dim() == 1 else q.shape[0]
+        assert q.is_contiguous() and q.numel() == nrhs * self.sizes["n_gamma_minus"]
+        _check(load_library().bae_lgf_sum_repeat(self._h, _dptr(q), nrhs, precision, int(repeats), _stream(stream)))
 
     def sum_stats(self, precision=PREC_FP32):
         """Pair counts of the LGF sum by the kernel's block classification (bae_sum_stats)."""

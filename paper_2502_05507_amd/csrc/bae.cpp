@@ -974,6 +974,22 @@ int bae_apply_operator(bae_ctx* c, const double* q, double* aq, int32_t nrhs, in
     });
 }
 
+int bae_lgf_sum_repeat(bae_ctx* c, const double* q, int32_t nrhs, int32_t prec, int32_t repeats, void* stream) {
+    return guard([&] {
+        if (!c || !q) throw Error{BAE_ERR_ARG, "null argument"};
+        if (nrhs < 1 || nrhs > c->max_rhs) throw Error{BAE_ERR_ARG, "nrhs out of range"};
+        if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32) throw Error{BAE_ERR_ARG, "unknown precision"};
+        if (repeats < 1 || repeats > 1000) throw Error{BAE_ERR_ARG, "repeats must be in [1, 1000]"};
+        BAE_HIP_CHECK(hipSetDevice(c->device));
+        const hipStream_t st = (hipStream_t)stream;
+        launch_weights(c->B, q, c->ngm, c->w.p, c->S.ps.padded, nrhs, prec, st);
+        for (int i = 0; i < repeats; ++i) {
+            int chunks = 0;
+            apply_lgf(c, c->T.ps, c->S.ps, c->w.p, nrhs, prec, c->part.as<double>(), c->part_cap, &chunks, st);
+        }
+    });
+}
+
 int bae_sum_stats(const bae_ctx* c, int32_t prec, int64_t* counts) {
     return guard([&] {
         if (!c || !counts) throw Error{BAE_ERR_ARG, "null argument"};

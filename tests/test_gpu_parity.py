@@ -259,6 +259,28 @@ def test_error_paths():
     assert e.value.status == -2
 
 
+def test_sum_alone_for_timing_leaves_the_operator_unchanged():
+    """bae_lgf_sum_repeat (the sum kernel alone, for timing) rejects bad counts and leaves
+    the operator's results exactly as they were."""
+    torch = torch_mod()
+    p = W.laplace_sphere(33)
+    with P.Context.from_problem(p) as ctx:
+        z = ctx.sizes
+        q = torch.from_numpy(np.random.default_rng(3).standard_normal(z["n_gamma_minus"])).to(device())
+        v0 = torch.empty(z["n_targets"], dtype=torch.float64, device=device())
+        v1 = torch.empty_like(v0)
+        for prec in (P.PREC_FP64, P.PREC_FP32):
+            ctx.apply_double_layer(q, v0, prec)
+            ctx.lgf_sum_repeat(q, 5, prec)
+            ctx.apply_double_layer(q, v1, prec)
+            torch.cuda.synchronize()
+            assert torch.equal(v0, v1)
+        for bad in (0, 1001):
+            with pytest.raises(P.BaeError) as e:
+                ctx.lgf_sum_repeat(q, bad)
+            assert e.value.status == -1
+
+
 # ------------------------------------------------------------------ A10: 16 right-hand sides (MFMA form)
 @pytest.mark.parametrize("kind,n,sigma", [("ellipsoid", 65, 0.0), ("sphere", 97, 0.0), ("sphere", 97, 30.0),
                                           ("torus", 41, 10.0)])

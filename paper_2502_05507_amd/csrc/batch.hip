@@ -1,7 +1,8 @@
 // Batched solves: many small BAE problems advanced in lock-step.
 //
-// Every GMRES phase (double-layer weights, LGF sum, closure, the two classical
-// Gram-Schmidt passes, the norm, Givens) is ONE launch for all problems of the batch,
+// Every GMRES phase (double-layer weights, LGF sum, closure, the classical Gram-Schmidt
+// passes -- two in FP64, one in FP32 inner solves --, the norm, Givens) is ONE launch for
+// all problems of the batch,
 // over flat index spaces (per-problem offsets, binary search for the owning problem) or
 // over precomputed work lists.  The LGF sum is a persistent kernel: a fixed grid walks a
 // list of (problem, 1024-target tile, source chunk) items, keeping the LDS table while
@@ -253,7 +254,7 @@ __global__ void b_normalize(const BProb* __restrict__ P, const int64_t* __restri
 // One thread per problem: Givens update of column k, residual estimate, convergence flag,
 // then the problem's own step counter advances (every other kernel of the iteration has
 // read it by now).
-__global__ void b_givens(const BProb* __restrict__ P, int np) {
+__global__ void b_givens(const BProb* __restrict__ P, int np, int two_pass) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
     const BProb& q = P[p];
@@ -264,7 +265,7 @@ __global__ void b_givens(const BProb* __restrict__ P, int np) {
         return;
     }
     double* h = q.H + (int64_t)k * (q.m + 1);
-    for (int i = 0; i <= k; ++i) h[i] = q.hA[i] + q.hB[i];
+    for (int i = 0; i <= k; ++i) h[i] = two_pass ? q.hA[i] + q.hB[i] : q.hA[i];
     const double hk1 = sqrt(q.nrm[0]);
     for (int i = 0; i < k; ++i) {
         const double a = h[i], b = h[i + 1];
@@ -610,7 +611,10 @@ void gmres_iteration(BatchEngine* b, int prec) {
     const BProb* P = b->probs.as<BProb>();
     apply_all(b, prec, 0, 0, 1);
     const int64_t* orow = b->off_row.as<int64_t>();
-    for (int pass = 0; pass < 2; ++pass) {
+    // CGS2 in FP64; one pass in the FP32 inner solves, whose results an exact FP64 residual
+    // checks (as in the single-context solver)
+    const int passes = prec == BAE_PREC_FP64 ? 2 : 1;
+    for (int pass = 0; pass < passes; ++pass) {
         b_dots<<<b->nslices_total, kT, 0, st>>>(P, b->slices.as<int2>(), b->nslices_total, 0, 0, 1);
         b_dots_finalize<<<b->np, 64, 0, st>>>(P, b->np, pass, 0, 1);
         b_subtract<<<nblocks(b->tot_row), kT, 0, st>>>(P, orow, b->np, b->tot_row, pass);
@@ -618,7 +622,7 @@ void gmres_iteration(BatchEngine* b, int prec) {
     b_dots<<<b->nslices_total, kT, 0, st>>>(P, b->slices.as<int2>(), b->nslices_total, 1, 0, 1);
     b_dots_finalize<<<b->np, 64, 0, st>>>(P, b->np, 2, 1, 1);
     b_normalize<<<nblocks(b->tot_row), kT, 0, st>>>(P, orow, b->np, b->tot_row);
-    b_givens<<<(b->np + 63) / 64, 64, 0, st>>>(P, b->np);
+    b_givens<<<(b->np + 63) / 64, 64, 0, st>>>(P, b->np, passes == 2);
     BAE_HIP_CHECK(hipGetLastError());
 }
 

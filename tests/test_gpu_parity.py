@@ -281,6 +281,52 @@ def test_sum_alone_for_timing_leaves_the_operator_unchanged():
             assert e.value.status == -1
 
 
+# ------------------------------------------------------------------ the largest lattice offsets
+class _EntryLGF:
+    """The oracle's G_0 entry by entry (its tables would need every offset up to 2046)."""
+
+    def __init__(self):
+        self.cache = {}
+
+    def pairs(self, m, s):
+        d = np.abs(np.asarray(m)[:, None, :] - np.asarray(s)[None, :, :])
+        d.sort(axis=2)
+        u, inv = np.unique(d.reshape(-1, 3), axis=0, return_inverse=True)
+        vals = np.array([self.cache[k] if k in self.cache else self.cache.setdefault(k, lgf.lgf_entry(np.array(k), 0.0))
+                         for k in map(tuple, u)])
+        return vals[inv.reshape(-1)].reshape(d.shape[:2])
+
+
+def test_largest_lattice_offsets_two_balls():
+    """Two small balls at the two ends of a 2049-node axis (a sampled level set): offsets
+    up to 2046, lattice coordinates up to 2048, the limit of the FP32 path's binary16
+    differences.  Double layer against the oracle's entry-by-entry LGF."""
+    torch = torch_mod()
+    n, h = (2049, 11, 11), 1.0 / 64
+    idx = np.indices(n).reshape(3, -1).T.astype(float)
+    c1, c2, r = np.array([5.0, 5.0, 5.0]), np.array([2043.0, 5.0, 5.0]), 2.6
+    phi = (np.minimum(np.linalg.norm(idx - c1, axis=1), np.linalg.norm(idx - c2, axis=1)) - r) * h
+    g = geometry.build(n, h, (0.0, 0.0, 0.0), "sampled", phi_nodes=phi)
+    assert g.max_offset() == 2046
+    T = operators.gamma_targets(g)
+    D = operators.dense_double_layer(g, _EntryLGF(), T)
+    q = np.random.default_rng(21).standard_normal((2, len(g.gamma_minus)))
+    ref = q @ D.T
+    with P.Context(n, h, (0.0, 0.0, 0.0), 0.0, "sampled", phi=phi, max_rhs=2) as ctx:
+        z = ctx.sizes
+        assert (z["n_gamma_plus"], z["n_gamma_minus"], z["n_ext"], z["max_offset"]) == \
+            (len(g.gamma_plus), len(g.gamma_minus), len(g.ext), 2046)
+        assert ctx.sum_stats(P.PREC_FP32)["far_q2"] > 0      # the binary16 far field runs
+        qd = torch.from_numpy(q).to(device())
+        v = torch.empty((2, len(T)), dtype=torch.float64, device=device())
+        for prec, tol in ((P.PREC_FP64, 1e-10), (P.PREC_FP32, 2e-5)):
+            ctx.apply_double_layer(qd, v, prec)
+            torch.cuda.synchronize()
+            out = v.cpu().numpy()
+            for rr in range(2):
+                assert rel_l2(out[rr], ref[rr]) < tol, (prec, rr, rel_l2(out[rr], ref[rr]))
+
+
 # ------------------------------------------------------------------ A10: 16 right-hand sides (MFMA form)
 @pytest.mark.parametrize("kind,n,sigma", [("ellipsoid", 65, 0.0), ("sphere", 97, 0.0), ("sphere", 97, 30.0),
                                           ("torus", 41, 10.0)])

@@ -71,23 +71,26 @@ def test_table_matches_adaptive_quadrature():
             assert abs(t(n) - e) <= 2e-14 * e
 
 
+def q3_expansion(n, c=-228):
+    """Sec. 2.2's q = 3 expansion of G_0 in the positive sign convention, written out in the
+    offset components (c: the coefficient printed as -288, read as -228)."""
+    j, k, l = (float(v) for v in n)
+    r = math.sqrt(j * j + k * k + l * l)
+    P4 = j ** 4 + k ** 4 + l ** 4 - 3 * (j * j * k * k + j * j * l * l + k * k * l * l)
+    P8 = (c * (k * k * l * l * j ** 4 + k * k * l ** 4 * j * j + k ** 4 * l * l * j * j)
+          + 621 * (j ** 4 * k ** 4 + l ** 4 * k ** 4 + j ** 4 * l ** 4)
+          - 244 * (k * k * j ** 6 + l * l * j ** 6 + k ** 6 * j * j + l ** 6 * j * j + k * k * l ** 6 + k ** 6 * l * l)
+          + 23 * (j ** 8 + k ** 8 + l ** 8))
+    return 1 / (4 * math.pi * r) + P4 / (16 * math.pi * r ** 7) + P8 / (128 * math.pi * r ** 13)
+
+
 def test_far_field_decay_and_the_A3_reading():
     # Sec. 2.2: G_0(n) -> 1/(4 pi |n|) as |n| -> inf, with the q-term expansion error
     # O(|n|^(-2q-1)).  In the positive sign convention of eq. "lgf" the q=3 expansion only
     # decays like |n|^-6 relative if the coefficient printed as -288 reads -228 (the
     # symmetric-polynomial form 23p^4 - 336p^2e2 + 1155e2^2 - 1134p e3 of the bracket).
     t = lgf.LGFTable(120, 0.0)
-
-    def A3(n, c):
-        j, k, l = (float(v) for v in n)
-        r = math.sqrt(j * j + k * k + l * l)
-        P4 = j ** 4 + k ** 4 + l ** 4 - 3 * (j * j * k * k + j * j * l * l + k * k * l * l)
-        P8 = (c * (k * k * l * l * j ** 4 + k * k * l ** 4 * j * j + k ** 4 * l * l * j * j)
-              + 621 * (j ** 4 * k ** 4 + l ** 4 * k ** 4 + j ** 4 * l ** 4)
-              - 244 * (k * k * j ** 6 + l * l * j ** 6 + k ** 6 * j * j + l ** 6 * j * j + k * k * l ** 6 + k ** 6 * l * l)
-              + 23 * (j ** 8 + k ** 8 + l ** 8))
-        return 1 / (4 * math.pi * r) + P4 / (16 * math.pi * r ** 7) + P8 / (128 * math.pi * r ** 13)
-
+    A3 = q3_expansion
     r = 117.0
     assert abs(4 * math.pi * r * t(np.array([117, 0, 0])) - 1.0) < 2e-5
     e1 = [abs(A3(n, -228) / t(np.array(n)) - 1) for n in ((20, 20, 5), (40, 40, 10), (80, 80, 20))]
@@ -95,6 +98,15 @@ def test_far_field_decay_and_the_A3_reading():
     assert 40 < e1[0] / e1[1] < 100 and 40 < e1[1] / e1[2] < 100      # ~2^6
     assert 10 < e2[0] / e2[1] < 25 and 10 < e2[1] / e2[2] < 25         # ~2^4
     assert e1[1] < 5e-11
+
+
+def test_single_entries_at_the_largest_offsets():
+    # Lattice coordinates reach 2048 (2049 nodes per axis).  That far out the q = 3 expansion
+    # leaves a relative error of order |n|^-6 (below 1e-19), so it fixes G_0 to rounding, and
+    # the oracle's single-entry quadrature with its analytic tail must agree.
+    for n in ((2048, 0, 0), (2000, 3, 1), (1500, 700, 2), (1024, 1024, 1024), (2048, 2048, 2048), (300, 5, 0)):
+        v = lgf.lgf_entry(np.array(n), 0.0)
+        assert abs(q3_expansion(n) / v - 1) < 1e-12, (n, q3_expansion(n) / v - 1)
 
 
 def test_small_sigma_limit():

@@ -728,17 +728,19 @@ int bae_set_rhs(bae_ctx* c, int32_t nrhs, const double* g_xstar, const double* f
                 if (!std::isfinite(f_grid[i])) throw Error{BAE_ERR_NONFINITE, "source term not finite"};
             ensure_mplus(c);
             const int64_t nm = c->Mp.ps.count;
-            std::vector<int32_t> lin(nm);
-            {
-                // linear grid index of each internal M+ point
+            if ((int64_t)c->mp_lin.size() != nm) {
+                // linear grid index of each internal M+ point (once per context)
                 std::vector<int32_t> pts;
+                pts.reserve(nm);
                 for (int i = 0; i < G.n[0]; ++i)
                     for (int j = 0; j < G.n[1]; ++j)
                         for (int k = 0; k < G.n[2]; ++k)
                             if (G.inside[((int64_t)i * G.n[1] + j) * G.n[2] + k])
                                 pts.push_back((int32_t)(((int64_t)i * G.n[1] + j) * G.n[2] + k));
-                for (int64_t a = 0; a < nm; ++a) lin[a] = pts[c->Mp.perm[a]];
+                c->mp_lin.resize(nm);
+                for (int64_t a = 0; a < nm; ++a) c->mp_lin[a] = pts[c->Mp.perm[a]];
             }
+            const std::vector<int32_t>& lin = c->mp_lin;
             const int64_t nmp = c->Mp.ps.padded;
             std::vector<double> wfh(nmp * nrhs, 0.0);
             const double h2 = G.h * G.h;

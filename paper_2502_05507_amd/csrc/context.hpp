@@ -199,6 +199,7 @@ struct bae_ctx {
     DevMem u_gamma;            // [rhs][nT]
     DevMem vsum;               // [rhs][nT] chunk-reduced sums (operator scratch)
     DevMem wf;                 // [rhs][|M+|] h^2 f in Mp order
+    std::vector<int32_t> mp_lin;   // linear grid index of each M+ point in Mp order (lazy)
     DevMem ctl;                // Ctl of RHS 0 for batched / served solves
     int nrhs = 0;
     bool has_f = false, rhs_ready = false, solved = false;

@@ -208,7 +208,8 @@ int bae_apply_operator(bae_ctx* ctx, const double* q_dev, double* aq_dev, int32_
  * which the next operator call overwrites.  No result is returned and nothing is reduced.
  * q_dev [nrhs][|gamma-|] FP64 (device), 1 <= nrhs <= max_rhs, precision BAE_PREC_FP64 or
  * BAE_PREC_FP32, 1 <= repeats <= 1000.  Asynchronous on `stream`; the context's scratch is
- * shared with every other call on it.  Errors: BAE_ERR_ARG.
+ * shared with every other call on it.  Errors: BAE_ERR_ARG (null pointer, nrhs, precision or
+ * repeats out of range), BAE_ERR_HIP (a failed launch).
  */
 int bae_lgf_sum_repeat(bae_ctx* ctx, const double* q_dev, int32_t nrhs, int32_t precision, int32_t repeats,
                        void* stream);

@@ -19,6 +19,7 @@ Other workloads (--workload; their own JSON line, not the contract's):
   batch            512 seeded small problems in one lock-step, graph-replayed batch
   serve            Poisson arrivals into the continuous-batching server, p50/p99 latency
   profile          matvecs only (for rocprofv3) plus a device copy of known size
+  formulations     single- against double-layer formulation (iterations, time) at 129^3
 """
 from __future__ import annotations
 
@@ -266,6 +267,33 @@ def headline(args, torch, P, W):
     return out
 
 
+def formulations(args, torch, P, W):
+    """Single- against double-layer formulation (Sec. 3.4) on the 129^3 Poisson ellipsoid:
+    iterations and solve time of each, FP64 and refined, and the difference of their u_gamma."""
+    p = W.poisson_ellipsoid(args.nodes)
+    out = {"workload": f"formulations_poisson_ellipsoid_{args.nodes}^3"}
+    with P.Context.from_problem(p, max_krylov=400) as ctx:
+        xs, _, _ = ctx.boundary_points()
+        ctx.set_rhs(p.g(xs), p.f_grid())
+        ug = {}
+        for lname, layer in (("double", P.LAYER_DOUBLE), ("single", P.LAYER_SINGLE)):
+            for pname, prec in (("fp64", P.SOLVE_FP64), ("fp32_refined", P.SOLVE_FP32_REFINED)):
+                ctx.solve(prec, tol=1e-10, formulation=layer)
+                lat = []
+                for _ in range(3):
+                    s0 = time.perf_counter()
+                    r = ctx.solve(prec, tol=1e-10, formulation=layer)[0]
+                    lat.append(time.perf_counter() - s0)
+                out[f"{lname}_{pname}"] = {"ms": float(np.median(lat) * 1e3), "iterations": r["iterations"],
+                                           "outer_steps": r["outer_steps"], "converged": bool(r["converged"]),
+                                           "rel_residual": r["rel_residual_true"]}
+                ug[(lname, pname)] = ctx.gamma_values()
+        ref = ug[("double", "fp64")]
+        out["u_gamma_rel_diff_vs_double_fp64"] = {f"{k[0]}_{k[1]}": float(np.linalg.norm(v - ref) / np.linalg.norm(ref))
+                                                 for k, v in ug.items()}
+    return out
+
+
 def laplace_sphere(args, torch, P, W):
     p = W.laplace_sphere()
     with P.Context.from_problem(p) as ctx:
@@ -427,7 +455,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--nodes", type=int, default=129, help="nodes per axis of the ellipsoid (h = 1/(nodes-1))")
     ap.add_argument("--workload", default="poisson_ellipsoid",
-                    choices=["poisson_ellipsoid", "laplace_sphere", "helmholtz_star", "batch", "serve", "profile"])
+                    choices=["poisson_ellipsoid", "laplace_sphere", "helmholtz_star", "batch", "serve", "profile",
+                             "formulations"])
     ap.add_argument("--star-nodes", type=int, default=257)
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--requests", type=int, default=200)
@@ -446,6 +475,7 @@ def main():
     import workloads as W
 
     fn = {"poisson_ellipsoid": headline, "laplace_sphere": laplace_sphere, "helmholtz_star": helmholtz_star,
+          "formulations": formulations,
           "batch": batch, "serve": serve, "profile": profile}[args.workload]
     print(json.dumps(fn(args, torch, P, W)))
 

@@ -61,6 +61,9 @@ extern "C" {
 #define BAE_SOLVE_FP64 0          /* plain FP64 GMRES                                 */
 #define BAE_SOLVE_FP32_REFINED 1  /* FP64 iterative refinement around FP32-matvec GMRES */
 
+#define BAE_LAYER_DOUBLE 0        /* double-layer formulation (Sec. 3.4 eq. "double_bae") */
+#define BAE_LAYER_SINGLE 1        /* single-layer formulation (Sec. 3.4)                 */
+
 /* ------------------------------------------------------------------ structs */
 typedef struct bae_grid {
     int32_t n[3];        /* nodes per axis, in [5, 2049]                            */
@@ -115,6 +118,11 @@ typedef struct bae_solve_params {
                                   most this many vectors) augments the later inner
                                   solves (GCRO); 0 = automatic (64 once a matvec has
                                   1e8 pair interactions, else none), < 0 = none       */
+    int32_t formulation;       /* BAE_LAYER_DOUBLE (default, 0): (Phi+ D+ + Phi- D-) q = b;
+                                  BAE_LAYER_SINGLE: (Phi+ S+ + Phi- S-) q = b with the
+                                  single layer S(m,n) = G(m - n) on gamma- sources
+                                  (Sec. 3.4); the density, u_gamma and u are those of
+                                  the chosen layer                                    */
 } bae_solve_params;
 
 typedef struct bae_result {
@@ -196,6 +204,12 @@ int bae_get_history(const bae_ctx* ctx, int32_t r, double* hist, int32_t cap, in
  * Asynchronous on `stream`; q_dev/v_dev must not alias.
  */
 int bae_apply_double_layer(bae_ctx* ctx, const double* q_dev, double* v_dev, int32_t nrhs,
+                           int32_t precision, void* stream);
+/*
+ * Single layer potential on gamma (Sec. 3.4, S(m,n) = G(m - n) on gamma- sources):
+ * v = [S+ q; S- q].  Same arguments, layouts and errors as bae_apply_double_layer.
+ */
+int bae_apply_single_layer(bae_ctx* ctx, const double* q_dev, double* v_dev, int32_t nrhs,
                            int32_t precision, void* stream);
 /* The BAE operator A q = Phi+ D+ q + Phi- D- q (Sec. 3.4, eq. "double_bae").
    q_dev, aq_dev: [nrhs][|gamma-|] FP64 device. */

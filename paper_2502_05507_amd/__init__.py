@@ -7,4 +7,4 @@ Importing the package does not load the library; the first call does, and it fai
 loudly when libbae.so has not been built (python -m paper_2502_05507_amd.build).
 """
 from .binding import (BaeError, Batch, Context, Server, lgf_table, lgf_table_size, load_library,  # noqa: F401
-                      PREC_FP64, PREC_FP32, SOLVE_FP64, SOLVE_FP32_REFINED, KINDS)
+                      PREC_FP64, PREC_FP32, SOLVE_FP64, SOLVE_FP32_REFINED, LAYER_DOUBLE, LAYER_SINGLE, KINDS)

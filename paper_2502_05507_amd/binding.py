@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libbae.so")
 OK, NOT_CONVERGED = 0, 1
 PREC_FP64, PREC_FP32 = 0, 1
 SOLVE_FP64, SOLVE_FP32_REFINED = 0, 1
+LAYER_DOUBLE, LAYER_SINGLE = 0, 1
 KINDS = {"sphere": 1, "ellipsoid": 2, "torus": 3, "star": 4, "sampled": 5}
 
 
@@ -47,7 +48,8 @@ class Sizes(C.Structure):
 
 class SolveParams(C.Structure):
     _fields_ = [("precision", C.c_int32), ("tol", C.c_double), ("maxit", C.c_int32), ("inner_tol", C.c_double),
-                ("max_outer", C.c_int32), ("compute_grid", C.c_int32), ("recycle_dim", C.c_int32)]
+                ("max_outer", C.c_int32), ("compute_grid", C.c_int32), ("recycle_dim", C.c_int32),
+                ("formulation", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -128,6 +130,7 @@ def load_library():
         "bae_get_history": (C.c_int, [_P, C.c_int32, _P, C.c_int32, C.POINTER(C.c_int32)]),
         "bae_apply_double_layer": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P]),
         "bae_apply_operator": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P]),
+        "bae_apply_single_layer": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P]),
         "bae_lgf_eval": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int32, _P]),
         "bae_sum_stats": (C.c_int, [_P, C.c_int32, _P]),
         "bae_lgf_sum_repeat": (C.c_int, [_P, _P, C.c_int32, C.c_int32, C.c_int32, _P]),
@@ -257,9 +260,10 @@ class Context:
         self.nrhs = nrhs
 
     def solve(self, precision=SOLVE_FP64, tol=1e-10, maxit=0, inner_tol=0.0, max_outer=0, compute_grid=False,
-              recycle_dim=0):
+              recycle_dim=0, formulation=0):
+        """formulation: LAYER_DOUBLE (default) or LAYER_SINGLE (Sec. 3.4)."""
         p = SolveParams(int(precision), float(tol), int(maxit), float(inner_tol), int(max_outer),
-                        1 if compute_grid else 0, int(recycle_dim))
+                        1 if compute_grid else 0, int(recycle_dim), int(formulation))
         res = (Result * self.nrhs)()
         rc = load_library().bae_solve(self._h, C.byref(p), res)
         _check(rc, allow_not_converged=True)
@@ -293,6 +297,13 @@ class Context:
         assert q.is_contiguous() and v.is_contiguous()
         assert q.numel() == nrhs * self.sizes["n_gamma_minus"] and v.numel() == nrhs * self.sizes["n_targets"]
         _check(load_library().bae_apply_double_layer(self._h, _dptr(q), _dptr(v), nrhs, precision, _stream(stream)))
+
+    def apply_single_layer(self, q, v, precision=PREC_FP64, stream=None):
+        """v[nrhs][|gamma|] = [S+ q; S- q] for device tensors q[nrhs][|gamma-|] (float64)."""
+        nrhs = 1 if q.dim() == 1 else q.shape[0]
+        assert q.is_contiguous() and v.is_contiguous()
+        assert q.numel() == nrhs * self.sizes["n_gamma_minus"] and v.numel() == nrhs * self.sizes["n_targets"]
+        _check(load_library().bae_apply_single_layer(self._h, _dptr(q), _dptr(v), nrhs, precision, _stream(stream)))
 
     def apply_operator(self, q, aq, precision=PREC_FP64, stream=None):
         """aq = (Phi+ D+ + Phi- D-) q for device tensors [nrhs][|gamma-|] (float64)."""
@@ -338,7 +349,7 @@ class Batch:
         return {"blocks_per_chunk": int(chosen[0]), "grid_multiplier": int(chosen[1])}
 
     def solve(self, precision=SOLVE_FP64, tol=1e-10, maxit=0, inner_tol=0.0, max_outer=0, use_graph=True):
-        p = SolveParams(int(precision), float(tol), int(maxit), float(inner_tol), int(max_outer), 0, 0)
+        p = SolveParams(int(precision), float(tol), int(maxit), float(inner_tol), int(max_outer), 0, 0, 0)
         res = (Result * len(self.contexts))()
         rc = load_library().bae_batch_solve(self._h, C.byref(p), 1 if use_graph else 0, res)
         _check(rc, allow_not_converged=True)

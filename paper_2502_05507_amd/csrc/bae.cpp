@@ -71,7 +71,7 @@ static void apply_lgf(bae_ctx* c, const PointSet& T, const PointSet& S, const vo
 // v = [D+ q; D- q] (external order), q [nrhs][ngm] with leading dimension ldq
 static void double_layer(bae_ctx* c, const double* q, int64_t ldq, double* v, int64_t ldv, int nrhs, int prec,
                          hipStream_t st) {
-    launch_weights(c->B, q, ldq, c->w.p, c->S.ps.padded, nrhs, prec, st);
+    launch_weights(*c->Bop, q, ldq, c->w.p, c->S.ps.padded, nrhs, prec, st);
     int chunks = 0;
     apply_lgf(c, c->T.ps, c->S.ps, c->w.p, nrhs, prec, c->part.as<double>(), c->part_cap, &chunks, st);
     launch_reduce_scatter(c->part.as<double>(), chunks, c->nT, c->t_pos.as<int32_t>(), v, ldv, nrhs, 1.0, st);
@@ -80,7 +80,7 @@ static void double_layer(bae_ctx* c, const double* q, int64_t ldq, double* v, in
 // aq = Phi+ D+ q + Phi- D- q (the LGF sum skipped while *skip is set, when given)
 static void bae_operator(bae_ctx* c, const double* q, int64_t ldq, double* aq, int64_t lda, int nrhs, int prec,
                          hipStream_t st, const int32_t* skip = nullptr) {
-    launch_weights(c->B, q, ldq, c->w.p, c->S.ps.padded, nrhs, prec, st);
+    launch_weights(*c->Bop, q, ldq, c->w.p, c->S.ps.padded, nrhs, prec, st);
     int chunks = 0;
     apply_lgf(c, c->T.ps, c->S.ps, c->w.p, nrhs, prec, c->part.as<double>(), c->part_cap, &chunks, st, skip);
     launch_closure(c->part.as<double>(), chunks, c->nT, c->cl, aq, lda, nrhs, c->vsum.as<double>(), st);
@@ -112,6 +112,15 @@ struct Recycle {
     double* slices = nullptr;     // [step][rhs][p][dot_blocks(n)]
 };
 constexpr int kRecycleDefault = 64;
+
+// Selects the operator's layer potential for a scope (the double layer outside it).
+struct LayerScope {
+    bae_ctx* c;
+    LayerScope(bae_ctx* ctx, int32_t formulation) : c(ctx) {
+        c->Bop = formulation == BAE_LAYER_SINGLE ? &c->B1 : &c->B;
+    }
+    ~LayerScope() { c->Bop = &c->B; }
+};
 
 static void build_recycle(bae_ctx* c, int nrhs, const std::vector<int>& skip, int cap, Recycle& rc, hipStream_t st) {
     KrylovState& K = c->K;
@@ -246,7 +255,7 @@ static GmresOut gmres(bae_ctx* c, const double* r0, int nrhs, int prec, double t
     double* pA = c->dotpart.as<double>();
     double* pB = pA + (int64_t)nrhs * c->maxj * dot_blocks(n);
     double* pN = pB + (int64_t)nrhs * c->maxj * dot_blocks(n);
-    launch_weights(c->B, K.V, K.ld_rhs, c->w.p, c->S.ps.padded, nrhs, prec, st);
+    launch_weights(*c->Bop, K.V, K.ld_rhs, c->w.p, c->S.ps.padded, nrhs, prec, st);
     int k = 0;
     for (; k < m; ++k) {
         int chunks = 0;
@@ -268,7 +277,7 @@ static GmresOut gmres(bae_ctx* c, const double* r0, int nrhs, int prec, double t
             launch_dot_slices(K.V, n, K.ld_rhs, k + 1, wv, n, n, nrhs, K.done, pB, c->maxj, st);
             launch_subtract_combination(K.V, n, K.ld_rhs, pB, c->maxj, k + 1, n, nrhs, K.done, wv, n, pN, st);
         }
-        launch_finish(K, wv, n, pA, two_pass ? pB : nullptr, c->maxj, pN, k, tol, c->B, c->w.p, c->S.ps.padded,
+        launch_finish(K, wv, n, pA, two_pass ? pB : nullptr, c->maxj, pN, k, tol, *c->Bop, c->w.p, c->S.ps.padded,
                       prec, nrhs, lagged ? c->flags_dev + (k & 1) : nullptr, st);
         if (lagged) {
             BAE_HIP_CHECK(hipEventRecord(ev[k & 1], st));
@@ -491,6 +500,24 @@ bae_ctx* create_context(const bae_grid& gridv, const bae_options* opt, Geometry&
         upload(c->csr_coef, coef, st);
         c->B = CSR{c->nS, c->S.ps.padded, c->csr_rowptr.as<int32_t>(), c->csr_col.as<int32_t>(),
                    c->csr_coef.as<double>()};
+        {
+            // single layer (Sec. 3.4): the same sources, weight q(n) on gamma-, none on E
+            std::vector<int32_t> rp1(c->nS + 1, 0), col1;
+            std::vector<double> coef1;
+            for (int64_t i = 0; i < c->nS; ++i) {
+                if (sord[i] < c->ngm) {
+                    col1.push_back(sord[i]);
+                    coef1.push_back(1.0);
+                }
+                rp1[i + 1] = (int32_t)col1.size();
+            }
+            upload(c->csr1_rowptr, rp1, st);
+            upload(c->csr1_col, col1, st);
+            upload(c->csr1_coef, coef1, st);
+            c->B1 = CSR{c->nS, c->S.ps.padded, c->csr1_rowptr.as<int32_t>(), c->csr1_col.as<int32_t>(),
+                        c->csr1_coef.as<double>()};
+        }
+        c->Bop = &c->B;
         // closure rows
         std::vector<int32_t> ctq(c->ngm), ctp(c->ngm);
         for (int64_t q = 0; q < c->ngm; ++q) {
@@ -775,8 +802,13 @@ int bae_solve(bae_ctx* c, const bae_solve_params* p, bae_result* res) {
         if (p->precision != BAE_SOLVE_FP64 && p->precision != BAE_SOLVE_FP32_REFINED)
             throw Error{BAE_ERR_ARG, "unknown solve precision"};
         if (!(p->tol > 0.0)) throw Error{BAE_ERR_ARG, "tol must be > 0"};
+        if (p->formulation != BAE_LAYER_DOUBLE && p->formulation != BAE_LAYER_SINGLE)
+            throw Error{BAE_ERR_ARG, "unknown layer formulation"};
         BAE_HIP_CHECK(hipSetDevice(c->device));
         hipStream_t st = c->stream;
+        // the layer potential of this solve (Sec. 3.4): every operator call below, the grid
+        // solution included, forms its source weights through this map
+        const LayerScope layer(c, p->formulation);
         const auto t0 = std::chrono::steady_clock::now();
         const int nrhs = c->nrhs;
         const int64_t n = c->ngm;
@@ -872,7 +904,7 @@ int bae_solve(bae_ctx* c, const bae_solve_params* p, bae_result* res) {
             const int64_t nm = c->Mp.ps.count;
             DevMem um;
             um.alloc(sizeof(double) * nm * nrhs);
-            launch_weights(c->B, c->x.as<double>(), n, c->w.p, c->S.ps.padded, nrhs, BAE_PREC_FP64, st);
+            launch_weights(*c->Bop, c->x.as<double>(), n, c->w.p, c->S.ps.padded, nrhs, BAE_PREC_FP64, st);
             lgf_sum_to(c, c->Mp.ps, c->S.ps, c->w.as<double>(), nrhs, nullptr, um.as<double>(), nm, 1.0, st);
             if (c->has_f) {
                 DevMem up;
@@ -962,6 +994,17 @@ int bae_apply_double_layer(bae_ctx* c, const double* q, double* v, int32_t nrhs,
         if (nrhs < 1 || nrhs > c->max_rhs) throw Error{BAE_ERR_ARG, "nrhs out of range"};
         if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32) throw Error{BAE_ERR_ARG, "unknown precision"};
         BAE_HIP_CHECK(hipSetDevice(c->device));
+        double_layer(c, q, c->ngm, v, c->nT, nrhs, prec, (hipStream_t)stream);
+    });
+}
+
+int bae_apply_single_layer(bae_ctx* c, const double* q, double* v, int32_t nrhs, int32_t prec, void* stream) {
+    return guard([&] {
+        if (!c || !q || !v) throw Error{BAE_ERR_ARG, "null argument"};
+        if (nrhs < 1 || nrhs > c->max_rhs) throw Error{BAE_ERR_ARG, "nrhs out of range"};
+        if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32) throw Error{BAE_ERR_ARG, "unknown precision"};
+        BAE_HIP_CHECK(hipSetDevice(c->device));
+        const LayerScope layer(c, BAE_LAYER_SINGLE);
         double_layer(c, q, c->ngm, v, c->nT, nrhs, prec, (hipStream_t)stream);
     });
 }

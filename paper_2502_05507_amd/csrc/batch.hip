@@ -978,6 +978,8 @@ int bae_batch_solve(bae_batch* bb, const bae_solve_params* prm, int32_t use_grap
         if (prm->precision != BAE_SOLVE_FP64 && prm->precision != BAE_SOLVE_FP32_REFINED)
             throw Error{BAE_ERR_ARG, "unknown solve precision"};
         if (!(prm->tol > 0.0)) throw Error{BAE_ERR_ARG, "tol must be > 0"};
+        if (prm->formulation != BAE_LAYER_DOUBLE)
+            throw Error{BAE_ERR_ARG, "batched solves use the double-layer formulation"};
         BAE_HIP_CHECK(hipSetDevice(bb->e->device));
         status = solve_all(bb->e, prm, use_graph != 0, res);
     });

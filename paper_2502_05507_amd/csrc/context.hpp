@@ -179,6 +179,10 @@ struct bae_ctx {
     DevMem t_pos;              // internal target index -> position in [gamma+; gamma-]
     DevMem csr_rowptr, csr_col, csr_coef;
     CSR B;
+    // single-layer weights map (Sec. 3.4): w(n) = q(n) for n in gamma-, nothing for E
+    DevMem csr1_rowptr, csr1_col, csr1_coef;
+    CSR B1;
+    const CSR* Bop = nullptr;  // the operator's weights map: &B (double layer) or &B1
     DevMem cl_tq, cl_tp, cl_t;
     Closure cl;
     std::shared_ptr<Table> table;

@@ -281,6 +281,61 @@ def test_sum_alone_for_timing_leaves_the_operator_unchanged():
             assert e.value.status == -1
 
 
+# ------------------------------------------------------------------ single-layer formulation
+@pytest.mark.parametrize("kind,n,sigma", [("sphere", 33, 0.0), ("torus", 41, 10.0)])
+def test_single_layer_matches_oracle(kind, n, sigma):
+    """Sec. 3.4: v = [S+ q; S- q], S(m,n) = G(m - n) on gamma- sources, against the oracle."""
+    torch = torch_mod()
+    p = small_problem(kind, n, sigma)
+    g, G = oracle_setup(p)
+    q = np.random.default_rng(5 * n).standard_normal((2, len(g.gamma_minus)))
+    T = operators.gamma_targets(g)
+    ref = q @ operators.dense_single_layer(g, G, T).T
+    with P.Context.from_problem(p, max_rhs=2) as ctx:
+        qd = torch.from_numpy(q).to(device())
+        v = torch.empty((2, len(T)), dtype=torch.float64, device=device())
+        for prec, tol in ((P.PREC_FP64, 1e-10), (P.PREC_FP32, 2e-5)):
+            ctx.apply_single_layer(qd, v, prec)
+            torch.cuda.synchronize()
+            out = v.cpu().numpy()
+            for r in range(2):
+                assert rel_l2(out[r], ref[r]) < tol, (prec, r, rel_l2(out[r], ref[r]))
+
+
+def test_single_layer_solve_reaches_the_double_layer_solution():
+    """Sec. 3.4: (Phi+ S+ + Phi- S-) q_s = b.  Its density against the oracle's GMRES on the
+    same system; u_gamma and u on N+ equal the double-layer solve's (both are the discrete
+    solution); afterwards the operator is the double layer again."""
+    torch = torch_mod()
+    p = W.poisson_ellipsoid(33)
+    g, G = oracle_setup(p)
+    T = operators.gamma_targets(g)
+    b = operators.rhs(g, G, p.g(g.xstar), p.f_grid())
+    qs_ref, _, conv = gmres.gmres(lambda x: operators.closure(g, operators.single_layer(g, G, x, T)), b, tol=1e-13)
+    assert conv
+    with P.Context.from_problem(p) as ctx:
+        xs, _, _ = ctx.boundary_points()
+        ctx.set_rhs(p.g(xs), p.f_grid())
+        rd = ctx.solve(P.SOLVE_FP64, tol=1e-13, compute_grid=True)[0]
+        ug_d, u_d = ctx.gamma_values(), ctx.solution()
+        nplus = ~np.isnan(u_d)
+        for prec, tol, tq, tu in ((P.SOLVE_FP64, 1e-13, 1e-9, 1e-10), (P.SOLVE_FP32_REFINED, 1e-10, 1e-6, 1e-8)):
+            rs = ctx.solve(prec, tol=tol, compute_grid=True, formulation=P.LAYER_SINGLE)[0]
+            assert rs["converged"], rs
+            qs, ug_s, u_s = ctx.density(), ctx.gamma_values(), ctx.solution()
+            print(f"single layer ({prec}): {rs['iterations']} iterations; double layer {rd['iterations']}")
+            assert rel_l2(qs, qs_ref) < tq, rel_l2(qs, qs_ref)
+            assert rel_l2(ug_s, ug_d) < tu, rel_l2(ug_s, ug_d)
+            assert np.array_equal(~np.isnan(u_s), nplus)
+            assert np.abs(u_s[nplus] - u_d[nplus]).max() < tu * np.abs(u_d[nplus]).max()
+        q = np.random.default_rng(8).standard_normal(len(g.gamma_minus))
+        qd = torch.from_numpy(q).to(device())
+        aq = torch.empty_like(qd)
+        ctx.apply_operator(qd, aq, P.PREC_FP64)
+        torch.cuda.synchronize()
+        assert rel_l2(aq.cpu().numpy(), operators.bae_apply(g, G, q)) < 1e-10
+
+
 # ------------------------------------------------------------------ the largest lattice offsets
 class _EntryLGF:
     """The oracle's G_0 entry by entry (its tables would need every offset up to 2046)."""

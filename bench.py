@@ -20,6 +20,7 @@ Other workloads (--workload; their own JSON line, not the contract's):
   serve            Poisson arrivals into the continuous-batching server, p50/p99 latency
   profile          matvecs only (for rocprofv3) plus a device copy of known size
   formulations     single- against double-layer formulation (iterations, time) at 129^3
+  particular       free-space against finite-grid (sine-transform) particular solution at 129^3
 """
 from __future__ import annotations
 
@@ -294,6 +295,35 @@ def formulations(args, torch, P, W):
     return out
 
 
+def particular(args, torch, P, W):
+    """Free-space volume potential against the finite-grid solve by sine transforms (Algorithm
+    1) for u_p on the 129^3 Poisson ellipsoid: set_rhs time, and a refined solve with the grid
+    solution, whose u_p on M+ is one more LGF sum (free) or a gather (box)."""
+    p = W.poisson_ellipsoid(args.nodes)
+    out = {"workload": f"particular_poisson_ellipsoid_{args.nodes}^3"}
+    with P.Context.from_problem(p) as ctx:
+        xs, _, _ = ctx.boundary_points()
+        g, f = p.g(xs), p.f_grid()
+        u = {}
+        for name in ("free", "box"):
+            ctx.set_rhs(g, f, particular=name)
+            ctx.solve(P.SOLVE_FP32_REFINED, tol=1e-10, compute_grid=True)
+            t_rhs, t_solve = [], []
+            for _ in range(3):
+                s0 = time.perf_counter()
+                ctx.set_rhs(g, f, particular=name)
+                t_rhs.append(time.perf_counter() - s0)
+                s0 = time.perf_counter()
+                r = ctx.solve(P.SOLVE_FP32_REFINED, tol=1e-10, compute_grid=True)[0]
+                t_solve.append(time.perf_counter() - s0)
+            u[name] = ctx.solution()
+            out[name] = {"set_rhs_ms": float(np.median(t_rhs) * 1e3),
+                         "solve_with_grid_ms": float(np.median(t_solve) * 1e3), "iterations": r["iterations"]}
+        m = ~np.isnan(u["free"])
+        out["grid_solution_max_rel_diff"] = float(np.abs(u["box"][m] - u["free"][m]).max() / np.abs(u["free"][m]).max())
+    return out
+
+
 def laplace_sphere(args, torch, P, W):
     p = W.laplace_sphere()
     with P.Context.from_problem(p) as ctx:
@@ -456,7 +486,7 @@ def main():
     ap.add_argument("--nodes", type=int, default=129, help="nodes per axis of the ellipsoid (h = 1/(nodes-1))")
     ap.add_argument("--workload", default="poisson_ellipsoid",
                     choices=["poisson_ellipsoid", "laplace_sphere", "helmholtz_star", "batch", "serve", "profile",
-                             "formulations"])
+                             "formulations", "particular"])
     ap.add_argument("--star-nodes", type=int, default=257)
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--requests", type=int, default=200)
@@ -475,7 +505,7 @@ def main():
     import workloads as W
 
     fn = {"poisson_ellipsoid": headline, "laplace_sphere": laplace_sphere, "helmholtz_star": helmholtz_star,
-          "formulations": formulations,
+          "formulations": formulations, "particular": particular,
           "batch": batch, "serve": serve, "profile": profile}[args.workload]
     print(json.dumps(fn(args, torch, P, W)))
 

@@ -182,6 +182,19 @@ int bae_get_boundary_points(const bae_ctx* ctx, double* xstar, int32_t* partner,
  * nrhs in [1, max_rhs].  BAE_ERR_NONFINITE on NaN/Inf input.
  */
 int bae_set_rhs(bae_ctx* ctx, int32_t nrhs, const double* g_xstar, const double* f_grid);
+/*
+ * The same with Algorithm 1's particular solution on the finite grid: u_p = G_h[chi_{M+} f],
+ * G_h the inverse of the 7-point operator on the interior nodes of the box with u = 0 on its
+ * boundary nodes (Sec. 2.1), by sine transforms along the three axes (DST-I, each a dense
+ * contraction on the device), instead of the free-space volume LGF sum.  u, u_gamma and the
+ * grid solution are the same discrete solution either way; the density q differs.  Needs a
+ * cubic grid when f is given (BAE_ERR_ARG otherwise); with f == NULL it equals bae_set_rhs.
+ * The context keeps u_p on the device (N^3 doubles per RHS, N = n - 2) for the grid solution.
+ */
+int bae_set_rhs_box(bae_ctx* ctx, int32_t nrhs, const double* g_xstar, const double* f_grid);
+/* u_p of right-hand side r on the whole grid (n0*n1*n2, k fastest; zero on the box boundary)
+   after bae_set_rhs_box with f; caller-owned host buffer.  BAE_ERR_STATE otherwise. */
+int bae_get_particular(const bae_ctx* ctx, int32_t r, double* up_grid);
 
 /*
  * Solve A q_d = b for every RHS (GMRES, x0 = 0, no preconditioner: Sec. 4), then form

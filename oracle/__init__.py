@@ -12,6 +12,7 @@ Modules
   operators  single/double layer potentials, the BAE operator, volume potential (Sec. 3.2-3.4)
   gmres      unrestarted GMRES with modified Gram-Schmidt and Givens rotations (Sec. 4)
   sparse     the plain sparse discrete Dirichlet problem the method is equivalent to (Sec. 2.2)
+  box        the particular solution on the finite grid, G_h[chi_{M+} f] (Algorithm 1)
   bae        Algorithm 1 end to end
 
 Every function is pinned by tests under tests/ (test_oracle_*.py) to values the paper

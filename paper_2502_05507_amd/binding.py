@@ -123,6 +123,8 @@ def load_library():
         "bae_get_sets": (C.c_int, [_P, _P, _P, _P]),
         "bae_get_boundary_points": (C.c_int, [_P, _P, _P, _P]),
         "bae_set_rhs": (C.c_int, [_P, C.c_int32, _P, _P]),
+        "bae_set_rhs_box": (C.c_int, [_P, C.c_int32, _P, _P]),
+        "bae_get_particular": (C.c_int, [_P, C.c_int32, _P]),
         "bae_solve": (C.c_int, [_P, C.POINTER(SolveParams), _P]),
         "bae_get_density": (C.c_int, [_P, C.c_int32, _P]),
         "bae_get_gamma_values": (C.c_int, [_P, C.c_int32, _P]),
@@ -251,13 +253,22 @@ class Context:
         _check(load_library().bae_get_boundary_points(self._h, _ptr(xs), _ptr(pa), _ptr(t)))
         return xs, pa, t
 
-    def set_rhs(self, g, f=None):
+    def set_rhs(self, g, f=None, particular="free"):
+        """g at x* ([nrhs][|gamma-|]) and optional f on the grid.  particular: "free" (the
+        free-space volume potential) or "box" (Algorithm 1's finite-grid solve, bae_set_rhs_box)."""
         g = np.ascontiguousarray(g, dtype=np.float64)
         nrhs = 1 if g.ndim == 1 else g.shape[0]
         if f is not None:
             f = np.ascontiguousarray(f, dtype=np.float64)
-        _check(load_library().bae_set_rhs(self._h, nrhs, _ptr(g), _ptr(f)))
+        fn = {"free": load_library().bae_set_rhs, "box": load_library().bae_set_rhs_box}[particular]
+        _check(fn(self._h, nrhs, _ptr(g), _ptr(f)))
         self.nrhs = nrhs
+
+    def particular(self, r=0):
+        """u_p on the grid after set_rhs(..., particular="box") with f."""
+        u = np.empty(self.n)
+        _check(load_library().bae_get_particular(self._h, r, _ptr(u)))
+        return u
 
     def solve(self, precision=SOLVE_FP64, tol=1e-10, maxit=0, inner_tol=0.0, max_outer=0, compute_grid=False,
               recycle_dim=0, formulation=0):

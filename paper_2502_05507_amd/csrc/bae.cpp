@@ -738,59 +738,124 @@ int bae_get_boundary_points(const bae_ctx* c, double* xstar, int32_t* partner, d
     });
 }
 
-int bae_set_rhs(bae_ctx* c, int32_t nrhs, const double* g_xstar, const double* f_grid) {
-    return guard([&] {
-        if (!c || !g_xstar) throw Error{BAE_ERR_ARG, "null argument"};
-        if (nrhs < 1 || nrhs > c->max_rhs) throw Error{BAE_ERR_ARG, "nrhs out of range"};
-        BAE_HIP_CHECK(hipSetDevice(c->device));
-        hipStream_t st = c->stream;
-        const Geometry& G = c->geo;
-        const int64_t n = c->ngm, N3 = (int64_t)G.n[0] * G.n[1] * G.n[2];
-        for (int64_t i = 0; i < n * nrhs; ++i)
-            if (!std::isfinite(g_xstar[i])) throw Error{BAE_ERR_NONFINITE, "boundary data not finite"};
-        std::vector<double> bh(g_xstar, g_xstar + n * nrhs);
-        c->has_f = f_grid != nullptr;
-        if (c->has_f) {
-            for (int64_t i = 0; i < N3 * nrhs; ++i)
-                if (!std::isfinite(f_grid[i])) throw Error{BAE_ERR_NONFINITE, "source term not finite"};
-            ensure_mplus(c);
-            const int64_t nm = c->Mp.ps.count;
-            if ((int64_t)c->mp_lin.size() != nm) {
-                // linear grid index of each internal M+ point (once per context)
-                std::vector<int32_t> pts;
-                pts.reserve(nm);
-                for (int i = 0; i < G.n[0]; ++i)
-                    for (int j = 0; j < G.n[1]; ++j)
-                        for (int k = 0; k < G.n[2]; ++k)
-                            if (G.inside[((int64_t)i * G.n[1] + j) * G.n[2] + k])
-                                pts.push_back((int32_t)(((int64_t)i * G.n[1] + j) * G.n[2] + k));
-                c->mp_lin.resize(nm);
-                for (int64_t a = 0; a < nm; ++a) c->mp_lin[a] = pts[c->Mp.perm[a]];
+// b = g(x*) - Phi [u_p]_gamma with the particular solution u_p of chi_{M+} f: the free-space
+// volume potential (an LGF sum over the M+ sources), or with `box` the finite-grid solve
+// G_h[chi_{M+} f] of Algorithm 1 (box.hip), kept on the device for the grid solution.
+static void set_rhs_impl(bae_ctx* c, int32_t nrhs, const double* g_xstar, const double* f_grid, bool box) {
+    if (!c || !g_xstar) throw Error{BAE_ERR_ARG, "null argument"};
+    if (nrhs < 1 || nrhs > c->max_rhs) throw Error{BAE_ERR_ARG, "nrhs out of range"};
+    const Geometry& G = c->geo;
+    if (box && f_grid && (G.n[0] != G.n[1] || G.n[1] != G.n[2]))
+        throw Error{BAE_ERR_ARG, "the box particular solution needs a cubic grid"};
+    BAE_HIP_CHECK(hipSetDevice(c->device));
+    hipStream_t st = c->stream;
+    const int64_t n = c->ngm, N3 = (int64_t)G.n[0] * G.n[1] * G.n[2];
+    for (int64_t i = 0; i < n * nrhs; ++i)
+        if (!std::isfinite(g_xstar[i])) throw Error{BAE_ERR_NONFINITE, "boundary data not finite"};
+    std::vector<double> bh(g_xstar, g_xstar + n * nrhs);
+    c->has_f = f_grid != nullptr;
+    c->particular_box = false;
+    if (c->has_f) {
+        for (int64_t i = 0; i < N3 * nrhs; ++i)
+            if (!std::isfinite(f_grid[i])) throw Error{BAE_ERR_NONFINITE, "source term not finite"};
+        ensure_mplus(c);
+        const int64_t nm = c->Mp.ps.count;
+        if ((int64_t)c->mp_lin.size() != nm) {
+            // linear grid index of each internal M+ point (once per context)
+            std::vector<int32_t> pts;
+            pts.reserve(nm);
+            for (int i = 0; i < G.n[0]; ++i)
+                for (int j = 0; j < G.n[1]; ++j)
+                    for (int k = 0; k < G.n[2]; ++k)
+                        if (G.inside[((int64_t)i * G.n[1] + j) * G.n[2] + k])
+                            pts.push_back((int32_t)(((int64_t)i * G.n[1] + j) * G.n[2] + k));
+            c->mp_lin.resize(nm);
+            for (int64_t a = 0; a < nm; ++a) c->mp_lin[a] = pts[c->Mp.perm[a]];
+        }
+        const std::vector<int32_t>& lin = c->mp_lin;
+        const double h2 = G.h * G.h;
+        if (box) {
+            const int N = G.n[0] - 2;
+            const int64_t nn = (int64_t)N * N * N;
+            auto interior = [&](int64_t l) {   // grid index -> interior index
+                const int64_t i = l / ((int64_t)G.n[1] * G.n[2]), j = (l / G.n[2]) % G.n[1], k = l % G.n[2];
+                return (int32_t)(((i - 1) * N + (j - 1)) * N + (k - 1));
+            };
+            if (c->box_N != N) {
+                c->box_S.alloc(sizeof(double) * N * N);
+                box_dst_matrix(N, c->box_S.as<double>(), st);
+                c->box_tmp.alloc(sizeof(double) * nn);
+                std::vector<int32_t> tidx(c->nT), midx(nm);
+                for (int64_t t = 0; t < c->nT; ++t) {
+                    const int32_t* v = t < c->ngp ? &G.gp[3 * t] : &G.gm[3 * (t - c->ngp)];
+                    tidx[t] = (int32_t)(((int64_t)(v[0] - 1) * N + (v[1] - 1)) * N + (v[2] - 1));
+                }
+                for (int64_t a = 0; a < nm; ++a) midx[a] = interior(lin[a]);
+                upload(c->box_tidx, tidx, st);
+                upload(c->box_mpidx, midx, st);
+                BAE_HIP_CHECK(hipStreamSynchronize(st));   // tidx, midx leave scope
+                c->box_N = N;
             }
-            const std::vector<int32_t>& lin = c->mp_lin;
+            if (c->box_u.bytes < sizeof(double) * nn * nrhs) c->box_u.alloc(sizeof(double) * nn * nrhs);
+            std::vector<double> q(nn * nrhs, 0.0);
+            for (int r = 0; r < nrhs; ++r)
+                for (int64_t a = 0; a < nm; ++a) q[r * nn + interior(lin[a])] = h2 * f_grid[r * N3 + lin[a]];
+            BAE_HIP_CHECK(hipMemcpyAsync(c->box_u.p, q.data(), sizeof(double) * q.size(), hipMemcpyHostToDevice, st));
+            for (int r = 0; r < nrhs; ++r)
+                box_solve(c->box_S.as<double>(), c->box_u.as<double>() + r * nn, c->box_tmp.as<double>(), N, c->s, st);
+            launch_gather(c->box_u.as<double>(), nn, c->box_tidx.as<int32_t>(), c->nT, c->up_gamma.as<double>(),
+                          c->nT, nrhs, 1.0, st);
+            c->particular_box = true;
+        } else {
             const int64_t nmp = c->Mp.ps.padded;
             std::vector<double> wfh(nmp * nrhs, 0.0);
-            const double h2 = G.h * G.h;
             for (int r = 0; r < nrhs; ++r)
                 for (int64_t a = 0; a < nm; ++a) wfh[r * nmp + a] = h2 * f_grid[r * N3 + lin[a]];
             upload(c->wf, wfh, st);
-            lgf_sum_to(c, c->T.ps, c->Mp.ps, c->wf.as<double>(), nrhs, c->t_pos.as<int32_t>(), c->up_gamma.as<double>(),
-                       c->nT, 1.0, st);
-            std::vector<double> up(c->nT * nrhs);
-            BAE_HIP_CHECK(hipMemcpy(up.data(), c->up_gamma.p, sizeof(double) * up.size(), hipMemcpyDeviceToHost));
-            for (int r = 0; r < nrhs; ++r)
-                for (int64_t q = 0; q < n; ++q) {
-                    const double t = G.t[q];
-                    bh[r * n + q] -= (1.0 - t) * up[r * c->nT + c->ngp + q] + t * up[r * c->nT + G.partner[q]];
-                }
-        } else {
-            launch_fill(c->up_gamma.as<double>(), c->nT * nrhs, 0.0, st);
+            lgf_sum_to(c, c->T.ps, c->Mp.ps, c->wf.as<double>(), nrhs, c->t_pos.as<int32_t>(),
+                       c->up_gamma.as<double>(), c->nT, 1.0, st);
         }
-        BAE_HIP_CHECK(hipMemcpyAsync(c->b.p, bh.data(), sizeof(double) * bh.size(), hipMemcpyHostToDevice, st));
+        std::vector<double> up(c->nT * nrhs);
+        BAE_HIP_CHECK(hipMemcpyAsync(up.data(), c->up_gamma.p, sizeof(double) * up.size(), hipMemcpyDeviceToHost, st));
         BAE_HIP_CHECK(hipStreamSynchronize(st));
-        c->nrhs = nrhs;
-        c->rhs_ready = true;
-        c->solved = false;
+        for (int r = 0; r < nrhs; ++r)
+            for (int64_t q = 0; q < n; ++q) {
+                const double t = G.t[q];
+                bh[r * n + q] -= (1.0 - t) * up[r * c->nT + c->ngp + q] + t * up[r * c->nT + G.partner[q]];
+            }
+    } else {
+        launch_fill(c->up_gamma.as<double>(), c->nT * nrhs, 0.0, st);
+    }
+    BAE_HIP_CHECK(hipMemcpyAsync(c->b.p, bh.data(), sizeof(double) * bh.size(), hipMemcpyHostToDevice, st));
+    BAE_HIP_CHECK(hipStreamSynchronize(st));
+    c->nrhs = nrhs;
+    c->rhs_ready = true;
+    c->solved = false;
+}
+
+int bae_set_rhs(bae_ctx* c, int32_t nrhs, const double* g_xstar, const double* f_grid) {
+    return guard([&] { set_rhs_impl(c, nrhs, g_xstar, f_grid, false); });
+}
+
+int bae_set_rhs_box(bae_ctx* c, int32_t nrhs, const double* g_xstar, const double* f_grid) {
+    return guard([&] { set_rhs_impl(c, nrhs, g_xstar, f_grid, true); });
+}
+
+int bae_get_particular(const bae_ctx* c, int32_t r, double* up_grid) {
+    return guard([&] {
+        if (!c || !up_grid) throw Error{BAE_ERR_ARG, "null argument"};
+        if (!c->particular_box) throw Error{BAE_ERR_STATE, "no box particular solution (bae_set_rhs_box with f)"};
+        if (r < 0 || r >= c->nrhs) throw Error{BAE_ERR_ARG, "rhs index out of range"};
+        const Geometry& G = c->geo;
+        const int N = c->box_N;
+        const int64_t nn = (int64_t)N * N * N, N3 = (int64_t)G.n[0] * G.n[1] * G.n[2];
+        std::vector<double> u(nn);
+        BAE_HIP_CHECK(hipMemcpy(u.data(), c->box_u.as<double>() + r * nn, sizeof(double) * nn, hipMemcpyDeviceToHost));
+        std::fill(up_grid, up_grid + N3, 0.0);
+        for (int i = 1; i <= N; ++i)
+            for (int j = 1; j <= N; ++j)
+                for (int k = 1; k <= N; ++k)
+                    up_grid[((int64_t)i * G.n[1] + j) * G.n[2] + k] = u[((int64_t)(i - 1) * N + (j - 1)) * N + (k - 1)];
     });
 }
 
@@ -909,7 +974,13 @@ int bae_solve(bae_ctx* c, const bae_solve_params* p, bae_result* res) {
             if (c->has_f) {
                 DevMem up;
                 up.alloc(sizeof(double) * nm * nrhs);
-                lgf_sum_to(c, c->Mp.ps, c->Mp.ps, c->wf.as<double>(), nrhs, nullptr, up.as<double>(), nm, 1.0, st);
+                if (c->particular_box) {   // the finite-grid u_p is known at every node
+                    const int64_t nn = (int64_t)c->box_N * c->box_N * c->box_N;
+                    launch_gather(c->box_u.as<double>(), nn, c->box_mpidx.as<int32_t>(), nm, up.as<double>(), nm,
+                                  nrhs, 1.0, st);
+                } else {
+                    lgf_sum_to(c, c->Mp.ps, c->Mp.ps, c->wf.as<double>(), nrhs, nullptr, up.as<double>(), nm, 1.0, st);
+                }
                 launch_axpby(1.0, up.as<double>(), nm, 1.0, um.as<double>(), nm, nm, nrhs, st);
             }
             std::vector<double> hu(nm * nrhs), hg(c->nT * nrhs);

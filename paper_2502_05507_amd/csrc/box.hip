@@ -1,0 +1,136 @@
+// The particular solution on the finite grid (Algorithm 1, first step): u_p = G_h[chi_{M+} f],
+// G_h the inverse of the 7-point operator L_h u = (6 + s) u(m) - sum of the six neighbours on
+// the N^3 interior nodes of the box with u = 0 on its boundary nodes (Sec. 2.1).
+//
+// The sine vectors diagonalise L_h: with the DST-I matrix S[m][l] = sin(pi (m+1)(l+1) / (N+1))
+// (symmetric, S S = (N+1)/2 I) applied along each axis,
+//   u = (2/(N+1))^3 S_3 S_2 S_1 [ (S_1 S_2 S_3 q) / lambda ],
+//   lambda(k) = (6 + s) - 2 (cos(pi k1/(N+1)) + cos(pi k2/(N+1)) + cos(pi k3/(N+1))).
+// Each S along an axis is a dense contraction: the grid viewed as an N x N^2 matrix times S
+// from the left (a tiled FP64 GEMM), then a transpose to N^2 x N that rotates the axes, so
+// three passes transform every axis and return the original order.  O(N^4) work: at
+// N = 255, six passes of 8.5e9 flops.
+#include "internal.hpp"
+#include "ops.hpp"
+
+namespace bae {
+namespace {
+
+constexpr int kTile = 64;     // GEMM output tile (rows x columns)
+constexpr int kTileK = 16;    // contraction chunk
+constexpr int kTr = 32;       // transpose tile
+
+__global__ void dst_matrix_kernel(int N, double* __restrict__ S) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)N * N) return;
+    const int m = (int)(i / N), l = (int)(i % N);
+    // reduce (m+1)(l+1) modulo 2(N+1) first, so the sine's argument stays below 2 pi
+    const int64_t r = ((int64_t)(m + 1) * (l + 1)) % (2 * (int64_t)(N + 1));
+    S[i] = sin(M_PI * (double)r / (double)(N + 1));
+}
+
+// C[m][p] = sum_l S[m][l] B[l][p], m < N, p < P; S N x N, B and C N x P, row-major.
+// 256 threads, each 4 x 4 outputs of a 64 x 64 tile; S and B chunks staged in LDS.
+__global__ __launch_bounds__(256) void gemm_s_kernel(const double* __restrict__ S, const double* __restrict__ B,
+                                                     double* __restrict__ C, int N, int64_t P) {
+    __shared__ double As[kTileK][kTile + 1];   // As[l][m] = S[m0 + m][l0 + l]
+    __shared__ double Bs[kTileK][kTile];
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int m0 = blockIdx.y * kTile;
+    const int64_t p0 = (int64_t)blockIdx.x * kTile;
+    double acc[4][4] = {};
+    for (int l0 = 0; l0 < N; l0 += kTileK) {
+        for (int e = threadIdx.x; e < kTile * kTileK; e += 256) {
+            const int m = e / kTileK, l = e % kTileK;
+            As[l][m] = (m0 + m < N && l0 + l < N) ? S[(int64_t)(m0 + m) * N + l0 + l] : 0.0;
+            const int lb = e / kTile, pb = e % kTile;
+            Bs[lb][pb] = (l0 + lb < N && p0 + pb < P) ? B[(int64_t)(l0 + lb) * P + p0 + pb] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int l = 0; l < kTileK; ++l) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[l][ty * 4 + i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[l][tx + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int m = m0 + ty * 4 + i;
+        if (m >= N) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t p = p0 + tx + 16 * j;
+            if (p < P) C[(int64_t)m * P + p] = acc[i][j];
+        }
+    }
+}
+
+// out[p][m] = in[m][p] for an R x Q row-major input (R = N rows, Q = N^2 columns).
+__global__ __launch_bounds__(kTr * 8) void transpose_kernel(const double* __restrict__ in, double* __restrict__ out,
+                                                            int64_t R, int64_t Q) {
+    __shared__ double t[kTr][kTr + 1];
+    const int64_t q0 = (int64_t)blockIdx.x * kTr, r0 = (int64_t)blockIdx.y * kTr;
+    const int tx = threadIdx.x % kTr, ty = threadIdx.x / kTr;
+    for (int y = ty; y < kTr; y += 8) {
+        const int64_t r = r0 + y, q = q0 + tx;
+        t[y][tx] = (r < R && q < Q) ? in[r * Q + q] : 0.0;
+    }
+    __syncthreads();
+    for (int y = ty; y < kTr; y += 8) {
+        const int64_t q = q0 + y, r = r0 + tx;
+        if (q < Q && r < R) out[q * R + r] = t[tx][y];
+    }
+}
+
+// x[k1][k2][k3] *= scale / lambda(k)  (the three axes in any order: lambda is symmetric)
+__global__ void eigen_scale_kernel(double* __restrict__ x, int N, double s, double scale) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n3 = (int64_t)N * N * N;
+    if (i >= n3) return;
+    const int k1 = (int)(i / ((int64_t)N * N)), k2 = (int)((i / N) % N), k3 = (int)(i % N);
+    const double w = M_PI / (double)(N + 1);
+    const double lam = (6.0 + s) - 2.0 * (cos(w * (k1 + 1)) + cos(w * (k2 + 1)) + cos(w * (k3 + 1)));
+    x[i] *= scale / lam;
+}
+
+// the three axis passes: x <- S along every axis (x and tmp: N^3 each; result in x)
+void dst3(const double* S, double* x, double* tmp, int N, hipStream_t st) {
+    const int64_t P = (int64_t)N * N;
+    const dim3 gg((unsigned)((P + kTile - 1) / kTile), (unsigned)((N + kTile - 1) / kTile));
+    const dim3 tg((unsigned)((P + kTr - 1) / kTr), (unsigned)((N + kTr - 1) / kTr));
+    for (int pass = 0; pass < 3; ++pass) {
+        gemm_s_kernel<<<gg, 256, 0, st>>>(S, x, tmp, N, P);
+        transpose_kernel<<<tg, kTr * 8, 0, st>>>(tmp, x, N, P);
+    }
+    BAE_HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace
+
+// u = G_h q on the N^3 interior nodes, in place in x (one RHS); S: the N x N DST-I matrix
+// (box_dst_matrix); tmp: N^3 scratch.
+void box_solve(const double* S, double* x, double* tmp, int N, double s, hipStream_t st) {
+    if (N <= 0) return;
+    dst3(S, x, tmp, N, st);
+    const int64_t n3 = (int64_t)N * N * N;
+    const double c = 2.0 / (double)(N + 1);
+    eigen_scale_kernel<<<(unsigned)((n3 + 255) / 256), 256, 0, st>>>(x, N, s, c * c * c);
+    BAE_HIP_CHECK(hipGetLastError());
+    dst3(S, x, tmp, N, st);
+}
+
+void box_dst_matrix(int N, double* S, hipStream_t st) {
+    if (N <= 0) return;
+    dst_matrix_kernel<<<(unsigned)(((int64_t)N * N + 255) / 256), 256, 0, st>>>(N, S);
+    BAE_HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace bae

@@ -204,6 +204,11 @@ struct bae_ctx {
     DevMem vsum;               // [rhs][nT] chunk-reduced sums (operator scratch)
     DevMem wf;                 // [rhs][|M+|] h^2 f in Mp order
     std::vector<int32_t> mp_lin;   // linear grid index of each M+ point in Mp order (lazy)
+    // box particular solution (bae_set_rhs_box): u_p on the N^3 interior nodes per RHS, the
+    // DST-I matrix, scratch, and the interior index of every target and of every M+ point
+    bool particular_box = false;
+    int box_N = 0;
+    DevMem box_S, box_u, box_tmp, box_tidx, box_mpidx;
     DevMem ctl;                // Ctl of RHS 0 for batched / served solves
     int nrhs = 0;
     bool has_f = false, rhs_ready = false, solved = false;

@@ -1,6 +1,7 @@
 """The paper's printed error tables, end to end on the device: Sec. 4.1 Table 1 (Poisson,
 ellipsoid) and Sec. 4.2 Table 2 (modified Helmholtz, torus).  The library solves each problem
-(LGF table, particular solution, GMRES, grid solution on M+) and the largest error against the
+(LGF table, particular solution -- the free-space volume potential, or the finite-grid
+solve by sine transforms that Algorithm 1 prints --, GMRES, grid solution on M+) and the largest error against the
 exact solution must match the printed value to within one unit of its last digit.  The
 printed values are the fixtures in golden/paper_tables.json; the oracle only supplies the
 point set M+ at which the error is taken."""
@@ -41,13 +42,14 @@ def case(which, N):
                                      ("poisson_ellipsoid", 127), ("poisson_ellipsoid", 255),
                                      ("helmholtz_torus", 31), ("helmholtz_torus", 63),
                                      ("helmholtz_torus", 127), ("helmholtz_torus", 255)])
-@pytest.mark.parametrize("precision", [P.SOLVE_FP64, P.SOLVE_FP32_REFINED])
-def test_paper_tables_on_device(which, N, precision):
+@pytest.mark.parametrize("precision,particular", [(P.SOLVE_FP64, "free"), (P.SOLVE_FP32_REFINED, "free"),
+                                                  (P.SOLVE_FP64, "box")])
+def test_paper_tables_on_device(which, N, precision, particular):
     tab, n, h, o, kind, params, u, f, X = case(which, N)
     mplus = geometry.build(n, h, o, kind, (0.0, 0.0, 0.0), params).mplus
     with P.Context(n, h, o, tab["sigma"], kind, (0.0, 0.0, 0.0), params) as ctx:
         xs, _, _ = ctx.boundary_points()
-        ctx.set_rhs(u(*xs.T), f)
+        ctx.set_rhs(u(*xs.T), f, particular=particular)
         res = ctx.solve(precision, tol=1e-11 if precision == P.SOLVE_FP64 else 1e-10, compute_grid=True)[0]
         grid = ctx.solution()
         empty = ctx.sizes["n_empty_d"]
@@ -58,7 +60,7 @@ def test_paper_tables_on_device(which, N, precision):
     printed = tab["max_error"][str(N)]
     unit = 10.0 ** (math.floor(math.log10(printed)) - 4)
     shown = round(err / unit) * unit                 # the error to the printed digits
-    print(f"{which} N={N}: max error {err:.5e} (printed {printed:.4e}), empty D_n nodes {empty}, "
+    print(f"{which} N={N} ({particular} u_p): max error {err:.5e} (printed {printed:.4e}), empty D_n nodes {empty}, "
           f"{res['iterations']} iterations")
     # at most one unit of the last printed digit (Table 2 at N = 31 and 127 rounds one unit
     # below the print, as the oracle's discrete solution does)

@@ -281,6 +281,35 @@ def test_sum_alone_for_timing_leaves_the_operator_unchanged():
             assert e.value.status == -1
 
 
+# ------------------------------------------------------------------ Algorithm 1: box particular solution
+@pytest.mark.parametrize("kind,n,sigma", [("ellipsoid", 33, 0.0), ("torus", 41, 10.0)])
+def test_box_particular_solution_matches_oracle(kind, n, sigma):
+    """u_p = G_h[chi_{M+} f] on the finite grid (sine transforms on the device) against the
+    oracle's; the solve on it gives the free-space path's u_gamma and grid solution."""
+    from oracle import box
+    p = small_problem(kind, n, sigma)
+    g = geometry.from_problem(p)
+    X = g.coords(np.indices(g.n).reshape(3, -1).T)
+    f = (np.sin(2 * X[:, 0]) + X[:, 1] * X[:, 2] + 1.0).reshape(-1)
+    ref = box.particular_box(g, sigma * p.h ** 2, f)
+    gx_fn = lambda Y: np.cos(Y[:, 0]) * Y[:, 1] + Y[:, 2]
+    with P.Context.from_problem(p) as ctx:
+        xs, _, _ = ctx.boundary_points()
+        ctx.set_rhs(gx_fn(xs), f, particular="box")
+        up = ctx.particular()
+        assert np.abs(up - ref).max() < 1e-12 * np.abs(ref).max(), np.abs(up - ref).max() / np.abs(ref).max()
+        rb = ctx.solve(P.SOLVE_FP64, tol=1e-13, compute_grid=True)[0]
+        ug_b, u_b = ctx.gamma_values(), ctx.solution()
+        ctx.set_rhs(gx_fn(xs), f)
+        rf = ctx.solve(P.SOLVE_FP64, tol=1e-13, compute_grid=True)[0]
+        ug_f, u_f = ctx.gamma_values(), ctx.solution()
+    assert rb["converged"] and rf["converged"]
+    assert rel_l2(ug_b, ug_f) < 1e-10
+    nplus = ~np.isnan(u_f)
+    assert np.array_equal(~np.isnan(u_b), nplus)
+    assert np.abs(u_b[nplus] - u_f[nplus]).max() < 1e-10 * np.abs(u_f[nplus]).max()
+
+
 # ------------------------------------------------------------------ single-layer formulation
 @pytest.mark.parametrize("kind,n,sigma", [("sphere", 33, 0.0), ("torus", 41, 10.0)])
 def test_single_layer_matches_oracle(kind, n, sigma):

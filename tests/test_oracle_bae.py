@@ -236,3 +236,35 @@ def test_algorithm1_driver_laplace_sphere():
     assert np.abs(r["u_gamma"] - us[tuple(T.T)]).max() < 1e-10
     mp = g.mplus
     assert np.abs(r["u_grid"][tuple(mp.T)] - us[tuple(mp.T)]).max() < 1e-10
+
+
+# ------------------------------------------------------------------ Algorithm 1: box particular solution
+@pytest.mark.parametrize("sigma", [0.0, 10.0])
+def test_box_particular_solution(sigma):
+    # u_p = G_h[chi_{M+} f] on the finite grid: the 7-point equation holds at every interior
+    # node (applied directly, no transform), u_p vanishes on the box boundary, and the BAE
+    # built on it reaches the same discrete solution as with the free-space volume potential
+    # (Sec. 2.2 equivalence).
+    from oracle import box
+    g, G, s = small("ellipsoid", 17, sigma)
+    X = g.coords(np.indices(g.n).reshape(3, -1).T)
+    f = (np.sin(2 * X[:, 0]) + X[:, 1] * X[:, 2]).reshape(-1)
+    u = box.particular_box(g, s, f)
+    q = np.zeros(g.n)
+    q[tuple(g.mplus.T)] = g.h ** 2 * f.reshape(g.n)[tuple(g.mplus.T)]
+    c = u[1:-1, 1:-1, 1:-1]
+    Lu = ((6 + s) * c - u[:-2, 1:-1, 1:-1] - u[2:, 1:-1, 1:-1] - u[1:-1, :-2, 1:-1] - u[1:-1, 2:, 1:-1]
+          - u[1:-1, 1:-1, :-2] - u[1:-1, 1:-1, 2:])
+    assert np.abs(Lu - q[1:-1, 1:-1, 1:-1]).max() < 1e-14 * max(1.0, np.abs(q).max()) * 100
+    assert np.all(u[0] == 0) and np.all(u[-1] == 0) and np.all(u[:, 0] == 0) and np.all(u[:, :, -1] == 0)
+    # the BAE on either particular solution gives the sparse discrete solution on M+
+    gx = np.cos(g.xstar[:, 0]) * g.xstar[:, 1]
+    T = operators.gamma_targets(g)
+    up_t = u[tuple(T.T)]
+    b = gx - operators.closure(g, up_t)
+    qd, _, conv = gmres.gmres(lambda x: operators.bae_apply(g, G, x), b, tol=1e-13)
+    assert conv
+    mp = g.mplus
+    um = operators.double_layer(g, G, qd, mp) + u[tuple(mp.T)]
+    us = sparse.solve(g, s, gx, f)
+    assert np.abs(um - us[tuple(mp.T)]).max() < 1e-10 * np.abs(us[tuple(mp.T)]).max()

@@ -409,6 +409,13 @@ def test_largest_lattice_offsets_two_balls():
             out = v.cpu().numpy()
             for rr in range(2):
                 assert rel_l2(out[rr], ref[rr]) < tol, (prec, rr, rel_l2(out[rr], ref[rr]))
+        # the box particular solution needs a cubic grid; without it there is no u_p to read
+        with pytest.raises(P.BaeError) as e:
+            ctx.set_rhs(np.zeros(len(g.gamma_minus)), np.ones(int(np.prod(n))), particular="box")
+        assert e.value.status == -1
+        ctx.set_rhs(np.zeros(len(g.gamma_minus)), np.ones(int(np.prod(n))))
+        with pytest.raises(P.BaeError):
+            ctx.particular()
 
 
 # ------------------------------------------------------------------ A10: 16 right-hand sides (MFMA form)

@@ -797,10 +797,13 @@ static void set_rhs_impl(bae_ctx* c, int32_t nrhs, const double* g_xstar, const 
                 c->box_N = N;
             }
             if (c->box_u.bytes < sizeof(double) * nn * nrhs) c->box_u.alloc(sizeof(double) * nn * nrhs);
-            std::vector<double> q(nn * nrhs, 0.0);
+            // h^2 f at the M+ points only crosses the bus; the device places it in the zeroed grid
+            std::vector<double> wfh(nm * nrhs);
             for (int r = 0; r < nrhs; ++r)
-                for (int64_t a = 0; a < nm; ++a) q[r * nn + interior(lin[a])] = h2 * f_grid[r * N3 + lin[a]];
-            BAE_HIP_CHECK(hipMemcpyAsync(c->box_u.p, q.data(), sizeof(double) * q.size(), hipMemcpyHostToDevice, st));
+                for (int64_t a = 0; a < nm; ++a) wfh[r * nm + a] = h2 * f_grid[r * N3 + lin[a]];
+            upload(c->wf, wfh, st);
+            launch_fill(c->box_u.as<double>(), nn * nrhs, 0.0, st);
+            box_scatter(c->wf.as<double>(), nm, c->box_mpidx.as<int32_t>(), nm, c->box_u.as<double>(), nn, nrhs, st);
             for (int r = 0; r < nrhs; ++r)
                 box_solve(c->box_S.as<double>(), c->box_u.as<double>() + r * nn, c->box_tmp.as<double>(), N, c->s, st);
             launch_gather(c->box_u.as<double>(), nn, c->box_tidx.as<int32_t>(), c->nT, c->up_gamma.as<double>(),

@@ -101,6 +101,14 @@ __global__ void eigen_scale_kernel(double* __restrict__ x, int N, double s, doub
     x[i] *= scale / lam;
 }
 
+// dst[r][idx[i]] = src[r][i]: the source values at M+ into the zeroed interior grid
+__global__ void scatter_kernel(const double* __restrict__ src, int64_t lds, const int32_t* __restrict__ idx,
+                               int64_t n, double* __restrict__ dst, int64_t ldd) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i < n) dst[r * ldd + idx[i]] = src[r * lds + i];
+}
+
 // the three axis passes: x <- S along every axis (x and tmp: N^3 each; result in x)
 void dst3(const double* S, double* x, double* tmp, int N, hipStream_t st) {
     const int64_t P = (int64_t)N * N;
@@ -125,6 +133,13 @@ void box_solve(const double* S, double* x, double* tmp, int N, double s, hipStre
     eigen_scale_kernel<<<(unsigned)((n3 + 255) / 256), 256, 0, st>>>(x, N, s, c * c * c);
     BAE_HIP_CHECK(hipGetLastError());
     dst3(S, x, tmp, N, st);
+}
+
+void box_scatter(const double* src, int64_t lds, const int32_t* idx, int64_t n, double* dst, int64_t ldd, int nrhs,
+                 hipStream_t st) {
+    if (n <= 0) return;
+    scatter_kernel<<<dim3((unsigned)((n + 255) / 256), nrhs), 256, 0, st>>>(src, lds, idx, n, dst, ldd);
+    BAE_HIP_CHECK(hipGetLastError());
 }
 
 void box_dst_matrix(int N, double* S, hipStream_t st) {

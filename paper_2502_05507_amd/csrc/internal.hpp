@@ -158,5 +158,8 @@ double yukawa_check(const double* table, int R, int from_r, double kappa, hipStr
 // S: the N x N DST-I matrix from box_dst_matrix; tmp: N^3 doubles of scratch.
 void box_solve(const double* S, double* x, double* tmp, int N, double s, hipStream_t st);
 void box_dst_matrix(int N, double* S, hipStream_t st);
+// dst[r][idx[i]] = src[r][i] for i < n (row strides lds, ldd)
+void box_scatter(const double* src, int64_t lds, const int32_t* idx, int64_t n, double* dst, int64_t ldd, int nrhs,
+                 hipStream_t st);
 
 }  // namespace bae

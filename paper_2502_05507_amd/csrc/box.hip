@@ -7,7 +7,7 @@
 //   u = (2/(N+1))^3 S_3 S_2 S_1 [ (S_1 S_2 S_3 q) / lambda ],
 //   lambda(k) = (6 + s) - 2 (cos(pi k1/(N+1)) + cos(pi k2/(N+1)) + cos(pi k3/(N+1))).
 // Each S along an axis is a dense contraction: the grid viewed as an N x N^2 matrix times S
-// from the left (a tiled FP64 GEMM), then a transpose to N^2 x N that rotates the axes, so
+// from the left (a GEMM on the FP64 matrix cores), then a transpose to N^2 x N that rotates the axes, so
 // three passes transform every axis and return the original order.  O(N^4) work: at
 // N = 255, six passes of 8.5e9 flops.
 #include "internal.hpp"
@@ -29,16 +29,28 @@ __global__ void dst_matrix_kernel(int N, double* __restrict__ S) {
     S[i] = sin(M_PI * (double)r / (double)(N + 1));
 }
 
-// C[m][p] = sum_l S[m][l] B[l][p], m < N, p < P; S N x N, B and C N x P, row-major.
-// 256 threads, each 4 x 4 outputs of a 64 x 64 tile; S and B chunks staged in LDS.
+// C[m][p] = sum_l S[m][l] B[l][p], m < N, p < P; S N x N, B and C N x P, row-major, on the
+// FP64 matrix cores (v_mfma_f64_16x16x4).  A block of 4 wavefronts owns a 64 x 64 tile of C,
+// each wavefront 32 x 32 as 2 x 2 MFMA tiles; chunks of 16 along l are staged in LDS.
+// Operand layouts (16x16x4 f64, measured on gfx950): A[i][k] in lane 16k + i, B[k][j] in
+// lane 16k + j; D[i][j] in lane 16v' + j, element v, with i = v' + 4v.
+using V4d = __attribute__((__vector_size__(4 * sizeof(double)))) double;
 __global__ __launch_bounds__(256) void gemm_s_kernel(const double* __restrict__ S, const double* __restrict__ B,
                                                      double* __restrict__ C, int N, int64_t P) {
     __shared__ double As[kTileK][kTile + 1];   // As[l][m] = S[m0 + m][l0 + l]
-    __shared__ double Bs[kTileK][kTile];
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    __shared__ double Bs[kTileK][kTile + 1];   // Bs[l][p] = B[l0 + l][p0 + p]
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = lane & 15, kq = lane >> 4;
+    const int wm = (w >> 1) * 32, wp = (w & 1) * 32;
     const int m0 = blockIdx.y * kTile;
     const int64_t p0 = (int64_t)blockIdx.x * kTile;
-    double acc[4][4] = {};
+    V4d acc[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[t][u][v] = 0.0;
     for (int l0 = 0; l0 < N; l0 += kTileK) {
         for (int e = threadIdx.x; e < kTile * kTileK; e += 256) {
             const int m = e / kTileK, l = e % kTileK;
@@ -48,29 +60,29 @@ __global__ __launch_bounds__(256) void gemm_s_kernel(const double* __restrict__ 
         }
         __syncthreads();
 #pragma unroll
-        for (int l = 0; l < kTileK; ++l) {
-            double a[4], b[4];
+        for (int kk = 0; kk < kTileK; kk += 4) {
+            double a[2], b[2];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[l][ty * 4 + i];
+            for (int t = 0; t < 2; ++t) a[t] = As[kk + kq][wm + 16 * t + i];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[l][tx + 16 * j];
+            for (int u = 0; u < 2; ++u) b[u] = Bs[kk + kq][wp + 16 * u + i];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int t = 0; t < 2; ++t)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+                for (int u = 0; u < 2; ++u) acc[t][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[u], acc[t][u], 0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int m = m0 + ty * 4 + i;
-        if (m >= N) continue;
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t p = p0 + tx + 16 * j;
-            if (p < P) C[(int64_t)m * P + p] = acc[i][j];
-        }
-    }
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int m = m0 + wm + 16 * t + kq + 4 * v;
+                const int64_t p = p0 + wp + 16 * u + i;
+                if (m < N && p < P) C[(int64_t)m * P + p] = acc[t][u][v];
+            }
 }
 
 // out[p][m] = in[m][p] for an R x Q row-major input (R = N rows, Q = N^2 columns).

@@ -269,8 +269,9 @@ typedef struct bae_batch bae_batch;
  */
 int bae_batch_create(bae_ctx* const* ctxs, int32_t n, bae_batch** out);
 /*
- * Time the LGF-sum tiling candidates (source blocks per chunk x persistent grid size) on
- * this batch at `precision`, keep the fastest, and append it to the tuning cache
+ * Time the LGF-sum tiling candidates (source blocks per chunk in {2, 4, 8, 16, 32, 64} x
+ * persistent grid of {1, 2, 4} workgroups per compute unit) on this batch at `precision`,
+ * keep the fastest, and append it to the tuning cache
  * ($BAE_AUTOTUNE_CACHE, else ~/.cache/bae_autotune.txt; keyed by GPU arch, log2 of the
  * pair count and of the batch size) that bae_batch_create reads.  chosen: 2 int32 (or NULL).
  */

@@ -78,7 +78,8 @@ def test_batch_refined_and_autotune(solo, tmp_path):
     ctxs = contexts(probs)
     with P.Batch(ctxs) as b:
         chosen = b.autotune(P.PREC_FP32)
-        assert chosen["blocks_per_chunk"] in (2, 4, 8, 16, 32, 64) and chosen["grid_multiplier"] in (2, 4, 8)
+        # the tuner times every (blocks per chunk, grid multiplier) candidate and keeps the fastest
+        assert chosen["blocks_per_chunk"] in (2, 4, 8, 16, 32, 64) and chosen["grid_multiplier"] in (1, 2, 4)
         res = b.solve(P.SOLVE_FP32_REFINED, tol=1e-11, use_graph=True)
         assert all(r["converged"] for r in res)
         for c, (q, ug) in zip(ctxs, ref):

@@ -31,7 +31,8 @@ __global__ void dst_matrix_kernel(int N, double* __restrict__ S) {
 
 // C[m][p] = sum_l S[m][l] B[l][p], m < N, p < P; S N x N, B and C N x P, row-major, on the
 // FP64 matrix cores (v_mfma_f64_16x16x4).  A block of 4 wavefronts owns a 64 x 64 tile of C,
-// each wavefront 32 x 32 as 2 x 2 MFMA tiles; chunks of 16 along l are staged in LDS.
+// each wavefront 32 x 32 as 2 x 2 MFMA tiles; chunks of 16 along l are staged in LDS, the
+// next chunk's loads in flight while the current one is contracted.
 // Operand layouts (16x16x4 f64, measured on gfx950): A[i][k] in lane 16k + i, B[k][j] in
 // lane 16k + j; D[i][j] in lane 16v' + j, element v, with i = v' + 4v.
 using V4d = __attribute__((__vector_size__(4 * sizeof(double)))) double;
@@ -51,14 +52,28 @@ __global__ __launch_bounds__(256) void gemm_s_kernel(const double* __restrict__ 
         for (int u = 0; u < 2; ++u)
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[t][u][v] = 0.0;
-    for (int l0 = 0; l0 < N; l0 += kTileK) {
-        for (int e = threadIdx.x; e < kTile * kTileK; e += 256) {
+    // the chunk's operands: 4 + 4 values per thread, loaded one chunk ahead of their use
+    double ra[4], rb[4];
+    auto load = [&](int l0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = threadIdx.x + 256 * r;
             const int m = e / kTileK, l = e % kTileK;
-            As[l][m] = (m0 + m < N && l0 + l < N) ? S[(int64_t)(m0 + m) * N + l0 + l] : 0.0;
+            ra[r] = (m0 + m < N && l0 + l < N) ? S[(int64_t)(m0 + m) * N + l0 + l] : 0.0;
             const int lb = e / kTile, pb = e % kTile;
-            Bs[lb][pb] = (l0 + lb < N && p0 + pb < P) ? B[(int64_t)(l0 + lb) * P + p0 + pb] : 0.0;
+            rb[r] = (l0 + lb < N && p0 + pb < P) ? B[(int64_t)(l0 + lb) * P + p0 + pb] : 0.0;
+        }
+    };
+    load(0);
+    for (int l0 = 0; l0 < N; l0 += kTileK) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int e = threadIdx.x + 256 * r;
+            As[e % kTileK][e / kTileK] = ra[r];
+            Bs[e / kTile][e % kTile] = rb[r];
         }
         __syncthreads();
+        if (l0 + kTileK < N) load(l0 + kTileK);
 #pragma unroll
         for (int kk = 0; kk < kTileK; kk += 4) {
             double a[2], b[2];

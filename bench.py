@@ -1,32 +1,39 @@
 #!/usr/bin/env python3
 """Benchmark of the unfitted-BAE hot path on one MI355X.
 
-Default workload (the JSON line the contract asks for): Poisson -Lap u = f on the ellipsoid
-with semi-axes (0.45, 0.3, 0.25) centred in the unit cube, h = 1/128 (129^3 nodes), f and g
-from u = sin(pi x) sin(pi y) sin(pi z).  One step = one complete solve on device-resident
-inputs: FP64 iterative refinement around GMRES with the FP32 LGF sum (every matvec =
-double-layer weights, the LGF sum over |gamma| x |gamma- u E| pairs, the closure) and the FP64
-residual matvecs, the last of which also gives u_gamma.  value = LGF pair-interactions
-evaluated in the timed steps divided by their wall time.  Also reported: solves/s and p50/p99
-latency of the refined and of the plain FP64 path, matvec-only rates (HIP events on the launch
-stream), the roofline of the FP32 LGF-sum kernel (its operations and flops counted per pair
-class, over the kernel's own duration: HIP events around back-to-back launches of the sum
-alone), and the CPU oracle's rate on a bounded sample of the same matvec.
+Default workload (the JSON line the contract asks for; the largest single-GPU
+configuration): modified Helmholtz -Lap u + kappa^2 u = 0, kappa^2 = 10, on the star
+r = 0.4 (1 + 0.15 sin 3 theta cos 2 phi) centred in the unit cube, h = 1/256 (257^3 nodes),
+16 right-hand sides (seeded harmonic-polynomial boundary data).  One step = one complete
+Algorithm 1 solve of all 16 right-hand sides on device-resident inputs: the right-hand side
+(bae_set_rhs_device), then FP64 iterative refinement around GMRES whose matvecs run the FP32
+16-RHS LGF sum on the matrix cores (every matvec = double-layer weights, the LGF sum over
+|gamma| x |gamma- u E| pairs for 16 densities, the closure), the FP64 residual matvecs, the
+last of which gives u_gamma.  value = LGF pair-interactions (pairs x right-hand sides)
+evaluated in the timed steps divided by their wall time.  Also reported: solves/s (one per
+right-hand side) and p50/p99 step latency of the refined path and of the plain FP64 path,
+the roofline of the dominant kernel (the FP32 16-RHS matrix-core sum: algorithmic flops per
+launch over its own duration, HIP events around back-to-back launches of the sum alone, on
+the stream it runs on), and the CPU oracle on 2,000 seeded rows of the same matvec, on one
+core and on all cores.  The 129^3 Poisson ellipsoid (the one-RHS VALU sum) is reported
+beside it under "poisson_ellipsoid_129".
 
 Other workloads (--workload; their own JSON line, not the contract's):
-  laplace_sphere   33^3 Laplace sphere, FP64 and refined solve latency
-  helmholtz_star   257^3 modified Helmholtz, 16 right-hand sides (MFMA form), refined
-  batch            512 seeded small problems in one lock-step, graph-replayed batch
-  serve            Poisson arrivals into the continuous-batching server, p50/p99 latency
-  profile          matvecs only (for rocprofv3) plus a device copy of known size
-  formulations     single- against double-layer formulation (iterations, time) at 129^3
-  particular       free-space against finite-grid (sine-transform) particular solution at 129^3
+  poisson_ellipsoid  129^3 Poisson ellipsoid, one RHS, FP32 VALU sum (the former headline)
+  laplace_sphere     33^3 Laplace sphere, FP64 and refined solve latency, oracle solve rate
+  batch              512 seeded small problems in one lock-step, graph-replayed batch
+  serve              Poisson arrivals into the continuous-batching server, p50/p99 latency
+  profile            129^3 matvecs only (for rocprofv3) plus a device copy of known size
+  profile_star       257^3 16-RHS FP32 sums only (for rocprofv3) plus the same copy
+  formulations       single- against double-layer formulation (iterations, time) at 129^3
+  particular         free-space against finite-grid (sine-transform) particular solution at 129^3
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -36,58 +43,61 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "LGF pair-interactions/s per BAE matvec; solves/s + p99 latency at rel err ≤1e-8"
-PEAK_FP32_VECTOR = 157.3   # TFLOP/s, MI355X published FP32 vector peak (packed FP32 included)
-PEAK_FP64_VECTOR = 78.6    # TFLOP/s
-# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one lane-operation per lane and
-# clock (an FMA is one operation; its two flops make 78.6 TFLOP/s non-packed)
+PEAK_FP32 = 157.3   # TFLOP/s, MI355X published FP32 peak (vector and matrix cores)
+PEAK_FP64 = 78.6    # TFLOP/s
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations per second
 PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# flops per pair (kernel value + one accumulate) by the kernel's pair classes
-FLOPS = {"fp32": {"near": 2, "far": 23, "far_q2": 23, "mixed_near": 2, "mixed_far": 23},
-         "fp64": {"near": 2, "far": 46, "far_q2": 46, "mixed_near": 2, "mixed_far": 46}}
-# VALU lane-operations per pair the evaluation needs, by pair class:
-#   table lookup: 3 |t - s| + min/median/max + index add (+ a shift in FP64) + accumulate
-#   far field, FP64 (q = 4): 3 differences, 3 squares, r^2, e2 and e3, the rsqrt estimate
-#     and its Newton step, the rho powers and invariants, the polynomial, the product with
-#     1/|n| and the accumulate
-#   far field, FP32 (q = 2): the packed binary16 (x, y) difference, the z difference and its
-#     square, two dot products (|n|^2 and n_y^2 - n_x^2), rsqrt, rho, the two ratios, the
-#     four-term polynomial, the product with 1/|n| and the accumulate
-#   mixed pairs: the chosen path plus the per-pair test
-OPS = {"fp32": {"near": 8, "far": 19, "far_q2": 15, "mixed_near": 10, "mixed_far": 24},
-       "fp64": {"near": 9, "far": 37, "far_q2": 37, "mixed_near": 11, "mixed_far": 42}}
+# Algorithmic flop convention (frozen with the oracle's far-field formula): a far-field
+# kernel value costs 32 flop (the corrected q = 3 expansion: 3 differences, 3 squares, 2 adds,
+# e2 4, e3 1, rsqrt 1, rho 1, x and y 4, the degree-8 polynomial 6, the degree-4 term 2, the
+# bracket 4, the final product 1); every (pair, right-hand side) adds its multiply-accumulate,
+# 2 flop.  Table lookups and global-table gathers generate their value without flops.
+# Compensation and index arithmetic are overhead, not counted.
+F_FAR = 32
+F_RHS = 2
 
 
-# HBM bytes per launch of the FP32 LGF-sum kernel on this workload, from rocprofv3 FETCH_SIZE
-# (x2.00) and WRITE_SIZE (x1.00) runs calibrated on 256 MiB copies
-# (profiles/lgf_sum_poisson_ellipsoid_129_counters.md); valid only for the kernel sources
-# it was measured on, identified by their hash.
-MEASURED_TRAFFIC = {"sources_sha256_16": "c8628c25f06815ff", "bytes": (12255.2 * 2.0 + 18518.7 * 1.0) * 1024}
-KERNEL_SOURCES = ("paper_2502_05507_amd/csrc/lgf_sum.hip", "paper_2502_05507_amd/csrc/lgf_device.hpp")
-
-
-def kernel_hash():
+def kernel_hash(files=("paper_2502_05507_amd/csrc/lgf_sum.hip", "paper_2502_05507_amd/csrc/lgf_device.hpp")):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in files:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()[:16]
+
+
+# Counter measurements of the dominant kernels (rocprofv3 --pmc runs of `bench.py --workload
+# profile_star` / `profile`, profiles/*_counters.md), valid only for the kernel sources they
+# were taken on (their hash): HBM bytes per launch (FETCH_SIZE x f + WRITE_SIZE x w, the
+# factors calibrated on copies of known size), VALU-issue and matrix-core-busy shares.
+MEASURED = {}
+
+
+def measured(key):
+    m = MEASURED.get(key)
+    return m if m and m["sources_sha256_16"] == kernel_hash() else None
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def flops_of(stats, prec, nrhs=1, gathers=False):
-    """Algorithmic flops of one launch: far-field pairs count their formula, table lookups
-    (near pairs; with sigma > 0 every pair) only the accumulate."""
-    per = {k: 2 for k in FLOPS[prec]} if gathers else FLOPS[prec]
-    tot = sum(stats[k] * per[k] for k in per)
-    return tot + (nrhs - 1) * 2 * sum(stats.values())
+def far_values(stats, prec, sigma0, far_ok):
+    """Kernel values of one launch that the far-field expansion generates (bae_sum_stats
+    classes): the FP32 far blocks, the FP64 far blocks at sigma = 0, and the far part of mixed
+    blocks when the sum has a far field."""
+    v = stats["far_q2"]
+    if prec == "fp64" and sigma0:
+        v += stats["far"]
+    if far_ok:
+        v += stats["mixed_far"]
+    return v
 
 
-def ops_of(stats, prec):
-    """VALU lane-operations of one launch (OPS per pair class)."""
-    return sum(stats[k] * OPS[prec][k] for k in OPS[prec])
+def flops_of(stats, prec, nrhs, sigma0, far_ok):
+    """Algorithmic flops of one launch of the LGF sum (F_FAR per far-field value, F_RHS per
+    pair and right-hand side)."""
+    pairs = sum(stats.values())
+    return F_FAR * far_values(stats, prec, sigma0, far_ok) + F_RHS * nrhs * pairs
 
 
 def time_applies(torch, ctx, q, v, prec, reps):
@@ -107,9 +117,10 @@ def time_applies(torch, ctx, q, v, prec, reps):
 
 
 def time_sum_kernel(torch, ctx, q, prec, reps, burst=20):
-    """Average duration of the LGF-sum kernel alone: HIP events on the launch stream around
-    1 and 1 + burst back-to-back launches (bae_lgf_sum_repeat, which forms the weights once
-    first); the difference over burst removes the weights launch and the event overhead."""
+    """Average duration of the LGF-sum kernel alone: HIP events on the launch stream (torch's
+    current stream, which the library launches on) around 1 and 1 + burst back-to-back
+    launches (bae_lgf_sum_repeat, which forms the weights once first); the difference over
+    burst removes the weights launch and the event overhead."""
     stream = torch.cuda.current_stream()
 
     def timed(n):
@@ -126,109 +137,163 @@ def time_sum_kernel(torch, ctx, q, prec, reps, burst=20):
     return float(np.median(per))
 
 
-def cpu_baseline(p, budget_s=12.0):
-    """The oracle's literal double-layer sum on a bounded sample of targets (1 thread)."""
+def cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores():
+    """Cores this process may use, capped at the 16 a one-GPU machine grants."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+# ----------------------------------------------------------------------------- CPU oracle
+_ORACLE = {}
+
+
+def _oracle_rows(task):
+    """Worker: the oracle's literal double-layer sum at a block of target rows, one density."""
+    from oracle import operators
+    rows, r = task
+    geo, G, Q = _ORACLE["geo"], _ORACLE["G"], _ORACLE["Q"]
+    return operators.double_layer(geo, G, Q[r], rows)
+
+
+def cpu_baseline_worker(workload, nrows, nrhs_all):
+    """Runs in a child process that never touches the GPU: the oracle (plain FP64 NumPy) on
+    `nrows` seeded target rows of the workload's matvec -- one density on one core, then
+    `nrhs_all` densities over every core (a fork pool).  Prints one JSON object."""
+    import multiprocessing as mp
+    import workloads as W
     from oracle import geometry, lgf, operators
-    g = geometry.from_problem(p)
-    G = lgf.LGFTable(g.max_offset(), p.sigma * p.h ** 2)
-    rng = np.random.default_rng(1234)
-    q = rng.standard_normal(len(g.gamma_minus))
-    T = operators.gamma_targets(g)
-    n_src = len(g.gamma_minus) + len(g.ext)
-    order = rng.permutation(len(T))
-    done = 0
+    p = {"helmholtz_star": lambda: W.helmholtz_star(257), "poisson_ellipsoid": lambda: W.poisson_ellipsoid(129)}[workload]()
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s and done < len(T):
-        blk = T[order[done:done + 64]]
-        operators.double_layer(g, G, q, blk)
-        done += len(blk)
-    dt = time.perf_counter() - t0
-    return {"value": done * n_src / dt, "unit": "pair-interactions/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} of {len(T)} gamma targets x {n_src} sources (literal double-layer sum, FP64, "
-                      f"NumPy single thread), {dt:.1f} s"}
+    geo = geometry.from_problem(p)
+    G = lgf.LGFTable(geo.max_offset(), p.sigma * p.h ** 2)
+    t_setup = time.perf_counter() - t0
+    rng = np.random.default_rng(2000)
+    T = operators.gamma_targets(geo)
+    rows = T[np.sort(rng.choice(len(T), size=min(nrows, len(T)), replace=False))]
+    cores = host_cores()
+    nrhs_all = nrhs_all if nrhs_all > 0 else cores
+    Q = rng.standard_normal((nrhs_all, len(geo.gamma_minus)))
+    n_src = len(geo.gamma_minus) + len(geo.ext)
+    _ORACLE.update(geo=geo, G=G, Q=Q)
+    blocks = [rows[i:i + 64] for i in range(0, len(rows), 64)]
+    t0 = time.perf_counter()
+    for b in blocks:
+        _oracle_rows((b, 0))
+    t1 = time.perf_counter() - t0
+    tasks = [(b, r) for r in range(nrhs_all) for b in blocks]
+    with mp.get_context("fork").Pool(cores) as pool:
+        t0 = time.perf_counter()
+        pool.map(_oracle_rows, tasks, chunksize=max(1, len(tasks) // (4 * cores)))
+        tall = time.perf_counter() - t0
+    print(json.dumps({"single": len(rows) * n_src / t1, "all": len(rows) * n_src * nrhs_all / tall, "nrhs": nrhs_all,
+                      "t_single": t1, "t_all": tall, "rows": len(rows), "targets": len(T), "sources": n_src,
+                      "cores": cores, "setup_s": t_setup}))
 
 
+def cpu_baseline(workload, nrows, nrhs_all):
+    """The oracle timed on this machine's host cores, in a child process (the benchmark's own
+    process holds the GPU), on a bounded sample of the workload's matvec."""
+    out = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker", workload,
+                          "--cpu-rows", str(nrows), "--cpu-rhs", str(nrhs_all)],
+                         capture_output=True, text=True, timeout=900)
+    if out.returncode != 0:
+        raise RuntimeError(f"cpu baseline worker failed: {out.stderr[-2000:]}")
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    return {"value": r["all"], "unit": "pair-interactions/s", "cores": r["cores"], "kind": "oracle",
+            "sample": f"{r['rows']} seeded of {r['targets']} gamma target rows x {r['sources']} sources x "
+                      f"{r['nrhs']} densities (literal double-layer sum, FP64 NumPy) on {r['cores']} processes: "
+                      f"{r['t_all']:.1f} s; one density on one core: {r['t_single']:.1f} s",
+            "single_core_value": r["single"], "nproc": os.cpu_count(), "cpu_model": cpu_model()}
+
+
+# ----------------------------------------------------------------------------- headline (257^3 star)
 def headline(args, torch, P, W):
     dev = torch.device("cuda:0")
-    p = W.poisson_ellipsoid(args.nodes)
+    nrhs = 16
+    p = W.helmholtz_star(args.star_nodes)
     t_setup = time.perf_counter()
-    ctx = P.Context.from_problem(p)
+    ctx = P.Context.from_problem(p, max_rhs=nrhs, max_krylov=200)
     xs, _, _ = ctx.boundary_points()
-    ctx.set_rhs(p.g(xs), p.f_grid())
+    G = torch.from_numpy(np.stack([p.g(xs, r) for r in range(nrhs)])).to(dev)
+    torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     z = ctx.sizes
-    pairs_mv = z["n_targets"] * z["n_sources"]
+    pairs_mv = z["n_targets"] * z["n_sources"] * nrhs
     log(f"setup {t_setup:.2f}s sizes {z}")
 
     tol = 1e-10
+
+    def step(prec):
+        ctx.set_rhs_device(G)
+        return ctx.solve(prec, tol=tol)
+
     for _ in range(args.warmup):
-        ctx.solve(P.SOLVE_FP32_REFINED, tol=tol)
+        step(P.SOLVE_FP32_REFINED)
     torch.cuda.synchronize()
     lat, pairs_total = [], 0
     t0 = time.perf_counter()
     for k in range(args.steps):
         s0 = time.perf_counter()
-        r = ctx.solve(P.SOLVE_FP32_REFINED, tol=tol)[0]
+        res = step(P.SOLVE_FP32_REFINED)
         lat.append(time.perf_counter() - s0)
-        pairs_total += (r["matvecs_fp64"] + r["matvecs_fp32"]) * pairs_mv
-        log(f"step {k}: {lat[-1] * 1e3:.1f} ms, iters {r['iterations']}, outer {r['outer_steps']}, "
-            f"relres {r['rel_residual_true']:.2e}")
+        pairs_total += (res[0]["matvecs_fp64"] + res[0]["matvecs_fp32"]) * pairs_mv
+        log(f"step {k}: {lat[-1] * 1e3:.0f} ms, iters {max(r['iterations'] for r in res)}, "
+            f"outer {res[0]['outer_steps']}, relres {max(r['rel_residual_true'] for r in res):.2e}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    refined = r
-    u32 = ctx.gamma_values()
+    refined = res
+    u32 = np.stack([ctx.gamma_values(r) for r in range(nrhs)])
 
-    ctx.solve(P.SOLVE_FP64, tol=tol)
     lat64 = []
-    for _ in range(max(2, args.steps // 3)):
+    for _ in range(args.fp64_steps):
         s0 = time.perf_counter()
-        r64 = ctx.solve(P.SOLVE_FP64, tol=tol)[0]
+        r64 = step(P.SOLVE_FP64)
         lat64.append(time.perf_counter() - s0)
-    u64 = ctx.gamma_values()
-    rel_err = float(np.linalg.norm(u32 - u64) / np.linalg.norm(u64))
+    u64 = np.stack([ctx.gamma_values(r) for r in range(nrhs)])
+    rel_err = float(max(np.linalg.norm(u32[r] - u64[r]) / np.linalg.norm(u64[r]) for r in range(nrhs)))
+    log(f"fp64: {np.median(lat64) * 1e3:.0f} ms iters {max(r['iterations'] for r in r64)}; "
+        f"refined vs fp64 rel err {rel_err:.2e}")
 
-    # Inputs starting in host memory: g at x* and f on the grid uploaded (set_rhs also forms
-    # the particular solution on the device), the refined solve, u_gamma read back.  Context
-    # set-up (point sets, closure, LGF table) is not repeated.  Reported beside `value`.
-    g_host, f_host = p.g(xs), p.f_grid()
-    host = []
-    for _ in range(3):
-        s0 = time.perf_counter()
-        ctx.set_rhs(g_host, f_host)
-        rh = ctx.solve(P.SOLVE_FP32_REFINED, tol=tol)[0]
-        ctx.gamma_values()
-        host.append(time.perf_counter() - s0)
-    t_host = float(np.median(host))
-    host_inclusive = {"ms_per_solve": t_host * 1e3,
-                      "pair_interactions_per_s": (rh["matvecs_fp64"] + rh["matvecs_fp32"]) * pairs_mv / t_host,
-                      "includes": "g (|gamma-| FP64) and f (n^3 FP64) uploaded from host memory, the particular "
-                                  "solution, the refined solve, u_gamma read back"}
-    log(f"fp64: {np.median(lat64) * 1e3:.1f} ms iters {r64['iterations']}; refined vs fp64 rel err {rel_err:.2e}")
-
-    q = torch.from_numpy(np.random.default_rng(5).standard_normal(z["n_gamma_minus"])).to(dev)
-    v = torch.empty(z["n_targets"], dtype=torch.float64, device=dev)
-    mv, roof, ops = {}, {}, {}
-    for name, prec in (("fp32", P.PREC_FP32), ("fp64", P.PREC_FP64)):
-        t_med = time_applies(torch, ctx, q, v, prec, args.matvec_reps)
-        t_sum = time_sum_kernel(torch, ctx, q, prec, max(3, args.matvec_reps // 4))
-        st = ctx.sum_stats(prec)
-        fl = flops_of(st, name)
-        mv[name] = {"median_ms": t_med * 1e3, "pairs_per_s": pairs_mv / t_med, "sum_kernel_ms": t_sum * 1e3,
-                    "tflops": fl / t_sum / 1e12, "tops": ops_of(st, name) / t_sum / 1e12, "pair_classes": st}
-        roof[name] = fl / t_sum / 1e12
-        ops[name] = ops_of(st, name) / t_sum / 1e12
-    traffic = MEASURED_TRAFFIC["bytes"] if (kernel_hash() == MEASURED_TRAFFIC["sources_sha256_16"]
-                                            and args.nodes == 129) else None
-    # The sum is bound by VALU issue: table lookups replace most of the far-field flops
-    # by integer index work, so the roofline counts lane-operations; the flop view follows.
-    roofline = {"bound": "alu", "achieved": ops["fp32"], "peak": PEAK_VALU_OPS,
-                "unit": "Top/s (VALU lane-operations, FMA = 1)", "frac": ops["fp32"] / PEAK_VALU_OPS,
-                "traffic": traffic,
-                "kernel": "lgf_sum_kernel<float,1> (HIP events around back-to-back launches of the sum alone)",
-                "ops_per_launch": ops_of(mv["fp32"]["pair_classes"], "fp32"),
-                "flops": {"achieved": roof["fp32"], "peak": PEAK_FP32_VECTOR, "unit": "TFLOP/s",
-                          "frac": roof["fp32"] / PEAK_FP32_VECTOR,
-                          "flops_per_launch": flops_of(mv["fp32"]["pair_classes"], "fp32")}}
+    # the dominant kernel: the FP32 16-RHS matrix-core sum, alone
+    q = torch.from_numpy(np.random.default_rng(6).standard_normal((nrhs, z["n_gamma_minus"]))).to(dev)
+    t_sum = time_sum_kernel(torch, ctx, q, P.PREC_FP32, 3, burst=5)
+    st32 = ctx.sum_stats(P.PREC_FP32)
+    far_ok = bool(z["far_field_fp32"])
+    fl = flops_of(st32, "fp32", nrhs, False, far_ok)
+    t_sum64 = time_sum_kernel(torch, ctx, q, P.PREC_FP64, 2, burst=3)
+    st64 = ctx.sum_stats(P.PREC_FP64)
+    fl64 = flops_of(st64, "fp64", nrhs, False, bool(z["far_field_fp64"]))
+    log(f"sum kernels: fp32 {t_sum * 1e3:.1f} ms, fp64 {t_sum64 * 1e3:.1f} ms")
+    meas = measured("lgf_sum_mfma_helmholtz_star_257")
+    roofline = {"bound": "mfma", "achieved": fl / t_sum / 1e12, "peak": PEAK_FP32, "unit": "TFLOP/s",
+                "frac": fl / t_sum / 1e12 / PEAK_FP32, "traffic": meas["bytes"] if meas else None,
+                "kernel": "lgf_sum_mfma_kernel<float> (FP32, 16 right-hand sides; HIP events around back-to-back "
+                          "launches of the sum alone)",
+                "kernel_ms": t_sum * 1e3, "flops_per_launch": fl,
+                "flop_convention": f"{F_FAR} per far-field kernel value + {F_RHS} per (pair, RHS)",
+                "pair_classes": st32,
+                "valu_issue_share": meas["valu_issue"] if meas else None,
+                "mfma_busy_share": meas["mfma_busy"] if meas else None}
 
     out = {
         "metric": METRIC,
@@ -241,30 +306,120 @@ def headline(args, torch, P, W):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 LGF sum + f64 refinement",
+        "dtype": "f32 (16-RHS matrix-core LGF sum) + f64 refinement",
         "data": "synthetic",
-        "config": {"workload": f"poisson_ellipsoid_{args.nodes}^3",
-                   "geometry": "ellipsoid (0.45,0.3,0.25) in unit cube", "h": p.h, "sigma": 0.0,
-                   "gamma_targets": z["n_targets"], "sources": z["n_sources"], "pairs_per_matvec": pairs_mv,
-                   "tol": tol},
-        "solves_per_s": args.steps / elapsed,
+        "config": {"workload": f"helmholtz_star_{args.star_nodes}^3_16rhs",
+                   "geometry": "star r=0.4(1+0.15 sin3t cos2p) in unit cube", "h": p.h, "kappa2": p.sigma,
+                   "rhs": nrhs, "gamma_targets": z["n_targets"], "sources": z["n_sources"],
+                   "pairs_per_matvec": pairs_mv, "tol": tol},
+        "solves_per_s": nrhs * args.steps / elapsed,
         "p50_ms": float(np.percentile(lat, 50) * 1e3),
         "p99_ms": float(np.percentile(lat, 99) * 1e3),
-        "refined": {"iterations": refined["iterations"], "outer_steps": refined["outer_steps"],
-                    "matvecs_fp32": refined["matvecs_fp32"], "matvecs_fp64": refined["matvecs_fp64"],
-                    "rel_residual": refined["rel_residual_true"], "rel_err_vs_fp64_gpu": rel_err},
-        "fp64_plain": {"solves_per_s": 1.0 / float(np.mean(lat64)), "p50_ms": float(np.percentile(lat64, 50) * 1e3),
-                       "p99_ms": float(np.percentile(lat64, 99) * 1e3), "iterations": r64["iterations"],
-                       "rel_residual": r64["rel_residual_true"]},
-        "matvec": mv,
+        "latency_unit": "one step: set_rhs_device + refined solve of all 16 right-hand sides",
+        "refined": {"iterations": max(r["iterations"] for r in refined), "outer_steps": refined[0]["outer_steps"],
+                    "matvecs_fp32": refined[0]["matvecs_fp32"], "matvecs_fp64": refined[0]["matvecs_fp64"],
+                    "max_rel_residual": max(r["rel_residual_true"] for r in refined),
+                    "max_rel_err_vs_fp64_gpu": rel_err},
+        "fp64_plain": {"solves_per_s": nrhs / float(np.mean(lat64)), "p50_ms": float(np.percentile(lat64, 50) * 1e3),
+                       "p99_ms": float(np.percentile(lat64, 99) * 1e3),
+                       "iterations": max(r["iterations"] for r in r64),
+                       "max_rel_residual": max(r["rel_residual_true"] for r in r64)},
         "roofline": roofline,
-        "fp64_sum": {"ops_frac": ops["fp64"] / PEAK_VALU_OPS, "flops_frac_of_fp64_peak": roof["fp64"] / PEAK_FP64_VECTOR},
+        "fp64_sum": {"kernel_ms": t_sum64 * 1e3, "tflops": fl64 / t_sum64 / 1e12,
+                     "frac_of_fp64_peak": fl64 / t_sum64 / 1e12 / PEAK_FP64, "pair_classes": st64},
         "setup_s": t_setup,
-        "host_inclusive": host_inclusive,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p)
     ctx.close()
+    if not args.no_extra:
+        out["poisson_ellipsoid_129"] = ellipsoid(args, torch, P, W, steps=5, warmup=2, extra=True)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline("helmholtz_star", args.cpu_rows, args.cpu_rhs)
+    return out
+
+
+def ellipsoid(args, torch, P, W, steps=None, warmup=None, extra=False):
+    """129^3 Poisson ellipsoid, one RHS: a step is set_rhs_box (f and g device-resident; the
+    particular solution by sine transforms) + the refined solve."""
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    dev = torch.device("cuda:0")
+    p = W.poisson_ellipsoid(args.nodes)
+    t_setup = time.perf_counter()
+    ctx = P.Context.from_problem(p)
+    xs, _, _ = ctx.boundary_points()
+    g = torch.from_numpy(p.g(xs)).to(dev)
+    f = torch.from_numpy(p.f_grid()).to(dev)
+    ctx.set_rhs_device(g, f, particular="box")
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    z = ctx.sizes
+    pairs_mv = z["n_targets"] * z["n_sources"]
+    tol = 1e-10
+
+    def step(prec):
+        ctx.set_rhs_device(g, f, particular="box")
+        return ctx.solve(prec, tol=tol)[0]
+
+    for _ in range(warmup):
+        step(P.SOLVE_FP32_REFINED)
+    torch.cuda.synchronize()
+    lat, pairs_total = [], 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s0 = time.perf_counter()
+        r = step(P.SOLVE_FP32_REFINED)
+        lat.append(time.perf_counter() - s0)
+        pairs_total += (r["matvecs_fp64"] + r["matvecs_fp32"]) * pairs_mv
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    u32 = ctx.gamma_values()
+    lat64 = []
+    for _ in range(max(2, steps // 3)):
+        s0 = time.perf_counter()
+        r64 = step(P.SOLVE_FP64)
+        lat64.append(time.perf_counter() - s0)
+    u64 = ctx.gamma_values()
+    rel_err = float(np.linalg.norm(u32 - u64) / np.linalg.norm(u64))
+    q = torch.from_numpy(np.random.default_rng(5).standard_normal(z["n_gamma_minus"])).to(dev)
+    v = torch.empty(z["n_targets"], dtype=torch.float64, device=dev)
+    mv = {}
+    for name, prec in (("fp32", P.PREC_FP32), ("fp64", P.PREC_FP64)):
+        t_med = time_applies(torch, ctx, q, v, prec, args.matvec_reps)
+        t_sum = time_sum_kernel(torch, ctx, q, prec, max(3, args.matvec_reps // 4))
+        st = ctx.sum_stats(prec)
+        fl = flops_of(st, name, 1, True, True)
+        mv[name] = {"median_ms": t_med * 1e3, "pairs_per_s": pairs_mv / t_med, "sum_kernel_ms": t_sum * 1e3,
+                    "tflops": fl / t_sum / 1e12,
+                    "frac": fl / t_sum / 1e12 / (PEAK_FP32 if name == "fp32" else PEAK_FP64), "pair_classes": st}
+    meas = measured("lgf_sum_poisson_ellipsoid_129")
+    roofline = {"bound": "alu", "achieved": mv["fp32"]["tflops"], "peak": PEAK_FP32, "unit": "TFLOP/s",
+                "frac": mv["fp32"]["frac"], "traffic": meas["bytes"] if meas else None,
+                "kernel": "lgf_sum_kernel<float,1> (HIP events around back-to-back launches of the sum alone)",
+                "flop_convention": f"{F_FAR} per far-field kernel value + {F_RHS} per pair",
+                "valu_issue_share": meas["valu_issue"] if meas else None}
+    ctx.close()
+    body = {"config": {"workload": f"poisson_ellipsoid_{args.nodes}^3", "h": p.h, "sigma": 0.0,
+                       "gamma_targets": z["n_targets"], "sources": z["n_sources"], "pairs_per_matvec": pairs_mv,
+                       "tol": tol},
+            "value": pairs_total / elapsed, "unit": "pair-interactions/s",
+            "ms_per_step": elapsed / steps * 1e3, "solves_per_s": steps / elapsed,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "latency_unit": "one step: set_rhs_device (box particular solution) + refined solve",
+            "refined": {"iterations": r["iterations"], "outer_steps": r["outer_steps"],
+                        "matvecs_fp32": r["matvecs_fp32"], "matvecs_fp64": r["matvecs_fp64"],
+                        "rel_residual": r["rel_residual_true"], "rel_err_vs_fp64_gpu": rel_err},
+            "fp64_plain": {"solves_per_s": 1.0 / float(np.mean(lat64)),
+                           "p50_ms": float(np.percentile(lat64, 50) * 1e3),
+                           "p99_ms": float(np.percentile(lat64, 99) * 1e3), "iterations": r64["iterations"]},
+            "matvec": mv, "roofline": roofline, "setup_s": t_setup}
+    if extra:
+        return body
+    out = {"metric": METRIC, "value": body.pop("value"), "unit": body.pop("unit"), "n_gpus": 1, "steps": steps,
+           "warmup": warmup, "ms_per_step": body.pop("ms_per_step"), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32 LGF sum + f64 refinement", "data": "synthetic",
+           "config": body.pop("config"), **body}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline("poisson_ellipsoid", args.cpu_rows, args.cpu_rhs)
     return out
 
 
@@ -344,35 +499,6 @@ def laplace_sphere(args, torch, P, W):
         X = np.concatenate(ctx.sets()[:2]) * p.h
         err = np.abs(ctx.gamma_values() - p.exact(*X.T)).max()
         return {"workload": "laplace_sphere_33^3", "sizes": ctx.sizes, **res, "max_err_vs_exact": float(err)}
-
-
-def helmholtz_star(args, torch, P, W):
-    p = W.helmholtz_star(args.star_nodes)
-    t0 = time.perf_counter()
-    with P.Context.from_problem(p, max_rhs=16, max_krylov=200) as ctx:
-        xs, _, _ = ctx.boundary_points()
-        G = np.stack([p.g(xs, r) for r in range(16)])
-        ctx.set_rhs(G)
-        t_setup = time.perf_counter() - t0
-        z = ctx.sizes
-        pairs_mv = z["n_targets"] * z["n_sources"] * 16
-        dev = torch.device("cuda:0")
-        q = torch.from_numpy(np.random.default_rng(6).standard_normal((16, z["n_gamma_minus"]))).to(dev)
-        v = torch.empty((16, z["n_targets"]), dtype=torch.float64, device=dev)
-        mv = {}
-        for name, prec in (("fp32", P.PREC_FP32), ("fp64", P.PREC_FP64)):
-            t_med = time_applies(torch, ctx, q, v, prec, 5)
-            mv[name] = {"median_ms": t_med * 1e3, "pair_rhs_per_s": pairs_mv / t_med}
-            log(f"star 16-RHS matvec {name}: {t_med * 1e3:.1f} ms")
-        s0 = time.perf_counter()
-        res = ctx.solve(P.SOLVE_FP32_REFINED, tol=1e-10)
-        t_solve = time.perf_counter() - s0
-        log(f"star solve {t_solve:.2f}s iters {res[0]['iterations']}")
-        return {"workload": f"helmholtz_star_{args.star_nodes}^3_16rhs", "sizes": z, "setup_s": t_setup,
-                "matvec": mv, "solve_s": t_solve, "iterations": res[0]["iterations"],
-                "outer_steps": res[0]["outer_steps"], "converged": all(r["converged"] for r in res),
-                "max_rel_residual": max(r["rel_residual_true"] for r in res),
-                "pair_rhs_per_s_in_solve": (res[0]["matvecs_fp32"] + res[0]["matvecs_fp64"]) * pairs_mv / t_solve}
 
 
 def resolved_problems(P, count, make):
@@ -478,23 +604,51 @@ def profile(args, torch, P, W):
     return {"workload": "profile", "copy_bytes_each_way": a.numel() * 8}
 
 
+def profile_star(args, torch, P, W):
+    """The 257^3 star's 16-RHS sums only: FP32 (matrix cores) then FP64 LGF-sum launches, then
+    the same 256 MiB device copy (the counter runs' calibration)."""
+    dev = torch.device("cuda:0")
+    p = W.helmholtz_star(args.star_nodes)
+    with P.Context.from_problem(p, max_rhs=16, max_krylov=8) as ctx:
+        z = ctx.sizes
+        q = torch.from_numpy(np.random.default_rng(6).standard_normal((16, z["n_gamma_minus"]))).to(dev)
+        for prec in (P.PREC_FP32, P.PREC_FP64):
+            ctx.lgf_sum_repeat(q, args.steps, prec)
+            torch.cuda.synchronize()
+            log(f"profile_star: {args.steps} sums done ({'fp32' if prec == P.PREC_FP32 else 'fp64'})")
+    a = torch.empty(1 << 25, dtype=torch.float64, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"workload": "profile_star", "copy_bytes_each_way": a.numel() * 8, "sizes": z}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--nodes", type=int, default=129, help="nodes per axis of the ellipsoid (h = 1/(nodes-1))")
-    ap.add_argument("--workload", default="poisson_ellipsoid",
-                    choices=["poisson_ellipsoid", "laplace_sphere", "helmholtz_star", "batch", "serve", "profile",
-                             "formulations", "particular"])
+    ap.add_argument("--workload", default="helmholtz_star",
+                    choices=["helmholtz_star", "poisson_ellipsoid", "laplace_sphere", "batch", "serve", "profile",
+                             "profile_star", "formulations", "particular"])
     ap.add_argument("--star-nodes", type=int, default=257)
+    ap.add_argument("--fp64-steps", type=int, default=1, help="plain FP64 solves timed beside the headline")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 129^3 ellipsoid beside the headline")
+    ap.add_argument("--cpu-rows", type=int, default=256, help="target rows of the CPU oracle sample")
+    ap.add_argument("--cpu-rhs", type=int, default=0, help="densities of the all-core sample (0: one per core)")
+    ap.add_argument("--cpu-baseline-worker", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--batch", type=int, default=512)
-    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--requests", type=int, default=500)
     ap.add_argument("--slots", type=int, default=64)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--matvec-reps", type=int, default=20)
     args = ap.parse_args()
+    if args.cpu_baseline_worker:        # child process of cpu_baseline: CPU only
+        cpu_baseline_worker(args.cpu_baseline_worker, args.cpu_rows, args.cpu_rhs)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
@@ -504,9 +658,9 @@ def main():
     import paper_2502_05507_amd as P
     import workloads as W
 
-    fn = {"poisson_ellipsoid": headline, "laplace_sphere": laplace_sphere, "helmholtz_star": helmholtz_star,
-          "formulations": formulations, "particular": particular,
-          "batch": batch, "serve": serve, "profile": profile}[args.workload]
+    fn = {"helmholtz_star": headline, "poisson_ellipsoid": ellipsoid, "laplace_sphere": laplace_sphere,
+          "formulations": formulations, "particular": particular, "batch": batch, "serve": serve,
+          "profile": profile, "profile_star": profile_star}[args.workload]
     print(json.dumps(fn(args, torch, P, W)))
 
 

@@ -64,6 +64,9 @@ extern "C" {
 #define BAE_LAYER_DOUBLE 0        /* double-layer formulation (Sec. 3.4 eq. "double_bae") */
 #define BAE_LAYER_SINGLE 1        /* single-layer formulation (Sec. 3.4)                 */
 
+#define BAE_PARTICULAR_FREE 0     /* u_p: the free-space volume potential (LGF sum)     */
+#define BAE_PARTICULAR_BOX 1      /* u_p: Algorithm 1's finite-grid G_h[chi_{M+} f]      */
+
 /* ------------------------------------------------------------------ structs */
 typedef struct bae_grid {
     int32_t n[3];        /* nodes per axis, in [5, 2049]                            */
@@ -85,6 +88,10 @@ typedef struct bae_options {   /* zero-initialise for defaults                  
     int32_t near_radius_fp32;  /* kernels (47 / 60 for sigma = 0, 46 / 59 otherwise)  */
     int32_t max_krylov;        /* Krylov basis capacity per RHS (default 400)       */
     int32_t max_rhs;           /* right-hand sides the context can hold (default 16) */
+    int32_t sum_wait_polls;    /* polls of each bounded wait in the LGF sum's work hand-off
+                                  before the sum gives up and the call reports BAE_ERR_HIP
+                                  (0: default 2^22, ~0.1 s; < 0: none, every wait gives up at
+                                  once -- for tests of that failure path)               */
 } bae_options;
 
 typedef struct bae_sizes {
@@ -123,6 +130,11 @@ typedef struct bae_solve_params {
                                   single layer S(m,n) = G(m - n) on gamma- sources
                                   (Sec. 3.4); the density, u_gamma and u are those of
                                   the chosen layer                                    */
+    const double* x0_dev;      /* initial densities [nrhs][|gamma-|] (device, FP64), or NULL
+                                  for x0 = 0 (the paper's choice, Sec. 4); GMRES then solves
+                                  A d = b - A x0 and returns x0 + d.  Read during the solve
+                                  (bae_solve: ordered after the null stream's work;
+                                  bae_solve_async: after its stream's)                 */
 } bae_solve_params;
 
 typedef struct bae_result {
@@ -192,6 +204,17 @@ int bae_set_rhs(bae_ctx* ctx, int32_t nrhs, const double* g_xstar, const double*
  * The context keeps u_p on the device (N^3 doubles per RHS, N = n - 2) for the grid solution.
  */
 int bae_set_rhs_box(bae_ctx* ctx, int32_t nrhs, const double* g_xstar, const double* f_grid);
+/*
+ * Device form of bae_set_rhs / bae_set_rhs_box, asynchronous on `stream`: g_dev
+ * [nrhs][|gamma-|] and f_dev [nrhs][n0 n1 n2] (or NULL for f = 0) are device FP64 arrays
+ * (e.g. torch tensors) that must stay valid until `stream` has passed this call's work.
+ * particular: BAE_PARTICULAR_FREE or BAE_PARTICULAR_BOX (as bae_set_rhs_box; cubic grid).
+ * Nothing is read back: a non-finite g or f is flagged on the device and the next solve
+ * fails with BAE_ERR_NONFINITE.  The first call with f on a context does one-time set-up
+ * (index maps, work list) on the host and the context's own stream.  Errors: BAE_ERR_ARG.
+ */
+int bae_set_rhs_device(bae_ctx* ctx, int32_t nrhs, const double* g_dev, const double* f_dev, int32_t particular,
+                       void* stream);
 /* u_p of right-hand side r on the whole grid (n0*n1*n2, k fastest; zero on the box boundary)
    after bae_set_rhs_box with f; caller-owned host buffer.  BAE_ERR_STATE otherwise. */
 int bae_get_particular(const bae_ctx* ctx, int32_t r, double* up_grid);
@@ -202,12 +225,33 @@ int bae_get_particular(const bae_ctx* ctx, int32_t r, double* up_grid);
  * Returns BAE_NOT_CONVERGED if any RHS missed the tolerance.
  */
 int bae_solve(bae_ctx* ctx, const bae_solve_params* params, bae_result* results);
-/* Outputs of the last solve, RHS r (host buffers): q_d (|gamma-|), u_gamma (|gamma|),
-   u on the grid (n0 n1 n2, NaN outside N+; needs compute_grid), residual history. */
+/* Outputs of the last solve, RHS r (or every RHS for r = -1, [nrhs][len]; host buffers):
+   q_d (|gamma-|), u_gamma (|gamma|), u on the grid (n0 n1 n2, NaN outside N+; needs
+   compute_grid), residual history (r >= 0 only). */
 int bae_get_density(const bae_ctx* ctx, int32_t r, double* q);
 int bae_get_gamma_values(const bae_ctx* ctx, int32_t r, double* u_gamma);
 int bae_get_solution(const bae_ctx* ctx, int32_t r, double* u_grid);
 int bae_get_history(const bae_ctx* ctx, int32_t r, double* hist, int32_t cap, int32_t* len);
+/*
+ * Asynchronous solve (Algorithm 1's solve step, as bae_solve): its device work is ordered
+ * after everything queued on `stream` so far (a PyTorch caller passes its current stream;
+ * no device synchronisation) and runs on the context's own stream, driven by a host thread
+ * of the context, and the call returns at once.  Argument errors are reported here; errors
+ * of the solve itself by bae_solve_wait.  Any other call on the context (set_rhs, getters,
+ * applies, another solve) first waits for the solve's host thread.
+ */
+int bae_solve_async(bae_ctx* ctx, const bae_solve_params* params, void* stream);
+/* done = 1 once the asynchronous solve has finished (or none is running), else 0; never blocks. */
+int bae_solve_poll(const bae_ctx* ctx, int32_t* done);
+/* Waits for the asynchronous solve, copies its results (nrhs entries, may be NULL) and makes
+   `stream` wait for every output of the solve on the device.  Returns the solve's status
+   (BAE_OK, BAE_NOT_CONVERGED or its error); BAE_ERR_STATE if no solve was started. */
+int bae_solve_wait(bae_ctx* ctx, void* stream, bae_result* results);
+/* Device forms of the getters, asynchronous on `stream`: RHS r, or every RHS for r = -1
+   ([nrhs][len]); q_dev |gamma-|, u_dev |gamma| or n0 n1 n2 doubles per RHS. */
+int bae_get_density_device(const bae_ctx* ctx, int32_t r, double* q_dev, void* stream);
+int bae_get_gamma_values_device(const bae_ctx* ctx, int32_t r, double* u_dev, void* stream);
+int bae_get_solution_device(const bae_ctx* ctx, int32_t r, double* u_dev, void* stream);
 
 /* ------------------------------------------------------------------ operators (hot path) */
 /*
@@ -283,12 +327,19 @@ int bae_batch_autotune(bae_batch* b, int32_t precision, int32_t* chosen);
  * (bae_get_density / bae_get_gamma_values / bae_get_history).
  */
 int bae_batch_solve(bae_batch* b, const bae_solve_params* params, int32_t use_graph, bae_result* results);
+/*
+ * Pair counts of the batched LGF sum (Sec. 3.2) summed over the batch's problems, in the
+ * classes of bae_sum_stats, as the batched kernel classifies them: its LDS table holds the
+ * general layout (radius 59 in FP32, 46 in FP64), so a problem's counts can differ from its
+ * solo ones.  Host computation; counts: 5 int64.  Errors: BAE_ERR_ARG.
+ */
+int bae_batch_sum_stats(const bae_batch* b, int32_t precision, int64_t* counts);
 int bae_batch_destroy(bae_batch* b);
 
 /* ------------------------------------------------------------------ serving (continuous batching) */
 typedef struct bae_server bae_server;
 /* Boundary data callback: g_out[i] = g(xyz[3i], xyz[3i+1], xyz[3i+2]) for i < count.  It is
-   called on the server's scheduler thread when a request is admitted. */
+   called on the server's set-up thread when a request is admitted. */
 typedef void (*bae_boundary_fn)(void* user, int64_t count, const double* xyz, double* g_out);
 
 typedef struct bae_server_options {
@@ -321,18 +372,23 @@ typedef struct bae_server_stats {
 } bae_server_stats;
 
 /*
- * Start a server: a scheduler thread that admits requests in arrival order when a slot
- * is free and their device footprint (computed from the classified geometry, before any
- * allocation) fits in hbm_budget, adds them to the running batch at the next step,
- * advances all running requests together (one launch per GMRES phase), and retires
- * finished ones, releasing their slot and memory.  A request larger than the whole
- * budget fails with BAE_ERR_ADMISSION.
+ * Start a server: a set-up thread admits requests in arrival order when a slot is free and
+ * their device footprint (computed from the classified geometry, before any allocation)
+ * fits in hbm_budget, and builds each one's context (point sets, LGF table, boundary data
+ * through its callback) on the context's own stream while the batch runs; a scheduler
+ * thread adds set-up requests to the running batch at the next step, advances all running
+ * requests together (one launch per GMRES phase), and retires finished ones, releasing
+ * their slot and memory.  A request larger than the whole budget fails with
+ * BAE_ERR_ADMISSION; any other set-up failure fails that request only.
  */
 int bae_server_create(const bae_server_options* opt, bae_server** out);
 int bae_server_submit(bae_server* s, const bae_request* req, uint64_t* ticket);
 /* Block until the request is done (timeout_s < 0: no limit).  Returns its status
    (BAE_OK / BAE_NOT_CONVERGED) or the error that failed it. */
 int bae_server_wait(bae_server* s, uint64_t ticket, double timeout_s, bae_result* res, bae_request_info* info);
+/* The request's state without blocking: 0 waiting, 1 admitted (set-up or running), 2 done,
+   3 failed (its error then comes from bae_server_wait).  Errors: BAE_ERR_ARG (unknown ticket). */
+int bae_server_poll(bae_server* s, uint64_t ticket, int32_t* state);
 /* Copy a done request's density (|gamma-|) and u_gamma (|gamma|) out and forget it. */
 int bae_server_fetch(bae_server* s, uint64_t ticket, double* q, int64_t q_cap, double* u_gamma, int64_t u_cap);
 int bae_server_stats_get(bae_server* s, bae_server_stats* out);

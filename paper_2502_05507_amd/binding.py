@@ -17,6 +17,7 @@ OK, NOT_CONVERGED = 0, 1
 PREC_FP64, PREC_FP32 = 0, 1
 SOLVE_FP64, SOLVE_FP32_REFINED = 0, 1
 LAYER_DOUBLE, LAYER_SINGLE = 0, 1
+PARTICULAR = {"free": 0, "box": 1}
 KINDS = {"sphere": 1, "ellipsoid": 2, "torus": 3, "star": 4, "sampled": 5}
 
 
@@ -31,7 +32,7 @@ class LevelSet(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("device", C.c_int32), ("near_radius_fp64", C.c_int32), ("near_radius_fp32", C.c_int32),
-                ("max_krylov", C.c_int32), ("max_rhs", C.c_int32)]
+                ("max_krylov", C.c_int32), ("max_rhs", C.c_int32), ("sum_wait_polls", C.c_int32)]
 
 
 class Sizes(C.Structure):
@@ -49,7 +50,7 @@ class Sizes(C.Structure):
 class SolveParams(C.Structure):
     _fields_ = [("precision", C.c_int32), ("tol", C.c_double), ("maxit", C.c_int32), ("inner_tol", C.c_double),
                 ("max_outer", C.c_int32), ("compute_grid", C.c_int32), ("recycle_dim", C.c_int32),
-                ("formulation", C.c_int32)]
+                ("formulation", C.c_int32), ("x0_dev", C.c_void_p)]
 
 
 class Result(C.Structure):
@@ -130,6 +131,13 @@ def load_library():
         "bae_get_gamma_values": (C.c_int, [_P, C.c_int32, _P]),
         "bae_get_solution": (C.c_int, [_P, C.c_int32, _P]),
         "bae_get_history": (C.c_int, [_P, C.c_int32, _P, C.c_int32, C.POINTER(C.c_int32)]),
+        "bae_set_rhs_device": (C.c_int, [_P, C.c_int32, _P, _P, C.c_int32, _P]),
+        "bae_solve_async": (C.c_int, [_P, C.POINTER(SolveParams), _P]),
+        "bae_solve_poll": (C.c_int, [_P, C.POINTER(C.c_int32)]),
+        "bae_solve_wait": (C.c_int, [_P, _P, _P]),
+        "bae_get_density_device": (C.c_int, [_P, C.c_int32, _P, _P]),
+        "bae_get_gamma_values_device": (C.c_int, [_P, C.c_int32, _P, _P]),
+        "bae_get_solution_device": (C.c_int, [_P, C.c_int32, _P, _P]),
         "bae_apply_double_layer": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P]),
         "bae_apply_operator": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P]),
         "bae_apply_single_layer": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P]),
@@ -140,10 +148,12 @@ def load_library():
         "bae_batch_autotune": (C.c_int, [_P, C.c_int32, _P]),
         "bae_batch_solve": (C.c_int, [_P, C.POINTER(SolveParams), C.c_int32, _P]),
         "bae_batch_destroy": (C.c_int, [_P]),
+        "bae_batch_sum_stats": (C.c_int, [_P, C.c_int32, _P]),
         "bae_server_create": (C.c_int, [C.POINTER(ServerOptions), C.POINTER(_P)]),
         "bae_server_submit": (C.c_int, [_P, C.POINTER(Request), C.POINTER(C.c_uint64)]),
         "bae_server_wait": (C.c_int, [_P, C.c_uint64, C.c_double, _P, _P]),
         "bae_server_fetch": (C.c_int, [_P, C.c_uint64, _P, C.c_int64, _P, C.c_int64]),
+        "bae_server_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(C.c_int32)]),
         "bae_server_stats_get": (C.c_int, [_P, C.POINTER(ServerStats)]),
         "bae_server_destroy": (C.c_int, [_P]),
     }
@@ -192,7 +202,7 @@ class Context:
     """One geometry / grid / sigma (Algorithm 1 set-up), owning its device state."""
 
     def __init__(self, n, h, origin, sigma, kind, center=(0.0, 0.0, 0.0), params=(), phi=None,
-                 device=0, max_krylov=0, max_rhs=0):
+                 device=0, max_krylov=0, max_rhs=0, sum_wait_polls=0):
         lib = load_library()
         g = Grid((C.c_int32 * 3)(*[int(v) for v in n]), (C.c_double * 3)(*[float(v) for v in origin]),
                  float(h), float(sigma))
@@ -203,7 +213,7 @@ class Context:
         ls = LevelSet(KINDS[kind], (C.c_double * 3)(*[float(v) for v in center]),
                       (C.c_double * 8)(*[float(v) for v in p[:8]]),
                       self._phi.ctypes.data_as(C.POINTER(C.c_double)) if self._phi is not None else None)
-        opt = Options(int(device), 0, 0, int(max_krylov), int(max_rhs))
+        opt = Options(int(device), 0, 0, int(max_krylov), int(max_rhs), int(sum_wait_polls))
         h_ = _P()
         _check(lib.bae_create(C.byref(g), C.byref(ls), C.byref(opt), C.byref(h_)))
         self._h = h_
@@ -264,21 +274,71 @@ class Context:
         _check(fn(self._h, nrhs, _ptr(g), _ptr(f)))
         self.nrhs = nrhs
 
+    def set_rhs_device(self, g, f=None, particular="free", stream=None):
+        """Device form of set_rhs on torch tensors g [nrhs][|gamma-|] and f [nrhs][n0 n1 n2] (float64),
+        asynchronous on `stream` (default: torch's current stream)."""
+        nrhs = 1 if g.dim() == 1 else g.shape[0]
+        assert g.is_contiguous() and g.numel() == nrhs * self.sizes["n_gamma_minus"]
+        if f is not None:
+            assert f.is_contiguous() and f.numel() == nrhs * int(np.prod(self.n))
+        _check(load_library().bae_set_rhs_device(self._h, nrhs, _dptr(g), _dptr(f) if f is not None else None,
+                                                 PARTICULAR[particular], _stream(stream)))
+        self.nrhs = nrhs
+
     def particular(self, r=0):
         """u_p on the grid after set_rhs(..., particular="box") with f."""
         u = np.empty(self.n)
         _check(load_library().bae_get_particular(self._h, r, _ptr(u)))
         return u
 
+    @staticmethod
+    def _params(precision, tol, maxit, inner_tol, max_outer, compute_grid, recycle_dim, formulation, x0):
+        return SolveParams(int(precision), float(tol), int(maxit), float(inner_tol), int(max_outer),
+                           1 if compute_grid else 0, int(recycle_dim), int(formulation),
+                           C.c_void_p(x0.data_ptr()) if x0 is not None else None)
+
     def solve(self, precision=SOLVE_FP64, tol=1e-10, maxit=0, inner_tol=0.0, max_outer=0, compute_grid=False,
-              recycle_dim=0, formulation=0):
-        """formulation: LAYER_DOUBLE (default) or LAYER_SINGLE (Sec. 3.4)."""
-        p = SolveParams(int(precision), float(tol), int(maxit), float(inner_tol), int(max_outer),
-                        1 if compute_grid else 0, int(recycle_dim), int(formulation))
+              recycle_dim=0, formulation=0, x0=None):
+        """formulation: LAYER_DOUBLE (default) or LAYER_SINGLE (Sec. 3.4); x0: optional device tensor of
+        initial densities [nrhs][|gamma-|]."""
+        p = self._params(precision, tol, maxit, inner_tol, max_outer, compute_grid, recycle_dim, formulation, x0)
         res = (Result * self.nrhs)()
         rc = load_library().bae_solve(self._h, C.byref(p), res)
         _check(rc, allow_not_converged=True)
         return [r.as_dict() for r in res]
+
+    def solve_async(self, precision=SOLVE_FP64, tol=1e-10, maxit=0, inner_tol=0.0, max_outer=0, compute_grid=False,
+                    recycle_dim=0, formulation=0, x0=None, stream=None):
+        """bae_solve_async: ordered after `stream` (default: torch's current stream), returns at once."""
+        p = self._params(precision, tol, maxit, inner_tol, max_outer, compute_grid, recycle_dim, formulation, x0)
+        self._x0 = x0      # kept alive until the solve is collected
+        _check(load_library().bae_solve_async(self._h, C.byref(p), _stream(stream)))
+
+    def solve_poll(self):
+        d = C.c_int32(0)
+        _check(load_library().bae_solve_poll(self._h, C.byref(d)))
+        return bool(d.value)
+
+    def solve_wait(self, stream=None):
+        res = (Result * self.nrhs)()
+        rc = load_library().bae_solve_wait(self._h, _stream(stream), res)
+        self._x0 = None
+        _check(rc, allow_not_converged=True)
+        return [r.as_dict() for r in res]
+
+    def _device_out(self, fn, out, r, length, stream):
+        count = length * (self.nrhs if r < 0 else 1)
+        assert out.is_contiguous() and out.numel() == count and out.element_size() == 8
+        _check(fn(self._h, int(r), _dptr(out), _stream(stream)))
+
+    def density_device(self, out, r=-1, stream=None):
+        self._device_out(load_library().bae_get_density_device, out, r, self.sizes["n_gamma_minus"], stream)
+
+    def gamma_values_device(self, out, r=-1, stream=None):
+        self._device_out(load_library().bae_get_gamma_values_device, out, r, self.sizes["n_targets"], stream)
+
+    def solution_device(self, out, r=-1, stream=None):
+        self._device_out(load_library().bae_get_solution_device, out, r, int(np.prod(self.n)), stream)
 
     def density(self, r=0):
         q = np.empty(self.sizes["n_gamma_minus"])
@@ -360,11 +420,18 @@ class Batch:
         return {"blocks_per_chunk": int(chosen[0]), "grid_multiplier": int(chosen[1])}
 
     def solve(self, precision=SOLVE_FP64, tol=1e-10, maxit=0, inner_tol=0.0, max_outer=0, use_graph=True):
-        p = SolveParams(int(precision), float(tol), int(maxit), float(inner_tol), int(max_outer), 0, 0, 0)
+        p = SolveParams(int(precision), float(tol), int(maxit), float(inner_tol), int(max_outer), 0, 0, 0, None)
         res = (Result * len(self.contexts))()
         rc = load_library().bae_batch_solve(self._h, C.byref(p), 1 if use_graph else 0, res)
         _check(rc, allow_not_converged=True)
         return [r.as_dict() for r in res]
+
+    def sum_stats(self, precision=PREC_FP32):
+        """Pair counts of the batched LGF sum by its own block classification (bae_batch_sum_stats)."""
+        c = np.zeros(5, np.int64)
+        _check(load_library().bae_batch_sum_stats(self._h, precision, _ptr(c)))
+        return {"near": int(c[0]), "far": int(c[1]), "far_q2": int(c[2]), "mixed_near": int(c[3]),
+                "mixed_far": int(c[4])}
 
     def close(self):
         if getattr(self, "_h", None):
@@ -431,6 +498,12 @@ class Server:
         rc = load_library().bae_server_wait(self._h, ticket, float(timeout), C.byref(r), C.byref(info))
         _check(rc, allow_not_converged=True)
         return r.as_dict(), info.as_dict()
+
+    def poll(self, ticket):
+        """0 waiting, 1 admitted, 2 done, 3 failed (never blocks)."""
+        st = C.c_int32(0)
+        _check(load_library().bae_server_poll(self._h, ticket, C.byref(st)))
+        return st.value
 
     def fetch(self, ticket, n_gamma_minus, n_targets):
         q = np.empty(n_gamma_minus)

@@ -52,7 +52,8 @@ using namespace bae;
 
 namespace bae {
 
-void PlanBuf::build(const PointSet& T, const PointSet& S, const SumTables& tabs, hipStream_t st) {
+void PlanBuf::build(const PointSet& T, const PointSet& S, const SumTables& tabs, int32_t* err_dev, uint32_t polls,
+                    hipStream_t st) {
     std::vector<uint32_t> host;
     plan_sum(T, S, tabs, plan, host);
     upload(items, host, st);
@@ -60,7 +61,24 @@ void PlanBuf::build(const PointSet& T, const PointSet& S, const SumTables& tabs,
     launch_fill_int(counter.as<int32_t>(), 2, 0, st);
     plan.items = items.as<uint32_t>();
     plan.counter = counter.as<unsigned long long>();
+    plan.err = err_dev;
+    plan.wait_polls = polls;
     BAE_HIP_CHECK(hipStreamSynchronize(st));
+}
+
+void join_job(bae_ctx* c) {
+    if (c->job.th.joinable()) c->job.th.join();
+}
+
+void check_sum_error(bae_ctx* c) {
+    if (!c->err_host || __atomic_load_n(c->err_host, __ATOMIC_ACQUIRE) == 0) return;
+    BAE_HIP_CHECK(hipSetDevice(c->device));
+    BAE_HIP_CHECK(hipDeviceSynchronize());   // no sum of this context is still in flight
+    launch_fill_int(c->plan.counter.as<int32_t>(), 2, 0, c->stream);
+    BAE_HIP_CHECK(hipStreamSynchronize(c->stream));
+    __atomic_store_n(c->err_host, 0, __ATOMIC_RELEASE);
+    throw Error{BAE_ERR_HIP, "LGF sum: a bounded wait of the work hand-off gave up; the results of the calls "
+                             "since the last check are incomplete"};
 }
 
 static void apply_lgf(bae_ctx* c, const PointSet& T, const PointSet& S, const void* w, int nrhs, int prec,
@@ -240,9 +258,16 @@ static GmresOut gmres(bae_ctx* c, const double* r0, int nrhs, int prec, double t
     const bool lagged = nrhs == 1;
     const double pairs = (double)c->nT * (double)c->nS * nrhs;
     const int check = pairs > 2e7 ? 1 : (pairs > 2e6 ? 2 : 6);
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    struct Events {   // released on every exit, errors included
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~Events() {
+            for (auto& x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } evs;
+    hipEvent_t* ev = evs.e;
     if (lagged)
-        for (auto& e : ev) BAE_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        for (int i = 0; i < 2; ++i) BAE_HIP_CHECK(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
     // Step k: LGF sum of the weights of V[k] (formed by step k-1's closing launch, or here
     // for k = 0), closure into the work vector, classical Gram-Schmidt, then one closing
     // launch that scales the work vector into V[k+1], forms the next weights from it and
@@ -283,6 +308,7 @@ static GmresOut gmres(bae_ctx* c, const double* r0, int nrhs, int prec, double t
             BAE_HIP_CHECK(hipEventRecord(ev[k & 1], st));
             if (k >= 1) {
                 BAE_HIP_CHECK(hipEventSynchronize(ev[(k - 1) & 1]));
+                check_sum_error(c);
                 if (c->pinned_flags[(k - 1) & 1]) {
                     (*matvecs)--;   // the LGF sum of iteration k was skipped
                     break;
@@ -292,6 +318,7 @@ static GmresOut gmres(bae_ctx* c, const double* r0, int nrhs, int prec, double t
         } else if ((k + 1) % check == 0 || k + 1 == m) {
             BAE_HIP_CHECK(hipMemcpyAsync(c->pinned_flags, K.done, sizeof(int32_t) * nrhs, hipMemcpyDeviceToHost, st));
             BAE_HIP_CHECK(hipStreamSynchronize(st));
+            check_sum_error(c);
             bool all = true;
             for (int r = 0; r < nrhs; ++r) all &= c->pinned_flags[r] != 0;
             if (all) {
@@ -300,8 +327,6 @@ static GmresOut gmres(bae_ctx* c, const double* r0, int nrhs, int prec, double t
             }
         }
     }
-    for (auto& e : ev)
-        if (e) (void)hipEventDestroy(e);
     // host back substitution R y = g for each RHS
     std::vector<int32_t> kd(nrhs), dn(nrhs);
     BAE_HIP_CHECK(hipMemcpyAsync(kd.data(), K.kdone, sizeof(int32_t) * nrhs, hipMemcpyDeviceToHost, st));
@@ -312,6 +337,7 @@ static GmresOut gmres(bae_ctx* c, const double* r0, int nrhs, int prec, double t
     BAE_HIP_CHECK(hipMemcpyAsync(g.data(), K.g, sizeof(double) * g.size(), hipMemcpyDeviceToHost, st));
     BAE_HIP_CHECK(hipMemcpyAsync(hs.data(), K.hist, sizeof(double) * hs.size(), hipMemcpyDeviceToHost, st));
     BAE_HIP_CHECK(hipStreamSynchronize(st));
+    check_sum_error(c);
     GmresOut out;
     std::vector<double> y((size_t)K.m * nrhs, 0.0);
     for (int r = 0; r < nrhs; ++r) {
@@ -385,6 +411,7 @@ static std::vector<double> residual(bae_ctx* c, int nrhs, const std::vector<doub
     BAE_HIP_CHECK(hipMemcpyAsync(c->r.p, c->b.p, sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, st));
     launch_axpby(-1.0, c->tmp.as<double>(), n, 1.0, c->r.as<double>(), n, n, nrhs, st);
     std::vector<double> rn = host_norms(c, c->r.as<double>(), nrhs, st);
+    check_sum_error(c);
     for (int i = 0; i < nrhs; ++i) rn[i] = bn[i] > 0 ? rn[i] / bn[i] : 0.0;
     return rn;
 }
@@ -407,13 +434,14 @@ static void ensure_mplus(bae_ctx* c) {
 static void lgf_sum_to(bae_ctx* c, const PointSet& T, const PointSet& S, const double* w, int nrhs,
                        const int32_t* pos, double* out, int64_t ldo, double scale, hipStream_t st) {
     PlanBuf plan;
-    plan.build(T, S, c->tabs, st);
+    plan.build(T, S, c->tabs, c->err_dev, c->wait_polls, st);
     DevMem p;
     const int64_t cap = (int64_t)plan.plan.chunks * T.count * nrhs;
     p.alloc(sizeof(double) * cap);
     int used = lgf_sum_launch(T, S, w, nrhs, BAE_PREC_FP64, c->tabs, plan.plan, p.as<double>(), cap, c->sum_grid, st);
     launch_reduce_scatter(p.as<double>(), used, T.count, pos, out, ldo, nrhs, scale, st);
     BAE_HIP_CHECK(hipStreamSynchronize(st));
+    check_sum_error(c);
 }
 
 int guard(const std::function<void()>& fn) {
@@ -527,6 +555,7 @@ bae_ctx* create_context(const bae_grid& gridv, const bae_options* opt, Geometry&
         upload(c->cl_tq, ctq, st);
         upload(c->cl_tp, ctp, st);
         upload(c->cl_t, G.t, st);
+        upload(c->partner_dev, G.partner, st);
         c->cl = Closure{c->ngm, c->cl_tq.as<int32_t>(), c->cl_tp.as<int32_t>(), c->cl_t.as<double>()};
 
         // LGF table: for sigma = 0 one table of the FP32 LDS radius shared by all contexts
@@ -554,7 +583,18 @@ bae_ctx* create_context(const bae_grid& gridv, const bae_options* opt, Geometry&
             c->tabs.yukawa32 = c->tabs.yukawa_err <= kYukawaTolerance;
         }
         c->sum_grid = lgf_sum_grid(c->device);
-        c->plan.build(c->T.ps, c->S.ps, c->tabs, st);
+        BAE_HIP_CHECK(hipHostMalloc((void**)&c->pinned_flags, sizeof(int32_t) * (2 * c->max_rhs + 2),
+                                    hipHostMallocMapped | hipHostMallocCoherent));
+        BAE_HIP_CHECK(hipHostGetDevicePointer((void**)&c->flags_dev, c->pinned_flags, 0));
+        std::memset(c->pinned_flags, 0, sizeof(int32_t) * (2 * c->max_rhs + 2));
+        c->err_host = c->pinned_flags + 2 * c->max_rhs;
+        c->err_dev = c->flags_dev + 2 * c->max_rhs;
+        c->bad_host = c->pinned_flags + 2 * c->max_rhs + 1;
+        c->bad_dev = c->flags_dev + 2 * c->max_rhs + 1;
+        BAE_HIP_CHECK(hipEventCreateWithFlags(&c->rhs_ev, hipEventDisableTiming));
+        c->wait_polls = c->opt.sum_wait_polls > 0 ? (uint32_t)c->opt.sum_wait_polls
+                        : c->opt.sum_wait_polls < 0 ? 0u : kWaitPolls;
+        c->plan.build(c->T.ps, c->S.ps, c->tabs, c->err_dev, c->wait_polls, st);
 
         // work buffers
         const int mr = c->max_rhs;
@@ -592,11 +632,9 @@ bae_ctx* create_context(const bae_grid& gridv, const bae_options* opt, Geometry&
         c->ycoef.alloc(sizeof(double) * m * mr);
         for (DevMem* d : {&c->b, &c->x, &c->r, &c->tmp}) d->alloc(sizeof(double) * n * mr);
         c->up_gamma.alloc(sizeof(double) * c->nT * mr);
+        c->gdev.alloc(sizeof(double) * n * mr);
         c->u_gamma.alloc(sizeof(double) * c->nT * mr);
         c->vsum.alloc(sizeof(double) * c->nT * mr);
-        BAE_HIP_CHECK(hipHostMalloc((void**)&c->pinned_flags, sizeof(int32_t) * 2 * mr,
-                                    hipHostMallocMapped | hipHostMallocCoherent));
-        BAE_HIP_CHECK(hipHostGetDevicePointer((void**)&c->flags_dev, c->pinned_flags, 0));
         // batched / served solves: idle until started (done = 1, k = 0)
         c->ctl.alloc(sizeof(Ctl));
         const Ctl idle{0, 0, 0.0};
@@ -607,6 +645,46 @@ bae_ctx* create_context(const bae_grid& gridv, const bae_options* opt, Geometry&
         return c.release();
 }
 
+
+void classify_pairs(const bae_ctx* c, bool fp32, int tab_r, bool far_ok, int far_gap, int64_t* cnt) {
+    const PointSet& T = c->T.ps;
+    const PointSet& S = c->S.ps;
+    const int64_t nt = T.count, ns = S.count, nblk = S.nblk;
+    // the kernels' classification, per (wavefront of 64 targets, source block)
+    for (int64_t w0 = 0; w0 < nt; w0 += 64) {
+        const int64_t w1 = std::min(nt, w0 + 64);
+        int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {0, 0, 0};
+        for (int64_t i = w0; i < w0 + 64; ++i) {
+            const int64_t t = std::min(i, nt - 1);
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = std::min(lo[a], T.hq[3 * t + a]);
+                hi[a] = std::max(hi[a], T.hq[3 * t + a]);
+            }
+        }
+        for (int64_t b = 0; b < nblk; ++b) {
+            const int32_t* bb = &S.hbox[6 * b];
+            int gap = 0, span = 0;
+            for (int a = 0; a < 3; ++a) {
+                gap = std::max(gap, std::max(bb[a] - hi[a], lo[a] - bb[3 + a]));
+                span = std::max(span, std::max(bb[3 + a] - lo[a], hi[a] - bb[a]));
+            }
+            const int64_t s0 = b * kSourceBlock, s1 = std::min(ns, s0 + kSourceBlock);
+            const int64_t pairs = (w1 - w0) * (s1 - s0);
+            switch (block_class(gap, span, tab_r, far_ok, fp32, far_gap)) {
+                case kClassTable: cnt[0] += pairs; break;
+                case kClassFar: case kClassGather: cnt[1] += pairs; break;
+                case kClassFar2: cnt[2] += pairs; break;
+                default:
+                    for (int64_t t = w0; t < w1; ++t)
+                        for (int64_t s = s0; s < s1; ++s) {
+                            int m = 0;
+                            for (int a = 0; a < 3; ++a) m = std::max(m, std::abs(T.hq[3 * t + a] - S.hq[3 * s + a]));
+                            cnt[m <= kQuant * tab_r ? 3 : 4]++;
+                        }
+            }
+        }
+    }
+}
 
 // Device bytes create_context will allocate for this geometry (admission control).
 int64_t estimate_context_bytes(const Geometry& G, double s, const bae_options* opt) {
@@ -676,7 +754,9 @@ int bae_create(const bae_grid* grid, const bae_levelset* ls, const bae_options* 
 
 int bae_destroy(bae_ctx* c) {
     if (!c) return BAE_OK;
+    join_job(c);
     (void)hipSetDevice(c->device);
+    if (c->rhs_ev) (void)hipEventDestroy(c->rhs_ev);
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->pinned_flags) (void)hipHostFree(c->pinned_flags);
     hipStream_t st = c->stream;
@@ -738,102 +818,382 @@ int bae_get_boundary_points(const bae_ctx* c, double* xstar, int32_t* partner, d
     });
 }
 
-// b = g(x*) - Phi [u_p]_gamma with the particular solution u_p of chi_{M+} f: the free-space
-// volume potential (an LGF sum over the M+ sources), or with `box` the finite-grid solve
-// G_h[chi_{M+} f] of Algorithm 1 (box.hip), kept on the device for the grid solution.
-static void set_rhs_impl(bae_ctx* c, int32_t nrhs, const double* g_xstar, const double* f_grid, bool box) {
-    if (!c || !g_xstar) throw Error{BAE_ERR_ARG, "null argument"};
-    if (nrhs < 1 || nrhs > c->max_rhs) throw Error{BAE_ERR_ARG, "nrhs out of range"};
+// ------------------------------------------------------------------ right-hand side
+// Lazy per-context device maps: the linear grid index of every M+ point (internal Mp order)
+// and of every gamma- node (lexicographic).
+static void ensure_lin(bae_ctx* c) {
+    ensure_mplus(c);
     const Geometry& G = c->geo;
-    if (box && f_grid && (G.n[0] != G.n[1] || G.n[1] != G.n[2]))
-        throw Error{BAE_ERR_ARG, "the box particular solution needs a cubic grid"};
-    BAE_HIP_CHECK(hipSetDevice(c->device));
+    const int64_t nm = c->Mp.ps.count;
+    if ((int64_t)c->mp_lin.size() == nm && c->gm_lin_dev.p) return;
+    std::vector<int32_t> pts;
+    pts.reserve(nm);
+    for (int i = 0; i < G.n[0]; ++i)
+        for (int j = 0; j < G.n[1]; ++j)
+            for (int k = 0; k < G.n[2]; ++k)
+                if (G.inside[((int64_t)i * G.n[1] + j) * G.n[2] + k])
+                    pts.push_back((int32_t)(((int64_t)i * G.n[1] + j) * G.n[2] + k));
+    c->mp_lin.resize(nm);
+    for (int64_t a = 0; a < nm; ++a) c->mp_lin[a] = pts[c->Mp.perm[a]];
+    std::vector<int32_t> gl(c->ngm);
+    for (int64_t q = 0; q < c->ngm; ++q) {
+        const int32_t* v = &G.gm[3 * q];
+        gl[q] = (int32_t)(((int64_t)v[0] * G.n[1] + v[1]) * G.n[2] + v[2]);
+    }
+    upload(c->mp_lin_dev, c->mp_lin, c->stream);
+    upload(c->gm_lin_dev, gl, c->stream);
+    BAE_HIP_CHECK(hipStreamSynchronize(c->stream));
+}
+
+// Lazy set-up of the box particular solution: the DST-I matrix, scratch, and the interior
+// index of every target and of every M+ point.
+static void ensure_box(bae_ctx* c) {
+    const Geometry& G = c->geo;
+    const int N = G.n[0] - 2;
+    if (c->box_N == N) return;
     hipStream_t st = c->stream;
-    const int64_t n = c->ngm, N3 = (int64_t)G.n[0] * G.n[1] * G.n[2];
-    for (int64_t i = 0; i < n * nrhs; ++i)
-        if (!std::isfinite(g_xstar[i])) throw Error{BAE_ERR_NONFINITE, "boundary data not finite"};
-    std::vector<double> bh(g_xstar, g_xstar + n * nrhs);
-    c->has_f = f_grid != nullptr;
-    c->particular_box = false;
-    if (c->has_f) {
-        for (int64_t i = 0; i < N3 * nrhs; ++i)
-            if (!std::isfinite(f_grid[i])) throw Error{BAE_ERR_NONFINITE, "source term not finite"};
-        ensure_mplus(c);
-        const int64_t nm = c->Mp.ps.count;
-        if ((int64_t)c->mp_lin.size() != nm) {
-            // linear grid index of each internal M+ point (once per context)
-            std::vector<int32_t> pts;
-            pts.reserve(nm);
-            for (int i = 0; i < G.n[0]; ++i)
-                for (int j = 0; j < G.n[1]; ++j)
-                    for (int k = 0; k < G.n[2]; ++k)
-                        if (G.inside[((int64_t)i * G.n[1] + j) * G.n[2] + k])
-                            pts.push_back((int32_t)(((int64_t)i * G.n[1] + j) * G.n[2] + k));
-            c->mp_lin.resize(nm);
-            for (int64_t a = 0; a < nm; ++a) c->mp_lin[a] = pts[c->Mp.perm[a]];
-        }
-        const std::vector<int32_t>& lin = c->mp_lin;
-        const double h2 = G.h * G.h;
-        if (box) {
-            const int N = G.n[0] - 2;
-            const int64_t nn = (int64_t)N * N * N;
-            auto interior = [&](int64_t l) {   // grid index -> interior index
-                const int64_t i = l / ((int64_t)G.n[1] * G.n[2]), j = (l / G.n[2]) % G.n[1], k = l % G.n[2];
-                return (int32_t)(((i - 1) * N + (j - 1)) * N + (k - 1));
-            };
-            if (c->box_N != N) {
-                c->box_S.alloc(sizeof(double) * N * N);
-                box_dst_matrix(N, c->box_S.as<double>(), st);
-                c->box_tmp.alloc(sizeof(double) * nn);
-                std::vector<int32_t> tidx(c->nT), midx(nm);
-                for (int64_t t = 0; t < c->nT; ++t) {
-                    const int32_t* v = t < c->ngp ? &G.gp[3 * t] : &G.gm[3 * (t - c->ngp)];
-                    tidx[t] = (int32_t)(((int64_t)(v[0] - 1) * N + (v[1] - 1)) * N + (v[2] - 1));
-                }
-                for (int64_t a = 0; a < nm; ++a) midx[a] = interior(lin[a]);
-                upload(c->box_tidx, tidx, st);
-                upload(c->box_mpidx, midx, st);
-                BAE_HIP_CHECK(hipStreamSynchronize(st));   // tidx, midx leave scope
-                c->box_N = N;
-            }
-            if (c->box_u.bytes < sizeof(double) * nn * nrhs) c->box_u.alloc(sizeof(double) * nn * nrhs);
-            // h^2 f at the M+ points only crosses the bus; the device places it in the zeroed grid
-            std::vector<double> wfh(nm * nrhs);
-            for (int r = 0; r < nrhs; ++r)
-                for (int64_t a = 0; a < nm; ++a) wfh[r * nm + a] = h2 * f_grid[r * N3 + lin[a]];
-            upload(c->wf, wfh, st);
-            launch_fill(c->box_u.as<double>(), nn * nrhs, 0.0, st);
-            box_scatter(c->wf.as<double>(), nm, c->box_mpidx.as<int32_t>(), nm, c->box_u.as<double>(), nn, nrhs, st);
-            for (int r = 0; r < nrhs; ++r)
-                box_solve(c->box_S.as<double>(), c->box_u.as<double>() + r * nn, c->box_tmp.as<double>(), N, c->s, st);
-            launch_gather(c->box_u.as<double>(), nn, c->box_tidx.as<int32_t>(), c->nT, c->up_gamma.as<double>(),
-                          c->nT, nrhs, 1.0, st);
-            c->particular_box = true;
-        } else {
-            const int64_t nmp = c->Mp.ps.padded;
-            std::vector<double> wfh(nmp * nrhs, 0.0);
-            for (int r = 0; r < nrhs; ++r)
-                for (int64_t a = 0; a < nm; ++a) wfh[r * nmp + a] = h2 * f_grid[r * N3 + lin[a]];
-            upload(c->wf, wfh, st);
-            lgf_sum_to(c, c->T.ps, c->Mp.ps, c->wf.as<double>(), nrhs, c->t_pos.as<int32_t>(),
-                       c->up_gamma.as<double>(), c->nT, 1.0, st);
-        }
-        std::vector<double> up(c->nT * nrhs);
-        BAE_HIP_CHECK(hipMemcpyAsync(up.data(), c->up_gamma.p, sizeof(double) * up.size(), hipMemcpyDeviceToHost, st));
-        BAE_HIP_CHECK(hipStreamSynchronize(st));
+    const int64_t nn = (int64_t)N * N * N;
+    c->box_S.alloc(sizeof(double) * N * N);
+    box_dst_matrix(N, c->box_S.as<double>(), st);
+    c->box_tmp.alloc(sizeof(double) * nn);
+    const int64_t nm = c->Mp.ps.count;
+    auto interior = [&](int64_t l) {   // grid index -> interior index
+        const int64_t i = l / ((int64_t)G.n[1] * G.n[2]), j = (l / G.n[2]) % G.n[1], k = l % G.n[2];
+        return (int32_t)(((i - 1) * N + (j - 1)) * N + (k - 1));
+    };
+    std::vector<int32_t> tidx(c->nT), midx(nm);
+    for (int64_t t = 0; t < c->nT; ++t) {
+        const int32_t* v = t < c->ngp ? &G.gp[3 * t] : &G.gm[3 * (t - c->ngp)];
+        tidx[t] = (int32_t)(((int64_t)(v[0] - 1) * N + (v[1] - 1)) * N + (v[2] - 1));
+    }
+    for (int64_t a = 0; a < nm; ++a) midx[a] = interior(c->mp_lin[a]);
+    upload(c->box_tidx, tidx, st);
+    upload(c->box_mpidx, midx, st);
+    BAE_HIP_CHECK(hipStreamSynchronize(st));   // tidx, midx leave scope
+    c->box_N = N;
+}
+
+// Lazy work list and partial-sum buffer of the (gamma targets, M+ sources) LGF sum that
+// forms the free-space particular solution.
+static void ensure_plan_mp(bae_ctx* c) {
+    if (c->plan_mp.items.p) return;
+    c->plan_mp.build(c->T.ps, c->Mp.ps, c->tabs, c->err_dev, c->wait_polls, c->stream);
+    c->part_mp.alloc(sizeof(double) * (int64_t)c->plan_mp.plan.chunks * c->nT * c->max_rhs);
+}
+
+// The device part of the right-hand side, on stream st: with f (h^2 f at the M+ points
+// already in c->wf, [nrhs][Mp padded]) the particular solution u_p on gamma -- the free-space
+// volume potential (LGF sum over the M+ sources) or, with `box`, Algorithm 1's finite-grid
+// G_h[chi_{M+} f] (box.hip) -- then b = g - Phi u_p (Sec. 3.4) from g (device, [nrhs][ngm]).
+static void rhs_on_device(bae_ctx* c, int nrhs, const double* g, int64_t ldg, bool has_f, bool box, hipStream_t st) {
+    const int64_t nmp = c->Mp.ps.padded;
+    if (has_f && box) {
+        const int N = c->box_N;
+        const int64_t nn = (int64_t)N * N * N, nm = c->Mp.ps.count;
+        launch_fill(c->box_u.as<double>(), nn * nrhs, 0.0, st);
+        box_scatter(c->wf.as<double>(), nmp, c->box_mpidx.as<int32_t>(), nm, c->box_u.as<double>(), nn, nrhs, st);
         for (int r = 0; r < nrhs; ++r)
-            for (int64_t q = 0; q < n; ++q) {
-                const double t = G.t[q];
-                bh[r * n + q] -= (1.0 - t) * up[r * c->nT + c->ngp + q] + t * up[r * c->nT + G.partner[q]];
-            }
+            box_solve(c->box_S.as<double>(), c->box_u.as<double>() + r * nn, c->box_tmp.as<double>(), N, c->s, st);
+        launch_gather(c->box_u.as<double>(), nn, c->box_tidx.as<int32_t>(), c->nT, c->up_gamma.as<double>(), c->nT,
+                      nrhs, 1.0, st);
+    } else if (has_f) {
+        const int used = lgf_sum_launch(c->T.ps, c->Mp.ps, c->wf.as<double>(), nrhs, BAE_PREC_FP64, c->tabs,
+                                        c->plan_mp.plan, c->part_mp.as<double>(),
+                                        (int64_t)c->plan_mp.plan.chunks * c->nT * c->max_rhs, c->sum_grid, st);
+        launch_reduce_scatter(c->part_mp.as<double>(), used, c->nT, c->t_pos.as<int32_t>(), c->up_gamma.as<double>(),
+                              c->nT, nrhs, 1.0, st);
     } else {
         launch_fill(c->up_gamma.as<double>(), c->nT * nrhs, 0.0, st);
     }
-    BAE_HIP_CHECK(hipMemcpyAsync(c->b.p, bh.data(), sizeof(double) * bh.size(), hipMemcpyHostToDevice, st));
-    BAE_HIP_CHECK(hipStreamSynchronize(st));
+    launch_rhs(g, ldg, has_f ? c->up_gamma.as<double>() : nullptr, c->nT, c->partner_dev.as<int32_t>(),
+               c->cl_t.as<double>(), c->ngp, c->ngm, c->b.as<double>(), c->ngm, nrhs, c->bad_dev, st);
+    BAE_HIP_CHECK(hipEventRecord(c->rhs_ev, st));
     c->nrhs = nrhs;
+    c->has_f = has_f;
+    c->particular_box = has_f && box;
     c->rhs_ready = true;
     c->solved = false;
+    c->has_grid = false;
+}
+
+static void check_rhs_args(bae_ctx* c, int32_t nrhs, const void* g, const void* f, bool box) {
+    if (!c || !g) throw Error{BAE_ERR_ARG, "null argument"};
+    if (nrhs < 1 || nrhs > c->max_rhs) throw Error{BAE_ERR_ARG, "nrhs out of range"};
+    const Geometry& G = c->geo;
+    if (box && f && (G.n[0] != G.n[1] || G.n[1] != G.n[2]))
+        throw Error{BAE_ERR_ARG, "the box particular solution needs a cubic grid"};
+}
+
+// Host inputs: validated here, h^2 f gathered at the M+ points on the host (only those cross
+// the bus), g staged on the device, then the device part on the context's stream.
+static void set_rhs_impl(bae_ctx* c, int32_t nrhs, const double* g_xstar, const double* f_grid, bool box) {
+    check_rhs_args(c, nrhs, g_xstar, f_grid, box);
+    join_job(c);
+    BAE_HIP_CHECK(hipSetDevice(c->device));
+    hipStream_t st = c->stream;
+    const Geometry& G = c->geo;
+    const int64_t n = c->ngm, N3 = (int64_t)G.n[0] * G.n[1] * G.n[2];
+    for (int64_t i = 0; i < n * nrhs; ++i)
+        if (!std::isfinite(g_xstar[i])) throw Error{BAE_ERR_NONFINITE, "boundary data not finite"};
+    if (f_grid) {
+        for (int64_t i = 0; i < N3 * nrhs; ++i)
+            if (!std::isfinite(f_grid[i])) throw Error{BAE_ERR_NONFINITE, "source term not finite"};
+        ensure_lin(c);
+        if (box) ensure_box(c);
+        else ensure_plan_mp(c);
+        const int64_t nm = c->Mp.ps.count, nmp = c->Mp.ps.padded;
+        std::vector<double> wfh(nmp * nrhs, 0.0);
+        const double h2 = G.h * G.h;
+        for (int r = 0; r < nrhs; ++r)
+            for (int64_t a = 0; a < nm; ++a) wfh[r * nmp + a] = h2 * f_grid[r * N3 + c->mp_lin[a]];
+        if (c->wf.bytes < sizeof(double) * wfh.size()) c->wf.alloc(sizeof(double) * nmp * c->max_rhs);
+        BAE_HIP_CHECK(hipMemcpyAsync(c->wf.p, wfh.data(), sizeof(double) * wfh.size(), hipMemcpyHostToDevice, st));
+        if (box) {
+            const int64_t nn = (int64_t)c->box_N * c->box_N * c->box_N;
+            if (c->box_u.bytes < sizeof(double) * nn * nrhs) c->box_u.alloc(sizeof(double) * nn * nrhs);
+        }
+        BAE_HIP_CHECK(hipStreamSynchronize(st));   // wfh leaves scope
+    }
+    BAE_HIP_CHECK(hipMemcpyAsync(c->gdev.p, g_xstar, sizeof(double) * n * nrhs, hipMemcpyHostToDevice, st));
+    rhs_on_device(c, nrhs, c->gdev.as<double>(), n, f_grid != nullptr, box, st);
+    BAE_HIP_CHECK(hipStreamSynchronize(st));
+}
+
+// Device inputs, on the caller's stream: nothing is read back, so non-finite values are
+// flagged on the device and reported by the next solve.
+static void set_rhs_device_impl(bae_ctx* c, int32_t nrhs, const double* g_dev, const double* f_dev, int32_t particular,
+                                hipStream_t st) {
+    if (particular != BAE_PARTICULAR_FREE && particular != BAE_PARTICULAR_BOX)
+        throw Error{BAE_ERR_ARG, "unknown particular-solution kind"};
+    const bool box = particular == BAE_PARTICULAR_BOX;
+    check_rhs_args(c, nrhs, g_dev, f_dev, box);
+    join_job(c);
+    BAE_HIP_CHECK(hipSetDevice(c->device));
+    if (f_dev) {
+        // one-time set-up (host work and uploads on the context's stream) before any of the
+        // caller's work is touched
+        ensure_lin(c);
+        if (box) ensure_box(c);
+        else ensure_plan_mp(c);
+        const int64_t nmp = c->Mp.ps.padded;
+        if (c->wf.bytes < sizeof(double) * nmp * nrhs) c->wf.alloc(sizeof(double) * nmp * c->max_rhs);
+        if (box) {
+            const int64_t nn = (int64_t)c->box_N * c->box_N * c->box_N;
+            if (c->box_u.bytes < sizeof(double) * nn * nrhs) c->box_u.alloc(sizeof(double) * nn * nrhs);
+        }
+        const Geometry& G = c->geo;
+        const int64_t N3 = (int64_t)G.n[0] * G.n[1] * G.n[2];
+        launch_finite_check(f_dev, N3, N3, nrhs, c->bad_dev, st);
+        launch_fill(c->wf.as<double>(), nmp * nrhs, 0.0, st);
+        launch_gather(f_dev, N3, c->mp_lin_dev.as<int32_t>(), c->Mp.ps.count, c->wf.as<double>(), nmp, nrhs,
+                      G.h * G.h, st);
+    }
+    rhs_on_device(c, nrhs, g_dev, c->ngm, f_dev != nullptr, box, st);
+}
+
+// u on the grid (Algorithm 1's last step, Sec. 2.1 eq. "discrete_green"): u = u_p + D q on
+// M+ by the LGF sum at the M+ targets, u_gamma on gamma-, NaN elsewhere; assembled on the
+// device in c->ugrid ([nrhs][n0 n1 n2]).
+static void grid_solution(bae_ctx* c, int nrhs, hipStream_t st) {
+    const Geometry& G = c->geo;
+    ensure_lin(c);
+    const int64_t nm = c->Mp.ps.count, n = c->ngm;
+    const int64_t N3 = (int64_t)G.n[0] * G.n[1] * G.n[2];
+    DevMem um;
+    um.alloc(sizeof(double) * nm * nrhs);
+    launch_weights(*c->Bop, c->x.as<double>(), n, c->w.p, c->S.ps.padded, nrhs, BAE_PREC_FP64, st);
+    lgf_sum_to(c, c->Mp.ps, c->S.ps, c->w.as<double>(), nrhs, nullptr, um.as<double>(), nm, 1.0, st);
+    if (c->has_f) {
+        DevMem up;
+        up.alloc(sizeof(double) * nm * nrhs);
+        if (c->particular_box) {   // the finite-grid u_p is known at every node
+            const int64_t nn = (int64_t)c->box_N * c->box_N * c->box_N;
+            launch_gather(c->box_u.as<double>(), nn, c->box_mpidx.as<int32_t>(), nm, up.as<double>(), nm, nrhs, 1.0,
+                          st);
+        } else {
+            lgf_sum_to(c, c->Mp.ps, c->Mp.ps, c->wf.as<double>(), nrhs, nullptr, up.as<double>(), nm, 1.0, st);
+        }
+        launch_axpby(1.0, up.as<double>(), nm, 1.0, um.as<double>(), nm, nm, nrhs, st);
+    }
+    if (c->ugrid.bytes < sizeof(double) * N3 * nrhs) c->ugrid.alloc(sizeof(double) * N3 * nrhs);
+    launch_fill(c->ugrid.as<double>(), N3 * nrhs, NAN, st);
+    launch_scatter(um.as<double>(), nm, c->mp_lin_dev.as<int32_t>(), nm, c->ugrid.as<double>(), N3, nrhs, st);
+    launch_scatter(c->u_gamma.as<double>() + c->ngp, c->nT, c->gm_lin_dev.as<int32_t>(), n, c->ugrid.as<double>(), N3,
+                   nrhs, st);
+    BAE_HIP_CHECK(hipStreamSynchronize(st));   // um, up leave scope
+}
+
+// ------------------------------------------------------------------ solve
+static void check_solve_args(const bae_ctx* c, const bae_solve_params* p) {
+    if (!c || !p) throw Error{BAE_ERR_ARG, "null argument"};
+    if (!c->rhs_ready) throw Error{BAE_ERR_STATE, "bae_set_rhs must precede bae_solve"};
+    if (p->precision != BAE_SOLVE_FP64 && p->precision != BAE_SOLVE_FP32_REFINED)
+        throw Error{BAE_ERR_ARG, "unknown solve precision"};
+    if (!(p->tol > 0.0)) throw Error{BAE_ERR_ARG, "tol must be > 0"};
+    if (p->formulation != BAE_LAYER_DOUBLE && p->formulation != BAE_LAYER_SINGLE)
+        throw Error{BAE_ERR_ARG, "unknown layer formulation"};
+}
+
+// The solve of Algorithm 1 on the context's stream (which the caller has already ordered
+// after its own work): GMRES (FP64, or FP64 refinement around FP32-sum GMRES) from x0 = 0 or
+// the given densities, then u_gamma and, if asked, u on the grid.  Returns BAE_OK or
+// BAE_NOT_CONVERGED; throws Error.
+static int solve_impl(bae_ctx* c, const bae_solve_params* p, bae_result* res) {
+    check_solve_args(c, p);
+    BAE_HIP_CHECK(hipSetDevice(c->device));
+    hipStream_t st = c->stream;
+    // the layer potential of this solve (Sec. 3.4): every operator call below, the grid
+    // solution included, forms its source weights through this map
+    const LayerScope layer(c, p->formulation);
+    const auto t0 = std::chrono::steady_clock::now();
+    const int nrhs = c->nrhs;
+    const int64_t n = c->ngm;
+    const int maxit = p->maxit > 0 ? std::min(p->maxit, c->K.m) : c->K.m;
+    c->hist.assign(nrhs, {});
+    c->solved = false;
+    c->has_grid = false;
+    int64_t mv64 = 0, mv32 = 0;
+    BAE_HIP_CHECK(hipStreamWaitEvent(st, c->rhs_ev, 0));   // the right-hand side's device work
+    std::vector<double> bn = host_norms(c, c->b.as<double>(), nrhs, st);
+    if (__atomic_exchange_n(c->bad_host, 0, __ATOMIC_ACQ_REL))
+        throw Error{BAE_ERR_NONFINITE, "boundary data or source term not finite"};
+    std::vector<int> iters(nrhs, 0), conv(nrhs, 0), outer(nrhs, 0);
+    std::vector<double> est(nrhs, 0.0), relres;
+    bool dq_in_vsum = false;   // the last operator call was the FP64 residual of the final q
+    const bool warm = p->x0_dev != nullptr;
+    if (warm) {
+        BAE_HIP_CHECK(hipMemcpyAsync(c->x.p, p->x0_dev, sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, st));
+        launch_finite_check(c->x.as<double>(), n, n, nrhs, c->bad_dev, st);
+    } else {
+        launch_fill(c->x.as<double>(), n * nrhs, 0.0, st);
+    }
+    if (p->precision == BAE_SOLVE_FP64) {
+        // from x0: GMRES on A d = b - A x0, x = x0 + d
+        if (warm) {
+            relres = residual(c, nrhs, bn, st, &mv64);
+            if (__atomic_exchange_n(c->bad_host, 0, __ATOMIC_ACQ_REL))
+                throw Error{BAE_ERR_NONFINITE, "initial densities not finite"};
+        }
+        std::vector<int> skip;
+        bool all = false;
+        if (warm) {
+            skip.assign(nrhs, 0);
+            all = true;
+            for (int r = 0; r < nrhs; ++r) {
+                skip[r] = relres[r] <= p->tol;
+                all &= skip[r] != 0;
+            }
+            dq_in_vsum = true;
+        }
+        if (!all) {   // (a warm start that already meets tol needs no iteration)
+            GmresOut g = gmres(c, warm ? c->r.as<double>() : c->b.as<double>(), nrhs, BAE_PREC_FP64, p->tol, maxit,
+                               skip, c->x.as<double>(), warm, st, &mv64);
+            for (int r = 0; r < nrhs; ++r) {
+                iters[r] = g.iters[r];
+                est[r] = g.last_est[r];
+                conv[r] = g.converged[r];
+            }
+            relres = residual(c, nrhs, bn, st, &mv64);
+            dq_in_vsum = true;
+        }
+        for (int r = 0; r < nrhs; ++r) conv[r] = conv[r] || relres[r] <= p->tol;
+    } else {
+        // inner tolerance of outer step k: just enough to reach tol from the current
+        // residual, but never below the floor where the FP32 operator's own error (~1e-6
+        // relative) makes further inner iterations useless
+        const double floor_tol = p->inner_tol > 0 ? p->inner_tol : 1e-6;
+        const int max_outer = p->max_outer > 0 ? p->max_outer : 8;
+        // recycling costs a few host round trips per outer step: worth it once a matvec
+        // is long (1e8 pair interactions, ~50 us), not for the smallest problems
+        const bool long_matvec = (double)c->nT * (double)c->nS * nrhs >= 1e8;
+        const int recycle_cap = p->recycle_dim < 0   ? 0
+                                : p->recycle_dim > 0 ? p->recycle_dim
+                                                     : (long_matvec ? kRecycleDefault : 0);
+        Recycle rc;
+        if (warm) {
+            relres = residual(c, nrhs, bn, st, &mv64);   // r = b - A64 x0
+            if (__atomic_exchange_n(c->bad_host, 0, __ATOMIC_ACQ_REL))
+                throw Error{BAE_ERR_NONFINITE, "initial densities not finite"};
+            dq_in_vsum = true;
+        } else {
+            BAE_HIP_CHECK(hipMemcpyAsync(c->r.p, c->b.p, sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, st));
+            relres.assign(nrhs, 1.0);
+            for (int r = 0; r < nrhs; ++r) relres[r] = bn[r] > 0 ? 1.0 : 0.0;
+        }
+        for (int o = 0; o < max_outer; ++o) {
+            std::vector<int> skip(nrhs, 0);
+            bool all = true;
+            double worst = 0.0;
+            for (int r = 0; r < nrhs; ++r) {
+                skip[r] = relres[r] <= p->tol;
+                all &= skip[r] != 0;
+                if (!skip[r]) worst = std::max(worst, relres[r]);
+            }
+            if (all) break;
+            const double inner = std::min(0.1, std::max(floor_tol, 0.5 * p->tol / worst));
+            // with a recycled space: its part of the residual first, then GMRES on the
+            // rest to the same absolute target (tolerance relative to what is left)
+            double gtol = inner;
+            std::vector<double> rscale(relres);
+            if (rc.p > 0) {
+                recycle_project(c, rc, nrhs, skip, c->x.as<double>(), c->r.as<double>(), st);
+                const std::vector<double> rn = host_norms(c, c->r.as<double>(), nrhs, st);
+                double ratio = 1e300;
+                for (int r = 0; r < nrhs; ++r) {
+                    if (skip[r]) continue;
+                    rscale[r] = bn[r] > 0 ? rn[r] / bn[r] : 0.0;
+                    if (rn[r] > 0) ratio = std::min(ratio, relres[r] * bn[r] / rn[r]);
+                }
+                gtol = ratio < 1e300 ? std::min(0.5, inner * ratio) : inner;
+            } else {
+                for (int r = 0; r < nrhs; ++r) rscale[r] = relres[r];
+            }
+            GmresOut g = gmres(c, c->r.as<double>(), nrhs, BAE_PREC_FP32, gtol, maxit, skip, c->x.as<double>(), true,
+                               st, &mv32, rc.p > 0 ? &rc : nullptr);
+            for (int r = 0; r < nrhs; ++r) {
+                iters[r] += g.iters[r];
+                if (!skip[r]) {
+                    outer[r]++;
+                    est[r] = g.last_est[r] * rscale[r];
+                }
+            }
+            if (o == 0 && recycle_cap > 0) build_recycle(c, nrhs, skip, recycle_cap, rc, st);
+            relres = residual(c, nrhs, bn, st, &mv64);
+            dq_in_vsum = true;
+        }
+        for (int r = 0; r < nrhs; ++r) conv[r] = relres[r] <= p->tol;
+    }
+    // u_gamma = D q + u_p on gamma.  The last call above is the FP64 residual of the final
+    // q, whose operator left D q at every target (internal order) in vsum: scattering it
+    // saves a double-layer evaluation.
+    if (dq_in_vsum && c->cl.n > 0)
+        launch_reduce_scatter(c->vsum.as<double>(), 1, c->nT, c->t_pos.as<int32_t>(), c->u_gamma.as<double>(), c->nT,
+                              nrhs, 1.0, st);
+    else
+        double_layer(c, c->x.as<double>(), n, c->u_gamma.as<double>(), c->nT, nrhs, BAE_PREC_FP64, st);
+    launch_axpby(1.0, c->up_gamma.as<double>(), c->nT, 1.0, c->u_gamma.as<double>(), c->nT, c->nT, nrhs, st);
+    if (p->compute_grid) grid_solution(c, nrhs, st);
+    BAE_HIP_CHECK(hipStreamSynchronize(st));
+    check_sum_error(c);
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int status = BAE_OK;
+    for (int r = 0; r < nrhs; ++r) {
+        if (!conv[r]) status = BAE_NOT_CONVERGED;
+        if (res) {
+            res[r].status = conv[r] ? BAE_OK : BAE_NOT_CONVERGED;
+            res[r].iterations = iters[r];
+            res[r].outer_steps = outer[r];
+            res[r].converged = conv[r];
+            res[r].rel_residual_est = est[r];
+            res[r].rel_residual_true = relres[r];
+            res[r].seconds = secs;
+            res[r].matvecs_fp64 = mv64;
+            res[r].matvecs_fp32 = mv32;
+        }
+    }
+    c->solved = true;
+    c->has_grid = p->compute_grid != 0;
+    return status;
 }
 
 int bae_set_rhs(bae_ctx* c, int32_t nrhs, const double* g_xstar, const double* f_grid) {
@@ -844,11 +1204,20 @@ int bae_set_rhs_box(bae_ctx* c, int32_t nrhs, const double* g_xstar, const doubl
     return guard([&] { set_rhs_impl(c, nrhs, g_xstar, f_grid, true); });
 }
 
-int bae_get_particular(const bae_ctx* c, int32_t r, double* up_grid) {
+int bae_set_rhs_device(bae_ctx* c, int32_t nrhs, const double* g_dev, const double* f_dev, int32_t particular,
+                       void* stream) {
+    return guard([&] { set_rhs_device_impl(c, nrhs, g_dev, f_dev, particular, (hipStream_t)stream); });
+}
+
+int bae_get_particular(const bae_ctx* cc, int32_t r, double* up_grid) {
     return guard([&] {
-        if (!c || !up_grid) throw Error{BAE_ERR_ARG, "null argument"};
+        if (!cc || !up_grid) throw Error{BAE_ERR_ARG, "null argument"};
+        bae_ctx* c = const_cast<bae_ctx*>(cc);
+        join_job(c);
         if (!c->particular_box) throw Error{BAE_ERR_STATE, "no box particular solution (bae_set_rhs_box with f)"};
         if (r < 0 || r >= c->nrhs) throw Error{BAE_ERR_ARG, "rhs index out of range"};
+        BAE_HIP_CHECK(hipSetDevice(c->device));
+        BAE_HIP_CHECK(hipStreamSynchronize(c->stream));
         const Geometry& G = c->geo;
         const int N = c->box_N;
         const int64_t nn = (int64_t)N * N * N, N3 = (int64_t)G.n[0] * G.n[1] * G.n[2];
@@ -862,200 +1231,159 @@ int bae_get_particular(const bae_ctx* c, int32_t r, double* up_grid) {
     });
 }
 
+// Orders the context's stream after the work queued on `stream` so far (no host wait).
+static void order_after(bae_ctx* c, hipStream_t stream) {
+    hipEvent_t ev;
+    BAE_HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(ev, stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, ev, 0);
+    (void)hipEventDestroy(ev);
+    if (e != hipSuccess) throw Error{BAE_ERR_HIP, std::string("ordering on the caller's stream: ") + hipGetErrorString(e)};
+}
+
 int bae_solve(bae_ctx* c, const bae_solve_params* p, bae_result* res) {
     int status = BAE_OK;
     int rc = guard([&] {
-        if (!c || !p) throw Error{BAE_ERR_ARG, "null argument"};
-        if (!c->rhs_ready) throw Error{BAE_ERR_STATE, "bae_set_rhs must precede bae_solve"};
-        if (p->precision != BAE_SOLVE_FP64 && p->precision != BAE_SOLVE_FP32_REFINED)
-            throw Error{BAE_ERR_ARG, "unknown solve precision"};
-        if (!(p->tol > 0.0)) throw Error{BAE_ERR_ARG, "tol must be > 0"};
-        if (p->formulation != BAE_LAYER_DOUBLE && p->formulation != BAE_LAYER_SINGLE)
-            throw Error{BAE_ERR_ARG, "unknown layer formulation"};
+        check_solve_args(c, p);
+        join_job(c);
+        c->job.state.store(0);
         BAE_HIP_CHECK(hipSetDevice(c->device));
-        hipStream_t st = c->stream;
-        // the layer potential of this solve (Sec. 3.4): every operator call below, the grid
-        // solution included, forms its source weights through this map
-        const LayerScope layer(c, p->formulation);
-        const auto t0 = std::chrono::steady_clock::now();
-        const int nrhs = c->nrhs;
-        const int64_t n = c->ngm;
-        const int maxit = p->maxit > 0 ? std::min(p->maxit, c->K.m) : c->K.m;
-        c->hist.assign(nrhs, {});
-        int64_t mv64 = 0, mv32 = 0;
-        std::vector<double> bn = host_norms(c, c->b.as<double>(), nrhs, st);
-        std::vector<int> iters(nrhs, 0), conv(nrhs, 0), outer(nrhs, 0);
-        std::vector<double> est(nrhs, 0.0), relres;
-        bool dq_in_vsum = false;   // the last operator call was the FP64 residual of the final q
-        launch_fill(c->x.as<double>(), n * nrhs, 0.0, st);
-        if (p->precision == BAE_SOLVE_FP64) {
-            GmresOut g = gmres(c, c->b.as<double>(), nrhs, BAE_PREC_FP64, p->tol, maxit, {}, c->x.as<double>(), false,
-                               st, &mv64);
-            for (int r = 0; r < nrhs; ++r) {
-                iters[r] = g.iters[r];
-                est[r] = g.last_est[r];
-            }
-            relres = residual(c, nrhs, bn, st, &mv64);
-            dq_in_vsum = true;
-            for (int r = 0; r < nrhs; ++r) conv[r] = g.converged[r];
-        } else {
-            // inner tolerance of outer step k: just enough to reach tol from the current
-            // residual, but never below the floor where the FP32 operator's own error (~1e-6
-            // relative) makes further inner iterations useless
-            const double floor_tol = p->inner_tol > 0 ? p->inner_tol : 1e-6;
-            const int max_outer = p->max_outer > 0 ? p->max_outer : 8;
-            // recycling costs a few host round trips per outer step: worth it once a matvec
-            // is long (1e8 pair interactions, ~50 us), not for the smallest problems
-            const bool long_matvec = (double)c->nT * (double)c->nS * nrhs >= 1e8;
-            const int recycle_cap = p->recycle_dim < 0   ? 0
-                                    : p->recycle_dim > 0 ? p->recycle_dim
-                                                         : (long_matvec ? kRecycleDefault : 0);
-            Recycle rc;
-            BAE_HIP_CHECK(hipMemcpyAsync(c->r.p, c->b.p, sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, st));
-            relres.assign(nrhs, 1.0);
-            for (int r = 0; r < nrhs; ++r) relres[r] = bn[r] > 0 ? 1.0 : 0.0;
-            for (int o = 0; o < max_outer; ++o) {
-                std::vector<int> skip(nrhs, 0);
-                bool all = true;
-                double worst = 0.0;
-                for (int r = 0; r < nrhs; ++r) {
-                    skip[r] = relres[r] <= p->tol;
-                    all &= skip[r] != 0;
-                    if (!skip[r]) worst = std::max(worst, relres[r]);
-                }
-                if (all) break;
-                const double inner = std::min(0.1, std::max(floor_tol, 0.5 * p->tol / worst));
-                // with a recycled space: its part of the residual first, then GMRES on the
-                // rest to the same absolute target (tolerance relative to what is left)
-                double gtol = inner;
-                std::vector<double> rscale(relres);
-                if (rc.p > 0) {
-                    recycle_project(c, rc, nrhs, skip, c->x.as<double>(), c->r.as<double>(), st);
-                    const std::vector<double> rn = host_norms(c, c->r.as<double>(), nrhs, st);
-                    double ratio = 1e300;
-                    for (int r = 0; r < nrhs; ++r) {
-                        if (skip[r]) continue;
-                        rscale[r] = bn[r] > 0 ? rn[r] / bn[r] : 0.0;
-                        if (rn[r] > 0) ratio = std::min(ratio, relres[r] * bn[r] / rn[r]);
-                    }
-                    gtol = ratio < 1e300 ? std::min(0.5, inner * ratio) : inner;
-                }
-                GmresOut g = gmres(c, c->r.as<double>(), nrhs, BAE_PREC_FP32, gtol, maxit, skip, c->x.as<double>(),
-                                   true, st, &mv32, rc.p > 0 ? &rc : nullptr);
-                for (int r = 0; r < nrhs; ++r) {
-                    iters[r] += g.iters[r];
-                    if (!skip[r]) {
-                        outer[r]++;
-                        est[r] = g.last_est[r] * rscale[r];
-                    }
-                }
-                if (o == 0 && recycle_cap > 0) build_recycle(c, nrhs, skip, recycle_cap, rc, st);
-                relres = residual(c, nrhs, bn, st, &mv64);
-                dq_in_vsum = true;
-            }
-            for (int r = 0; r < nrhs; ++r) conv[r] = relres[r] <= p->tol;
-        }
-        // u_gamma = D q + u_p on gamma.  The last call above is the FP64 residual of the final
-        // q, whose operator left D q at every target (internal order) in vsum: scattering it
-        // saves a double-layer evaluation.
-        if (dq_in_vsum && c->cl.n > 0)
-            launch_reduce_scatter(c->vsum.as<double>(), 1, c->nT, c->t_pos.as<int32_t>(), c->u_gamma.as<double>(),
-                                  c->nT, nrhs, 1.0, st);
-        else
-            double_layer(c, c->x.as<double>(), n, c->u_gamma.as<double>(), c->nT, nrhs, BAE_PREC_FP64, st);
-        launch_axpby(1.0, c->up_gamma.as<double>(), c->nT, 1.0, c->u_gamma.as<double>(), c->nT, c->nT, nrhs, st);
-        BAE_HIP_CHECK(hipStreamSynchronize(st));
-        c->ugrid.clear();
-        if (p->compute_grid) {
-            const Geometry& G = c->geo;
-            ensure_mplus(c);
-            const int64_t nm = c->Mp.ps.count;
-            DevMem um;
-            um.alloc(sizeof(double) * nm * nrhs);
-            launch_weights(*c->Bop, c->x.as<double>(), n, c->w.p, c->S.ps.padded, nrhs, BAE_PREC_FP64, st);
-            lgf_sum_to(c, c->Mp.ps, c->S.ps, c->w.as<double>(), nrhs, nullptr, um.as<double>(), nm, 1.0, st);
-            if (c->has_f) {
-                DevMem up;
-                up.alloc(sizeof(double) * nm * nrhs);
-                if (c->particular_box) {   // the finite-grid u_p is known at every node
-                    const int64_t nn = (int64_t)c->box_N * c->box_N * c->box_N;
-                    launch_gather(c->box_u.as<double>(), nn, c->box_mpidx.as<int32_t>(), nm, up.as<double>(), nm,
-                                  nrhs, 1.0, st);
-                } else {
-                    lgf_sum_to(c, c->Mp.ps, c->Mp.ps, c->wf.as<double>(), nrhs, nullptr, up.as<double>(), nm, 1.0, st);
-                }
-                launch_axpby(1.0, up.as<double>(), nm, 1.0, um.as<double>(), nm, nm, nrhs, st);
-            }
-            std::vector<double> hu(nm * nrhs), hg(c->nT * nrhs);
-            BAE_HIP_CHECK(hipMemcpyAsync(hu.data(), um.p, sizeof(double) * hu.size(), hipMemcpyDeviceToHost, st));
-            BAE_HIP_CHECK(hipMemcpyAsync(hg.data(), c->u_gamma.p, sizeof(double) * hg.size(), hipMemcpyDeviceToHost, st));
-            BAE_HIP_CHECK(hipStreamSynchronize(st));
-            const int64_t N3 = (int64_t)G.n[0] * G.n[1] * G.n[2];
-            c->ugrid.assign(N3 * nrhs, NAN);
-            std::vector<int32_t> lin;
-            for (int i = 0; i < G.n[0]; ++i)
-                for (int j = 0; j < G.n[1]; ++j)
-                    for (int k = 0; k < G.n[2]; ++k)
-                        if (G.inside[((int64_t)i * G.n[1] + j) * G.n[2] + k])
-                            lin.push_back((int32_t)(((int64_t)i * G.n[1] + j) * G.n[2] + k));
-            for (int r = 0; r < nrhs; ++r) {
-                for (int64_t a = 0; a < nm; ++a) c->ugrid[r * N3 + lin[c->Mp.perm[a]]] = hu[r * nm + a];
-                for (int64_t q = 0; q < n; ++q) {
-                    const int32_t* v = &G.gm[3 * q];
-                    c->ugrid[r * N3 + ((int64_t)v[0] * G.n[1] + v[1]) * G.n[2] + v[2]] = hg[r * c->nT + c->ngp + q];
-                }
-            }
-        }
-        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        for (int r = 0; r < nrhs; ++r) {
-            if (!conv[r]) status = BAE_NOT_CONVERGED;
-            if (res) {
-                res[r].status = conv[r] ? BAE_OK : BAE_NOT_CONVERGED;
-                res[r].iterations = iters[r];
-                res[r].outer_steps = outer[r];
-                res[r].converged = conv[r];
-                res[r].rel_residual_est = est[r];
-                res[r].rel_residual_true = relres[r];
-                res[r].seconds = secs;
-                res[r].matvecs_fp64 = mv64;
-                res[r].matvecs_fp32 = mv32;
-            }
-        }
-        c->solved = true;
+        if (p->x0_dev) order_after(c, nullptr);   // the initial densities, written on the null stream
+        status = solve_impl(c, p, res);
     });
     return rc != BAE_OK ? rc : status;
 }
 
-int bae_get_density(const bae_ctx* c, int32_t r, double* q) {
+int bae_solve_async(bae_ctx* c, const bae_solve_params* p, void* stream) {
     return guard([&] {
-        if (!c || !q) throw Error{BAE_ERR_ARG, "null argument"};
-        if (!c->solved || r < 0 || r >= c->nrhs) throw Error{BAE_ERR_STATE, "no solution for this RHS"};
-        BAE_HIP_CHECK(hipMemcpy(q, c->x.as<double>() + r * c->ngm, sizeof(double) * c->ngm, hipMemcpyDeviceToHost));
+        check_solve_args(c, p);
+        join_job(c);
+        BAE_HIP_CHECK(hipSetDevice(c->device));
+        order_after(c, (hipStream_t)stream);
+        c->job.state.store(1);
+        c->job.status = BAE_OK;
+        c->job.error.clear();
+        c->job.res.assign(c->nrhs, bae_result{});
+        const bae_solve_params prm = *p;
+        c->job.th = std::thread([c, prm] {
+            int status = BAE_OK;
+            const int rc = guard([&] { status = solve_impl(c, &prm, c->job.res.data()); });
+            c->job.status = rc != BAE_OK ? rc : status;
+            if (rc != BAE_OK) c->job.error = bae_last_error();
+            c->job.state.store(2);
+        });
     });
 }
 
-int bae_get_gamma_values(const bae_ctx* c, int32_t r, double* u) {
+int bae_solve_poll(const bae_ctx* c, int32_t* done) {
     return guard([&] {
-        if (!c || !u) throw Error{BAE_ERR_ARG, "null argument"};
-        if (!c->solved || r < 0 || r >= c->nrhs) throw Error{BAE_ERR_STATE, "no solution for this RHS"};
-        BAE_HIP_CHECK(hipMemcpy(u, c->u_gamma.as<double>() + r * c->nT, sizeof(double) * c->nT, hipMemcpyDeviceToHost));
+        if (!c || !done) throw Error{BAE_ERR_ARG, "null argument"};
+        *done = c->job.state.load() != 1;
     });
 }
 
-int bae_get_solution(const bae_ctx* c, int32_t r, double* u) {
+int bae_solve_wait(bae_ctx* c, void* stream, bae_result* res) {
+    int status = BAE_OK;
+    int rc = guard([&] {
+        if (!c) throw Error{BAE_ERR_ARG, "null argument"};
+        if (c->job.state.load() == 0) throw Error{BAE_ERR_STATE, "no solve started by bae_solve_async"};
+        join_job(c);
+        c->job.state.store(0);
+        if (res) std::copy(c->job.res.begin(), c->job.res.end(), res);
+        if (c->job.status < 0) throw Error{c->job.status, c->job.error};
+        status = c->job.status;
+        // the caller's later work on `stream` sees every output of the solve
+        BAE_HIP_CHECK(hipSetDevice(c->device));
+        hipEvent_t ev;
+        BAE_HIP_CHECK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        hipError_t e = hipEventRecord(ev, c->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent((hipStream_t)stream, ev, 0);
+        (void)hipEventDestroy(ev);
+        if (e != hipSuccess) throw Error{BAE_ERR_HIP, std::string("ordering the caller's stream: ") + hipGetErrorString(e)};
+    });
+    return rc != BAE_OK ? rc : status;
+}
+
+// Output r (or all RHS for r = -1) of length len per RHS from the device buffer src (row
+// stride len) into dst: host (dev = false) or device memory on `stream`.
+static void copy_out(bae_ctx* c, int32_t r, const double* src, int64_t len, double* dst, bool dev, hipStream_t stream) {
+    if (r < -1 || r >= c->nrhs) throw Error{BAE_ERR_ARG, "rhs index out of range"};
+    const double* from = r < 0 ? src : src + r * len;
+    const int64_t count = r < 0 ? len * c->nrhs : len;
+    BAE_HIP_CHECK(hipSetDevice(c->device));
+    if (dev) {
+        BAE_HIP_CHECK(hipMemcpyAsync(dst, from, sizeof(double) * count, hipMemcpyDeviceToDevice, stream));
+    } else {
+        BAE_HIP_CHECK(hipMemcpyAsync(dst, from, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
+        BAE_HIP_CHECK(hipStreamSynchronize(c->stream));
+    }
+}
+
+static bae_ctx* solved_ctx(const bae_ctx* cc) {
+    if (!cc) throw Error{BAE_ERR_ARG, "null argument"};
+    bae_ctx* c = const_cast<bae_ctx*>(cc);
+    join_job(c);
+    if (!c->solved) throw Error{BAE_ERR_STATE, "no solution (solve first)"};
+    return c;
+}
+
+int bae_get_density(const bae_ctx* cc, int32_t r, double* q) {
     return guard([&] {
-        if (!c || !u) throw Error{BAE_ERR_ARG, "null argument"};
-        if (!c->solved || r < 0 || r >= c->nrhs || c->ugrid.empty())
-            throw Error{BAE_ERR_STATE, "no grid solution (solve with compute_grid)"};
+        bae_ctx* c = solved_ctx(cc);
+        if (!q) throw Error{BAE_ERR_ARG, "null argument"};
+        copy_out(c, r, c->x.as<double>(), c->ngm, q, false, nullptr);
+    });
+}
+
+int bae_get_gamma_values(const bae_ctx* cc, int32_t r, double* u) {
+    return guard([&] {
+        bae_ctx* c = solved_ctx(cc);
+        if (!u) throw Error{BAE_ERR_ARG, "null argument"};
+        copy_out(c, r, c->u_gamma.as<double>(), c->nT, u, false, nullptr);
+    });
+}
+
+int bae_get_solution(const bae_ctx* cc, int32_t r, double* u) {
+    return guard([&] {
+        bae_ctx* c = solved_ctx(cc);
+        if (!u) throw Error{BAE_ERR_ARG, "null argument"};
+        if (!c->has_grid) throw Error{BAE_ERR_STATE, "no grid solution (solve with compute_grid)"};
         const int64_t N3 = (int64_t)c->geo.n[0] * c->geo.n[1] * c->geo.n[2];
-        std::memcpy(u, c->ugrid.data() + r * N3, sizeof(double) * N3);
+        copy_out(c, r, c->ugrid.as<double>(), N3, u, false, nullptr);
     });
 }
 
-int bae_get_history(const bae_ctx* c, int32_t r, double* h, int32_t cap, int32_t* len) {
+int bae_get_density_device(const bae_ctx* cc, int32_t r, double* q_dev, void* stream) {
     return guard([&] {
-        if (!c || !len) throw Error{BAE_ERR_ARG, "null argument"};
-        if (!c->solved || r < 0 || r >= c->nrhs) throw Error{BAE_ERR_STATE, "no solution for this RHS"};
+        bae_ctx* c = solved_ctx(cc);
+        if (!q_dev) throw Error{BAE_ERR_ARG, "null argument"};
+        copy_out(c, r, c->x.as<double>(), c->ngm, q_dev, true, (hipStream_t)stream);
+    });
+}
+
+int bae_get_gamma_values_device(const bae_ctx* cc, int32_t r, double* u_dev, void* stream) {
+    return guard([&] {
+        bae_ctx* c = solved_ctx(cc);
+        if (!u_dev) throw Error{BAE_ERR_ARG, "null argument"};
+        copy_out(c, r, c->u_gamma.as<double>(), c->nT, u_dev, true, (hipStream_t)stream);
+    });
+}
+
+int bae_get_solution_device(const bae_ctx* cc, int32_t r, double* u_dev, void* stream) {
+    return guard([&] {
+        bae_ctx* c = solved_ctx(cc);
+        if (!u_dev) throw Error{BAE_ERR_ARG, "null argument"};
+        if (!c->has_grid) throw Error{BAE_ERR_STATE, "no grid solution (solve with compute_grid)"};
+        const int64_t N3 = (int64_t)c->geo.n[0] * c->geo.n[1] * c->geo.n[2];
+        copy_out(c, r, c->ugrid.as<double>(), N3, u_dev, true, (hipStream_t)stream);
+    });
+}
+
+int bae_get_history(const bae_ctx* cc, int32_t r, double* h, int32_t cap, int32_t* len) {
+    return guard([&] {
+        bae_ctx* c = solved_ctx(cc);
+        if (!len) throw Error{BAE_ERR_ARG, "null argument"};
+        if (r < 0 || r >= c->nrhs) throw Error{BAE_ERR_ARG, "rhs index out of range"};
         const auto& v = c->hist[r];
         *len = (int32_t)v.size();
         if (h) std::memcpy(h, v.data(), sizeof(double) * std::min<size_t>(v.size(), cap > 0 ? cap : 0));
@@ -1068,6 +1396,8 @@ int bae_apply_double_layer(bae_ctx* c, const double* q, double* v, int32_t nrhs,
         if (nrhs < 1 || nrhs > c->max_rhs) throw Error{BAE_ERR_ARG, "nrhs out of range"};
         if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32) throw Error{BAE_ERR_ARG, "unknown precision"};
         BAE_HIP_CHECK(hipSetDevice(c->device));
+        join_job(c);
+        check_sum_error(c);   // a sum queued by an earlier call gave up
         double_layer(c, q, c->ngm, v, c->nT, nrhs, prec, (hipStream_t)stream);
     });
 }
@@ -1078,6 +1408,8 @@ int bae_apply_single_layer(bae_ctx* c, const double* q, double* v, int32_t nrhs,
         if (nrhs < 1 || nrhs > c->max_rhs) throw Error{BAE_ERR_ARG, "nrhs out of range"};
         if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32) throw Error{BAE_ERR_ARG, "unknown precision"};
         BAE_HIP_CHECK(hipSetDevice(c->device));
+        join_job(c);
+        check_sum_error(c);   // a sum queued by an earlier call gave up
         const LayerScope layer(c, BAE_LAYER_SINGLE);
         double_layer(c, q, c->ngm, v, c->nT, nrhs, prec, (hipStream_t)stream);
     });
@@ -1089,6 +1421,8 @@ int bae_apply_operator(bae_ctx* c, const double* q, double* aq, int32_t nrhs, in
         if (nrhs < 1 || nrhs > c->max_rhs) throw Error{BAE_ERR_ARG, "nrhs out of range"};
         if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32) throw Error{BAE_ERR_ARG, "unknown precision"};
         BAE_HIP_CHECK(hipSetDevice(c->device));
+        join_job(c);
+        check_sum_error(c);   // a sum queued by an earlier call gave up
         bae_operator(c, q, c->ngm, aq, c->ngm, nrhs, prec, (hipStream_t)stream);
     });
 }
@@ -1100,6 +1434,8 @@ int bae_lgf_sum_repeat(bae_ctx* c, const double* q, int32_t nrhs, int32_t prec, 
         if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32) throw Error{BAE_ERR_ARG, "unknown precision"};
         if (repeats < 1 || repeats > 1000) throw Error{BAE_ERR_ARG, "repeats must be in [1, 1000]"};
         BAE_HIP_CHECK(hipSetDevice(c->device));
+        join_job(c);
+        check_sum_error(c);   // a sum queued by an earlier call gave up
         const hipStream_t st = (hipStream_t)stream;
         launch_weights(c->B, q, c->ngm, c->w.p, c->S.ps.padded, nrhs, prec, st);
         for (int i = 0; i < repeats; ++i) {
@@ -1115,46 +1451,9 @@ int bae_sum_stats(const bae_ctx* c, int32_t prec, int64_t* counts) {
         if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32) throw Error{BAE_ERR_ARG, "unknown precision"};
         const bool fp32 = prec == BAE_PREC_FP32;
         const int tab_r = fp32 ? c->tabs.tab_r32 : c->tabs.tab_r64;
-        const PointSet& T = c->T.ps;
-        const PointSet& S = c->S.ps;
-        const int64_t nt = T.count, ns = S.count, nblk = S.nblk;
-        int64_t cnt[5] = {0, 0, 0, 0, 0};
-        // the kernel's classification, per (wavefront of 64 targets, source block)
-        for (int64_t w0 = 0; w0 < nt; w0 += 64) {
-            const int64_t w1 = std::min(nt, w0 + 64);
-            int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {0, 0, 0};
-            for (int64_t i = w0; i < w0 + 64; ++i) {
-                const int64_t t = std::min(i, nt - 1);
-                for (int a = 0; a < 3; ++a) {
-                    lo[a] = std::min(lo[a], T.hq[3 * t + a]);
-                    hi[a] = std::max(hi[a], T.hq[3 * t + a]);
-                }
-            }
-            for (int64_t b = 0; b < nblk; ++b) {
-                const int32_t* bb = &S.hbox[6 * b];
-                int gap = 0, span = 0;
-                for (int a = 0; a < 3; ++a) {
-                    gap = std::max(gap, std::max(bb[a] - hi[a], lo[a] - bb[3 + a]));
-                    span = std::max(span, std::max(bb[3 + a] - lo[a], hi[a] - bb[a]));
-                }
-                const int64_t s0 = b * kSourceBlock, s1 = std::min(ns, s0 + kSourceBlock);
-                const int64_t pairs = (w1 - w0) * (s1 - s0);
-                switch (block_class(gap, span, tab_r, fp32 ? c->tabs.far32() : c->tabs.far64(), fp32,
-                                    fp32 ? c->tabs.far_gap32() : c->tabs.far_gap64())) {
-                    case kClassTable: cnt[0] += pairs; break;
-                    case kClassFar: case kClassGather: cnt[1] += pairs; break;
-                    case kClassFar2: cnt[2] += pairs; break;
-                    default:
-                        for (int64_t t = w0; t < w1; ++t)
-                            for (int64_t s = s0; s < s1; ++s) {
-                                int m = 0;
-                                for (int a = 0; a < 3; ++a) m = std::max(m, std::abs(T.hq[3 * t + a] - S.hq[3 * s + a]));
-                                cnt[m <= kQuant * tab_r ? 3 : 4]++;
-                            }
-                }
-            }
-        }
-        for (int i = 0; i < 5; ++i) counts[i] = cnt[i];
+        for (int i = 0; i < 5; ++i) counts[i] = 0;
+        classify_pairs(c, fp32, tab_r, fp32 ? c->tabs.far32() : c->tabs.far64(),
+                       fp32 ? c->tabs.far_gap32() : c->tabs.far_gap64(), counts);
     });
 }
 

@@ -851,7 +851,7 @@ int solve_all(BatchEngine* b, const bae_solve_params* prm, bool use_graph, bae_r
         const int conv = relres[p] <= prm->tol;
         if (!conv) status = BAE_NOT_CONVERGED;
         c->solved = true;
-        c->ugrid.clear();
+        c->has_grid = false;
         if (res) {
             res[p].status = conv ? BAE_OK : BAE_NOT_CONVERGED;
             res[p].iterations = iters[p];
@@ -971,6 +971,22 @@ int bae_batch_autotune(bae_batch* bb, int32_t precision, int32_t* chosen) {
     });
 }
 
+int bae_batch_sum_stats(const bae_batch* bb, int32_t precision, int64_t* counts) {
+    return guard([&] {
+        if (!bb || !counts) throw Error{BAE_ERR_ARG, "null argument"};
+        if (precision != BAE_PREC_FP64 && precision != BAE_PREC_FP32) throw Error{BAE_ERR_ARG, "unknown precision"};
+        const bool fp32 = precision == BAE_PREC_FP32;
+        for (int i = 0; i < 5; ++i) counts[i] = 0;
+        // the batched sum's own classification: the general LDS layout's radii
+        for (const bae_ctx* c : bb->e->ctx) {
+            const int tab_r = fp32 ? std::min(c->tabs.tab_r32, kLdsRadius32) : std::min(c->tabs.tab_r64, kLdsRadius64);
+            const bool far_ok = fp32 ? c->tabs.far32() : c->tabs.far64();
+            const int far_gap = fp32 ? (c->tabs.yukawa32 ? tab_r : c->tabs.far_gap32()) : c->tabs.far_gap64();
+            classify_pairs(c, fp32, tab_r, far_ok, far_gap, counts);
+        }
+    });
+}
+
 int bae_batch_solve(bae_batch* bb, const bae_solve_params* prm, int32_t use_graph, bae_result* res) {
     int status = BAE_OK;
     int rc = guard([&] {
@@ -980,6 +996,7 @@ int bae_batch_solve(bae_batch* bb, const bae_solve_params* prm, int32_t use_grap
         if (!(prm->tol > 0.0)) throw Error{BAE_ERR_ARG, "tol must be > 0"};
         if (prm->formulation != BAE_LAYER_DOUBLE)
             throw Error{BAE_ERR_ARG, "batched solves use the double-layer formulation"};
+        if (prm->x0_dev) throw Error{BAE_ERR_ARG, "batched solves start from x0 = 0"};
         BAE_HIP_CHECK(hipSetDevice(bb->e->device));
         status = solve_all(bb->e, prm, use_graph != 0, res);
     });

@@ -3,8 +3,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstring>
 #include <functional>
+#include <thread>
 #include <memory>
 #include <string>
 #include <vector>
@@ -159,7 +161,9 @@ struct PointBuf {
 struct PlanBuf {
     SumPlan plan;
     DevMem items, counter;
-    void build(const PointSet& T, const PointSet& S, const SumTables& tabs, hipStream_t st);
+    // err_dev: the device view of the error word the sum's bounded waits set on giving up
+    void build(const PointSet& T, const PointSet& S, const SumTables& tabs, int32_t* err_dev, uint32_t polls,
+               hipStream_t st);
 };
 
 }  // namespace bae
@@ -213,12 +217,42 @@ struct bae_ctx {
     int nrhs = 0;
     bool has_f = false, rhs_ready = false, solved = false;
     std::vector<std::vector<double>> hist;  // per rhs
-    std::vector<double> ugrid;              // [rhs][n0 n1 n2] when computed
-    int32_t* pinned_flags = nullptr;        // host pinned, coherent and mapped, 2 * max_rhs
+    bool has_grid = false;                  // ugrid holds the last solve's grid solution
+    DevMem ugrid;                           // [rhs][n0 n1 n2], NaN outside N+
+    DevMem gdev;                            // [max_rhs][ngm] boundary data staged from the host
+    DevMem partner_dev;                     // gamma+ index of each gamma- node's partner
+    DevMem mp_lin_dev, gm_lin_dev;          // linear grid index of each M+ (Mp order) / gamma- node (lazy)
+    PlanBuf plan_mp;                        // work list of the (gamma, M+) sum of u_p (lazy)
+    DevMem part_mp;
+    hipEvent_t rhs_ev = nullptr;            // end of the last right-hand side's device work
+    // a solve started by bae_solve_async, driven by a host thread of its own
+    struct Job {
+        std::thread th;
+        std::atomic<int> state{0};          // 0 none, 1 running, 2 finished (not yet collected)
+        int status = 0;
+        std::string error;
+        std::vector<bae_result> res;
+    } job;
+    int32_t* pinned_flags = nullptr;        // host pinned, coherent and mapped, 2 * max_rhs + 1
     int32_t* flags_dev = nullptr;           // the same memory as the device sees it
+    int32_t* err_host = nullptr;            // word 2 max_rhs: set by an LGF sum whose bounded wait gave up
+    int32_t* err_dev = nullptr;
+    int32_t* bad_host = nullptr;            // word 2 max_rhs + 1: set by a non-finite device input
+    int32_t* bad_dev = nullptr;
+    uint32_t wait_polls = kWaitPolls;
 };
 
 namespace bae {
+// Throws BAE_ERR_HIP when an LGF sum launched on the context since the last check gave up
+// on a bounded wait (its results are incomplete); clears the word and resets the work
+// counter first, so the context stays usable.
+void check_sum_error(bae_ctx* c);
+// Waits for the host thread of a solve started by bae_solve_async (its results stay for
+// bae_solve_wait).
+void join_job(bae_ctx* c);
+// Pair counts of the LGF sum over gamma x (gamma- u E) by the kernels' block classification
+// (table, far / gather, FP32 far, mixed within / beyond the LDS radius), added to cnt[5].
+void classify_pairs(const bae_ctx* c, bool fp32, int tab_r, bool far_ok, int far_gap, int64_t* cnt);
 // Device part of bae_create for an already classified geometry (throws Error).
 bae_ctx* create_context(const bae_grid& grid, const bae_options* opt, Geometry&& geo);
 int64_t estimate_context_bytes(const Geometry& G, double s, const bae_options* opt);

@@ -66,6 +66,7 @@ constexpr double kYukawaTolerance = 1e-6; // sigma > 0 FP32 far field: largest a
 constexpr int kSumThreads = 1024;         // threads per workgroup of the LGF sum
 constexpr int kMaxChunks = 64;            // source chunks (partial sums per target)
 constexpr int kGroupTiles = 16;           // 64-target tiles per work item of the LGF sum
+constexpr uint32_t kWaitPolls = 1u << 22;  // polls (s_sleep 1 each, ~0.1 s in all) of a bounded wait
 constexpr int kMaxLatticeCoord = 2048;    // largest lattice coordinate: every integer up to 2048
                                           // is exact in binary16 (the FP32 far field's differences)
 
@@ -132,6 +133,8 @@ struct SumPlan {
     int64_t nitems = 0;
     uint32_t* items = nullptr;     // device: group | chunk << 20
     unsigned long long* counter = nullptr;   // device: work counter, 0 between launches
+    int32_t* err = nullptr;        // device view of the error word a bounded wait sets on giving up
+    uint32_t wait_polls = kWaitPolls;   // polls of each bounded wait of the sum's work hand-off
     int64_t class_pairs[2][5] = {{0}};   // [fp64, fp32][class] pairs (mixed split: 3 table, 4 other)
 };
 // Host: chunking, per-item cost, order and pair statistics (items left on the host in

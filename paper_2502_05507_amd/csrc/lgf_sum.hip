@@ -58,13 +58,14 @@ struct Sched {
     unsigned long long* counter;   // hands out items G.. (a type no input array has: its
                                    // atomics cannot alias the inputs, whose uniform loads
                                    // then stay scalar); 0 between launches
+    int32_t* err;          // set to 1 (system scope) when a bounded wait gives up
+    uint32_t polls;        // polls of each bounded wait before it gives up (0: at once)
 };
 
 // Per-workgroup hand-off of work items in LDS: a ring of the global item indices of the
 // workgroup's next local items, each with its local number as tag, and the number of units
 // of it whose wavefronts have read it.
 constexpr uint32_t kRing = 4;
-constexpr uint32_t kSpinLimit = 1u << 22;   // bounded waits (a wait this long is a bug)
 struct ItemRing {
     uint32_t units;             // (local item, tile) units handed out so far
     uint32_t item[kRing];
@@ -78,6 +79,13 @@ __device__ __forceinline__ void ring_init(ItemRing* r) {
         r->tag[threadIdx.x] = ~0u;
         r->readers[threadIdx.x] = kGroupTiles;
     }
+}
+
+// A bounded wait that gives up ends its wavefront's work loop and reports it: the sum's
+// partial results are then incomplete and the work counter is left mid-way, so the host
+// (which polls the error word after the launch) fails the call and resets the counter.
+__device__ __forceinline__ void give_up(const Sched& q) {
+    if ((threadIdx.x & 63) == 0) __hip_atomic_store(q.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // The work loop of one wavefront.  Items are (group of kGroupTiles consecutive target
@@ -103,11 +111,14 @@ __device__ __forceinline__ void for_each_item(const Sched& q, ItemRing* r, F&& b
         uint32_t idx = blockIdx.x;
         if (k > 0) {
             const uint32_t s = k % kRing;
-            uint32_t spins = 0;
-            while (__hip_atomic_load(&r->tag[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != k &&
-                   ++spins < kSpinLimit)
+            for (uint32_t polls = 0;; ++polls) {
+                if (polls >= q.polls) {
+                    give_up(q);
+                    return;
+                }
+                if (__hip_atomic_load(&r->tag[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == k) break;
                 __builtin_amdgcn_s_sleep(1);
-            if (spins >= kSpinLimit) return;
+            }
             idx = __builtin_amdgcn_readfirstlane(r->item[s]);
             if (lane == 0) __hip_atomic_fetch_add(&r->readers[s], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
@@ -121,10 +132,15 @@ __device__ __forceinline__ void for_each_item(const Sched& q, ItemRing* r, F&& b
             if (v == q.nitems - 1 && lane == 0)
                 __hip_atomic_store(q.counter, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t s = (k + 1) % kRing;
-            uint32_t spins = 0;
-            while (__hip_atomic_load(&r->readers[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != kGroupTiles &&
-                   ++spins < kSpinLimit)
+            for (uint32_t polls = 0;; ++polls) {
+                if (polls >= q.polls) {
+                    give_up(q);
+                    return;
+                }
+                if (__hip_atomic_load(&r->readers[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == kGroupTiles)
+                    break;
                 __builtin_amdgcn_s_sleep(1);
+            }
             if (lane == 0) {
                 r->item[s] = G + v;
                 r->readers[s] = 0;
@@ -499,7 +515,8 @@ void launch_all(const PointSet& T, const PointSet& S, const Real* w, int nrhs, c
         ar.w = w + (int64_t)r * a.ldw;
         ar.part = part + (int64_t)r * a.ldp;
         const int threads = left >= 16 ? mfma_threads<Real>() : left >= 4 ? rhs4_threads<Real>() : kSumThreads;
-        const Sched q{skip, plan.items, (uint32_t)plan.nitems, (uint32_t)((T.count + kWave - 1) / kWave), plan.counter};
+        const Sched q{skip, plan.items, (uint32_t)plan.nitems, (uint32_t)((T.count + kWave - 1) / kWave), plan.counter,
+                      plan.err, plan.wait_polls};
         if (left >= 16) {
             if (lds_far) lgf_sum_mfma_kernel<Real, mfma_threads<Real>(), true><<<grid, mfma_threads<Real>(), 0, st>>>(ar, q);
             else lgf_sum_mfma_kernel<Real, mfma_threads<Real>(), false><<<grid, mfma_threads<Real>(), 0, st>>>(ar, q);

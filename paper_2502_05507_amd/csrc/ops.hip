@@ -368,6 +368,37 @@ __global__ void gather_kernel(const double* __restrict__ x, int64_t ldx, const i
     if (i < n) y[r * ldy + i] = scale * x[r * ldx + idx[i]];
 }
 
+// b[r][q] = g[r][q] - ((1 - t_q) up[r][ngp + q] + t_q up[r][partner_q])  (Sec. 3.4: the
+// right-hand side g - Phi u_p; up on gamma in [gamma+; gamma-] order, or null for u_p = 0).
+// A non-finite g sets *bad (system scope: it may be mapped host memory).
+__global__ void rhs_kernel(const double* __restrict__ g, int64_t ldg, const double* __restrict__ up, int64_t ldu,
+                           const int32_t* __restrict__ partner, const double* __restrict__ t, int64_t ngp,
+                           int64_t ngm, double* __restrict__ b, int64_t ldb, int32_t* __restrict__ bad) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (q >= ngm) return;
+    const double gv = g[r * ldg + q];
+    if (!isfinite(gv)) __hip_atomic_store(bad, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    double v = gv;
+    if (up) v -= (1.0 - t[q]) * up[r * ldu + ngp + q] + t[q] * up[r * ldu + partner[q]];
+    b[r * ldb + q] = v;
+}
+
+// *bad = 1 (system scope) if any of x[r][i], i < n, is not finite.
+__global__ void finite_check_kernel(const double* __restrict__ x, int64_t ldx, int64_t n, int32_t* __restrict__ bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i < n && !isfinite(x[r * ldx + i])) __hip_atomic_store(bad, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// y[r][idx[i]] = x[r][i]
+__global__ void scatter_kernel(const double* __restrict__ x, int64_t ldx, const int32_t* __restrict__ idx, int64_t n,
+                               double* __restrict__ y, int64_t ldy) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (i < n) y[r * ldy + idx[i]] = x[r * ldx + i];
+}
+
 __global__ void fill_kernel(double* __restrict__ y, int64_t n, double v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) y[i] = v;
@@ -517,6 +548,26 @@ void launch_gather(const double* x, int64_t ldx, const int32_t* idx, int64_t n, 
                    double scale, hipStream_t st) {
     if (n == 0) return;
     gather_kernel<<<dim3(blocks_for(n), nrhs), kThreads, 0, st>>>(x, ldx, idx, n, y, ldy, scale);
+    LAUNCH_CHECK();
+}
+
+void launch_rhs(const double* g, int64_t ldg, const double* up, int64_t ldu, const int32_t* partner, const double* t,
+                int64_t ngp, int64_t ngm, double* b, int64_t ldb, int nrhs, int32_t* bad, hipStream_t st) {
+    if (ngm == 0) return;
+    rhs_kernel<<<dim3(blocks_for(ngm), nrhs), kThreads, 0, st>>>(g, ldg, up, ldu, partner, t, ngp, ngm, b, ldb, bad);
+    LAUNCH_CHECK();
+}
+
+void launch_finite_check(const double* x, int64_t ldx, int64_t n, int nrhs, int32_t* bad, hipStream_t st) {
+    if (n == 0) return;
+    finite_check_kernel<<<dim3(blocks_for(n), nrhs), kThreads, 0, st>>>(x, ldx, n, bad);
+    LAUNCH_CHECK();
+}
+
+void launch_scatter(const double* x, int64_t ldx, const int32_t* idx, int64_t n, double* y, int64_t ldy, int nrhs,
+                    hipStream_t st) {
+    if (n == 0) return;
+    scatter_kernel<<<dim3(blocks_for(n), nrhs), kThreads, 0, st>>>(x, ldx, idx, n, y, ldy);
     LAUNCH_CHECK();
 }
 

@@ -84,6 +84,14 @@ void launch_axpby(double a, const double* x, int64_t ldx, double b, double* y, i
                   hipStream_t st);
 void launch_gather(const double* x, int64_t ldx, const int32_t* idx, int64_t n, double* y, int64_t ldy, int nrhs,
                    double scale, hipStream_t st);
+// b = g - Phi u_p on gamma- (up: [nrhs][ngp + ngm] in [gamma+; gamma-] order, or null);
+// a non-finite g sets *bad.
+void launch_rhs(const double* g, int64_t ldg, const double* up, int64_t ldu, const int32_t* partner, const double* t,
+                int64_t ngp, int64_t ngm, double* b, int64_t ldb, int nrhs, int32_t* bad, hipStream_t st);
+void launch_finite_check(const double* x, int64_t ldx, int64_t n, int nrhs, int32_t* bad, hipStream_t st);
+// y[r][idx[i]] = x[r][i]
+void launch_scatter(const double* x, int64_t ldx, const int32_t* idx, int64_t n, double* y, int64_t ldy, int nrhs,
+                    hipStream_t st);
 void launch_fill(double* y, int64_t n, double v, hipStream_t st);
 void launch_fill_int(int32_t* y, int64_t n, int32_t v, hipStream_t st);
 void launch_to_float(const double* x, float* y, int64_t n, hipStream_t st);

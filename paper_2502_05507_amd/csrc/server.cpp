@@ -1,14 +1,16 @@
 // Serving loop with continuous batching.
 //
-// A scheduler thread owns one batch engine.  Submitted requests wait in FIFO order; a
-// request is admitted when a slot is free and its device footprint (computed from its
-// classified geometry before any device allocation) fits in the remaining memory budget.
-// Admitted requests keep their point sets, LGF table and Krylov state on the device and
-// join the running batch at the next step boundary; every step advances all running
-// requests by a few GMRES iterations with one launch per phase, so new work overlaps with
-// work already on the GPU.  A finished request (FP64 GMRES, or the FP32 inner solve of a
-// refinement step followed by its FP64 residual) leaves the batch, its result is copied to
-// the host and its memory and slot are released for the requests still waiting.
+// Two host threads share the device.  Submitted requests wait in FIFO order; the set-up
+// thread admits one when a slot is free and its device footprint (computed from its
+// classified geometry before any device allocation) fits in the remaining memory budget,
+// reserves both, and builds the request's context -- point sets, LGF table, boundary data
+// through the caller's callback -- on the context's own stream, while the running batch
+// keeps the device busy.  The scheduler thread owns one batch engine: at each step boundary
+// it takes the requests whose set-up has finished into the batch; every step advances all
+// running requests by a few GMRES iterations with one launch per phase, so new work
+// overlaps with work already on the GPU.  A finished request (FP64 GMRES, or the FP32 inner
+// solve of a refinement step followed by its FP64 residual) leaves the batch, its result is
+// copied to the host and its memory and slot are released for the requests still waiting.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -57,12 +59,14 @@ using namespace bae;
 struct bae_server {
     bae_server_options opt{};
     BatchEngine* engine = nullptr;
-    std::thread thread;
+    std::thread thread, setup_thread;
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_work, cv_setup, cv_done;
     bool stop = false;
     uint64_t next_ticket = 1;
     std::deque<std::shared_ptr<Req>> waiting;
+    int in_setup = 0;                                  // admitted, context being built
+    std::vector<std::shared_ptr<Req>> ready;           // set up, joining at the next step
     std::vector<std::shared_ptr<Req>> running;
     std::map<uint64_t, std::shared_ptr<Req>> all;
     int64_t used = 0;
@@ -82,72 +86,101 @@ void fail(bae_server* s, const std::shared_ptr<Req>& r, int status, const std::s
     s->stats.failed++;
 }
 
-// Admit waiting requests (FIFO) while a slot and memory are available.  Returns the
-// newly admitted ones.  Called on the scheduler thread without the lock held, except
-// around queue manipulation.
-std::vector<std::shared_ptr<Req>> admit(bae_server* s) {
-    std::vector<std::shared_ptr<Req>> fresh;
+// The set-up thread: admits waiting requests in FIFO order while a slot and memory are
+// free (both reserved at admission) and builds each one's context, then hands it to the
+// scheduler.  Every failure fails that request only.
+void setup_loop(bae_server* s) {
+    (void)hipSetDevice(s->opt.device);
+    bae_options o{};
+    o.device = s->opt.device;
+    o.max_rhs = 1;
+    o.max_krylov = s->opt.max_krylov;
     for (;;) {
         std::shared_ptr<Req> r;
         {
-            std::lock_guard<std::mutex> lk(s->mu);
-            if (s->waiting.empty() || (int)(s->running.size() + fresh.size()) >= s->opt.max_slots) break;
+            std::unique_lock<std::mutex> lk(s->mu);
+            auto slot_free = [&] {
+                return (int)(s->running.size() + s->ready.size()) + s->in_setup < s->opt.max_slots;
+            };
+            s->cv_setup.wait(lk, [&] { return s->stop || (!s->waiting.empty() && slot_free()); });
+            if (s->stop) return;
             r = s->waiting.front();
         }
-        bae_options o{};
-        o.device = s->opt.device;
-        o.max_rhs = 1;
-        o.max_krylov = s->opt.max_krylov;
-        if (!r->geo) {
+        // the geometry (host) gives the exact footprint before any device allocation
+        std::string fail_msg;
+        int fail_code = BAE_OK;
+        if (!r->geo && r->bytes == 0) {
             try {
-                r->geo = std::make_unique<Geometry>();
+                auto geo = std::make_unique<Geometry>();
                 bae_levelset ls = r->ls;
                 if (ls.kind == BAE_LS_SAMPLED) ls.phi_samples = r->phi.data();
-                build_geometry(r->grid, ls, *r->geo);
-                r->bytes = estimate_context_bytes(*r->geo, r->grid.sigma * r->grid.h * r->grid.h, &o);
+                build_geometry(r->grid, ls, *geo);
+                r->bytes = estimate_context_bytes(*geo, r->grid.sigma * r->grid.h * r->grid.h, &o);
+                r->geo = std::move(geo);
             } catch (const Error& e) {
-                std::lock_guard<std::mutex> lk(s->mu);
+                fail_code = e.code;
+                fail_msg = e.msg;
+            } catch (const std::exception& e) {
+                fail_code = BAE_ERR_ARG;
+                fail_msg = std::string("geometry: ") + e.what();
+            }
+        }
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            if (fail_code == BAE_OK && r->bytes > s->opt.hbm_budget) {
+                fail_code = BAE_ERR_ADMISSION;
+                fail_msg = "request needs more device memory than the whole budget";
+            }
+            if (fail_code != BAE_OK) {
                 s->waiting.pop_front();
-                fail(s, r, e.code, e.msg);
+                fail(s, r, fail_code, fail_msg);
                 s->cv_done.notify_all();
                 continue;
             }
-        }
-        if (r->bytes > s->opt.hbm_budget) {
-            std::lock_guard<std::mutex> lk(s->mu);
+            // wait for memory in FIFO order (finished requests release it)
+            s->cv_setup.wait(lk, [&] { return s->stop || s->used + r->bytes <= s->opt.hbm_budget; });
+            if (s->stop) return;
             s->waiting.pop_front();
-            fail(s, r, BAE_ERR_ADMISSION, "request needs more device memory than the whole budget");
-            s->cv_done.notify_all();
-            continue;
+            s->used += r->bytes;
+            s->in_setup++;
+            s->stats.admitted++;
+            s->stats.peak_bytes = std::max<int64_t>(s->stats.peak_bytes, s->used);
+            r->state = Q_RUNNING;
+            r->t_admit = s->now();
         }
-        if (s->used + r->bytes > s->opt.hbm_budget) break;   // wait for memory (FIFO order)
         try {
             r->ctx = create_context(r->grid, &o, std::move(*r->geo));
             r->geo.reset();
             const int64_t n = r->ctx->ngm;
             std::vector<double> gx(n);
             r->g(r->user, n, r->ctx->geo.xstar.data(), gx.data());
-            if (int rc = bae_set_rhs(r->ctx, 1, gx.data(), nullptr); rc != BAE_OK)
-                throw Error{rc, bae_last_error()};
+            if (int rc = bae_set_rhs(r->ctx, 1, gx.data(), nullptr); rc != BAE_OK) throw Error{rc, bae_last_error()};
         } catch (const Error& e) {
-            if (r->ctx) bae_destroy(r->ctx);
+            fail_code = e.code;
+            fail_msg = e.msg;
+        } catch (const std::bad_alloc&) {
+            fail_code = BAE_ERR_OOM;
+            fail_msg = "host allocation failed during set-up";
+        } catch (const std::exception& e) {
+            fail_code = BAE_ERR_ARG;
+            fail_msg = std::string("set-up: ") + e.what();
+        }
+        if (fail_code != BAE_OK && r->ctx) {
+            bae_destroy(r->ctx);
             r->ctx = nullptr;
-            std::lock_guard<std::mutex> lk(s->mu);
-            s->waiting.pop_front();
-            fail(s, r, e.code, e.msg);
-            s->cv_done.notify_all();
-            continue;
         }
         std::lock_guard<std::mutex> lk(s->mu);
-        s->waiting.pop_front();
-        r->state = Q_RUNNING;
-        r->t_admit = s->now();
-        s->used += r->bytes;
-        s->stats.admitted++;
-        s->stats.peak_bytes = std::max<int64_t>(s->stats.peak_bytes, s->used);
-        fresh.push_back(r);
+        s->in_setup--;
+        if (fail_code != BAE_OK) {
+            s->used -= r->bytes;
+            fail(s, r, fail_code, fail_msg);
+            s->cv_done.notify_all();
+            s->cv_setup.notify_all();
+            continue;
+        }
+        s->ready.push_back(r);
+        s->cv_work.notify_all();
     }
-    return fresh;
 }
 
 void scheduler(bae_server* s) {
@@ -159,18 +192,14 @@ void scheduler(bae_server* s) {
         {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv_work.wait_for(lk, std::chrono::milliseconds(20), [&] {
-                return s->stop || !s->waiting.empty() || !s->running.empty();
+                return (s->stop && s->in_setup == 0) || !s->ready.empty() || !s->running.empty();
             });
-            if (s->stop && s->running.empty() && s->waiting.empty()) return;
+            if (s->stop && s->running.empty() && s->ready.empty() && s->in_setup == 0) return;
         }
-        std::vector<std::shared_ptr<Req>> fresh;
-        try {
-            fresh = admit(s);
-        } catch (...) {
-        }
-        std::vector<std::shared_ptr<Req>> run;
+        std::vector<std::shared_ptr<Req>> fresh, run;
         {
             std::lock_guard<std::mutex> lk(s->mu);
+            fresh.swap(s->ready);
             s->running.insert(s->running.end(), fresh.begin(), fresh.end());
             run = s->running;
             s->stats.max_active = std::max<int64_t>(s->stats.max_active, (int64_t)run.size());
@@ -250,6 +279,7 @@ void scheduler(bae_server* s) {
                 s->used -= r->bytes;
                 s->stats.completed++;
             }
+            s->cv_setup.notify_all();   // slots and memory were released
             std::vector<bae_ctx*> members;
             for (auto& r : keep) members.push_back(r->ctx);
             batch_set_members(s->engine, members);
@@ -269,6 +299,7 @@ void scheduler(bae_server* s) {
             }
             s->running.clear();
             s->cv_done.notify_all();
+            s->cv_setup.notify_all();
         }
     }
 }
@@ -295,6 +326,7 @@ int bae_server_create(const bae_server_options* opt, bae_server** out) {
         s->engine = batch_engine_new(s->opt.device, nullptr);
         s->t0 = clock_t_::now();
         s->thread = std::thread(scheduler, s.get());
+        s->setup_thread = std::thread(setup_loop, s.get());
         *out = s.release();
     });
 }
@@ -321,7 +353,7 @@ int bae_server_submit(bae_server* s, const bae_request* req, uint64_t* ticket) {
         s->all[r->ticket] = r;
         s->stats.submitted++;
         *ticket = r->ticket;
-        s->cv_work.notify_one();
+        s->cv_setup.notify_all();
     });
 }
 
@@ -363,6 +395,16 @@ int bae_server_wait(bae_server* s, uint64_t ticket, double timeout_s, bae_result
     return rc != BAE_OK ? rc : status;
 }
 
+int bae_server_poll(bae_server* s, uint64_t ticket, int32_t* state) {
+    return guard([&] {
+        if (!s || !state) throw Error{BAE_ERR_ARG, "null argument"};
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->all.find(ticket);
+        if (it == s->all.end()) throw Error{BAE_ERR_ARG, "unknown ticket"};
+        *state = it->second->state;
+    });
+}
+
 int bae_server_fetch(bae_server* s, uint64_t ticket, double* q, int64_t q_cap, double* u_gamma, int64_t u_cap) {
     return guard([&] {
         if (!s) throw Error{BAE_ERR_ARG, "null server"};
@@ -399,8 +441,10 @@ int bae_server_destroy(bae_server* s) {
         for (auto& r : s->waiting) fail(s, r, BAE_ERR_STATE, "server shut down");
         s->waiting.clear();
         s->cv_work.notify_all();
+        s->cv_setup.notify_all();
         s->cv_done.notify_all();
     }
+    if (s->setup_thread.joinable()) s->setup_thread.join();   // a set-up in progress finishes first
     if (s->thread.joinable()) s->thread.join();
     (void)hipSetDevice(s->opt.device);
     batch_engine_delete(s->engine);

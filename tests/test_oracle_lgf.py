@@ -151,3 +151,18 @@ def test_yukawa_far_field_form():
     x = (40 ** 2 * 25 ** 2 + 25 ** 2 * 10 ** 2 + 10 ** 2 * 40 ** 2) / r ** 4
     q2 = 1 / (4 * math.pi * r) * (1 + (1 - 5 * x) / (4 * r * r))
     assert abs(form(n, 0.0) - q2) < 1e-15 * q2 and abs(q2 / t0(n) - 1) < 1e-6
+
+
+def test_the_257_star_table():
+    # The table the 257^3 modified-Helmholtz parity cases read (kappa^2 = 10, h = 1/256,
+    # offsets to 238): the stencil identity on every entry, QUADPACK's adaptive rule at
+    # large offsets and mpmath at one off-axis offset.
+    s = 10.0 / 256 ** 2
+    t = lgf.LGFTable(238, s)
+    _, res = t.stencil_residual()
+    assert np.abs(res).max() < 2e-15
+    for n in [(237, 0, 0), (200, 150, 3), (120, 120, 120), (238, 238, 238), (61, 17, 5), (238, 1, 0)]:
+        e = lgf.lgf_entry(n, s, R=238)
+        assert abs(t(np.array(n)) - e) <= 1e-13 * e, n
+    ref = mp_lgf((90, 40, 7), s, dps=20)
+    assert abs(t(np.array((90, 40, 7))) - ref) <= 1e-13 * ref

@@ -166,6 +166,17 @@ int64_t bae_lgf_table_size(int32_t R);
  * R in [0, 4096]; s finite and >= 0, else BAE_ERR_ARG.  Runs on `stream`, asynchronous.
  */
 int bae_lgf_table(double s, int32_t R, double* out_dev, void* stream);
+/*
+ * bae_lgf_table for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same kernels and the
+ * same table, with their scratch (quadrature nodes, weights and scaled Bessel values) in a
+ * static device array of 8.9 MB that each GPU the library runs on holds until the process
+ * ends; no hipMalloc, hipFree or stream synchronisation, asynchronous on `stream` (a stream
+ * of the current device).  R in [0, 2048] (BAE_ERR_ARG beyond: the scratch holds the rule
+ * for at most that radius); s finite and >= 0.  Every call on one GPU shares that GPU's
+ * scratch: calls that overlap on one GPU (other streams, other threads) race.
+ */
+int bae_lgf_table_noalloc(double s, int32_t R, double* out_dev, void* stream);
 
 /* ------------------------------------------------------------------ context (Alg. 1 setup) */
 /*

@@ -118,6 +118,7 @@ def load_library():
         "bae_last_error": (C.c_char_p, []),
         "bae_lgf_table_size": (C.c_int64, [C.c_int32]),
         "bae_lgf_table": (C.c_int, [C.c_double, C.c_int32, _P, _P]),
+        "bae_lgf_table_noalloc": (C.c_int, [C.c_double, C.c_int32, _P, _P]),
         "bae_create": (C.c_int, [C.POINTER(Grid), C.POINTER(LevelSet), C.POINTER(Options), C.POINTER(_P)]),
         "bae_destroy": (C.c_int, [_P]),
         "bae_get_sizes": (C.c_int, [_P, C.POINTER(Sizes)]),
@@ -196,6 +197,12 @@ def lgf_table(s, R, out, stream=None):
     """FP64 LGF table G_s for 0 <= a <= b <= c <= R into the device tensor `out`."""
     assert out.dtype.is_floating_point and out.element_size() == 8 and out.numel() >= lgf_table_size(R)
     _check(load_library().bae_lgf_table(float(s), int(R), _dptr(out), _stream(stream)))
+
+
+def lgf_table_noalloc(s, R, out, stream=None):
+    """bae_lgf_table_noalloc: the same table, scratch in the library's static device array."""
+    assert out.dtype.is_floating_point and out.element_size() == 8 and out.numel() >= lgf_table_size(R)
+    _check(load_library().bae_lgf_table_noalloc(float(s), int(R), _dptr(out), _stream(stream)))
 
 
 class Context:

@@ -742,6 +742,14 @@ int bae_lgf_table(double s, int32_t R, double* out_dev, void* stream) {
     });
 }
 
+int bae_lgf_table_noalloc(double s, int32_t R, double* out_dev, void* stream) {
+    return guard([&] {
+        if (!out_dev || R < 0 || !(s >= 0.0) || !std::isfinite(s))
+            throw Error{BAE_ERR_ARG, "bae_lgf_table_noalloc: bad argument"};
+        lgf_table_generate_noalloc(s, R, out_dev, (hipStream_t)stream);
+    });
+}
+
 int bae_create(const bae_grid* grid, const bae_levelset* ls, const bae_options* opt, bae_ctx** out) {
     return guard([&] {
         if (!grid || !ls || !out) throw Error{BAE_ERR_ARG, "bae_create: null argument"};

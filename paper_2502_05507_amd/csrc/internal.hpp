@@ -49,6 +49,10 @@ std::vector<int32_t> morton_order(const int32_t* pts, int64_t count, const int l
 int64_t table_size(int R);
 // FP64 table G_s for 0<=a<=b<=c<=R into out (device), on stream.
 void lgf_table_generate(double s, int R, double* out, hipStream_t stream);
+// The same with no allocation: scratch in a static device array (R <= kNoAllocMaxR);
+// asynchronous on stream; calls that overlap on one GPU race on the scratch.
+constexpr int kNoAllocMaxR = 2048;
+void lgf_table_generate_noalloc(double s, int R, double* out, hipStream_t stream);
 
 // ------------------------------------------------------------------ LGF sum (device)
 // Points are grouped in blocks of kSourceBlock consecutive (Morton-ordered) points; each

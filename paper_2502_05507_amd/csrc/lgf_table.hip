@@ -18,8 +18,9 @@
 //     (B stored node-major so consecutive a are coalesced) plus the tail series.
 // Table layout: sorted triple a <= b <= c at index c(c+1)(c+2)/6 + b(b+1)/2 + a (the
 // 1/48 symmetry of Sec. 4).
+#include <array>
 #include <cmath>
-#include <vector>
+#include <mutex>
 
 #include "internal.hpp"
 
@@ -32,9 +33,7 @@ constexpr int kTail = 10;        // asymptotic terms per Bessel factor
 constexpr double kULo = -40.0;
 
 // Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_n.
-void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
-    x.resize(n);
-    w.resize(n);
+void gauss_legendre(int n, double* x, double* w) {
     for (int i = 0; i < n; ++i) {
         double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
         for (int it = 0; it < 100; ++it) {
@@ -68,6 +67,34 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
 struct TailParams {
     double J[3 * kTail + 1];   // (4 pi)^-3/2 2^-k int_T^inf e^{-st} t^{-3/2-k} dt
 };
+
+// The composite rule in u = ln t: kGL-point panels of width 4 on [kULo, -8] (n_lo of them),
+// then of width 1.5 from -8, the last one ending at u_hi = ln T* (n_hi of them).
+struct Rule {
+    double gx[kGL], gw[kGL];   // Gauss-Legendre on [-1, 1]
+    double s, u_hi;
+    int n_lo, n_hi;
+};
+
+// Node q of the rule: t_q = e^u and the weight of dt = t du with the factor e^{-s t}.
+__global__ void nodes_kernel(const Rule rule, int Q, double* __restrict__ t, double* __restrict__ w) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= Q) return;
+    const int p = q / kGL, i = q % kGL;
+    double lo, hi;
+    if (p < rule.n_lo) {
+        lo = kULo + 4.0 * p;
+        hi = p + 1 < rule.n_lo ? lo + 4.0 : -8.0;
+    } else {
+        const int k = p - rule.n_lo;
+        lo = -8.0 + 1.5 * k;
+        hi = k + 1 < rule.n_hi ? lo + 1.5 : rule.u_hi;
+    }
+    const double u = 0.5 * (hi - lo) * rule.gx[i] + 0.5 * (hi + lo);
+    const double tq = exp(u);
+    t[q] = tq;
+    w[q] = 0.5 * (hi - lo) * rule.gw[i] * tq * exp(-rule.s * tq);
+}
 
 // int_T^inf exp(-s t) t^{-3/2-k} dt for k = 0..kmax (host).
 void tail_moments(double s, double T, int kmax, double* J) {
@@ -154,52 +181,95 @@ __global__ void table_kernel(const double* __restrict__ B, const double* __restr
 
 int64_t table_size(int R) { return (int64_t)(R + 1) * (R + 2) * (R + 3) / 6; }
 
-void lgf_table_generate(double s, int R, double* out, hipStream_t stream) {
+// Host part of the rule for radius R (no heap allocation): T* = 8 R^2 + 64.
+static void make_rule(double s, int R, Rule& rule, TailParams& tp, int& Q) {
     const double T = 8.0 * R * (double)R + 64.0;
-    const double uhi = std::log(T);
-    std::vector<double> gx, gw;
-    gauss_legendre(kGL, gx, gw);
-    std::vector<double> edges;
-    for (double u = kULo; u < -8.0 - 1e-12; u += 4.0) edges.push_back(u);
-    for (double u = -8.0; u < uhi - 1e-9; u += 1.5) edges.push_back(u);
-    edges.push_back(uhi);
-    std::vector<double> tq, wq;
-    for (size_t p = 0; p + 1 < edges.size(); ++p) {
-        const double lo = edges[p], hi = edges[p + 1];
-        for (int i = 0; i < kGL; ++i) {
-            const double u = 0.5 * (hi - lo) * gx[i] + 0.5 * (hi + lo);
-            const double t = std::exp(u);
-            tq.push_back(t);
-            wq.push_back(0.5 * (hi - lo) * gw[i] * t * std::exp(-s * t));  // dt = t du, e^{-st}
-        }
-    }
-    const int Q = (int)tq.size();
-    TailParams tp;
+    rule.s = s;
+    rule.u_hi = std::log(T);
+    gauss_legendre(kGL, rule.gx, rule.gw);
+    rule.n_lo = 0;
+    for (double u = kULo; u < -8.0 - 1e-12; u += 4.0) rule.n_lo++;
+    rule.n_hi = 0;
+    for (double u = -8.0; u < rule.u_hi - 1e-9; u += 1.5) rule.n_hi++;
+    Q = (rule.n_lo + rule.n_hi) * kGL;
     double J[3 * kTail + 1];
     tail_moments(s, T, 3 * kTail, J);
     const double c0 = std::pow(4.0 * M_PI, -1.5);
     for (int k = 0; k <= 3 * kTail; ++k) tp.J[k] = c0 * std::ldexp(J[k], -k);
+}
 
-    double *dt = nullptr, *dw = nullptr, *dB = nullptr;
-    if (hipMalloc((void**)&dt, sizeof(double) * Q) != hipSuccess ||
-        hipMalloc((void**)&dw, sizeof(double) * Q) != hipSuccess ||
-        hipMalloc((void**)&dB, sizeof(double) * (int64_t)Q * (R + 1)) != hipSuccess) {
-        (void)hipFree(dt);
-        (void)hipFree(dw);
-        throw Error{BAE_ERR_OOM, "LGF table scratch allocation failed"};
-    }
-    BAE_HIP_CHECK(hipMemcpyAsync(dt, tq.data(), sizeof(double) * Q, hipMemcpyHostToDevice, stream));
-    BAE_HIP_CHECK(hipMemcpyAsync(dw, wq.data(), sizeof(double) * Q, hipMemcpyHostToDevice, stream));
+// The three launches on `stream`; scratch: 2 Q + Q (R + 1) doubles (nodes, weights, the
+// scaled Bessel values B[q][n]).
+static void launch_table(const Rule& rule, const TailParams& tp, int Q, int R, double* scratch, double* out,
+                         hipStream_t stream) {
+    double* dt = scratch;
+    double* dw = scratch + Q;
+    double* dB = scratch + 2 * (int64_t)Q;
+    nodes_kernel<<<(Q + 63) / 64, 64, 0, stream>>>(rule, Q, dt, dw);
+    BAE_HIP_CHECK(hipGetLastError());
     bessel_kernel<<<(Q + 63) / 64, 64, 0, stream>>>(dt, Q, R, dB);
     BAE_HIP_CHECK(hipGetLastError());
     const int64_t E = table_size(R);
     table_kernel<<<(unsigned)((E + 255) / 256), 256, 0, stream>>>(dB, dw, Q, R, E, tp, out);
     BAE_HIP_CHECK(hipGetLastError());
-    // scratch and the pageable host vectors must outlive the kernels
-    BAE_HIP_CHECK(hipStreamSynchronize(stream));
-    BAE_HIP_CHECK(hipFree(dB));
-    BAE_HIP_CHECK(hipFree(dw));
-    BAE_HIP_CHECK(hipFree(dt));
+}
+
+void lgf_table_generate(double s, int R, double* out, hipStream_t stream) {
+    Rule rule;
+    TailParams tp;
+    int Q = 0;
+    make_rule(s, R, rule, tp, Q);
+    double* scratch = nullptr;
+    if (hipMalloc((void**)&scratch, sizeof(double) * (2 * (int64_t)Q + (int64_t)Q * (R + 1))) != hipSuccess)
+        throw Error{BAE_ERR_OOM, "LGF table scratch allocation failed"};
+    try {
+        launch_table(rule, tp, Q, R, scratch, out, stream);
+    } catch (...) {
+        (void)hipStreamSynchronize(stream);
+        (void)hipFree(scratch);
+        throw;
+    }
+    BAE_HIP_CHECK(hipStreamSynchronize(stream));   // the scratch must outlive the kernels
+    BAE_HIP_CHECK(hipFree(scratch));
+}
+
+// ------------------------------------------------------------------ allocation-free form
+// For callers that cannot allocate (graph capture, serving loops): the same kernels with
+// their scratch in a file-scope device array that each GPU holds until the process ends.
+// Host code reaches it only through the address hipGetSymbolAddress returns on that
+// device; the array's own name is a host-side stand-in there.
+constexpr int kNoAllocQMax = 540;   // nodes of the rule for any R <= 4096 (at most 520)
+constexpr int64_t kNoAllocDoubles = 2 * (int64_t)kNoAllocQMax + (int64_t)kNoAllocQMax * (kNoAllocMaxR + 1);
+static __device__ __align__(256) double scratch[kNoAllocDoubles];   // 8.9 MB
+
+static std::mutex g_scratch_mu;
+static std::array<double*, 64> g_scratch_ptr{};   // per device ordinal
+
+static double* scratch_on(int device) {
+    if (device < 0 || device >= (int)g_scratch_ptr.size()) throw Error{BAE_ERR_ARG, "device ordinal out of range"};
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));   // this device's copy
+        if (e != hipSuccess || !p)
+            throw Error{BAE_ERR_HIP, std::string("scratch address: ") + hipGetErrorString(e)};
+        g_scratch_ptr[device] = (double*)p;
+    }
+    return g_scratch_ptr[device];
+}
+
+void lgf_table_generate_noalloc(double s, int R, double* out, hipStream_t stream) {
+    if (R > kNoAllocMaxR)
+        throw Error{BAE_ERR_ARG, "bae_lgf_table_noalloc: R = " + std::to_string(R) + " exceeds its scratch (R <= " +
+                                     std::to_string(kNoAllocMaxR) + ")"};
+    Rule rule;
+    TailParams tp;
+    int Q = 0;
+    make_rule(s, R, rule, tp, Q);
+    if (Q > kNoAllocQMax) throw Error{BAE_ERR_ARG, "bae_lgf_table_noalloc: quadrature rule exceeds its scratch"};
+    int device = 0;
+    BAE_HIP_CHECK(hipGetDevice(&device));
+    launch_table(rule, tp, Q, R, scratch_on(device), out, stream);
 }
 
 }  // namespace bae

@@ -43,6 +43,7 @@ def test_null_arguments_are_rejected():
     assert lib.bae_create(None, None, None, None) == -1          # BAE_ERR_ARG
     assert b"null" in lib.bae_last_error()
     assert lib.bae_lgf_table(0.0, -1, None, None) == -1
+    assert lib.bae_lgf_table_noalloc(0.0, 8, None, None) == -1
     assert lib.bae_lgf_sum_repeat(None, None, 1, 1, 1, None) == -1
     assert lib.bae_destroy(None) == 0
 

@@ -69,7 +69,11 @@ def kernel_hash(files=("paper_2502_05507_amd/csrc/lgf_sum.hip", "paper_2502_0550
 # profile_star` / `profile`, profiles/*_counters.md), valid only for the kernel sources they
 # were taken on (their hash): HBM bytes per launch (FETCH_SIZE x f + WRITE_SIZE x w, the
 # factors calibrated on copies of known size), VALU-issue and matrix-core-busy shares.
-MEASURED = {}
+MEASURED = {
+    "lgf_sum_mfma_helmholtz_star_257": {"sources_sha256_16": "f00872bff75eb908",
+                                        "bytes": (1.39173e7 * 2.0 + 1.069e6 * 1.0) * 1024,
+                                        "valu_issue": 0.807, "mfma_busy": 0.232},
+}
 
 
 def measured(key):
@@ -424,15 +428,16 @@ def ellipsoid(args, torch, P, W, steps=None, warmup=None, extra=False):
 
 
 def formulations(args, torch, P, W):
-    """Single- against double-layer formulation (Sec. 3.4) on the 129^3 Poisson ellipsoid:
-    iterations and solve time of each, FP64 and refined, and the difference of their u_gamma."""
+    """Double-layer, single-layer (Sec. 3.4) and direct (Sec. 3.1) formulations on the 129^3
+    Poisson ellipsoid: iterations and solve time of each, FP64 and refined, and the difference
+    of their u_gamma."""
     p = W.poisson_ellipsoid(args.nodes)
     out = {"workload": f"formulations_poisson_ellipsoid_{args.nodes}^3"}
     with P.Context.from_problem(p, max_krylov=400) as ctx:
         xs, _, _ = ctx.boundary_points()
         ctx.set_rhs(p.g(xs), p.f_grid())
         ug = {}
-        for lname, layer in (("double", P.LAYER_DOUBLE), ("single", P.LAYER_SINGLE)):
+        for lname, layer in (("double", P.LAYER_DOUBLE), ("single", P.LAYER_SINGLE), ("direct", P.LAYER_DIRECT)):
             for pname, prec in (("fp64", P.SOLVE_FP64), ("fp32_refined", P.SOLVE_FP32_REFINED)):
                 ctx.solve(prec, tol=1e-10, formulation=layer)
                 lat = []

@@ -63,6 +63,8 @@ extern "C" {
 
 #define BAE_LAYER_DOUBLE 0        /* double-layer formulation (Sec. 3.4 eq. "double_bae") */
 #define BAE_LAYER_SINGLE 1        /* single-layer formulation (Sec. 3.4)                 */
+#define BAE_LAYER_DIRECT 2        /* direct formulation (Sec. 3.1, eq. "direct_sys"): the
+                                     unknowns are v on gamma itself                      */
 
 #define BAE_PARTICULAR_FREE 0     /* u_p: the free-space volume potential (LGF sum)     */
 #define BAE_PARTICULAR_BOX 1      /* u_p: Algorithm 1's finite-grid G_h[chi_{M+} f]      */
@@ -129,7 +131,14 @@ typedef struct bae_solve_params {
                                   BAE_LAYER_SINGLE: (Phi+ S+ + Phi- S-) q = b with the
                                   single layer S(m,n) = G(m - n) on gamma- sources
                                   (Sec. 3.4); the density, u_gamma and u are those of
-                                  the chosen layer                                    */
+                                  the chosen layer.
+                                  BAE_LAYER_DIRECT: the direct system (Sec. 3.1)
+                                  [(I - P+) v+ - P- v- ; Phi+ v+ + Phi- v-] = [0 ; b] for v
+                                  on gamma ([gamma+; gamma-], the "density" returned, of
+                                  length |gamma|); u_gamma = v + u_p.  Its first use on a
+                                  context sets up the gamma x gamma sum and |gamma|-long
+                                  Krylov vectors (BAE_ERR_STATE while the context belongs
+                                  to a batch)                                          */
     const double* x0_dev;      /* initial densities [nrhs][|gamma-|] (device, FP64), or NULL
                                   for x0 = 0 (the paper's choice, Sec. 4); GMRES then solves
                                   A d = b - A x0 and returns x0 + d.  Read during the solve
@@ -279,6 +288,15 @@ int bae_apply_double_layer(bae_ctx* ctx, const double* q_dev, double* v_dev, int
  */
 int bae_apply_single_layer(bae_ctx* ctx, const double* q_dev, double* v_dev, int32_t nrhs,
                            int32_t precision, void* stream);
+/*
+ * The direct system's operator (Sec. 3.1): y = [v+ - P+ v+ - P- v- ; Phi+ v+ + Phi- v-] with
+ * (P+ v+)(p*) = -sum_edges G(q - p*) v(p), (P- v-)(p*) = sum_edges G(p - p*) v(q) over the
+ * neighbour pairs p in gamma+, q in gamma-.  v_dev, y_dev: [nrhs][|gamma|] FP64 device,
+ * [gamma+; gamma-] order; precision of the LGF sum as in bae_apply_double_layer.  The first
+ * call sets up the direct formulation (see bae_solve_params.formulation).  Asynchronous on
+ * `stream` after that set-up.
+ */
+int bae_apply_direct(bae_ctx* ctx, const double* v_dev, double* y_dev, int32_t nrhs, int32_t precision, void* stream);
 /* The BAE operator A q = Phi+ D+ q + Phi- D- q (Sec. 3.4, eq. "double_bae").
    q_dev, aq_dev: [nrhs][|gamma-|] FP64 device. */
 int bae_apply_operator(bae_ctx* ctx, const double* q_dev, double* aq_dev, int32_t nrhs,

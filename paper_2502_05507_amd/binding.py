@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libbae.so")
 OK, NOT_CONVERGED = 0, 1
 PREC_FP64, PREC_FP32 = 0, 1
 SOLVE_FP64, SOLVE_FP32_REFINED = 0, 1
-LAYER_DOUBLE, LAYER_SINGLE = 0, 1
+LAYER_DOUBLE, LAYER_SINGLE, LAYER_DIRECT = 0, 1, 2
 PARTICULAR = {"free": 0, "box": 1}
 KINDS = {"sphere": 1, "ellipsoid": 2, "torus": 3, "star": 4, "sampled": 5}
 
@@ -142,6 +142,7 @@ def load_library():
         "bae_apply_double_layer": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P]),
         "bae_apply_operator": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P]),
         "bae_apply_single_layer": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P]),
+        "bae_apply_direct": (C.c_int, [_P, _P, _P, C.c_int32, C.c_int32, _P]),
         "bae_lgf_eval": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int32, _P]),
         "bae_sum_stats": (C.c_int, [_P, C.c_int32, _P]),
         "bae_lgf_sum_repeat": (C.c_int, [_P, _P, C.c_int32, C.c_int32, C.c_int32, _P]),
@@ -310,6 +311,7 @@ class Context:
         initial densities [nrhs][|gamma-|]."""
         p = self._params(precision, tol, maxit, inner_tol, max_outer, compute_grid, recycle_dim, formulation, x0)
         res = (Result * self.nrhs)()
+        self._formulation = int(formulation)
         rc = load_library().bae_solve(self._h, C.byref(p), res)
         _check(rc, allow_not_converged=True)
         return [r.as_dict() for r in res]
@@ -319,6 +321,7 @@ class Context:
         """bae_solve_async: ordered after `stream` (default: torch's current stream), returns at once."""
         p = self._params(precision, tol, maxit, inner_tol, max_outer, compute_grid, recycle_dim, formulation, x0)
         self._x0 = x0      # kept alive until the solve is collected
+        self._formulation = int(formulation)
         _check(load_library().bae_solve_async(self._h, C.byref(p), _stream(stream)))
 
     def solve_poll(self):
@@ -339,7 +342,7 @@ class Context:
         _check(fn(self._h, int(r), _dptr(out), _stream(stream)))
 
     def density_device(self, out, r=-1, stream=None):
-        self._device_out(load_library().bae_get_density_device, out, r, self.sizes["n_gamma_minus"], stream)
+        self._device_out(load_library().bae_get_density_device, out, r, self.density_length(), stream)
 
     def gamma_values_device(self, out, r=-1, stream=None):
         self._device_out(load_library().bae_get_gamma_values_device, out, r, self.sizes["n_targets"], stream)
@@ -347,8 +350,13 @@ class Context:
     def solution_device(self, out, r=-1, stream=None):
         self._device_out(load_library().bae_get_solution_device, out, r, int(np.prod(self.n)), stream)
 
+    def density_length(self):
+        """|gamma-| (layer potentials), or |gamma| after a direct-formulation solve."""
+        direct = getattr(self, "_formulation", 0) == LAYER_DIRECT
+        return self.sizes["n_targets"] if direct else self.sizes["n_gamma_minus"]
+
     def density(self, r=0):
-        q = np.empty(self.sizes["n_gamma_minus"])
+        q = np.empty(self.density_length())
         _check(load_library().bae_get_density(self._h, r, _ptr(q)))
         return q
 
@@ -382,6 +390,13 @@ class Context:
         assert q.is_contiguous() and v.is_contiguous()
         assert q.numel() == nrhs * self.sizes["n_gamma_minus"] and v.numel() == nrhs * self.sizes["n_targets"]
         _check(load_library().bae_apply_single_layer(self._h, _dptr(q), _dptr(v), nrhs, precision, _stream(stream)))
+
+    def apply_direct(self, v, y, precision=PREC_FP64, stream=None):
+        """y = the direct system's operator (Sec. 3.1) on device tensors v, y [nrhs][|gamma|] (float64)."""
+        nrhs = 1 if v.dim() == 1 else v.shape[0]
+        assert v.is_contiguous() and y.is_contiguous()
+        assert v.numel() == y.numel() == nrhs * self.sizes["n_targets"]
+        _check(load_library().bae_apply_direct(self._h, _dptr(v), _dptr(y), nrhs, precision, _stream(stream)))
 
     def apply_operator(self, q, aq, precision=PREC_FP64, stream=None):
         """aq = (Phi+ D+ + Phi- D-) q for device tensors [nrhs][|gamma-|] (float64)."""

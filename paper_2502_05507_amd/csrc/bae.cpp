@@ -12,6 +12,7 @@
 #include <memory>
 #include <mutex>
 #include <numeric>
+#include <unordered_map>
 
 #include "context.hpp"
 
@@ -81,31 +82,48 @@ void check_sum_error(bae_ctx* c) {
                              "since the last check are incomplete"};
 }
 
-static void apply_lgf(bae_ctx* c, const PointSet& T, const PointSet& S, const void* w, int nrhs, int prec,
-                      double* part, int64_t cap, int* chunks_out, hipStream_t st, const int32_t* skip = nullptr) {
-    *chunks_out = lgf_sum_launch(T, S, w, nrhs, prec, c->tabs, c->plan.plan, part, cap, c->sum_grid, st, skip);
+// The current operator's LGF sum at the gamma targets (its sources, weights, work list).
+static void apply_lgf(bae_ctx* c, const void* w, int nrhs, int prec, int* chunks_out, hipStream_t st,
+                      const int32_t* skip = nullptr) {
+    *chunks_out = lgf_sum_launch(c->T.ps, *c->op.S, w, nrhs, prec, c->tabs, c->op.plan->plan, c->part.as<double>(),
+                                 c->part_cap, c->sum_grid, st, skip);
 }
 
-// v = [D+ q; D- q] (external order), q [nrhs][ngm] with leading dimension ldq
+// v = [D+ q; D- q] (external order) for the layer potential of c->op (double or single
+// layer), q [nrhs][ngm] with leading dimension ldq
 static void double_layer(bae_ctx* c, const double* q, int64_t ldq, double* v, int64_t ldv, int nrhs, int prec,
                          hipStream_t st) {
-    launch_weights(*c->Bop, q, ldq, c->w.p, c->S.ps.padded, nrhs, prec, st);
+    launch_weights(*c->op.B, q, ldq, c->w.p, c->op.S->padded, nrhs, prec, st);
     int chunks = 0;
-    apply_lgf(c, c->T.ps, c->S.ps, c->w.p, nrhs, prec, c->part.as<double>(), c->part_cap, &chunks, st);
+    apply_lgf(c, c->w.p, nrhs, prec, &chunks, st);
     launch_reduce_scatter(c->part.as<double>(), chunks, c->nT, c->t_pos.as<int32_t>(), v, ldv, nrhs, 1.0, st);
 }
 
-// aq = Phi+ D+ q + Phi- D- q (the LGF sum skipped while *skip is set, when given)
+// The closing step of the operator from the chunk partials: the Dirichlet rows Phi+ v+ +
+// Phi- v- of the layer potential (Sec. 3.4), or for the direct formulation v+ + (the sum) on
+// gamma+ and the Dirichlet rows of v itself on gamma- (v: the operator's input).
+static void op_closure(bae_ctx* c, int chunks, const double* v, int64_t ldv, double* aq, int64_t lda, int nrhs,
+                       hipStream_t st) {
+    if (c->op.direct)
+        launch_direct_closure(c->part.as<double>(), chunks, c->nT, c->t_inv.as<int32_t>(), c->ngp,
+                              c->partner_dev.as<int32_t>(), c->cl_t.as<double>(), v, ldv, aq, lda, nrhs,
+                              c->vsum.as<double>(), st);
+    else
+        launch_closure(c->part.as<double>(), chunks, c->nT, c->cl, aq, lda, nrhs, c->vsum.as<double>(), st);
+}
+
+// aq = A q for the current operator: Phi+ D+ q + Phi- D- q (double / single layer) or the
+// direct system (the LGF sum skipped while *skip is set, when given)
 static void bae_operator(bae_ctx* c, const double* q, int64_t ldq, double* aq, int64_t lda, int nrhs, int prec,
                          hipStream_t st, const int32_t* skip = nullptr) {
-    launch_weights(*c->Bop, q, ldq, c->w.p, c->S.ps.padded, nrhs, prec, st);
+    launch_weights(*c->op.B, q, ldq, c->w.p, c->op.S->padded, nrhs, prec, st);
     int chunks = 0;
-    apply_lgf(c, c->T.ps, c->S.ps, c->w.p, nrhs, prec, c->part.as<double>(), c->part_cap, &chunks, st, skip);
-    launch_closure(c->part.as<double>(), chunks, c->nT, c->cl, aq, lda, nrhs, c->vsum.as<double>(), st);
+    apply_lgf(c, c->w.p, nrhs, prec, &chunks, st, skip);
+    op_closure(c, chunks, q, ldq, aq, lda, nrhs, st);
 }
 
 static void norms2(bae_ctx* c, const double* v, int64_t ldv, int nrhs, double* out_dev, hipStream_t st) {
-    launch_dots(v, 0, ldv, 1, v, ldv, c->ngm, nrhs, nullptr, c->dotpart.as<double>(), c->maxj, out_dev, 1, 0, st);
+    launch_dots(v, 0, ldv, 1, v, ldv, c->op.n, nrhs, nullptr, c->dotpart.as<double>(), c->maxj, out_dev, 1, 0, st);
 }
 
 struct GmresOut {
@@ -131,18 +149,102 @@ struct Recycle {
 };
 constexpr int kRecycleDefault = 64;
 
-// Selects the operator's layer potential for a scope (the double layer outside it).
+// Set-up of the direct formulation (Sec. 3.1), once per context: the boundary edges (p in
+// gamma+, q in gamma-, neighbours), the weights map of its gamma+ rows -- a source at q
+// carries +v(p), a source at p carries -v(q), summed over the edges, so that the LGF sum at
+// p* is sum_edges [G(q - p*) v(p) - G(p - p*) v(q)] -- over the targets' own point set, the
+// (gamma, gamma) work list, and vectors of |gamma| unknowns.
+static void ensure_direct(bae_ctx* c) {
+    if (c->direct_ready) return;
+    if (c->vec_cap < c->nT && c->batch_refs > 0)
+        throw Error{BAE_ERR_STATE, "a direct solve grows the context's vectors: not while it belongs to a batch"};
+    hipStream_t st = c->stream;
+    const Geometry& G = c->geo;
+    std::unordered_map<int64_t, int32_t> gp_at;
+    gp_at.reserve((size_t)c->ngp * 2);
+    auto lin = [&](const int32_t* v) { return ((int64_t)v[0] * G.n[1] + v[1]) * G.n[2] + v[2]; };
+    for (int64_t i = 0; i < c->ngp; ++i) gp_at[lin(&G.gp[3 * i])] = (int32_t)i;
+    static const int dirs[6][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+    std::vector<std::vector<std::pair<int32_t, double>>> rows(c->nT);   // by position in [gamma+; gamma-]
+    for (int64_t q = 0; q < c->ngm; ++q) {
+        const int32_t* v = &G.gm[3 * q];
+        for (const auto& d : dirs) {
+            const int32_t m[3] = {v[0] + d[0], v[1] + d[1], v[2] + d[2]};
+            if (m[0] < 0 || m[1] < 0 || m[2] < 0 || m[0] >= G.n[0] || m[1] >= G.n[1] || m[2] >= G.n[2]) continue;
+            if (!G.inside[lin(m)]) continue;
+            const auto it = gp_at.find(lin(m));
+            if (it == gp_at.end()) throw Error{BAE_ERR_GEOMETRY, "an M+ neighbour of gamma- is not in gamma+"};
+            rows[c->ngp + q].push_back({it->second, 1.0});
+            rows[it->second].push_back({(int32_t)(c->ngp + q), -1.0});
+        }
+    }
+    std::vector<int32_t> rowptr(c->nT + 1, 0), col, tinv(c->nT);
+    std::vector<double> coef;
+    for (int64_t i = 0; i < c->nT; ++i) {   // internal (Morton) target order
+        const int32_t j = c->T.perm[i];
+        tinv[j] = (int32_t)i;
+        for (const auto& e : rows[j]) {
+            col.push_back(e.first);
+            coef.push_back(e.second);
+        }
+        rowptr[i + 1] = (int32_t)col.size();
+    }
+    upload(c->csrd_rowptr, rowptr, st);
+    upload(c->csrd_col, col, st);
+    upload(c->csrd_coef, coef, st);
+    upload(c->t_inv, tinv, st);
+    c->Bd = CSR{c->nT, c->T.ps.padded, c->csrd_rowptr.as<int32_t>(), c->csrd_col.as<int32_t>(),
+                c->csrd_coef.as<double>()};
+    c->plan_dir.build(c->T.ps, c->T.ps, c->tabs, c->err_dev, c->wait_polls, st);
+    const int mr = c->max_rhs;
+    if (c->w.bytes < sizeof(double) * c->T.ps.padded * mr) c->w.alloc(sizeof(double) * std::max(c->T.ps.padded, c->S.ps.padded) * mr);
+    const int64_t pc = (int64_t)c->plan_dir.plan.chunks * c->nT * mr;
+    if (pc > c->part_cap) {
+        c->part.alloc(sizeof(double) * pc);
+        c->part_cap = pc;
+    }
+    c->bdir.alloc(sizeof(double) * c->nT * mr);
+    if (c->vec_cap < c->nT) {
+        const int64_t n = c->nT, m = c->K.m;
+        for (DevMem* d : {&c->x, &c->r, &c->tmp}) d->alloc(sizeof(double) * n * mr);
+        c->kV.alloc(sizeof(double) * (m + 1) * n * mr);
+        c->K.V = c->kV.as<double>();
+        c->dotpart.alloc(sizeof(double) * mr * (2 * (int64_t)c->maxj * dot_blocks(n) + norm_blocks(n)));
+        c->vec_cap = n;
+    }
+    BAE_HIP_CHECK(hipStreamSynchronize(st));
+    c->direct_ready = true;
+}
+
+// The double-layer operator (the default outside a solve).
+static void use_double_layer(bae_ctx* c) {
+    c->op = bae_ctx::OpView{&c->B, &c->S.ps, &c->plan, c->ngm, false};
+    c->K.n = c->ngm;
+    c->K.ld_rhs = (int64_t)(c->K.m + 1) * c->ngm;
+}
+
+// Selects the operator of a formulation for a scope (the double layer outside it): the
+// single layer's weights map over the same sources, or the direct formulation's map, sources
+// and unknowns; the Krylov vectors take the operator's length.
 struct LayerScope {
     bae_ctx* c;
     LayerScope(bae_ctx* ctx, int32_t formulation) : c(ctx) {
-        c->Bop = formulation == BAE_LAYER_SINGLE ? &c->B1 : &c->B;
+        if (formulation == BAE_LAYER_DIRECT) {
+            ensure_direct(c);
+            c->op = bae_ctx::OpView{&c->Bd, &c->T.ps, &c->plan_dir, c->nT, true};
+        } else {
+            c->op = bae_ctx::OpView{formulation == BAE_LAYER_SINGLE ? &c->B1 : &c->B, &c->S.ps, &c->plan, c->ngm,
+                                    false};
+        }
+        c->K.n = c->op.n;
+        c->K.ld_rhs = (int64_t)(c->K.m + 1) * c->op.n;
     }
-    ~LayerScope() { c->Bop = &c->B; }
+    ~LayerScope() { use_double_layer(c); }
 };
 
 static void build_recycle(bae_ctx* c, int nrhs, const std::vector<int>& skip, int cap, Recycle& rc, hipStream_t st) {
     KrylovState& K = c->K;
-    const int64_t n = c->ngm;
+    const int64_t n = c->op.n;
     rc.p = 0;
     std::vector<int32_t> kd(nrhs);
     BAE_HIP_CHECK(hipMemcpyAsync(kd.data(), K.kdone, sizeof(int32_t) * nrhs, hipMemcpyDeviceToHost, st));
@@ -210,7 +312,7 @@ static void build_recycle(bae_ctx* c, int nrhs, const std::vector<int>& skip, in
 // x += U C'r and r -= C C'r (the part of r in the span of C), skipped RHS left alone.
 static void recycle_project(bae_ctx* c, const Recycle& rc, int nrhs, const std::vector<int>& skip, double* x,
                             double* r, hipStream_t st) {
-    const int64_t n = c->ngm;
+    const int64_t n = c->op.n;
     DevMem c0, pn;
     c0.alloc(sizeof(double) * 2 * nrhs * rc.p);
     launch_dots(rc.C, n, rc.ld, rc.p, r, n, n, nrhs, nullptr, c->dotpart.as<double>(), c->maxj, c0.as<double>(),
@@ -240,7 +342,7 @@ static GmresOut gmres(bae_ctx* c, const double* r0, int nrhs, int prec, double t
                       const std::vector<int>& skip, double* xout, bool accumulate, hipStream_t st,
                       int64_t* matvecs, const Recycle* rc = nullptr) {
     KrylovState& K = c->K;
-    const int64_t n = c->ngm;
+    const int64_t n = c->op.n;
     const int m = std::min(maxit, K.m);
     norms2(c, r0, n, nrhs, c->nrm.as<double>(), st);
     launch_gmres_init(r0, n, K, n, c->nrm.as<double>(), nrhs, st);
@@ -280,13 +382,12 @@ static GmresOut gmres(bae_ctx* c, const double* r0, int nrhs, int prec, double t
     double* pA = c->dotpart.as<double>();
     double* pB = pA + (int64_t)nrhs * c->maxj * dot_blocks(n);
     double* pN = pB + (int64_t)nrhs * c->maxj * dot_blocks(n);
-    launch_weights(*c->Bop, K.V, K.ld_rhs, c->w.p, c->S.ps.padded, nrhs, prec, st);
+    launch_weights(*c->op.B, K.V, K.ld_rhs, c->w.p, c->op.S->padded, nrhs, prec, st);
     int k = 0;
     for (; k < m; ++k) {
         int chunks = 0;
-        apply_lgf(c, c->T.ps, c->S.ps, c->w.p, nrhs, prec, c->part.as<double>(), c->part_cap, &chunks, st,
-                  lagged ? K.done : nullptr);
-        launch_closure(c->part.as<double>(), chunks, c->nT, c->cl, wv, n, nrhs, c->vsum.as<double>(), st);
+        apply_lgf(c, c->w.p, nrhs, prec, &chunks, st, lagged ? K.done : nullptr);
+        op_closure(c, chunks, K.V + (int64_t)k * n, K.ld_rhs, wv, n, nrhs, st);
         (*matvecs)++;
         if (rc) {   // w -= C (C'w), the coefficients kept for the final update
             double* sl = rc->slices + (int64_t)k * nrhs * rc->p * dot_blocks(n);
@@ -302,7 +403,7 @@ static GmresOut gmres(bae_ctx* c, const double* r0, int nrhs, int prec, double t
             launch_dot_slices(K.V, n, K.ld_rhs, k + 1, wv, n, n, nrhs, K.done, pB, c->maxj, st);
             launch_subtract_combination(K.V, n, K.ld_rhs, pB, c->maxj, k + 1, n, nrhs, K.done, wv, n, pN, st);
         }
-        launch_finish(K, wv, n, pA, two_pass ? pB : nullptr, c->maxj, pN, k, tol, *c->Bop, c->w.p, c->S.ps.padded,
+        launch_finish(K, wv, n, pA, two_pass ? pB : nullptr, c->maxj, pN, k, tol, *c->op.B, c->w.p, c->op.S->padded,
                       prec, nrhs, lagged ? c->flags_dev + (k & 1) : nullptr, st);
         if (lagged) {
             BAE_HIP_CHECK(hipEventRecord(ev[k & 1], st));
@@ -393,8 +494,11 @@ static GmresOut gmres(bae_ctx* c, const double* r0, int nrhs, int prec, double t
     return out;
 }
 
+// The right-hand side of the current operator's system: b, or [0; b] for the direct one.
+static const double* rhs_vector(bae_ctx* c) { return c->op.direct ? c->bdir.as<double>() : c->b.as<double>(); }
+
 static std::vector<double> host_norms(bae_ctx* c, const double* v, int nrhs, hipStream_t st) {
-    norms2(c, v, c->ngm, nrhs, c->nrm.as<double>(), st);
+    norms2(c, v, c->op.n, nrhs, c->nrm.as<double>(), st);
     std::vector<double> h(nrhs);
     BAE_HIP_CHECK(hipMemcpyAsync(h.data(), c->nrm.p, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
     BAE_HIP_CHECK(hipStreamSynchronize(st));
@@ -405,10 +509,10 @@ static std::vector<double> host_norms(bae_ctx* c, const double* v, int nrhs, hip
 // r = b - A64 x ; returns ||r|| / ||b|| per RHS
 static std::vector<double> residual(bae_ctx* c, int nrhs, const std::vector<double>& bn, hipStream_t st,
                                     int64_t* matvecs) {
-    const int64_t n = c->ngm;
+    const int64_t n = c->op.n;
     bae_operator(c, c->x.as<double>(), n, c->tmp.as<double>(), n, nrhs, BAE_PREC_FP64, st);
     (*matvecs)++;
-    BAE_HIP_CHECK(hipMemcpyAsync(c->r.p, c->b.p, sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, st));
+    BAE_HIP_CHECK(hipMemcpyAsync(c->r.p, rhs_vector(c), sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, st));
     launch_axpby(-1.0, c->tmp.as<double>(), n, 1.0, c->r.as<double>(), n, n, nrhs, st);
     std::vector<double> rn = host_norms(c, c->r.as<double>(), nrhs, st);
     check_sum_error(c);
@@ -545,7 +649,6 @@ bae_ctx* create_context(const bae_grid& gridv, const bae_options* opt, Geometry&
             c->B1 = CSR{c->nS, c->S.ps.padded, c->csr1_rowptr.as<int32_t>(), c->csr1_col.as<int32_t>(),
                         c->csr1_coef.as<double>()};
         }
-        c->Bop = &c->B;
         // closure rows
         std::vector<int32_t> ctq(c->ngm), ctp(c->ngm);
         for (int64_t q = 0; q < c->ngm; ++q) {
@@ -625,6 +728,8 @@ bae_ctx* create_context(const bae_grid& gridv, const bae_options* opt, Geometry&
         K.done = c->kdone.as<int32_t>();
         K.kdone = c->kkdone.as<int32_t>();
         c->maxj = m + 1;
+        c->vec_cap = n;
+        use_double_layer(c.get());
         c->hA.alloc(sizeof(double) * c->maxj * mr);
         c->hB.alloc(sizeof(double) * c->maxj * mr);
         c->nrm.alloc(sizeof(double) * c->maxj * mr);
@@ -1005,12 +1110,15 @@ static void set_rhs_device_impl(bae_ctx* c, int32_t nrhs, const double* g_dev, c
 static void grid_solution(bae_ctx* c, int nrhs, hipStream_t st) {
     const Geometry& G = c->geo;
     ensure_lin(c);
-    const int64_t nm = c->Mp.ps.count, n = c->ngm;
+    const int64_t nm = c->Mp.ps.count, n = c->op.n;
     const int64_t N3 = (int64_t)G.n[0] * G.n[1] * G.n[2];
     DevMem um;
     um.alloc(sizeof(double) * nm * nrhs);
-    launch_weights(*c->Bop, c->x.as<double>(), n, c->w.p, c->S.ps.padded, nrhs, BAE_PREC_FP64, st);
-    lgf_sum_to(c, c->Mp.ps, c->S.ps, c->w.as<double>(), nrhs, nullptr, um.as<double>(), nm, 1.0, st);
+    // the layer potential at the M+ targets; for the direct formulation Green's third
+    // identity, whose weights are those of its gamma+ rows with the opposite sign
+    launch_weights(*c->op.B, c->x.as<double>(), n, c->w.p, c->op.S->padded, nrhs, BAE_PREC_FP64, st);
+    lgf_sum_to(c, c->Mp.ps, *c->op.S, c->w.as<double>(), nrhs, nullptr, um.as<double>(), nm, c->op.direct ? -1.0 : 1.0,
+               st);
     if (c->has_f) {
         DevMem up;
         up.alloc(sizeof(double) * nm * nrhs);
@@ -1026,8 +1134,8 @@ static void grid_solution(bae_ctx* c, int nrhs, hipStream_t st) {
     if (c->ugrid.bytes < sizeof(double) * N3 * nrhs) c->ugrid.alloc(sizeof(double) * N3 * nrhs);
     launch_fill(c->ugrid.as<double>(), N3 * nrhs, NAN, st);
     launch_scatter(um.as<double>(), nm, c->mp_lin_dev.as<int32_t>(), nm, c->ugrid.as<double>(), N3, nrhs, st);
-    launch_scatter(c->u_gamma.as<double>() + c->ngp, c->nT, c->gm_lin_dev.as<int32_t>(), n, c->ugrid.as<double>(), N3,
-                   nrhs, st);
+    launch_scatter(c->u_gamma.as<double>() + c->ngp, c->nT, c->gm_lin_dev.as<int32_t>(), c->ngm, c->ugrid.as<double>(),
+                   N3, nrhs, st);
     BAE_HIP_CHECK(hipStreamSynchronize(st));   // um, up leave scope
 }
 
@@ -1038,8 +1146,8 @@ static void check_solve_args(const bae_ctx* c, const bae_solve_params* p) {
     if (p->precision != BAE_SOLVE_FP64 && p->precision != BAE_SOLVE_FP32_REFINED)
         throw Error{BAE_ERR_ARG, "unknown solve precision"};
     if (!(p->tol > 0.0)) throw Error{BAE_ERR_ARG, "tol must be > 0"};
-    if (p->formulation != BAE_LAYER_DOUBLE && p->formulation != BAE_LAYER_SINGLE)
-        throw Error{BAE_ERR_ARG, "unknown layer formulation"};
+    if (p->formulation != BAE_LAYER_DOUBLE && p->formulation != BAE_LAYER_SINGLE && p->formulation != BAE_LAYER_DIRECT)
+        throw Error{BAE_ERR_ARG, "unknown formulation"};
 }
 
 // The solve of Algorithm 1 on the context's stream (which the caller has already ordered
@@ -1055,14 +1163,20 @@ static int solve_impl(bae_ctx* c, const bae_solve_params* p, bae_result* res) {
     const LayerScope layer(c, p->formulation);
     const auto t0 = std::chrono::steady_clock::now();
     const int nrhs = c->nrhs;
-    const int64_t n = c->ngm;
+    const int64_t n = c->op.n;
     const int maxit = p->maxit > 0 ? std::min(p->maxit, c->K.m) : c->K.m;
     c->hist.assign(nrhs, {});
     c->solved = false;
     c->has_grid = false;
     int64_t mv64 = 0, mv32 = 0;
     BAE_HIP_CHECK(hipStreamWaitEvent(st, c->rhs_ev, 0));   // the right-hand side's device work
-    std::vector<double> bn = host_norms(c, c->b.as<double>(), nrhs, st);
+    if (c->op.direct) {   // the direct system's right-hand side [0; b] (Sec. 3.4, eq. "direct_sys")
+        launch_fill(c->bdir.as<double>(), c->nT * nrhs, 0.0, st);
+        BAE_HIP_CHECK(hipMemcpy2DAsync(c->bdir.as<double>() + c->ngp, sizeof(double) * c->nT, c->b.p,
+                                       sizeof(double) * c->ngm, sizeof(double) * c->ngm, nrhs,
+                                       hipMemcpyDeviceToDevice, st));
+    }
+    std::vector<double> bn = host_norms(c, rhs_vector(c), nrhs, st);
     if (__atomic_exchange_n(c->bad_host, 0, __ATOMIC_ACQ_REL))
         throw Error{BAE_ERR_NONFINITE, "boundary data or source term not finite"};
     std::vector<int> iters(nrhs, 0), conv(nrhs, 0), outer(nrhs, 0);
@@ -1094,7 +1208,7 @@ static int solve_impl(bae_ctx* c, const bae_solve_params* p, bae_result* res) {
             dq_in_vsum = true;
         }
         if (!all) {   // (a warm start that already meets tol needs no iteration)
-            GmresOut g = gmres(c, warm ? c->r.as<double>() : c->b.as<double>(), nrhs, BAE_PREC_FP64, p->tol, maxit,
+            GmresOut g = gmres(c, warm ? c->r.as<double>() : rhs_vector(c), nrhs, BAE_PREC_FP64, p->tol, maxit,
                                skip, c->x.as<double>(), warm, st, &mv64);
             for (int r = 0; r < nrhs; ++r) {
                 iters[r] = g.iters[r];
@@ -1124,7 +1238,7 @@ static int solve_impl(bae_ctx* c, const bae_solve_params* p, bae_result* res) {
                 throw Error{BAE_ERR_NONFINITE, "initial densities not finite"};
             dq_in_vsum = true;
         } else {
-            BAE_HIP_CHECK(hipMemcpyAsync(c->r.p, c->b.p, sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, st));
+            BAE_HIP_CHECK(hipMemcpyAsync(c->r.p, rhs_vector(c), sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, st));
             relres.assign(nrhs, 1.0);
             for (int r = 0; r < nrhs; ++r) relres[r] = bn[r] > 0 ? 1.0 : 0.0;
         }
@@ -1174,7 +1288,10 @@ static int solve_impl(bae_ctx* c, const bae_solve_params* p, bae_result* res) {
     // u_gamma = D q + u_p on gamma.  The last call above is the FP64 residual of the final
     // q, whose operator left D q at every target (internal order) in vsum: scattering it
     // saves a double-layer evaluation.
-    if (dq_in_vsum && c->cl.n > 0)
+    // (the direct formulation's unknowns are v on gamma itself: u_gamma = v + u_p.)
+    if (c->op.direct)
+        BAE_HIP_CHECK(hipMemcpyAsync(c->u_gamma.p, c->x.p, sizeof(double) * c->nT * nrhs, hipMemcpyDeviceToDevice, st));
+    else if (dq_in_vsum && c->cl.n > 0)
         launch_reduce_scatter(c->vsum.as<double>(), 1, c->nT, c->t_pos.as<int32_t>(), c->u_gamma.as<double>(), c->nT,
                               nrhs, 1.0, st);
     else
@@ -1201,6 +1318,7 @@ static int solve_impl(bae_ctx* c, const bae_solve_params* p, bae_result* res) {
     }
     c->solved = true;
     c->has_grid = p->compute_grid != 0;
+    c->dens_n = n;
     return status;
 }
 
@@ -1339,7 +1457,7 @@ int bae_get_density(const bae_ctx* cc, int32_t r, double* q) {
     return guard([&] {
         bae_ctx* c = solved_ctx(cc);
         if (!q) throw Error{BAE_ERR_ARG, "null argument"};
-        copy_out(c, r, c->x.as<double>(), c->ngm, q, false, nullptr);
+        copy_out(c, r, c->x.as<double>(), c->dens_n, q, false, nullptr);
     });
 }
 
@@ -1365,7 +1483,7 @@ int bae_get_density_device(const bae_ctx* cc, int32_t r, double* q_dev, void* st
     return guard([&] {
         bae_ctx* c = solved_ctx(cc);
         if (!q_dev) throw Error{BAE_ERR_ARG, "null argument"};
-        copy_out(c, r, c->x.as<double>(), c->ngm, q_dev, true, (hipStream_t)stream);
+        copy_out(c, r, c->x.as<double>(), c->dens_n, q_dev, true, (hipStream_t)stream);
     });
 }
 
@@ -1435,6 +1553,19 @@ int bae_apply_operator(bae_ctx* c, const double* q, double* aq, int32_t nrhs, in
     });
 }
 
+int bae_apply_direct(bae_ctx* c, const double* v, double* y, int32_t nrhs, int32_t prec, void* stream) {
+    return guard([&] {
+        if (!c || !v || !y) throw Error{BAE_ERR_ARG, "null argument"};
+        if (nrhs < 1 || nrhs > c->max_rhs) throw Error{BAE_ERR_ARG, "nrhs out of range"};
+        if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32) throw Error{BAE_ERR_ARG, "unknown precision"};
+        join_job(c);
+        BAE_HIP_CHECK(hipSetDevice(c->device));
+        check_sum_error(c);   // a sum queued by an earlier call gave up
+        const LayerScope layer(c, BAE_LAYER_DIRECT);
+        bae_operator(c, v, c->nT, y, c->nT, nrhs, prec, (hipStream_t)stream);
+    });
+}
+
 int bae_lgf_sum_repeat(bae_ctx* c, const double* q, int32_t nrhs, int32_t prec, int32_t repeats, void* stream) {
     return guard([&] {
         if (!c || !q) throw Error{BAE_ERR_ARG, "null argument"};
@@ -1448,7 +1579,7 @@ int bae_lgf_sum_repeat(bae_ctx* c, const double* q, int32_t nrhs, int32_t prec, 
         launch_weights(c->B, q, c->ngm, c->w.p, c->S.ps.padded, nrhs, prec, st);
         for (int i = 0; i < repeats; ++i) {
             int chunks = 0;
-            apply_lgf(c, c->T.ps, c->S.ps, c->w.p, nrhs, prec, c->part.as<double>(), c->part_cap, &chunks, st);
+            apply_lgf(c, c->w.p, nrhs, prec, &chunks, st);
         }
     });
 }

@@ -911,6 +911,7 @@ int bae_batch_create(bae_ctx* const* ctxs, int32_t n, bae_batch** out) {
             }
         }
         build_layout(b->e);
+        for (bae_ctx* c : members) c->batch_refs++;
         *out = b.release();
     });
 }
@@ -918,6 +919,7 @@ int bae_batch_create(bae_ctx* const* ctxs, int32_t n, bae_batch** out) {
 int bae_batch_destroy(bae_batch* b) {
     if (!b) return BAE_OK;
     (void)hipSetDevice(b->e->device);
+    for (bae_ctx* c : b->e->ctx) c->batch_refs--;
     batch_engine_delete(b->e);
     delete b;
     return BAE_OK;

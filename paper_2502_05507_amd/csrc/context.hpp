@@ -186,7 +186,26 @@ struct bae_ctx {
     // single-layer weights map (Sec. 3.4): w(n) = q(n) for n in gamma-, nothing for E
     DevMem csr1_rowptr, csr1_col, csr1_coef;
     CSR B1;
-    const CSR* Bop = nullptr;  // the operator's weights map: &B (double layer) or &B1
+    // The operator of the current solve (set per solve, the double layer outside one):
+    // source weights map, source points, their work list, and the number of unknowns.
+    struct OpView {
+        const CSR* B = nullptr;
+        const PointSet* S = nullptr;
+        PlanBuf* plan = nullptr;
+        int64_t n = 0;
+        bool direct = false;   // the direct formulation (Sec. 3.1): unknowns v on gamma
+    } op;
+    // direct formulation: its weights map from v on gamma ([gamma+; gamma-]) onto the sources
+    // gamma (the targets' own point set), its work list (gamma x gamma), the RHS [0; b]
+    bool direct_ready = false;
+    DevMem csrd_rowptr, csrd_col, csrd_coef;
+    CSR Bd;
+    PlanBuf plan_dir;
+    DevMem t_inv;              // position in [gamma+; gamma-] -> internal target index
+    DevMem bdir;               // [rhs][nT]
+    int64_t vec_cap = 0;       // elements per RHS of b, x, r, tmp and the Krylov vectors
+    int64_t dens_n = 0;        // length of the last solve's density (|gamma-|, or |gamma| for direct)
+    int batch_refs = 0;        // batches holding this context (they keep pointers to its vectors)
     DevMem cl_tq, cl_tp, cl_t;
     Closure cl;
     std::shared_ptr<Table> table;

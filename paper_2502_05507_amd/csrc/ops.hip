@@ -62,6 +62,28 @@ __global__ void closure_kernel(const double* __restrict__ v, int64_t ldv, const 
     aq[r * lda + i] = (1.0 - t) * v[r * ldv + tq[i]] + t * v[r * ldv + tp[i]];
 }
 
+// The direct system (Sec. 3.1, eq. "direct_sys") from the reduced LGF sums vsum (internal
+// target order, [nrhs][nt]): rows on gamma+ (j < ngp) v[j] + vsum[tinv[j]]; rows on gamma-
+// (j = ngp + q) the Dirichlet row (1 - t_q) v[j] + t_q v[partner_q].
+__global__ void direct_closure_kernel(const double* __restrict__ vsum, int64_t nt, const int32_t* __restrict__ tinv,
+                                      int64_t ngp, const int32_t* __restrict__ partner,
+                                      const double* __restrict__ tw, const double* __restrict__ v, int64_t ldv,
+                                      double* __restrict__ aq, int64_t lda) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (j >= nt) return;
+    const double* vr = v + r * ldv;
+    double y;
+    if (j < ngp) {
+        y = vr[j] + vsum[r * nt + tinv[j]];
+    } else {
+        const int64_t q = j - ngp;
+        const double t = tw[q];
+        y = (1.0 - t) * vr[j] + t * vr[partner[q]];
+    }
+    aq[r * lda + j] = y;
+}
+
 __device__ inline double block_sum(double v, double* sh) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -445,6 +467,16 @@ void launch_closure(const double* part, int chunks, int64_t nt, const Closure& c
     launch_reduce_scatter(part, chunks, nt, nullptr, vsum, nt, nrhs, 1.0, st);
     dim3 grid(blocks_for(cl.n), nrhs);
     closure_kernel<<<grid, kThreads, 0, st>>>(vsum, nt, cl.tq, cl.tp, cl.t, cl.n, aq, lda);
+    LAUNCH_CHECK();
+}
+
+void launch_direct_closure(const double* part, int chunks, int64_t nt, const int32_t* tinv, int64_t ngp,
+                           const int32_t* partner, const double* t, const double* v, int64_t ldv, double* aq,
+                           int64_t lda, int nrhs, double* vsum, hipStream_t st) {
+    if (nt == 0) return;
+    launch_reduce_scatter(part, chunks, nt, nullptr, vsum, nt, nrhs, 1.0, st);
+    direct_closure_kernel<<<dim3(blocks_for(nt), nrhs), kThreads, 0, st>>>(vsum, nt, tinv, ngp, partner, t, v, ldv,
+                                                                           aq, lda);
     LAUNCH_CHECK();
 }
 

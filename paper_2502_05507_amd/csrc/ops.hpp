@@ -48,6 +48,11 @@ void launch_reduce_scatter(const double* part, int chunks, int64_t nt, const int
 // vsum: scratch [nrhs][nt] for the chunk-reduced sums
 void launch_closure(const double* part, int chunks, int64_t nt, const Closure& cl, double* aq, int64_t lda, int nrhs,
                     double* vsum, hipStream_t st);
+// The direct formulation's system rows (Sec. 3.1) from the chunk partials of its LGF sum:
+// v + (sum) on gamma+, the Dirichlet rows of v on gamma-; v and aq in [gamma+; gamma-] order.
+void launch_direct_closure(const double* part, int chunks, int64_t nt, const int32_t* tinv, int64_t ngp,
+                           const int32_t* partner, const double* t, const double* v, int64_t ldv, double* aq,
+                           int64_t lda, int nrhs, double* vsum, hipStream_t st);
 int dot_blocks(int64_t n);
 // h[r][j] (+)= <X[r][j], y[r]> for j < nj; partial: scratch [nrhs][maxj][dot_blocks(n)].
 void launch_dots(const double* X, int64_t ldx_vec, int64_t ldx_rhs, int nj, const double* y, int64_t ldy, int64_t n,

@@ -20,7 +20,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libbae.so")
 ARCH = "gfx950"
 
-SOURCES = ["geometry.cpp", "lgf_table.hip", "lgf_sum.hip", "ops.hip", "box.hip", "bae.cpp", "batch.hip", "server.cpp"]
+SOURCES = ["geometry.cpp", "lgf_table.hip", "lgf_sum.hip", "ops.hip", "fft.hip", "bae.cpp", "batch.hip",
+           "server.cpp"]
 
 # Packed FP32 VALU forms are disabled for all device code; hipcc's host pass warns that it
 # does not know the feature, which is harmless.

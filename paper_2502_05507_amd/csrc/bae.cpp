@@ -15,6 +15,7 @@
 #include <unordered_map>
 
 #include "context.hpp"
+#include "fft.hpp"
 
 namespace bae {
 
@@ -958,32 +959,32 @@ static void ensure_lin(bae_ctx* c) {
     BAE_HIP_CHECK(hipStreamSynchronize(c->stream));
 }
 
-// Lazy set-up of the box particular solution: the DST-I matrix, scratch, and the interior
-// index of every target and of every M+ point.
+// Lazy set-up of the box of Algorithm 1 (its interior nodes n_d - 2 per axis): the interior
+// index of every target and of every M+ point, and the M+ mask on the device.
 static void ensure_box(bae_ctx* c) {
+    if (c->box_ready) return;
+    ensure_lin(c);
     const Geometry& G = c->geo;
-    const int N = G.n[0] - 2;
-    if (c->box_N == N) return;
     hipStream_t st = c->stream;
-    const int64_t nn = (int64_t)N * N * N;
-    c->box_S.alloc(sizeof(double) * N * N);
-    box_dst_matrix(N, c->box_S.as<double>(), st);
-    c->box_tmp.alloc(sizeof(double) * nn);
+    for (int a = 0; a < 3; ++a) c->box_n[a] = G.n[a] - 2;
+    const int N1 = c->box_n[1], N2 = c->box_n[2];
+    c->box_nn = (int64_t)c->box_n[0] * N1 * N2;
     const int64_t nm = c->Mp.ps.count;
-    auto interior = [&](int64_t l) {   // grid index -> interior index
-        const int64_t i = l / ((int64_t)G.n[1] * G.n[2]), j = (l / G.n[2]) % G.n[1], k = l % G.n[2];
-        return (int32_t)(((i - 1) * N + (j - 1)) * N + (k - 1));
-    };
+    auto interior = [&](int64_t i, int64_t j, int64_t k) { return (int32_t)(((i - 1) * N1 + (j - 1)) * N2 + (k - 1)); };
     std::vector<int32_t> tidx(c->nT), midx(nm);
     for (int64_t t = 0; t < c->nT; ++t) {
         const int32_t* v = t < c->ngp ? &G.gp[3 * t] : &G.gm[3 * (t - c->ngp)];
-        tidx[t] = (int32_t)(((int64_t)(v[0] - 1) * N + (v[1] - 1)) * N + (v[2] - 1));
+        tidx[t] = interior(v[0], v[1], v[2]);
     }
-    for (int64_t a = 0; a < nm; ++a) midx[a] = interior(c->mp_lin[a]);
+    for (int64_t a = 0; a < nm; ++a) {
+        const int64_t l = c->mp_lin[a];
+        midx[a] = interior(l / ((int64_t)G.n[1] * G.n[2]), (l / G.n[2]) % G.n[1], l % G.n[2]);
+    }
     upload(c->box_tidx, tidx, st);
     upload(c->box_mpidx, midx, st);
+    upload(c->inside_dev, G.inside, st);
     BAE_HIP_CHECK(hipStreamSynchronize(st));   // tidx, midx leave scope
-    c->box_N = N;
+    c->box_ready = true;
 }
 
 // Lazy work list and partial-sum buffer of the (gamma targets, M+ sources) LGF sum that
@@ -1001,12 +1002,11 @@ static void ensure_plan_mp(bae_ctx* c) {
 static void rhs_on_device(bae_ctx* c, int nrhs, const double* g, int64_t ldg, bool has_f, bool box, hipStream_t st) {
     const int64_t nmp = c->Mp.ps.padded;
     if (has_f && box) {
-        const int N = c->box_N;
-        const int64_t nn = (int64_t)N * N * N, nm = c->Mp.ps.count;
+        const int64_t nn = c->box_nn, nm = c->Mp.ps.count;
         launch_fill(c->box_u.as<double>(), nn * nrhs, 0.0, st);
-        box_scatter(c->wf.as<double>(), nmp, c->box_mpidx.as<int32_t>(), nm, c->box_u.as<double>(), nn, nrhs, st);
+        launch_scatter(c->wf.as<double>(), nmp, c->box_mpidx.as<int32_t>(), nm, c->box_u.as<double>(), nn, nrhs, st);
         for (int r = 0; r < nrhs; ++r)
-            box_solve(c->box_S.as<double>(), c->box_u.as<double>() + r * nn, c->box_tmp.as<double>(), N, c->s, st);
+            box_solve_fft(c->box_u.as<double>() + r * nn, c->box_n[0], c->box_n[1], c->box_n[2], c->s, st);
         launch_gather(c->box_u.as<double>(), nn, c->box_tidx.as<int32_t>(), c->nT, c->up_gamma.as<double>(), c->nT,
                       nrhs, 1.0, st);
     } else if (has_f) {
@@ -1030,11 +1030,10 @@ static void rhs_on_device(bae_ctx* c, int nrhs, const double* g, int64_t ldg, bo
 }
 
 static void check_rhs_args(bae_ctx* c, int32_t nrhs, const void* g, const void* f, bool box) {
+    (void)f;
+    (void)box;
     if (!c || !g) throw Error{BAE_ERR_ARG, "null argument"};
     if (nrhs < 1 || nrhs > c->max_rhs) throw Error{BAE_ERR_ARG, "nrhs out of range"};
-    const Geometry& G = c->geo;
-    if (box && f && (G.n[0] != G.n[1] || G.n[1] != G.n[2]))
-        throw Error{BAE_ERR_ARG, "the box particular solution needs a cubic grid"};
 }
 
 // Host inputs: validated here, h^2 f gathered at the M+ points on the host (only those cross
@@ -1061,10 +1060,8 @@ static void set_rhs_impl(bae_ctx* c, int32_t nrhs, const double* g_xstar, const 
             for (int64_t a = 0; a < nm; ++a) wfh[r * nmp + a] = h2 * f_grid[r * N3 + c->mp_lin[a]];
         if (c->wf.bytes < sizeof(double) * wfh.size()) c->wf.alloc(sizeof(double) * nmp * c->max_rhs);
         BAE_HIP_CHECK(hipMemcpyAsync(c->wf.p, wfh.data(), sizeof(double) * wfh.size(), hipMemcpyHostToDevice, st));
-        if (box) {
-            const int64_t nn = (int64_t)c->box_N * c->box_N * c->box_N;
-            if (c->box_u.bytes < sizeof(double) * nn * nrhs) c->box_u.alloc(sizeof(double) * nn * nrhs);
-        }
+        if (box && c->box_u.bytes < sizeof(double) * c->box_nn * nrhs)
+            c->box_u.alloc(sizeof(double) * c->box_nn * c->max_rhs);
         BAE_HIP_CHECK(hipStreamSynchronize(st));   // wfh leaves scope
     }
     BAE_HIP_CHECK(hipMemcpyAsync(c->gdev.p, g_xstar, sizeof(double) * n * nrhs, hipMemcpyHostToDevice, st));
@@ -1090,10 +1087,8 @@ static void set_rhs_device_impl(bae_ctx* c, int32_t nrhs, const double* g_dev, c
         else ensure_plan_mp(c);
         const int64_t nmp = c->Mp.ps.padded;
         if (c->wf.bytes < sizeof(double) * nmp * nrhs) c->wf.alloc(sizeof(double) * nmp * c->max_rhs);
-        if (box) {
-            const int64_t nn = (int64_t)c->box_N * c->box_N * c->box_N;
-            if (c->box_u.bytes < sizeof(double) * nn * nrhs) c->box_u.alloc(sizeof(double) * nn * nrhs);
-        }
+        if (box && c->box_u.bytes < sizeof(double) * c->box_nn * nrhs)
+            c->box_u.alloc(sizeof(double) * c->box_nn * c->max_rhs);
         const Geometry& G = c->geo;
         const int64_t N3 = (int64_t)G.n[0] * G.n[1] * G.n[2];
         launch_finite_check(f_dev, N3, N3, nrhs, c->bad_dev, st);
@@ -1104,39 +1099,51 @@ static void set_rhs_device_impl(bae_ctx* c, int32_t nrhs, const double* g_dev, c
     rhs_on_device(c, nrhs, g_dev, c->ngm, f_dev != nullptr, box, st);
 }
 
-// u on the grid (Algorithm 1's last step, Sec. 2.1 eq. "discrete_green"): u = u_p + D q on
-// M+ by the LGF sum at the M+ targets, u_gamma on gamma-, NaN elsewhere; assembled on the
-// device in c->ugrid ([nrhs][n0 n1 n2]).
+// u on the grid (Algorithm 1's last step; Sec. 2.1 eq. "discrete_green_v"): the part of u_gamma
+// beyond the particular solution, h_gamma = u_gamma - u_p, is lattice harmonic in M+, so its
+// difference potential G_h[chi_{M-} L_h h_gamma] (h_gamma extended by zero off gamma; G_h by the
+// box's sine transforms) reproduces it there, and u = u_p + G_h[chi_{M-} L_h h_gamma] on M+,
+// u_gamma on gamma-, NaN elsewhere; assembled on the device in c->ugrid ([nrhs][n0 n1 n2]).
+// u_p on M+ is the box solve's own (bae_set_rhs_box), the free-space volume potential (an LGF
+// sum over the M+ sources at the M+ targets), or zero without f.
 static void grid_solution(bae_ctx* c, int nrhs, hipStream_t st) {
     const Geometry& G = c->geo;
-    ensure_lin(c);
-    const int64_t nm = c->Mp.ps.count, n = c->op.n;
+    ensure_box(c);
+    const int64_t nm = c->Mp.ps.count, nn = c->box_nn;
     const int64_t N3 = (int64_t)G.n[0] * G.n[1] * G.n[2];
-    DevMem um;
+    if (c->box_h.bytes < sizeof(double) * nn) c->box_h.alloc(sizeof(double) * nn);
+    if (c->box_w.bytes < sizeof(double) * nn) c->box_w.alloc(sizeof(double) * nn);
+    DevMem hg, um;
+    hg.alloc(sizeof(double) * c->nT * nrhs);
     um.alloc(sizeof(double) * nm * nrhs);
-    // the layer potential at the M+ targets; for the direct formulation Green's third
-    // identity, whose weights are those of its gamma+ rows with the opposite sign
-    launch_weights(*c->op.B, c->x.as<double>(), n, c->w.p, c->op.S->padded, nrhs, BAE_PREC_FP64, st);
-    lgf_sum_to(c, c->Mp.ps, *c->op.S, c->w.as<double>(), nrhs, nullptr, um.as<double>(), nm, c->op.direct ? -1.0 : 1.0,
-               st);
+    // h_gamma = u_gamma - u_p on gamma
+    BAE_HIP_CHECK(hipMemcpyAsync(hg.p, c->u_gamma.p, sizeof(double) * c->nT * nrhs, hipMemcpyDeviceToDevice, st));
+    launch_axpby(-1.0, c->up_gamma.as<double>(), c->nT, 1.0, hg.as<double>(), c->nT, c->nT, nrhs, st);
+    for (int r = 0; r < nrhs; ++r) {
+        launch_fill(c->box_h.as<double>(), nn, 0.0, st);
+        launch_scatter(hg.as<double>() + r * c->nT, c->nT, c->box_tidx.as<int32_t>(), c->nT, c->box_h.as<double>(), nn, 1,
+                    st);
+        difference_source(c->box_h.as<double>(), c->inside_dev.as<uint8_t>(), G.n, c->s, c->box_w.as<double>(), st);
+        box_solve_fft(c->box_w.as<double>(), c->box_n[0], c->box_n[1], c->box_n[2], c->s, st);
+        launch_gather(c->box_w.as<double>(), nn, c->box_mpidx.as<int32_t>(), nm, um.as<double>() + r * nm, nm, 1, 1.0,
+                      st);
+    }
     if (c->has_f) {
         DevMem up;
         up.alloc(sizeof(double) * nm * nrhs);
-        if (c->particular_box) {   // the finite-grid u_p is known at every node
-            const int64_t nn = (int64_t)c->box_N * c->box_N * c->box_N;
-            launch_gather(c->box_u.as<double>(), nn, c->box_mpidx.as<int32_t>(), nm, up.as<double>(), nm, nrhs, 1.0,
-                          st);
-        } else {
+        if (c->particular_box)   // the finite-grid u_p is known at every node
+            launch_gather(c->box_u.as<double>(), nn, c->box_mpidx.as<int32_t>(), nm, up.as<double>(), nm, nrhs, 1.0, st);
+        else
             lgf_sum_to(c, c->Mp.ps, c->Mp.ps, c->wf.as<double>(), nrhs, nullptr, up.as<double>(), nm, 1.0, st);
-        }
         launch_axpby(1.0, up.as<double>(), nm, 1.0, um.as<double>(), nm, nm, nrhs, st);
+        BAE_HIP_CHECK(hipStreamSynchronize(st));   // up leaves scope
     }
     if (c->ugrid.bytes < sizeof(double) * N3 * nrhs) c->ugrid.alloc(sizeof(double) * N3 * nrhs);
     launch_fill(c->ugrid.as<double>(), N3 * nrhs, NAN, st);
     launch_scatter(um.as<double>(), nm, c->mp_lin_dev.as<int32_t>(), nm, c->ugrid.as<double>(), N3, nrhs, st);
     launch_scatter(c->u_gamma.as<double>() + c->ngp, c->nT, c->gm_lin_dev.as<int32_t>(), c->ngm, c->ugrid.as<double>(),
                    N3, nrhs, st);
-    BAE_HIP_CHECK(hipStreamSynchronize(st));   // um, up leave scope
+    BAE_HIP_CHECK(hipStreamSynchronize(st));   // hg, um leave scope
 }
 
 // ------------------------------------------------------------------ solve
@@ -1345,15 +1352,15 @@ int bae_get_particular(const bae_ctx* cc, int32_t r, double* up_grid) {
         BAE_HIP_CHECK(hipSetDevice(c->device));
         BAE_HIP_CHECK(hipStreamSynchronize(c->stream));
         const Geometry& G = c->geo;
-        const int N = c->box_N;
-        const int64_t nn = (int64_t)N * N * N, N3 = (int64_t)G.n[0] * G.n[1] * G.n[2];
+        const int N0 = c->box_n[0], N1 = c->box_n[1], N2 = c->box_n[2];
+        const int64_t nn = c->box_nn, N3 = (int64_t)G.n[0] * G.n[1] * G.n[2];
         std::vector<double> u(nn);
         BAE_HIP_CHECK(hipMemcpy(u.data(), c->box_u.as<double>() + r * nn, sizeof(double) * nn, hipMemcpyDeviceToHost));
         std::fill(up_grid, up_grid + N3, 0.0);
-        for (int i = 1; i <= N; ++i)
-            for (int j = 1; j <= N; ++j)
-                for (int k = 1; k <= N; ++k)
-                    up_grid[((int64_t)i * G.n[1] + j) * G.n[2] + k] = u[((int64_t)(i - 1) * N + (j - 1)) * N + (k - 1)];
+        for (int i = 1; i <= N0; ++i)
+            for (int j = 1; j <= N1; ++j)
+                for (int k = 1; k <= N2; ++k)
+                    up_grid[((int64_t)i * G.n[1] + j) * G.n[2] + k] = u[((int64_t)(i - 1) * N1 + (j - 1)) * N2 + (k - 1)];
     });
 }
 

@@ -227,11 +227,15 @@ struct bae_ctx {
     DevMem vsum;               // [rhs][nT] chunk-reduced sums (operator scratch)
     DevMem wf;                 // [rhs][|M+|] h^2 f in Mp order
     std::vector<int32_t> mp_lin;   // linear grid index of each M+ point in Mp order (lazy)
-    // box particular solution (bae_set_rhs_box): u_p on the N^3 interior nodes per RHS, the
-    // DST-I matrix, scratch, and the interior index of every target and of every M+ point
+    // box of Algorithm 1 (bae_set_rhs_box and the grid solution): u_p on the interior nodes per
+    // RHS, and the interior index of every target and of every M+ point
     bool particular_box = false;
-    int box_N = 0;
-    DevMem box_S, box_u, box_tmp, box_tidx, box_mpidx;
+    bool box_ready = false;
+    int box_n[3] = {0, 0, 0};  // interior nodes per axis (n_d - 2)
+    int64_t box_nn = 0;
+    DevMem box_u, box_tidx, box_mpidx;
+    DevMem box_h, box_w;       // reconstruction scratch: the density on the box, chi_{M-} L_h of it
+    DevMem inside_dev;         // M+ mask of the grid (uint8)
     DevMem ctl;                // Ctl of RHS 0 for batched / served solves
     int nrhs = 0;
     bool has_f = false, rhs_ready = false, solved = false;

@@ -1,0 +1,314 @@
+// Mixed-radix FFTs in LDS and the sine transforms built on them.
+//
+// Algorithm 1 solves the finite auxiliary problem G_h (Sec. 2.1: L_h on the interior nodes of
+// the box, zero on its boundary) "via FFT".  The sine vectors diagonalise L_h on the box:
+// along an axis of N interior nodes the DST-I X_k = sum_{n=1..N} x_n sin(pi n k / (N + 1)).
+// Here every DST-I is one complex FFT of length M = 2(N + 1) of the odd extension
+// y = (0, x_1..x_N, 0, -x_N..-x_1), whose transform is -2i X; two real lines ride in one
+// complex FFT (a in the real part, b in the imaginary part: FFT = -2i X_a + 2 X_b).
+//
+// The FFT itself is a Stockham autosort transform in LDS (no bit reversal): M factors into
+// radices 4, 2, 3, 5 and any remaining primes; stage s with radix R and stride Ns maps input
+// j + r M/R (r < R), twiddled by w^(r (j mod Ns) M/(Ns R)), to output
+// (j div Ns) Ns R + (j mod Ns) + k Ns after an R-point DFT (w = e^(-2 pi i / M); every root
+// comes from one table of M entries).  Radices up to 8 run their DFT in registers; larger
+// primes evaluate each output as an R-term sum straight from LDS (O(M R) per stage: such
+// lengths are rare, and correct).
+//
+// Lines along any axis of a row-major [n0][n1][n2] array are gathered by one workgroup each
+// group of P lines: along the contiguous axis whole rows, along the others P consecutive
+// columns, so every load and store is a run of P (or n2) consecutive doubles.
+#include <cmath>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "fft.hpp"
+
+namespace bae {
+
+namespace {
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+// the table root w^t = e^(-2 pi i t / M), conjugated for the inverse transform
+__device__ __forceinline__ double2 root(const FftDev& p, int t, bool inv) {
+    const double2 w = p.tw[t];
+    return inv ? make_double2(w.x, -w.y) : w;
+}
+// multiplication by -i (forward) or +i (inverse)
+__device__ __forceinline__ double2 rot(double2 a, bool inv) {
+    return inv ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
+}
+
+constexpr int kRegRadix = 8;   // radices up to this run their DFT in registers
+
+// `count` FFTs of length p.M stored one after another at src (LDS); ping-pong with dst.
+// Returns the buffer that holds the result.  Every thread of the block must call it.
+__device__ double2* fft_lds(double2* src, double2* dst, int count, const FftDev& p, bool inv) {
+    const int M = p.M;
+    int Ns = 1;
+    for (int s = 0; s < p.nf; ++s) {
+        const int R = p.f[s];
+        const int m = M / R;              // butterflies per line
+        const int tstep = M / (Ns * R);   // root index of the twiddle step
+        if (R <= kRegRadix) {
+            for (int e = threadIdx.x; e < count * m; e += blockDim.x) {
+                const int c = e / m, j = e - c * m;
+                const double2* in = src + (int64_t)c * M;
+                double2* out = dst + (int64_t)c * M;
+                const int jm = j % Ns;
+                double2 v[kRegRadix];
+                for (int r = 0; r < R; ++r) {
+                    v[r] = in[j + r * m];
+                    if (r > 0 && jm > 0) v[r] = cmul(v[r], root(p, (r * jm * tstep) % M, inv));
+                }
+                const int o = (j / Ns) * Ns * R + jm;
+                if (R == 2) {
+                    out[o] = cadd(v[0], v[1]);
+                    out[o + Ns] = csub(v[0], v[1]);
+                } else if (R == 4) {
+                    const double2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+                    const double2 c2 = cadd(v[1], v[3]), d = rot(csub(v[1], v[3]), inv);
+                    out[o] = cadd(a, c2);
+                    out[o + Ns] = cadd(b, d);
+                    out[o + 2 * Ns] = csub(a, c2);
+                    out[o + 3 * Ns] = csub(b, d);
+                } else {
+                    // R-point DFT with the table: X_k = sum_r v_r w^(r k M / R)
+                    const int rs = M / R;
+                    for (int k = 0; k < R; ++k) {
+                        double2 acc = v[0];
+                        for (int r = 1; r < R; ++r) acc = cadd(acc, cmul(v[r], root(p, ((r * k) % R) * rs, inv)));
+                        out[o + k * Ns] = acc;
+                    }
+                }
+            }
+        } else {
+            // large prime radix: each output directly, X = sum_r in[j + r m] w^(r base)
+            for (int e = threadIdx.x; e < count * M; e += blockDim.x) {
+                const int c = e / M, q = e - c * M;
+                const int k = q / m, j = q - k * m;
+                const double2* in = src + (int64_t)c * M;
+                double2* out = dst + (int64_t)c * M;
+                const int jm = j % Ns;
+                const int base = (jm * tstep + k * (M / R)) % M;
+                double2 acc = in[j];
+                int t = 0;
+                for (int r = 1; r < R; ++r) {
+                    t += base;
+                    if (t >= M) t -= M;
+                    acc = cadd(acc, cmul(in[j + r * m], root(p, t, inv)));
+                }
+                out[(j / Ns) * Ns * R + jm + k * Ns] = acc;
+            }
+        }
+        __syncthreads();
+        double2* x = src;
+        src = dst;
+        dst = x;
+        Ns *= R;
+    }
+    return src;
+}
+
+// Position of element n of line l along `axis` of an [n0][n1][n2] array.
+__device__ __forceinline__ int64_t line_at(int axis, int64_t l, int64_t n, int n0, int n1, int n2) {
+    (void)n0;
+    if (axis == 2) return l * n2 + n;                                       // l = i n1 + j
+    if (axis == 1) return (l / n2) * (int64_t)n1 * n2 + (l % n2) + n * n2;  // l = i n2 + k
+    return l + n * (int64_t)n1 * n2;                                        // l = j n2 + k
+}
+
+// DST-I of every line along `axis` (length N = its extent), in place, times `scale`.  A block
+// takes P lines (P even: line pairs share a complex FFT of length p.M = 2(N + 1)).
+__global__ void dst_axis_kernel(double* __restrict__ x, int axis, int n0, int n1, int n2, int64_t nlines, int P,
+                                const FftDev p, double scale) {
+    extern __shared__ double2 lds[];
+    const int N = axis == 0 ? n0 : axis == 1 ? n1 : n2;
+    const int M = p.M;
+    const int nfft = P / 2;
+    double2* A = lds;
+    double2* B = lds + (int64_t)nfft * M;
+    const int64_t l0 = (int64_t)blockIdx.x * P;
+    double* Ad = (double*)A;
+    // the two end points of every odd extension are zero
+    for (int e = threadIdx.x; e < nfft; e += blockDim.x) {
+        A[(int64_t)e * M] = make_double2(0.0, 0.0);
+        A[(int64_t)e * M + N + 1] = make_double2(0.0, 0.0);
+    }
+    for (int e = threadIdx.x; e < P * N; e += blockDim.x) {
+        int pl, n;
+        if (axis == 2) {
+            pl = e / N;
+            n = e - pl * N;
+        } else {
+            n = e / P;
+            pl = e - n * P;
+        }
+        const int64_t l = l0 + pl;
+        const double v = l < nlines ? x[line_at(axis, l, n, n0, n1, n2)] : 0.0;
+        const int64_t c = pl >> 1, comp = pl & 1;
+        Ad[2 * (c * M + n + 1) + comp] = v;
+        Ad[2 * (c * M + M - n - 1) + comp] = -v;
+    }
+    __syncthreads();
+    const double2* Z = fft_lds(A, B, nfft, p, false);
+    const double h = 0.5 * scale;
+    for (int e = threadIdx.x; e < P * N; e += blockDim.x) {
+        int pl, n;
+        if (axis == 2) {
+            pl = e / N;
+            n = e - pl * N;
+        } else {
+            n = e / P;
+            pl = e - n * P;
+        }
+        const int64_t l = l0 + pl;
+        if (l >= nlines) continue;
+        const double2 z = Z[(int64_t)(pl >> 1) * M + n + 1];
+        x[line_at(axis, l, n, n0, n1, n2)] = (pl & 1) ? h * z.x : -h * z.y;
+    }
+}
+
+// x[k1][k2][k3] *= scale / lambda(k), lambda = (6 + s) - 2 sum_d cos(pi (k_d + 1) / (n_d + 1))
+__global__ void box_eigen_kernel(double* __restrict__ x, int n0, int n1, int n2, double s, double scale) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n0 * n1 * n2) return;
+    const int k1 = (int)(i / ((int64_t)n1 * n2)), k2 = (int)((i / n2) % n1), k3 = (int)(i % n2);
+    const double lam = (6.0 + s) - 2.0 * (cospi((double)(k1 + 1) / (n0 + 1)) + cospi((double)(k2 + 1) / (n1 + 1)) +
+                                          cospi((double)(k3 + 1) / (n2 + 1)));
+    x[i] *= scale / lam;
+}
+
+// W = chi_{M-} L_h H on the interior nodes (N0 x N1 x N2, offset one node from the full grid
+// [n0][n1][n2]): the source of the difference potential G_h[chi_{M-} L_h u_gamma] (Sec. 2.1),
+// H the density extended by zero; nodes of the box boundary count as zero.
+__global__ void difference_source_kernel(const double* __restrict__ H, const uint8_t* __restrict__ inside, int n1,
+                                         int n2, int N0, int N1, int N2, double s, double* __restrict__ W) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)N0 * N1 * N2) return;
+    const int a = (int)(i / ((int64_t)N1 * N2)), b = (int)((i / N2) % N1), c = (int)(i % N2);
+    if (inside[((int64_t)(a + 1) * n1 + (b + 1)) * n2 + (c + 1)]) {
+        W[i] = 0.0;
+        return;
+    }
+    const int64_t sa = (int64_t)N1 * N2, sb = N2;
+    double v = (6.0 + s) * H[i];
+    if (a > 0) v -= H[i - sa];
+    if (a + 1 < N0) v -= H[i + sa];
+    if (b > 0) v -= H[i - sb];
+    if (b + 1 < N1) v -= H[i + sb];
+    if (c > 0) v -= H[i - 1];
+    if (c + 1 < N2) v -= H[i + 1];
+    W[i] = v;
+}
+
+struct PlanHolder {
+    FftDev dev{};
+    double2* tw = nullptr;
+    ~PlanHolder() {}   // the table lives until the process ends (plans are shared)
+};
+
+std::mutex g_plan_mu;
+auto* g_plans = new std::map<std::pair<int, int>, std::unique_ptr<PlanHolder>>();
+
+}  // namespace
+
+std::vector<int> fft_factors(int M) {
+    std::vector<int> f;
+    int r = M;
+    while (r % 4 == 0) {
+        f.push_back(4);
+        r /= 4;
+    }
+    for (int q : {2, 3, 5})
+        while (r % q == 0) {
+            f.push_back(q);
+            r /= q;
+        }
+    for (int q = 7; (int64_t)q * q <= r; q += 2)
+        while (r % q == 0) {
+            f.push_back(q);
+            r /= q;
+        }
+    if (r > 1) f.push_back(r);
+    return f;
+}
+
+FftDev fft_plan(int M, hipStream_t st) {
+    if (M < 1 || M > kFftMaxLen) throw Error{BAE_ERR_ARG, "FFT length out of range"};
+    int device = 0;
+    BAE_HIP_CHECK(hipGetDevice(&device));
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    auto& slot = (*g_plans)[{device, M}];
+    if (!slot) {
+        auto h = std::make_unique<PlanHolder>();
+        const std::vector<int> f = fft_factors(M);
+        if ((int)f.size() > kFftMaxFactors) throw Error{BAE_ERR_ARG, "FFT length has too many factors"};
+        h->dev.M = M;
+        h->dev.nf = (int)f.size();
+        for (size_t i = 0; i < f.size(); ++i) h->dev.f[i] = f[i];
+        std::vector<double2> tw(M);
+        for (int t = 0; t < M; ++t) {
+            // extended precision keeps every root correct to FP64 rounding
+            const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)t / (long double)M;
+            tw[t] = make_double2((double)cosl(a), (double)(-sinl(a)));
+        }
+        BAE_HIP_CHECK(hipMalloc((void**)&h->tw, sizeof(double2) * M));
+        BAE_HIP_CHECK(hipMemcpyAsync(h->tw, tw.data(), sizeof(double2) * M, hipMemcpyHostToDevice, st));
+        BAE_HIP_CHECK(hipStreamSynchronize(st));
+        h->dev.tw = h->tw;
+        slot = std::move(h);
+    }
+    return slot->dev;
+}
+
+static int lines_per_block(int M) {
+    // LDS: two buffers of P/2 complex lines of length M; at most 64 KB, P even, <= 32
+    int P = 2 * (int)(65536 / (32 * (int64_t)M));
+    P = std::max(2, std::min(32, P));
+    return P;
+}
+
+void dst_axis(double* x, int n0, int n1, int n2, int axis, double scale, hipStream_t st) {
+    const int N = axis == 0 ? n0 : axis == 1 ? n1 : n2;
+    if (N <= 0) return;
+    const FftDev p = fft_plan(2 * (N + 1), st);
+    const int P = lines_per_block(p.M);
+    const int64_t nlines = (int64_t)n0 * n1 * n2 / N;
+    const size_t lds = sizeof(double2) * (size_t)P * p.M;
+    static bool attr = false;
+    if (!attr) {
+        BAE_HIP_CHECK(hipFuncSetAttribute((const void*)dst_axis_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          160 * 1024));
+        attr = true;
+    }
+    const unsigned blocks = (unsigned)((nlines + P - 1) / P);
+    dst_axis_kernel<<<blocks, 256, lds, st>>>(x, axis, n0, n1, n2, nlines, P, p, scale);
+    BAE_HIP_CHECK(hipGetLastError());
+}
+
+void difference_source(const double* H, const uint8_t* inside, const int* n, double s, double* W, hipStream_t st) {
+    const int N0 = n[0] - 2, N1 = n[1] - 2, N2 = n[2] - 2;
+    const int64_t nn = (int64_t)N0 * N1 * N2;
+    if (nn <= 0) return;
+    difference_source_kernel<<<(unsigned)((nn + 255) / 256), 256, 0, st>>>(H, inside, n[1], n[2], N0, N1, N2, s, W);
+    BAE_HIP_CHECK(hipGetLastError());
+}
+
+void box_solve_fft(double* x, int n0, int n1, int n2, double s, hipStream_t st) {
+    if ((int64_t)n0 * n1 * n2 <= 0) return;
+    for (int a = 0; a < 3; ++a) dst_axis(x, n0, n1, n2, a, 1.0, st);
+    const double scale = (2.0 / (n0 + 1)) * (2.0 / (n1 + 1)) * (2.0 / (n2 + 1));
+    const int64_t n3 = (int64_t)n0 * n1 * n2;
+    box_eigen_kernel<<<(unsigned)((n3 + 255) / 256), 256, 0, st>>>(x, n0, n1, n2, s, scale);
+    BAE_HIP_CHECK(hipGetLastError());
+    for (int a = 0; a < 3; ++a) dst_axis(x, n0, n1, n2, a, 1.0, st);
+}
+
+}  // namespace bae

@@ -160,13 +160,4 @@ void lgf_eval_launch(const int32_t* off, int64_t count, double* out, int prec, c
 // the exact table over every offset with max-norm in (from_r, R]; host result.
 double yukawa_check(const double* table, int R, int from_r, double kappa, hipStream_t st);
 
-// ------------------------------------------------------------------ box particular solution
-// u = G_h q on the N^3 interior nodes of a cubic box (zero on its boundary), in place in x;
-// S: the N x N DST-I matrix from box_dst_matrix; tmp: N^3 doubles of scratch.
-void box_solve(const double* S, double* x, double* tmp, int N, double s, hipStream_t st);
-void box_dst_matrix(int N, double* S, hipStream_t st);
-// dst[r][idx[i]] = src[r][i] for i < n (row strides lds, ldd)
-void box_scatter(const double* src, int64_t lds, const int32_t* idx, int64_t n, double* dst, int64_t ldd, int nrhs,
-                 hipStream_t st);
-
 }  // namespace bae

@@ -409,13 +409,46 @@ def test_largest_lattice_offsets_two_balls():
             out = v.cpu().numpy()
             for rr in range(2):
                 assert rel_l2(out[rr], ref[rr]) < tol, (prec, rr, rel_l2(out[rr], ref[rr]))
-        # the box particular solution needs a cubic grid; without it there is no u_p to read
-        with pytest.raises(P.BaeError) as e:
-            ctx.set_rhs(np.zeros(len(g.gamma_minus)), np.ones(int(np.prod(n))), particular="box")
-        assert e.value.status == -1
+        # the box particular solution on this long, thin box (a 2047-point sine transform,
+        # FFT length 4096); without it there is no u_p to read
+        from oracle import box
+        ctx.set_rhs(np.zeros(len(g.gamma_minus)), np.ones(int(np.prod(n))), particular="box")
+        ref_p = box.particular_box(g, 0.0, np.ones(int(np.prod(n))))
+        assert np.abs(ctx.particular() - ref_p).max() < 1e-12 * np.abs(ref_p).max()
         ctx.set_rhs(np.zeros(len(g.gamma_minus)), np.ones(int(np.prod(n))))
         with pytest.raises(P.BaeError):
             ctx.particular()
+
+
+@pytest.mark.parametrize("n", [(41, 36, 29), (39, 44, 35)])
+def test_box_on_non_cubic_grids(n):
+    """Sine transforms of lengths whose FFTs take radices 4, 2, 5, 7 and the primes 17, 19, 43:
+    u_p against the oracle's (scipy DST-I) and Algorithm 1's reconstruction of u on the grid
+    against the sparse solve."""
+    from oracle import box, sparse
+    h = 1.0 / 40
+    c = tuple(0.5 * (v - 1) * h for v in n)
+    p = W.Problem("box", n, h, (0.0, 0.0, 0.0), 20.0, "ellipsoid", c, (0.33, 0.36, 0.29))
+    g = geometry.from_problem(p)
+    X = g.coords(np.indices(g.n).reshape(3, -1).T)
+    f = (np.cos(3 * X[:, 0]) + X[:, 1] * X[:, 2] ** 2 + 0.5).reshape(-1)
+    gx_fn = lambda Y: np.sin(Y[:, 0] + 2 * Y[:, 1]) + Y[:, 2]
+    s = p.sigma * h * h
+    ref_p = box.particular_box(g, s, f)
+    u_ref = sparse.solve(g, s, gx_fn(g.xstar), f)
+    with P.Context.from_problem(p) as ctx:
+        xs, _, _ = ctx.boundary_points()
+        for particular in ("box", "free"):
+            ctx.set_rhs(gx_fn(xs), f, particular=particular)
+            if particular == "box":
+                up = ctx.particular()
+                assert np.abs(up - ref_p).max() < 1e-12 * np.abs(ref_p).max()
+            r = ctx.solve(P.SOLVE_FP64, tol=1e-13, compute_grid=True)[0]
+            assert r["converged"]
+            u = ctx.solution()
+            m = ~np.isnan(u_ref)
+            assert np.array_equal(~np.isnan(u), m)
+            assert np.abs(u[m] - u_ref[m]).max() < 1e-10 * np.abs(u_ref[m]).max(), particular
 
 
 # ------------------------------------------------------------------ A10: 16 right-hand sides (MFMA form)

@@ -57,16 +57,20 @@ extern "C" {
 
 #define BAE_PREC_FP64 0     /* FP64 LGF sum                                           */
 #define BAE_PREC_FP32 1     /* FP32 LGF sum, compensated accumulation                 */
+#define BAE_PREC_FFT 2      /* the LGF sum as an FFT convolution on the grid box, FP64
+                               (fast summation: O(B log B) for a box of B nodes instead
+                               of O(|targets| |sources|))                               */
 
 #define BAE_SOLVE_FP64 0          /* plain FP64 GMRES                                 */
 #define BAE_SOLVE_FP32_REFINED 1  /* FP64 iterative refinement around FP32-matvec GMRES */
+#define BAE_SOLVE_FFT 2           /* FP64 GMRES whose matvecs are FFT convolutions        */
 
 #define BAE_LAYER_DOUBLE 0        /* double-layer formulation (Sec. 3.4 eq. "double_bae") */
 #define BAE_LAYER_SINGLE 1        /* single-layer formulation (Sec. 3.4)                 */
 #define BAE_LAYER_DIRECT 2        /* direct formulation (Sec. 3.1, eq. "direct_sys"): the
                                      unknowns are v on gamma itself                      */
 
-#define BAE_PARTICULAR_FREE 0     /* u_p: the free-space volume potential (LGF sum)     */
+#define BAE_PARTICULAR_FREE 0     /* u_p: the free-space volume potential (LGF sum, FFT)  */
 #define BAE_PARTICULAR_BOX 1      /* u_p: Algorithm 1's finite-grid G_h[chi_{M+} f]      */
 
 /* ------------------------------------------------------------------ structs */
@@ -115,14 +119,16 @@ typedef struct bae_sizes {
 } bae_sizes;
 
 typedef struct bae_solve_params {
-    int32_t precision;         /* BAE_SOLVE_*                                       */
+    int32_t precision;         /* BAE_SOLVE_* (FFT: every matvec an FFT convolution) */
     double tol;                /* relative residual target ||b - A q|| / ||b||      */
     int32_t maxit;             /* GMRES iterations per (inner) solve; <= max_krylov */
     double inner_tol;          /* refined mode: floor of the inner FP32 GMRES tolerance
                                   (default 1e-6); each outer step asks for
                                   max(floor, 0.5 tol / current residual), capped at 0.1 */
     int32_t max_outer;         /* refinement steps (default 8)                       */
-    int32_t compute_grid;      /* also form u on N+ (volume-target LGF sums)         */
+    int32_t compute_grid;      /* also form u on N+: Algorithm 1's reconstruction
+                                  u = u_p + G_h[chi_{M-} L_h (u_gamma - u_p)] (one box
+                                  solve per RHS)                                      */
     int32_t recycle_dim;       /* refined mode: the first inner solve's Krylov space (at
                                   most this many vectors) augments the later inner
                                   solves (GCRO); 0 = automatic (64 once a matvec has
@@ -210,18 +216,19 @@ int bae_get_boundary_points(const bae_ctx* ctx, double* xstar, int32_t* partner,
 /*
  * Right-hand sides: g_xstar [nrhs][|gamma-|] (host), f_grid [nrhs][n0 n1 n2] (host, or
  * NULL for f = 0).  With f the particular solution u_p = h^2 sum_{M+} G_s(m-n) f(n) (the
- * free-space volume potential) is formed on gamma by the FP64 LGF sum, and b = g - Phi u_p.
+ * free-space volume potential) is formed on gamma by the LGF sum as an FP64 FFT convolution
+ * on the box of N+ u E (set up on first use), and b = g - Phi u_p.
  * nrhs in [1, max_rhs].  BAE_ERR_NONFINITE on NaN/Inf input.
  */
 int bae_set_rhs(bae_ctx* ctx, int32_t nrhs, const double* g_xstar, const double* f_grid);
 /*
  * The same with Algorithm 1's particular solution on the finite grid: u_p = G_h[chi_{M+} f],
  * G_h the inverse of the 7-point operator on the interior nodes of the box with u = 0 on its
- * boundary nodes (Sec. 2.1), by sine transforms along the three axes (DST-I, each a dense
- * contraction on the device), instead of the free-space volume LGF sum.  u, u_gamma and the
- * grid solution are the same discrete solution either way; the density q differs.  Needs a
- * cubic grid when f is given (BAE_ERR_ARG otherwise); with f == NULL it equals bae_set_rhs.
- * The context keeps u_p on the device (N^3 doubles per RHS, N = n - 2) for the grid solution.
+ * boundary nodes (Sec. 2.1), by sine transforms along the three axes (DST-I, each an FFT of
+ * length 2(N_d + 1); any n0 x n1 x n2 grid), instead of the free-space volume potential.  u,
+ * u_gamma and the grid solution are the same discrete solution either way; the density q
+ * differs.  With f == NULL it equals bae_set_rhs.  The context keeps u_p on the device
+ * ((n0-2)(n1-2)(n2-2) doubles per RHS) for the grid solution.
  */
 int bae_set_rhs_box(bae_ctx* ctx, int32_t nrhs, const double* g_xstar, const double* f_grid);
 /*

@@ -8,4 +8,4 @@ loudly when libbae.so has not been built (python -m paper_2502_05507_amd.build).
 """
 from .binding import (BaeError, Batch, Context, Server, lgf_table, lgf_table_noalloc, lgf_table_size,  # noqa: F401
                       load_library,
-                      PREC_FP64, PREC_FP32, SOLVE_FP64, SOLVE_FP32_REFINED, LAYER_DOUBLE, LAYER_SINGLE, LAYER_DIRECT, KINDS)
+                      PREC_FP64, PREC_FP32, PREC_FFT, SOLVE_FP64, SOLVE_FP32_REFINED, SOLVE_FFT, LAYER_DOUBLE, LAYER_SINGLE, LAYER_DIRECT, KINDS)

@@ -14,8 +14,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbae.so")
 
 OK, NOT_CONVERGED = 0, 1
-PREC_FP64, PREC_FP32 = 0, 1
-SOLVE_FP64, SOLVE_FP32_REFINED = 0, 1
+PREC_FP64, PREC_FP32, PREC_FFT = 0, 1, 2
+SOLVE_FP64, SOLVE_FP32_REFINED, SOLVE_FFT = 0, 1, 2
 LAYER_DOUBLE, LAYER_SINGLE, LAYER_DIRECT = 0, 1, 2
 PARTICULAR = {"free": 0, "box": 1}
 KINDS = {"sphere": 1, "ellipsoid": 2, "torus": 3, "star": 4, "sampled": 5}

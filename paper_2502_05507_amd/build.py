@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libbae.so")
 ARCH = "gfx950"
 
-SOURCES = ["geometry.cpp", "lgf_table.hip", "lgf_sum.hip", "ops.hip", "fft.hip", "bae.cpp", "batch.hip",
+SOURCES = ["geometry.cpp", "lgf_table.hip", "lgf_sum.hip", "ops.hip", "fft.hip", "conv.hip", "bae.cpp", "batch.hip",
            "server.cpp"]
 
 # Packed FP32 VALU forms are disabled for all device code; hipcc's host pass warns that it

@@ -83,9 +83,55 @@ void check_sum_error(bae_ctx* c) {
                              "since the last check are incomplete"};
 }
 
-// The current operator's LGF sum at the gamma targets (its sources, weights, work list).
+// The source weights are FP32 only for the FP32 sum kernels; the FFT convolution takes FP64.
+static int weight_prec(int prec) { return prec == BAE_PREC_FP32 ? BAE_PREC_FP32 : BAE_PREC_FP64; }
+
+// Box indices of a point set's points (internal order) in the convolution box.
+static std::vector<int32_t> conv_indices(const ConvPlan& cp, const PointSet& ps) {
+    std::vector<int32_t> v(ps.count);
+    for (int64_t i = 0; i < ps.count; ++i)
+        v[i] = (int32_t)cp.index(ps.hq[3 * i] / kQuant, ps.hq[3 * i + 1] / kQuant, ps.hq[3 * i + 2] / kQuant);
+    return v;
+}
+
+static void ensure_mplus(bae_ctx* c);
+
+// The FFT convolution of the LGF sum (lazy, once per context): its plan on the box of N+ u E
+// and the box index of every source and target.
+static void ensure_conv(bae_ctx* c, bool mplus = false) {
+    if (!c->conv) {
+        const Geometry& G = c->geo;
+        int64_t box = 1;
+        for (int a = 0; a < 3; ++a) box *= (int64_t)(G.bbox_hi[a] - G.bbox_lo[a] + 1);
+        if (box > INT32_MAX) throw Error{BAE_ERR_ARG, "LGF convolution: box beyond 2^31 nodes"};
+        auto cp = std::make_unique<ConvPlan>();
+        cp->build(G.bbox_lo, G.bbox_hi, c->tabs, c->stream);
+        upload(c->conv_sidx, conv_indices(*cp, c->S.ps), c->stream);
+        upload(c->conv_tidx, conv_indices(*cp, c->T.ps), c->stream);
+        BAE_HIP_CHECK(hipStreamSynchronize(c->stream));
+        c->conv = std::move(cp);
+    }
+    if (mplus && !c->conv_midx.p) {
+        ensure_mplus(c);
+        upload(c->conv_midx, conv_indices(*c->conv, c->Mp.ps), c->stream);
+        BAE_HIP_CHECK(hipStreamSynchronize(c->stream));
+    }
+}
+
+// The current operator's LGF sum at the gamma targets (its sources, weights, work list), or
+// with BAE_PREC_FFT its FFT convolution (one partial per target, FP64).
 static void apply_lgf(bae_ctx* c, const void* w, int nrhs, int prec, int* chunks_out, hipStream_t st,
                       const int32_t* skip = nullptr) {
+    if (prec == BAE_PREC_FFT) {
+        ensure_conv(c);
+        const int32_t* sidx = c->op.direct ? c->conv_tidx.as<int32_t>() : c->conv_sidx.as<int32_t>();
+        const int64_t ldw = c->op.S->padded;
+        for (int r = 0; r < nrhs; ++r)
+            c->conv->apply((const double*)w + r * ldw, sidx, c->op.S->count, c->conv_tidx.as<int32_t>(), c->nT,
+                           c->part.as<double>() + r * c->nT, 1.0, skip, st);
+        *chunks_out = 1;
+        return;
+    }
     *chunks_out = lgf_sum_launch(c->T.ps, *c->op.S, w, nrhs, prec, c->tabs, c->op.plan->plan, c->part.as<double>(),
                                  c->part_cap, c->sum_grid, st, skip);
 }
@@ -94,7 +140,7 @@ static void apply_lgf(bae_ctx* c, const void* w, int nrhs, int prec, int* chunks
 // layer), q [nrhs][ngm] with leading dimension ldq
 static void double_layer(bae_ctx* c, const double* q, int64_t ldq, double* v, int64_t ldv, int nrhs, int prec,
                          hipStream_t st) {
-    launch_weights(*c->op.B, q, ldq, c->w.p, c->op.S->padded, nrhs, prec, st);
+    launch_weights(*c->op.B, q, ldq, c->w.p, c->op.S->padded, nrhs, weight_prec(prec), st);
     int chunks = 0;
     apply_lgf(c, c->w.p, nrhs, prec, &chunks, st);
     launch_reduce_scatter(c->part.as<double>(), chunks, c->nT, c->t_pos.as<int32_t>(), v, ldv, nrhs, 1.0, st);
@@ -117,7 +163,7 @@ static void op_closure(bae_ctx* c, int chunks, const double* v, int64_t ldv, dou
 // direct system (the LGF sum skipped while *skip is set, when given)
 static void bae_operator(bae_ctx* c, const double* q, int64_t ldq, double* aq, int64_t lda, int nrhs, int prec,
                          hipStream_t st, const int32_t* skip = nullptr) {
-    launch_weights(*c->op.B, q, ldq, c->w.p, c->op.S->padded, nrhs, prec, st);
+    launch_weights(*c->op.B, q, ldq, c->w.p, c->op.S->padded, nrhs, weight_prec(prec), st);
     int chunks = 0;
     apply_lgf(c, c->w.p, nrhs, prec, &chunks, st, skip);
     op_closure(c, chunks, q, ldq, aq, lda, nrhs, st);
@@ -378,12 +424,12 @@ static GmresOut gmres(bae_ctx* c, const double* r0, int nrhs, int prec, double t
     // refined solve stop near 1e-6 and every result they feed is checked by an exact FP64
     // residual, so one pass is enough there: the two launches of the second pass cost 14% of
     // a 33^3 refined solve and change no iteration count on the test problems.
-    const bool two_pass = prec == BAE_PREC_FP64;
+    const bool two_pass = prec != BAE_PREC_FP32;
     double* wv = c->tmp.as<double>();
     double* pA = c->dotpart.as<double>();
     double* pB = pA + (int64_t)nrhs * c->maxj * dot_blocks(n);
     double* pN = pB + (int64_t)nrhs * c->maxj * dot_blocks(n);
-    launch_weights(*c->op.B, K.V, K.ld_rhs, c->w.p, c->op.S->padded, nrhs, prec, st);
+    launch_weights(*c->op.B, K.V, K.ld_rhs, c->w.p, c->op.S->padded, nrhs, weight_prec(prec), st);
     int k = 0;
     for (; k < m; ++k) {
         int chunks = 0;
@@ -405,7 +451,7 @@ static GmresOut gmres(bae_ctx* c, const double* r0, int nrhs, int prec, double t
             launch_subtract_combination(K.V, n, K.ld_rhs, pB, c->maxj, k + 1, n, nrhs, K.done, wv, n, pN, st);
         }
         launch_finish(K, wv, n, pA, two_pass ? pB : nullptr, c->maxj, pN, k, tol, *c->op.B, c->w.p, c->op.S->padded,
-                      prec, nrhs, lagged ? c->flags_dev + (k & 1) : nullptr, st);
+                      weight_prec(prec), nrhs, lagged ? c->flags_dev + (k & 1) : nullptr, st);
         if (lagged) {
             BAE_HIP_CHECK(hipEventRecord(ev[k & 1], st));
             if (k >= 1) {
@@ -509,9 +555,9 @@ static std::vector<double> host_norms(bae_ctx* c, const double* v, int nrhs, hip
 
 // r = b - A64 x ; returns ||r|| / ||b|| per RHS
 static std::vector<double> residual(bae_ctx* c, int nrhs, const std::vector<double>& bn, hipStream_t st,
-                                    int64_t* matvecs) {
+                                    int64_t* matvecs, int prec = BAE_PREC_FP64) {
     const int64_t n = c->op.n;
-    bae_operator(c, c->x.as<double>(), n, c->tmp.as<double>(), n, nrhs, BAE_PREC_FP64, st);
+    bae_operator(c, c->x.as<double>(), n, c->tmp.as<double>(), n, nrhs, prec, st);
     (*matvecs)++;
     BAE_HIP_CHECK(hipMemcpyAsync(c->r.p, rhs_vector(c), sizeof(double) * n * nrhs, hipMemcpyDeviceToDevice, st));
     launch_axpby(-1.0, c->tmp.as<double>(), n, 1.0, c->r.as<double>(), n, n, nrhs, st);
@@ -532,21 +578,6 @@ static void ensure_mplus(bae_ctx* c) {
                 if (G.inside[((int64_t)i * G.n[1] + j) * G.n[2] + k]) pts.insert(pts.end(), {i, j, k});
     const std::vector<int32_t> ord = morton_order(pts.data(), (int64_t)pts.size() / 3, G.bbox_lo);
     c->Mp.set(pts, ord, c->stream);
-}
-
-// out[r][t] (internal Mp or given target order) = sum over sources S of w G, FP64, into a
-// temporary partial buffer; result scattered through pos (or identity).
-static void lgf_sum_to(bae_ctx* c, const PointSet& T, const PointSet& S, const double* w, int nrhs,
-                       const int32_t* pos, double* out, int64_t ldo, double scale, hipStream_t st) {
-    PlanBuf plan;
-    plan.build(T, S, c->tabs, c->err_dev, c->wait_polls, st);
-    DevMem p;
-    const int64_t cap = (int64_t)plan.plan.chunks * T.count * nrhs;
-    p.alloc(sizeof(double) * cap);
-    int used = lgf_sum_launch(T, S, w, nrhs, BAE_PREC_FP64, c->tabs, plan.plan, p.as<double>(), cap, c->sum_grid, st);
-    launch_reduce_scatter(p.as<double>(), used, T.count, pos, out, ldo, nrhs, scale, st);
-    BAE_HIP_CHECK(hipStreamSynchronize(st));
-    check_sum_error(c);
 }
 
 int guard(const std::function<void()>& fn) {
@@ -910,6 +941,7 @@ int bae_get_sizes(const bae_ctx* c, bae_sizes* o) {
                                 &c->r, &c->tmp, &c->up_gamma, &c->u_gamma, &c->vsum, &c->wf, &c->plan.items,
                                 &c->plan.counter})
             bytes += d->bytes;
+        if (c->conv) bytes += (size_t)c->conv->bytes;
         o->device_bytes = (int64_t)bytes;
     });
 }
@@ -987,17 +1019,10 @@ static void ensure_box(bae_ctx* c) {
     c->box_ready = true;
 }
 
-// Lazy work list and partial-sum buffer of the (gamma targets, M+ sources) LGF sum that
-// forms the free-space particular solution.
-static void ensure_plan_mp(bae_ctx* c) {
-    if (c->plan_mp.items.p) return;
-    c->plan_mp.build(c->T.ps, c->Mp.ps, c->tabs, c->err_dev, c->wait_polls, c->stream);
-    c->part_mp.alloc(sizeof(double) * (int64_t)c->plan_mp.plan.chunks * c->nT * c->max_rhs);
-}
-
 // The device part of the right-hand side, on stream st: with f (h^2 f at the M+ points
 // already in c->wf, [nrhs][Mp padded]) the particular solution u_p on gamma -- the free-space
-// volume potential (LGF sum over the M+ sources) or, with `box`, Algorithm 1's finite-grid
+// volume potential (the LGF sum over the M+ sources as an FFT convolution) or, with `box`,
+// Algorithm 1's finite-grid
 // G_h[chi_{M+} f] (box.hip) -- then b = g - Phi u_p (Sec. 3.4) from g (device, [nrhs][ngm]).
 static void rhs_on_device(bae_ctx* c, int nrhs, const double* g, int64_t ldg, bool has_f, bool box, hipStream_t st) {
     const int64_t nmp = c->Mp.ps.padded;
@@ -1010,11 +1035,13 @@ static void rhs_on_device(bae_ctx* c, int nrhs, const double* g, int64_t ldg, bo
         launch_gather(c->box_u.as<double>(), nn, c->box_tidx.as<int32_t>(), c->nT, c->up_gamma.as<double>(), c->nT,
                       nrhs, 1.0, st);
     } else if (has_f) {
-        const int used = lgf_sum_launch(c->T.ps, c->Mp.ps, c->wf.as<double>(), nrhs, BAE_PREC_FP64, c->tabs,
-                                        c->plan_mp.plan, c->part_mp.as<double>(),
-                                        (int64_t)c->plan_mp.plan.chunks * c->nT * c->max_rhs, c->sum_grid, st);
-        launch_reduce_scatter(c->part_mp.as<double>(), used, c->nT, c->t_pos.as<int32_t>(), c->up_gamma.as<double>(),
-                              c->nT, nrhs, 1.0, st);
+        // the free-space volume potential h^2 sum_{M+} G(m - n) f(n) on gamma, by the FFT
+        // convolution (FP64), in internal target order, then into [gamma+; gamma-] order
+        for (int r = 0; r < nrhs; ++r)
+            c->conv->apply(c->wf.as<double>() + r * nmp, c->conv_midx.as<int32_t>(), c->Mp.ps.count,
+                           c->conv_tidx.as<int32_t>(), c->nT, c->vsum.as<double>() + r * c->nT, 1.0, nullptr, st);
+        launch_reduce_scatter(c->vsum.as<double>(), 1, c->nT, c->t_pos.as<int32_t>(), c->up_gamma.as<double>(), c->nT,
+                              nrhs, 1.0, st);
     } else {
         launch_fill(c->up_gamma.as<double>(), c->nT * nrhs, 0.0, st);
     }
@@ -1052,7 +1079,7 @@ static void set_rhs_impl(bae_ctx* c, int32_t nrhs, const double* g_xstar, const 
             if (!std::isfinite(f_grid[i])) throw Error{BAE_ERR_NONFINITE, "source term not finite"};
         ensure_lin(c);
         if (box) ensure_box(c);
-        else ensure_plan_mp(c);
+        else ensure_conv(c, true);
         const int64_t nm = c->Mp.ps.count, nmp = c->Mp.ps.padded;
         std::vector<double> wfh(nmp * nrhs, 0.0);
         const double h2 = G.h * G.h;
@@ -1084,7 +1111,7 @@ static void set_rhs_device_impl(bae_ctx* c, int32_t nrhs, const double* g_dev, c
         // caller's work is touched
         ensure_lin(c);
         if (box) ensure_box(c);
-        else ensure_plan_mp(c);
+        else ensure_conv(c, true);
         const int64_t nmp = c->Mp.ps.padded;
         if (c->wf.bytes < sizeof(double) * nmp * nrhs) c->wf.alloc(sizeof(double) * nmp * c->max_rhs);
         if (box && c->box_u.bytes < sizeof(double) * c->box_nn * nrhs)
@@ -1133,8 +1160,10 @@ static void grid_solution(bae_ctx* c, int nrhs, hipStream_t st) {
         up.alloc(sizeof(double) * nm * nrhs);
         if (c->particular_box)   // the finite-grid u_p is known at every node
             launch_gather(c->box_u.as<double>(), nn, c->box_mpidx.as<int32_t>(), nm, up.as<double>(), nm, nrhs, 1.0, st);
-        else
-            lgf_sum_to(c, c->Mp.ps, c->Mp.ps, c->wf.as<double>(), nrhs, nullptr, up.as<double>(), nm, 1.0, st);
+        else   // the free-space volume potential at the M+ targets, by the FFT convolution
+            for (int r = 0; r < nrhs; ++r)
+                c->conv->apply(c->wf.as<double>() + r * c->Mp.ps.padded, c->conv_midx.as<int32_t>(), nm,
+                               c->conv_midx.as<int32_t>(), nm, up.as<double>() + r * nm, 1.0, nullptr, st);
         launch_axpby(1.0, up.as<double>(), nm, 1.0, um.as<double>(), nm, nm, nrhs, st);
         BAE_HIP_CHECK(hipStreamSynchronize(st));   // up leaves scope
     }
@@ -1150,7 +1179,7 @@ static void grid_solution(bae_ctx* c, int nrhs, hipStream_t st) {
 static void check_solve_args(const bae_ctx* c, const bae_solve_params* p) {
     if (!c || !p) throw Error{BAE_ERR_ARG, "null argument"};
     if (!c->rhs_ready) throw Error{BAE_ERR_STATE, "bae_set_rhs must precede bae_solve"};
-    if (p->precision != BAE_SOLVE_FP64 && p->precision != BAE_SOLVE_FP32_REFINED)
+    if (p->precision != BAE_SOLVE_FP64 && p->precision != BAE_SOLVE_FP32_REFINED && p->precision != BAE_SOLVE_FFT)
         throw Error{BAE_ERR_ARG, "unknown solve precision"};
     if (!(p->tol > 0.0)) throw Error{BAE_ERR_ARG, "tol must be > 0"};
     if (p->formulation != BAE_LAYER_DOUBLE && p->formulation != BAE_LAYER_SINGLE && p->formulation != BAE_LAYER_DIRECT)
@@ -1196,10 +1225,12 @@ static int solve_impl(bae_ctx* c, const bae_solve_params* p, bae_result* res) {
     } else {
         launch_fill(c->x.as<double>(), n * nrhs, 0.0, st);
     }
-    if (p->precision == BAE_SOLVE_FP64) {
+    if (p->precision == BAE_SOLVE_FP64 || p->precision == BAE_SOLVE_FFT) {
+        // FP64 GMRES with the FP64 sum or its FFT convolution for every matvec
+        const int mprec = p->precision == BAE_SOLVE_FFT ? BAE_PREC_FFT : BAE_PREC_FP64;
         // from x0: GMRES on A d = b - A x0, x = x0 + d
         if (warm) {
-            relres = residual(c, nrhs, bn, st, &mv64);
+            relres = residual(c, nrhs, bn, st, &mv64, mprec);
             if (__atomic_exchange_n(c->bad_host, 0, __ATOMIC_ACQ_REL))
                 throw Error{BAE_ERR_NONFINITE, "initial densities not finite"};
         }
@@ -1215,14 +1246,14 @@ static int solve_impl(bae_ctx* c, const bae_solve_params* p, bae_result* res) {
             dq_in_vsum = true;
         }
         if (!all) {   // (a warm start that already meets tol needs no iteration)
-            GmresOut g = gmres(c, warm ? c->r.as<double>() : rhs_vector(c), nrhs, BAE_PREC_FP64, p->tol, maxit,
-                               skip, c->x.as<double>(), warm, st, &mv64);
+            GmresOut g = gmres(c, warm ? c->r.as<double>() : rhs_vector(c), nrhs, mprec, p->tol, maxit, skip,
+                               c->x.as<double>(), warm, st, &mv64);
             for (int r = 0; r < nrhs; ++r) {
                 iters[r] = g.iters[r];
                 est[r] = g.last_est[r];
                 conv[r] = g.converged[r];
             }
-            relres = residual(c, nrhs, bn, st, &mv64);
+            relres = residual(c, nrhs, bn, st, &mv64, mprec);
             dq_in_vsum = true;
         }
         for (int r = 0; r < nrhs; ++r) conv[r] = conv[r] || relres[r] <= p->tol;
@@ -1527,7 +1558,8 @@ int bae_apply_double_layer(bae_ctx* c, const double* q, double* v, int32_t nrhs,
     return guard([&] {
         if (!c || !q || !v) throw Error{BAE_ERR_ARG, "null argument"};
         if (nrhs < 1 || nrhs > c->max_rhs) throw Error{BAE_ERR_ARG, "nrhs out of range"};
-        if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32) throw Error{BAE_ERR_ARG, "unknown precision"};
+        if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32 && prec != BAE_PREC_FFT)
+            throw Error{BAE_ERR_ARG, "unknown precision"};
         BAE_HIP_CHECK(hipSetDevice(c->device));
         join_job(c);
         check_sum_error(c);   // a sum queued by an earlier call gave up
@@ -1539,7 +1571,8 @@ int bae_apply_single_layer(bae_ctx* c, const double* q, double* v, int32_t nrhs,
     return guard([&] {
         if (!c || !q || !v) throw Error{BAE_ERR_ARG, "null argument"};
         if (nrhs < 1 || nrhs > c->max_rhs) throw Error{BAE_ERR_ARG, "nrhs out of range"};
-        if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32) throw Error{BAE_ERR_ARG, "unknown precision"};
+        if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32 && prec != BAE_PREC_FFT)
+            throw Error{BAE_ERR_ARG, "unknown precision"};
         BAE_HIP_CHECK(hipSetDevice(c->device));
         join_job(c);
         check_sum_error(c);   // a sum queued by an earlier call gave up
@@ -1552,7 +1585,8 @@ int bae_apply_operator(bae_ctx* c, const double* q, double* aq, int32_t nrhs, in
     return guard([&] {
         if (!c || !q || !aq) throw Error{BAE_ERR_ARG, "null argument"};
         if (nrhs < 1 || nrhs > c->max_rhs) throw Error{BAE_ERR_ARG, "nrhs out of range"};
-        if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32) throw Error{BAE_ERR_ARG, "unknown precision"};
+        if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32 && prec != BAE_PREC_FFT)
+            throw Error{BAE_ERR_ARG, "unknown precision"};
         BAE_HIP_CHECK(hipSetDevice(c->device));
         join_job(c);
         check_sum_error(c);   // a sum queued by an earlier call gave up
@@ -1564,7 +1598,8 @@ int bae_apply_direct(bae_ctx* c, const double* v, double* y, int32_t nrhs, int32
     return guard([&] {
         if (!c || !v || !y) throw Error{BAE_ERR_ARG, "null argument"};
         if (nrhs < 1 || nrhs > c->max_rhs) throw Error{BAE_ERR_ARG, "nrhs out of range"};
-        if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32) throw Error{BAE_ERR_ARG, "unknown precision"};
+        if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32 && prec != BAE_PREC_FFT)
+            throw Error{BAE_ERR_ARG, "unknown precision"};
         join_job(c);
         BAE_HIP_CHECK(hipSetDevice(c->device));
         check_sum_error(c);   // a sum queued by an earlier call gave up
@@ -1577,13 +1612,14 @@ int bae_lgf_sum_repeat(bae_ctx* c, const double* q, int32_t nrhs, int32_t prec, 
     return guard([&] {
         if (!c || !q) throw Error{BAE_ERR_ARG, "null argument"};
         if (nrhs < 1 || nrhs > c->max_rhs) throw Error{BAE_ERR_ARG, "nrhs out of range"};
-        if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32) throw Error{BAE_ERR_ARG, "unknown precision"};
+        if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32 && prec != BAE_PREC_FFT)
+            throw Error{BAE_ERR_ARG, "unknown precision"};
         if (repeats < 1 || repeats > 1000) throw Error{BAE_ERR_ARG, "repeats must be in [1, 1000]"};
         BAE_HIP_CHECK(hipSetDevice(c->device));
         join_job(c);
         check_sum_error(c);   // a sum queued by an earlier call gave up
         const hipStream_t st = (hipStream_t)stream;
-        launch_weights(c->B, q, c->ngm, c->w.p, c->S.ps.padded, nrhs, prec, st);
+        launch_weights(c->B, q, c->ngm, c->w.p, c->S.ps.padded, nrhs, weight_prec(prec), st);
         for (int i = 0; i < repeats; ++i) {
             int chunks = 0;
             apply_lgf(c, c->w.p, nrhs, prec, &chunks, st);
@@ -1594,7 +1630,8 @@ int bae_lgf_sum_repeat(bae_ctx* c, const double* q, int32_t nrhs, int32_t prec, 
 int bae_sum_stats(const bae_ctx* c, int32_t prec, int64_t* counts) {
     return guard([&] {
         if (!c || !counts) throw Error{BAE_ERR_ARG, "null argument"};
-        if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32) throw Error{BAE_ERR_ARG, "unknown precision"};
+        if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32)
+            throw Error{BAE_ERR_ARG, "precision: BAE_PREC_FP64 or BAE_PREC_FP32 (the sum kernels)"};
         const bool fp32 = prec == BAE_PREC_FP32;
         const int tab_r = fp32 ? c->tabs.tab_r32 : c->tabs.tab_r64;
         for (int i = 0; i < 5; ++i) counts[i] = 0;
@@ -1606,7 +1643,8 @@ int bae_sum_stats(const bae_ctx* c, int32_t prec, int64_t* counts) {
 int bae_lgf_eval(bae_ctx* c, const int32_t* off, int64_t count, double* out, int32_t prec, void* stream) {
     return guard([&] {
         if (!c || (count > 0 && (!off || !out)) || count < 0) throw Error{BAE_ERR_ARG, "bad argument"};
-        if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32) throw Error{BAE_ERR_ARG, "unknown precision"};
+        if (prec != BAE_PREC_FP64 && prec != BAE_PREC_FP32)
+            throw Error{BAE_ERR_ARG, "precision: BAE_PREC_FP64 or BAE_PREC_FP32 (the sum kernels)"};
         BAE_HIP_CHECK(hipSetDevice(c->device));
         lgf_eval_launch(off, count, out, prec, c->tabs, (hipStream_t)stream);
     });

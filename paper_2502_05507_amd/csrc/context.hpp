@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "conv.hpp"
 #include "internal.hpp"
 #include "ops.hpp"
 
@@ -206,6 +207,11 @@ struct bae_ctx {
     int64_t vec_cap = 0;       // elements per RHS of b, x, r, tmp and the Krylov vectors
     int64_t dens_n = 0;        // length of the last solve's density (|gamma-|, or |gamma| for direct)
     int batch_refs = 0;        // batches holding this context (they keep pointers to its vectors)
+    // the LGF sum by FFT convolution on the box of N+ u E (lazy): the plan, and the box index
+    // of every source (gamma- u E), target (gamma, also the direct formulation's sources) and
+    // M+ point, each in its point set's internal order
+    std::unique_ptr<ConvPlan> conv;
+    DevMem conv_sidx, conv_tidx, conv_midx;
     DevMem cl_tq, cl_tp, cl_t;
     Closure cl;
     std::shared_ptr<Table> table;
@@ -245,8 +251,6 @@ struct bae_ctx {
     DevMem gdev;                            // [max_rhs][ngm] boundary data staged from the host
     DevMem partner_dev;                     // gamma+ index of each gamma- node's partner
     DevMem mp_lin_dev, gm_lin_dev;          // linear grid index of each M+ (Mp order) / gamma- node (lazy)
-    PlanBuf plan_mp;                        // work list of the (gamma, M+) sum of u_p (lazy)
-    DevMem part_mp;
     hipEvent_t rhs_ev = nullptr;            // end of the last right-hand side's device work
     // a solve started by bae_solve_async, driven by a host thread of its own
     struct Job {

@@ -37,6 +37,8 @@ __global__ __launch_bounds__(kConvThreads) void conv_z_fwd(const double* __restr
     const int M = p.M, nfft = P / 2;
     double2* A = lds;
     double2* B = lds + (int64_t)nfft * M;
+    double2* tw = B + (int64_t)nfft * M;
+    load_roots(p, tw);
     double* Ad = (double*)A;
     const int64_t l0 = (int64_t)blockIdx.x * P, nl = (int64_t)e0 * e1;
     for (int e = threadIdx.x; e < nfft * M; e += blockDim.x) A[e] = make_double2(0.0, 0.0);
@@ -47,7 +49,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_z_fwd(const double* __restr
         if (l < nl) Ad[2 * ((int64_t)(pl >> 1) * M + k) + (pl & 1)] = R[l * e2 + k];
     }
     __syncthreads();
-    const double2* Z = fft_lds(A, B, nfft, p, false);
+    const double2* Z = fft_lds(A, B, nfft, p, tw, false);
     for (int e = threadIdx.x; e < P * M; e += blockDim.x) {
         const int pl = e / M, k = e - pl * M;
         const int64_t l = l0 + pl;
@@ -76,6 +78,8 @@ __global__ __launch_bounds__(kConvThreads) void conv_lines(double2* __restrict__
     const int M = p.M;
     double2* A = lds;
     double2* B = lds + (int64_t)P * M;
+    double2* tw = B + (int64_t)P * M;
+    load_roots(p, tw);
     const int64_t l0 = (int64_t)blockIdx.x * P;
     const int nl = mode == 2 ? M : nload;
     for (int e = threadIdx.x; e < P * M; e += blockDim.x) {
@@ -86,7 +90,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_lines(double2* __restrict__
         A[(int64_t)pl * M + n] = v;
     }
     __syncthreads();
-    double2* Z = fft_lds(A, B, P, p, mode == 2);
+    double2* Z = fft_lds(A, B, P, p, tw, mode == 2);
     if (mode == 1) {
         double2* other = Z == A ? B : A;
         for (int e = threadIdx.x; e < P * M; e += blockDim.x) {
@@ -101,7 +105,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_lines(double2* __restrict__
             Z[(int64_t)pl * M + n] = make_double2(g * z.x, g * z.y);
         }
         __syncthreads();
-        Z = fft_lds(Z, other, P, p, true);
+        Z = fft_lds(Z, other, P, p, tw, true);
     }
     for (int e = threadIdx.x; e < P * nstore; e += blockDim.x) {
         const int n = e / P, pl = e - n * P;
@@ -120,6 +124,8 @@ __global__ __launch_bounds__(kConvThreads) void conv_z_inv(const double2* __rest
     const int M = p.M, nfft = P / 2;
     double2* A = lds;
     double2* B = lds + (int64_t)nfft * M;
+    double2* tw = B + (int64_t)nfft * M;
+    load_roots(p, tw);
     const int64_t l0 = (int64_t)blockIdx.x * P, nl = (int64_t)e0 * e1;
     for (int e = threadIdx.x; e < nfft * M; e += blockDim.x) {
         const int c = e / M, k = e - c * M;
@@ -130,7 +136,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_z_inv(const double2* __rest
         A[e] = make_double2(xa.x - xb.y, xa.y + xb.x);
     }
     __syncthreads();
-    const double2* Z = fft_lds(A, B, nfft, p, true);
+    const double2* Z = fft_lds(A, B, nfft, p, tw, true);
     for (int e = threadIdx.x; e < P * e2; e += blockDim.x) {
         const int pl = e / e2, k = e - pl * e2;
         const int64_t l = l0 + pl;
@@ -226,7 +232,7 @@ void run_lines(const ConvPlan& cp, double2* C, int axis, int nload, int nstore, 
         sline = (int64_t)M1 * M2;
     }
     const int P = lines_for(p.M, false);
-    const size_t lds = sizeof(double2) * 2 * (size_t)P * p.M;
+    const size_t lds = sizeof(double2) * (2 * (size_t)P + 1) * p.M;
     conv_lines<<<(unsigned)((nlines + P - 1) / P), kConvThreads, lds, st>>>(
         C, nlines, lin, sout, sline, nload, nstore, mode, p, P, cp.ghat, M1, M2, cp.H[1], cp.H[2], skip);
     BAE_HIP_CHECK(hipGetLastError());
@@ -280,19 +286,19 @@ void ConvPlan::build(const int lo_[3], const int hi_[3], const SumTables& tabs, 
     {   // z: rows of the full grid (complex, contiguous)
         const int P = lines_for(M[2], false);
         const int64_t nl = (int64_t)M[0] * M[1];
-        conv_lines<<<(unsigned)((nl + P - 1) / P), kConvThreads, sizeof(double2) * 2 * (size_t)P * M[2], st>>>(
+        conv_lines<<<(unsigned)((nl + P - 1) / P), kConvThreads, sizeof(double2) * (2 * (size_t)P + 1) * M[2], st>>>(
             g, nl, 1, M[2], 1, M[2], M[2], 0, fz, P, nullptr, M[1], M[2], H[1], H[2], nullptr);
         BAE_HIP_CHECK(hipGetLastError());
     }
     {   // y over every plane, x over every line
         const int P = lines_for(M[1], false);
         const int64_t nl = (int64_t)M[0] * M[2];
-        conv_lines<<<(unsigned)((nl + P - 1) / P), kConvThreads, sizeof(double2) * 2 * (size_t)P * M[1], st>>>(
+        conv_lines<<<(unsigned)((nl + P - 1) / P), kConvThreads, sizeof(double2) * (2 * (size_t)P + 1) * M[1], st>>>(
             g, nl, M[2], (int64_t)M[1] * M[2], M[2], M[1], M[1], 0, fy, P, nullptr, M[1], M[2], H[1], H[2], nullptr);
         BAE_HIP_CHECK(hipGetLastError());
         const int Px = lines_for(M[0], false);
         const int64_t nlx = (int64_t)M[1] * M[2];
-        conv_lines<<<(unsigned)((nlx + Px - 1) / Px), kConvThreads, sizeof(double2) * 2 * (size_t)Px * M[0], st>>>(
+        conv_lines<<<(unsigned)((nlx + Px - 1) / Px), kConvThreads, sizeof(double2) * (2 * (size_t)Px + 1) * M[0], st>>>(
             g, nlx, nlx, 0, nlx, M[0], M[0], 0, fx, Px, nullptr, M[1], M[2], H[1], H[2], nullptr);
         BAE_HIP_CHECK(hipGetLastError());
     }
@@ -310,7 +316,7 @@ void ConvPlan::apply(const double* w, const int32_t* sidx, int64_t ns, const int
     BAE_HIP_CHECK(hipGetLastError());
     const int Pz = lines_for(M[2], true);
     const int64_t nrow = (int64_t)e[0] * e[1];
-    const size_t ldsz = sizeof(double2) * (size_t)Pz * M[2];   // two buffers of Pz / 2 lines
+    const size_t ldsz = sizeof(double2) * (size_t)(Pz + 1) * M[2];   // two buffers of Pz / 2 lines, the roots
     conv_z_fwd<<<(unsigned)((nrow + Pz - 1) / Pz), kConvThreads, ldsz, st>>>(R, e[0], e[1], e[2], M[1], C, fz, Pz,
                                                                            skip);
     BAE_HIP_CHECK(hipGetLastError());

@@ -51,6 +51,8 @@ __global__ void dst_axis_kernel(double* __restrict__ x, int axis, int n0, int n1
     const int nfft = P / 2;
     double2* A = lds;
     double2* B = lds + (int64_t)nfft * M;
+    double2* tw = B + (int64_t)nfft * M;
+    load_roots(p, tw);
     const int64_t l0 = (int64_t)blockIdx.x * P;
     double* Ad = (double*)A;
     // the two end points of every odd extension are zero
@@ -74,7 +76,7 @@ __global__ void dst_axis_kernel(double* __restrict__ x, int axis, int n0, int n1
         Ad[2 * (c * M + M - n - 1) + comp] = -v;
     }
     __syncthreads();
-    const double2* Z = fft_lds(A, B, nfft, p, false);
+    const double2* Z = fft_lds(A, B, nfft, p, tw, false);
     const double h = 0.5 * scale;
     for (int e = threadIdx.x; e < P * N; e += blockDim.x) {
         int pl, n;
@@ -198,7 +200,7 @@ void dst_axis(double* x, int n0, int n1, int n2, int axis, double scale, hipStre
     const FftDev p = fft_plan(2 * (N + 1), st);
     const int P = lines_per_block(p.M);
     const int64_t nlines = (int64_t)n0 * n1 * n2 / N;
-    const size_t lds = sizeof(double2) * (size_t)P * p.M;
+    const size_t lds = sizeof(double2) * (size_t)(P + 1) * p.M;   // two buffers of P / 2 lines, the roots
     static bool attr = false;
     if (!attr) {
         BAE_HIP_CHECK(hipFuncSetAttribute((const void*)dst_axis_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -1,4 +1,11 @@
 // Device side of the LDS FFT (shared by the sine transforms and the LGF convolution).
+//
+// Stockham autosort stages in LDS: stage s with radix R and stride Ns maps input j + r M/R
+// (r < R), twiddled by w^(r (j mod Ns) M/(Ns R)), to output (j div Ns) Ns R + (j mod Ns) + k Ns
+// after an R-point DFT (w = e^(-2 pi i / M)).  Radices 2, 3, 4 and 5 have their butterflies
+// written out, in registers; any other prime evaluates each output as an R-term sum straight
+// from LDS.  The root table is staged in LDS by the caller.  Index divisions by stage
+// constants go through a float reciprocal with one correction step (exact for the sizes here).
 #pragma once
 
 #include "fft.hpp"
@@ -11,77 +18,129 @@ __device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_doub
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
 }
-// the table root w^t = e^(-2 pi i t / M), conjugated for the inverse transform
-__device__ __forceinline__ double2 root(const FftDev& p, int t, bool inv) {
-    const double2 w = p.tw[t];
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(s * a.x, s * a.y); }
+// the root w^t, conjugated for the inverse transform
+__device__ __forceinline__ double2 root(const double2* tw, int t, bool inv) {
+    const double2 w = tw[t];
     return inv ? make_double2(w.x, -w.y) : w;
 }
 // multiplication by -i (forward) or +i (inverse)
 __device__ __forceinline__ double2 rot(double2 a, bool inv) {
     return inv ? make_double2(-a.y, a.x) : make_double2(a.y, -a.x);
 }
+// e div d for 0 <= e < 2^22, rd = 1/d in float
+__device__ __forceinline__ int fdiv(int e, int d, float rd) {
+    int q = (int)((float)e * rd);
+    if (q * d > e) --q;
+    else if ((q + 1) * d <= e) ++q;
+    return q;
+}
 
-constexpr int kRegRadix = 8;   // radices up to this run their DFT in registers
+template <int R>
+__device__ __forceinline__ void butterfly(double2 (&v)[R], bool inv) {
+    if constexpr (R == 2) {
+        const double2 a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (R == 4) {
+        const double2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+        const double2 c = cadd(v[1], v[3]), d = rot(csub(v[1], v[3]), inv);
+        v[0] = cadd(a, c);
+        v[1] = cadd(b, d);
+        v[2] = csub(a, c);
+        v[3] = csub(b, d);
+    } else if constexpr (R == 3) {
+        constexpr double s3 = 0.86602540378443864676;   // sin(2 pi / 3)
+        const double2 a = cadd(v[1], v[2]);
+        const double2 t = make_double2(v[0].x - 0.5 * a.x, v[0].y - 0.5 * a.y);
+        const double2 d = rot(cscale(csub(v[1], v[2]), s3), inv);
+        v[0] = cadd(v[0], a);
+        v[1] = cadd(t, d);
+        v[2] = csub(t, d);
+    } else if constexpr (R == 5) {
+        constexpr double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;   // cos(2pi/5), cos(4pi/5)
+        constexpr double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;    // sin(2pi/5), sin(4pi/5)
+        const double2 a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+        const double2 a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+        const double2 x0 = v[0];
+        const double2 p1 = make_double2(x0.x + c1 * a1.x + c2 * a2.x, x0.y + c1 * a1.y + c2 * a2.y);
+        const double2 p2 = make_double2(x0.x + c2 * a1.x + c1 * a2.x, x0.y + c2 * a1.y + c1 * a2.y);
+        const double2 q1 = rot(make_double2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y), inv);
+        const double2 q2 = rot(make_double2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y), inv);
+        v[0] = cadd(x0, cadd(a1, a2));
+        v[1] = cadd(p1, q1);
+        v[4] = csub(p1, q1);
+        v[2] = cadd(p2, q2);
+        v[3] = csub(p2, q2);
+    }
+}
 
-// `count` FFTs of length p.M stored one after another at src (LDS); ping-pong with dst.
-// Returns the buffer that holds the result.  Every thread of the block must call it.
-static __device__ __noinline__ double2* fft_lds(double2* src, double2* dst, int count, const FftDev& p, bool inv) {
+template <int R>
+__device__ __forceinline__ void stage(const double2* __restrict__ src, double2* __restrict__ dst, int count, int M,
+                                      int Ns, const double2* __restrict__ tw, bool inv) {
+    const int m = M / R, tstep = M / (Ns * R), total = count * m;
+    const float rm = 1.0f / (float)m, rns = 1.0f / (float)Ns;
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+        const int c = fdiv(e, m, rm), j = e - c * m;
+        const int jq = fdiv(j, Ns, rns), jm = j - jq * Ns;
+        const double2* in = src + c * M;
+        double2* out = dst + c * M;
+        double2 v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[r] = in[j + r * m];
+        if (jm > 0) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[r] = cmul(v[r], root(tw, r * jm * tstep, inv));
+        }
+        butterfly<R>(v, inv);
+        const int o = jq * Ns * R + jm;
+#pragma unroll
+        for (int k = 0; k < R; ++k) out[o + k * Ns] = v[k];
+    }
+}
+
+// any radix R: every output an R-term sum, X = sum_r in[j + r m] w^(r base)
+__device__ __forceinline__ void stage_any(const double2* __restrict__ src, double2* __restrict__ dst, int count, int M,
+                                          int Ns, int R, const double2* __restrict__ tw, bool inv) {
+    const int m = M / R, tstep = M / (Ns * R), total = count * M;
+    const float rM = 1.0f / (float)M, rm = 1.0f / (float)m, rns = 1.0f / (float)Ns;
+    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+        const int c = fdiv(e, M, rM), q = e - c * M;
+        const int k = fdiv(q, m, rm), j = q - k * m;
+        const int jq = fdiv(j, Ns, rns), jm = j - jq * Ns;
+        const double2* in = src + c * M;
+        const int base = jm * tstep + k * m;   // < M
+        double2 acc = in[j];
+        int t = 0;
+        for (int r = 1; r < R; ++r) {
+            t += base;
+            if (t >= M) t -= M;
+            acc = cadd(acc, cmul(in[j + r * m], root(tw, t, inv)));
+        }
+        dst[c * M + jq * Ns * R + jm + k * Ns] = acc;
+    }
+}
+
+// Copies the root table (M entries) into LDS; the caller synchronises before fft_lds.
+__device__ __forceinline__ void load_roots(const FftDev& p, double2* tw) {
+    for (int t = threadIdx.x; t < p.M; t += blockDim.x) tw[t] = p.tw[t];
+}
+
+// `count` FFTs of length p.M stored one after another at src (LDS); ping-pong with dst; tw: the
+// root table in LDS.  Returns the buffer that holds the result.  Every thread of the block
+// must call it.
+__device__ __forceinline__ double2* fft_lds(double2* src, double2* dst, int count, const FftDev& p,
+                                            const double2* tw, bool inv) {
     const int M = p.M;
     int Ns = 1;
     for (int s = 0; s < p.nf; ++s) {
         const int R = p.f[s];
-        const int m = M / R;              // butterflies per line
-        const int tstep = M / (Ns * R);   // root index of the twiddle step
-        if (R <= kRegRadix) {
-            for (int e = threadIdx.x; e < count * m; e += blockDim.x) {
-                const int c = e / m, j = e - c * m;
-                const double2* in = src + (int64_t)c * M;
-                double2* out = dst + (int64_t)c * M;
-                const int jm = j % Ns;
-                double2 v[kRegRadix];
-                for (int r = 0; r < R; ++r) {
-                    v[r] = in[j + r * m];
-                    if (r > 0 && jm > 0) v[r] = cmul(v[r], root(p, (r * jm * tstep) % M, inv));
-                }
-                const int o = (j / Ns) * Ns * R + jm;
-                if (R == 2) {
-                    out[o] = cadd(v[0], v[1]);
-                    out[o + Ns] = csub(v[0], v[1]);
-                } else if (R == 4) {
-                    const double2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
-                    const double2 c2 = cadd(v[1], v[3]), d = rot(csub(v[1], v[3]), inv);
-                    out[o] = cadd(a, c2);
-                    out[o + Ns] = cadd(b, d);
-                    out[o + 2 * Ns] = csub(a, c2);
-                    out[o + 3 * Ns] = csub(b, d);
-                } else {
-                    // R-point DFT with the table: X_k = sum_r v_r w^(r k M / R)
-                    const int rs = M / R;
-                    for (int k = 0; k < R; ++k) {
-                        double2 acc = v[0];
-                        for (int r = 1; r < R; ++r) acc = cadd(acc, cmul(v[r], root(p, ((r * k) % R) * rs, inv)));
-                        out[o + k * Ns] = acc;
-                    }
-                }
-            }
-        } else {
-            // large prime radix: each output directly, X = sum_r in[j + r m] w^(r base)
-            for (int e = threadIdx.x; e < count * M; e += blockDim.x) {
-                const int c = e / M, q = e - c * M;
-                const int k = q / m, j = q - k * m;
-                const double2* in = src + (int64_t)c * M;
-                double2* out = dst + (int64_t)c * M;
-                const int jm = j % Ns;
-                const int base = (jm * tstep + k * (M / R)) % M;
-                double2 acc = in[j];
-                int t = 0;
-                for (int r = 1; r < R; ++r) {
-                    t += base;
-                    if (t >= M) t -= M;
-                    acc = cadd(acc, cmul(in[j + r * m], root(p, t, inv)));
-                }
-                out[(j / Ns) * Ns * R + jm + k * Ns] = acc;
-            }
+        switch (R) {
+            case 2: stage<2>(src, dst, count, M, Ns, tw, inv); break;
+            case 3: stage<3>(src, dst, count, M, Ns, tw, inv); break;
+            case 4: stage<4>(src, dst, count, M, Ns, tw, inv); break;
+            case 5: stage<5>(src, dst, count, M, Ns, tw, inv); break;
+            default: stage_any(src, dst, count, M, Ns, R, tw, inv); break;
         }
         __syncthreads();
         double2* x = src;

@@ -104,6 +104,53 @@ def flops_of(stats, prec, nrhs, sigma0, far_ok):
     return F_FAR * far_values(stats, prec, sigma0, far_ok) + F_RHS * nrhs * pairs
 
 
+PEAK_HBM = 8000.0   # GB/s, MI355X HBM3E
+
+
+def conv_bytes(z):
+    """Algorithmic HBM bytes of one FFT convolution (one right-hand side) on the box of extents
+    e with FFT lengths M (bae_sizes conv_box / conv_fft): every pass reads and writes the pruned
+    arrays once -- real box E, half-spectrum rows e0 e1 H2, planes e0 M1 H2, the kernel's
+    transform on one octant H0 H1 H2 (complex 16 B, real 8 B)."""
+    e, M = z["conv_box"], z["conv_fft"]
+    H = [m // 2 + 1 for m in M]
+    E = e[0] * e[1] * e[2]
+    rows = e[0] * e[1] * H[2]
+    planes = e[0] * M[1] * H[2]
+    return (8 * E + 16 * rows) + (16 * rows + 16 * planes) + (32 * planes + 8 * H[0] * H[1] * H[2]) \
+        + (16 * planes + 16 * rows) + (16 * rows + 8 * E)
+
+
+def fast_summation(torch, P, ctx, step_fft, steps, z, nrhs, q, ref_u, log_name):
+    """The FFT-convolution path on the same context: solves (every matvec a convolution, FP64),
+    the convolution alone, and its HBM roofline."""
+    step_fft()
+    lat, pairs_total = [], 0
+    pairs_mv = z["n_targets"] * z["n_sources"] * nrhs
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s0 = time.perf_counter()
+        res = step_fft()
+        lat.append(time.perf_counter() - s0)
+        pairs_total += (res[0]["matvecs_fp64"] + res[0]["matvecs_fp32"]) * pairs_mv
+    elapsed = time.perf_counter() - t0
+    u = np.stack([ctx.gamma_values(r) for r in range(nrhs)])
+    err = float(max(np.linalg.norm(u[r] - ref_u[r]) / np.linalg.norm(ref_u[r]) for r in range(nrhs)))
+    t_conv = time_sum_kernel(torch, ctx, q, P.PREC_FFT, 3, burst=3) / nrhs
+    zz = ctx.get_sizes()
+    b = conv_bytes(zz)
+    log(f"{log_name} fft: {np.median(lat) * 1e3:.0f} ms per step, convolution {t_conv * 1e3:.3f} ms per RHS")
+    return {"pair_interactions_per_s": pairs_total / elapsed, "solves_per_s": nrhs * steps / elapsed,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "iterations": max(r["iterations"] for r in res), "max_rel_residual": max(r["rel_residual_true"] for r in res),
+            "max_rel_diff_vs_headline_path": err,
+            "convolution_ms_per_rhs": t_conv * 1e3, "matvec_pair_interactions_per_s": pairs_mv / (t_conv * nrhs),
+            "box": zz["conv_box"], "fft_lengths": zz["conv_fft"],
+            "roofline": {"bound": "hbm", "achieved": b / t_conv / 1e9, "peak": PEAK_HBM, "unit": "GB/s",
+                         "frac": b / t_conv / 1e9 / PEAK_HBM, "bytes_per_convolution": b,
+                         "kernel": "one convolution (HIP events): clear, scatter of the weights, the five FFT passes (conv_z_fwd, conv_lines x3, conv_z_inv), gather; bytes count the FFT passes"}}
+
+
 def time_applies(torch, ctx, q, v, prec, reps):
     stream = torch.cuda.current_stream()
     for _ in range(3):
@@ -333,6 +380,8 @@ def headline(args, torch, P, W):
                      "frac_of_fp64_peak": fl64 / t_sum64 / 1e12 / PEAK_FP64, "pair_classes": st64},
         "setup_s": t_setup,
     }
+    out["fast_summation"] = fast_summation(torch, P, ctx, lambda: step(P.SOLVE_FFT), max(1, min(args.steps, 3)), z,
+                                           nrhs, q, u32, "star")
     ctx.close()
     if not args.no_extra:
         out["poisson_ellipsoid_129"] = ellipsoid(args, torch, P, W, steps=5, warmup=2, extra=True)
@@ -395,6 +444,8 @@ def ellipsoid(args, torch, P, W, steps=None, warmup=None, extra=False):
         mv[name] = {"median_ms": t_med * 1e3, "pairs_per_s": pairs_mv / t_med, "sum_kernel_ms": t_sum * 1e3,
                     "tflops": fl / t_sum / 1e12,
                     "frac": fl / t_sum / 1e12 / (PEAK_FP32 if name == "fp32" else PEAK_FP64), "pair_classes": st}
+    fast = fast_summation(torch, P, ctx, lambda: [step(P.SOLVE_FFT)], max(2, steps), z, 1, q, u32[None],
+                          "ellipsoid")
     meas = measured("lgf_sum_poisson_ellipsoid_129")
     roofline = {"bound": "alu", "achieved": mv["fp32"]["tflops"], "peak": PEAK_FP32, "unit": "TFLOP/s",
                 "frac": mv["fp32"]["frac"], "traffic": meas["bytes"] if meas else None,
@@ -415,7 +466,7 @@ def ellipsoid(args, torch, P, W, steps=None, warmup=None, extra=False):
             "fp64_plain": {"solves_per_s": 1.0 / float(np.mean(lat64)),
                            "p50_ms": float(np.percentile(lat64, 50) * 1e3),
                            "p99_ms": float(np.percentile(lat64, 99) * 1e3), "iterations": r64["iterations"]},
-            "matvec": mv, "roofline": roofline, "setup_s": t_setup}
+            "matvec": mv, "roofline": roofline, "fast_summation": fast, "setup_s": t_setup}
     if extra:
         return body
     out = {"metric": METRIC, "value": body.pop("value"), "unit": body.pop("unit"), "n_gpus": 1, "steps": steps,
@@ -629,6 +680,27 @@ def profile_star(args, torch, P, W):
     return {"workload": "profile_star", "copy_bytes_each_way": a.numel() * 8, "sizes": z}
 
 
+def profile_fft(args, torch, P, W):
+    """FFT-convolution matvecs only (129^3 ellipsoid, then one right-hand side of the 257^3
+    star), then the same 256 MiB device copy (the counter runs' calibration)."""
+    dev = torch.device("cuda:0")
+    for p, name in ((W.poisson_ellipsoid(args.nodes), "ellipsoid"), (W.helmholtz_star(args.star_nodes), "star")):
+        with P.Context.from_problem(p, max_rhs=1, max_krylov=8) as ctx:
+            z = ctx.sizes
+            q = torch.from_numpy(np.random.default_rng(5).standard_normal(z["n_gamma_minus"])).to(dev)
+            v = torch.empty(z["n_targets"], dtype=torch.float64, device=dev)
+            for _ in range(args.steps):
+                ctx.apply_double_layer(q, v, P.PREC_FFT)
+            torch.cuda.synchronize()
+            log(f"profile_fft: {args.steps} convolutions done ({name})")
+    a = torch.empty(1 << 25, dtype=torch.float64, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"workload": "profile_fft", "copy_bytes_each_way": a.numel() * 8}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -637,7 +709,7 @@ def main():
     ap.add_argument("--nodes", type=int, default=129, help="nodes per axis of the ellipsoid (h = 1/(nodes-1))")
     ap.add_argument("--workload", default="helmholtz_star",
                     choices=["helmholtz_star", "poisson_ellipsoid", "laplace_sphere", "batch", "serve", "profile",
-                             "profile_star", "formulations", "particular"])
+                             "profile_star", "profile_fft", "formulations", "particular"])
     ap.add_argument("--star-nodes", type=int, default=257)
     ap.add_argument("--fp64-steps", type=int, default=1, help="plain FP64 solves timed beside the headline")
     ap.add_argument("--no-extra", action="store_true", help="skip the 129^3 ellipsoid beside the headline")
@@ -665,7 +737,7 @@ def main():
 
     fn = {"helmholtz_star": headline, "poisson_ellipsoid": ellipsoid, "laplace_sphere": laplace_sphere,
           "formulations": formulations, "particular": particular, "batch": batch, "serve": serve,
-          "profile": profile, "profile_star": profile_star}[args.workload]
+          "profile": profile, "profile_star": profile_star, "profile_fft": profile_fft}[args.workload]
     print(json.dumps(fn(args, torch, P, W)))
 
 

@@ -116,6 +116,8 @@ typedef struct bae_sizes {
                                /*    sigma > 0 form in FP32); 0: the exact table      */
     double far_field_err_fp32; /* sigma > 0: largest relative error of that form      */
                                /* against the context's table (-1 when not checked)   */
+    int32_t conv_box[3];       /* the FFT convolution (BAE_PREC_FFT): extents of its box  */
+    int32_t conv_fft[3];       /*   and its FFT lengths (zeros until first used)       */
 } bae_sizes;
 
 typedef struct bae_solve_params {

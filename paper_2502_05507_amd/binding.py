@@ -41,10 +41,11 @@ class Sizes(C.Structure):
                 ("n_targets", C.c_int64), ("n_empty_d", C.c_int64), ("max_offset", C.c_int32),
                 ("table_radius", C.c_int32), ("table_entries", C.c_int64), ("device_bytes", C.c_int64),
                 ("lds_radius_fp32", C.c_int32), ("lds_radius_fp64", C.c_int32), ("far_field_fp32", C.c_int32),
-                ("far_field_fp64", C.c_int32), ("far_field_err_fp32", C.c_double)]
+                ("far_field_fp64", C.c_int32), ("far_field_err_fp32", C.c_double), ("conv_box", C.c_int32 * 3),
+                ("conv_fft", C.c_int32 * 3)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: (list(v) if isinstance(v, C.Array) else v) for k, v in ((k, getattr(self, k)) for k, _ in self._fields_)}
 
 
 class SolveParams(C.Structure):

@@ -941,6 +941,10 @@ int bae_get_sizes(const bae_ctx* c, bae_sizes* o) {
                                 &c->r, &c->tmp, &c->up_gamma, &c->u_gamma, &c->vsum, &c->wf, &c->plan.items,
                                 &c->plan.counter})
             bytes += d->bytes;
+        for (int a = 0; a < 3; ++a) {
+            o->conv_box[a] = c->conv ? c->conv->e[a] : 0;
+            o->conv_fft[a] = c->conv ? c->conv->M[a] : 0;
+        }
         if (c->conv) bytes += (size_t)c->conv->bytes;
         o->device_bytes = (int64_t)bytes;
     });

@@ -6,10 +6,11 @@
 // G is even in every coordinate, so its transform is real and even: one octant is stored.
 //
 // Per right-hand side the transform is pruned to where data are: the z transforms run on the
-// e0 x e1 rows that hold weights (two real rows per complex FFT), the y transforms on e0 x M2
-// lines, the x transforms on all M1 x M2 lines fused with the product by the kernel's
-// transform and the inverse x transform, which keeps only the e0 planes of the box; the
-// inverse y and z transforms keep only the box again.  All passes are FP64 in LDS (fft_lds).
+// e0 x e1 rows that hold weights (two real rows per complex FFT) and keep the half spectrum
+// k <= M2/2 of each real row (the rest is its conjugate mirror), the y transforms run on
+// e0 x (M2/2 + 1) lines, the x transforms on all M1 x (M2/2 + 1) lines fused with the product by
+// the kernel's transform and the inverse x transform, which keeps only the e0 planes of the
+// box; the inverse y and z transforms keep only the box again.  All passes are FP64 in LDS.
 #include <cmath>
 
 #include "conv.hpp"
@@ -22,13 +23,13 @@ namespace {
 
 using namespace fftdev;
 
-constexpr int kConvThreads = 256;
+constexpr int kConvThreads = kFftThreads;
 
 __device__ __forceinline__ int64_t idx3(int i, int j, int k, int n1, int n2) { return ((int64_t)i * n1 + j) * n2 + k; }
 
 // Pass 1: forward z transforms of the real rows (i < e0, j < e1) of R [e0][e1][e2], zero-padded
 // to M2, two rows per complex FFT (Z = F(a + i b): F a = (Z_k + conj Z_{-k}) / 2,
-// F b = (Z_k - conj Z_{-k}) / 2i), into C [e0][M1][M2].
+// F b = (Z_k - conj Z_{-k}) / 2i); the half spectrum k < H2 = M2/2 + 1 into C [e0][M1][H2].
 __global__ __launch_bounds__(kConvThreads) void conv_z_fwd(const double* __restrict__ R, int e0, int e1, int e2,
                                                           int M1, double2* __restrict__ C, const FftDev p, int P,
                                                           const int32_t* __restrict__ skip) {
@@ -36,8 +37,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_z_fwd(const double* __restr
     if (skip && *skip) return;
     const int M = p.M, nfft = P / 2;
     double2* A = lds;
-    double2* B = lds + (int64_t)nfft * M;
-    double2* tw = B + (int64_t)nfft * M;
+    double2* tw = A + (int64_t)nfft * M;
     load_roots(p, tw);
     double* Ad = (double*)A;
     const int64_t l0 = (int64_t)blockIdx.x * P, nl = (int64_t)e0 * e1;
@@ -49,9 +49,11 @@ __global__ __launch_bounds__(kConvThreads) void conv_z_fwd(const double* __restr
         if (l < nl) Ad[2 * ((int64_t)(pl >> 1) * M + k) + (pl & 1)] = R[l * e2 + k];
     }
     __syncthreads();
-    const double2* Z = fft_lds(A, B, nfft, p, tw, false);
-    for (int e = threadIdx.x; e < P * M; e += blockDim.x) {
-        const int pl = e / M, k = e - pl * M;
+    fft_lds(A, nfft, p, tw, false);
+    const double2* Z = A;
+    const int H = M / 2 + 1;
+    for (int e = threadIdx.x; e < P * H; e += blockDim.x) {
+        const int pl = e / H, k = e - pl * H;
         const int64_t l = l0 + pl;
         if (l >= nl) continue;
         const double2* z = Z + (int64_t)(pl >> 1) * M;
@@ -59,7 +61,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_z_fwd(const double* __restr
         // b is conjugated: conj(b) = (b.x, -b.y)
         const double2 X = (pl & 1) ? make_double2(0.5 * (a.y + b.y), -0.5 * (a.x - b.x))
                                    : make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
-        C[idx3((int)(l / e1), (int)(l % e1), 0, M1, M) + k] = X;
+        C[idx3((int)(l / e1), (int)(l % e1), 0, M1, H) + k] = X;
     }
 }
 
@@ -71,14 +73,13 @@ __global__ __launch_bounds__(kConvThreads) void conv_z_fwd(const double* __restr
 __global__ __launch_bounds__(kConvThreads) void conv_lines(double2* __restrict__ C, int64_t nlines, int64_t lin,
                                                           int64_t sout, int64_t sline, int nload, int nstore, int mode,
                                                           const FftDev p, int P, const double* __restrict__ ghat,
-                                                          int M1, int M2, int H1, int H2,
+                                                          int M1, int L2, int H1, int H2,
                                                           const int32_t* __restrict__ skip) {
     extern __shared__ double2 lds[];
     if (skip && *skip) return;
     const int M = p.M;
     double2* A = lds;
-    double2* B = lds + (int64_t)P * M;
-    double2* tw = B + (int64_t)P * M;
+    double2* tw = A + (int64_t)P * M;
     load_roots(p, tw);
     const int64_t l0 = (int64_t)blockIdx.x * P;
     const int nl = mode == 2 ? M : nload;
@@ -90,22 +91,24 @@ __global__ __launch_bounds__(kConvThreads) void conv_lines(double2* __restrict__
         A[(int64_t)pl * M + n] = v;
     }
     __syncthreads();
-    double2* Z = fft_lds(A, B, P, p, tw, mode == 2);
-    if (mode == 1) {
-        double2* other = Z == A ? B : A;
+    double2* Z = A;
+    // mode 1 transforms twice (forward, the product, inverse) through one copy of the FFT code
+    for (int pass = 0; pass < (mode == 1 ? 2 : 1); ++pass) {
+        fft_lds(Z, P, p, tw, mode == 2 || pass == 1);
+        if (mode != 1 || pass == 1) break;
         for (int e = threadIdx.x; e < P * M; e += blockDim.x) {
             const int pl = e / M, n = e - pl * M;
             const int64_t l = l0 + pl;
             if (l >= nlines) continue;
-            // line l = j M2 + k of the x pass; the transform is even in every index
-            const int j = (int)(l / M2), k = (int)(l % M2);
-            const int a = min(n, M - n), b = min(j, M1 - j), c = min(k, M2 - k);
+            // line l = j L2 + k of the x pass on half spectra (L2 = M2/2 + 1, k <= M2/2); the
+            // transform is even in every index
+            const int j = (int)(l / L2), k = (int)(l % L2);
+            const int a = min(n, M - n), b = min(j, M1 - j), c = k;
             const double g = ghat[idx3(a, b, c, H1, H2)];
             const double2 z = Z[(int64_t)pl * M + n];
             Z[(int64_t)pl * M + n] = make_double2(g * z.x, g * z.y);
         }
         __syncthreads();
-        Z = fft_lds(Z, other, P, p, tw, true);
     }
     for (int e = threadIdx.x; e < P * nstore; e += blockDim.x) {
         const int n = e / P, pl = e - n * P;
@@ -114,8 +117,9 @@ __global__ __launch_bounds__(kConvThreads) void conv_lines(double2* __restrict__
     }
 }
 
-// Last pass: inverse z transforms of the rows (i < e0, j < e1) of C, two rows per complex FFT
-// (the results are real: F^-1(X_a + i X_b) = a + i b), n < e2 kept, times scale, into R.
+// Last pass: inverse z transforms of the rows (i < e0, j < e1) of C (half spectra, the rest the
+// conjugate mirror X_k = conj X_{M-k}), two rows per complex FFT (the results are real:
+// F^-1(X_a + i X_b) = a + i b), n < e2 kept, times scale, into R.
 __global__ __launch_bounds__(kConvThreads) void conv_z_inv(const double2* __restrict__ C, int e0, int e1, int e2,
                                                           int M1, double* __restrict__ R, const FftDev p, int P,
                                                           double scale, const int32_t* __restrict__ skip) {
@@ -123,20 +127,27 @@ __global__ __launch_bounds__(kConvThreads) void conv_z_inv(const double2* __rest
     if (skip && *skip) return;
     const int M = p.M, nfft = P / 2;
     double2* A = lds;
-    double2* B = lds + (int64_t)nfft * M;
-    double2* tw = B + (int64_t)nfft * M;
+    double2* tw = A + (int64_t)nfft * M;
     load_roots(p, tw);
     const int64_t l0 = (int64_t)blockIdx.x * P, nl = (int64_t)e0 * e1;
+    const int H = M / 2 + 1;
     for (int e = threadIdx.x; e < nfft * M; e += blockDim.x) {
         const int c = e / M, k = e - c * M;
+        const bool mirror = k >= H;
+        const int kk = mirror ? M - k : k;
         const int64_t la = l0 + 2 * c, lb = la + 1;
         double2 xa = make_double2(0.0, 0.0), xb = make_double2(0.0, 0.0);
-        if (la < nl) xa = C[idx3((int)(la / e1), (int)(la % e1), 0, M1, M) + k];
-        if (lb < nl) xb = C[idx3((int)(lb / e1), (int)(lb % e1), 0, M1, M) + k];
+        if (la < nl) xa = C[idx3((int)(la / e1), (int)(la % e1), 0, M1, H) + kk];
+        if (lb < nl) xb = C[idx3((int)(lb / e1), (int)(lb % e1), 0, M1, H) + kk];
+        if (mirror) {
+            xa.y = -xa.y;
+            xb.y = -xb.y;
+        }
         A[e] = make_double2(xa.x - xb.y, xa.y + xb.x);
     }
     __syncthreads();
-    const double2* Z = fft_lds(A, B, nfft, p, tw, true);
+    fft_lds(A, nfft, p, tw, true);
+    const double2* Z = A;
     for (int e = threadIdx.x; e < P * e2; e += blockDim.x) {
         const int pl = e / e2, k = e - pl * e2;
         const int64_t l = l0 + pl;
@@ -197,20 +208,16 @@ __global__ void conv_fill(double* __restrict__ x, int64_t n, const int32_t* __re
     if (i < n) x[i] = 0.0;
 }
 
-// lines per block of a pass: two LDS buffers of P lines of length M within 64 KB (at least
-// one line; an even number for the packed real passes)
-int lines_for(int M, bool even) {
-    int P = (int)(65536 / (32 * (int64_t)M));
-    P = std::max(1, std::min(16, P));
-    if (even) P = std::max(2, P & ~1);
-    return P;
+// Lines per block of a pass (fft_lines_per_block); packed real rows go two to a complex line.
+int lines_for(int M, bool packed) {
+    return packed ? 2 * fft_lines_per_block(M, 16) : fft_lines_per_block(M, 32);
 }
 
 void set_lds_attr() {
     static bool done = false;
     if (done) return;
     for (const void* f : {(const void*)conv_z_fwd, (const void*)conv_lines, (const void*)conv_z_inv})
-        BAE_HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        BAE_HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFftLdsBytes));
     done = true;
 }
 
@@ -220,21 +227,22 @@ void run_lines(const ConvPlan& cp, double2* C, int axis, int nload, int nstore, 
     const int M1 = cp.M[1], M2 = cp.M[2];
     const FftDev& p = axis == 1 ? cp.fy : cp.fx;
     int64_t nlines, lin, sout, sline;
+    const int H2 = cp.H[2];   // the half spectrum along z
     if (axis == 1) {
-        nlines = (int64_t)cp.e[0] * M2;
-        lin = M2;
-        sout = (int64_t)M1 * M2;
-        sline = M2;
+        nlines = (int64_t)cp.e[0] * H2;
+        lin = H2;
+        sout = (int64_t)M1 * H2;
+        sline = H2;
     } else {
-        nlines = (int64_t)M1 * M2;
+        nlines = (int64_t)M1 * H2;
         lin = nlines;
         sout = 0;
-        sline = (int64_t)M1 * M2;
+        sline = (int64_t)M1 * H2;
     }
     const int P = lines_for(p.M, false);
-    const size_t lds = sizeof(double2) * (2 * (size_t)P + 1) * p.M;
+    const size_t lds = sizeof(double2) * ((size_t)P + 1) * p.M;
     conv_lines<<<(unsigned)((nlines + P - 1) / P), kConvThreads, lds, st>>>(
-        C, nlines, lin, sout, sline, nload, nstore, mode, p, P, cp.ghat, M1, M2, cp.H[1], cp.H[2], skip);
+        C, nlines, lin, sout, sline, nload, nstore, mode, p, P, cp.ghat, M1, H2, cp.H[1], cp.H[2], skip);
     BAE_HIP_CHECK(hipGetLastError());
 }
 
@@ -243,7 +251,7 @@ void run_lines(const ConvPlan& cp, double2* C, int axis, int nload, int nstore, 
 int fft_smooth_length(int n) {
     for (int m = std::max(1, n);; ++m) {
         int r = m;
-        for (int q : {2, 3, 5, 7})
+        for (int q : {2, 3, 5})
             while (r % q == 0) r /= q;
         if (r == 1) return m;
     }
@@ -268,7 +276,7 @@ void ConvPlan::build(const int lo_[3], const int hi_[3], const SumTables& tabs, 
     fy = fft_plan(M[1], st);
     fz = fft_plan(M[2], st);
     const int64_t full = (int64_t)M[0] * M[1] * M[2], oct = (int64_t)H[0] * H[1] * H[2];
-    const int64_t box = (int64_t)e[0] * e[1] * e[2], cbytes = (int64_t)e[0] * M[1] * M[2];
+    const int64_t box = (int64_t)e[0] * e[1] * e[2], cbytes = (int64_t)e[0] * M[1] * H[2];
     auto dmalloc = [](void** p, size_t n) {
         if (hipMalloc(p, n) != hipSuccess) throw Error{BAE_ERR_OOM, "LGF convolution: device allocation failed"};
     };
@@ -286,19 +294,19 @@ void ConvPlan::build(const int lo_[3], const int hi_[3], const SumTables& tabs, 
     {   // z: rows of the full grid (complex, contiguous)
         const int P = lines_for(M[2], false);
         const int64_t nl = (int64_t)M[0] * M[1];
-        conv_lines<<<(unsigned)((nl + P - 1) / P), kConvThreads, sizeof(double2) * (2 * (size_t)P + 1) * M[2], st>>>(
+        conv_lines<<<(unsigned)((nl + P - 1) / P), kConvThreads, sizeof(double2) * ((size_t)P + 1) * M[2], st>>>(
             g, nl, 1, M[2], 1, M[2], M[2], 0, fz, P, nullptr, M[1], M[2], H[1], H[2], nullptr);
         BAE_HIP_CHECK(hipGetLastError());
     }
     {   // y over every plane, x over every line
         const int P = lines_for(M[1], false);
         const int64_t nl = (int64_t)M[0] * M[2];
-        conv_lines<<<(unsigned)((nl + P - 1) / P), kConvThreads, sizeof(double2) * (2 * (size_t)P + 1) * M[1], st>>>(
+        conv_lines<<<(unsigned)((nl + P - 1) / P), kConvThreads, sizeof(double2) * ((size_t)P + 1) * M[1], st>>>(
             g, nl, M[2], (int64_t)M[1] * M[2], M[2], M[1], M[1], 0, fy, P, nullptr, M[1], M[2], H[1], H[2], nullptr);
         BAE_HIP_CHECK(hipGetLastError());
         const int Px = lines_for(M[0], false);
         const int64_t nlx = (int64_t)M[1] * M[2];
-        conv_lines<<<(unsigned)((nlx + Px - 1) / Px), kConvThreads, sizeof(double2) * (2 * (size_t)Px + 1) * M[0], st>>>(
+        conv_lines<<<(unsigned)((nlx + Px - 1) / Px), kConvThreads, sizeof(double2) * ((size_t)Px + 1) * M[0], st>>>(
             g, nlx, nlx, 0, nlx, M[0], M[0], 0, fx, Px, nullptr, M[1], M[2], H[1], H[2], nullptr);
         BAE_HIP_CHECK(hipGetLastError());
     }
@@ -316,7 +324,7 @@ void ConvPlan::apply(const double* w, const int32_t* sidx, int64_t ns, const int
     BAE_HIP_CHECK(hipGetLastError());
     const int Pz = lines_for(M[2], true);
     const int64_t nrow = (int64_t)e[0] * e[1];
-    const size_t ldsz = sizeof(double2) * (size_t)(Pz + 1) * M[2];   // two buffers of Pz / 2 lines, the roots
+    const size_t ldsz = sizeof(double2) * (size_t)(Pz / 2 + 1) * M[2];   // Pz / 2 complex lines, the roots
     conv_z_fwd<<<(unsigned)((nrow + Pz - 1) / Pz), kConvThreads, ldsz, st>>>(R, e[0], e[1], e[2], M[1], C, fz, Pz,
                                                                            skip);
     BAE_HIP_CHECK(hipGetLastError());

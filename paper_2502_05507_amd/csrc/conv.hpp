@@ -32,7 +32,7 @@ struct ConvPlan {
     }
 };
 
-// Smallest length >= n whose prime factors are 2, 3, 5 and 7.
+// Smallest length >= n whose prime factors are 2, 3 and 5 (the LDS FFT's register radices).
 int fft_smooth_length(int n);
 
 }  // namespace bae

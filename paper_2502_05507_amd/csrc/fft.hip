@@ -43,15 +43,15 @@ __device__ __forceinline__ int64_t line_at(int axis, int64_t l, int64_t n, int n
 
 // DST-I of every line along `axis` (length N = its extent), in place, times `scale`.  A block
 // takes P lines (P even: line pairs share a complex FFT of length p.M = 2(N + 1)).
-__global__ void dst_axis_kernel(double* __restrict__ x, int axis, int n0, int n1, int n2, int64_t nlines, int P,
-                                const FftDev p, double scale) {
+__global__ __launch_bounds__(kFftThreads) void dst_axis_kernel(double* __restrict__ x, int axis, int n0, int n1,
+                                                                int n2, int64_t nlines, int P, const FftDev p,
+                                                                double scale) {
     extern __shared__ double2 lds[];
     const int N = axis == 0 ? n0 : axis == 1 ? n1 : n2;
     const int M = p.M;
     const int nfft = P / 2;
     double2* A = lds;
-    double2* B = lds + (int64_t)nfft * M;
-    double2* tw = B + (int64_t)nfft * M;
+    double2* tw = A + (int64_t)nfft * M;
     load_roots(p, tw);
     const int64_t l0 = (int64_t)blockIdx.x * P;
     double* Ad = (double*)A;
@@ -76,7 +76,8 @@ __global__ void dst_axis_kernel(double* __restrict__ x, int axis, int n0, int n1
         Ad[2 * (c * M + M - n - 1) + comp] = -v;
     }
     __syncthreads();
-    const double2* Z = fft_lds(A, B, nfft, p, tw, false);
+    fft_lds(A, nfft, p, tw, false);
+    const double2* Z = A;
     const double h = 0.5 * scale;
     for (int e = threadIdx.x; e < P * N; e += blockDim.x) {
         int pl, n;
@@ -188,10 +189,7 @@ FftDev fft_plan(int M, hipStream_t st) {
 }
 
 static int lines_per_block(int M) {
-    // LDS: two buffers of P/2 complex lines of length M; at most 64 KB, P even, <= 32
-    int P = 2 * (int)(65536 / (32 * (int64_t)M));
-    P = std::max(2, std::min(32, P));
-    return P;
+    return 2 * fft_lines_per_block(M, 16);   // two real lines per complex FFT, at most 32
 }
 
 void dst_axis(double* x, int n0, int n1, int n2, int axis, double scale, hipStream_t st) {
@@ -200,15 +198,15 @@ void dst_axis(double* x, int n0, int n1, int n2, int axis, double scale, hipStre
     const FftDev p = fft_plan(2 * (N + 1), st);
     const int P = lines_per_block(p.M);
     const int64_t nlines = (int64_t)n0 * n1 * n2 / N;
-    const size_t lds = sizeof(double2) * (size_t)(P + 1) * p.M;   // two buffers of P / 2 lines, the roots
+    const size_t lds = sizeof(double2) * (size_t)(P / 2 + 1) * p.M;   // P / 2 complex lines, the roots
     static bool attr = false;
     if (!attr) {
         BAE_HIP_CHECK(hipFuncSetAttribute((const void*)dst_axis_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                          160 * 1024));
+                                          (int)kFftLdsBytes));
         attr = true;
     }
     const unsigned blocks = (unsigned)((nlines + P - 1) / P);
-    dst_axis_kernel<<<blocks, 256, lds, st>>>(x, axis, n0, n1, n2, nlines, P, p, scale);
+    dst_axis_kernel<<<blocks, fftdev::kFftThreads, lds, st>>>(x, axis, n0, n1, n2, nlines, P, p, scale);
     BAE_HIP_CHECK(hipGetLastError());
 }
 

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "internal.hpp"
@@ -11,6 +12,16 @@ namespace bae {
 
 constexpr int kFftMaxLen = 4608;     // longest transform: two LDS buffers of it fit the 160 KB
 constexpr int kFftMaxFactors = 16;
+constexpr size_t kFftLdsBytes = 160 * 1024;
+
+// Complex lines of length M that one block transforms at once: c M <= 8192 points (the
+// in-place stages' register staging), and the c lines plus the root table (M more points,
+// 16 B each) within the LDS; at most `cap`, at least 1 (M <= kFftMaxLen).
+inline int fft_lines_per_block(int M, int cap) {
+    const int by_points = 8192 / M;
+    const int by_lds = (int)(kFftLdsBytes / (16 * (size_t)M)) - 1;
+    return std::max(1, std::min(cap, std::min(by_points, by_lds)));
+}
 
 // A transform length with its radices and root table e^(-2 pi i t / M), t < M (device).
 struct FftDev {

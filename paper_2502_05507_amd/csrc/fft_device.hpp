@@ -2,7 +2,8 @@
 //
 // Stockham autosort stages in LDS: stage s with radix R and stride Ns maps input j + r M/R
 // (r < R), twiddled by w^(r (j mod Ns) M/(Ns R)), to output (j div Ns) Ns R + (j mod Ns) + k Ns
-// after an R-point DFT (w = e^(-2 pi i / M)).  Radices 2, 3, 4 and 5 have their butterflies
+// after an R-point DFT (w = e^(-2 pi i / M)); all inputs of a stage are read into registers
+// before any output is written, so one LDS buffer serves.  Radices 2, 3, 4 and 5 have their butterflies
 // written out, in registers; any other prime evaluates each output as an R-term sum straight
 // from LDS.  The root table is staged in LDS by the caller.  Index divisions by stage
 // constants go through a float reciprocal with one correction step (exact for the sizes here).
@@ -75,50 +76,78 @@ __device__ __forceinline__ void butterfly(double2 (&v)[R], bool inv) {
     }
 }
 
+// In-place stages: a block of kFftThreads threads holds `count` lines of length M (count M <=
+// kFftPoints) in one LDS buffer; every thread reads its butterflies' inputs into registers,
+// the block synchronises, and the outputs overwrite the buffer.
+constexpr int kFftThreads = 1024;
+constexpr int kFftPoints = 8192;                         // count * M per block at most
+
 template <int R>
-__device__ __forceinline__ void stage(const double2* __restrict__ src, double2* __restrict__ dst, int count, int M,
-                                      int Ns, const double2* __restrict__ tw, bool inv) {
+__device__ __forceinline__ void stage(double2* __restrict__ buf, int count, int M, int Ns,
+                                      const double2* __restrict__ tw, bool inv) {
     const int m = M / R, tstep = M / (Ns * R), total = count * m;
     const float rm = 1.0f / (float)m, rns = 1.0f / (float)Ns;
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    constexpr int I = (kFftPoints / R + kFftThreads - 1) / kFftThreads;
+    double2 v[I][R];
+    int o[I];
+#pragma unroll
+    for (int it = 0; it < I; ++it) {
+        const int e = threadIdx.x + it * kFftThreads;
+        o[it] = -1;
+        if (e >= total) continue;
         const int c = fdiv(e, m, rm), j = e - c * m;
         const int jq = fdiv(j, Ns, rns), jm = j - jq * Ns;
-        const double2* in = src + c * M;
-        double2* out = dst + c * M;
-        double2 v[R];
+        const double2* in = buf + c * M;
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = in[j + r * m];
+        for (int r = 0; r < R; ++r) v[it][r] = in[j + r * m];
         if (jm > 0) {
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[r] = cmul(v[r], root(tw, r * jm * tstep, inv));
+            for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], root(tw, r * jm * tstep, inv));
         }
-        butterfly<R>(v, inv);
-        const int o = jq * Ns * R + jm;
+        butterfly<R>(v[it], inv);
+        o[it] = c * M + jq * Ns * R + jm;
+    }
+    __syncthreads();
 #pragma unroll
-        for (int k = 0; k < R; ++k) out[o + k * Ns] = v[k];
+    for (int it = 0; it < I; ++it) {
+        if (o[it] < 0) continue;
+#pragma unroll
+        for (int k = 0; k < R; ++k) buf[o[it] + k * Ns] = v[it][k];
     }
 }
 
 // any radix R: every output an R-term sum, X = sum_r in[j + r m] w^(r base)
-__device__ __forceinline__ void stage_any(const double2* __restrict__ src, double2* __restrict__ dst, int count, int M,
-                                          int Ns, int R, const double2* __restrict__ tw, bool inv) {
+__device__ __forceinline__ void stage_any(double2* __restrict__ buf, int count, int M, int Ns, int R,
+                                          const double2* __restrict__ tw, bool inv) {
     const int m = M / R, tstep = M / (Ns * R), total = count * M;
     const float rM = 1.0f / (float)M, rm = 1.0f / (float)m, rns = 1.0f / (float)Ns;
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    constexpr int I = kFftPoints / kFftThreads;
+    double2 acc[I];
+    int o[I];
+#pragma unroll
+    for (int it = 0; it < I; ++it) {
+        const int e = threadIdx.x + it * kFftThreads;
+        o[it] = -1;
+        if (e >= total) continue;
         const int c = fdiv(e, M, rM), q = e - c * M;
         const int k = fdiv(q, m, rm), j = q - k * m;
         const int jq = fdiv(j, Ns, rns), jm = j - jq * Ns;
-        const double2* in = src + c * M;
+        const double2* in = buf + c * M;
         const int base = jm * tstep + k * m;   // < M
-        double2 acc = in[j];
+        double2 a = in[j];
         int t = 0;
         for (int r = 1; r < R; ++r) {
             t += base;
             if (t >= M) t -= M;
-            acc = cadd(acc, cmul(in[j + r * m], root(tw, t, inv)));
+            a = cadd(a, cmul(in[j + r * m], root(tw, t, inv)));
         }
-        dst[c * M + jq * Ns * R + jm + k * Ns] = acc;
+        acc[it] = a;
+        o[it] = c * M + jq * Ns * R + jm + k * Ns;
     }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < I; ++it)
+        if (o[it] >= 0) buf[o[it]] = acc[it];
 }
 
 // Copies the root table (M entries) into LDS; the caller synchronises before fft_lds.
@@ -126,29 +155,24 @@ __device__ __forceinline__ void load_roots(const FftDev& p, double2* tw) {
     for (int t = threadIdx.x; t < p.M; t += blockDim.x) tw[t] = p.tw[t];
 }
 
-// `count` FFTs of length p.M stored one after another at src (LDS); ping-pong with dst; tw: the
-// root table in LDS.  Returns the buffer that holds the result.  Every thread of the block
-// must call it.
-__device__ __forceinline__ double2* fft_lds(double2* src, double2* dst, int count, const FftDev& p,
-                                            const double2* tw, bool inv) {
+// `count` FFTs of length p.M (count p.M <= kFftPoints) stored one after another in buf (LDS),
+// in place, by a block of kFftThreads threads; tw: the root table in LDS.  Every thread of
+// the block must call it; the result is in buf when it returns.
+__device__ __forceinline__ void fft_lds(double2* buf, int count, const FftDev& p, const double2* tw, bool inv) {
     const int M = p.M;
     int Ns = 1;
     for (int s = 0; s < p.nf; ++s) {
         const int R = p.f[s];
         switch (R) {
-            case 2: stage<2>(src, dst, count, M, Ns, tw, inv); break;
-            case 3: stage<3>(src, dst, count, M, Ns, tw, inv); break;
-            case 4: stage<4>(src, dst, count, M, Ns, tw, inv); break;
-            case 5: stage<5>(src, dst, count, M, Ns, tw, inv); break;
-            default: stage_any(src, dst, count, M, Ns, R, tw, inv); break;
+            case 2: stage<2>(buf, count, M, Ns, tw, inv); break;
+            case 3: stage<3>(buf, count, M, Ns, tw, inv); break;
+            case 4: stage<4>(buf, count, M, Ns, tw, inv); break;
+            case 5: stage<5>(buf, count, M, Ns, tw, inv); break;
+            default: stage_any(buf, count, M, Ns, R, tw, inv); break;
         }
         __syncthreads();
-        double2* x = src;
-        src = dst;
-        dst = x;
         Ns *= R;
     }
-    return src;
 }
 
 }  // namespace fftdev

@@ -403,12 +403,14 @@ def test_largest_lattice_offsets_two_balls():
         assert ctx.sum_stats(P.PREC_FP32)["far_q2"] > 0      # the binary16 far field runs
         qd = torch.from_numpy(q).to(device())
         v = torch.empty((2, len(T)), dtype=torch.float64, device=device())
-        for prec, tol in ((P.PREC_FP64, 1e-10), (P.PREC_FP32, 2e-5)):
+        # the FFT convolution runs on a box 2043 nodes long: transform length 4096 along x
+        for prec, tol in ((P.PREC_FP64, 1e-10), (P.PREC_FP32, 2e-5), (P.PREC_FFT, 1e-10)):
             ctx.apply_double_layer(qd, v, prec)
             torch.cuda.synchronize()
             out = v.cpu().numpy()
             for rr in range(2):
                 assert rel_l2(out[rr], ref[rr]) < tol, (prec, rr, rel_l2(out[rr], ref[rr]))
+        assert ctx.get_sizes()["conv_fft"][0] >= 2 * ctx.get_sizes()["conv_box"][0] - 1 > 4000
         # the box particular solution on this long, thin box (a 2047-point sine transform,
         # FFT length 4096); without it there is no u_p to read
         from oracle import box

@@ -261,6 +261,11 @@ int bae_get_density(const bae_ctx* ctx, int32_t r, double* q);
 int bae_get_gamma_values(const bae_ctx* ctx, int32_t r, double* u_gamma);
 int bae_get_solution(const bae_ctx* ctx, int32_t r, double* u_grid);
 int bae_get_history(const bae_ctx* ctx, int32_t r, double* hist, int32_t cap, int32_t* len);
+/* Length per RHS of the last solve's density: |gamma-| for the layer potentials (solo,
+   batched or served), |gamma| for the direct formulation (Sec. 3.1).  Size the buffers of
+   bae_get_density / bae_get_density_device from it.  Errors: BAE_ERR_ARG, BAE_ERR_STATE (no
+   solve yet). */
+int bae_get_density_length(const bae_ctx* ctx, int64_t* len);
 /*
  * Asynchronous solve (Algorithm 1's solve step, as bae_solve): its device work is ordered
  * after everything queued on `stream` so far (a PyTorch caller passes its current stream;

@@ -130,6 +130,7 @@ def load_library():
         "bae_get_particular": (C.c_int, [_P, C.c_int32, _P]),
         "bae_solve": (C.c_int, [_P, C.POINTER(SolveParams), _P]),
         "bae_get_density": (C.c_int, [_P, C.c_int32, _P]),
+        "bae_get_density_length": (C.c_int, [_P, C.POINTER(C.c_int64)]),
         "bae_get_gamma_values": (C.c_int, [_P, C.c_int32, _P]),
         "bae_get_solution": (C.c_int, [_P, C.c_int32, _P]),
         "bae_get_history": (C.c_int, [_P, C.c_int32, _P, C.c_int32, C.POINTER(C.c_int32)]),
@@ -312,7 +313,6 @@ class Context:
         initial densities [nrhs][|gamma-|]."""
         p = self._params(precision, tol, maxit, inner_tol, max_outer, compute_grid, recycle_dim, formulation, x0)
         res = (Result * self.nrhs)()
-        self._formulation = int(formulation)
         rc = load_library().bae_solve(self._h, C.byref(p), res)
         _check(rc, allow_not_converged=True)
         return [r.as_dict() for r in res]
@@ -322,7 +322,6 @@ class Context:
         """bae_solve_async: ordered after `stream` (default: torch's current stream), returns at once."""
         p = self._params(precision, tol, maxit, inner_tol, max_outer, compute_grid, recycle_dim, formulation, x0)
         self._x0 = x0      # kept alive until the solve is collected
-        self._formulation = int(formulation)
         _check(load_library().bae_solve_async(self._h, C.byref(p), _stream(stream)))
 
     def solve_poll(self):
@@ -352,9 +351,11 @@ class Context:
         self._device_out(load_library().bae_get_solution_device, out, r, int(np.prod(self.n)), stream)
 
     def density_length(self):
-        """|gamma-| (layer potentials), or |gamma| after a direct-formulation solve."""
-        direct = getattr(self, "_formulation", 0) == LAYER_DIRECT
-        return self.sizes["n_targets"] if direct else self.sizes["n_gamma_minus"]
+        """Length of the last solve's density: |gamma-| (layer potentials), or |gamma| after a
+        direct-formulation solve."""
+        n = C.c_int64()
+        _check(load_library().bae_get_density_length(self._h, C.byref(n)))
+        return int(n.value)
 
     def density(self, r=0):
         q = np.empty(self.density_length())

@@ -1503,6 +1503,14 @@ int bae_get_density(const bae_ctx* cc, int32_t r, double* q) {
     });
 }
 
+int bae_get_density_length(const bae_ctx* cc, int64_t* len) {
+    return guard([&] {
+        bae_ctx* c = solved_ctx(cc);
+        if (!len) throw Error{BAE_ERR_ARG, "null argument"};
+        *len = c->dens_n;
+    });
+}
+
 int bae_get_gamma_values(const bae_ctx* cc, int32_t r, double* u) {
     return guard([&] {
         bae_ctx* c = solved_ctx(cc);

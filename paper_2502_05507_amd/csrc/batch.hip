@@ -852,6 +852,7 @@ int solve_all(BatchEngine* b, const bae_solve_params* prm, bool use_graph, bae_r
         if (!conv) status = BAE_NOT_CONVERGED;
         c->solved = true;
         c->has_grid = false;
+        c->dens_n = c->ngm;
         if (res) {
             res[p].status = conv ? BAE_OK : BAE_NOT_CONVERGED;
             res[p].iterations = iters[p];

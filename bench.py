@@ -25,6 +25,8 @@ Other workloads (--workload; their own JSON line, not the contract's):
   serve              Poisson arrivals into the continuous-batching server, p50/p99 latency
   profile            129^3 matvecs only (for rocprofv3) plus a device copy of known size
   profile_star       257^3 16-RHS FP32 sums only (for rocprofv3) plus the same copy
+  profile_fft        FFT-convolution matvecs only (129^3 ellipsoid, 257^3 star) plus the same copy
+  profile_box        the box particular solution alone at --nodes per axis plus the same copy
   formulations       single- against double-layer formulation (iterations, time) at 129^3
   particular         free-space against finite-grid (sine-transform) particular solution at 129^3
 """
@@ -246,7 +248,7 @@ def cpu_baseline_worker(workload, nrows, nrhs_all):
     Q = rng.standard_normal((nrhs_all, len(geo.gamma_minus)))
     n_src = len(geo.gamma_minus) + len(geo.ext)
     _ORACLE.update(geo=geo, G=G, Q=Q)
-    blocks = [rows[i:i + 64] for i in range(0, len(rows), 64)]
+    blocks = [rows[i:i + 32] for i in range(0, len(rows), 32)]
     t0 = time.perf_counter()
     for b in blocks:
         _oracle_rows((b, 0))
@@ -701,6 +703,28 @@ def profile_fft(args, torch, P, W):
     return {"workload": "profile_fft", "copy_bytes_each_way": a.numel() * 8}
 
 
+def profile_box(args, torch, P, W):
+    """Algorithm 1's box particular solution alone (set_rhs_device with f on the device, the
+    sine transforms by the LDS FFT) on the Poisson ellipsoid at --nodes per axis, then the same
+    256 MiB device copy."""
+    dev = torch.device("cuda:0")
+    p = W.poisson_ellipsoid(args.nodes)
+    with P.Context.from_problem(p, max_rhs=1, max_krylov=8) as ctx:
+        xs, _, _ = ctx.boundary_points()
+        g = torch.from_numpy(p.g(xs)).to(dev)
+        f = torch.from_numpy(p.f_grid()).to(dev)
+        for _ in range(args.steps):
+            ctx.set_rhs_device(g, f, particular="box")
+        torch.cuda.synchronize()
+        log(f"profile_box: {args.steps} box solves done ({args.nodes}^3)")
+    a = torch.empty(1 << 25, dtype=torch.float64, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"workload": f"profile_box_{args.nodes}^3", "copy_bytes_each_way": a.numel() * 8}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -709,12 +733,12 @@ def main():
     ap.add_argument("--nodes", type=int, default=129, help="nodes per axis of the ellipsoid (h = 1/(nodes-1))")
     ap.add_argument("--workload", default="helmholtz_star",
                     choices=["helmholtz_star", "poisson_ellipsoid", "laplace_sphere", "batch", "serve", "profile",
-                             "profile_star", "profile_fft", "formulations", "particular"])
+                             "profile_star", "profile_fft", "profile_box", "formulations", "particular"])
     ap.add_argument("--star-nodes", type=int, default=257)
     ap.add_argument("--fp64-steps", type=int, default=1, help="plain FP64 solves timed beside the headline")
     ap.add_argument("--no-extra", action="store_true", help="skip the 129^3 ellipsoid beside the headline")
-    ap.add_argument("--cpu-rows", type=int, default=256, help="target rows of the CPU oracle sample")
-    ap.add_argument("--cpu-rhs", type=int, default=0, help="densities of the all-core sample (0: one per core)")
+    ap.add_argument("--cpu-rows", type=int, default=2000, help="target rows of the CPU oracle sample")
+    ap.add_argument("--cpu-rhs", type=int, default=1, help="densities of the all-core sample (0: one per core)")
     ap.add_argument("--cpu-baseline-worker", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--requests", type=int, default=500)
@@ -737,7 +761,8 @@ def main():
 
     fn = {"helmholtz_star": headline, "poisson_ellipsoid": ellipsoid, "laplace_sphere": laplace_sphere,
           "formulations": formulations, "particular": particular, "batch": batch, "serve": serve,
-          "profile": profile, "profile_star": profile_star, "profile_fft": profile_fft}[args.workload]
+          "profile": profile, "profile_star": profile_star, "profile_fft": profile_fft,
+          "profile_box": profile_box}[args.workload]
     print(json.dumps(fn(args, torch, P, W)))
 
 

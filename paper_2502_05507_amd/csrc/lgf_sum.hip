@@ -293,6 +293,72 @@ __device__ __forceinline__ void mfma_far2_block(const SumArgs<float>& a, const u
     }
 }
 
+// Table-value blocks of the FP64 kernel: table blocks read the LDS table (GLOBAL = false);
+// gather blocks and mixed blocks without a far field (sigma > 0: the global table holds every
+// offset, the LDS prefix included) read the global table, which the L2 and the MALL hold.
+// Loaded per step, a step would wait on its sources' coordinates and then on the table reads
+// they address, with two wavefronts per SIMD to cover that latency (the LDS table allows one
+// workgroup per compute unit).  Here the block's 64 sources are loaded once, one per lane,
+// and each step takes its four by a lane permutation (an LDS-crossbar operation, outside the
+// vector-memory counter); the weights and table reads of the next DEPTH steps are in flight
+// while the current step is contracted.
+template <typename Real, bool GLOBAL>
+__device__ __forceinline__ void mfma_lookup_block(const SumArgs<Real>& a, const Lds<Real>& L,
+                                                  const uint32_t (&ix)[kTiles], const uint32_t (&iy)[kTiles],
+                                                  const uint32_t (&iz)[kTiles], int sb, int row, int kq,
+                                                  typename MfmaAcc<Real>::V (&blk)[kTiles]) {
+    constexpr int DEPTH = GLOBAL ? 2 : 1;
+    constexpr int kSteps = kSourceBlock / 4;
+    const int lane = threadIdx.x & 63;
+    const int bx = (int)a.sx[sb + lane], by = (int)a.sy[sb + lane], bz = (int)a.sz[sb + lane];
+    const Real* pw = a.w + ((int64_t)row * a.ldw + sb + kq);
+    // the step's weight and its four kernel values (source 4 st + kq of the block)
+    auto issue = [&](int st, Real& wv, Real (&g)[kTiles]) {
+        const int from = (4 * st + kq) << 2;
+        const uint32_t sx = (uint32_t)__builtin_amdgcn_ds_bpermute(from, bx);
+        const uint32_t sy = (uint32_t)__builtin_amdgcn_ds_bpermute(from, by);
+        const uint32_t sz = (uint32_t)__builtin_amdgcn_ds_bpermute(from, bz);
+        // in phases (sorted triples, every index-array read, the sums), so that the eight LDS
+        // reads are in flight together
+        uint32_t lo[kTiles], mid[kTiles], hi[kTiles];
+#pragma unroll
+        for (int j = 0; j < kTiles; ++j) {
+            const uint32_t da = absdiff_v(ix[j], sx), db = absdiff_v(iy[j], sy), dc = absdiff_v(iz[j], sz);
+            lo[j] = min3u(da, db, dc);
+            mid[j] = med3u(da, db, dc);
+            hi[j] = max3u(da, db, dc);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        uint32_t th[kTiles], tm[kTiles];
+#pragma unroll
+        for (int j = 0; j < kTiles; ++j) {
+            th[j] = *(const uint32_t*)((const char*)L.tet + hi[j]);
+            tm[j] = *(const uint32_t*)((const char*)L.tri + mid[j]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        wv = pw[4 * st];
+#pragma unroll
+        for (int j = 0; j < kTiles; ++j) {
+            const uint32_t o = th[j] + tm[j] + (uint32_t)(sizeof(Real) / 4) * lo[j];
+            g[j] = GLOBAL ? global_value(a.full_tab, o) : lds_value(L, o);
+        }
+    };
+    Real wq[DEPTH + 1];
+    Real G[DEPTH + 1][kTiles];
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) issue(d, wq[d], G[d]);
+#pragma unroll
+    for (int st = 0; st < kSteps; ++st) {
+        if (st + DEPTH < kSteps) issue(st + DEPTH, wq[(st + DEPTH) % (DEPTH + 1)], G[(st + DEPTH) % (DEPTH + 1)]);
+        // the later steps' reads are issued before this step's contraction waits on its own
+        __builtin_amdgcn_sched_barrier(0);
+        const int c = st % (DEPTH + 1);
+#pragma unroll
+        for (int j = 0; j < kTiles; ++j) blk[j] = MfmaAcc<Real>::mma(G[c][j], wq[c], blk[j]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 template <typename Real>
 __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real>& L, int tile, int chunk) {
     using V = typename MfmaAcc<Real>::V;
@@ -301,7 +367,6 @@ __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real
     const int kq = lane >> 4;             // A column / B row (source within the step of 4)
     const int base = tile * kWave;
     uint32_t ix[kTiles], iy[kTiles], iz[kTiles], txy[kTiles];
-    Real fx[kTiles], fy[kTiles], fz[kTiles];
     float tzl[kTiles];
     int lx = 1 << 30, ly = 1 << 30, lz = 1 << 30, hx = 0, hy = 0, hz = 0;
 #pragma unroll
@@ -312,9 +377,6 @@ __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real
         iz[j] = a.tz[tc];
         txy[j] = sizeof(Real) == 4 ? a.txy[tc] : 0u;
         tzl[j] = sizeof(Real) == 4 ? a.tzl[tc] : 0.f;
-        fx[j] = (Real)ix[j];
-        fy[j] = (Real)iy[j];
-        fz[j] = (Real)iz[j];
         lx = min(lx, (int)ix[j]);
         ly = min(ly, (int)iy[j]);
         lz = min(lz, (int)iz[j]);
@@ -360,23 +422,39 @@ __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real
                 else mfma_far2_block<false>(a, txy, tzl, sb, row, kq, blk);
             }
         }
-        if (sizeof(Real) == 8 || cls != kClassFar2)
+        // FP64 table-value blocks have loops of their own (the FP32 kernel's registers, at four
+        // wavefronts per SIMD, leave no room for them: its table, gather and mixed blocks take
+        // the step loop below)
+        bool done = false;
+        if constexpr (sizeof(Real) == 8) {
+            if (cls == kClassTable) {
+                mfma_lookup_block<Real, false>(a, L, ix, iy, iz, sb, row, kq, blk);
+                done = true;
+            } else if (cls == kClassGather || (cls == kClassMixed && !a.far_ok)) {
+                mfma_lookup_block<Real, true>(a, L, ix, iy, iz, sb, row, kq, blk);
+                done = true;
+            }
+        } else {
+            done = cls == kClassFar2;
+        }
+        if (!done)
         for (int st = 0; st < kSourceBlock; st += 4) {
             const int s = sb + st + kq;
             const Real wb = a.w[row * a.ldw + s];
             Real G[kTiles];
             if (sizeof(Real) == 8 && cls == kClassFar) {
                 const Real sx = a.sxr[s], sy = a.syr[s], sz = a.szr[s];
+                // the targets' coordinates converted here (registers kept for the loops above)
                 if (a.yukawa) {
 #pragma unroll
                     for (int j = 0; j < kTiles; ++j) {
-                        const Real dx = fx[j] - sx, dy = fy[j] - sy, dz = fz[j] - sz;
+                        const Real dx = (Real)ix[j] - sx, dy = (Real)iy[j] - sy, dz = (Real)iz[j] - sz;
                         G[j] = far_field_yukawa<Real>(dx * dx, dy * dy, dz * dz, a.kq, a.yk);
                     }
                 } else {
 #pragma unroll
                     for (int j = 0; j < kTiles; ++j) {
-                        const Real dx = fx[j] - sx, dy = fy[j] - sy, dz = fz[j] - sz;
+                        const Real dx = (Real)ix[j] - sx, dy = (Real)iy[j] - sy, dz = (Real)iz[j] - sz;
                         G[j] = far_field<Real>(dx * dx, dy * dy, dz * dz);
                     }
                 }
@@ -399,11 +477,8 @@ __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real
                         if (max3u(da, db, dc) <= tab_q) {
                             G[j] = lds_value(L, table_offset(L, da, db, dc));
                         } else if (a.far_ok) {
-                            // FP32: the target's coordinates converted here, not kept in registers
-                            const Real tx = sizeof(Real) == 8 ? fx[j] : (Real)ix[j];
-                            const Real ty = sizeof(Real) == 8 ? fy[j] : (Real)iy[j];
-                            const Real tz = sizeof(Real) == 8 ? fz[j] : (Real)iz[j];
-                            const Real dx = tx - a.sxr[s], dy = ty - a.syr[s], dz = tz - a.szr[s];
+                            const Real dx = (Real)ix[j] - a.sxr[s], dy = (Real)iy[j] - a.syr[s],
+                                       dz = (Real)iz[j] - a.szr[s];
                             G[j] = a.yukawa ? far_field_yukawa<Real>(dx * dx, dy * dy, dz * dz, a.kq, a.yk)
                                             : far_field<Real>(dx * dx, dy * dy, dz * dz);
                         } else {

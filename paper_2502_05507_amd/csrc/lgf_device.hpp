@@ -161,20 +161,24 @@ __device__ __forceinline__ double far_field_q4(double X, double Y, double Z) {
     return rinv * B;
 }
 
-// sigma > 0 (s = kappa^2 in lattice units), FP32: the same Fourier-symbol expansion with
+// sigma > 0 (s = kappa^2 in lattice units): the same Fourier-symbol expansion with
 // 1/(s + |theta|^2)^k in place of 1/|theta|^(2k) gives, with u = kappa |n|,
 //   G_s(n) = e^(-u) / (4 pi |n|) [1 + T2 + O(|n|^-4)],
 //   T2 = [(1 + u)(1 - 5x)/4 - u^2 x/2 + u^3 (1 - 2x)/24] / |n|^2,
-// which at u = 0 is the q = 2 term above.  The expansion is asymptotic in 1/|n| at fixed u
-// only while kappa is small, so a context uses it only after checking it against its own
-// exact table at every offset beyond the LDS radius.  kq = kappa / kQuant and
-// yk = -kappa log2(e) / kQuant (quantised offsets: |D| = kQuant |n|).
+// which at u = 0 is the q = 2 term above.  It is evaluated as e^(-u + T2) / (4 pi |n|): the
+// factor 1 + T2 becomes e^T2, which differs from it by T2^2/2 = O(|n|^-4), the order of the
+// first dropped term, and puts the correction into the exponent (one instruction fewer per
+// value).  The expansion is asymptotic in 1/|n| at fixed u only while kappa is small, so a
+// context uses it only after checking this form against its own exact table at every offset
+// beyond the LDS radius.  kq = kappa / kQuant and yk = -kappa log2(e) / kQuant (quantised
+// offsets: |D| = kQuant |n|).
 template <typename Real>
 __device__ __forceinline__ Real far_field_yukawa(Real X, Real Y, Real Z, Real kq, Real yk) {
     constexpr double kLog2C = -1.6514961294723187;   // log2(kQuant / (4 pi)) = log2(1 / pi)
+    constexpr double kL = 1.4426950408889634;         // log2(e)
     const Real r2 = X + Y + Z;
     const Real e2 = fma(X, Y + Z, Y * Z);
-    Real rinv, ex;
+    Real rinv;
     if constexpr (sizeof(Real) == 4) {
         rinv = __builtin_amdgcn_rsqf(r2);
     } else {
@@ -184,36 +188,36 @@ __device__ __forceinline__ Real far_field_yukawa(Real X, Real Y, Real Z, Real kq
     const Real x = e2 * rho * rho;
     const Real rq = r2 * rinv;
     const Real u = rq * kq;
-    if constexpr (sizeof(Real) == 4) ex = __builtin_amdgcn_exp2f(fmaf(rq, yk, float(kLog2C)));
-    else ex = exp2(fma(rq, yk, kLog2C));
-    // kQuant^2 = 16 folded into the bracket (rho is 1/|D|^2 = 1/(16 |n|^2))
-    const Real A = fma(Real(-20), x, Real(4));
-    const Real c2 = Real(-8) * x;
-    const Real c3 = fma(Real(-4.0 / 3.0), x, Real(2.0 / 3.0));
+    // kQuant^2 = 16 folded into the bracket (rho is 1/|D|^2 = 1/(16 |n|^2)), and log2(e)
+    const Real A = fma(Real(-20 * kL), x, Real(4 * kL));
+    const Real c2 = Real(-8 * kL) * x;
+    const Real c3 = fma(Real(-4.0 / 3.0 * kL), x, Real(2.0 / 3.0 * kL));
     const Real br = fma(u, fma(u, fma(u, c3, c2), A), A);
-    return ex * rinv * fma(rho, br, Real(1));
+    const Real arg = fma(rho, br, fma(rq, yk, Real(kLog2C)));
+    if constexpr (sizeof(Real) == 4) return __builtin_amdgcn_exp2f(arg) * rinv;
+    else return exp2(arg) * rinv;
 }
 
 // The same sigma > 0 form from the lattice offset (FP32), through r2, Z and m as in
 // far_field_q2_lattice: with x4 = 4 e2/|n|^4 = 1 + 2 zeta - 3 zeta^2 - mu^2, the bracket is
 //   T2 |n|^2 = P0(u) + x4 P1(u),  P0 = (1 + u)/4 + u^3/24,  P1 = -5(1 + u)/16 - u^2/8 - u^3/48,
 // evaluated as one cubic in u, A (1 + u) + B u^2 + C u^3 with A = 1/4 - 5 x4/16, B = -x4/8
-// and C = 1/24 - x4/48.
+// and C = 1/24 - x4/48 (each times log2(e), for the exponent).
 // kl = kappa, ykl = -kappa log2(e) (lattice units).
 __device__ __forceinline__ float far_field_yukawa_lattice(float r2, float Z, float m, float kl, float ykl) {
     constexpr float kLog2C = -3.6514961294723187f;   // log2(1 / (4 pi))
+    constexpr double kL = 1.4426950408889634;         // log2(e)
     const float rinv = __builtin_amdgcn_rsqf(r2);
     const float rho = rinv * rinv;
     const float zeta = Z * rho, mu = m * rho;
     const float x4 = fmaf(-mu, mu, fmaf(zeta, fmaf(zeta, -3.0f, 2.0f), 1.0f));
     const float rq = r2 * rinv;
     const float u = rq * kl;
-    const float ex = __builtin_amdgcn_exp2f(fmaf(rq, ykl, kLog2C));
-    const float A = fmaf(x4, -0.3125f, 0.25f);
-    const float B = -0.125f * x4;
-    const float C = fmaf(x4, -1.0f / 48.0f, 1.0f / 24.0f);
+    const float A = fmaf(x4, float(-0.3125 * kL), float(0.25 * kL));
+    const float B = float(-0.125 * kL) * x4;
+    const float C = fmaf(x4, float(-kL / 48.0), float(kL / 24.0));
     const float br = fmaf(u, fmaf(u, fmaf(u, C, B), A), A);
-    return ex * rinv * fmaf(rho, br, 1.0f);
+    return __builtin_amdgcn_exp2f(fmaf(rho, br, fmaf(rq, ykl, kLog2C))) * rinv;
 }
 
 template <typename Real>

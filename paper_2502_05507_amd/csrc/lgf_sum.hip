@@ -252,8 +252,8 @@ struct MfmaAcc<double> {
 // FP32 far block (every pair beyond the far-field gap): the lattice-form far field from the
 // binary16 differences, with the next step's source and weight loads in flight while this
 // step is evaluated.  The 16 steps are unrolled so that every load addresses its block by an
-// immediate offset from three per-lane pointers set once per block.  Without the Yukawa
-// factor the block sums are scaled by kFarScale32 once at the end.
+// immediate offset from three per-lane pointers set once per block.  The products add to the
+// running block sums blk (several blocks are summed before they are folded).
 template <bool YUK>
 __device__ __forceinline__ void mfma_far2_block(const SumArgs<float>& a, const uint32_t (&txy)[kTiles],
                                                 const float (&tzl)[kTiles], int sb, int row, int kq,
@@ -280,16 +280,13 @@ __device__ __forceinline__ void mfma_far2_block(const SumArgs<float>& a, const u
 #pragma unroll
         for (int j = 0; j < kTiles; ++j)
             G[j] = YUK ? far_field_yukawa_lattice(r2[j], Z[j], m[j], a.kl, a.ykl) : far_field_q2_lattice(r2[j], Z[j], m[j]);
+        // sigma = 0: the lattice form's common factor kFarScale32 rides on the weights
+        const float ws = YUK ? wb : wb * kFarScale32;
 #pragma unroll
-        for (int j = 0; j < kTiles; ++j) blk[j] = MfmaAcc<float>::mma(G[j], wb, blk[j]);
+        for (int j = 0; j < kTiles; ++j) blk[j] = MfmaAcc<float>::mma(G[j], ws, blk[j]);
         sxy = sxy_n;
         szl = szl_n;
         wb = wb_n;
-    }
-    if (!YUK) {
-#pragma unroll
-        for (int j = 0; j < kTiles; ++j)
-            for (int v = 0; v < 4; ++v) blk[j][v] *= kFarScale32;
     }
 }
 
@@ -490,14 +487,15 @@ __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real
 #pragma unroll
             for (int j = 0; j < kTiles; ++j) blk[j] = MfmaAcc<Real>::mma(G[j], wb, blk[j]);
         }
-        // fold the block's sums into the running (compensated, for FP32) accumulators
+        // fold the block's sums into the running accumulators: compensated (Kahan) for FP32,
+        // 4 VALU instructions per accumulator element (Neumaier's branch-free form takes 8)
 #pragma unroll
         for (int j = 0; j < kTiles; ++j)
             for (int v = 0; v < 4; ++v) {
                 if constexpr (sizeof(Real) == 4) {
-                    const Real x = blk[j][v], sum = acc[j][v];
-                    const Real t = sum + x;
-                    comp[j][v] += fabs(sum) >= fabs(x) ? (sum - t) + x : (x - t) + sum;
+                    const Real y = blk[j][v] - comp[j][v];
+                    const Real t = acc[j][v] + y;
+                    comp[j][v] = (t - acc[j][v]) - y;
                     acc[j][v] = t;
                 } else {
                     acc[j][v] += blk[j][v];
@@ -511,7 +509,7 @@ __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real
             const int i = sizeof(Real) == 4 ? 4 * kq + v : kq + 4 * v;
             const int t = base + 16 * j + i;
             if (t < a.nt)
-                a.part[(int64_t)row * a.ldp + (int64_t)chunk * a.nt + t] = (double)acc[j][v] + (double)comp[j][v];
+                a.part[(int64_t)row * a.ldp + (int64_t)chunk * a.nt + t] = (double)acc[j][v] - (double)comp[j][v];
         }
 }
 

@@ -72,9 +72,10 @@ def kernel_hash(files=("paper_2502_05507_amd/csrc/lgf_sum.hip", "paper_2502_0550
 # were taken on (their hash): HBM bytes per launch (FETCH_SIZE x f + WRITE_SIZE x w, the
 # factors calibrated on copies of known size), VALU-issue and matrix-core-busy shares.
 MEASURED = {
-    "lgf_sum_mfma_helmholtz_star_257": {"sources_sha256_16": "f00872bff75eb908",
-                                        "bytes": (1.39173e7 * 2.0 + 1.069e6 * 1.0) * 1024,
-                                        "valu_issue": 0.807, "mfma_busy": 0.232},
+    "lgf_sum_mfma_helmholtz_star_257": {"sources_sha256_16": "5a11ec51ee3a964a",
+                                        "bytes": (1.3922e7 * 2.0 + 1.0685e6 * 1.0) * 1024,
+                                        "valu_issue": 0.783, "valu_busy": 0.836, "mfma_busy": 0.241,
+                                        "l2_hit": 0.742},
 }
 
 
@@ -346,7 +347,9 @@ def headline(args, torch, P, W):
                 "flop_convention": f"{F_FAR} per far-field kernel value + {F_RHS} per (pair, RHS)",
                 "pair_classes": st32,
                 "valu_issue_share": meas["valu_issue"] if meas else None,
-                "mfma_busy_share": meas["mfma_busy"] if meas else None}
+                "valu_busy_share": meas["valu_busy"] if meas else None,
+                "mfma_busy_share": meas["mfma_busy"] if meas else None,
+                "l2_hit_rate": meas["l2_hit"] if meas else None}
 
     out = {
         "metric": METRIC,

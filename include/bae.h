@@ -237,7 +237,7 @@ int bae_set_rhs_box(bae_ctx* ctx, int32_t nrhs, const double* g_xstar, const dou
  * Device form of bae_set_rhs / bae_set_rhs_box, asynchronous on `stream`: g_dev
  * [nrhs][|gamma-|] and f_dev [nrhs][n0 n1 n2] (or NULL for f = 0) are device FP64 arrays
  * (e.g. torch tensors) that must stay valid until `stream` has passed this call's work.
- * particular: BAE_PARTICULAR_FREE or BAE_PARTICULAR_BOX (as bae_set_rhs_box; cubic grid).
+ * particular: BAE_PARTICULAR_FREE or BAE_PARTICULAR_BOX (as bae_set_rhs_box).
  * Nothing is read back: a non-finite g or f is flagged on the device and the next solve
  * fails with BAE_ERR_NONFINITE.  The first call with f on a context does one-time set-up
  * (index maps, work list) on the host and the context's own stream.  Errors: BAE_ERR_ARG.
@@ -255,8 +255,9 @@ int bae_get_particular(const bae_ctx* ctx, int32_t r, double* up_grid);
  */
 int bae_solve(bae_ctx* ctx, const bae_solve_params* params, bae_result* results);
 /* Outputs of the last solve, RHS r (or every RHS for r = -1, [nrhs][len]; host buffers):
-   q_d (|gamma-|), u_gamma (|gamma|), u on the grid (n0 n1 n2, NaN outside N+; needs
-   compute_grid), residual history (r >= 0 only). */
+   the density (|gamma-|, or |gamma| after a direct-formulation solve: bae_get_density_length),
+   u_gamma (|gamma|), u on the grid (n0 n1 n2, NaN outside N+; needs compute_grid), residual
+   history (r >= 0 only).  Errors: BAE_ERR_ARG, BAE_ERR_STATE (no solve yet). */
 int bae_get_density(const bae_ctx* ctx, int32_t r, double* q);
 int bae_get_gamma_values(const bae_ctx* ctx, int32_t r, double* u_gamma);
 int bae_get_solution(const bae_ctx* ctx, int32_t r, double* u_grid);
@@ -282,7 +283,8 @@ int bae_solve_poll(const bae_ctx* ctx, int32_t* done);
    (BAE_OK, BAE_NOT_CONVERGED or its error); BAE_ERR_STATE if no solve was started. */
 int bae_solve_wait(bae_ctx* ctx, void* stream, bae_result* results);
 /* Device forms of the getters, asynchronous on `stream`: RHS r, or every RHS for r = -1
-   ([nrhs][len]); q_dev |gamma-|, u_dev |gamma| or n0 n1 n2 doubles per RHS. */
+   ([nrhs][len]); q_dev bae_get_density_length doubles, u_dev |gamma| or n0 n1 n2 doubles per
+   RHS. */
 int bae_get_density_device(const bae_ctx* ctx, int32_t r, double* q_dev, void* stream);
 int bae_get_gamma_values_device(const bae_ctx* ctx, int32_t r, double* u_dev, void* stream);
 int bae_get_solution_device(const bae_ctx* ctx, int32_t r, double* u_dev, void* stream);
@@ -394,6 +396,8 @@ typedef struct bae_server_options {
     int32_t maxit;             /* GMRES iterations per (inner) solve                   */
     int32_t max_krylov;        /* Krylov capacity per request (default 200)            */
     int32_t iters_per_step;    /* GMRES iterations between scheduling points (default 4) */
+    int32_t setup_threads;     /* host threads that classify geometries and build contexts
+                                  (default 4, at most 16)                                */
 } bae_server_options;
 
 typedef struct bae_request {   /* one Dirichlet problem, f = 0 (sigma >= 0)             */
@@ -415,10 +419,12 @@ typedef struct bae_server_stats {
 } bae_server_stats;
 
 /*
- * Start a server: a set-up thread admits requests in arrival order when a slot is free and
- * their device footprint (computed from the classified geometry, before any allocation)
- * fits in hbm_budget, and builds each one's context (point sets, LGF table, boundary data
- * through its callback) on the context's own stream while the batch runs; a scheduler
+ * Start a server: set-up threads classify the geometry of the first waiting requests (which
+ * gives each one's device footprint before any allocation), admit requests in arrival order
+ * when a slot is free and the footprint fits in hbm_budget, and build each one's context
+ * (point sets, LGF table, boundary data through its callback; the callback may run on any of
+ * these threads, one call at a time per request) on the context's own stream while the
+ * batch runs; a scheduler
  * thread adds set-up requests to the running batch at the next step, advances all running
  * requests together (one launch per GMRES phase), and retires finished ones, releasing
  * their slot and memory.  A request larger than the whole budget fails with

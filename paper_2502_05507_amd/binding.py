@@ -69,7 +69,7 @@ BoundaryFn = C.CFUNCTYPE(None, C.c_void_p, C.c_int64, C.POINTER(C.c_double), C.P
 class ServerOptions(C.Structure):
     _fields_ = [("device", C.c_int32), ("max_slots", C.c_int32), ("hbm_budget", C.c_int64),
                 ("precision", C.c_int32), ("tol", C.c_double), ("maxit", C.c_int32), ("max_krylov", C.c_int32),
-                ("iters_per_step", C.c_int32)]
+                ("iters_per_step", C.c_int32), ("setup_threads", C.c_int32)]
 
 
 class Request(C.Structure):
@@ -487,13 +487,13 @@ def _grid_and_levelset(n, h, origin, sigma, kind, center, params, phi=None):
 
 class Server:
     """Continuous-batching solve server (bae_server_*).  Boundary data are Python callables
-    g(xyz: (N,3) array) -> (N,) array, called on the server thread at admission."""
+    g(xyz: (N,3) array) -> (N,) array, called on one of the server's set-up threads at admission."""
 
     def __init__(self, hbm_budget, max_slots=64, precision=SOLVE_FP64, tol=1e-10, maxit=0, max_krylov=200,
-                 iters_per_step=4, device=0):
+                 iters_per_step=4, device=0, setup_threads=0):
         lib = load_library()
         o = ServerOptions(int(device), int(max_slots), int(hbm_budget), int(precision), float(tol), int(maxit),
-                          int(max_krylov), int(iters_per_step))
+                          int(max_krylov), int(iters_per_step), int(setup_threads))
         h = _P()
         _check(lib.bae_server_create(C.byref(o), C.byref(h)))
         self._h = h

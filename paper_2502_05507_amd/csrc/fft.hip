@@ -43,9 +43,20 @@ __device__ __forceinline__ int64_t line_at(int axis, int64_t l, int64_t n, int n
 
 // DST-I of every line along `axis` (length N = its extent), in place, times `scale`.  A block
 // takes P lines (P even: line pairs share a complex FFT of length p.M = 2(N + 1)).
+// With eig.c0 set (the last forward pass, axis 2), each output is also divided by the
+// eigenvalue of L_h at its frequency (i, j, k): lambda = (6 + s) - c0[i] - c1[j] - c2[k] with
+// c_d[k] = 2 cos(pi (k + 1) / (n_d + 1)) -- the division of the box solve, fused into the pass
+// that produces the last frequency index.
+struct BoxEigen {
+    const double* c0 = nullptr;
+    const double* c1 = nullptr;
+    const double* c2 = nullptr;
+    double shift = 0.0;   // 6 + s
+};
+
 __global__ __launch_bounds__(kFftThreads) void dst_axis_kernel(double* __restrict__ x, int axis, int n0, int n1,
                                                                 int n2, int64_t nlines, int P, const FftDev p,
-                                                                double scale) {
+                                                                double scale, const BoxEigen eig) {
     extern __shared__ double2 lds[];
     const int N = axis == 0 ? n0 : axis == 1 ? n1 : n2;
     const int M = p.M;
@@ -91,18 +102,13 @@ __global__ __launch_bounds__(kFftThreads) void dst_axis_kernel(double* __restric
         const int64_t l = l0 + pl;
         if (l >= nlines) continue;
         const double2 z = Z[(int64_t)(pl >> 1) * M + n + 1];
-        x[line_at(axis, l, n, n0, n1, n2)] = (pl & 1) ? h * z.x : -h * z.y;
+        double v = (pl & 1) ? h * z.x : -h * z.y;
+        if (eig.c0) {   // axis 2: line l = i n1 + j, element n = k
+            const int i = (int)(l / n1), j = (int)(l - (int64_t)i * n1);
+            v /= eig.shift - (eig.c0[i] + eig.c1[j] + eig.c2[n]);
+        }
+        x[line_at(axis, l, n, n0, n1, n2)] = v;
     }
-}
-
-// x[k1][k2][k3] *= scale / lambda(k), lambda = (6 + s) - 2 sum_d cos(pi (k_d + 1) / (n_d + 1))
-__global__ void box_eigen_kernel(double* __restrict__ x, int n0, int n1, int n2, double s, double scale) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)n0 * n1 * n2) return;
-    const int k1 = (int)(i / ((int64_t)n1 * n2)), k2 = (int)((i / n2) % n1), k3 = (int)(i % n2);
-    const double lam = (6.0 + s) - 2.0 * (cospi((double)(k1 + 1) / (n0 + 1)) + cospi((double)(k2 + 1) / (n1 + 1)) +
-                                          cospi((double)(k3 + 1) / (n2 + 1)));
-    x[i] *= scale / lam;
 }
 
 // W = chi_{M-} L_h H on the interior nodes (N0 x N1 x N2, offset one node from the full grid
@@ -136,6 +142,28 @@ struct PlanHolder {
 
 std::mutex g_plan_mu;
 auto* g_plans = new std::map<std::pair<int, int>, std::unique_ptr<PlanHolder>>();
+// c[k] = 2 cos(pi (k + 1) / (N + 1)), k < N, per (device, N): the axis terms of the box
+// eigenvalues (kept until the process ends, like the plans)
+auto* g_cos = new std::map<std::pair<int, int>, double*>();
+
+const double* eigen_cos(int N, hipStream_t st) {
+    int device = 0;
+    BAE_HIP_CHECK(hipGetDevice(&device));
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    double*& slot = (*g_cos)[{device, N}];
+    if (!slot) {
+        std::vector<double> c(N);
+        for (int k = 0; k < N; ++k)
+            c[k] = (double)(2.0L * cosl(3.14159265358979323846264338327950288L * (long double)(k + 1) /
+                                        (long double)(N + 1)));
+        double* d = nullptr;
+        BAE_HIP_CHECK(hipMalloc((void**)&d, sizeof(double) * N));
+        BAE_HIP_CHECK(hipMemcpyAsync(d, c.data(), sizeof(double) * N, hipMemcpyHostToDevice, st));
+        BAE_HIP_CHECK(hipStreamSynchronize(st));
+        slot = d;
+    }
+    return slot;
+}
 
 }  // namespace
 
@@ -192,7 +220,8 @@ static int lines_per_block(int M) {
     return 2 * fft_lines_per_block(M, 16);   // two real lines per complex FFT, at most 32
 }
 
-void dst_axis(double* x, int n0, int n1, int n2, int axis, double scale, hipStream_t st) {
+static void dst_axis_eig(double* x, int n0, int n1, int n2, int axis, double scale, const BoxEigen& eig,
+                         hipStream_t st) {
     const int N = axis == 0 ? n0 : axis == 1 ? n1 : n2;
     if (N <= 0) return;
     const FftDev p = fft_plan(2 * (N + 1), st);
@@ -206,8 +235,12 @@ void dst_axis(double* x, int n0, int n1, int n2, int axis, double scale, hipStre
         attr = true;
     }
     const unsigned blocks = (unsigned)((nlines + P - 1) / P);
-    dst_axis_kernel<<<blocks, fftdev::kFftThreads, lds, st>>>(x, axis, n0, n1, n2, nlines, P, p, scale);
+    dst_axis_kernel<<<blocks, fftdev::kFftThreads, lds, st>>>(x, axis, n0, n1, n2, nlines, P, p, scale, eig);
     BAE_HIP_CHECK(hipGetLastError());
+}
+
+void dst_axis(double* x, int n0, int n1, int n2, int axis, double scale, hipStream_t st) {
+    dst_axis_eig(x, n0, n1, n2, axis, scale, BoxEigen{}, st);
 }
 
 void difference_source(const double* H, const uint8_t* inside, const int* n, double s, double* W, hipStream_t st) {
@@ -220,11 +253,15 @@ void difference_source(const double* H, const uint8_t* inside, const int* n, dou
 
 void box_solve_fft(double* x, int n0, int n1, int n2, double s, hipStream_t st) {
     if ((int64_t)n0 * n1 * n2 <= 0) return;
-    for (int a = 0; a < 3; ++a) dst_axis(x, n0, n1, n2, a, 1.0, st);
     const double scale = (2.0 / (n0 + 1)) * (2.0 / (n1 + 1)) * (2.0 / (n2 + 1));
-    const int64_t n3 = (int64_t)n0 * n1 * n2;
-    box_eigen_kernel<<<(unsigned)((n3 + 255) / 256), 256, 0, st>>>(x, n0, n1, n2, s, scale);
-    BAE_HIP_CHECK(hipGetLastError());
+    BoxEigen eig;
+    eig.c0 = eigen_cos(n0, st);
+    eig.c1 = eigen_cos(n1, st);
+    eig.c2 = eigen_cos(n2, st);
+    eig.shift = 6.0 + s;
+    dst_axis(x, n0, n1, n2, 0, 1.0, st);
+    dst_axis(x, n0, n1, n2, 1, 1.0, st);
+    dst_axis_eig(x, n0, n1, n2, 2, scale, eig, st);   // with the eigenvalue division
     for (int a = 0; a < 3; ++a) dst_axis(x, n0, n1, n2, a, 1.0, st);
 }
 

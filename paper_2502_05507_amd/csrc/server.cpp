@@ -1,11 +1,14 @@
 // Serving loop with continuous batching.
 //
-// Two host threads share the device.  Submitted requests wait in FIFO order; the set-up
-// thread admits one when a slot is free and its device footprint (computed from its
-// classified geometry before any device allocation) fits in the remaining memory budget,
-// reserves both, and builds the request's context -- point sets, LGF table, boundary data
-// through the caller's callback -- on the context's own stream, while the running batch
-// keeps the device busy.  The scheduler thread owns one batch engine: at each step boundary
+// Host threads share the device.  Submitted requests wait in FIFO order.  A pool of set-up
+// threads classifies the geometry of the first waiting requests (host work, in parallel:
+// that sizes each request's device footprint before any device allocation), admits the
+// front request when a slot is free and its footprint fits in the remaining memory budget
+// (admission stays FIFO), reserves both, and builds the request's context -- point sets,
+// LGF table, boundary data through the caller's callback -- on the context's own stream,
+// while the running batch keeps the device busy.  With one set-up thread the host geometry
+// of the larger grids limited admission to about 12 requests a second, with most slots idle.
+// The scheduler thread owns one batch engine: at each step boundary
 // it takes the requests whose set-up has finished into the batch; every step advances all
 // running requests by a few GMRES iterations with one launch per phase, so new work
 // overlaps with work already on the GPU.  A finished request (FP64 GMRES, or the FP32 inner
@@ -39,6 +42,7 @@ struct Req {
     int status = BAE_OK;
     std::string error;
     std::unique_ptr<Geometry> geo;
+    bool sizing = false, sized = false;   // geometry being classified / classified
     int64_t bytes = 0;
     bae_ctx* ctx = nullptr;
     double bnorm = 0.0, relres = 1.0;
@@ -59,7 +63,8 @@ using namespace bae;
 struct bae_server {
     bae_server_options opt{};
     BatchEngine* engine = nullptr;
-    std::thread thread, setup_thread;
+    std::thread thread;
+    std::vector<std::thread> setup_threads;
     std::mutex mu;
     std::condition_variable cv_work, cv_setup, cv_done;
     bool stop = false;
@@ -86,9 +91,13 @@ void fail(bae_server* s, const std::shared_ptr<Req>& r, int status, const std::s
     s->stats.failed++;
 }
 
-// The set-up thread: admits waiting requests in FIFO order while a slot and memory are
-// free (both reserved at admission) and builds each one's context, then hands it to the
-// scheduler.  Every failure fails that request only.
+// Waiting requests whose geometry the set-up threads classify ahead of admission.
+constexpr int kSizeAhead = 16;
+
+// A set-up thread: admits the front request when it is classified and a slot and its memory
+// are free (both reserved at admission) and builds its context, then hands it to the
+// scheduler; otherwise classifies the geometry of one of the first waiting requests.  Every
+// failure fails that request only.
 void setup_loop(bae_server* s) {
     (void)hipSetDevice(s->opt.device);
     bae_options o{};
@@ -96,27 +105,52 @@ void setup_loop(bae_server* s) {
     o.max_rhs = 1;
     o.max_krylov = s->opt.max_krylov;
     for (;;) {
-        std::shared_ptr<Req> r;
+        std::shared_ptr<Req> r, sz;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             auto slot_free = [&] {
                 return (int)(s->running.size() + s->ready.size()) + s->in_setup < s->opt.max_slots;
             };
-            s->cv_setup.wait(lk, [&] { return s->stop || (!s->waiting.empty() && slot_free()); });
+            auto admissible = [&] {
+                if (s->waiting.empty()) return false;
+                const auto& f = s->waiting.front();
+                return f->sized && slot_free() && s->used + f->bytes <= s->opt.hbm_budget;
+            };
+            auto to_size = [&]() -> std::shared_ptr<Req> {
+                int k = 0;
+                for (const auto& w : s->waiting) {
+                    if (k++ >= kSizeAhead) break;
+                    if (!w->sized && !w->sizing) return w;
+                }
+                return nullptr;
+            };
+            s->cv_setup.wait(lk, [&] { return s->stop || admissible() || to_size() != nullptr; });
             if (s->stop) return;
-            r = s->waiting.front();
+            if (admissible()) {
+                r = s->waiting.front();
+                s->waiting.pop_front();
+                s->used += r->bytes;
+                s->in_setup++;
+                s->stats.admitted++;
+                s->stats.peak_bytes = std::max<int64_t>(s->stats.peak_bytes, s->used);
+                r->state = Q_RUNNING;
+                r->t_admit = s->now();
+            } else {
+                sz = to_size();
+                sz->sizing = true;
+            }
         }
-        // the geometry (host) gives the exact footprint before any device allocation
         std::string fail_msg;
         int fail_code = BAE_OK;
-        if (!r->geo && r->bytes == 0) {
+        if (sz) {
+            // the geometry (host) gives the exact footprint before any device allocation
+            auto geo = std::make_unique<Geometry>();
+            int64_t bytes = 0;
             try {
-                auto geo = std::make_unique<Geometry>();
-                bae_levelset ls = r->ls;
-                if (ls.kind == BAE_LS_SAMPLED) ls.phi_samples = r->phi.data();
-                build_geometry(r->grid, ls, *geo);
-                r->bytes = estimate_context_bytes(*geo, r->grid.sigma * r->grid.h * r->grid.h, &o);
-                r->geo = std::move(geo);
+                bae_levelset ls = sz->ls;
+                if (ls.kind == BAE_LS_SAMPLED) ls.phi_samples = sz->phi.data();
+                build_geometry(sz->grid, ls, *geo);
+                bytes = estimate_context_bytes(*geo, sz->grid.sigma * sz->grid.h * sz->grid.h, &o);
             } catch (const Error& e) {
                 fail_code = e.code;
                 fail_msg = e.msg;
@@ -124,29 +158,25 @@ void setup_loop(bae_server* s) {
                 fail_code = BAE_ERR_ARG;
                 fail_msg = std::string("geometry: ") + e.what();
             }
-        }
-        {
-            std::unique_lock<std::mutex> lk(s->mu);
-            if (fail_code == BAE_OK && r->bytes > s->opt.hbm_budget) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            sz->sizing = false;
+            if (fail_code == BAE_OK && bytes > s->opt.hbm_budget) {
                 fail_code = BAE_ERR_ADMISSION;
                 fail_msg = "request needs more device memory than the whole budget";
             }
+            const auto it = std::find(s->waiting.begin(), s->waiting.end(), sz);
+            if (it == s->waiting.end()) continue;   // failed meanwhile (server shut down)
             if (fail_code != BAE_OK) {
-                s->waiting.pop_front();
-                fail(s, r, fail_code, fail_msg);
+                s->waiting.erase(it);
+                fail(s, sz, fail_code, fail_msg);
                 s->cv_done.notify_all();
-                continue;
+            } else {
+                sz->geo = std::move(geo);
+                sz->bytes = bytes;
+                sz->sized = true;
             }
-            // wait for memory in FIFO order (finished requests release it)
-            s->cv_setup.wait(lk, [&] { return s->stop || s->used + r->bytes <= s->opt.hbm_budget; });
-            if (s->stop) return;
-            s->waiting.pop_front();
-            s->used += r->bytes;
-            s->in_setup++;
-            s->stats.admitted++;
-            s->stats.peak_bytes = std::max<int64_t>(s->stats.peak_bytes, s->used);
-            r->state = Q_RUNNING;
-            r->t_admit = s->now();
+            s->cv_setup.notify_all();
+            continue;
         }
         try {
             r->ctx = create_context(r->grid, &o, std::move(*r->geo));
@@ -322,11 +352,13 @@ int bae_server_create(const bae_server_options* opt, bae_server** out) {
         if (s->opt.max_krylov <= 0) s->opt.max_krylov = 200;
         if (s->opt.maxit <= 0 || s->opt.maxit > s->opt.max_krylov) s->opt.maxit = s->opt.max_krylov;
         if (s->opt.iters_per_step <= 0) s->opt.iters_per_step = 4;
+        if (s->opt.setup_threads <= 0) s->opt.setup_threads = 4;
+        s->opt.setup_threads = std::min(s->opt.setup_threads, 16);
         BAE_HIP_CHECK(hipSetDevice(s->opt.device));
         s->engine = batch_engine_new(s->opt.device, nullptr);
         s->t0 = clock_t_::now();
         s->thread = std::thread(scheduler, s.get());
-        s->setup_thread = std::thread(setup_loop, s.get());
+        for (int k = 0; k < s->opt.setup_threads; ++k) s->setup_threads.emplace_back(setup_loop, s.get());
         *out = s.release();
     });
 }
@@ -444,7 +476,8 @@ int bae_server_destroy(bae_server* s) {
         s->cv_setup.notify_all();
         s->cv_done.notify_all();
     }
-    if (s->setup_thread.joinable()) s->setup_thread.join();   // a set-up in progress finishes first
+    for (auto& t : s->setup_threads)   // set-ups in progress finish first
+        if (t.joinable()) t.join();
     if (s->thread.joinable()) s->thread.join();
     (void)hipSetDevice(s->opt.device);
     batch_engine_delete(s->engine);

@@ -124,7 +124,9 @@ def test_yukawa_far_field_form():
     # T2 |n|^2 = (1 + u)(1 - 5x)/4 - u^2 x/2 + u^3 (1 - 2x)/24, x = e2/|n|^4.  Against the
     # table: the dropped term is O(|n|^-4) at fixed u (error ratio ~2^4 when |n| doubles
     # along a ray), and at s = 0 it is the paper's q = 2 form.
-    def form(n, s):
+    # The device evaluates the exponentiated form e^(-u + T2) / (4 pi |n|), which differs from
+    # the expansion by T2^2 / 2 = O(|n|^-4), the order of the dropped term: both are pinned.
+    def form(n, s, exponent=False):
         j, k, l = (float(v) for v in n)
         X, Y, Z = j * j, k * k, l * l
         r2 = X + Y + Z
@@ -132,19 +134,20 @@ def test_yukawa_far_field_form():
         x = (X * Y + Y * Z + Z * X) / r2 ** 2
         u = math.sqrt(s) * r
         T2 = ((1 + u) * (1 - 5 * x) / 4 - u * u * x / 2 + u ** 3 * (1 - 2 * x) / 24) / r2
-        return math.exp(-u) / (4 * math.pi * r) * (1 + T2)
+        return math.exp(-u) / (4 * math.pi * r) * (math.exp(T2) if exponent else 1 + T2)
 
     s = 1.5e-4                                          # kappa^2 h^2 of the 257^3 star
     t = lgf.LGFTable(150, s)
     rays = [(1, 0, 0), (1, 1, 0)]                      # directions where the dropped term is largest
-    for d in rays:
-        errs = []
-        for m in (12, 24, 48):
-            n = np.array([m * c for c in d])
-            errs.append(abs(form(n, s) / t(n) - 1))
-        assert 8 < errs[0] / errs[1] < 32 and 8 < errs[1] / errs[2] < 32, errs
-    n = np.array([56, 0, 0])
-    assert abs(form(n, s) / t(n) - 1) < 1.5e-7          # the worst offset beyond the LDS radius
+    for exponent in (False, True):
+        for d in rays:
+            errs = []
+            for m in (12, 24, 48):
+                n = np.array([m * c for c in d])
+                errs.append(abs(form(n, s, exponent) / t(n) - 1))
+            assert 8 < errs[0] / errs[1] < 32 and 8 < errs[1] / errs[2] < 32, errs
+        n = np.array([56, 0, 0])
+        assert abs(form(n, s, exponent) / t(n) - 1) < 1.5e-7   # the worst offset beyond the LDS radius
     t0 = lgf.LGFTable(60, 0.0)
     n = np.array([40, 25, 10])
     r = math.sqrt(40 ** 2 + 25 ** 2 + 10 ** 2)

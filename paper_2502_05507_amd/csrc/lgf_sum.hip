@@ -434,7 +434,18 @@ __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real
         } else {
             done = cls == kClassFar2;
         }
-        if (!done)
+        if (!done) {
+        // Table, gather and mixed blocks take the block's 64 integer source coordinates once,
+        // one per lane, and each step its four by a lane permutation (outside the
+        // vector-memory counter).
+        const bool by_lane = !(sizeof(Real) == 8 && cls == kClassFar);
+        int bxq = 0, byq = 0, bzq = 0;
+        if (by_lane) {
+            const int lane = threadIdx.x & 63;
+            bxq = (int)a.sx[sb + lane];
+            byq = (int)a.sy[sb + lane];
+            bzq = (int)a.sz[sb + lane];
+        }
         for (int st = 0; st < kSourceBlock; st += 4) {
             const int s = sb + st + kq;
             const Real wb = a.w[row * a.ldw + s];
@@ -456,7 +467,10 @@ __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real
                     }
                 }
             } else {
-                const uint32_t sx = a.sx[s], sy = a.sy[s], sz = a.sz[s];
+                const int from = (st + kq) << 2;
+                const uint32_t sx = (uint32_t)__builtin_amdgcn_ds_bpermute(from, bxq);
+                const uint32_t sy = (uint32_t)__builtin_amdgcn_ds_bpermute(from, byq);
+                const uint32_t sz = (uint32_t)__builtin_amdgcn_ds_bpermute(from, bzq);
                 if (cls == kClassTable) {
 #pragma unroll
                     for (int j = 0; j < kTiles; ++j)
@@ -474,8 +488,8 @@ __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real
                         if (max3u(da, db, dc) <= tab_q) {
                             G[j] = lds_value(L, table_offset(L, da, db, dc));
                         } else if (a.far_ok) {
-                            const Real dx = (Real)ix[j] - a.sxr[s], dy = (Real)iy[j] - a.syr[s],
-                                       dz = (Real)iz[j] - a.szr[s];
+                            // |d| components of the integer offsets, exact in the kernel's precision
+                            const Real dx = (Real)da, dy = (Real)db, dz = (Real)dc;
                             G[j] = a.yukawa ? far_field_yukawa<Real>(dx * dx, dy * dy, dz * dz, a.kq, a.yk)
                                             : far_field<Real>(dx * dx, dy * dy, dz * dz);
                         } else {
@@ -486,6 +500,7 @@ __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real
             }
 #pragma unroll
             for (int j = 0; j < kTiles; ++j) blk[j] = MfmaAcc<Real>::mma(G[j], wb, blk[j]);
+        }
         }
         // fold the block's sums into the running accumulators: compensated (Kahan) for FP32,
         // 4 VALU instructions per accumulator element (Neumaier's branch-free form takes 8)

@@ -20,7 +20,7 @@ beside it under "poisson_ellipsoid_129".
 
 Other workloads (--workload; their own JSON line, not the contract's):
   poisson_ellipsoid  129^3 Poisson ellipsoid, one RHS, FP32 VALU sum (the former headline)
-  laplace_sphere     33^3 Laplace sphere, FP64 and refined solve latency, oracle solve rate
+  laplace_sphere     33^3 Laplace sphere, FP64 and refined solve latency, the oracle's solve rate
   batch              512 seeded small problems in one lock-step, graph-replayed batch
   serve              Poisson arrivals into the continuous-batching server, p50/p99 latency
   profile            129^3 matvecs only (for rocprofv3) plus a device copy of known size
@@ -558,8 +558,24 @@ def laplace_sphere(args, torch, P, W):
                          "p99_ms": float(np.percentile(lat, 99) * 1e3), "iterations": r["iterations"],
                          "rel_residual": r["rel_residual_true"]}
         X = np.concatenate(ctx.sets()[:2]) * p.h
-        err = np.abs(ctx.gamma_values() - p.exact(*X.T)).max()
-        return {"workload": "laplace_sphere_33^3", "sizes": ctx.sizes, **res, "max_err_vs_exact": float(err)}
+        ug = ctx.gamma_values()
+        err = np.abs(ug - p.exact(*X.T)).max()
+    out = {"workload": "laplace_sphere_33^3", "sizes": ctx.sizes, **res, "max_err_vs_exact": float(err)}
+    if not args.no_cpu_baseline:
+        # the oracle's solve of the same problem (its literal sums, its own GMRES), one process
+        import resource
+        from oracle import bae as obae
+        c0 = resource.getrusage(resource.RUSAGE_SELF)
+        t0 = time.perf_counter()
+        ref = obae.solve(p, tol=1e-10)
+        t_or = time.perf_counter() - t0
+        c1 = resource.getrusage(resource.RUSAGE_SELF)
+        cpu_s = (c1.ru_utime - c0.ru_utime) + (c1.ru_stime - c0.ru_stime)
+        out["oracle_solve"] = {"solves_per_s": 1.0 / t_or, "seconds": t_or, "iterations": len(ref["history"]),
+                               "u_gamma_rel_diff_vs_gpu": float(np.linalg.norm(ug - ref["u_gamma"]) /
+                                                                np.linalg.norm(ref["u_gamma"])),
+                               "cpu_seconds_per_wall_second": cpu_s / t_or, "cpu_model": cpu_model()}
+    return out
 
 
 def resolved_problems(P, count, make):

@@ -38,12 +38,12 @@ def solo(p, prec):
         return c.density(), c.gamma_values(), c.sizes
 
 
-@pytest.mark.parametrize("prec", [P.SOLVE_FP64, P.SOLVE_FP32_REFINED])
-def test_results_alone_equal_results_in_the_mix(prec):
+@pytest.mark.parametrize("prec,threads", [(P.SOLVE_FP64, 1), (P.SOLVE_FP64, 4), (P.SOLVE_FP32_REFINED, 4)])
+def test_results_alone_equal_results_in_the_mix(prec, threads):
     probs = requests()
     ref = [solo(p, prec) for p in probs]
     budget = int(sum(z["device_bytes"] for _, _, z in ref) * 0.5)    # forces queueing
-    with P.Server(hbm_budget=budget, max_slots=6, precision=prec,
+    with P.Server(hbm_budget=budget, max_slots=6, precision=prec, setup_threads=threads,
                   tol=1e-13 if prec == P.SOLVE_FP64 else 1e-11) as srv:
         tickets = []
         # staggered arrivals from another thread while earlier requests run
@@ -54,12 +54,16 @@ def test_results_alone_equal_results_in_the_mix(prec):
         th = threading.Thread(target=feed)
         th.start()
         th.join()
+        admits = []
         for t, (q0, u0, _) in zip(tickets, ref):
             r, info, q, u = srv.result(t)
             assert r["converged"], r
             tol = 1e-10 if prec == P.SOLVE_FP64 else 1e-8
             assert rel_l2(u, u0) < tol and rel_l2(q, q0) < tol
             assert info["t_submit"] <= info["t_admit"] <= info["t_done"]
+            admits.append(info["t_admit"])
+        # admission is first come, first served, however many set-up threads classify ahead
+        assert all(a <= b for a, b in zip(admits, admits[1:])), admits
         st = srv.stats()
         assert st["completed"] == len(probs) and st["failed"] == 0
         assert st["peak_bytes"] <= budget and st["max_active"] <= 6

@@ -531,7 +531,7 @@ void build_layout(BatchEngine* b) {
         q.s64.far_gap = c->tabs.far_gap64();
         q.s64.yukawa = 0;
         q.s64.kq = q.s64.yk = 0.0;
-        q.s64.kl = q.s64.ykl = 0.f;
+        q.s64.yl = YukawaLattice{};
         fill(q.s32, c->tabs.near32, c->tabs.full32, c->S.ps.xf, c->S.ps.yf, c->S.ps.zf);
         q.s32.w = (const float*)c->w.p;
         q.s32.tab_r = std::min(c->tabs.tab_r32, kLdsRadius32);
@@ -540,8 +540,7 @@ void build_layout(BatchEngine* b) {
         q.s32.yukawa = c->tabs.yukawa32 ? 1 : 0;
         q.s32.kq = (float)(c->tabs.kappa / kQuant);
         q.s32.yk = (float)(-c->tabs.kappa * 1.4426950408889634 / kQuant);
-        q.s32.kl = (float)c->tabs.kappa;
-        q.s32.ykl = (float)(-c->tabs.kappa * 1.4426950408889634);
+        q.s32.yl = yukawa_lattice(c->tabs.kappa);
     }
     b->nslices_total = (int)sl.size();
     b->nitems = (int)it.size();

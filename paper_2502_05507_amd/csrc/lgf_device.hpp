@@ -199,25 +199,45 @@ __device__ __forceinline__ Real far_field_yukawa(Real X, Real Y, Real Z, Real kq
 }
 
 // The same sigma > 0 form from the lattice offset (FP32), through r2, Z and m as in
-// far_field_q2_lattice: with x4 = 4 e2/|n|^4 = 1 + 2 zeta - 3 zeta^2 - mu^2, the bracket is
-//   T2 |n|^2 = P0(u) + x4 P1(u),  P0 = (1 + u)/4 + u^3/24,  P1 = -5(1 + u)/16 - u^2/8 - u^3/48,
-// evaluated as one cubic in u, A (1 + u) + B u^2 + C u^3 with A = 1/4 - 5 x4/16, B = -x4/8
-// and C = 1/24 - x4/48 (each times log2(e), for the exponent).
-// kl = kappa, ykl = -kappa log2(e) (lattice units).
-__device__ __forceinline__ float far_field_yukawa_lattice(float r2, float Z, float m, float kl, float ykl) {
-    constexpr float kLog2C = -3.6514961294723187f;   // log2(1 / (4 pi))
-    constexpr double kL = 1.4426950408889634;         // log2(e)
+// far_field_q2_lattice: with x4 = 4 e2/|n|^4 = 1 + 2 zeta - 3 zeta^2 - mu^2,
+//   T2 |n|^2 = A (1 + u) + B u^2 + C u^3,  A = 1/4 - 5 x4/16, B = -x4/8, C = 1/24 - x4/48.
+// Since u^2 / |n|^2 = kappa^2 and u^3 / |n|^2 = kappa^3 |n|, the exponent of
+// G = 2^arg / |n| is, with L = log2(e),
+//   arg = log2(1/(4 pi)) - L u + L T2 = P + |n| Q + rho L A (1 + u),
+//   P = log2(1/(4 pi)) + L kappa^2 B,   Q = -L kappa + L kappa^3 C,
+// P and Q linear in x4 with per-launch coefficients (YukawaLattice): two fused
+// multiply-adds fewer per value than the cubic in u.  rho r2 = 1 up to the rounding of the
+// rsqrt estimate, which touches the two folded terms (at most 1e-3 of the exponent's
+// correction) at 1e-7.
+struct YukawaLattice {
+    float kl = 0.f;           // kappa (lattice units)
+    float p0 = 0.f, p1 = 0.f; // P = p0 + p1 x4
+    float q0 = 0.f, q1 = 0.f; // Q = q0 + q1 x4
+};
+inline YukawaLattice yukawa_lattice(double kappa) {
+    constexpr double L = 1.4426950408889634;
+    const double k2 = kappa * kappa, k3 = k2 * kappa;
+    YukawaLattice y;
+    y.kl = (float)kappa;
+    y.p0 = (float)-3.6514961294723187;   // log2(1 / (4 pi))
+    y.p1 = (float)(-L * k2 / 8.0);
+    y.q0 = (float)(-L * kappa + L * k3 / 24.0);
+    y.q1 = (float)(-L * k3 / 48.0);
+    return y;
+}
+__device__ __forceinline__ float far_field_yukawa_lattice(float r2, float Z, float m, const YukawaLattice& y) {
+    constexpr double kL = 1.4426950408889634;   // log2(e)
     const float rinv = __builtin_amdgcn_rsqf(r2);
     const float rho = rinv * rinv;
     const float zeta = Z * rho, mu = m * rho;
     const float x4 = fmaf(-mu, mu, fmaf(zeta, fmaf(zeta, -3.0f, 2.0f), 1.0f));
     const float rq = r2 * rinv;
-    const float u = rq * kl;
-    const float A = fmaf(x4, float(-0.3125 * kL), float(0.25 * kL));
-    const float B = float(-0.125 * kL) * x4;
-    const float C = fmaf(x4, float(-kL / 48.0), float(kL / 24.0));
-    const float br = fmaf(u, fmaf(u, fmaf(u, C, B), A), A);
-    return __builtin_amdgcn_exp2f(fmaf(rho, br, fmaf(rq, ykl, kLog2C))) * rinv;
+    const float P = fmaf(x4, y.p1, y.p0);
+    const float Q = fmaf(x4, y.q1, y.q0);
+    const float AL = fmaf(x4, float(-0.3125 * kL), float(0.25 * kL));
+    const float onepu = fmaf(rq, y.kl, 1.0f);
+    const float arg = fmaf(AL * rho, onepu, fmaf(rq, Q, P));
+    return __builtin_amdgcn_exp2f(arg) * rinv;
 }
 
 template <typename Real>
@@ -395,7 +415,7 @@ struct SumArgs {
     int far_gap;                      // smallest far-block gap (lattice units)
     int yukawa;                       // the far field is the sigma > 0 form (kq, yk)
     Real kq, yk;
-    float kl, ykl;                    // the same in lattice units (FP32 far-field blocks)
+    YukawaLattice yl;                 // the same in lattice units (FP32 far-field blocks)
     double* part;
     int64_t ldp;
 };
@@ -506,7 +526,7 @@ __device__ __forceinline__ void far2_block(const SumArgs<Real>& a, uint32_t txy,
             far_pairs4(txy, st.xy[u0], st.xy[u0 + 1], st.xy[u0 + 2], st.xy[u0 + 3], Z, r2, m);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const Real G = YUK ? far_field_yukawa_lattice(r2[k], Z[k], m[k], a.kl, a.ykl)
+                const Real G = YUK ? far_field_yukawa_lattice(r2[k], Z[k], m[k], a.yl)
                                    : far_field_q2_lattice(r2[k], Z[k], m[k]);
 #pragma unroll
                 for (int r = 0; r < NR; ++r) acc[r].add(G * st.w[r][u0 + k]);

@@ -167,7 +167,7 @@ __global__ __launch_bounds__(THREADS) void lgf_sum_kernel(const SumArgs<Real> a,
 template <typename Real>
 __global__ void lgf_eval_kernel(const int32_t* __restrict__ off, int64_t count, const Real* __restrict__ tab,
                                 int tab_r, int full_r, int far_ok, int yukawa, Real kq, Real yk,
-                                double* __restrict__ out) {
+                                const YukawaLattice yl, double* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     const int64_t a = abs(off[3 * i]), b = abs(off[3 * i + 1]), c = abs(off[3 * i + 2]);
@@ -177,8 +177,7 @@ __global__ void lgf_eval_kernel(const int32_t* __restrict__ off, int64_t count, 
         if constexpr (sizeof(Real) == 4) {
             // the forms of the sum's far blocks (lattice units)
             const float x2 = float(a * a), y2 = float(b * b), z2 = float(c * c);
-            out[i] = yukawa ? (double)far_field_yukawa_lattice(x2 + y2 + z2, z2, y2 - x2, (float)kq * kQuant,
-                                                                (float)yk * kQuant)
+            out[i] = yukawa ? (double)far_field_yukawa_lattice(x2 + y2 + z2, z2, y2 - x2, yl)
                             : (double)(kFarScale32 * far_field_q2_lattice(x2 + y2 + z2, z2, y2 - x2));
         } else if (yukawa) {
             out[i] = (double)far_field_yukawa<Real>(X * X, Y * Y, Z * Z, kq, yk);
@@ -279,7 +278,7 @@ __device__ __forceinline__ void mfma_far2_block(const SumArgs<float>& a, const u
         far_pairs4v(txy, sxy, Z, r2, m);
 #pragma unroll
         for (int j = 0; j < kTiles; ++j)
-            G[j] = YUK ? far_field_yukawa_lattice(r2[j], Z[j], m[j], a.kl, a.ykl) : far_field_q2_lattice(r2[j], Z[j], m[j]);
+            G[j] = YUK ? far_field_yukawa_lattice(r2[j], Z[j], m[j], a.yl) : far_field_q2_lattice(r2[j], Z[j], m[j]);
         // sigma = 0: the lattice form's common factor kFarScale32 rides on the weights
         const float ws = YUK ? wb : wb * kFarScale32;
 #pragma unroll
@@ -593,8 +592,7 @@ void launch_all(const PointSet& T, const PointSet& S, const Real* w, int nrhs, c
     a.yukawa = fp32 && tabs.yukawa32 ? 1 : 0;
     a.kq = (Real)(tabs.kappa / kQuant);
     a.yk = (Real)(-tabs.kappa * 1.4426950408889634 / kQuant);
-    a.kl = (float)tabs.kappa;
-    a.ykl = (float)(-tabs.kappa * 1.4426950408889634);
+    a.yl = yukawa_lattice(tabs.kappa);
     a.ldp = (int64_t)plan.chunks * T.count;
     int r = 0;
     while (r < nrhs) {
@@ -731,11 +729,11 @@ void lgf_eval_launch(const int32_t* off, int64_t count, double* out, int prec, c
     const double kq = tabs.kappa / kQuant, yk = -tabs.kappa * 1.4426950408889634 / kQuant;
     if (prec == BAE_PREC_FP64)
         lgf_eval_kernel<double><<<blocks, 256, 0, st>>>(off, count, tabs.full64, tabs.tab_r64, tabs.full_r,
-                                                        tabs.far64() ? 1 : 0, 0, kq, yk, out);
+                                                        tabs.far64() ? 1 : 0, 0, kq, yk, YukawaLattice{}, out);
     else
         lgf_eval_kernel<float><<<blocks, 256, 0, st>>>(off, count, tabs.full32, tabs.tab_r32, tabs.full_r,
                                                        tabs.far32() ? 1 : 0, tabs.yukawa32 ? 1 : 0, (float)kq,
-                                                       (float)yk, out);
+                                                       (float)yk, yukawa_lattice(tabs.kappa), out);
     BAE_HIP_CHECK(hipGetLastError());
 }
 

@@ -235,8 +235,9 @@ __device__ __forceinline__ float far_field_yukawa_lattice(float r2, float Z, flo
     const float P = fmaf(x4, y.p1, y.p0);
     const float Q = fmaf(x4, y.q1, y.q0);
     const float AL = fmaf(x4, float(-0.3125 * kL), float(0.25 * kL));
-    const float onepu = fmaf(rq, y.kl, 1.0f);
-    const float arg = fmaf(AL * rho, onepu, fmaf(rq, Q, P));
+    // rho (1 + u) = rho + kappa rinv (rho |n| = rinv)
+    const float s1 = fmaf(rinv, y.kl, rho);
+    const float arg = fmaf(AL, s1, fmaf(rq, Q, P));
     return __builtin_amdgcn_exp2f(arg) * rinv;
 }
 

@@ -408,10 +408,15 @@ __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real
         const int span = max(max(max(bb[3] - lx, hx - bb[0]), max(bb[4] - ly, hy - bb[1])),
                              max(bb[5] - lz, hz - bb[2]));
         const int cls = block_class(gap, span, a.tab_r, a.far_ok != 0, sizeof(Real) == 4, a.far_gap);
-        V blk[kTiles];
+        // FP32: the block's own sums, folded below; FP64: the running sums themselves (no
+        // compensation to apply, and 32 registers left for table reads in flight)
+        V blkz[kTiles];
+        if constexpr (sizeof(Real) == 4) {
 #pragma unroll
-        for (int j = 0; j < kTiles; ++j)
-            for (int v = 0; v < 4; ++v) blk[j][v] = Real(0);
+            for (int j = 0; j < kTiles; ++j)
+                for (int v = 0; v < 4; ++v) blkz[j][v] = Real(0);
+        }
+        V (&blk)[kTiles] = *(sizeof(Real) == 8 ? &acc : &blkz);
         if constexpr (sizeof(Real) == 4) {
             if (cls == kClassFar2) {
                 if (a.yukawa) mfma_far2_block<true>(a, txy, tzl, sb, row, kq, blk);
@@ -501,20 +506,18 @@ __device__ __forceinline__ void mfma_tile(const SumArgs<Real>& a, const Lds<Real
             for (int j = 0; j < kTiles; ++j) blk[j] = MfmaAcc<Real>::mma(G[j], wb, blk[j]);
         }
         }
-        // fold the block's sums into the running accumulators: compensated (Kahan) for FP32,
+        // FP32: fold the block's sums into the running accumulators, compensated (Kahan):
         // 4 VALU instructions per accumulator element (Neumaier's branch-free form takes 8)
+        if constexpr (sizeof(Real) == 4) {
 #pragma unroll
-        for (int j = 0; j < kTiles; ++j)
-            for (int v = 0; v < 4; ++v) {
-                if constexpr (sizeof(Real) == 4) {
+            for (int j = 0; j < kTiles; ++j)
+                for (int v = 0; v < 4; ++v) {
                     const Real y = blk[j][v] - comp[j][v];
                     const Real t = acc[j][v] + y;
                     comp[j][v] = (t - acc[j][v]) - y;
                     acc[j][v] = t;
-                } else {
-                    acc[j][v] += blk[j][v];
                 }
-            }
+        }
     }
     // element v of lane (kq, row): D[i][row], i = 4 kq + v (f32) or kq + 4 v (f64)
 #pragma unroll

@@ -72,10 +72,10 @@ def kernel_hash(files=("paper_2502_05507_amd/csrc/lgf_sum.hip", "paper_2502_0550
 # were taken on (their hash): HBM bytes per launch (FETCH_SIZE x f + WRITE_SIZE x w, the
 # factors calibrated on copies of known size), VALU-issue and matrix-core-busy shares.
 MEASURED = {
-    "lgf_sum_mfma_helmholtz_star_257": {"sources_sha256_16": "8084561e04eb60b1",
-                                        "bytes": (1.3455e7 * 2.0 + 1.0693e6 * 1.0) * 1024,
-                                        "valu_issue": 0.799, "valu_busy": 0.854, "mfma_busy": 0.249,
-                                        "l2_hit": 0.692},
+    "lgf_sum_mfma_helmholtz_star_257": {"sources_sha256_16": "211868e5dbd39cd9",
+                                        "bytes": (1.3422e7 * 2.0 + 1.0688e6 * 1.0) * 1024,
+                                        "valu_issue": 0.765, "valu_busy": 0.823, "mfma_busy": 0.264,
+                                        "l2_hit": 0.697},
 }
 
 

@@ -384,7 +384,8 @@ class _EntryLGF:
 def test_largest_lattice_offsets_two_balls():
     """Two small balls at the two ends of a 2049-node axis (a sampled level set): offsets
     up to 2046, lattice coordinates up to 2048, the limit of the FP32 path's binary16
-    differences.  Double layer against the oracle's entry-by-entry LGF."""
+    differences and of its matrix-core offset forms (16 right-hand sides: the far blocks of
+    the blocked kernel).  Double layer against the oracle's entry-by-entry LGF."""
     torch = torch_mod()
     n, h = (2049, 11, 11), 1.0 / 64
     idx = np.indices(n).reshape(3, -1).T.astype(float)
@@ -394,21 +395,22 @@ def test_largest_lattice_offsets_two_balls():
     assert g.max_offset() == 2046
     T = operators.gamma_targets(g)
     D = operators.dense_double_layer(g, _EntryLGF(), T)
-    q = np.random.default_rng(21).standard_normal((2, len(g.gamma_minus)))
+    nr = 16
+    q = np.random.default_rng(21).standard_normal((nr, len(g.gamma_minus)))
     ref = q @ D.T
-    with P.Context(n, h, (0.0, 0.0, 0.0), 0.0, "sampled", phi=phi, max_rhs=2) as ctx:
+    with P.Context(n, h, (0.0, 0.0, 0.0), 0.0, "sampled", phi=phi, max_rhs=nr) as ctx:
         z = ctx.sizes
         assert (z["n_gamma_plus"], z["n_gamma_minus"], z["n_ext"], z["max_offset"]) == \
             (len(g.gamma_plus), len(g.gamma_minus), len(g.ext), 2046)
         assert ctx.sum_stats(P.PREC_FP32)["far_q2"] > 0      # the binary16 far field runs
         qd = torch.from_numpy(q).to(device())
-        v = torch.empty((2, len(T)), dtype=torch.float64, device=device())
+        v = torch.empty((nr, len(T)), dtype=torch.float64, device=device())
         # the FFT convolution runs on a box 2043 nodes long: transform length 4096 along x
         for prec, tol in ((P.PREC_FP64, 1e-10), (P.PREC_FP32, 2e-5), (P.PREC_FFT, 1e-10)):
             ctx.apply_double_layer(qd, v, prec)
             torch.cuda.synchronize()
             out = v.cpu().numpy()
-            for rr in range(2):
+            for rr in range(nr):
                 assert rel_l2(out[rr], ref[rr]) < tol, (prec, rr, rel_l2(out[rr], ref[rr]))
         assert ctx.get_sizes()["conv_fft"][0] >= 2 * ctx.get_sizes()["conv_box"][0] - 1 > 4000
         # the box particular solution on this long, thin box (a 2047-point sine transform,

@@ -770,7 +770,7 @@ def main():
         cpu_baseline_worker(args.cpu_baseline_worker, args.cpu_rows, args.cpu_rhs)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); this build has no multi-GPU path",
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the library has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
 

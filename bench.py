@@ -280,6 +280,52 @@ def cpu_baseline(workload, nrows, nrhs_all):
             "single_core_value": r["single"], "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
+def _oracle_solve_batch_problem(i):
+    """Worker: the oracle's solve (its literal sums, its own GMRES) of batch problem i."""
+    import workloads as W
+    from oracle import bae as obae
+    t0 = time.perf_counter()
+    r = obae.solve(W.batch_problem(i))
+    return {"i": i, "seconds": time.perf_counter() - t0, "iterations": len(r["history"]),
+            "converged": bool(r["converged"])}
+
+
+def oracle_batch_worker(indices):
+    """Runs in a child process that never touches the GPU: the oracle's solves of the given
+    batch problems, one per process over the host's cores.  Prints one JSON object."""
+    import multiprocessing as mp
+    cores = host_cores()
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(min(cores, len(indices))) as pool:
+        res = pool.map(_oracle_solve_batch_problem, indices, chunksize=1)
+    print(json.dumps({"wall_s": time.perf_counter() - t0, "cores": cores, "solves": res}))
+
+
+def oracle_batch_sample(probs, results, count=16):
+    """The oracle's solves of a seeded sample of the batch, the first `count` problems of the
+    stream (one per host core; the largest takes the oracle about a minute), timed in a child
+    process; with the batch's own pair and iteration counts, an estimate of the oracle's time
+    for the whole batch."""
+    pick = list(range(min(count, len(probs))))
+    idx = [int(probs[k][0].name[len("batch"):]) for k in pick]
+    out = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-batch-worker",
+                          ",".join(str(i) for i in idx)], capture_output=True, text=True, timeout=900)
+    if out.returncode != 0:
+        raise RuntimeError(f"oracle batch worker failed: {out.stderr[-2000:]}")
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    work = lambda k, it: probs[k][1].sizes["n_targets"] * probs[k][1].sizes["n_sources"] * (it + 2)
+    sample_work = sum(work(k, s["iterations"]) for k, s in zip(pick, r["solves"]))
+    cpu_s = sum(s["seconds"] for s in r["solves"])
+    batch_work = sum(work(k, res["iterations"]) for k, res in enumerate(results))
+    return {"sample": f"the first {len(idx)} problems of the seeded stream",
+            "problems": idx, "solves_per_s_all_cores": len(idx) / r["wall_s"], "wall_s": r["wall_s"],
+            "cores": r["cores"], "cpu_s_per_solve": cpu_s / len(idx),
+            "converged": sum(s["converged"] for s in r["solves"]),
+            "batch_estimate_all_cores_s": batch_work * cpu_s / sample_work / r["cores"],
+            "estimate": "(pairs per matvec) x (GMRES iterations + 2) over the batch, at the sample's oracle "
+                        "seconds per pair-matvec, divided over the cores", "cpu_model": cpu_model()}
+
+
 # ----------------------------------------------------------------------------- headline (257^3 star)
 def headline(args, torch, P, W):
     dev = torch.device("cuda:0")
@@ -479,7 +525,17 @@ def ellipsoid(args, torch, P, W, steps=None, warmup=None, extra=False):
            "vs_baseline": None, "dtype": "f32 LGF sum + f64 refinement", "data": "synthetic",
            "config": body.pop("config"), **body}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline("poisson_ellipsoid", args.cpu_rows, args.cpu_rhs)
+        cb = cpu_baseline("poisson_ellipsoid", args.cpu_rows, args.cpu_rhs)
+        # a full oracle solve here takes about 10^11 pair evaluations: derived from the measured
+        # matvec rate, not run
+        n_mv = out["fp64_plain"]["iterations"] + 2
+        cb["oracle_solve_estimate"] = {"matvecs": n_mv, "seconds_one_core": n_mv * pairs_mv / cb["single_core_value"],
+                                       "seconds_all_cores": n_mv * pairs_mv / cb["value"],
+                                       "solves_per_s_all_cores": cb["value"] / (n_mv * pairs_mv),
+                                       "derived": "GMRES iterations of the FP64 GPU solve + 2 (true residual, "
+                                                  "u_gamma) literal matvecs at the rates measured above; the "
+                                                  "volume potential of f is not included"}
+        out["cpu_baseline"] = cb
     return out
 
 
@@ -602,6 +658,7 @@ def batch(args, torch, P, W):
     ctxs = [c for _, c in probs]
     pairs = sum(c.sizes["n_targets"] * c.sizes["n_sources"] for c in ctxs)
     out = {"workload": f"batch_{len(ctxs)}", "setup_s": t_setup, "pairs_per_matvec_sum": pairs}
+    res64 = None
     with P.Batch(ctxs) as b:
         out["autotune"] = b.autotune(P.PREC_FP32)
         for name, prec in (("fp64", P.SOLVE_FP64), ("fp32_refined", P.SOLVE_FP32_REFINED)):
@@ -609,11 +666,16 @@ def batch(args, torch, P, W):
             s0 = time.perf_counter()
             res = b.solve(prec, tol=1e-10)
             dt = time.perf_counter() - s0
+            if prec == P.SOLVE_FP64:
+                res64 = res
             out[name] = {"wall_s": dt, "solves_per_s": len(ctxs) / dt,
                          "converged": sum(r["converged"] for r in res),
                          "max_iterations": max(r["iterations"] for r in res),
                          "lockstep_matvecs": res[0]["matvecs_fp32"] + res[0]["matvecs_fp64"]}
             log(f"batch {name}: {dt:.2f}s for {len(ctxs)} solves")
+    if not args.no_cpu_baseline:
+        out["oracle_sample"] = oracle_batch_sample(probs, res64)
+        log(f"batch oracle sample: {out['oracle_sample']['solves_per_s_all_cores']:.3f} solves/s")
     for c in ctxs:
         c.close()
     return out
@@ -759,6 +821,7 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=2000, help="target rows of the CPU oracle sample")
     ap.add_argument("--cpu-rhs", type=int, default=1, help="densities of the all-core sample (0: one per core)")
     ap.add_argument("--cpu-baseline-worker", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--oracle-batch-worker", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--requests", type=int, default=500)
     ap.add_argument("--slots", type=int, default=64)
@@ -768,6 +831,9 @@ def main():
     args = ap.parse_args()
     if args.cpu_baseline_worker:        # child process of cpu_baseline: CPU only
         cpu_baseline_worker(args.cpu_baseline_worker, args.cpu_rows, args.cpu_rhs)
+        return
+    if args.oracle_batch_worker:        # child process of oracle_batch_sample: CPU only
+        oracle_batch_worker([int(v) for v in args.oracle_batch_worker.split(",")])
         return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the library has no multi-GPU path",

@@ -76,6 +76,9 @@ MEASURED = {
                                         "bytes": (1.3422e7 * 2.0 + 1.0688e6 * 1.0) * 1024,
                                         "valu_issue": 0.765, "valu_busy": 0.823, "mfma_busy": 0.264,
                                         "l2_hit": 0.697},
+    "lgf_sum_poisson_ellipsoid_129": {"sources_sha256_16": "211868e5dbd39cd9",
+                                      "bytes": (12283 * 2.0 + 18519 * 1.0) * 1024,
+                                      "valu_issue": 0.872},
 }
 
 

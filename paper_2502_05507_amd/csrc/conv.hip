@@ -24,6 +24,8 @@ namespace {
 using namespace fftdev;
 
 constexpr int kConvThreads = kFftThreads;
+constexpr int kMaxLinesPerBlock = 32;   // lines_for's cap (packed real rows included)
+constexpr int kIt = kFftPoints / kConvThreads;   // elements per thread of a block's lines, at most
 
 __device__ __forceinline__ int64_t idx3(int i, int j, int k, int n1, int n2) { return ((int64_t)i * n1 + j) * n2 + k; }
 
@@ -34,6 +36,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_z_fwd(const double* __restr
                                                           int M1, double2* __restrict__ C, const FftDev p, int P,
                                                           const int32_t* __restrict__ skip) {
     extern __shared__ double2 lds[];
+    __shared__ int64_t cbase[kMaxLinesPerBlock];   // start of row l0 + pl's half spectrum in C (-1: none)
     if (skip && *skip) return;
     const int M = p.M, nfft = P / 2;
     double2* A = lds;
@@ -41,27 +44,50 @@ __global__ __launch_bounds__(kConvThreads) void conv_z_fwd(const double* __restr
     load_roots(p, tw);
     double* Ad = (double*)A;
     const int64_t l0 = (int64_t)blockIdx.x * P, nl = (int64_t)e0 * e1;
+    const int H = M / 2 + 1;
+    if ((int)threadIdx.x < P) {
+        const int64_t l = l0 + threadIdx.x;
+        cbase[threadIdx.x] = l < nl ? idx3((int)(l / e1), (int)(l % e1), 0, M1, H) : -1;
+    }
     for (int e = threadIdx.x; e < nfft * M; e += blockDim.x) A[e] = make_double2(0.0, 0.0);
     __syncthreads();
-    for (int e = threadIdx.x; e < P * e2; e += blockDim.x) {
-        const int pl = e / e2, k = e - pl * e2;
-        const int64_t l = l0 + pl;
-        if (l < nl) Ad[2 * ((int64_t)(pl >> 1) * M + k) + (pl & 1)] = R[l * e2 + k];
+    const float re2 = 1.0f / (float)e2, rH = 1.0f / (float)H;
+    // every load of the thread issued before the first LDS write (one memory latency, not eight)
+    {
+        double v[kIt];
+        int at[kIt];
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int e = threadIdx.x + it * kConvThreads;
+            at[it] = -1;
+            if (e >= P * e2) continue;
+            const int pl = fdiv(e, e2, re2), k = e - pl * e2;
+            if (cbase[pl] < 0) continue;
+            v[it] = R[(l0 + pl) * e2 + k];
+            at[it] = 2 * ((pl >> 1) * M + k) + (pl & 1);
+        }
+#pragma unroll
+        for (int it = 0; it < kIt; ++it)
+            if (at[it] >= 0) Ad[at[it]] = v[it];
+        // P e2 can pass kFftPoints by up to P / 2 (e2 <= (M + 1) / 2)
+        for (int e = threadIdx.x + kIt * kConvThreads; e < P * e2; e += kConvThreads) {
+            const int pl = fdiv(e, e2, re2), k = e - pl * e2;
+            if (cbase[pl] >= 0) Ad[2 * ((pl >> 1) * M + k) + (pl & 1)] = R[(l0 + pl) * e2 + k];
+        }
     }
     __syncthreads();
     fft_lds(A, nfft, p, tw, false);
     const double2* Z = A;
-    const int H = M / 2 + 1;
     for (int e = threadIdx.x; e < P * H; e += blockDim.x) {
-        const int pl = e / H, k = e - pl * H;
-        const int64_t l = l0 + pl;
-        if (l >= nl) continue;
+        const int pl = fdiv(e, H, rH), k = e - pl * H;
+        const int64_t cb = cbase[pl];
+        if (cb < 0) continue;
         const double2* z = Z + (int64_t)(pl >> 1) * M;
         const double2 a = z[k], b = z[k == 0 ? 0 : M - k];
         // b is conjugated: conj(b) = (b.x, -b.y)
         const double2 X = (pl & 1) ? make_double2(0.5 * (a.y + b.y), -0.5 * (a.x - b.x))
                                    : make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
-        C[idx3((int)(l / e1), (int)(l % e1), 0, M1, H) + k] = X;
+        C[cb + k] = X;
     }
 }
 
@@ -76,44 +102,69 @@ __global__ __launch_bounds__(kConvThreads) void conv_lines(double2* __restrict__
                                                           int M1, int L2, int H1, int H2,
                                                           const int32_t* __restrict__ skip) {
     extern __shared__ double2 lds[];
+    // per line of the block: its first element in C (-1: past the last line) and, in the x
+    // pass, its row of the kernel's transform; element n is then lbase + n sline
+    __shared__ int64_t lbase[kMaxLinesPerBlock];
+    __shared__ int32_t grow[kMaxLinesPerBlock];
     if (skip && *skip) return;
     const int M = p.M;
     double2* A = lds;
     double2* tw = A + (int64_t)P * M;
     load_roots(p, tw);
     const int64_t l0 = (int64_t)blockIdx.x * P;
+    if ((int)threadIdx.x < P) {
+        const int64_t l = l0 + threadIdx.x;
+        lbase[threadIdx.x] = l < nlines ? (l / lin) * sout + (l % lin) : -1;
+        if (mode == 1) {
+            // line l = j L2 + k of the x pass on half spectra (L2 = M2/2 + 1, k <= M2/2); the
+            // transform is even in every index
+            const int j = (int)(l / L2), k = (int)(l % L2);
+            grow[threadIdx.x] = min(j, M1 - j) * H2 + k;
+        }
+    }
+    __syncthreads();
+    const float rP = 1.0f / (float)P, rM = 1.0f / (float)M;
     const int nl = mode == 2 ? M : nload;
-    for (int e = threadIdx.x; e < P * M; e += blockDim.x) {
-        const int n = e / P, pl = e - n * P;
-        const int64_t l = l0 + pl;
-        double2 v = make_double2(0.0, 0.0);
-        if (n < nl && l < nlines) v = C[(l / lin) * sout + (l % lin) + n * sline];
-        A[(int64_t)pl * M + n] = v;
+    // every load of the thread issued before the first LDS write (one memory latency, not eight)
+    {
+        double2 v[kIt];
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int e = threadIdx.x + it * kConvThreads;
+            v[it] = make_double2(0.0, 0.0);
+            if (e >= P * M) continue;
+            const int n = fdiv(e, P, rP), pl = e - n * P;
+            const int64_t lb = lbase[pl];
+            if (n < nl && lb >= 0) v[it] = C[lb + n * sline];
+        }
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int e = threadIdx.x + it * kConvThreads;
+            if (e >= P * M) continue;
+            const int n = fdiv(e, P, rP), pl = e - n * P;
+            A[pl * M + n] = v[it];
+        }
     }
     __syncthreads();
     double2* Z = A;
     // mode 1 transforms twice (forward, the product, inverse) through one copy of the FFT code
+    const int64_t gplane = (int64_t)H1 * H2;
     for (int pass = 0; pass < (mode == 1 ? 2 : 1); ++pass) {
         fft_lds(Z, P, p, tw, mode == 2 || pass == 1);
         if (mode != 1 || pass == 1) break;
         for (int e = threadIdx.x; e < P * M; e += blockDim.x) {
-            const int pl = e / M, n = e - pl * M;
-            const int64_t l = l0 + pl;
-            if (l >= nlines) continue;
-            // line l = j L2 + k of the x pass on half spectra (L2 = M2/2 + 1, k <= M2/2); the
-            // transform is even in every index
-            const int j = (int)(l / L2), k = (int)(l % L2);
-            const int a = min(n, M - n), b = min(j, M1 - j), c = k;
-            const double g = ghat[idx3(a, b, c, H1, H2)];
+            const int pl = fdiv(e, M, rM), n = e - pl * M;
+            if (lbase[pl] < 0) continue;
+            const double g = ghat[min(n, M - n) * gplane + grow[pl]];
             const double2 z = Z[(int64_t)pl * M + n];
             Z[(int64_t)pl * M + n] = make_double2(g * z.x, g * z.y);
         }
         __syncthreads();
     }
     for (int e = threadIdx.x; e < P * nstore; e += blockDim.x) {
-        const int n = e / P, pl = e - n * P;
-        const int64_t l = l0 + pl;
-        if (l < nlines) C[(l / lin) * sout + (l % lin) + n * sline] = Z[(int64_t)pl * M + n];
+        const int n = fdiv(e, P, rP), pl = e - n * P;
+        const int64_t lb = lbase[pl];
+        if (lb >= 0) C[lb + n * sline] = Z[(int64_t)pl * M + n];
     }
 }
 
@@ -124,6 +175,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_z_inv(const double2* __rest
                                                           int M1, double* __restrict__ R, const FftDev p, int P,
                                                           double scale, const int32_t* __restrict__ skip) {
     extern __shared__ double2 lds[];
+    __shared__ int64_t cbase[kMaxLinesPerBlock];   // start of row l0 + pl's half spectrum in C (-1: none)
     if (skip && *skip) return;
     const int M = p.M, nfft = P / 2;
     double2* A = lds;
@@ -131,29 +183,47 @@ __global__ __launch_bounds__(kConvThreads) void conv_z_inv(const double2* __rest
     load_roots(p, tw);
     const int64_t l0 = (int64_t)blockIdx.x * P, nl = (int64_t)e0 * e1;
     const int H = M / 2 + 1;
-    for (int e = threadIdx.x; e < nfft * M; e += blockDim.x) {
-        const int c = e / M, k = e - c * M;
-        const bool mirror = k >= H;
-        const int kk = mirror ? M - k : k;
-        const int64_t la = l0 + 2 * c, lb = la + 1;
-        double2 xa = make_double2(0.0, 0.0), xb = make_double2(0.0, 0.0);
-        if (la < nl) xa = C[idx3((int)(la / e1), (int)(la % e1), 0, M1, H) + kk];
-        if (lb < nl) xb = C[idx3((int)(lb / e1), (int)(lb % e1), 0, M1, H) + kk];
-        if (mirror) {
-            xa.y = -xa.y;
-            xb.y = -xb.y;
+    if ((int)threadIdx.x < P) {
+        const int64_t l = l0 + threadIdx.x;
+        cbase[threadIdx.x] = l < nl ? idx3((int)(l / e1), (int)(l % e1), 0, M1, H) : -1;
+    }
+    __syncthreads();
+    const float rM = 1.0f / (float)M, re2 = 1.0f / (float)e2;
+    // every load of the thread issued before the first LDS write (one memory latency, not four)
+    {
+        double2 xa[kIt], xb[kIt];   // nfft M <= kFftPoints
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int e = threadIdx.x + it * kConvThreads;
+            xa[it] = xb[it] = make_double2(0.0, 0.0);
+            if (e >= nfft * M) continue;
+            const int c = fdiv(e, M, rM), k = e - c * M;
+            const int kk = k >= H ? M - k : k;
+            const int64_t ba = cbase[2 * c], bb = cbase[2 * c + 1];
+            if (ba >= 0) xa[it] = C[ba + kk];
+            if (bb >= 0) xb[it] = C[bb + kk];
         }
-        A[e] = make_double2(xa.x - xb.y, xa.y + xb.x);
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int e = threadIdx.x + it * kConvThreads;
+            if (e >= nfft * M) continue;
+            const int c = fdiv(e, M, rM), k = e - c * M;
+            double2 a = xa[it], b = xb[it];
+            if (k >= H) {   // the conjugate mirror
+                a.y = -a.y;
+                b.y = -b.y;
+            }
+            A[e] = make_double2(a.x - b.y, a.y + b.x);
+        }
     }
     __syncthreads();
     fft_lds(A, nfft, p, tw, true);
     const double2* Z = A;
     for (int e = threadIdx.x; e < P * e2; e += blockDim.x) {
-        const int pl = e / e2, k = e - pl * e2;
-        const int64_t l = l0 + pl;
-        if (l >= nl) continue;
+        const int pl = fdiv(e, e2, re2), k = e - pl * e2;
+        if (cbase[pl] < 0) continue;
         const double2 z = Z[(int64_t)(pl >> 1) * M + k];
-        R[l * e2 + k] = scale * ((pl & 1) ? z.y : z.x);
+        R[(l0 + pl) * e2 + k] = scale * ((pl & 1) ? z.y : z.x);
     }
 }
 
@@ -210,7 +280,9 @@ __global__ void conv_fill(double* __restrict__ x, int64_t n, const int32_t* __re
 
 // Lines per block of a pass (fft_lines_per_block); packed real rows go two to a complex line.
 int lines_for(int M, bool packed) {
-    return packed ? 2 * fft_lines_per_block(M, 16) : fft_lines_per_block(M, 32);
+    const int P = packed ? 2 * fft_lines_per_block(M, 16) : fft_lines_per_block(M, 32);
+    if (P > kMaxLinesPerBlock) throw Error{BAE_ERR_ARG, "LGF convolution: too many lines per block"};
+    return P;
 }
 
 void set_lds_attr() {

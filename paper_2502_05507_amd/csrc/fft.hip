@@ -54,60 +54,88 @@ struct BoxEigen {
     double shift = 0.0;   // 6 + s
 };
 
+constexpr int kMaxDstLines = 32;   // lines_per_block's cap
+
 __global__ __launch_bounds__(kFftThreads) void dst_axis_kernel(double* __restrict__ x, int axis, int n0, int n1,
                                                                 int n2, int64_t nlines, int P, const FftDev p,
                                                                 double scale, const BoxEigen eig) {
     extern __shared__ double2 lds[];
+    // per line of the block: the position of its element 0 (-1: past the last line) and, in
+    // the pass that divides by the eigenvalues, the line's part of them (c0[i] + c1[j]);
+    // element n of the line is then at lbase + n stride
+    __shared__ int64_t lbase[kMaxDstLines];
+    __shared__ double esum[kMaxDstLines];
     const int N = axis == 0 ? n0 : axis == 1 ? n1 : n2;
+    const int64_t stride = axis == 2 ? 1 : axis == 1 ? (int64_t)n2 : (int64_t)n1 * n2;
     const int M = p.M;
     const int nfft = P / 2;
     double2* A = lds;
     double2* tw = A + (int64_t)nfft * M;
     load_roots(p, tw);
     const int64_t l0 = (int64_t)blockIdx.x * P;
+    if ((int)threadIdx.x < P) {
+        const int64_t l = l0 + threadIdx.x;
+        lbase[threadIdx.x] = l >= nlines ? -1 : line_at(axis, l, 0, n0, n1, n2);
+        if (eig.c0 && l < nlines) {   // axis 2: line l = i n1 + j
+            const int i = (int)(l / n1), j = (int)(l - (int64_t)i * n1);
+            esum[threadIdx.x] = eig.c0[i] + eig.c1[j];
+        }
+    }
     double* Ad = (double*)A;
     // the two end points of every odd extension are zero
     for (int e = threadIdx.x; e < nfft; e += blockDim.x) {
         A[(int64_t)e * M] = make_double2(0.0, 0.0);
         A[(int64_t)e * M + N + 1] = make_double2(0.0, 0.0);
     }
-    for (int e = threadIdx.x; e < P * N; e += blockDim.x) {
-        int pl, n;
+    __syncthreads();
+    const float rN = 1.0f / (float)N, rP = 1.0f / (float)P;
+    // element e of the block: line pl, position n (lines consecutive along the contiguous
+    // axis, interleaved along the others)
+    auto split = [=](int e) -> int2 {
         if (axis == 2) {
-            pl = e / N;
-            n = e - pl * N;
-        } else {
-            n = e / P;
-            pl = e - n * P;
+            const int pl = fdiv(e, N, rN);
+            return make_int2(pl, e - pl * N);
         }
-        const int64_t l = l0 + pl;
-        const double v = l < nlines ? x[line_at(axis, l, n, n0, n1, n2)] : 0.0;
-        const int64_t c = pl >> 1, comp = pl & 1;
-        Ad[2 * (c * M + n + 1) + comp] = v;
-        Ad[2 * (c * M + M - n - 1) + comp] = -v;
+        const int n = fdiv(e, P, rP);
+        return make_int2(e - n * P, n);
+    };
+    // every load of the thread issued before the first LDS write (P N < (P / 2) M <= kFftPoints:
+    // at most kIt per thread)
+    {
+        constexpr int kIt = kFftPoints / kFftThreads;
+        double v[kIt];
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int e = threadIdx.x + it * kFftThreads;
+            v[it] = 0.0;
+            if (e >= P * N) continue;
+            const int2 q = split(e);
+            const int64_t lb = lbase[q.x];
+            if (lb >= 0) v[it] = x[lb + q.y * stride];
+        }
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int e = threadIdx.x + it * kFftThreads;
+            if (e >= P * N) continue;
+            const int2 q = split(e);
+            const int c = q.x >> 1, comp = q.x & 1;
+            Ad[2 * (c * M + q.y + 1) + comp] = v[it];
+            Ad[2 * (c * M + M - q.y - 1) + comp] = -v[it];
+        }
     }
     __syncthreads();
     fft_lds(A, nfft, p, tw, false);
     const double2* Z = A;
     const double h = 0.5 * scale;
     for (int e = threadIdx.x; e < P * N; e += blockDim.x) {
-        int pl, n;
-        if (axis == 2) {
-            pl = e / N;
-            n = e - pl * N;
-        } else {
-            n = e / P;
-            pl = e - n * P;
-        }
-        const int64_t l = l0 + pl;
-        if (l >= nlines) continue;
+        const int2 q = split(e);
+        const int pl = q.x, n = q.y;
+        const int64_t lb = lbase[pl];
+        if (lb < 0) continue;
         const double2 z = Z[(int64_t)(pl >> 1) * M + n + 1];
         double v = (pl & 1) ? h * z.x : -h * z.y;
-        if (eig.c0) {   // axis 2: line l = i n1 + j, element n = k
-            const int i = (int)(l / n1), j = (int)(l - (int64_t)i * n1);
-            v /= eig.shift - (eig.c0[i] + eig.c1[j] + eig.c2[n]);
-        }
-        x[line_at(axis, l, n, n0, n1, n2)] = v;
+        if (eig.c0) v /= eig.shift - (esum[pl] + eig.c2[n]);   // axis 2: element n = k
+        x[lb + n * stride] = v;
     }
 }
 
@@ -217,7 +245,9 @@ FftDev fft_plan(int M, hipStream_t st) {
 }
 
 static int lines_per_block(int M) {
-    return 2 * fft_lines_per_block(M, 16);   // two real lines per complex FFT, at most 32
+    const int P = 2 * fft_lines_per_block(M, 16);   // two real lines per complex FFT, at most 32
+    if (P > kMaxDstLines) throw Error{BAE_ERR_ARG, "sine transform: too many lines per block"};
+    return P;
 }
 
 static void dst_axis_eig(double* x, int n0, int n1, int n2, int axis, double scale, const BoxEigen& eig,

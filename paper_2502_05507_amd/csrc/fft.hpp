@@ -12,7 +12,7 @@ namespace bae {
 
 constexpr int kFftMaxLen = 4608;     // longest transform: two LDS buffers of it fit the 160 KB
 constexpr int kFftMaxFactors = 16;
-constexpr size_t kFftLdsBytes = 160 * 1024;
+constexpr size_t kFftLdsBytes = 159 * 1024;   // dynamic LDS: 160 KB less 1 KB for the kernels' line tables
 
 // Complex lines of length M that one block transforms at once: c M <= 8192 points (the
 // in-place stages' register staging), and the c lines plus the root table (M more points,

@@ -123,7 +123,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_lines(double2* __restrict__
         }
     }
     __syncthreads();
-    const float rP = 1.0f / (float)P, rM = 1.0f / (float)M;
+    const float rP = 1.0f / (float)P;
     const int nl = mode == 2 ? M : nload;
     // every load of the thread issued before the first LDS write (one memory latency, not eight)
     {
@@ -152,8 +152,10 @@ __global__ __launch_bounds__(kConvThreads) void conv_lines(double2* __restrict__
     for (int pass = 0; pass < (mode == 1 ? 2 : 1); ++pass) {
         fft_lds(Z, P, p, tw, mode == 2 || pass == 1);
         if (mode != 1 || pass == 1) break;
+        // the block's lines are consecutive rows of the kernel's transform: the line index
+        // fastest, so that a wavefront reads runs of consecutive values of it
         for (int e = threadIdx.x; e < P * M; e += blockDim.x) {
-            const int pl = fdiv(e, M, rM), n = e - pl * M;
+            const int n = fdiv(e, P, rP), pl = e - n * P;
             if (lbase[pl] < 0) continue;
             const double g = ghat[min(n, M - n) * gplane + grow[pl]];
             const double2 z = Z[(int64_t)pl * M + n];

@@ -32,7 +32,8 @@ __device__ __forceinline__ int64_t idx3(int i, int j, int k, int n1, int n2) { r
 // Pass 1: forward z transforms of the real rows (i < e0, j < e1) of R [e0][e1][e2], zero-padded
 // to M2, two rows per complex FFT (Z = F(a + i b): F a = (Z_k + conj Z_{-k}) / 2,
 // F b = (Z_k - conj Z_{-k}) / 2i); the half spectrum k < H2 = M2/2 + 1 into C [e0][M1][H2].
-__global__ __launch_bounds__(kConvThreads) void conv_z_fwd(const double* __restrict__ R, int e0, int e1, int e2,
+template <int THREADS>
+__global__ __launch_bounds__(THREADS, 4) void conv_z_fwd(const double* __restrict__ R, int e0, int e1, int e2,
                                                           int M1, double2* __restrict__ C, const FftDev p, int P,
                                                           const int32_t* __restrict__ skip) {
     extern __shared__ double2 lds[];
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_z_fwd(const double* __restr
         int at[kIt];
 #pragma unroll
         for (int it = 0; it < kIt; ++it) {
-            const int e = threadIdx.x + it * kConvThreads;
+            const int e = threadIdx.x + it * THREADS;
             at[it] = -1;
             if (e >= P * e2) continue;
             const int pl = fdiv(e, e2, re2), k = e - pl * e2;
@@ -70,13 +71,13 @@ __global__ __launch_bounds__(kConvThreads) void conv_z_fwd(const double* __restr
         for (int it = 0; it < kIt; ++it)
             if (at[it] >= 0) Ad[at[it]] = v[it];
         // P e2 can pass kFftPoints by up to P / 2 (e2 <= (M + 1) / 2)
-        for (int e = threadIdx.x + kIt * kConvThreads; e < P * e2; e += kConvThreads) {
+        for (int e = threadIdx.x + kIt * THREADS; e < P * e2; e += THREADS) {
             const int pl = fdiv(e, e2, re2), k = e - pl * e2;
             if (cbase[pl] >= 0) Ad[2 * ((pl >> 1) * M + k) + (pl & 1)] = R[(l0 + pl) * e2 + k];
         }
     }
     __syncthreads();
-    fft_lds(A, nfft, p, tw, false);
+    fft_lds<THREADS>(A, nfft, p, tw, false);
     const double2* Z = A;
     for (int e = threadIdx.x; e < P * H; e += blockDim.x) {
         const int pl = fdiv(e, H, rH), k = e - pl * H;
@@ -96,7 +97,8 @@ __global__ __launch_bounds__(kConvThreads) void conv_z_fwd(const double* __restr
 // beyond), n < nstore stored; mode 1: forward, times the kernel's transform, inverse (the x
 // pass; n < nload loaded and stored); mode 2: inverse, all M loaded, n < nstore stored.
 // P consecutive lines (consecutive in memory) per block.
-__global__ __launch_bounds__(kConvThreads) void conv_lines(double2* __restrict__ C, int64_t nlines, int64_t lin,
+template <int THREADS>
+__global__ __launch_bounds__(THREADS, 4) void conv_lines(double2* __restrict__ C, int64_t nlines, int64_t lin,
                                                           int64_t sout, int64_t sline, int nload, int nstore, int mode,
                                                           const FftDev p, int P, const double* __restrict__ ghat,
                                                           int M1, int L2, int H1, int H2,
@@ -130,7 +132,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_lines(double2* __restrict__
         double2 v[kIt];
 #pragma unroll
         for (int it = 0; it < kIt; ++it) {
-            const int e = threadIdx.x + it * kConvThreads;
+            const int e = threadIdx.x + it * THREADS;
             v[it] = make_double2(0.0, 0.0);
             if (e >= P * M) continue;
             const int n = fdiv(e, P, rP), pl = e - n * P;
@@ -139,7 +141,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_lines(double2* __restrict__
         }
 #pragma unroll
         for (int it = 0; it < kIt; ++it) {
-            const int e = threadIdx.x + it * kConvThreads;
+            const int e = threadIdx.x + it * THREADS;
             if (e >= P * M) continue;
             const int n = fdiv(e, P, rP), pl = e - n * P;
             A[pl * M + n] = v[it];
@@ -150,7 +152,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_lines(double2* __restrict__
     // mode 1 transforms twice (forward, the product, inverse) through one copy of the FFT code
     const int64_t gplane = (int64_t)H1 * H2;
     for (int pass = 0; pass < (mode == 1 ? 2 : 1); ++pass) {
-        fft_lds(Z, P, p, tw, mode == 2 || pass == 1);
+        fft_lds<THREADS>(Z, P, p, tw, mode == 2 || pass == 1);
         if (mode != 1 || pass == 1) break;
         // the block's lines are consecutive rows of the kernel's transform: the line index
         // fastest, so that a wavefront reads runs of consecutive values of it
@@ -173,7 +175,8 @@ __global__ __launch_bounds__(kConvThreads) void conv_lines(double2* __restrict__
 // Last pass: inverse z transforms of the rows (i < e0, j < e1) of C (half spectra, the rest the
 // conjugate mirror X_k = conj X_{M-k}), two rows per complex FFT (the results are real:
 // F^-1(X_a + i X_b) = a + i b), n < e2 kept, times scale, into R.
-__global__ __launch_bounds__(kConvThreads) void conv_z_inv(const double2* __restrict__ C, int e0, int e1, int e2,
+template <int THREADS>
+__global__ __launch_bounds__(THREADS, 4) void conv_z_inv(const double2* __restrict__ C, int e0, int e1, int e2,
                                                           int M1, double* __restrict__ R, const FftDev p, int P,
                                                           double scale, const int32_t* __restrict__ skip) {
     extern __shared__ double2 lds[];
@@ -196,7 +199,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_z_inv(const double2* __rest
         double2 xa[kIt], xb[kIt];   // nfft M <= kFftPoints
 #pragma unroll
         for (int it = 0; it < kIt; ++it) {
-            const int e = threadIdx.x + it * kConvThreads;
+            const int e = threadIdx.x + it * THREADS;
             xa[it] = xb[it] = make_double2(0.0, 0.0);
             if (e >= nfft * M) continue;
             const int c = fdiv(e, M, rM), k = e - c * M;
@@ -207,7 +210,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_z_inv(const double2* __rest
         }
 #pragma unroll
         for (int it = 0; it < kIt; ++it) {
-            const int e = threadIdx.x + it * kConvThreads;
+            const int e = threadIdx.x + it * THREADS;
             if (e >= nfft * M) continue;
             const int c = fdiv(e, M, rM), k = e - c * M;
             double2 a = xa[it], b = xb[it];
@@ -219,7 +222,7 @@ __global__ __launch_bounds__(kConvThreads) void conv_z_inv(const double2* __rest
         }
     }
     __syncthreads();
-    fft_lds(A, nfft, p, tw, true);
+    fft_lds<THREADS>(A, nfft, p, tw, true);
     const double2* Z = A;
     for (int e = threadIdx.x; e < P * e2; e += blockDim.x) {
         const int pl = fdiv(e, e2, re2), k = e - pl * e2;
@@ -287,10 +290,26 @@ int lines_for(int M, bool packed) {
     return P;
 }
 
+// The line passes run 512-thread blocks of half the points and LDS, two to a compute unit, so
+// that one block's loads and stores overlap the other's LDS stages (a 1024-thread block at
+// 128 VGPRs holds a compute unit alone and runs its phases in series); lengths beyond 2048
+// keep the 1024-thread blocks.
+constexpr int kHalfThreads = kConvThreads / 2;
+constexpr size_t kHalfLdsBytes = kFftLdsBytes / 2;
+bool half_blocks(int M) { return M <= 2048; }
+int half_lines(int M, bool packed = false) {
+    const int by_points = kFftPointsPerThread * kHalfThreads / M;
+    const int by_lds = (int)(kHalfLdsBytes / (16 * (size_t)M)) - 1;
+    const int c = std::max(1, std::min(packed ? kMaxLinesPerBlock / 2 : kMaxLinesPerBlock, std::min(by_points, by_lds)));
+    return packed ? 2 * c : c;
+}
+
 void set_lds_attr() {
     static bool done = false;
     if (done) return;
-    for (const void* f : {(const void*)conv_z_fwd, (const void*)conv_lines, (const void*)conv_z_inv})
+    for (const void* f : {(const void*)conv_z_fwd<kConvThreads>, (const void*)conv_z_fwd<kHalfThreads>,
+                          (const void*)conv_lines<kConvThreads>, (const void*)conv_lines<kHalfThreads>,
+                          (const void*)conv_z_inv<kConvThreads>, (const void*)conv_z_inv<kHalfThreads>})
         BAE_HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFftLdsBytes));
     done = true;
 }
@@ -313,10 +332,15 @@ void run_lines(const ConvPlan& cp, double2* C, int axis, int nload, int nstore, 
         sout = 0;
         sline = (int64_t)M1 * H2;
     }
-    const int P = lines_for(p.M, false);
+    const bool half = half_blocks(p.M);
+    const int P = half ? half_lines(p.M) : lines_for(p.M, false);
     const size_t lds = sizeof(double2) * ((size_t)P + 1) * p.M;
-    conv_lines<<<(unsigned)((nlines + P - 1) / P), kConvThreads, lds, st>>>(
-        C, nlines, lin, sout, sline, nload, nstore, mode, p, P, cp.ghat, M1, H2, cp.H[1], cp.H[2], skip);
+    if (half)
+        conv_lines<kHalfThreads><<<(unsigned)((nlines + P - 1) / P), kHalfThreads, lds, st>>>(
+            C, nlines, lin, sout, sline, nload, nstore, mode, p, P, cp.ghat, M1, H2, cp.H[1], cp.H[2], skip);
+    else
+        conv_lines<kConvThreads><<<(unsigned)((nlines + P - 1) / P), kConvThreads, lds, st>>>(
+            C, nlines, lin, sout, sline, nload, nstore, mode, p, P, cp.ghat, M1, H2, cp.H[1], cp.H[2], skip);
     BAE_HIP_CHECK(hipGetLastError());
 }
 
@@ -368,19 +392,19 @@ void ConvPlan::build(const int lo_[3], const int hi_[3], const SumTables& tabs, 
     {   // z: rows of the full grid (complex, contiguous)
         const int P = lines_for(M[2], false);
         const int64_t nl = (int64_t)M[0] * M[1];
-        conv_lines<<<(unsigned)((nl + P - 1) / P), kConvThreads, sizeof(double2) * ((size_t)P + 1) * M[2], st>>>(
+        conv_lines<kConvThreads><<<(unsigned)((nl + P - 1) / P), kConvThreads, sizeof(double2) * ((size_t)P + 1) * M[2], st>>>(
             g, nl, 1, M[2], 1, M[2], M[2], 0, fz, P, nullptr, M[1], M[2], H[1], H[2], nullptr);
         BAE_HIP_CHECK(hipGetLastError());
     }
     {   // y over every plane, x over every line
         const int P = lines_for(M[1], false);
         const int64_t nl = (int64_t)M[0] * M[2];
-        conv_lines<<<(unsigned)((nl + P - 1) / P), kConvThreads, sizeof(double2) * ((size_t)P + 1) * M[1], st>>>(
+        conv_lines<kConvThreads><<<(unsigned)((nl + P - 1) / P), kConvThreads, sizeof(double2) * ((size_t)P + 1) * M[1], st>>>(
             g, nl, M[2], (int64_t)M[1] * M[2], M[2], M[1], M[1], 0, fy, P, nullptr, M[1], M[2], H[1], H[2], nullptr);
         BAE_HIP_CHECK(hipGetLastError());
         const int Px = lines_for(M[0], false);
         const int64_t nlx = (int64_t)M[1] * M[2];
-        conv_lines<<<(unsigned)((nlx + Px - 1) / Px), kConvThreads, sizeof(double2) * ((size_t)Px + 1) * M[0], st>>>(
+        conv_lines<kConvThreads><<<(unsigned)((nlx + Px - 1) / Px), kConvThreads, sizeof(double2) * ((size_t)Px + 1) * M[0], st>>>(
             g, nlx, nlx, 0, nlx, M[0], M[0], 0, fx, Px, nullptr, M[1], M[2], H[1], H[2], nullptr);
         BAE_HIP_CHECK(hipGetLastError());
     }
@@ -396,18 +420,20 @@ void ConvPlan::apply(const double* w, const int32_t* sidx, int64_t ns, const int
     conv_fill<<<(unsigned)((box + 255) / 256), 256, 0, st>>>(R, box, skip);
     if (ns > 0) conv_scatter<<<(unsigned)((ns + 255) / 256), 256, 0, st>>>(w, sidx, ns, R);
     BAE_HIP_CHECK(hipGetLastError());
-    const int Pz = lines_for(M[2], true);
+    const bool halfz = half_blocks(M[2]);
+    const int Pz = halfz ? half_lines(M[2], true) : lines_for(M[2], true);
     const int64_t nrow = (int64_t)e[0] * e[1];
     const size_t ldsz = sizeof(double2) * (size_t)(Pz / 2 + 1) * M[2];   // Pz / 2 complex lines, the roots
-    conv_z_fwd<<<(unsigned)((nrow + Pz - 1) / Pz), kConvThreads, ldsz, st>>>(R, e[0], e[1], e[2], M[1], C, fz, Pz,
-                                                                           skip);
+    const unsigned gz = (unsigned)((nrow + Pz - 1) / Pz);
+    if (halfz) conv_z_fwd<kHalfThreads><<<gz, kHalfThreads, ldsz, st>>>(R, e[0], e[1], e[2], M[1], C, fz, Pz, skip);
+    else conv_z_fwd<kConvThreads><<<gz, kConvThreads, ldsz, st>>>(R, e[0], e[1], e[2], M[1], C, fz, Pz, skip);
     BAE_HIP_CHECK(hipGetLastError());
     run_lines(*this, C, 1, e[1], M[1], 0, skip, st);   // y forward: rows j < e1 hold data
     run_lines(*this, C, 0, e[0], e[0], 1, skip, st);   // x forward, product, x inverse
     run_lines(*this, C, 1, M[1], e[1], 2, skip, st);   // y inverse: keep j < e1
     const double norm = scale / ((double)M[0] * M[1] * M[2]);
-    conv_z_inv<<<(unsigned)((nrow + Pz - 1) / Pz), kConvThreads, ldsz, st>>>(C, e[0], e[1], e[2], M[1], R, fz, Pz, norm,
-                                                                           skip);
+    if (halfz) conv_z_inv<kHalfThreads><<<gz, kHalfThreads, ldsz, st>>>(C, e[0], e[1], e[2], M[1], R, fz, Pz, norm, skip);
+    else conv_z_inv<kConvThreads><<<gz, kConvThreads, ldsz, st>>>(C, e[0], e[1], e[2], M[1], R, fz, Pz, norm, skip);
     BAE_HIP_CHECK(hipGetLastError());
     if (nt > 0) conv_gather<<<(unsigned)((nt + 255) / 256), 256, 0, st>>>(R, tidx, nt, out);
     BAE_HIP_CHECK(hipGetLastError());

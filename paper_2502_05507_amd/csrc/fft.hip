@@ -56,7 +56,8 @@ struct BoxEigen {
 
 constexpr int kMaxDstLines = 32;   // lines_per_block's cap
 
-__global__ __launch_bounds__(kFftThreads) void dst_axis_kernel(double* __restrict__ x, int axis, int n0, int n1,
+template <int THREADS>
+__global__ __launch_bounds__(THREADS, 4) void dst_axis_kernel(double* __restrict__ x, int axis, int n0, int n1,
                                                                 int n2, int64_t nlines, int P, const FftDev p,
                                                                 double scale, const BoxEigen eig) {
     extern __shared__ double2 lds[];
@@ -102,11 +103,11 @@ __global__ __launch_bounds__(kFftThreads) void dst_axis_kernel(double* __restric
     // every load of the thread issued before the first LDS write (P N < (P / 2) M <= kFftPoints:
     // at most kIt per thread)
     {
-        constexpr int kIt = kFftPoints / kFftThreads;
+        constexpr int kIt = kFftPointsPerThread;
         double v[kIt];
 #pragma unroll
         for (int it = 0; it < kIt; ++it) {
-            const int e = threadIdx.x + it * kFftThreads;
+            const int e = threadIdx.x + it * THREADS;
             v[it] = 0.0;
             if (e >= P * N) continue;
             const int2 q = split(e);
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(kFftThreads) void dst_axis_kernel(double* __restric
         }
 #pragma unroll
         for (int it = 0; it < kIt; ++it) {
-            const int e = threadIdx.x + it * kFftThreads;
+            const int e = threadIdx.x + it * THREADS;
             if (e >= P * N) continue;
             const int2 q = split(e);
             const int c = q.x >> 1, comp = q.x & 1;
@@ -124,7 +125,7 @@ __global__ __launch_bounds__(kFftThreads) void dst_axis_kernel(double* __restric
         }
     }
     __syncthreads();
-    fft_lds(A, nfft, p, tw, false);
+    fft_lds<THREADS>(A, nfft, p, tw, false);
     const double2* Z = A;
     const double h = 0.5 * scale;
     for (int e = threadIdx.x; e < P * N; e += blockDim.x) {
@@ -250,22 +251,37 @@ static int lines_per_block(int M) {
     return P;
 }
 
+// Transforms up to 2048 long run 512-thread blocks of half the points and LDS, two to a
+// compute unit, so that one block's loads and stores overlap the other's LDS stages.
+constexpr int kDstHalfThreads = fftdev::kFftThreads / 2;
+static bool dst_half(int M) { return M <= 2048; }
+static int dst_half_lines(int M) {
+    const int by_points = fftdev::kFftPointsPerThread * kDstHalfThreads / M;
+    const int by_lds = (int)(kFftLdsBytes / 2 / (16 * (size_t)M)) - 1;
+    return 2 * std::max(1, std::min(kMaxDstLines / 2, std::min(by_points, by_lds)));
+}
+
 static void dst_axis_eig(double* x, int n0, int n1, int n2, int axis, double scale, const BoxEigen& eig,
                          hipStream_t st) {
     const int N = axis == 0 ? n0 : axis == 1 ? n1 : n2;
     if (N <= 0) return;
     const FftDev p = fft_plan(2 * (N + 1), st);
-    const int P = lines_per_block(p.M);
+    const bool half = dst_half(p.M);
+    const int P = half ? dst_half_lines(p.M) : lines_per_block(p.M);
     const int64_t nlines = (int64_t)n0 * n1 * n2 / N;
     const size_t lds = sizeof(double2) * (size_t)(P / 2 + 1) * p.M;   // P / 2 complex lines, the roots
     static bool attr = false;
     if (!attr) {
-        BAE_HIP_CHECK(hipFuncSetAttribute((const void*)dst_axis_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                          (int)kFftLdsBytes));
+        for (const void* f : {(const void*)dst_axis_kernel<fftdev::kFftThreads>, (const void*)dst_axis_kernel<kDstHalfThreads>})
+            BAE_HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFftLdsBytes));
         attr = true;
     }
     const unsigned blocks = (unsigned)((nlines + P - 1) / P);
-    dst_axis_kernel<<<blocks, fftdev::kFftThreads, lds, st>>>(x, axis, n0, n1, n2, nlines, P, p, scale, eig);
+    if (half)
+        dst_axis_kernel<kDstHalfThreads><<<blocks, kDstHalfThreads, lds, st>>>(x, axis, n0, n1, n2, nlines, P, p, scale, eig);
+    else
+        dst_axis_kernel<fftdev::kFftThreads><<<blocks, fftdev::kFftThreads, lds, st>>>(x, axis, n0, n1, n2, nlines, P, p,
+                                                                                    scale, eig);
     BAE_HIP_CHECK(hipGetLastError());
 }
 

@@ -82,17 +82,20 @@ __device__ __forceinline__ void butterfly(double2 (&v)[R], bool inv) {
 constexpr int kFftThreads = 1024;
 constexpr int kFftPoints = 8192;                         // count * M per block at most
 
-template <int R>
+// THREADS: the block size; a block holds at most kFftPointsPerThread * THREADS points.
+constexpr int kFftPointsPerThread = kFftPoints / kFftThreads;
+
+template <int R, int THREADS = kFftThreads>
 __device__ __forceinline__ void stage(double2* __restrict__ buf, int count, int M, int Ns,
                                       const double2* __restrict__ tw, bool inv) {
     const int m = M / R, tstep = M / (Ns * R), total = count * m;
     const float rm = 1.0f / (float)m, rns = 1.0f / (float)Ns;
-    constexpr int I = (kFftPoints / R + kFftThreads - 1) / kFftThreads;
+    constexpr int I = (kFftPointsPerThread * THREADS / R + THREADS - 1) / THREADS;
     double2 v[I][R];
     int o[I];
 #pragma unroll
     for (int it = 0; it < I; ++it) {
-        const int e = threadIdx.x + it * kFftThreads;
+        const int e = threadIdx.x + it * THREADS;
         o[it] = -1;
         if (e >= total) continue;
         const int c = fdiv(e, m, rm), j = e - c * m;
@@ -117,16 +120,17 @@ __device__ __forceinline__ void stage(double2* __restrict__ buf, int count, int 
 }
 
 // any radix R: every output an R-term sum, X = sum_r in[j + r m] w^(r base)
+template <int THREADS = kFftThreads>
 __device__ __forceinline__ void stage_any(double2* __restrict__ buf, int count, int M, int Ns, int R,
                                           const double2* __restrict__ tw, bool inv) {
     const int m = M / R, tstep = M / (Ns * R), total = count * M;
     const float rM = 1.0f / (float)M, rm = 1.0f / (float)m, rns = 1.0f / (float)Ns;
-    constexpr int I = kFftPoints / kFftThreads;
+    constexpr int I = kFftPointsPerThread;
     double2 acc[I];
     int o[I];
 #pragma unroll
     for (int it = 0; it < I; ++it) {
-        const int e = threadIdx.x + it * kFftThreads;
+        const int e = threadIdx.x + it * THREADS;
         o[it] = -1;
         if (e >= total) continue;
         const int c = fdiv(e, M, rM), q = e - c * M;
@@ -155,20 +159,21 @@ __device__ __forceinline__ void load_roots(const FftDev& p, double2* tw) {
     for (int t = threadIdx.x; t < p.M; t += blockDim.x) tw[t] = p.tw[t];
 }
 
-// `count` FFTs of length p.M (count p.M <= kFftPoints) stored one after another in buf (LDS),
-// in place, by a block of kFftThreads threads; tw: the root table in LDS.  Every thread of
-// the block must call it; the result is in buf when it returns.
+// `count` FFTs of length p.M (count p.M <= kFftPointsPerThread THREADS) stored one after
+// another in buf (LDS), in place, by a block of THREADS threads; tw: the root table in LDS.
+// Every thread of the block must call it; the result is in buf when it returns.
+template <int THREADS = kFftThreads>
 __device__ __forceinline__ void fft_lds(double2* buf, int count, const FftDev& p, const double2* tw, bool inv) {
     const int M = p.M;
     int Ns = 1;
     for (int s = 0; s < p.nf; ++s) {
         const int R = p.f[s];
         switch (R) {
-            case 2: stage<2>(buf, count, M, Ns, tw, inv); break;
-            case 3: stage<3>(buf, count, M, Ns, tw, inv); break;
-            case 4: stage<4>(buf, count, M, Ns, tw, inv); break;
-            case 5: stage<5>(buf, count, M, Ns, tw, inv); break;
-            default: stage_any(buf, count, M, Ns, R, tw, inv); break;
+            case 2: stage<2, THREADS>(buf, count, M, Ns, tw, inv); break;
+            case 3: stage<3, THREADS>(buf, count, M, Ns, tw, inv); break;
+            case 4: stage<4, THREADS>(buf, count, M, Ns, tw, inv); break;
+            case 5: stage<5, THREADS>(buf, count, M, Ns, tw, inv); break;
+            default: stage_any<THREADS>(buf, count, M, Ns, R, tw, inv); break;
         }
         __syncthreads();
         Ns *= R;

@@ -290,12 +290,14 @@ int lines_for(int M, bool packed) {
     return P;
 }
 
-// The line passes run 512-thread blocks of half the points and LDS, two to a compute unit, so
-// that one block's loads and stores overlap the other's LDS stages (a 1024-thread block at
-// 128 VGPRs holds a compute unit alone and runs its phases in series); lengths beyond 2048
+// The passes run 256-thread blocks of a quarter of the points and LDS, four to a compute unit,
+// so that some blocks' loads and stores overlap the others' LDS stages (a 1024-thread block at
+// 128 VGPRs holds a compute unit alone and runs its phases in series: two blocks of 512 took
+// the 257^3 convolution from 1.41 to 1.21 ms, four of 256 to 1.18 ms); lengths beyond 2048
 // keep the 1024-thread blocks.
-constexpr int kHalfThreads = kConvThreads / 2;
-constexpr size_t kHalfLdsBytes = kFftLdsBytes / 2;
+constexpr int kSplit = 4;
+constexpr int kHalfThreads = kConvThreads / kSplit;
+constexpr size_t kHalfLdsBytes = kFftLdsBytes / kSplit;
 bool half_blocks(int M) { return M <= 2048; }
 int half_lines(int M, bool packed = false) {
     const int by_points = kFftPointsPerThread * kHalfThreads / M;

@@ -251,13 +251,14 @@ static int lines_per_block(int M) {
     return P;
 }
 
-// Transforms up to 2048 long run 512-thread blocks of half the points and LDS, two to a
-// compute unit, so that one block's loads and stores overlap the other's LDS stages.
-constexpr int kDstHalfThreads = fftdev::kFftThreads / 2;
+// Transforms up to 2048 long run 256-thread blocks of a quarter of the points and LDS, four to
+// a compute unit, so that some blocks' loads and stores overlap the others' LDS stages.
+constexpr int kDstSplit = 4;
+constexpr int kDstHalfThreads = fftdev::kFftThreads / kDstSplit;
 static bool dst_half(int M) { return M <= 2048; }
 static int dst_half_lines(int M) {
     const int by_points = fftdev::kFftPointsPerThread * kDstHalfThreads / M;
-    const int by_lds = (int)(kFftLdsBytes / 2 / (16 * (size_t)M)) - 1;
+    const int by_lds = (int)(kFftLdsBytes / kDstSplit / (16 * (size_t)M)) - 1;
     return 2 * std::max(1, std::min(kMaxDstLines / 2, std::min(by_points, by_lds)));
 }
 

@@ -296,12 +296,12 @@ int lines_for(int M, bool packed) {
 // the 257^3 convolution from 1.41 to 1.21 ms, four of 256 to 1.18 ms); lengths beyond 2048
 // keep the 1024-thread blocks.
 constexpr int kSplit = 4;
-constexpr int kHalfThreads = kConvThreads / kSplit;
-constexpr size_t kHalfLdsBytes = kFftLdsBytes / kSplit;
-bool half_blocks(int M) { return M <= 2048; }
-int half_lines(int M, bool packed = false) {
-    const int by_points = kFftPointsPerThread * kHalfThreads / M;
-    const int by_lds = (int)(kHalfLdsBytes / (16 * (size_t)M)) - 1;
+constexpr int kSplitThreads = kConvThreads / kSplit;
+constexpr size_t kSplitLdsBytes = kFftLdsBytes / kSplit;
+bool split_blocks(int M) { return M <= 2048; }
+int split_lines(int M, bool packed = false) {
+    const int by_points = kFftPointsPerThread * kSplitThreads / M;
+    const int by_lds = (int)(kSplitLdsBytes / (16 * (size_t)M)) - 1;
     const int c = std::max(1, std::min(packed ? kMaxLinesPerBlock / 2 : kMaxLinesPerBlock, std::min(by_points, by_lds)));
     return packed ? 2 * c : c;
 }
@@ -309,9 +309,9 @@ int half_lines(int M, bool packed = false) {
 void set_lds_attr() {
     static bool done = false;
     if (done) return;
-    for (const void* f : {(const void*)conv_z_fwd<kConvThreads>, (const void*)conv_z_fwd<kHalfThreads>,
-                          (const void*)conv_lines<kConvThreads>, (const void*)conv_lines<kHalfThreads>,
-                          (const void*)conv_z_inv<kConvThreads>, (const void*)conv_z_inv<kHalfThreads>})
+    for (const void* f : {(const void*)conv_z_fwd<kConvThreads>, (const void*)conv_z_fwd<kSplitThreads>,
+                          (const void*)conv_lines<kConvThreads>, (const void*)conv_lines<kSplitThreads>,
+                          (const void*)conv_z_inv<kConvThreads>, (const void*)conv_z_inv<kSplitThreads>})
         BAE_HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFftLdsBytes));
     done = true;
 }
@@ -334,11 +334,11 @@ void run_lines(const ConvPlan& cp, double2* C, int axis, int nload, int nstore, 
         sout = 0;
         sline = (int64_t)M1 * H2;
     }
-    const bool half = half_blocks(p.M);
-    const int P = half ? half_lines(p.M) : lines_for(p.M, false);
+    const bool split = split_blocks(p.M);
+    const int P = split ? split_lines(p.M) : lines_for(p.M, false);
     const size_t lds = sizeof(double2) * ((size_t)P + 1) * p.M;
-    if (half)
-        conv_lines<kHalfThreads><<<(unsigned)((nlines + P - 1) / P), kHalfThreads, lds, st>>>(
+    if (split)
+        conv_lines<kSplitThreads><<<(unsigned)((nlines + P - 1) / P), kSplitThreads, lds, st>>>(
             C, nlines, lin, sout, sline, nload, nstore, mode, p, P, cp.ghat, M1, H2, cp.H[1], cp.H[2], skip);
     else
         conv_lines<kConvThreads><<<(unsigned)((nlines + P - 1) / P), kConvThreads, lds, st>>>(
@@ -422,19 +422,19 @@ void ConvPlan::apply(const double* w, const int32_t* sidx, int64_t ns, const int
     conv_fill<<<(unsigned)((box + 255) / 256), 256, 0, st>>>(R, box, skip);
     if (ns > 0) conv_scatter<<<(unsigned)((ns + 255) / 256), 256, 0, st>>>(w, sidx, ns, R);
     BAE_HIP_CHECK(hipGetLastError());
-    const bool halfz = half_blocks(M[2]);
-    const int Pz = halfz ? half_lines(M[2], true) : lines_for(M[2], true);
+    const bool splitz = split_blocks(M[2]);
+    const int Pz = splitz ? split_lines(M[2], true) : lines_for(M[2], true);
     const int64_t nrow = (int64_t)e[0] * e[1];
     const size_t ldsz = sizeof(double2) * (size_t)(Pz / 2 + 1) * M[2];   // Pz / 2 complex lines, the roots
     const unsigned gz = (unsigned)((nrow + Pz - 1) / Pz);
-    if (halfz) conv_z_fwd<kHalfThreads><<<gz, kHalfThreads, ldsz, st>>>(R, e[0], e[1], e[2], M[1], C, fz, Pz, skip);
+    if (splitz) conv_z_fwd<kSplitThreads><<<gz, kSplitThreads, ldsz, st>>>(R, e[0], e[1], e[2], M[1], C, fz, Pz, skip);
     else conv_z_fwd<kConvThreads><<<gz, kConvThreads, ldsz, st>>>(R, e[0], e[1], e[2], M[1], C, fz, Pz, skip);
     BAE_HIP_CHECK(hipGetLastError());
     run_lines(*this, C, 1, e[1], M[1], 0, skip, st);   // y forward: rows j < e1 hold data
     run_lines(*this, C, 0, e[0], e[0], 1, skip, st);   // x forward, product, x inverse
     run_lines(*this, C, 1, M[1], e[1], 2, skip, st);   // y inverse: keep j < e1
     const double norm = scale / ((double)M[0] * M[1] * M[2]);
-    if (halfz) conv_z_inv<kHalfThreads><<<gz, kHalfThreads, ldsz, st>>>(C, e[0], e[1], e[2], M[1], R, fz, Pz, norm, skip);
+    if (splitz) conv_z_inv<kSplitThreads><<<gz, kSplitThreads, ldsz, st>>>(C, e[0], e[1], e[2], M[1], R, fz, Pz, norm, skip);
     else conv_z_inv<kConvThreads><<<gz, kConvThreads, ldsz, st>>>(C, e[0], e[1], e[2], M[1], R, fz, Pz, norm, skip);
     BAE_HIP_CHECK(hipGetLastError());
     if (nt > 0) conv_gather<<<(unsigned)((nt + 255) / 256), 256, 0, st>>>(R, tidx, nt, out);

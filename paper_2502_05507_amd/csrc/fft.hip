@@ -254,10 +254,10 @@ static int lines_per_block(int M) {
 // Transforms up to 2048 long run 256-thread blocks of a quarter of the points and LDS, four to
 // a compute unit, so that some blocks' loads and stores overlap the others' LDS stages.
 constexpr int kDstSplit = 4;
-constexpr int kDstHalfThreads = fftdev::kFftThreads / kDstSplit;
-static bool dst_half(int M) { return M <= 2048; }
-static int dst_half_lines(int M) {
-    const int by_points = fftdev::kFftPointsPerThread * kDstHalfThreads / M;
+constexpr int kDstSplitThreads = fftdev::kFftThreads / kDstSplit;
+static bool dst_split(int M) { return M <= 2048; }
+static int dst_split_lines(int M) {
+    const int by_points = fftdev::kFftPointsPerThread * kDstSplitThreads / M;
     const int by_lds = (int)(kFftLdsBytes / kDstSplit / (16 * (size_t)M)) - 1;
     return 2 * std::max(1, std::min(kMaxDstLines / 2, std::min(by_points, by_lds)));
 }
@@ -267,19 +267,19 @@ static void dst_axis_eig(double* x, int n0, int n1, int n2, int axis, double sca
     const int N = axis == 0 ? n0 : axis == 1 ? n1 : n2;
     if (N <= 0) return;
     const FftDev p = fft_plan(2 * (N + 1), st);
-    const bool half = dst_half(p.M);
-    const int P = half ? dst_half_lines(p.M) : lines_per_block(p.M);
+    const bool split = dst_split(p.M);
+    const int P = split ? dst_split_lines(p.M) : lines_per_block(p.M);
     const int64_t nlines = (int64_t)n0 * n1 * n2 / N;
     const size_t lds = sizeof(double2) * (size_t)(P / 2 + 1) * p.M;   // P / 2 complex lines, the roots
     static bool attr = false;
     if (!attr) {
-        for (const void* f : {(const void*)dst_axis_kernel<fftdev::kFftThreads>, (const void*)dst_axis_kernel<kDstHalfThreads>})
+        for (const void* f : {(const void*)dst_axis_kernel<fftdev::kFftThreads>, (const void*)dst_axis_kernel<kDstSplitThreads>})
             BAE_HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFftLdsBytes));
         attr = true;
     }
     const unsigned blocks = (unsigned)((nlines + P - 1) / P);
-    if (half)
-        dst_axis_kernel<kDstHalfThreads><<<blocks, kDstHalfThreads, lds, st>>>(x, axis, n0, n1, n2, nlines, P, p, scale, eig);
+    if (split)
+        dst_axis_kernel<kDstSplitThreads><<<blocks, kDstSplitThreads, lds, st>>>(x, axis, n0, n1, n2, nlines, P, p, scale, eig);
     else
         dst_axis_kernel<fftdev::kFftThreads><<<blocks, fftdev::kFftThreads, lds, st>>>(x, axis, n0, n1, n2, nlines, P, p,
                                                                                     scale, eig);

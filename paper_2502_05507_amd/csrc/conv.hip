@@ -44,7 +44,7 @@ __global__ __launch_bounds__(THREADS, 4) void conv_z_fwd(const double* __restric
     double2* tw = A + (int64_t)nfft * M;
     load_roots(p, tw);
     double* Ad = (double*)A;
-    const int64_t l0 = (int64_t)blockIdx.x * P, nl = (int64_t)e0 * e1;
+    const int64_t l0 = (int64_t)xcd_group(blockIdx.x, gridDim.x) * P, nl = (int64_t)e0 * e1;
     const int H = M / 2 + 1;
     if ((int)threadIdx.x < P) {
         const int64_t l = l0 + threadIdx.x;
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(THREADS, 4) void conv_lines(double2* __restrict__ C
     double2* A = lds;
     double2* tw = A + (int64_t)P * M;
     load_roots(p, tw);
-    const int64_t l0 = (int64_t)blockIdx.x * P;
+    const int64_t l0 = (int64_t)xcd_group(blockIdx.x, gridDim.x) * P;
     if ((int)threadIdx.x < P) {
         const int64_t l = l0 + threadIdx.x;
         lbase[threadIdx.x] = l < nlines ? (l / lin) * sout + (l % lin) : -1;
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(THREADS, 4) void conv_z_inv(const double2* __restri
     double2* A = lds;
     double2* tw = A + (int64_t)nfft * M;
     load_roots(p, tw);
-    const int64_t l0 = (int64_t)blockIdx.x * P, nl = (int64_t)e0 * e1;
+    const int64_t l0 = (int64_t)xcd_group(blockIdx.x, gridDim.x) * P, nl = (int64_t)e0 * e1;
     const int H = M / 2 + 1;
     if ((int)threadIdx.x < P) {
         const int64_t l = l0 + threadIdx.x;

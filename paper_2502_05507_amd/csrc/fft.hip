@@ -73,7 +73,7 @@ __global__ __launch_bounds__(THREADS, 4) void dst_axis_kernel(double* __restrict
     double2* A = lds;
     double2* tw = A + (int64_t)nfft * M;
     load_roots(p, tw);
-    const int64_t l0 = (int64_t)blockIdx.x * P;
+    const int64_t l0 = (int64_t)xcd_group(blockIdx.x, gridDim.x) * P;
     if ((int)threadIdx.x < P) {
         const int64_t l = l0 + threadIdx.x;
         lbase[threadIdx.x] = l >= nlines ? -1 : line_at(axis, l, 0, n0, n1, n2);

@@ -154,6 +154,16 @@ __device__ __forceinline__ void stage_any(double2* __restrict__ buf, int count, 
         if (o[it] >= 0) buf[o[it]] = acc[it];
 }
 
+// Workgroups are dispatched to the 8 XCDs of an MI355X round-robin (workgroup b to XCD b mod 8).
+// The group of lines a workgroup takes is chosen so that each XCD walks a contiguous range of
+// groups: neighbouring groups share cache lines at their edges, which that XCD's L2 then fetches
+// once.  A bijection of [0, n).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_group(int b, int n) {
+    const int x = b % kXcds, k = b / kXcds, q = n / kXcds, r = n % kXcds;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
 // Copies the root table (M entries) into LDS; the caller synchronises before fft_lds.
 __device__ __forceinline__ void load_roots(const FftDev& p, double2* tw) {
     for (int t = threadIdx.x; t < p.M; t += blockDim.x) tw[t] = p.tw[t];

@@ -293,12 +293,13 @@ int lines_for(int M, bool packed) {
 // The passes run 256-thread blocks of a quarter of the points and LDS, four to a compute unit,
 // so that some blocks' loads and stores overlap the others' LDS stages (a 1024-thread block at
 // 128 VGPRs holds a compute unit alone and runs its phases in series: two blocks of 512 took
-// the 257^3 convolution from 1.41 to 1.21 ms, four of 256 to 1.18 ms); lengths beyond 2048
+// the 257^3 convolution from 1.41 to 1.21 ms, four of 256 to 1.18 ms, eight of 128 took 1.35 ms);
+// lines longer than such a block holds (2048)
 // keep the 1024-thread blocks.
 constexpr int kSplit = 4;
 constexpr int kSplitThreads = kConvThreads / kSplit;
 constexpr size_t kSplitLdsBytes = kFftLdsBytes / kSplit;
-bool split_blocks(int M) { return M <= 2048; }
+bool split_blocks(int M) { return M <= kFftPointsPerThread * kSplitThreads; }   // one line fits a block
 int split_lines(int M, bool packed = false) {
     const int by_points = kFftPointsPerThread * kSplitThreads / M;
     const int by_lds = (int)(kSplitLdsBytes / (16 * (size_t)M)) - 1;

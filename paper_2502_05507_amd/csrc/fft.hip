@@ -255,7 +255,7 @@ static int lines_per_block(int M) {
 // a compute unit, so that some blocks' loads and stores overlap the others' LDS stages.
 constexpr int kDstSplit = 4;
 constexpr int kDstSplitThreads = fftdev::kFftThreads / kDstSplit;
-static bool dst_split(int M) { return M <= 2048; }
+static bool dst_split(int M) { return M <= fftdev::kFftPointsPerThread * kDstSplitThreads; }   // one line pair fits a block
 static int dst_split_lines(int M) {
     const int by_points = fftdev::kFftPointsPerThread * kDstSplitThreads / M;
     const int by_lds = (int)(kFftLdsBytes / kDstSplit / (16 * (size_t)M)) - 1;

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(THREADS, 4) void conv_z_fwd(const double* __restric
     }
     for (int e = threadIdx.x; e < nfft * M; e += blockDim.x) A[e] = make_double2(0.0, 0.0);
     __syncthreads();
-    const float re2 = 1.0f / (float)e2, rH = 1.0f / (float)H;
+    const float re2 = rcp_up(e2), rH = rcp_up(H);
     // every load of the thread issued before the first LDS write (one memory latency, not eight)
     {
         double v[kIt];
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(THREADS, 4) void conv_z_fwd(const double* __restric
             const int e = threadIdx.x + it * THREADS;
             at[it] = -1;
             if (e >= P * e2) continue;
-            const int pl = fdiv(e, e2, re2), k = e - pl * e2;
+            const int pl = fdiv_up(e, re2), k = e - pl * e2;
             if (cbase[pl] < 0) continue;
             v[it] = R[(l0 + pl) * e2 + k];
             at[it] = 2 * ((pl >> 1) * M + k) + (pl & 1);
@@ -72,15 +72,15 @@ __global__ __launch_bounds__(THREADS, 4) void conv_z_fwd(const double* __restric
             if (at[it] >= 0) Ad[at[it]] = v[it];
         // P e2 can pass kFftPoints by up to P / 2 (e2 <= (M + 1) / 2)
         for (int e = threadIdx.x + kIt * THREADS; e < P * e2; e += THREADS) {
-            const int pl = fdiv(e, e2, re2), k = e - pl * e2;
+            const int pl = fdiv_up(e, re2), k = e - pl * e2;
             if (cbase[pl] >= 0) Ad[2 * ((pl >> 1) * M + k) + (pl & 1)] = R[(l0 + pl) * e2 + k];
         }
     }
     __syncthreads();
-    fft_lds<THREADS>(A, nfft, p, tw, false);
+    fft_lds<THREADS, false>(A, nfft, p, tw);
     const double2* Z = A;
     for (int e = threadIdx.x; e < P * H; e += blockDim.x) {
-        const int pl = fdiv(e, H, rH), k = e - pl * H;
+        const int pl = fdiv_up(e, rH), k = e - pl * H;
         const int64_t cb = cbase[pl];
         if (cb < 0) continue;
         const double2* z = Z + (int64_t)(pl >> 1) * M;
@@ -97,9 +97,10 @@ __global__ __launch_bounds__(THREADS, 4) void conv_z_fwd(const double* __restric
 // beyond), n < nstore stored; mode 1: forward, times the kernel's transform, inverse (the x
 // pass; n < nload loaded and stored); mode 2: inverse, all M loaded, n < nstore stored.
 // P consecutive lines (consecutive in memory) per block.
-template <int THREADS>
+// MODE is a template parameter so that each kernel holds only the transforms it runs.
+template <int THREADS, int MODE>
 __global__ __launch_bounds__(THREADS, 4) void conv_lines(double2* __restrict__ C, int64_t nlines, int64_t lin,
-                                                          int64_t sout, int64_t sline, int nload, int nstore, int mode,
+                                                          int64_t sout, int64_t sline, int nload, int nstore,
                                                           const FftDev p, int P, const double* __restrict__ ghat,
                                                           int M1, int L2, int H1, int H2,
                                                           const int32_t* __restrict__ skip) {
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(THREADS, 4) void conv_lines(double2* __restrict__ C
     if ((int)threadIdx.x < P) {
         const int64_t l = l0 + threadIdx.x;
         lbase[threadIdx.x] = l < nlines ? (l / lin) * sout + (l % lin) : -1;
-        if (mode == 1) {
+        if constexpr (MODE == 1) {
             // line l = j L2 + k of the x pass on half spectra (L2 = M2/2 + 1, k <= M2/2); the
             // transform is even in every index
             const int j = (int)(l / L2), k = (int)(l % L2);
@@ -125,8 +126,8 @@ __global__ __launch_bounds__(THREADS, 4) void conv_lines(double2* __restrict__ C
         }
     }
     __syncthreads();
-    const float rP = 1.0f / (float)P;
-    const int nl = mode == 2 ? M : nload;
+    const float rP = rcp_up(P);
+    const int nl = MODE == 2 ? M : nload;
     // every load of the thread issued before the first LDS write (one memory latency, not eight)
     {
         double2 v[kIt];
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(THREADS, 4) void conv_lines(double2* __restrict__ C
             const int e = threadIdx.x + it * THREADS;
             v[it] = make_double2(0.0, 0.0);
             if (e >= P * M) continue;
-            const int n = fdiv(e, P, rP), pl = e - n * P;
+            const int n = fdiv_up(e, rP), pl = e - n * P;
             const int64_t lb = lbase[pl];
             if (n < nl && lb >= 0) v[it] = C[lb + n * sline];
         }
@@ -143,30 +144,30 @@ __global__ __launch_bounds__(THREADS, 4) void conv_lines(double2* __restrict__ C
         for (int it = 0; it < kIt; ++it) {
             const int e = threadIdx.x + it * THREADS;
             if (e >= P * M) continue;
-            const int n = fdiv(e, P, rP), pl = e - n * P;
+            const int n = fdiv_up(e, rP), pl = e - n * P;
             A[pl * M + n] = v[it];
         }
     }
     __syncthreads();
     double2* Z = A;
-    // mode 1 transforms twice (forward, the product, inverse) through one copy of the FFT code
-    const int64_t gplane = (int64_t)H1 * H2;
-    for (int pass = 0; pass < (mode == 1 ? 2 : 1); ++pass) {
-        fft_lds<THREADS>(Z, P, p, tw, mode == 2 || pass == 1);
-        if (mode != 1 || pass == 1) break;
+    if constexpr (MODE == 2) fft_lds<THREADS, true>(Z, P, p, tw);
+    else fft_lds<THREADS, false>(Z, P, p, tw);
+    if constexpr (MODE == 1) {   // the product by the kernel's transform, then the inverse
+        const int64_t gplane = (int64_t)H1 * H2;
         // the block's lines are consecutive rows of the kernel's transform: the line index
         // fastest, so that a wavefront reads runs of consecutive values of it
         for (int e = threadIdx.x; e < P * M; e += blockDim.x) {
-            const int n = fdiv(e, P, rP), pl = e - n * P;
+            const int n = fdiv_up(e, rP), pl = e - n * P;
             if (lbase[pl] < 0) continue;
             const double g = ghat[min(n, M - n) * gplane + grow[pl]];
             const double2 z = Z[(int64_t)pl * M + n];
             Z[(int64_t)pl * M + n] = make_double2(g * z.x, g * z.y);
         }
         __syncthreads();
+        fft_lds<THREADS, true>(Z, P, p, tw);
     }
     for (int e = threadIdx.x; e < P * nstore; e += blockDim.x) {
-        const int n = fdiv(e, P, rP), pl = e - n * P;
+        const int n = fdiv_up(e, rP), pl = e - n * P;
         const int64_t lb = lbase[pl];
         if (lb >= 0) C[lb + n * sline] = Z[(int64_t)pl * M + n];
     }
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(THREADS, 4) void conv_z_inv(const double2* __restri
         cbase[threadIdx.x] = l < nl ? idx3((int)(l / e1), (int)(l % e1), 0, M1, H) : -1;
     }
     __syncthreads();
-    const float rM = 1.0f / (float)M, re2 = 1.0f / (float)e2;
+    const float rM = rcp_up(M), re2 = rcp_up(e2);
     // every load of the thread issued before the first LDS write (one memory latency, not four)
     {
         double2 xa[kIt], xb[kIt];   // nfft M <= kFftPoints
@@ -202,7 +203,7 @@ __global__ __launch_bounds__(THREADS, 4) void conv_z_inv(const double2* __restri
             const int e = threadIdx.x + it * THREADS;
             xa[it] = xb[it] = make_double2(0.0, 0.0);
             if (e >= nfft * M) continue;
-            const int c = fdiv(e, M, rM), k = e - c * M;
+            const int c = fdiv_up(e, rM), k = e - c * M;
             const int kk = k >= H ? M - k : k;
             const int64_t ba = cbase[2 * c], bb = cbase[2 * c + 1];
             if (ba >= 0) xa[it] = C[ba + kk];
@@ -212,7 +213,7 @@ __global__ __launch_bounds__(THREADS, 4) void conv_z_inv(const double2* __restri
         for (int it = 0; it < kIt; ++it) {
             const int e = threadIdx.x + it * THREADS;
             if (e >= nfft * M) continue;
-            const int c = fdiv(e, M, rM), k = e - c * M;
+            const int c = fdiv_up(e, rM), k = e - c * M;
             double2 a = xa[it], b = xb[it];
             if (k >= H) {   // the conjugate mirror
                 a.y = -a.y;
@@ -222,10 +223,10 @@ __global__ __launch_bounds__(THREADS, 4) void conv_z_inv(const double2* __restri
         }
     }
     __syncthreads();
-    fft_lds<THREADS>(A, nfft, p, tw, true);
+    fft_lds<THREADS, true>(A, nfft, p, tw);
     const double2* Z = A;
     for (int e = threadIdx.x; e < P * e2; e += blockDim.x) {
-        const int pl = fdiv(e, e2, re2), k = e - pl * e2;
+        const int pl = fdiv_up(e, re2), k = e - pl * e2;
         if (cbase[pl] < 0) continue;
         const double2 z = Z[(int64_t)(pl >> 1) * M + k];
         R[(l0 + pl) * e2 + k] = scale * ((pl & 1) ? z.y : z.x);
@@ -311,10 +312,20 @@ void set_lds_attr() {
     static bool done = false;
     if (done) return;
     for (const void* f : {(const void*)conv_z_fwd<kConvThreads>, (const void*)conv_z_fwd<kSplitThreads>,
-                          (const void*)conv_lines<kConvThreads>, (const void*)conv_lines<kSplitThreads>,
+                          (const void*)conv_lines<kConvThreads, 0>, (const void*)conv_lines<kSplitThreads, 0>,
+                          (const void*)conv_lines<kConvThreads, 1>, (const void*)conv_lines<kSplitThreads, 1>,
+                          (const void*)conv_lines<kConvThreads, 2>, (const void*)conv_lines<kSplitThreads, 2>,
                           (const void*)conv_z_inv<kConvThreads>, (const void*)conv_z_inv<kSplitThreads>})
         BAE_HIP_CHECK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFftLdsBytes));
     done = true;
+}
+
+// conv_lines for a mode known at run time
+template <int THREADS, typename... A>
+void launch_lines(int mode, unsigned grid, size_t lds, hipStream_t st, A... args) {
+    if (mode == 0) conv_lines<THREADS, 0><<<grid, THREADS, lds, st>>>(args...);
+    else if (mode == 1) conv_lines<THREADS, 1><<<grid, THREADS, lds, st>>>(args...);
+    else conv_lines<THREADS, 2><<<grid, THREADS, lds, st>>>(args...);
 }
 
 // C lines along y (i < e0, k < M2; j the element) or x (j < M1, k < M2; i the element)
@@ -338,12 +349,13 @@ void run_lines(const ConvPlan& cp, double2* C, int axis, int nload, int nstore, 
     const bool split = split_blocks(p.M);
     const int P = split ? split_lines(p.M) : lines_for(p.M, false);
     const size_t lds = sizeof(double2) * ((size_t)P + 1) * p.M;
+    const unsigned grid = (unsigned)((nlines + P - 1) / P);
     if (split)
-        conv_lines<kSplitThreads><<<(unsigned)((nlines + P - 1) / P), kSplitThreads, lds, st>>>(
-            C, nlines, lin, sout, sline, nload, nstore, mode, p, P, cp.ghat, M1, H2, cp.H[1], cp.H[2], skip);
+        launch_lines<kSplitThreads>(mode, grid, lds, st, C, nlines, lin, sout, sline, nload, nstore, p, P, cp.ghat, M1,
+                                    H2, cp.H[1], cp.H[2], skip);
     else
-        conv_lines<kConvThreads><<<(unsigned)((nlines + P - 1) / P), kConvThreads, lds, st>>>(
-            C, nlines, lin, sout, sline, nload, nstore, mode, p, P, cp.ghat, M1, H2, cp.H[1], cp.H[2], skip);
+        launch_lines<kConvThreads>(mode, grid, lds, st, C, nlines, lin, sout, sline, nload, nstore, p, P, cp.ghat, M1,
+                                   H2, cp.H[1], cp.H[2], skip);
     BAE_HIP_CHECK(hipGetLastError());
 }
 
@@ -395,20 +407,20 @@ void ConvPlan::build(const int lo_[3], const int hi_[3], const SumTables& tabs, 
     {   // z: rows of the full grid (complex, contiguous)
         const int P = lines_for(M[2], false);
         const int64_t nl = (int64_t)M[0] * M[1];
-        conv_lines<kConvThreads><<<(unsigned)((nl + P - 1) / P), kConvThreads, sizeof(double2) * ((size_t)P + 1) * M[2], st>>>(
-            g, nl, 1, M[2], 1, M[2], M[2], 0, fz, P, nullptr, M[1], M[2], H[1], H[2], nullptr);
+        conv_lines<kConvThreads, 0><<<(unsigned)((nl + P - 1) / P), kConvThreads, sizeof(double2) * ((size_t)P + 1) * M[2], st>>>(
+            g, nl, 1, M[2], 1, M[2], M[2], fz, P, nullptr, M[1], M[2], H[1], H[2], nullptr);
         BAE_HIP_CHECK(hipGetLastError());
     }
     {   // y over every plane, x over every line
         const int P = lines_for(M[1], false);
         const int64_t nl = (int64_t)M[0] * M[2];
-        conv_lines<kConvThreads><<<(unsigned)((nl + P - 1) / P), kConvThreads, sizeof(double2) * ((size_t)P + 1) * M[1], st>>>(
-            g, nl, M[2], (int64_t)M[1] * M[2], M[2], M[1], M[1], 0, fy, P, nullptr, M[1], M[2], H[1], H[2], nullptr);
+        conv_lines<kConvThreads, 0><<<(unsigned)((nl + P - 1) / P), kConvThreads, sizeof(double2) * ((size_t)P + 1) * M[1], st>>>(
+            g, nl, M[2], (int64_t)M[1] * M[2], M[2], M[1], M[1], fy, P, nullptr, M[1], M[2], H[1], H[2], nullptr);
         BAE_HIP_CHECK(hipGetLastError());
         const int Px = lines_for(M[0], false);
         const int64_t nlx = (int64_t)M[1] * M[2];
-        conv_lines<kConvThreads><<<(unsigned)((nlx + Px - 1) / Px), kConvThreads, sizeof(double2) * ((size_t)Px + 1) * M[0], st>>>(
-            g, nlx, nlx, 0, nlx, M[0], M[0], 0, fx, Px, nullptr, M[1], M[2], H[1], H[2], nullptr);
+        conv_lines<kConvThreads, 0><<<(unsigned)((nlx + Px - 1) / Px), kConvThreads, sizeof(double2) * ((size_t)Px + 1) * M[0], st>>>(
+            g, nlx, nlx, 0, nlx, M[0], M[0], fx, Px, nullptr, M[1], M[2], H[1], H[2], nullptr);
         BAE_HIP_CHECK(hipGetLastError());
     }
     conv_octant<<<(unsigned)((oct + 255) / 256), 256, 0, st>>>(g, M[1], M[2], H[0], H[1], H[2], ghat);

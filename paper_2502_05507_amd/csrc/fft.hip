@@ -89,15 +89,15 @@ __global__ __launch_bounds__(THREADS, 4) void dst_axis_kernel(double* __restrict
         A[(int64_t)e * M + N + 1] = make_double2(0.0, 0.0);
     }
     __syncthreads();
-    const float rN = 1.0f / (float)N, rP = 1.0f / (float)P;
+    const float rN = rcp_up(N), rP = rcp_up(P);
     // element e of the block: line pl, position n (lines consecutive along the contiguous
     // axis, interleaved along the others)
     auto split = [=](int e) -> int2 {
         if (axis == 2) {
-            const int pl = fdiv(e, N, rN);
+            const int pl = fdiv_up(e, rN);
             return make_int2(pl, e - pl * N);
         }
-        const int n = fdiv(e, P, rP);
+        const int n = fdiv_up(e, rP);
         return make_int2(e - n * P, n);
     };
     // every load of the thread issued before the first LDS write (P N < (P / 2) M <= kFftPoints:
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(THREADS, 4) void dst_axis_kernel(double* __restrict
         }
     }
     __syncthreads();
-    fft_lds<THREADS>(A, nfft, p, tw, false);
+    fft_lds<THREADS, false>(A, nfft, p, tw);
     const double2* Z = A;
     const double h = 0.5 * scale;
     for (int e = threadIdx.x; e < P * N; e += blockDim.x) {

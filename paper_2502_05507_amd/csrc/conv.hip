@@ -155,13 +155,24 @@ __global__ __launch_bounds__(THREADS, 4) void conv_lines(double2* __restrict__ C
     if constexpr (MODE == 1) {   // the product by the kernel's transform, then the inverse
         const int64_t gplane = (int64_t)H1 * H2;
         // the block's lines are consecutive rows of the kernel's transform: the line index
-        // fastest, so that a wavefront reads runs of consecutive values of it
-        for (int e = threadIdx.x; e < P * M; e += blockDim.x) {
+        // fastest, so that a wavefront reads runs of consecutive values of it; all of a
+        // thread's loads issued before the first product (P M <= kIt THREADS)
+        double g[kIt];
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int e = threadIdx.x + it * THREADS;
+            g[it] = 0.0;
+            if (e >= P * M) continue;
             const int n = fdiv_up(e, rP), pl = e - n * P;
-            if (lbase[pl] < 0) continue;
-            const double g = ghat[min(n, M - n) * gplane + grow[pl]];
+            if (lbase[pl] >= 0) g[it] = ghat[min(n, M - n) * gplane + grow[pl]];
+        }
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int e = threadIdx.x + it * THREADS;
+            if (e >= P * M) continue;
+            const int n = fdiv_up(e, rP), pl = e - n * P;
             const double2 z = Z[(int64_t)pl * M + n];
-            Z[(int64_t)pl * M + n] = make_double2(g * z.x, g * z.y);
+            Z[(int64_t)pl * M + n] = make_double2(g[it] * z.x, g[it] * z.y);
         }
         __syncthreads();
         fft_lds<THREADS, true>(Z, P, p, tw);

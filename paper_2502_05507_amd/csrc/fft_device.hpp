@@ -99,7 +99,10 @@ __device__ __forceinline__ void stage(double2* __restrict__ buf, int count, int 
     int o[I];
 #pragma unroll
     for (int it = 0; it < I; ++it) {
-        const int e = threadIdx.x + it * THREADS;
+        int e = threadIdx.x + it * THREADS;
+        // opaque, so that its quotients are formed here and not kept live across every stage
+        // of the transform (they are invariant per radix; held, they spill)
+        asm volatile("" : "+v"(e));
         o[it] = -1;
         if (e >= total) continue;
         const int c = fdiv_up(e, rm), j = e - c * m;

@@ -18,7 +18,6 @@
 // Lines along any axis of a row-major [n0][n1][n2] array are gathered by one workgroup each
 // group of P lines: along the contiguous axis whole rows, along the others P consecutive
 // columns, so every load and store is a run of P (or n2) consecutive doubles.
-#include <algorithm>
 #include <cmath>
 #include <map>
 #include <memory>
@@ -215,7 +214,6 @@ std::vector<int> fft_factors(int M) {
             r /= q;
         }
     if (r > 1) f.push_back(r);
-    std::reverse(f.begin(), f.end());
     return f;
 }
 

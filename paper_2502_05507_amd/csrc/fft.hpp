@@ -31,9 +31,7 @@ struct FftDev {
     const double2* tw = nullptr;
 };
 
-// Radices of M in the order the stages apply them: primes above 5, 5s, 3s, 2, then 4s.  The
-// first stage writes each thread's outputs R points apart, which odd R spreads over the LDS
-// banks; the radix-4 stages come last, where their outputs form runs of consecutive points.
+// Radices of M in the order the stages apply them (4s, 2, 3s, 5s, then other primes).
 std::vector<int> fft_factors(int M);
 // The plan of length M on the current device (cached until the process ends).
 FftDev fft_plan(int M, hipStream_t st);

@@ -24,8 +24,9 @@ def test_poisson_ellipsoid_129_matvec_sampled():
     with P.Context.from_problem(p) as ctx:
         qd = torch.from_numpy(q).to(device())
         v = torch.empty(len(T), dtype=torch.float64, device=device())
-        # FP32: 38% of the pairs take the q = 2 far field, whose dropped term is below 6.1e-7
-        for prec, tol in ((P.PREC_FP64, 1e-10), (P.PREC_FP32, 3e-6)):
+        # FP32: 38% of the pairs take the q = 2 far field, whose dropped term is below 6.1e-7;
+        # FFT: the convolution on the 240 x 162 x 135 grid, FP64
+        for prec, tol in ((P.PREC_FP64, 1e-10), (P.PREC_FP32, 3e-6), (P.PREC_FFT, 1e-10)):
             ctx.apply_double_layer(qd, v, prec)
             torch.cuda.synchronize()
             err = rel_l2(v.cpu().numpy()[pick], ref)
@@ -83,7 +84,8 @@ def test_helmholtz_star_257_sixteen_rhs_sampled():
         assert (z["n_gamma_plus"], z["n_gamma_minus"], z["n_ext"], z["n_edges"]) == (114202, 115646, 117098, 212182)
         qd = torch.from_numpy(q).to(device())
         v = torch.empty((16, len(T)), dtype=torch.float64, device=device())
-        for prec, tol in ((P.PREC_FP64, 1e-10), (P.PREC_FP32, 2e-5)):
+        # FFT: one convolution per right-hand side on the 375 x 480 x 450 grid, FP64
+        for prec, tol in ((P.PREC_FP64, 1e-10), (P.PREC_FP32, 2e-5), (P.PREC_FFT, 1e-10)):
             ctx.apply_double_layer(qd, v, prec)
             torch.cuda.synchronize()
             out = v.cpu().numpy()[:, pick]

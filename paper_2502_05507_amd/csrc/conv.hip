@@ -336,7 +336,8 @@ template <int THREADS, typename... A>
 void launch_lines(int mode, unsigned grid, size_t lds, hipStream_t st, A... args) {
     if (mode == 0) conv_lines<THREADS, 0><<<grid, THREADS, lds, st>>>(args...);
     else if (mode == 1) conv_lines<THREADS, 1><<<grid, THREADS, lds, st>>>(args...);
-    else conv_lines<THREADS, 2><<<grid, THREADS, lds, st>>>(args...);
+    else if (mode == 2) conv_lines<THREADS, 2><<<grid, THREADS, lds, st>>>(args...);
+    else throw Error{BAE_ERR_ARG, "LGF convolution: unknown line-pass mode"};
 }
 
 // C lines along y (i < e0, k < M2; j the element) or x (j < M1, k < M2; i the element)
